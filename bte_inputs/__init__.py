@@ -1,0 +1,229 @@
+"""Seeded synthetic inputs for the phonon-BTE workloads.
+
+This module only draws random numbers and lays out geometry, band tables and
+source fields.  It contains none of the solver's arithmetic and is the only
+code shared by the oracle side and the HIP side of the tests and benchmark.
+
+Band tables stand in for first-principles silicon data (not available here):
+v ~ U[1e3, 8e3] m/s, log10(tau) ~ U[lo, hi], C_raw ~ U(0, 1] rescaled so that
+sum C = 1.66e6 J/(m^3 K).  Draw order: v, then log10 tau, then C.
+Porous geometries: non-overlapping circular (2D) or spherical (3D) pores with
+a ligament of at least two cells (periodic wrap), added until the porosity
+reaches the target within 0.01; solid islands not connected to the main
+body are filled; the solid must percolate along x.
+"""
+import numpy as np
+
+BC_THERMAL, BC_SPECULAR, BC_DIFFUSE, BC_PERIODIC = 0, 1, 2, 3
+LIM_NONE, LIM_MC, LIM_MINMOD = 0, 1, 2
+SCHEME_SEQUENTIAL, SCHEME_SYNTHETIC = 0, 1
+
+C_TOTAL = 1.66e6
+
+
+def bands(rng, n_bands, tau_lo=1e-12, tau_hi=1e-10, v_lo=1e3, v_hi=8e3, c_total=C_TOTAL):
+    """Seeded band table (C, v, tau) as float64 arrays."""
+    if not isinstance(rng, np.random.Generator):
+        rng = np.random.default_rng(rng)
+    v = rng.uniform(v_lo, v_hi, n_bands)
+    tau = 10.0 ** rng.uniform(np.log10(tau_lo), np.log10(tau_hi), n_bands)
+    c = 1.0 - rng.random(n_bands)
+    c *= c_total / c.sum()
+    return dict(C=c.astype(np.float64), v=v.astype(np.float64), tau=tau.astype(np.float64))
+
+
+def _geometry(dim, n, length, bc, bcT=None, pdT=(0.0, 0.0, 0.0), solid=None, pore_bc=BC_DIFFUSE,
+              Tref=300.0):
+    n = list(n) + [1] * (3 - len(n))
+    length = list(length) + [1.0] * (3 - len(length))
+    return dict(dim=dim, n=n, len=length, bc=list(bc), bcT=list(bcT or [Tref] * 6),
+                pdT=list(pdT), solid=solid, pore_bc=pore_bc)
+
+
+def _cell_centres(n, length):
+    """Cell-centre coordinates, arrays of shape n[::-1] (z, y, x order flattened as c)."""
+    axes = [(np.arange(n[a]) + 0.5) * (length[a] / n[a]) for a in range(3)]
+    z, y, x = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return x.reshape(-1), y.reshape(-1), z.reshape(-1)
+
+
+def _keep_percolating(solid, n, dim):
+    """Fill solid islands not connected (periodically) to the main body; return
+    None if the main body does not span x."""
+    from scipy import ndimage
+    shape = tuple(n[a] for a in range(dim))[::-1]
+    s = solid.reshape(shape).astype(bool)
+    # periodic labelling by tiling 3x along each axis
+    reps = (3,) * dim
+    big = np.tile(s, reps)
+    lab, nl = ndimage.label(big)
+    sl = tuple(slice(shape[k], 2 * shape[k]) for k in range(dim))
+    centre = lab[sl]
+    if nl == 0:
+        return None
+    counts = np.bincount(centre.reshape(-1))
+    counts[0] = 0
+    main = counts.argmax()
+    keep = centre == main
+    # percolation along x (last array axis): main label in the first and last column
+    if not (keep[..., 0].any() and keep[..., -1].any()):
+        return None
+    return keep.reshape(-1).astype(np.uint8)
+
+
+def porous(rng, dim, n, dx, porosity, r_lo=0.05, r_hi=0.15, ligament=2, max_tries=20000):
+    """Random circular/spherical pores on a periodic grid of n cells (uniform dx)."""
+    n = list(n) + [1] * (3 - len(n))
+    side = min(n[a] for a in range(dim)) * dx
+    length = [n[a] * dx for a in range(3)]
+    x, y, z = _cell_centres(n, length)
+    coords = [x, y, z][:dim]
+    solid = np.ones(int(np.prod(n)), dtype=np.uint8)
+    pores = []
+    tries = 0
+    while tries < max_tries:
+        tries += 1
+        phi = 1.0 - solid.mean()
+        if phi >= porosity - 0.01:
+            break
+        r = rng.uniform(r_lo, r_hi) * side
+        ctr = [rng.uniform(0, length[a]) for a in range(dim)]
+        ok = True
+        for (c2, r2) in pores:
+            d2 = 0.0
+            for a in range(dim):
+                d = abs(ctr[a] - c2[a])
+                d = min(d, length[a] - d)
+                d2 += d * d
+            if np.sqrt(d2) < r + r2 + ligament * dx:
+                ok = False
+                break
+        if not ok:
+            continue
+        d2 = np.zeros_like(x)
+        for a in range(dim):
+            d = np.abs(coords[a] - ctr[a])
+            d = np.minimum(d, length[a] - d)
+            d2 += d * d
+        trial = solid.copy()
+        trial[d2 < r * r] = 0
+        if 1.0 - trial.mean() > porosity + 0.01:
+            continue
+        solid = trial
+        pores.append((ctr, r))
+    kept = _keep_percolating(solid, n, dim)
+    return kept
+
+
+# ------------------------------------------------------------------ workloads
+
+def config0(seed=0, n_cells=200, n_bands=10):
+    """1D cross-plane slab, L = 100 nm, walls at 301 K / 299 K, Tref 300 K,
+    16 polar directions (8 per hemisphere), FP64 steady synthetic."""
+    rng = np.random.default_rng(seed)
+    mat = bands(rng, n_bands, 1e-12, 1e-10)
+    mat.update(n_theta=8, n_phi=1, Tref=300.0)
+    bc = [BC_THERMAL, BC_THERMAL] + [BC_SPECULAR] * 4
+    bcT = [301.0, 299.0] + [300.0] * 4
+    geo = _geometry(1, (n_cells,), (100e-9,), bc, bcT)
+    return dict(name="slab1d", geometry=geo, material=mat, P=None, gamma=None,
+                limiter=LIM_NONE, scheme=SCHEME_SYNTHETIC, tol_T=1e-10)
+
+
+def config1(seed=1, n=256, n_bands=20, n_theta=2, n_phi=8):
+    """2D 1 um square, 256^2 cells; heat sink y=0 edge at 300 K, other edges
+    diffuse; Gaussian source (sigma 50 nm, peak 1e17 W/m^3) at the centre."""
+    rng = np.random.default_rng(seed)
+    mat = bands(rng, n_bands, 1e-12, 1e-9)
+    mat.update(n_theta=n_theta, n_phi=n_phi, Tref=300.0)
+    bc = [BC_DIFFUSE, BC_DIFFUSE, BC_THERMAL, BC_DIFFUSE, BC_SPECULAR, BC_SPECULAR]
+    L = 1e-6
+    geo = _geometry(2, (n, n), (L, L), bc)
+    x, y, _ = _cell_centres(geo["n"], geo["len"])
+    sig = 50e-9
+    P = 1e17 * np.exp(-((x - L / 2) ** 2 + (y - L / 2) ** 2) / (2 * sig * sig))
+    return dict(name="square2d_source", geometry=geo, material=mat, P=P, gamma=None,
+                limiter=LIM_NONE, scheme=SCHEME_SYNTHETIC)
+
+
+def laser_profile(geo, q0=4.64e18, w0=200e-9, depth=1.5e-6):
+    """Spatial part of the top-face laser source: Q0 exp(-2 r^2/w0^2) exp(-d/h)."""
+    x, y, z = _cell_centres(geo["n"], geo["len"])
+    Lx, Ly, Lz = geo["len"]
+    r2 = (x - Lx / 2) ** 2 + (y - Ly / 2) ** 2
+    d = Lz - z
+    return q0 * np.exp(-2 * r2 / (w0 * w0)) * np.exp(-d / depth)
+
+
+def tave_weights(geo, w0=200e-9):
+    """Weights of the surface-average temperature: top-layer cells with r < 2 w0,
+    weight exp(-2 r^2 / w0^2)."""
+    x, y, z = _cell_centres(geo["n"], geo["len"])
+    Lx, Ly, Lz = geo["len"]
+    hz = Lz / geo["n"][2]
+    r2 = (x - Lx / 2) ** 2 + (y - Ly / 2) ** 2
+    top = z > Lz - hz
+    return np.where(top & (r2 < 4 * w0 * w0), np.exp(-2 * r2 / (w0 * w0)), 0.0)
+
+
+def config2(seed=2, n=64, n_bands=40, n_theta=4, n_phi=4):
+    """3D (2 um)^3 cube, n^3 cells, top (+z) face diffuse, other faces at
+    300 K; Gaussian laser pulse (200 nm spot, 10 ps FWHM centred at 20 ps);
+    dt = 0.5 ps explicit steps; MC limiter."""
+    rng = np.random.default_rng(seed)
+    mat = bands(rng, n_bands, 1e-12, 1e-9)
+    mat.update(n_theta=n_theta, n_phi=n_phi, Tref=300.0)
+    bc = [BC_THERMAL] * 5 + [BC_DIFFUSE]
+    L = 2e-6
+    geo = _geometry(3, (n, n, n), (L, L, L), bc)
+    P = laser_profile(geo)
+    return dict(name="cube3d_laser", geometry=geo, material=mat, P=P, gamma=None,
+                limiter=LIM_MC, dt=0.5e-12, n_steps=2000, pulse=(20e-12, 10e-12),
+                hist_weights=tave_weights(geo))
+
+
+def config3(seed=3, n_films=64, sides=(32, 64, 128, 192, 256), n_bands=20, n_theta=2, n_phi=4):
+    """Batch of 2D porous films (periodic x with dT = 1 K, periodic y, diffuse
+    pores), dx = 1 um / 256; returns a list of film geometries and one band table."""
+    rng = np.random.default_rng(seed)
+    mat = bands(rng, n_bands, 1e-12, 1e-9)
+    mat.update(n_theta=n_theta, n_phi=n_phi, Tref=300.0)
+    dx = 1e-6 / 256
+    films = []
+    for child in rng.spawn(n_films):
+        for _ in range(50):
+            side = int(child.choice(sides))
+            phi = child.uniform(0.1, 0.4)
+            solid = porous(child, 2, (side, side), dx, phi)
+            if solid is not None:
+                break
+        bc = [BC_PERIODIC] * 4 + [BC_SPECULAR] * 2
+        films.append(_geometry(2, (side, side), (side * dx, side * dx), bc, pdT=(1.0, 0.0, 0.0),
+                               solid=solid))
+    return dict(name="porous2d_batch", films=films, material=mat, limiter=LIM_NONE,
+                scheme=SCHEME_SYNTHETIC)
+
+
+def config4(seed=4, n=48, n_bands=40, n_theta=3, n_phi=4, porosity=0.2):
+    """3D (1 um)^3 porous cube (spherical pores), periodic xyz with dT = 1 K
+    along x, per-cell extra scattering rate gamma ~ U[0, 1e11] 1/s."""
+    rng = np.random.default_rng(seed)
+    mat = bands(rng, n_bands, 1e-12, 1e-9)
+    mat.update(n_theta=n_theta, n_phi=n_phi, Tref=300.0)
+    dx = 1e-6 / n
+    solid = None
+    for _ in range(50):
+        solid = porous(rng, 3, (n, n, n), dx, porosity)
+        if solid is not None:
+            break
+    gamma = rng.uniform(0.0, 1e11, n ** 3)
+    bc = [BC_PERIODIC] * 6
+    geo = _geometry(3, (n, n, n), (n * dx,) * 3, bc, pdT=(1.0, 0.0, 0.0), solid=solid)
+    return dict(name="porous3d_adjoint", geometry=geo, material=mat, P=None, gamma=gamma,
+                limiter=LIM_NONE, scheme=SCHEME_SYNTHETIC)
+
+
+def random_field(seed, size, scale=1.0):
+    """Seeded uniform random array in [-scale, scale) (test perturbations)."""
+    rng = np.random.default_rng(seed)
+    return scale * (2.0 * rng.random(size) - 1.0)
