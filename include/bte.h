@@ -1,0 +1,194 @@
+/*
+ * bte.h -- C ABI of the MI355X (gfx950) phonon-BTE hot-path library.
+ *
+ * The library solves the energy-based, deviational phonon Boltzmann
+ * transport equation in the relaxation-time approximation (Hu et al.,
+ * GiftBTE, Sec. 2.1, eqs. BTE_origin / BTE_get_e0) with the discrete-
+ * ordinates method on structured Cartesian grids:
+ *   - steady state: implicit source iteration in delta form with a
+ *     second-order upwind finite-volume flux (Sec. 3.3, eq. disretized_BTE;
+ *     Sec. 3.5, stiffness matrix / right-hand side eq. B_BTE), sequential or
+ *     synthetic scheme (Sec. 3.4, Algorithm 1);
+ *   - transient: explicit forward-Euler step (Sec. 4.1,
+ *     eq. disretized_transientBTE, Algorithm 2);
+ *   - moments: temperature, lattice temperature, heat flux (eqs. BTE_get_e0,
+ *     getTQ);
+ *   - adjoint: gradient of the effective conductivity with respect to a
+ *     per-cell extra scattering rate.
+ *
+ * Conventions shared by every call
+ *   - Every call returns a bte_status and never throws or aborts.  On a
+ *     validation error nothing is written to any output.  bte_last_error()
+ *     returns a text description of the last failure on a handle.
+ *   - Device pointers are HIP device addresses (e.g. the data pointer of a
+ *     torch tensor on cuda:0); host pointers are ordinary CPU memory.  The
+ *     caller owns every buffer; the library allocates no device memory: its
+ *     scratch lives in a caller-provided workspace (bte_workspace_bytes /
+ *     bte_bind).
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     All device work of a call is enqueued on that stream.
+ *   - A handle may be used by one host thread and one stream at a time.
+ *
+ * Layout of the energy deviation e (J m^-3 sr^-1 relative to the
+ * equilibrium at T_ref):  e[cell][alpha][lambda], lambda fastest, cells
+ * c = ix + nx*(iy + ny*iz), element type float (BTE_F32) or double
+ * (BTE_F64).  For a batch of geometries the per-geometry arrays are
+ * concatenated in batch order.  Directions alpha are ordered octant-major
+ * (octant bits 1: s_x<0, 2: s_y<0, 4: s_z<0), then polar index (ascending
+ * theta), then azimuthal index (ascending phi); in one dimension there are
+ * two hemispheres (s_x>0 first), polar axis x.  bte_get_directions()
+ * returns the table.
+ */
+#ifndef BTE_H
+#define BTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BTE_OK = 0,
+    BTE_ERR_ARG = 1,            /* invalid argument (nothing written)              */
+    BTE_ERR_UNSUPPORTED = 2,    /* valid but not supported combination             */
+    BTE_ERR_HIP = 3,            /* HIP runtime error                               */
+    BTE_ERR_NOT_CONVERGED = 4,  /* max_iter reached; last iterate and stats written */
+    BTE_ERR_NONFINITE = 5,      /* NaN/Inf detected in the iteration               */
+    BTE_ERR_CFL = 6,            /* time step violates the explicit stability bound  */
+    BTE_ERR_STATE = 7           /* call order (e.g. no workspace bound)            */
+} bte_status;
+
+typedef enum { BTE_F32 = 0, BTE_F64 = 1 } bte_precision;          /* storage of e      */
+typedef enum { BTE_BC_THERMAL = 0, BTE_BC_SPECULAR = 1,
+               BTE_BC_DIFFUSE = 2, BTE_BC_PERIODIC = 3 } bte_bc;  /* Sec. 2.2          */
+typedef enum { BTE_SEQUENTIAL = 0, BTE_SYNTHETIC = 1 } bte_scheme; /* Sec. 3.4          */
+typedef enum { BTE_LIM_NONE = 0, BTE_LIM_MC = 1, BTE_LIM_MINMOD = 2 } bte_limiter;
+typedef enum { BTE_OBJ_KEFF_X = 0 } bte_objective;
+
+/* Geometry (the GEOMETRY input of Sec. 5: dimension, scales, boundary
+ * conditions).  Faces are ordered -x,+x,-y,+y,-z,+z; faces of axes beyond
+ * `dim` are ignored.  Periodic faces come in pairs.  periodic_dT[a] is the
+ * temperature drop imposed across a periodic axis (Sec. 2.2 (iv)): incoming
+ * values on the low face get +C dT/4pi, on the high face -C dT/4pi.
+ * Faces between solid cells and pores (solid[c] == 0) use pore_bc. */
+typedef struct {
+    int dim;                 /* 1, 2 or 3                                  */
+    int n[3];                /* cells per axis (unused axes: 1)            */
+    double len[3];           /* domain length per axis (m)                 */
+    const uint8_t *solid;    /* host, n0*n1*n2 bytes, NULL = all solid      */
+    int bc[6];               /* bte_bc per face                            */
+    double bc_T[6];          /* wall temperature of thermalizing faces (K) */
+    double periodic_dT[3];   /* K                                          */
+    int pore_bc;             /* BTE_BC_DIFFUSE or BTE_BC_SPECULAR          */
+} bte_geometry;
+
+/* Phonon bands (PHONON input: BandNumber, Ntheta, Nphi; Sec. 3.1-3.2) */
+typedef struct {
+    int n_bands;
+    const double *C;         /* host [n_bands] heat capacity, J m^-3 K^-1 */
+    const double *v;         /* host [n_bands] group speed, m/s           */
+    const double *tau;       /* host [n_bands] relaxation time, s         */
+    int n_theta, n_phi;      /* Gauss-Legendre nodes per octant (1D: per hemisphere, n_phi ignored) */
+    double T_ref;            /* reference temperature, K                  */
+} bte_material;
+
+/* Control (CONTROL input, Sec. 5: IterativeScheme, MaxNumIter,
+ * ResidualTemp, ResidualFlux, TimeStep) */
+typedef struct {
+    int precision;           /* bte_precision                               */
+    int scheme;              /* bte_scheme                                  */
+    int limiter;             /* bte_limiter                                 */
+    double residual_temp;    /* stop when eps_T <= residual_temp ...       */
+    double residual_flux;    /* ... and eps_q <= residual_flux             */
+    int max_iter;            /* source iterations (<= 0: 10000)            */
+    double cg_rtol;          /* relative residual of the CG solves          */
+    int cg_max_iter;         /* CG iteration cap per solve (<= 0: 2000)     */
+    double dt;               /* transient time step, s (0: steady only)     */
+} bte_control;
+
+typedef struct {
+    int iters;               /* source iterations performed                */
+    int cg_iters;            /* total CG iterations                        */
+    double eps_T, eps_q;     /* last convergence measures                  */
+    int converged;
+    double ms_total;         /* wall time of the call (host clock)         */
+} bte_solve_stats;
+
+typedef struct bte_problem bte_problem;
+
+/* Build a problem for n_geo geometries of identical dimension sharing one
+ * material and control (n_geo > 1: a batch of independent films, solved
+ * together).  All inputs are host memory and are copied.  On success *out
+ * receives the handle; bind a workspace before any device call. */
+bte_status bte_setup(const bte_geometry *geo, int n_geo, const bte_material *mat,
+                     const bte_control *ctl, bte_problem **out);
+
+/* Size in bytes of the device workspace the handle needs. */
+size_t bte_workspace_bytes(const bte_problem *p);
+
+/* Number of elements of e (all geometries), cells, directions and bands. */
+size_t bte_num_unknowns(const bte_problem *p);
+int bte_num_cells(const bte_problem *p);
+int bte_num_directions(const bte_problem *p);
+
+/* Attach a device workspace (>= bte_workspace_bytes, 256-byte aligned) and
+ * upload the tables; synchronous.  The workspace must stay alive and
+ * untouched by the caller while the handle is used. */
+bte_status bte_bind(bte_problem *p, void *workspace_dev, size_t bytes);
+
+/* Per-cell fields (device, double, all cells of all geometries; NULL = 0):
+ * P = volumetric heat generation sum_lambda Q (W/m^3), split over bands by
+ * C_lambda/C_tot and over solid angle (Sec. 2.1 source term); gamma = extra
+ * scattering rate (1/s) added to every band, 1/tau_i = 1/tau + gamma_i. */
+bte_status bte_set_fields(bte_problem *p, const double *P_dev, const double *gamma_dev, void *stream);
+
+/* Moments of e (eqs. BTE_get_e0, getTQ): T and T_L in K (pores: T_ref),
+ * q[cell][3] in W/m^2.  Any output may be NULL.  Asynchronous. */
+bte_status bte_moments(bte_problem *p, const void *e_dev, double *T_dev, double *TL_dev,
+                       double *q_dev, void *stream);
+
+/* Steady residual R(e) = -(1/V) sum_f e_f v s.n S - (e - C T_L/4pi)/tau + Q
+ * (right-hand side of eq. B_BTE with T_L from e), same layout/precision
+ * as e.  Asynchronous. */
+bte_status bte_residual(bte_problem *p, const void *e_dev, void *R_dev, void *stream);
+
+/* n_steps explicit steps (Sec. 4.1) of size ctl.dt, in place on e, starting
+ * at time t0.  pulse (host, may be NULL) = {t_centre, FWHM}: the source P is
+ * multiplied by exp(-4 ln2 (t - t_centre)^2 / FWHM^2) at t_n = t0 + n dt.
+ * Returns BTE_ERR_CFL if dt * (1/tau_min + sum_a v_max/h_a) >= 1.
+ * Asynchronous. */
+bte_status bte_transient_step(bte_problem *p, void *e_dev, int n_steps, double t0,
+                              const double *pulse, void *stream);
+
+/* Steady solve (Algorithm 1), in place on e.  init != 0 starts from the
+ * heat-diffusion solution (Sec. 3.5, eq. diff), else from e.  Synchronous
+ * (reads one convergence flag per iteration).  Returns BTE_ERR_NOT_CONVERGED
+ * with the last iterate if max_iter is reached.  stats may be NULL. */
+bte_status bte_steady_solve(bte_problem *p, void *e_dev, int init, bte_solve_stats *stats,
+                            void *stream);
+
+/* Effective conductivity along x (W/m/K) of each geometry from e:
+ * k = (L_x / dT_x) * (1/N_cells) * sum_solid q_x (pores count as zero).
+ * keff_dev: device double[n_geo].  Requires periodic_dT[0] != 0. */
+bte_status bte_keff(bte_problem *p, const void *e_dev, double *keff_dev, void *stream);
+
+/* Adjoint of the steady problem for J = k_eff (objective BTE_OBJ_KEFF_X):
+ * solves (dR/de)^T psi = -dJ/de with reversed-direction sweeps and returns
+ * dJ/dgamma per cell (device double[n_cells]).  e must be a converged
+ * steady solution for the current fields.  Limiter must be NONE.
+ * Synchronous. */
+bte_status bte_adjoint(bte_problem *p, const void *e_dev, int objective, double *dJ_dgamma_dev,
+                       bte_solve_stats *stats, void *stream);
+
+/* Host copy of the direction table: s[n_dir][3], w[n_dir]. */
+bte_status bte_get_directions(const bte_problem *p, double *s_host, double *w_host);
+
+const char *bte_last_error(const bte_problem *p);
+void bte_destroy(bte_problem *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BTE_H */

@@ -1,0 +1,271 @@
+"""ctypes binding of the gfx950 phonon-BTE library (include/bte.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library ``_lib/libbte.so``.  Device buffers are torch tensors on a ROCm
+device; the stream is torch's current stream.  If the library is missing
+the import of this module fails loudly -- there is no CPU fallback.
+"""
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libbte.so")
+
+BTE_OK, BTE_ERR_ARG, BTE_ERR_UNSUPPORTED, BTE_ERR_HIP = 0, 1, 2, 3
+BTE_ERR_NOT_CONVERGED, BTE_ERR_NONFINITE, BTE_ERR_CFL, BTE_ERR_STATE = 4, 5, 6, 7
+F32, F64 = 0, 1
+BC_THERMAL, BC_SPECULAR, BC_DIFFUSE, BC_PERIODIC = 0, 1, 2, 3
+SEQUENTIAL, SYNTHETIC = 0, 1
+LIM_NONE, LIM_MC, LIM_MINMOD = 0, 1, 2
+OBJ_KEFF_X = 0
+
+STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "ERR_NOT_CONVERGED",
+                5: "ERR_NONFINITE", 6: "ERR_CFL", 7: "ERR_STATE"}
+
+EXPORTS = ["bte_setup", "bte_workspace_bytes", "bte_num_unknowns", "bte_num_cells", "bte_num_directions",
+           "bte_bind", "bte_set_fields", "bte_moments", "bte_residual", "bte_transient_step",
+           "bte_steady_solve", "bte_keff", "bte_adjoint", "bte_get_directions", "bte_last_error",
+           "bte_destroy"]
+
+
+class BteError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class Geometry(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("len", C.c_double * 3),
+                ("solid", C.POINTER(C.c_uint8)), ("bc", C.c_int * 6), ("bc_T", C.c_double * 6),
+                ("periodic_dT", C.c_double * 3), ("pore_bc", C.c_int)]
+
+
+class Material(C.Structure):
+    _fields_ = [("n_bands", C.c_int), ("C", C.POINTER(C.c_double)), ("v", C.POINTER(C.c_double)),
+                ("tau", C.POINTER(C.c_double)), ("n_theta", C.c_int), ("n_phi", C.c_int),
+                ("T_ref", C.c_double)]
+
+
+class Control(C.Structure):
+    _fields_ = [("precision", C.c_int), ("scheme", C.c_int), ("limiter", C.c_int),
+                ("residual_temp", C.c_double), ("residual_flux", C.c_double), ("max_iter", C.c_int),
+                ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int), ("dt", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("cg_iters", C.c_int), ("eps_T", C.c_double), ("eps_q", C.c_double),
+                ("converged", C.c_int), ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        return dict(iters=self.iters, cg_iters=self.cg_iters, eps_T=self.eps_T, eps_q=self.eps_q,
+                    converged=bool(self.converged), ms_total=self.ms_total)
+
+
+_lib = None
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libbte.so not built (run python -m paper_2306_14181_amd.build): %s" % LIB_PATH)
+    lib = C.CDLL(LIB_PATH)
+    vp, dp, st = C.c_void_p, C.POINTER(C.c_double), C.c_int
+    sig = {
+        "bte_setup": ([C.POINTER(Geometry), C.c_int, C.POINTER(Material), C.POINTER(Control),
+                       C.POINTER(vp)], st),
+        "bte_workspace_bytes": ([vp], C.c_size_t),
+        "bte_num_unknowns": ([vp], C.c_size_t),
+        "bte_num_cells": ([vp], C.c_int),
+        "bte_num_directions": ([vp], C.c_int),
+        "bte_bind": ([vp, vp, C.c_size_t], st),
+        "bte_set_fields": ([vp, vp, vp, vp], st),
+        "bte_moments": ([vp, vp, vp, vp, vp, vp], st),
+        "bte_residual": ([vp, vp, vp, vp], st),
+        "bte_transient_step": ([vp, vp, C.c_int, C.c_double, dp, vp], st),
+        "bte_steady_solve": ([vp, vp, C.c_int, C.POINTER(SolveStats), vp], st),
+        "bte_keff": ([vp, vp, vp, vp], st),
+        "bte_adjoint": ([vp, vp, C.c_int, vp, C.POINTER(SolveStats), vp], st),
+        "bte_get_directions": ([vp, dp, dp], st),
+        "bte_last_error": ([vp], C.c_char_p),
+        "bte_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _geometry_struct(g):
+    s = Geometry()
+    s.dim = int(g["dim"])
+    n = list(g["n"]) + [1] * (3 - len(g["n"]))
+    ln = list(g["len"]) + [1.0] * (3 - len(g["len"]))
+    s.n[:] = [int(x) for x in n[:3]]
+    s.len[:] = [float(x) for x in ln[:3]]
+    keep = None
+    if g.get("solid") is not None:
+        import numpy as np
+        keep = np.ascontiguousarray(g["solid"], dtype=np.uint8)
+        s.solid = keep.ctypes.data_as(C.POINTER(C.c_uint8))
+    s.bc[:] = [int(x) for x in g["bc"]]
+    s.bc_T[:] = [float(x) for x in g.get("bcT", [300.0] * 6)]
+    s.periodic_dT[:] = [float(x) for x in g.get("pdT", [0.0, 0.0, 0.0])]
+    s.pore_bc = int(g.get("pore_bc", BC_DIFFUSE))
+    return s, keep
+
+
+class Problem:
+    """One problem (a geometry or a batch of geometries) bound to a device workspace.
+
+    geometries: dict or list of dicts (dim, n, len, solid, bc, bcT, pdT, pore_bc)
+    material:   dict(C, v, tau, n_theta, n_phi, Tref)
+    control:    dict(precision, scheme, limiter, residual_temp, residual_flux,
+                     max_iter, cg_rtol, cg_max_iter, dt)
+    """
+
+    def __init__(self, geometries, material, control, device="cuda"):
+        import numpy as np
+        lib = load()
+        if isinstance(geometries, dict):
+            geometries = [geometries]
+        self.device = torch.device(device)
+        structs, self._keep = [], []
+        for g in geometries:
+            s, keep = _geometry_struct(g)
+            structs.append(s)
+            self._keep.append(keep)
+        garr = (Geometry * len(structs))(*structs)
+        self._bands = [np.ascontiguousarray(material[k], dtype=np.float64) for k in ("C", "v", "tau")]
+        m = Material()
+        m.n_bands = len(self._bands[0])
+        m.C, m.v, m.tau = [b.ctypes.data_as(C.POINTER(C.c_double)) for b in self._bands]
+        m.n_theta = int(material["n_theta"])
+        m.n_phi = int(material.get("n_phi", 1))
+        m.T_ref = float(material["Tref"])
+        c = Control()
+        c.precision = int(control.get("precision", F32))
+        c.scheme = int(control.get("scheme", SYNTHETIC))
+        c.limiter = int(control.get("limiter", LIM_NONE))
+        c.residual_temp = float(control.get("residual_temp", 1e-5))
+        c.residual_flux = float(control.get("residual_flux", 1e-3))
+        c.max_iter = int(control.get("max_iter", 10000))
+        c.cg_rtol = float(control.get("cg_rtol", 1e-10))
+        c.cg_max_iter = int(control.get("cg_max_iter", 2000))
+        c.dt = float(control.get("dt", 0.0))
+        self.precision = c.precision
+        self.dtype = torch.float64 if c.precision == F64 else torch.float32
+        h = C.c_void_p()
+        st = lib.bte_setup(garr, len(structs), C.byref(m), C.byref(c), C.byref(h))
+        self._h = h
+        if st != BTE_OK:
+            msg = lib.bte_last_error(h).decode() if h else "setup failed"
+            if h:
+                lib.bte_destroy(h)
+                self._h = None
+            raise BteError(st, msg)
+        self.n_cells = lib.bte_num_cells(h)
+        self.n_dirs = lib.bte_num_directions(h)
+        self.n_bands = m.n_bands
+        self.n_unknowns = lib.bte_num_unknowns(h)
+        self.n_geo = len(structs)
+        nbytes = lib.bte_workspace_bytes(h)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self._check(lib.bte_bind(h, C.c_void_p(aligned), C.c_size_t(nbytes)))
+
+    # ------------------------------------------------------------------ utils
+    def _check(self, st, ok=(BTE_OK,)):
+        if st not in ok:
+            raise BteError(st, load().bte_last_error(self._h).decode())
+        return st
+
+    def _e(self, e):
+        if not (isinstance(e, torch.Tensor) and e.device.type == "cuda" and e.dtype == self.dtype
+                and e.is_contiguous() and e.numel() == self.n_unknowns):
+            raise ValueError("e must be a contiguous %s cuda tensor with %d elements"
+                             % (self.dtype, self.n_unknowns))
+        return _ptr(e)
+
+    def _cells(self, x, width=1):
+        if x is None:
+            return None
+        if not (isinstance(x, torch.Tensor) and x.device.type == "cuda" and x.dtype == torch.float64
+                and x.is_contiguous() and x.numel() == self.n_cells * width):
+            raise ValueError("expected a contiguous float64 cuda tensor with %d elements" % (self.n_cells * width))
+        return _ptr(x)
+
+    def zeros(self):
+        return torch.zeros(self.n_unknowns, dtype=self.dtype, device=self.device)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            try:
+                torch.cuda.synchronize(self.device)
+            except Exception:
+                pass
+            load().bte_destroy(self._h)
+            self._h = None
+
+    # -------------------------------------------------------------------- API
+    def directions(self):
+        import numpy as np
+        s = np.empty((self.n_dirs, 3))
+        w = np.empty(self.n_dirs)
+        self._check(load().bte_get_directions(self._h, s.ctypes.data_as(C.POINTER(C.c_double)),
+                                              w.ctypes.data_as(C.POINTER(C.c_double))))
+        return s, w
+
+    def set_fields(self, P=None, gamma=None):
+        self._check(load().bte_set_fields(self._h, self._cells(P), self._cells(gamma), _stream()))
+
+    def moments(self, e):
+        T = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)
+        TL = torch.empty_like(T)
+        q = torch.empty(self.n_cells * 3, dtype=torch.float64, device=self.device)
+        self._check(load().bte_moments(self._h, self._e(e), _ptr(T), _ptr(TL), _ptr(q), _stream()))
+        return T, TL, q.view(-1, 3)
+
+    def residual(self, e):
+        R = torch.empty_like(e)
+        self._check(load().bte_residual(self._h, self._e(e), _ptr(R), _stream()))
+        return R
+
+    def transient_step(self, e, n_steps, t0=0.0, pulse=None):
+        pl = None
+        if pulse is not None:
+            pl = (C.c_double * 2)(float(pulse[0]), float(pulse[1]))
+        self._check(load().bte_transient_step(self._h, self._e(e), int(n_steps), float(t0), pl, _stream()))
+        return e
+
+    def steady_solve(self, e, init=True, allow_not_converged=False):
+        st = SolveStats()
+        ok = (BTE_OK, BTE_ERR_NOT_CONVERGED) if allow_not_converged else (BTE_OK,)
+        self._check(load().bte_steady_solve(self._h, self._e(e), int(bool(init)), C.byref(st), _stream()), ok)
+        return st.as_dict()
+
+    def keff(self, e):
+        k = torch.empty(self.n_geo, dtype=torch.float64, device=self.device)
+        self._check(load().bte_keff(self._h, self._e(e), _ptr(k), _stream()))
+        return k
+
+    def adjoint(self, e, objective=OBJ_KEFF_X):
+        g = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)
+        st = SolveStats()
+        self._check(load().bte_adjoint(self._h, self._e(e), int(objective), _ptr(g), C.byref(st), _stream()))
+        return g, st.as_dict()

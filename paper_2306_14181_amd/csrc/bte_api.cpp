@@ -1,0 +1,917 @@
+// bte_api.cpp -- host runtime and C ABI of the phonon-BTE library.
+//
+// Setup precomputes everything that does not change during a solve
+// (Algorithm 1 precomputes its matrices once, Sec. 3.5): the angular
+// quadrature, mirror-direction table, per-cell neighbour codes, diffuse-wall
+// records and the tile-wavefront schedule of the sweep.  All device memory
+// is a caller-provided workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bte.h"
+#include "bte_internal.h"
+
+namespace bte {
+template <typename T> void launch_moments(const Dev &, const T *, const double *, double *, hipStream_t);
+template <typename T>
+void launch_walls(const Dev &, const T *, const double *, const int *, const double *, double *, int, hipStream_t);
+template <typename T>
+void launch_transient(const Dev &, const T *, T *, const double *, const double *, double, double, double *, int,
+                      hipStream_t);
+template <typename T>
+void launch_residual(const Dev &, const T *, T *, const double *, const double *, int, hipStream_t);
+template <typename T>
+void launch_sweep(const Dev &, const T *, T *, const double *, const double *, const double *, const SweepItem *, int,
+                  int, int3, int, int, double *, hipStream_t);
+template <typename T> void launch_set_equilibrium(const Dev &, T *, const double *, hipStream_t);
+template <typename T> void launch_apply_shift(const Dev &, const T *, T *, const double *, const double *, hipStream_t);
+void launch_keff(const Dev &, const double *, double *, hipStream_t);
+void launch_cell_setup(const Dev &, double *, double *, double *, const double[3], const double[3], hipStream_t);
+void launch_finalize(const Dev &, const double *, int, double, double *, double *, double *, double *, double *,
+                     double *, hipStream_t);
+void launch_steady_post(const Dev &, const double *, int, const double *, double *, double *, double *, double *, int,
+                        hipStream_t);
+void launch_film_eps(const Dev &, const double *, const double *, const double *, const double *, double *,
+                     hipStream_t);
+void launch_film_mean(const Dev &, const double *, double *, hipStream_t);
+void launch_sub_film_mean(const Dev &, double *, const double *, hipStream_t);
+void launch_tl_update(int, const double *, const double *, double *, double *, hipStream_t);
+int cg_nblk(const Dev &);
+void launch_cg_init(const Dev &, const CgArgs &, const double *, hipStream_t);
+void launch_cg_iter(const Dev &, const CgArgs &, int, hipStream_t);
+void launch_diff_rhs(const Dev &, const CgArgs &, double *, hipStream_t);
+}  // namespace bte
+
+using namespace bte;
+
+namespace {
+
+// Gauss-Legendre nodes/weights on [-1, 1], ascending (Newton on P_n).
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int j = 2; j <= n; ++j) {
+                double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) {
+                p1 = z;
+                p0 = 1.0;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int j = 2; j <= n; ++j) {
+            double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+            p0 = p1;
+            p1 = p2;
+        }
+        if (n == 1) p0 = 1.0, p1 = z;
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[n - 1 - i] = z;
+        w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct bte_problem {
+    std::string err;
+    int dim = 0, nfilm = 0, nc = 0, na = 0, nl = 0, nk = 0, noct = 0, na_oct = 0;
+    bte_control ctl{};
+    double Tref = 0, Ctot = 0, vmax = 0, itau_max = 0;
+    std::vector<Film> films;
+    std::vector<uint32_t> code;
+    std::vector<int> nb, fid, dbase, wrec, mirror;
+    std::vector<double> s, w, C4, v, itau;
+    double wden[6] = {0, 0, 0, 0, 0, 0};
+    double M[3] = {0, 0, 0}, H[3] = {0, 0, 0};
+    int nw = 0;
+    // sweep schedule
+    int3 tdim{1, 1, 1};
+    int nchunk_oct = 0;
+    std::vector<SweepItem> items;
+    std::vector<int> diag_off;
+    int floating_any = 0, thermal_any = 0;
+    // workspace
+    size_t ws_bytes = 0;
+    char *ws = nullptr;
+    size_t off_tables = 0;
+    struct Buf {
+        size_t off, bytes;
+    };
+    std::vector<std::pair<std::string, Buf>> layout;
+    Dev dev{};
+    bool fields_set = false;
+    // device pointers
+    double *S = nullptr, *kdif = nullptr, *kcor = nullptr, *gamma = nullptr, *P = nullptr;
+    double *TL = nullptr, *TLkin = nullptr, *T0 = nullptr, *T1 = nullptr, *q0 = nullptr, *q1 = nullptr;
+    double *r = nullptr, *delta = nullptr, *dpend = nullptr, *fmean = nullptr, *feps = nullptr;
+    double *cg_x = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr, *cg_diag = nullptr;
+    double *cg_part = nullptr, *cg_scal = nullptr;
+    double *din = nullptr, *part = nullptr;
+    void *e2 = nullptr;
+    SweepItem *d_items = nullptr;
+    int *d_wrec = nullptr;
+    double *d_wden = nullptr;
+    int npart_max = 0;
+
+    size_t esize() const { return ctl.precision == BTE_F64 ? 8 : 4; }
+    size_t nelem() const { return (size_t)nc * nk; }
+};
+
+#define FAIL(p, st, ...)                                                                                               \
+    do {                                                                                                               \
+        char _b[512];                                                                                                  \
+        snprintf(_b, sizeof _b, __VA_ARGS__);                                                                          \
+        (p)->err = _b;                                                                                                 \
+        return st;                                                                                                     \
+    } while (0)
+
+#define HIPCHK(p, x)                                                                                                   \
+    do {                                                                                                               \
+        hipError_t _e = (x);                                                                                           \
+        if (_e != hipSuccess) FAIL(p, BTE_ERR_HIP, "%s: %s", #x, hipGetErrorString(_e));                               \
+    } while (0)
+
+namespace {
+
+bte_status build_geometry(bte_problem *p, const bte_geometry *geo, int n_geo)
+{
+    p->dim = geo[0].dim;
+    p->nfilm = n_geo;
+    int cell0 = 0;
+    for (int f = 0; f < n_geo; ++f) {
+        const bte_geometry &g = geo[f];
+        if (g.dim != p->dim) FAIL(p, BTE_ERR_ARG, "geometry %d: all geometries must share dim", f);
+        Film fm{};
+        long long ncell = 1;
+        for (int a = 0; a < 3; ++a) {
+            fm.n[a] = a < g.dim ? g.n[a] : 1;
+            if (fm.n[a] < 1) FAIL(p, BTE_ERR_ARG, "geometry %d: n[%d] < 1", f, a);
+            fm.len[a] = a < g.dim ? g.len[a] : 1.0;
+            if (!(fm.len[a] > 0)) FAIL(p, BTE_ERR_ARG, "geometry %d: len[%d] must be > 0", f, a);
+            fm.h[a] = fm.len[a] / fm.n[a];
+            fm.ih[a] = 1.0 / fm.h[a];
+            fm.pdT[a] = a < g.dim ? g.periodic_dT[a] : 0.0;
+            ncell *= fm.n[a];
+        }
+        if (ncell + cell0 > 0x7fffffffLL / 8) FAIL(p, BTE_ERR_ARG, "too many cells");
+        for (int a = 0; a < g.dim; ++a) {
+            bool p0 = g.bc[2 * a] == BTE_BC_PERIODIC, p1 = g.bc[2 * a + 1] == BTE_BC_PERIODIC;
+            if (p0 != p1) FAIL(p, BTE_ERR_ARG, "geometry %d: periodic faces of axis %d must come in pairs", f, a);
+            for (int s = 0; s < 2; ++s)
+                if (g.bc[2 * a + s] < 0 || g.bc[2 * a + s] > 3) FAIL(p, BTE_ERR_ARG, "geometry %d: bad bc", f);
+            if (!p0 && g.periodic_dT[a] != 0.0)
+                FAIL(p, BTE_ERR_ARG, "geometry %d: periodic_dT on a non-periodic axis", f);
+        }
+        if (g.pore_bc != BTE_BC_DIFFUSE && g.pore_bc != BTE_BC_SPECULAR && g.pore_bc != BTE_BC_THERMAL)
+            FAIL(p, BTE_ERR_ARG, "geometry %d: pore_bc must be thermalizing, specular or diffuse", f);
+        for (int q = 0; q < 6; ++q) fm.wallT[q] = g.bc_T[q] - p->Tref;
+        fm.cell0 = cell0;
+        fm.ncell = (int)ncell;
+        cell0 += (int)ncell;
+        p->films.push_back(fm);
+    }
+    p->nc = cell0;
+    const int nc = p->nc;
+    p->code.assign(nc, 0);
+    p->nb.assign(6 * (size_t)nc, -1);
+    p->fid.assign(nc, 0);
+    p->dbase.assign(nc, -1);
+    int nw = 0;
+    for (int f = 0; f < n_geo; ++f) {
+        const bte_geometry &g = geo[f];
+        Film &fm = p->films[f];
+        auto solid_at = [&](int i) { return g.solid ? g.solid[i] != 0 : true; };
+        int nsolid = 0, thermal = 0;
+        for (int i = 0; i < fm.ncell; ++i) {
+            const int c = fm.cell0 + i;
+            p->fid[c] = f;
+            if (!solid_at(i)) continue;
+            ++nsolid;
+            uint32_t code = kSolidBit;
+            int idx[3] = {i % fm.n[0], (i / fm.n[0]) % fm.n[1], i / (fm.n[0] * fm.n[1])};
+            for (int a = 0; a < p->dim; ++a) {
+                for (int side = -1; side <= 1; side += 2) {
+                    int k = idx[a] + side;
+                    int fidx = face_of(a, side);
+                    bool wraps = false, outer = false;
+                    int kind = -1;
+                    if (k < 0 || k >= fm.n[a]) {
+                        if (g.bc[fidx] == BTE_BC_PERIODIC) {
+                            k = (k + fm.n[a]) % fm.n[a];
+                            wraps = true;
+                        } else {
+                            kind = g.bc[fidx];
+                            outer = true;
+                        }
+                    }
+                    int j = -1;
+                    if (kind < 0) {
+                        int jj[3] = {idx[0], idx[1], idx[2]};
+                        jj[a] = k;
+                        int li = jj[0] + fm.n[0] * (jj[1] + fm.n[1] * jj[2]);
+                        if (solid_at(li)) j = fm.cell0 + li;
+                        else {
+                            kind = g.pore_bc;
+                            wraps = false;
+                        }
+                    }
+                    uint32_t bits = 0;
+                    if (j >= 0) {
+                        bits |= side > 0 ? 2u : 1u;
+                        if (wraps) bits |= side > 0 ? 8u : 4u;
+                        p->nb[(size_t)fidx * nc + c] = j;
+                    } else {
+                        bits |= (uint32_t)kind << (side > 0 ? 6 : 4);
+                        if (outer) code |= 1u << ((side > 0 ? 28 : 25) + a);
+                        if (kind == BTE_BC_THERMAL) thermal = 1;
+                        if (kind == BTE_BC_DIFFUSE) {
+                            if (p->dbase[c] < 0) p->dbase[c] = nw;
+                            p->wrec.push_back(c);
+                            p->wrec.push_back(fidx);
+                            ++nw;
+                        }
+                    }
+                    code |= bits << (8 * a);
+                }
+            }
+            p->code[c] = code;
+        }
+        if (nsolid == 0) FAIL(p, BTE_ERR_ARG, "geometry %d has no solid cell", f);
+        fm.nsolid = nsolid;
+        fm.floating = thermal ? 0 : 1;
+        p->floating_any |= fm.floating;
+        p->thermal_any |= thermal;
+    }
+    p->nw = nw;
+    return BTE_OK;
+}
+
+bte_status build_quadrature(bte_problem *p, int n_theta, int n_phi)
+{
+    if (n_theta < 1 || (p->dim > 1 && n_phi < 1)) FAIL(p, BTE_ERR_ARG, "n_theta/n_phi must be >= 1");
+    std::vector<double> xt, wt, xp, wp;
+    gauss_legendre(n_theta, xt, wt);
+    std::vector<double> th(n_theta), wth(n_theta);
+    for (int i = 0; i < n_theta; ++i) {
+        th[i] = (xt[i] + 1.0) * M_PI / 4.0;
+        wth[i] = wt[i] * M_PI / 4.0;
+    }
+    p->s.clear();
+    p->w.clear();
+    if (p->dim == 1) {
+        for (int h = 0; h < 2; ++h)
+            for (int i = 0; i < n_theta; ++i) {
+                p->s.push_back((h ? -1.0 : 1.0) * std::cos(th[i]));
+                p->s.push_back(0.0);
+                p->s.push_back(0.0);
+                p->w.push_back(2.0 * M_PI * wth[i] * std::sin(th[i]));
+            }
+        p->noct = 2;
+    } else {
+        gauss_legendre(n_phi, xp, wp);
+        for (int o = 0; o < 8; ++o)
+            for (int i = 0; i < n_theta; ++i)
+                for (int j = 0; j < n_phi; ++j) {
+                    double ph = (xp[j] + 1.0) * M_PI / 4.0, wph = wp[j] * M_PI / 4.0, st = std::sin(th[i]);
+                    p->s.push_back((o & 1 ? -1.0 : 1.0) * st * std::cos(ph));
+                    p->s.push_back((o & 2 ? -1.0 : 1.0) * st * std::sin(ph));
+                    p->s.push_back((o & 4 ? -1.0 : 1.0) * std::cos(th[i]));
+                    p->w.push_back(wth[i] * wph * st);
+                }
+        p->noct = 8;
+    }
+    p->na = (int)p->w.size();
+    p->na_oct = p->na / p->noct;
+    double sw = 0;
+    for (double x : p->w) sw += x;
+    for (double &x : p->w) x *= 4.0 * M_PI / sw;   // exact 4 pi: equilibrium is a fixed point
+    p->mirror.assign(3 * (size_t)p->na, 0);
+    for (int a = 0; a < 3; ++a)
+        for (int al = 0; al < p->na; ++al) {
+            if (a >= p->dim) {
+                p->mirror[a * p->na + al] = al;
+                continue;
+            }
+            int best = -1;
+            double bd = 1e300;
+            for (int b = 0; b < p->na; ++b) {
+                double dd = 0;
+                for (int q = 0; q < 3; ++q) {
+                    double t = p->s[3 * al + q] * (q == a ? -1.0 : 1.0);
+                    dd += std::fabs(p->s[3 * b + q] - t);
+                }
+                if (dd < bd) bd = dd, best = b;
+            }
+            p->mirror[a * p->na + al] = best;
+        }
+    for (int a = 0; a < 3; ++a) {
+        double m = 0, h = 0;
+        for (int al = 0; al < p->na; ++al) {
+            double sa = p->s[3 * al + a];
+            m += p->w[al] * sa * sa;
+            if (sa > 0) h += p->w[al] * sa;
+        }
+        p->M[a] = m / (4.0 * M_PI);
+        p->H[a] = h;
+    }
+    for (int f = 0; f < 6; ++f) {
+        int a = f / 2, side = (f & 1) ? 1 : -1;
+        double den = 0;
+        for (int al = 0; al < p->na; ++al) {
+            double sn = p->s[3 * al + a] * side;
+            if (sn < 0) den += p->w[al] * (-sn);
+        }
+        p->wden[f] = den > 0 ? den : 1.0;
+    }
+    return BTE_OK;
+}
+
+void build_schedule(bte_problem *p)
+{
+    // tiles of 64 cells: 64 (1D), 8x8 (2D), 4x4x4 (3D)
+    if (p->dim == 1) p->tdim = make_int3(64, 1, 1);
+    else if (p->dim == 2) p->tdim = make_int3(8, 8, 1);
+    else p->tdim = make_int3(4, 4, 4);
+    const int lanes_oct = p->na_oct * p->nl;
+    p->nchunk_oct = (lanes_oct + 63) / 64;
+    struct Rec {
+        int d;
+        SweepItem it;
+    };
+    std::vector<Rec> recs;
+    int maxd = 0;
+    for (int f = 0; f < p->nfilm; ++f) {
+        const Film &fm = p->films[f];
+        const int nt[3] = {(fm.n[0] + p->tdim.x - 1) / p->tdim.x, (fm.n[1] + p->tdim.y - 1) / p->tdim.y,
+                           (fm.n[2] + p->tdim.z - 1) / p->tdim.z};
+        for (int o = 0; o < p->noct; ++o) {
+            int sg[3];
+            for (int a = 0; a < 3; ++a) sg[a] = p->s[3 * (o * p->na_oct) + a] > 0 ? 1 : -1;
+            for (int tz = 0; tz < nt[2]; ++tz)
+                for (int ty = 0; ty < nt[1]; ++ty)
+                    for (int tx = 0; tx < nt[0]; ++tx) {
+                        const int fx = sg[0] > 0 ? tx : nt[0] - 1 - tx;
+                        const int fy = sg[1] > 0 ? ty : nt[1] - 1 - ty;
+                        const int fz = sg[2] > 0 ? tz : nt[2] - 1 - tz;
+                        const int dg = fx + fy + (p->dim > 2 ? fz : tz);
+                        maxd = std::max(maxd, dg);
+                        for (int ch = 0; ch < p->nchunk_oct; ++ch)
+                            recs.push_back({dg, {f, o, ch, tx + nt[0] * (ty + nt[1] * tz)}});
+                    }
+        }
+    }
+    std::stable_sort(recs.begin(), recs.end(), [](const Rec &a, const Rec &b) { return a.d < b.d; });
+    p->items.clear();
+    p->diag_off.assign(maxd + 2, 0);
+    for (auto &r : recs) {
+        p->items.push_back(r.it);
+        p->diag_off[r.d + 1]++;
+    }
+    for (int d = 0; d <= maxd; ++d) p->diag_off[d + 1] += p->diag_off[d];
+}
+
+void plan_workspace(bte_problem *p)
+{
+    p->layout.clear();
+    size_t off = 0;
+    auto add = [&](const char *name, size_t bytes) {
+        p->layout.push_back({name, {off, bytes}});
+        off = align256(off + std::max<size_t>(bytes, 8));
+    };
+    const size_t nc = p->nc;
+    add("s", 8 * p->s.size());
+    add("w", 8 * p->w.size());
+    add("mirror", 4 * p->mirror.size());
+    add("C4", 8 * p->nl);
+    add("v", 8 * p->nl);
+    add("itau", 8 * p->nl);
+    add("film", sizeof(Film) * p->nfilm);
+    add("code", 4 * nc);
+    add("nb", 4 * 6 * nc);
+    add("fid", 4 * nc);
+    add("dbase", 4 * nc);
+    add("wrec", 4 * p->wrec.size());
+    add("wden", 8 * 6);
+    add("items", sizeof(SweepItem) * p->items.size());
+    for (const char *n : {"gamma", "P", "S", "TL", "TLkin", "T0", "T1", "q0", "q1", "r", "delta", "dpend", "cg_x",
+                          "cg_r", "cg_z", "cg_p", "cg_Ap", "cg_diag"})
+        add(n, 8 * nc);
+    add("kdif", 8 * 3 * nc);
+    add("kcor", 8 * 3 * nc);
+    add("fmean", 8 * p->nfilm);
+    add("feps", 8 * 5 * p->nfilm);
+    add("cg_part", 8 * 4 * (size_t)((nc + kBlock - 1) / kBlock));
+    add("cg_scal", 8 * 16);
+    add("din", 8 * (size_t)p->nw * p->nl);
+    const int nchunk_stream = (p->nk + kBlock - 1) / kBlock;
+    p->npart_max = std::max(nchunk_stream, p->noct * p->nchunk_oct);
+    add("part", 8 * (size_t)kMomN * nc * p->npart_max);
+    add("e2", p->esize() * p->nelem());
+    p->ws_bytes = off;
+}
+
+template <typename X> X *wsptr(bte_problem *p, const char *name)
+{
+    for (auto &l : p->layout)
+        if (l.first == name) return reinterpret_cast<X *>(p->ws + l.second.off);
+    return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+bte_status bte_setup(const bte_geometry *geo, int n_geo, const bte_material *mat, const bte_control *ctl,
+                     bte_problem **out)
+{
+    if (!out) return BTE_ERR_ARG;
+    *out = nullptr;
+    bte_problem *p = new (std::nothrow) bte_problem();
+    if (!p) return BTE_ERR_ARG;
+    bte_status st = BTE_OK;
+    auto bail = [&](bte_status s) {
+        // keep the handle so the caller can read the message
+        *out = p;
+        return s;
+    };
+    if (!geo || n_geo < 1 || !mat || !ctl) {
+        p->err = "null argument or n_geo < 1";
+        return bail(BTE_ERR_ARG);
+    }
+    if (geo[0].dim < 1 || geo[0].dim > 3) {
+        p->err = "dim must be 1, 2 or 3";
+        return bail(BTE_ERR_ARG);
+    }
+    if (mat->n_bands < 1 || mat->n_bands > 256 || !mat->C || !mat->v || !mat->tau) {
+        p->err = "n_bands must be in [1, 256] with C, v, tau given";
+        return bail(BTE_ERR_ARG);
+    }
+    p->ctl = *ctl;
+    if (p->ctl.precision != BTE_F32 && p->ctl.precision != BTE_F64) {
+        p->err = "precision must be BTE_F32 or BTE_F64";
+        return bail(BTE_ERR_ARG);
+    }
+    if (p->ctl.scheme != BTE_SEQUENTIAL && p->ctl.scheme != BTE_SYNTHETIC) {
+        p->err = "scheme must be sequential or synthetic";
+        return bail(BTE_ERR_ARG);
+    }
+    if (p->ctl.limiter < 0 || p->ctl.limiter > 2) {
+        p->err = "bad limiter";
+        return bail(BTE_ERR_ARG);
+    }
+    if (p->ctl.max_iter <= 0) p->ctl.max_iter = 10000;
+    if (p->ctl.cg_max_iter <= 0) p->ctl.cg_max_iter = 2000;
+    if (!(p->ctl.cg_rtol > 0)) p->ctl.cg_rtol = 1e-10;
+    p->Tref = mat->T_ref;
+    p->nl = mat->n_bands;
+    p->C4.resize(p->nl);
+    p->v.resize(p->nl);
+    p->itau.resize(p->nl);
+    p->Ctot = 0;
+    for (int l = 0; l < p->nl; ++l) {
+        if (!(mat->C[l] > 0) || !(mat->v[l] >= 0) || !(mat->tau[l] > 0)) {
+            p->err = "band properties must satisfy C > 0, v >= 0, tau > 0";
+            return bail(BTE_ERR_ARG);
+        }
+        p->C4[l] = mat->C[l] * kInvFourPi;
+        p->v[l] = mat->v[l];
+        p->itau[l] = 1.0 / mat->tau[l];
+        p->Ctot += mat->C[l];
+        p->vmax = std::max(p->vmax, mat->v[l]);
+        p->itau_max = std::max(p->itau_max, p->itau[l]);
+    }
+    if ((st = build_geometry(p, geo, n_geo)) != BTE_OK) return bail(st);
+    if ((st = build_quadrature(p, mat->n_theta, mat->n_phi)) != BTE_OK) return bail(st);
+    p->nk = p->na * p->nl;
+    build_schedule(p);
+    plan_workspace(p);
+    *out = p;
+    return BTE_OK;
+}
+
+size_t bte_workspace_bytes(const bte_problem *p) { return p ? p->ws_bytes : 0; }
+size_t bte_num_unknowns(const bte_problem *p) { return p ? p->nelem() : 0; }
+int bte_num_cells(const bte_problem *p) { return p ? p->nc : 0; }
+int bte_num_directions(const bte_problem *p) { return p ? p->na : 0; }
+
+bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!ws || bytes < p->ws_bytes) FAIL(p, BTE_ERR_ARG, "workspace too small (%zu < %zu)", bytes, p->ws_bytes);
+    if ((uintptr_t)ws & 255) FAIL(p, BTE_ERR_ARG, "workspace must be 256-byte aligned");
+    p->ws = (char *)ws;
+    auto up = [&](const char *name, const void *src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpy(wsptr<char>(p, name), src, n, hipMemcpyHostToDevice);
+    };
+    HIPCHK(p, up("s", p->s.data(), 8 * p->s.size()));
+    HIPCHK(p, up("w", p->w.data(), 8 * p->w.size()));
+    HIPCHK(p, up("mirror", p->mirror.data(), 4 * p->mirror.size()));
+    HIPCHK(p, up("C4", p->C4.data(), 8 * p->nl));
+    HIPCHK(p, up("v", p->v.data(), 8 * p->nl));
+    HIPCHK(p, up("itau", p->itau.data(), 8 * p->nl));
+    HIPCHK(p, up("film", p->films.data(), sizeof(Film) * p->nfilm));
+    HIPCHK(p, up("code", p->code.data(), 4 * (size_t)p->nc));
+    HIPCHK(p, up("nb", p->nb.data(), 4 * p->nb.size()));
+    HIPCHK(p, up("fid", p->fid.data(), 4 * (size_t)p->nc));
+    HIPCHK(p, up("dbase", p->dbase.data(), 4 * (size_t)p->nc));
+    HIPCHK(p, up("wrec", p->wrec.data(), 4 * p->wrec.size()));
+    HIPCHK(p, up("wden", p->wden, 8 * 6));
+    HIPCHK(p, up("items", p->items.data(), sizeof(SweepItem) * p->items.size()));
+    Dev &d = p->dev;
+    d.dim = p->dim;
+    d.nc = p->nc;
+    d.na = p->na;
+    d.nl = p->nl;
+    d.nk = p->nk;
+    d.nfilm = p->nfilm;
+    d.limiter = p->ctl.limiter;
+    d.Ctot = p->Ctot;
+    d.poreT = 0.0;
+    d.s = wsptr<double>(p, "s");
+    d.w = wsptr<double>(p, "w");
+    d.mirror = wsptr<int>(p, "mirror");
+    d.C4 = wsptr<double>(p, "C4");
+    d.v = wsptr<double>(p, "v");
+    d.itau = wsptr<double>(p, "itau");
+    d.film = wsptr<Film>(p, "film");
+    d.code = wsptr<uint32_t>(p, "code");
+    d.nb = wsptr<int>(p, "nb");
+    d.fid = wsptr<int>(p, "fid");
+    d.dbase = wsptr<int>(p, "dbase");
+    p->gamma = wsptr<double>(p, "gamma");
+    p->P = wsptr<double>(p, "P");
+    p->S = wsptr<double>(p, "S");
+    d.gamma = p->gamma;
+    d.P = nullptr;
+    d.S = p->S;
+    p->kdif = wsptr<double>(p, "kdif");
+    p->kcor = wsptr<double>(p, "kcor");
+    p->TL = wsptr<double>(p, "TL");
+    p->TLkin = wsptr<double>(p, "TLkin");
+    p->T0 = wsptr<double>(p, "T0");
+    p->T1 = wsptr<double>(p, "T1");
+    p->q0 = wsptr<double>(p, "q0");
+    p->q1 = wsptr<double>(p, "q1");
+    p->r = wsptr<double>(p, "r");
+    p->delta = wsptr<double>(p, "delta");
+    p->dpend = wsptr<double>(p, "dpend");
+    p->fmean = wsptr<double>(p, "fmean");
+    p->feps = wsptr<double>(p, "feps");
+    p->cg_x = wsptr<double>(p, "cg_x");
+    p->cg_r = wsptr<double>(p, "cg_r");
+    p->cg_z = wsptr<double>(p, "cg_z");
+    p->cg_p = wsptr<double>(p, "cg_p");
+    p->cg_Ap = wsptr<double>(p, "cg_Ap");
+    p->cg_diag = wsptr<double>(p, "cg_diag");
+    p->cg_part = wsptr<double>(p, "cg_part");
+    p->cg_scal = wsptr<double>(p, "cg_scal");
+    p->din = wsptr<double>(p, "din");
+    p->part = wsptr<double>(p, "part");
+    p->e2 = wsptr<void>(p, "e2");
+    p->d_items = wsptr<SweepItem>(p, "items");
+    p->d_wrec = wsptr<int>(p, "wrec");
+    p->d_wden = wsptr<double>(p, "wden");
+    // default fields: no source, no extra scattering
+    HIPCHK(p, hipMemset(p->gamma, 0, 8 * (size_t)p->nc));
+    HIPCHK(p, hipMemset(p->P, 0, 8 * (size_t)p->nc));
+    launch_cell_setup(p->dev, p->S, p->kdif, p->kcor, p->M, p->H, nullptr);
+    HIPCHK(p, hipGetLastError());
+    HIPCHK(p, hipDeviceSynchronize());
+    p->fields_set = true;
+    return BTE_OK;
+}
+
+bte_status bte_set_fields(bte_problem *p, const double *P_dev, const double *gamma_dev, void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = 8 * (size_t)p->nc;
+    if (P_dev) HIPCHK(p, hipMemcpyAsync(p->P, P_dev, nb, hipMemcpyDeviceToDevice, s));
+    else HIPCHK(p, hipMemsetAsync(p->P, 0, nb, s));
+    if (gamma_dev) HIPCHK(p, hipMemcpyAsync(p->gamma, gamma_dev, nb, hipMemcpyDeviceToDevice, s));
+    else HIPCHK(p, hipMemsetAsync(p->gamma, 0, nb, s));
+    p->dev.P = P_dev ? p->P : nullptr;
+    launch_cell_setup(p->dev, p->S, p->kdif, p->kcor, p->M, p->H, s);
+    HIPCHK(p, hipGetLastError());
+    return BTE_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- device flows
+
+namespace {
+
+template <typename T> bte_status moments_to(bte_problem *p, const T *e, const double *dpend, hipStream_t s)
+{
+    // one partial per cell in part[0]
+    launch_moments<T>(p->dev, e, dpend, p->part, s);
+    return BTE_OK;
+}
+
+// Jacobi-preconditioned CG on the heat-diffusion (corr = 0) or correction
+// (corr = 1) operator; b is projected per floating geometry beforehand, x is
+// projected afterwards.  Returns iterations, -1 on HIP error.
+int run_cg(bte_problem *p, int corr, double *b, double *x_out, double rtol, int maxit, hipStream_t s)
+{
+    const Dev &d = p->dev;
+    if (p->floating_any) {
+        launch_film_mean(d, b, p->fmean, s);
+        launch_sub_film_mean(d, b, p->fmean, s);
+    }
+    CgArgs g;
+    g.kax = corr ? p->kcor : p->kdif;
+    double cv = 0;
+    for (int l = 0; l < p->nl; ++l) cv += p->C4[l] * 4.0 * M_PI * p->v[l];
+    for (int a = 0; a < 3; ++a) g.Hm[a] = cv * p->H[a] / (2.0 * M_PI);
+    g.corr = corr;
+    g.x = p->cg_x;
+    g.r = p->cg_r;
+    g.z = p->cg_z;
+    g.p = p->cg_p;
+    g.Ap = p->cg_Ap;
+    g.diag = p->cg_diag;
+    g.part = p->cg_part;
+    g.scal = p->cg_scal;
+    g.rtol2 = rtol * rtol;
+    launch_cg_init(d, g, b, s);
+    int it = 0;
+    const int poll = 8;
+    double sc[16];
+    while (it < maxit) {
+        int n = std::min(poll, maxit - it);
+        for (int i = 0; i < n; ++i) launch_cg_iter(d, g, it + i, s);
+        it += n;
+        if (hipMemcpyAsync(sc, p->cg_scal, sizeof sc, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+        if (hipStreamSynchronize(s) != hipSuccess) return -1;
+        if (sc[5] != 0.0) break;
+    }
+    if (hipMemcpyAsync(sc, p->cg_scal, sizeof sc, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    if (p->floating_any) {
+        launch_film_mean(d, p->cg_x, p->fmean, s);
+        launch_sub_film_mean(d, p->cg_x, p->fmean, s);
+    }
+    if (hipMemcpyAsync(x_out, p->cg_x, 8 * (size_t)p->nc, hipMemcpyDeviceToDevice, s) != hipSuccess) return -1;
+    return (int)sc[6];
+}
+
+template <typename T>
+bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, hipStream_t s)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    const Dev &d = p->dev;
+    const int nc = p->nc;
+    const int synthetic = p->ctl.scheme == BTE_SYNTHETIC;
+    bte_solve_stats st{};
+    T *buf[2] = {e, (T *)p->e2};
+    int cur = 0;
+    HIPCHK(p, hipMemsetAsync(p->dpend, 0, 8 * (size_t)nc, s));
+    if (init) {
+        CgArgs g{};
+        g.kax = p->kdif;
+        g.corr = 0;
+        launch_diff_rhs(d, g, p->r, s);
+        int it = run_cg(p, 0, p->r, p->T0, 1e-13, 200000, s);
+        if (it < 0) FAIL(p, BTE_ERR_HIP, "CG failed");
+        launch_set_equilibrium<T>(d, e, p->T0, s);
+    }
+    // moments of the start field
+    launch_moments<T>(d, e, nullptr, p->part, s);
+    launch_finalize(d, p->part, 1, p->Tref, nullptr, nullptr, nullptr, p->TL, p->T0, p->q0, s);
+    std::vector<double> feps(5 * (size_t)p->nfilm);
+    const int np = p->noct * p->nchunk_oct;
+    bte_status ret = BTE_ERR_NOT_CONVERGED;
+    for (int iter = 1; iter <= p->ctl.max_iter; ++iter) {
+        const T *ein = buf[cur];
+        T *eout = buf[1 - cur];
+        launch_walls<T>(d, ein, p->dpend, p->d_wrec, p->d_wden, p->din, p->nw, s);
+        for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
+            const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
+            launch_sweep<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt, p->tdim, p->na_oct,
+                            p->nchunk_oct, p->part, s);
+        }
+        launch_steady_post(d, p->part, np, p->TL, p->TLkin, p->T1, p->q1, p->r, synthetic, s);
+        launch_film_eps(d, p->T0, p->T1, p->q0, p->q1, p->feps, s);
+        HIPCHK(p, hipGetLastError());
+        if (synthetic) {
+            int it = run_cg(p, 1, p->r, p->delta, p->ctl.cg_rtol, p->ctl.cg_max_iter, s);
+            if (it < 0) FAIL(p, BTE_ERR_HIP, "CG failed");
+            st.cg_iters += it;
+            launch_tl_update(nc, p->TLkin, p->delta, p->TL, p->dpend, s);
+        } else {
+            launch_tl_update(nc, p->TLkin, nullptr, p->TL, nullptr, s);
+        }
+        HIPCHK(p, hipMemcpyAsync(feps.data(), p->feps, 8 * feps.size(), hipMemcpyDeviceToHost, s));
+        HIPCHK(p, hipStreamSynchronize(s));
+        double eT = 0, eq = 0;
+        bool finite = true;
+        for (int f = 0; f < p->nfilm; ++f) {
+            const Film &fm = p->films[f];
+            const double *o = &feps[5 * f];
+            double a = std::sqrt(o[0] / fm.nsolid) / (o[1] > 1e-300 ? o[1] : 1.0);
+            double b = std::sqrt(o[2] / fm.nsolid) / (o[3] > 1e-300 ? o[3] : 1.0);
+            if (!std::isfinite(a) || !std::isfinite(b)) finite = false;
+            eT = std::max(eT, a);
+            eq = std::max(eq, b);
+        }
+        std::swap(p->T0, p->T1);
+        std::swap(p->q0, p->q1);
+        cur = 1 - cur;
+        st.iters = iter;
+        st.eps_T = eT;
+        st.eps_q = eq;
+        if (!finite) {
+            ret = BTE_ERR_NONFINITE;
+            break;
+        }
+        if (eT <= p->ctl.residual_temp && eq <= p->ctl.residual_flux) {
+            st.converged = 1;
+            ret = BTE_OK;
+            break;
+        }
+    }
+    // final field: pending correction and, for floating geometries, the gauge
+    // shift to zero mean T - T_ref (T0 now holds the last moments)
+    double *fshift = nullptr;
+    if (p->floating_any) {
+        launch_film_mean(d, p->T0, p->fmean, s);
+        // only floating films are shifted: zero the others on the host side
+        std::vector<double> fm(p->nfilm);
+        HIPCHK(p, hipMemcpyAsync(fm.data(), p->fmean, 8 * fm.size(), hipMemcpyDeviceToHost, s));
+        HIPCHK(p, hipStreamSynchronize(s));
+        for (int f = 0; f < p->nfilm; ++f)
+            if (!p->films[f].floating) fm[f] = 0.0;
+        HIPCHK(p, hipMemcpyAsync(p->fmean, fm.data(), 8 * fm.size(), hipMemcpyHostToDevice, s));
+        fshift = p->fmean;
+    }
+    launch_apply_shift<T>(d, buf[cur], e, synthetic ? p->dpend : nullptr, fshift, s);
+    HIPCHK(p, hipGetLastError());
+    HIPCHK(p, hipStreamSynchronize(s));
+    st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    if (ret == BTE_ERR_NOT_CONVERGED) p->err = "not converged within max_iter";
+    if (ret == BTE_ERR_NONFINITE) p->err = "non-finite convergence measure";
+    return ret;
+}
+
+template <typename T>
+bte_status transient_impl(bte_problem *p, T *e, int n_steps, double t0, const double *pulse, hipStream_t s)
+{
+    const Dev &d = p->dev;
+    const double dt = p->ctl.dt;
+    T *buf[2] = {e, (T *)p->e2};
+    int cur = 0;
+    const int cpb = 4;
+    launch_moments<T>(d, e, nullptr, p->part, s);
+    launch_finalize(d, p->part, 1, p->Tref, nullptr, nullptr, nullptr, p->TL, nullptr, nullptr, s);
+    const int nchunk = (p->nk + kBlock - 1) / kBlock;
+    for (int n = 0; n < n_steps; ++n) {
+        const double t = t0 + n * dt;
+        double src = 1.0;
+        if (pulse) {
+            const double x = t - pulse[0];
+            src = std::exp(-4.0 * std::log(2.0) * x * x / (pulse[1] * pulse[1]));
+        }
+        launch_walls<T>(d, buf[cur], nullptr, p->d_wrec, p->d_wden, p->din, p->nw, s);
+        launch_transient<T>(d, buf[cur], buf[1 - cur], p->TL, p->din, src, dt, p->part, cpb, s);
+        launch_finalize(d, p->part, nchunk, p->Tref, nullptr, nullptr, nullptr, p->TL, nullptr, nullptr, s);
+        cur = 1 - cur;
+    }
+    if (cur != 0) HIPCHK(p, hipMemcpyAsync(e, buf[cur], p->esize() * p->nelem(), hipMemcpyDeviceToDevice, s));
+    HIPCHK(p, hipGetLastError());
+    return BTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bte_status bte_moments(bte_problem *p, const void *e_dev, double *T_dev, double *TL_dev, double *q_dev, void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
+    if (!e_dev) FAIL(p, BTE_ERR_ARG, "e is null");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->ctl.precision == BTE_F64) launch_moments<double>(p->dev, (const double *)e_dev, nullptr, p->part, s);
+    else launch_moments<float>(p->dev, (const float *)e_dev, nullptr, p->part, s);
+    launch_finalize(p->dev, p->part, 1, p->Tref, T_dev, TL_dev, q_dev, nullptr, nullptr, nullptr, s);
+    HIPCHK(p, hipGetLastError());
+    return BTE_OK;
+}
+
+bte_status bte_residual(bte_problem *p, const void *e_dev, void *R_dev, void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
+    if (!e_dev || !R_dev) FAIL(p, BTE_ERR_ARG, "null e or R");
+    if (e_dev == R_dev) FAIL(p, BTE_ERR_ARG, "R must not alias e");
+    hipStream_t s = (hipStream_t)stream;
+    const Dev &d = p->dev;
+    if (p->ctl.precision == BTE_F64) {
+        launch_moments<double>(d, (const double *)e_dev, nullptr, p->part, s);
+        launch_finalize(d, p->part, 1, p->Tref, nullptr, nullptr, nullptr, p->TL, nullptr, nullptr, s);
+        launch_walls<double>(d, (const double *)e_dev, nullptr, p->d_wrec, p->d_wden, p->din, p->nw, s);
+        launch_residual<double>(d, (const double *)e_dev, (double *)R_dev, p->TL, p->din, 4, s);
+    } else {
+        launch_moments<float>(d, (const float *)e_dev, nullptr, p->part, s);
+        launch_finalize(d, p->part, 1, p->Tref, nullptr, nullptr, nullptr, p->TL, nullptr, nullptr, s);
+        launch_walls<float>(d, (const float *)e_dev, nullptr, p->d_wrec, p->d_wden, p->din, p->nw, s);
+        launch_residual<float>(d, (const float *)e_dev, (float *)R_dev, p->TL, p->din, 4, s);
+    }
+    HIPCHK(p, hipGetLastError());
+    return BTE_OK;
+}
+
+bte_status bte_transient_step(bte_problem *p, void *e_dev, int n_steps, double t0, const double *pulse, void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
+    if (!e_dev) FAIL(p, BTE_ERR_ARG, "e is null");
+    if (n_steps < 0) FAIL(p, BTE_ERR_ARG, "n_steps < 0");
+    if (!(p->ctl.dt > 0)) FAIL(p, BTE_ERR_ARG, "control.dt must be > 0");
+    if (pulse && !(pulse[1] > 0)) FAIL(p, BTE_ERR_ARG, "pulse FWHM must be > 0");
+    double adv = 0;
+    for (const Film &fm : p->films) {
+        double a = 0;
+        for (int q = 0; q < p->dim; ++q) a += fm.ih[q];
+        adv = std::max(adv, a);
+    }
+    if (p->ctl.dt * p->itau_max >= 1.0 || p->ctl.dt * p->vmax * adv >= 1.0)
+        FAIL(p, BTE_ERR_CFL, "dt violates dt/tau_min < 1 or dt v_max sum_a 1/h_a < 1");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->ctl.precision == BTE_F64) return transient_impl<double>(p, (double *)e_dev, n_steps, t0, pulse, s);
+    return transient_impl<float>(p, (float *)e_dev, n_steps, t0, pulse, s);
+}
+
+bte_status bte_steady_solve(bte_problem *p, void *e_dev, int init, bte_solve_stats *stats, void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
+    if (!e_dev) FAIL(p, BTE_ERR_ARG, "e is null");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->ctl.precision == BTE_F64) return steady_impl<double>(p, (double *)e_dev, init, stats, s);
+    return steady_impl<float>(p, (float *)e_dev, init, stats, s);
+}
+
+bte_status bte_keff(bte_problem *p, const void *e_dev, double *keff_dev, void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
+    if (!e_dev || !keff_dev) FAIL(p, BTE_ERR_ARG, "null argument");
+    for (const Film &fm : p->films)
+        if (fm.pdT[0] == 0.0) FAIL(p, BTE_ERR_ARG, "k_eff needs periodic_dT[0] != 0");
+    hipStream_t s = (hipStream_t)stream;
+    const Dev &d = p->dev;
+    if (p->ctl.precision == BTE_F64) launch_moments<double>(d, (const double *)e_dev, nullptr, p->part, s);
+    else launch_moments<float>(d, (const float *)e_dev, nullptr, p->part, s);
+    // q[nc][3] after the first partial set (part holds >= 2 sets of kMomN per cell)
+    double *q = p->part + (size_t)kMomN * p->nc;
+    launch_finalize(d, p->part, 1, p->Tref, nullptr, nullptr, q, nullptr, nullptr, nullptr, s);
+    launch_keff(d, q, keff_dev, s);
+    HIPCHK(p, hipGetLastError());
+    return BTE_OK;
+}
+
+bte_status bte_adjoint(bte_problem *p, const void *, int, double *, bte_solve_stats *, void *)
+{
+    if (!p) return BTE_ERR_ARG;
+    FAIL(p, BTE_ERR_UNSUPPORTED, "adjoint not built yet");
+}
+
+bte_status bte_get_directions(const bte_problem *p, double *s_host, double *w_host)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (s_host) std::memcpy(s_host, p->s.data(), 8 * p->s.size());
+    if (w_host) std::memcpy(w_host, p->w.data(), 8 * p->w.size());
+    return BTE_OK;
+}
+
+const char *bte_last_error(const bte_problem *p) { return p ? p->err.c_str() : "null handle"; }
+
+void bte_destroy(bte_problem *p) { delete p; }
+
+}  // extern "C"

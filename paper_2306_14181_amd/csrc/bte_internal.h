@@ -1,0 +1,84 @@
+// bte_internal.h -- device data structures shared by the gfx950 kernels and
+// the host runtime of the phonon-BTE library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bte {
+
+constexpr double kFourPi = 12.566370614359172953850573533118;
+constexpr double kInvFourPi = 1.0 / kFourPi;
+constexpr int kBlock = 256;          // threads per block of the streaming kernels
+constexpr int kMomN = 5;             // moment partials: sum w e, sum w e/tau, q_x, q_y, q_z
+
+// Per-cell geometry code.  For each axis a the byte at bit 8a holds
+//   bit0 minus neighbour is a solid cell, bit1 plus neighbour is a solid cell,
+//   bit2 minus neighbour reached through a periodic face, bit3 plus ditto,
+//   bits4-5 wall kind on the minus side, bits6-7 wall kind on the plus side
+//   (bte_bc: 0 thermal, 1 specular, 2 diffuse) when that side is not a cell.
+// bit24 solid, bits 25+a: minus-side wall is an outer face (else a pore),
+// bits 28+a: plus-side wall is an outer face.
+constexpr uint32_t kSolidBit = 1u << 24;
+
+__host__ __device__ inline uint32_t axis_bits(uint32_t code, int a) { return (code >> (8 * a)) & 0xffu; }
+__host__ __device__ inline bool side_is_cell(uint32_t ab, int side) { return ab & (side > 0 ? 2u : 1u); }
+__host__ __device__ inline bool side_wraps(uint32_t ab, int side) { return ab & (side > 0 ? 8u : 4u); }
+__host__ __device__ inline int side_wall(uint32_t ab, int side) { return (ab >> (side > 0 ? 6 : 4)) & 3; }
+__host__ __device__ inline bool side_outer(uint32_t code, int a, int side)
+{
+    return code & (1u << ((side > 0 ? 28 : 25) + a));
+}
+__host__ __device__ inline int face_of(int a, int side) { return 2 * a + (side > 0 ? 1 : 0); }
+
+// One geometry of a batch.
+struct Film {
+    double h[3], ih[3];      // cell size and its inverse per axis
+    double pdT[3];           // periodic temperature drop per axis
+    double wallT[6];         // thermalizing wall temperature minus T_ref, per face
+    double len[3];
+    int n[3];
+    int cell0, ncell;        // first cell and number of cells in the global numbering
+    int nsolid;
+    int floating;            // no thermalizing wall: gauge fixed by zero mean T - T_ref
+};
+
+// Everything a kernel needs to evaluate the discrete operators.
+struct Dev {
+    int dim, nc, na, nl, nk, nfilm;
+    int limiter;
+    double Ctot;             // sum_lambda C
+    double poreT;            // thermalizing pore wall temperature minus T_ref
+    const double *s;         // [na][3]
+    const double *w;         // [na]
+    const int *mirror;       // [3][na]
+    const double *C4;        // [nl] C/(4 pi)
+    const double *v;         // [nl]
+    const double *itau;      // [nl] 1/tau
+    const Film *film;        // [nfilm]
+    const uint32_t *code;    // [nc]
+    const int *nb;           // [6][nc] neighbour cell per face (or -1)
+    const int *fid;          // [nc] geometry index
+    const int *dbase;        // [nc] first diffuse-wall record of the cell or -1
+    const double *gamma;     // [nc]
+    const double *P;         // [nc]
+    const double *S;         // [nc] sum_lambda C (1/tau + gamma)
+};
+
+// One work item of the sweep: a tile of one geometry for 64 lanes of one octant.
+struct SweepItem {
+    int film, oct, chunk, tile;
+};
+
+// Arguments of the conjugate-gradient kernels.
+struct CgArgs {
+    const double *kax;      // [3][nc] per-axis conductivity
+    double Hm[3];           // wall emission conductance sum C v H_a/(2pi) (correction operator only)
+    int corr;               // 1: correction operator, 0: heat diffusion
+    double *x, *r, *z, *p, *Ap, *diag;
+    double *part;           // [2][nblk][2] block partial sums
+    double *scal;           // [1] |b|^2, [2] p.Ap, [3] r.r, [5] done, [6] iterations, [7],[8] r.z by parity
+    double rtol2;
+};
+
+}  // namespace bte

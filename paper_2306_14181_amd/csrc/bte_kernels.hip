@@ -1,0 +1,899 @@
+// bte_kernels.hip -- gfx950 kernels of the phonon-BTE hot path.
+//
+// Streaming kernels work on e[cell][k] with k = alpha*n_bands + lambda; a
+// 256-thread block covers 256 consecutive k of one cell (coalesced 1 KiB
+// rows for FP32) and loops over a few cells.  Moments (eqs. BTE_get_e0,
+// getTQ) are accumulated in FP64 and reduced deterministically: a butterfly
+// within each 64-wide wavefront, then a fixed-order sum over the block's
+// wavefronts, then a fixed-order sum over k-chunks in a finalize kernel.
+#include "bte_internal.h"
+#include "bte_stencil.h"
+
+namespace bte {
+
+// ----------------------------------------------------------------- reductions
+
+template <int N>
+__device__ inline void wave_sum(double (&v)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double x = v[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[i] = x;
+    }
+}
+
+// Sum over a 256-thread block; the result is valid in thread 0.
+template <int N>
+__device__ inline void block_sum(double (&v)[N], double *sh)
+{
+    wave_sum<N>(v);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i) sh[wave * N + i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = sh[i] + sh[N + i] + sh[2 * N + i] + sh[3 * N + i];
+    __syncthreads();
+}
+
+// XCD-aware block numbering: consecutive dispatch slots go round-robin over
+// the 8 XCDs, so give each XCD a contiguous range of logical blocks (its own
+// k-chunk / cell range) to keep stencil neighbours in its L2.  grid % 8 == 0.
+__device__ inline int xcd_logical_block()
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// ------------------------------------------------------------------- per cell
+
+// S_c = sum C (1/tau + gamma_c); per-axis conductivities of the heat-diffusion
+// operator, k = sum C v^2 tau_c M_aa (M_aa = sum w s_a^2 / 4pi), and of the
+// correction operator, which adds the conduction of the sweep's first-order
+// upwind increment, sum C v h_a H_a / 4pi (H_a = sum_{s_a>0} w s_a).
+__global__ void k_cell_setup(Dev d, double *S, double *kdif, double *kcor, double m0, double m1, double m2,
+                             double H0, double H1, double H2)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.nc) return;
+    const double g = d.gamma ? d.gamma[c] : 0.0;
+    double sm = 0, k = 0, cv = 0;
+    for (int l = 0; l < d.nl; ++l) {
+        const double C = d.C4[l] * kFourPi;
+        const double it = d.itau[l] + g;
+        sm += C * it;
+        k += C * d.v[l] * d.v[l] / it;
+        cv += C * d.v[l];
+    }
+    S[c] = sm;
+    const double m[3] = {m0, m1, m2}, H[3] = {H0, H1, H2};
+    const Film &fm = d.film[d.fid[c]];
+    for (int a = 0; a < 3; ++a) {
+        kdif[a * d.nc + c] = k * m[a];
+        kcor[a * d.nc + c] = k * m[a] + cv * fm.h[a] * H[a] / kFourPi;
+    }
+}
+
+// ------------------------------------------------------------------- moments
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_moments(Dev d, const T *__restrict__ e, const double *__restrict__ dpend,
+                                                     double *__restrict__ part)
+{
+    __shared__ double sh[4 * kMomN];
+    const int c = blockIdx.x;
+    double acc[kMomN] = {0, 0, 0, 0, 0};
+    if (d.code[c] & kSolidBit) {
+        const double g = d.gamma[c];
+        const double dp = dpend ? dpend[c] : 0.0;
+        for (int k = threadIdx.x; k < d.nk; k += kBlock) {
+            const LaneConst L = lane_const(d, k);
+            const double x = (double)e[(size_t)c * d.nk + k] + L.C4 * dp;
+            const double wx = L.w * x;
+            acc[0] += wx;
+            acc[1] += wx * (L.itau + g);
+            const double vw = wx * L.v;
+            acc[2] += vw * L.s[0];
+            acc[3] += vw * L.s[1];
+            acc[4] += vw * L.s[2];
+        }
+    }
+    block_sum<kMomN>(acc, sh);
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kMomN; ++i) part[(size_t)c * kMomN + i] = acc[i];
+}
+
+// Sum np partials per cell -> T, T_L (absolute), q, T_L deviation, |q|.
+__global__ void k_finalize(Dev d, const double *__restrict__ part, int np, double Tref, double *T, double *TL,
+                           double *q, double *TLdev, double *Tdev, double *qmag)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.nc) return;
+    double s[kMomN] = {0, 0, 0, 0, 0};
+    for (int p = 0; p < np; ++p)
+        for (int i = 0; i < kMomN; ++i) s[i] += part[((size_t)p * d.nc + c) * kMomN + i];
+    const bool solid = d.code[c] & kSolidBit;
+    const double td = solid ? s[0] / d.Ctot : 0.0;
+    const double tl = solid ? s[1] / d.S[c] : 0.0;
+    if (T) T[c] = Tref + td;
+    if (TL) TL[c] = Tref + tl;
+    if (q)
+        for (int a = 0; a < 3; ++a) q[3 * c + a] = solid ? s[2 + a] : 0.0;
+    if (TLdev) TLdev[c] = tl;
+    if (Tdev) Tdev[c] = td;
+    if (qmag) qmag[c] = solid ? sqrt(s[2] * s[2] + s[3] * s[3] + s[4] * s[4]) : 0.0;
+}
+
+// ---------------------------------------------------------------- diffuse walls
+
+// Incoming value of each diffuse wall record (Sec. 2.2, eq. diff_bound, with
+// the discrete normalisation): sum_{s.n>0} w s.n e_face / sum_{s.n<0} w |s.n|.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_walls(Dev d, const T *__restrict__ e, const double *__restrict__ dpend,
+                                                   const int *__restrict__ wrec, const double *__restrict__ wden,
+                                                   double *__restrict__ din, int nw)
+{
+    __shared__ double sh[kBlock];
+    const int r = blockIdx.x;
+    if (r >= nw) return;
+    const int c = wrec[2 * r], f = wrec[2 * r + 1];
+    const int a = f >> 1, side = (f & 1) ? 1 : -1;
+    const Film &fm = d.film[d.fid[c]];
+    const uint32_t ab = axis_bits(d.code[c], a);
+    const bool hu = side_is_cell(ab, -side);
+    const int j1 = hu ? d.nb[face_of(a, -side) * d.nc + c] : -1;
+    const int G = kBlock / d.nl;     // groups of n_bands threads (n_bands <= 256)
+    const int grp = threadIdx.x / d.nl, l = threadIdx.x - grp * d.nl;
+    double sum = 0.0;
+    if (grp < G) {
+        const T C4 = (T)d.C4[l];
+        const T J = C4 * (T)fm.pdT[a];
+        const T jump1 = (hu && side_wraps(ab, -side)) ? (T)side * J : (T)0;
+        const T ih = (T)fm.ih[a], hh = (T)(0.5 * fm.h[a]);
+        for (int al = grp; al < d.na; al += G) {
+            const double sa = d.s[3 * al + a];
+            if (sa * side <= 0.0) continue;
+            const int k = al * d.nl + l;
+            const T ec = ld_e(e, dpend, d, c, k, C4);
+            T g = (T)0;
+            if (d.limiter == LIM_NONE && hu) g = (ec - (ld_e(e, dpend, d, j1, k, C4) + jump1)) * ih;
+            sum += d.w[al] * fabs(sa) * (double)(ec + hh * g);
+        }
+    }
+    sh[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x < d.nl) {
+        double t = 0.0;
+        for (int g2 = 0; g2 < G; ++g2) t += sh[g2 * d.nl + threadIdx.x];
+        din[(size_t)r * d.nl + threadIdx.x] = t / wden[f];
+    }
+}
+
+// ------------------------------------------------------------ transient step
+
+// Explicit step (Sec. 4.1, eq. disretized_transientBTE with V and dt placed
+// dimensionally): e' = e + dt [ -(1/V) sum_f e_f v s.n S - (e - C T_L/4pi)/tau + Q ],
+// with FP64 moment partials of e' per (k-chunk, cell).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_transient(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
+                                                       const double *__restrict__ TLdev, const double *__restrict__ din,
+                                                       double src, double dt, double *__restrict__ part, int nchunk,
+                                                       int ngroup, int cpb)
+{
+    __shared__ double sh[4 * kMomN];
+    const int lb = xcd_logical_block();
+    const int chunk = lb / ngroup, grp = lb - chunk * ngroup;
+    if (chunk >= nchunk) return;
+    const int k = chunk * kBlock + threadIdx.x;
+    const bool active = k < d.nk;
+    const LaneConst L = lane_const(d, active ? k : 0);
+    const int c0 = grp * cpb;
+    for (int ci = 0; ci < cpb; ++ci) {
+        const int c = c0 + ci;
+        if (c >= d.nc) break;
+        const uint32_t code = d.code[c];
+        double acc[kMomN] = {0, 0, 0, 0, 0};
+        if (!(code & kSolidBit)) {
+            if (active) eout[(size_t)c * d.nk + k] = ein[(size_t)c * d.nk + k];
+        } else {
+            const Film &fm = d.film[d.fid[c]];
+            const double itc = L.itau + d.gamma[c];
+            const double qsrc = d.P ? src * d.P[c] / d.Ctot : 0.0;
+            const double tl = TLdev[c];
+            if (active) {
+                const T ec = ein[(size_t)c * d.nk + k];
+                const StencilOut<T> so = stencil<T>(ein, nullptr, din, d, fm, c, code, L, ec);
+                const T e0 = (T)(L.C4 * tl);
+                const T en = ec + (T)dt * (-so.D - (ec - e0) * (T)itc + (T)(L.C4 * qsrc));
+                eout[(size_t)c * d.nk + k] = en;
+                const double x = L.w * (double)en;
+                acc[0] = x;
+                acc[1] = x * itc;
+                acc[2] = x * L.v * L.s[0];
+                acc[3] = x * L.v * L.s[1];
+                acc[4] = x * L.v * L.s[2];
+            }
+        }
+        block_sum<kMomN>(acc, sh);
+        if (threadIdx.x == 0)
+            for (int i = 0; i < kMomN; ++i) part[((size_t)chunk * d.nc + c) * kMomN + i] = acc[i];
+    }
+}
+
+// Steady residual R(e) with e0 from TLdev (right-hand side of eq. B_BTE).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual(Dev d, const T *__restrict__ e, T *__restrict__ R,
+                                                      const double *__restrict__ TLdev, const double *__restrict__ din,
+                                                      int nchunk, int ngroup, int cpb)
+{
+    const int lb = xcd_logical_block();
+    const int chunk = lb / ngroup, grp = lb - chunk * ngroup;
+    if (chunk >= nchunk) return;
+    const int k = chunk * kBlock + threadIdx.x;
+    if (k >= d.nk) return;
+    const LaneConst L = lane_const(d, k);
+    for (int ci = 0; ci < cpb; ++ci) {
+        const int c = grp * cpb + ci;
+        if (c >= d.nc) break;
+        const uint32_t code = d.code[c];
+        if (!(code & kSolidBit)) {
+            R[(size_t)c * d.nk + k] = (T)0;
+            continue;
+        }
+        const Film &fm = d.film[d.fid[c]];
+        const double itc = L.itau + d.gamma[c];
+        const double qsrc = d.P ? d.P[c] / d.Ctot : 0.0;
+        const T ec = e[(size_t)c * d.nk + k];
+        const StencilOut<T> so = stencil<T>(e, nullptr, din, d, fm, c, code, L, ec);
+        const T e0 = (T)(L.C4 * TLdev[c]);
+        R[(size_t)c * d.nk + k] = -so.D - (ec - e0) * (T)itc + (T)(L.C4 * qsrc);
+    }
+}
+
+// ------------------------------------------------------------------- sweep
+//
+// One source-iteration transport solve in delta form (eq. disretized_BTE;
+// stiffness matrix A and right-hand side b of Sec. 3.5):  A de = b with
+// b = R(e^n; T_L^n), A_ii = 1/tau + sum_a |v s_a|/h_a, A_ij = -|v s_a|/h_a for
+// the upwind neighbour across an interior face (walls and periodic faces
+// are lagged into b).  A is lower-triangular in the upwind order of each
+// octant, so the solve is a sweep.  Cells are grouped in tiles; tiles on
+// one wavefront (hyperplane) of an octant are independent and run in one
+// launch, successive wavefronts in successive launches.  A 256-thread block
+// handles one tile for 64 (direction, band) lanes of one octant:
+//   phase A (4 wavefronts): b for every cell of the tile, plus the inflow of
+//     the already-swept upstream tiles, into LDS;
+//   phase B (wavefront 0): the upwind recurrence across the tile's cells;
+//   phase C (4 wavefronts): e^{n+1} = e^n + de and FP64 moment partials.
+constexpr int kTileCells = 64;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
+                                                   const double *__restrict__ dpend, const double *__restrict__ TLdev,
+                                                   const double *__restrict__ din, const SweepItem *__restrict__ items,
+                                                   int item0, int3 tdim, int na_oct, int nchunk_oct,
+                                                   double *__restrict__ part)
+{
+    __shared__ T bsh[kTileCells][64];
+    __shared__ T esh[kTileCells][64];
+    __shared__ int cell_sh[kTileCells];
+    __shared__ int upin_sh[kTileCells][3];   // in-tile upwind flow index per axis or -1
+    __shared__ double gam_sh[kTileCells];
+
+    const SweepItem it = items[item0 + blockIdx.x];
+    const Film &fm = d.film[it.film];
+    const int wave = threadIdx.x >> 6, t = threadIdx.x & 63;
+    const int kbeg = it.oct * na_oct * d.nl;
+    const int kend = kbeg + na_oct * d.nl;
+    const int k = kbeg + it.chunk * 64 + t;
+    const bool active = k < kend;
+    const LaneConst L = lane_const(d, active ? k : kbeg);
+
+    // octant flow signs from a representative direction of the octant
+    int sg[3];
+    for (int a = 0; a < 3; ++a) sg[a] = d.s[3 * (it.oct * na_oct) + a] > 0 ? 1 : -1;
+
+    // tile origin and extent in film coordinates
+    const int ntx = (fm.n[0] + tdim.x - 1) / tdim.x, nty = (fm.n[1] + tdim.y - 1) / tdim.y;
+    const int tx = it.tile % ntx, ty = (it.tile / ntx) % nty, tz = it.tile / (ntx * nty);
+    const int x0 = tx * tdim.x, y0 = ty * tdim.y, z0 = tz * tdim.z;
+    const int ex = min(tdim.x, fm.n[0] - x0), ey = min(tdim.y, fm.n[1] - y0), ez = min(tdim.z, fm.n[2] - z0);
+    const int ncell = ex * ey * ez;
+
+    // flow-ordered enumeration of the tile's cells
+    if (threadIdx.x < ncell) {
+        const int i = threadIdx.x;
+        const int fx = i % ex, fy = (i / ex) % ey, fz = i / (ex * ey);
+        const int ix = x0 + (sg[0] > 0 ? fx : ex - 1 - fx);
+        const int iy = y0 + (sg[1] > 0 ? fy : ey - 1 - fy);
+        const int iz = z0 + (d.dim > 2 ? (sg[2] > 0 ? fz : ez - 1 - fz) : fz);
+        const int c = fm.cell0 + ix + fm.n[0] * (iy + fm.n[1] * iz);
+        cell_sh[i] = c;
+        const uint32_t code = d.code[c];
+        const int f[3] = {fx, fy, fz};
+        const int stride[3] = {1, ex, ex * ey};
+        for (int a = 0; a < 3; ++a) {
+            int u = -1;
+            if (a < d.dim && f[a] > 0) {
+                const uint32_t ab = axis_bits(code, a);
+                if (side_is_cell(ab, -sg[a]) && !side_wraps(ab, -sg[a])) u = i - stride[a];
+            }
+            upin_sh[i][a] = u;
+        }
+        gam_sh[i] = d.gamma[c];
+    }
+    __syncthreads();
+
+    // phase A
+    for (int i = wave; i < ncell; i += 4) {
+        const int c = cell_sh[i];
+        const uint32_t code = d.code[c];
+        T b = (T)0, ec = (T)0;
+        if ((code & kSolidBit) && active) {
+            const T C4 = (T)L.C4;
+            ec = ld_e(ein, dpend, d, c, k, C4);
+            const StencilOut<T> so = stencil<T>(ein, dpend, din, d, fm, c, code, L, ec);
+            const double itc = L.itau + d.gamma[c];
+            b = -so.D - (ec - (T)(L.C4 * TLdev[c])) * (T)itc;
+            if (d.P) b += (T)(L.C4 * d.P[c] / d.Ctot);
+            for (int a = 0; a < d.dim; ++a)
+                if (so.jup[a] >= 0 && upin_sh[i][a] < 0) b += so.cup[a] * (eout[(size_t)so.jup[a] * d.nk + k] - so.eup[a]);
+        } else if (active) {
+            ec = ein[(size_t)c * d.nk + k];
+        }
+        bsh[i][t] = b;
+        esh[i][t] = ec;
+    }
+    __syncthreads();
+
+    // phase B
+    if (wave == 0 && active) {
+        T cpl[3];
+        T A0 = (T)0;
+        for (int a = 0; a < 3; ++a) {
+            cpl[a] = a < d.dim ? (T)(L.v * fabs(L.s[a]) * fm.ih[a]) : (T)0;
+            A0 += cpl[a];
+        }
+        for (int i = 0; i < ncell; ++i) {
+            if (!(d.code[cell_sh[i]] & kSolidBit)) {
+                bsh[i][t] = (T)0;
+                continue;
+            }
+            T num = bsh[i][t];
+            for (int a = 0; a < d.dim; ++a) {
+                const int u = upin_sh[i][a];
+                if (u >= 0) num += cpl[a] * bsh[u][t];
+            }
+            bsh[i][t] = num / (A0 + (T)(L.itau + gam_sh[i]));
+        }
+    }
+    __syncthreads();
+
+    // phase C
+    const int pidx = it.oct * nchunk_oct + it.chunk;
+    for (int i = wave; i < ncell; i += 4) {
+        const int c = cell_sh[i];
+        double acc[kMomN] = {0, 0, 0, 0, 0};
+        if (active) {
+            const T en = esh[i][t] + bsh[i][t];
+            eout[(size_t)c * d.nk + k] = en;
+            if (d.code[c] & kSolidBit) {
+                const double x = L.w * (double)en;
+                acc[0] = x;
+                acc[1] = x * (L.itau + gam_sh[i]);
+                acc[2] = x * L.v * L.s[0];
+                acc[3] = x * L.v * L.s[1];
+                acc[4] = x * L.v * L.s[2];
+            }
+        }
+        wave_sum<kMomN>(acc);
+        if (t == 0)
+            for (int q = 0; q < kMomN; ++q) part[((size_t)pidx * d.nc + c) * kMomN + q] = acc[q];
+    }
+}
+
+// -------------------------------------------------------------- cell kernels
+
+// e = C (T - T_ref)/4pi for every direction (pores: 0)
+template <typename T>
+__global__ void k_set_equilibrium(Dev d, T *__restrict__ e, const double *__restrict__ Tdev)
+{
+    const size_t n = (size_t)d.nc * d.nk;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i / d.nk), k = (int)(i - (size_t)c * d.nk);
+        const int l = k % d.nl;
+        e[i] = (d.code[c] & kSolidBit) ? (T)(d.C4[l] * Tdev[c]) : (T)0;
+    }
+}
+
+// out = in + C (dpend_c - shift_film)/4pi   (final correction and gauge)
+template <typename T>
+__global__ void k_apply_shift(Dev d, const T *__restrict__ in, T *__restrict__ out, const double *__restrict__ dpend,
+                              const double *__restrict__ fshift)
+{
+    const size_t n = (size_t)d.nc * d.nk;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i / d.nk), k = (int)(i - (size_t)c * d.nk);
+        const int l = k % d.nl;
+        double sft = (dpend ? dpend[c] : 0.0) - (fshift ? fshift[d.fid[c]] : 0.0);
+        out[i] = (d.code[c] & kSolidBit) ? (T)((double)in[i] + d.C4[l] * sft) : in[i];
+    }
+}
+
+// Steady bookkeeping after a sweep: moments of e^{n+1} (T_L^kin, T, |q|),
+// the synthetic defect r = S (T_L^kin - T_L^n) and the squared changes.
+__global__ void k_steady_post(Dev d, const double *__restrict__ part, int np, const double *__restrict__ TLn,
+                              double *__restrict__ TLkin, double *__restrict__ Tnew, double *__restrict__ qnew,
+                              double *__restrict__ r, int synthetic)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.nc) return;
+    double s[kMomN] = {0, 0, 0, 0, 0};
+    for (int p = 0; p < np; ++p)
+        for (int i = 0; i < kMomN; ++i) s[i] += part[((size_t)p * d.nc + c) * kMomN + i];
+    const bool solid = d.code[c] & kSolidBit;
+    const double tl = solid ? s[1] / d.S[c] : 0.0;
+    TLkin[c] = tl;
+    Tnew[c] = solid ? s[0] / d.Ctot : 0.0;
+    qnew[c] = solid ? sqrt(s[2] * s[2] + s[3] * s[3] + s[4] * s[4]) : 0.0;
+    if (synthetic) r[c] = solid ? d.S[c] * (tl - TLn[c]) : 0.0;
+}
+
+// Per-geometry convergence measures (Sec. 3.4): one block per geometry.
+// out[f] = {sum dT^2, max|T-Tref|, sum d|q|^2, max|q|, sum (T-Tref)}.
+__global__ __launch_bounds__(kBlock) void k_film_eps(Dev d, const double *__restrict__ T0, const double *__restrict__ T1,
+                                                      const double *__restrict__ q0, const double *__restrict__ q1,
+                                                      double *__restrict__ out)
+{
+    __shared__ double sh[4 * 5];
+    const Film &fm = d.film[blockIdx.x];
+    double a[5] = {0, 0, 0, 0, 0};
+    double mT = 0, mq = 0;
+    for (int i = threadIdx.x; i < fm.ncell; i += kBlock) {
+        const int c = fm.cell0 + i;
+        if (!(d.code[c] & kSolidBit)) continue;
+        const double dT = T0[c] - T1[c], dq = q0[c] - q1[c];
+        a[0] += dT * dT;
+        a[2] += dq * dq;
+        a[4] += T1[c];
+        mT = fmax(mT, fabs(T1[c]));
+        mq = fmax(mq, fabs(q1[c]));
+    }
+    // maxima: butterfly max then block max
+    for (int off = 32; off > 0; off >>= 1) {
+        mT = fmax(mT, __shfl_xor(mT, off, 64));
+        mq = fmax(mq, __shfl_xor(mq, off, 64));
+    }
+    __shared__ double shm[8];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        shm[wave] = mT;
+        shm[4 + wave] = mq;
+    }
+    block_sum<5>(a, sh);
+    if (threadIdx.x == 0) {
+        double MT = fmax(fmax(shm[0], shm[1]), fmax(shm[2], shm[3]));
+        double MQ = fmax(fmax(shm[4], shm[5]), fmax(shm[6], shm[7]));
+        double *o = out + 5 * blockIdx.x;
+        o[0] = a[0];
+        o[1] = MT;
+        o[2] = a[2];
+        o[3] = MQ;
+        o[4] = a[4];
+    }
+}
+
+// Per-geometry mean over solid cells of x (one block per geometry).
+__global__ __launch_bounds__(kBlock) void k_film_mean(Dev d, const double *__restrict__ x, double *__restrict__ mean)
+{
+    __shared__ double sh[4];
+    const Film &fm = d.film[blockIdx.x];
+    double a[1] = {0};
+    for (int i = threadIdx.x; i < fm.ncell; i += kBlock) {
+        const int c = fm.cell0 + i;
+        if (d.code[c] & kSolidBit) a[0] += x[c];
+    }
+    block_sum<1>(a, sh);
+    if (threadIdx.x == 0) mean[blockIdx.x] = a[0] / fm.nsolid;
+}
+
+// x -= mean of its geometry, only for floating geometries (no thermalizing wall)
+__global__ void k_sub_film_mean(Dev d, double *__restrict__ x, const double *__restrict__ mean)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.nc) return;
+    const int f = d.fid[c];
+    if (d.film[f].floating && (d.code[c] & kSolidBit)) x[c] -= mean[f];
+}
+
+// T_L^{n+1} = T_L^kin + delta, pending correction = delta
+__global__ void k_tl_update(int n, const double *__restrict__ TLkin, const double *__restrict__ delta,
+                            double *__restrict__ TL, double *__restrict__ dpend)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const double dl = delta ? delta[c] : 0.0;
+    TL[c] = TLkin[c] + dl;
+    if (dpend) dpend[c] = dl;
+}
+
+// ------------------------------------------------------------------- CG
+//
+// Finite-volume diffusion operator -div(k grad x) per unit volume: harmonic
+// face conductivity, thermalizing walls through a wall conductance, other
+// walls zero flux, periodic faces wrap.  Used for the heat-diffusion initial
+// guess (Sec. 3.5, eq. diff) and, with the correction conductivities, for the
+// synthetic correction.  Jacobi-preconditioned CG; the scalars live on the
+// device, the host only polls a convergence flag every few iterations.
+
+__device__ inline double wall_cond(const Dev &d, const CgArgs &g, int c, int a, const Film &fm)
+{
+    const double kd = 2.0 * g.kax[a * d.nc + c] * fm.ih[a];
+    if (!g.corr) return kd;
+    return 1.0 / (1.0 / kd + 1.0 / g.Hm[a]);
+}
+
+// row c of L applied to x (x may be null: diagonal only)
+__device__ inline double lap_row(const Dev &d, const CgArgs &g, int c, const double *__restrict__ x, double *dg)
+{
+    const uint32_t code = d.code[c];
+    const Film &fm = d.film[d.fid[c]];
+    double acc = 0.0, diag = 0.0;
+    for (int a = 0; a < d.dim; ++a) {
+        const double ih2 = fm.ih[a] * fm.ih[a];
+        const double ki = g.kax[a * d.nc + c];
+        const uint32_t ab = axis_bits(code, a);
+        for (int side = -1; side <= 1; side += 2) {
+            if (side_is_cell(ab, side)) {
+                const int j = d.nb[face_of(a, side) * d.nc + c];
+                const double kj = g.kax[a * d.nc + j];
+                const double kf = 2.0 * ki * kj / (ki + kj) * ih2;
+                if (x) acc += kf * (x[c] - x[j]);
+                diag += kf;
+            } else if (side_wall(ab, side) == 0) {
+                const double wc = wall_cond(d, g, c, a, fm) * fm.ih[a];
+                if (x) acc += wc * x[c];
+                diag += wc;
+            }
+        }
+    }
+    if (dg) *dg = diag;
+    return acc;
+}
+
+__device__ inline double blk_sum1(double v, double *sh)
+{
+    double a[1] = {v};
+    block_sum<1>(a, sh);
+    return a[0];
+}
+
+// init: x = 0, r = b (already projected), z = r/diag, p = z, partials of r.z and r.r
+__global__ __launch_bounds__(kBlock) void k_cg_init(Dev d, CgArgs g, const double *__restrict__ b)
+{
+    __shared__ double sh[8];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double rz = 0, rr = 0;
+    if (c < d.nc) {
+        const bool solid = d.code[c] & kSolidBit;
+        double dg = 1.0;
+        if (solid) lap_row(d, g, c, nullptr, &dg);
+        if (!(dg > 0)) dg = 1.0;
+        const double rc = solid ? b[c] : 0.0;
+        g.diag[c] = dg;
+        g.x[c] = 0.0;
+        g.r[c] = rc;
+        g.z[c] = rc / dg;
+        g.p[c] = rc / dg;
+        rz = rc * rc / dg;
+        rr = rc * rc;
+    }
+    rz = blk_sum1(rz, sh);
+    rr = blk_sum1(rr, sh);
+    if (threadIdx.x == 0) {
+        g.part[2 * blockIdx.x] = rz;
+        g.part[2 * blockIdx.x + 1] = rr;
+    }
+}
+
+__global__ void k_cg_init2(CgArgs g, int nblk)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double rz = 0, rr = 0;
+    for (int i = 0; i < nblk; ++i) {
+        rz += g.part[2 * i];
+        rr += g.part[2 * i + 1];
+    }
+    g.scal[7] = rz;
+    g.scal[1] = rr;
+    g.scal[5] = (rr > 0.0 && rz > 0.0) ? 0.0 : 1.0;
+    g.scal[6] = 0.0;
+}
+
+// Ap = L p, partial p.Ap
+__global__ __launch_bounds__(kBlock) void k_cg_a(Dev d, CgArgs g)
+{
+    __shared__ double sh[8];
+    if (g.scal[5] != 0.0) return;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double pap = 0;
+    if (c < d.nc) {
+        const double y = (d.code[c] & kSolidBit) ? lap_row(d, g, c, g.p, nullptr) : 0.0;
+        g.Ap[c] = y;
+        pap = g.p[c] * y;
+    }
+    pap = blk_sum1(pap, sh);
+    if (threadIdx.x == 0) g.part[2 * blockIdx.x] = pap;
+}
+
+// alpha = rz / pAp; x += alpha p; r -= alpha Ap; z = r/diag; partials r.z, r.r
+__global__ __launch_bounds__(kBlock) void k_cg_b(Dev d, CgArgs g, int nblk, int parity)
+{
+    __shared__ double sh[8];
+    __shared__ double alpha_sh;
+    if (g.scal[5] != 0.0) return;
+    if (threadIdx.x == 0) {
+        double pap = 0;
+        for (int i = 0; i < nblk; ++i) pap += g.part[2 * i];
+        alpha_sh = (pap > 0.0) ? g.scal[7 + parity] / pap : 0.0;
+        if (blockIdx.x == 0) g.scal[2] = pap;
+    }
+    __syncthreads();
+    const double alpha = alpha_sh;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double rz = 0, rr = 0;
+    if (c < d.nc) {
+        g.x[c] += alpha * g.p[c];
+        const double rc = g.r[c] - alpha * g.Ap[c];
+        g.r[c] = rc;
+        const double zc = rc / g.diag[c];
+        g.z[c] = zc;
+        rz = rc * zc;
+        rr = rc * rc;
+    }
+    __syncthreads();
+    rz = blk_sum1(rz, sh);
+    rr = blk_sum1(rr, sh);
+    if (threadIdx.x == 0) {
+        g.part[2 * nblk + 2 * blockIdx.x] = rz;
+        g.part[2 * nblk + 2 * blockIdx.x + 1] = rr;
+    }
+}
+
+// beta = rz_new / rz; p = z + beta p; convergence / breakdown flag
+__global__ __launch_bounds__(kBlock) void k_cg_c(Dev d, CgArgs g, int nblk, int parity)
+{
+    __shared__ double beta_sh, done_sh;
+    if (g.scal[5] != 0.0) return;
+    if (threadIdx.x == 0) {
+        double rz = 0, rr = 0;
+        for (int i = 0; i < nblk; ++i) {
+            rz += g.part[2 * nblk + 2 * i];
+            rr += g.part[2 * nblk + 2 * i + 1];
+        }
+        const double rz_old = g.scal[7 + parity];
+        const bool done = !(g.scal[2] > 0.0) || rr <= g.rtol2 * g.scal[1] || !(rz > 0.0);
+        beta_sh = done ? 0.0 : rz / rz_old;
+        done_sh = done ? 1.0 : 0.0;
+        if (blockIdx.x == 0) g.scal[8 - parity] = rz;
+    }
+    __syncthreads();
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < d.nc && done_sh == 0.0) g.p[c] = g.z[c] + beta_sh * g.p[c];
+}
+
+// bookkeeping after k_cg_c of one iteration (single thread): count, done flag
+__global__ void k_cg_tick(CgArgs g, int nblk)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (g.scal[5] != 0.0) return;
+    double rz = 0, rr = 0;
+    for (int i = 0; i < nblk; ++i) {
+        rz += g.part[2 * nblk + 2 * i];
+        rr += g.part[2 * nblk + 2 * i + 1];
+    }
+    g.scal[6] += 1.0;
+    g.scal[3] = rr;
+    if (!(g.scal[2] > 0.0) || rr <= g.rtol2 * g.scal[1] || !(rz > 0.0)) g.scal[5] = 1.0;
+}
+
+// right-hand side of the heat-diffusion initial guess: P plus thermalizing
+// wall and periodic-jump terms
+__global__ void k_diff_rhs(Dev d, CgArgs g, double *__restrict__ b)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.nc) return;
+    const uint32_t code = d.code[c];
+    if (!(code & kSolidBit)) {
+        b[c] = 0.0;
+        return;
+    }
+    const Film &fm = d.film[d.fid[c]];
+    double acc = d.P ? d.P[c] : 0.0;
+    for (int a = 0; a < d.dim; ++a) {
+        const double ih2 = fm.ih[a] * fm.ih[a];
+        const double ki = g.kax[a * d.nc + c];
+        const uint32_t ab = axis_bits(code, a);
+        for (int side = -1; side <= 1; side += 2) {
+            if (side_is_cell(ab, side)) {
+                if (side_wraps(ab, side)) {
+                    const int j = d.nb[face_of(a, side) * d.nc + c];
+                    const double kj = g.kax[a * d.nc + j];
+                    acc += 2.0 * ki * kj / (ki + kj) * ih2 * (-side) * fm.pdT[a];
+                }
+            } else if (side_wall(ab, side) == 0) {
+                const double Tw = side_outer(code, a, side) ? fm.wallT[face_of(a, side)] : d.poreT;
+                acc += wall_cond(d, g, c, a, fm) * fm.ih[a] * Tw;
+            }
+        }
+    }
+    b[c] = acc;
+}
+
+// k_eff per geometry: (L_x/dT) (1/N_cells) sum_solid q_x  (one block per geometry)
+__global__ __launch_bounds__(kBlock) void k_keff(Dev d, const double *__restrict__ q, double *__restrict__ keff)
+{
+    __shared__ double sh[4];
+    const Film &fm = d.film[blockIdx.x];
+    double a[1] = {0};
+    for (int i = threadIdx.x; i < fm.ncell; i += kBlock) a[0] += q[3 * (fm.cell0 + i)];
+    block_sum<1>(a, sh);
+    if (threadIdx.x == 0) keff[blockIdx.x] = fm.len[0] / fm.pdT[0] * a[0] / fm.ncell;
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <typename T>
+void launch_moments(const Dev &d, const T *e, const double *dpend, double *part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_moments<T>, dim3(d.nc), dim3(kBlock), 0, s, d, e, dpend, part);
+}
+
+template <typename T>
+void launch_walls(const Dev &d, const T *e, const double *dpend, const int *wrec, const double *wden, double *din,
+                  int nw, hipStream_t s)
+{
+    if (nw > 0) hipLaunchKernelGGL(k_walls<T>, dim3(nw), dim3(kBlock), 0, s, d, e, dpend, wrec, wden, din, nw);
+}
+
+static inline void stream_grid(const Dev &d, int cpb, int &nchunk, int &ngroup, int &grid)
+{
+    nchunk = (d.nk + kBlock - 1) / kBlock;
+    ngroup = (d.nc + cpb - 1) / cpb;
+    grid = nchunk * ngroup;
+    grid = (grid + 7) / 8 * 8;
+}
+
+template <typename T>
+void launch_transient(const Dev &d, const T *ein, T *eout, const double *TLdev, const double *din, double src,
+                      double dt, double *part, int cpb, hipStream_t s)
+{
+    int nchunk, ngroup, grid;
+    stream_grid(d, cpb, nchunk, ngroup, grid);
+    hipLaunchKernelGGL(k_transient<T>, dim3(grid), dim3(kBlock), 0, s, d, ein, eout, TLdev, din, src, dt, part,
+                       nchunk, ngroup, cpb);
+}
+
+template <typename T>
+void launch_residual(const Dev &d, const T *e, T *R, const double *TLdev, const double *din, int cpb, hipStream_t s)
+{
+    int nchunk, ngroup, grid;
+    stream_grid(d, cpb, nchunk, ngroup, grid);
+    hipLaunchKernelGGL(k_residual<T>, dim3(grid), dim3(kBlock), 0, s, d, e, R, TLdev, din, nchunk, ngroup, cpb);
+}
+
+template <typename T>
+void launch_sweep(const Dev &d, const T *ein, T *eout, const double *dpend, const double *TLdev, const double *din,
+                  const SweepItem *items, int item0, int count, int3 tdim, int na_oct, int nchunk_oct, double *part,
+                  hipStream_t s)
+{
+    if (count > 0)
+        hipLaunchKernelGGL(k_sweep<T>, dim3(count), dim3(kBlock), 0, s, d, ein, eout, dpend, TLdev, din, items,
+                           item0, tdim, na_oct, nchunk_oct, part);
+}
+
+template <typename T>
+void launch_set_equilibrium(const Dev &d, T *e, const double *Tdev, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_equilibrium<T>, dim3(2048), dim3(kBlock), 0, s, d, e, Tdev);
+}
+
+template <typename T>
+void launch_apply_shift(const Dev &d, const T *in, T *out, const double *dpend, const double *fshift, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_apply_shift<T>, dim3(2048), dim3(kBlock), 0, s, d, in, out, dpend, fshift);
+}
+
+void launch_keff(const Dev &d, const double *q, double *keff, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_keff, dim3(d.nfilm), dim3(kBlock), 0, s, d, q, keff);
+}
+
+#define BTE_INST(T)                                                                                                   \
+    template void launch_moments<T>(const Dev &, const T *, const double *, double *, hipStream_t);                  \
+    template void launch_walls<T>(const Dev &, const T *, const double *, const int *, const double *, double *,     \
+                                  int, hipStream_t);                                                                 \
+    template void launch_transient<T>(const Dev &, const T *, T *, const double *, const double *, double, double,   \
+                                      double *, int, hipStream_t);                                                   \
+    template void launch_residual<T>(const Dev &, const T *, T *, const double *, const double *, int, hipStream_t); \
+    template void launch_sweep<T>(const Dev &, const T *, T *, const double *, const double *, const double *,       \
+                                  const SweepItem *, int, int, int3, int, int, double *, hipStream_t);               \
+    template void launch_set_equilibrium<T>(const Dev &, T *, const double *, hipStream_t);                          \
+    template void launch_apply_shift<T>(const Dev &, const T *, T *, const double *, const double *, hipStream_t);
+BTE_INST(float)
+BTE_INST(double)
+
+void launch_cell_setup(const Dev &d, double *S, double *kdif, double *kcor, const double M[3], const double H[3],
+                       hipStream_t s)
+{
+    const int grid = (d.nc + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_cell_setup, dim3(grid), dim3(kBlock), 0, s, d, S, kdif, kcor, M[0], M[1], M[2], H[0], H[1],
+                       H[2]);
+}
+
+void launch_finalize(const Dev &d, const double *part, int np, double Tref, double *T, double *TL, double *q,
+                     double *TLdev, double *Tdev, double *qmag, hipStream_t s)
+{
+    const int grid = (d.nc + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kBlock), 0, s, d, part, np, Tref, T, TL, q, TLdev, Tdev, qmag);
+}
+
+void launch_steady_post(const Dev &d, const double *part, int np, const double *TLn, double *TLkin, double *Tnew,
+                        double *qnew, double *r, int synthetic, hipStream_t s)
+{
+    const int grid = (d.nc + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_steady_post, dim3(grid), dim3(kBlock), 0, s, d, part, np, TLn, TLkin, Tnew, qnew, r,
+                       synthetic);
+}
+
+void launch_film_eps(const Dev &d, const double *T0, const double *T1, const double *q0, const double *q1,
+                     double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_film_eps, dim3(d.nfilm), dim3(kBlock), 0, s, d, T0, T1, q0, q1, out);
+}
+
+void launch_film_mean(const Dev &d, const double *x, double *mean, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_film_mean, dim3(d.nfilm), dim3(kBlock), 0, s, d, x, mean);
+}
+
+void launch_sub_film_mean(const Dev &d, double *x, const double *mean, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sub_film_mean, dim3((d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, x, mean);
+}
+
+void launch_tl_update(int n, const double *TLkin, const double *delta, double *TL, double *dpend, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tl_update, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, TLkin, delta, TL, dpend);
+}
+
+// CG driver pieces
+int cg_nblk(const Dev &d) { return (d.nc + kBlock - 1) / kBlock; }
+
+void launch_cg_init(const Dev &d, const CgArgs &g, const double *b, hipStream_t s)
+{
+    const int nb = cg_nblk(d);
+    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kBlock), 0, s, d, g, b);
+    hipLaunchKernelGGL(k_cg_init2, dim3(1), dim3(64), 0, s, g, nb);
+}
+
+void launch_cg_iter(const Dev &d, const CgArgs &g, int iter, hipStream_t s)
+{
+    const int nb = cg_nblk(d);
+    hipLaunchKernelGGL(k_cg_a, dim3(nb), dim3(kBlock), 0, s, d, g);
+    hipLaunchKernelGGL(k_cg_b, dim3(nb), dim3(kBlock), 0, s, d, g, nb, iter & 1);
+    hipLaunchKernelGGL(k_cg_c, dim3(nb), dim3(kBlock), 0, s, d, g, nb, iter & 1);
+    hipLaunchKernelGGL(k_cg_tick, dim3(1), dim3(64), 0, s, g, nb);
+}
+
+void launch_diff_rhs(const Dev &d, const CgArgs &g, double *b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_diff_rhs, dim3((d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, g, b);
+}
+
+}  // namespace bte
