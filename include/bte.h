@@ -114,6 +114,11 @@ typedef struct {
     double eps_T, eps_q;     /* last convergence measures                  */
     int converged;
     double ms_total;         /* wall time of the call (host clock)         */
+    double ms_sweep;         /* device time of the transport sweeps (HIP events on the stream) */
+    double ms_walls;         /* device time of the wall-inflow kernels     */
+    double ms_post;          /* device time of moments/defect/eps kernels  */
+    double ms_cg;            /* device time of the synthetic correction    */
+    int sweep_launches;      /* kernel launches issued for the sweeps      */
 } bte_solve_stats;
 
 typedef struct bte_problem bte_problem;
@@ -124,6 +129,10 @@ typedef struct bte_problem bte_problem;
  * receives the handle; bind a workspace before any device call. */
 bte_status bte_setup(const bte_geometry *geo, int n_geo, const bte_material *mat,
                      const bte_control *ctl, bte_problem **out);
+
+/* Replace the control of a handle (scheme, limiter, tolerances, iteration
+ * caps, dt).  The precision must stay the same (it fixes the workspace). */
+bte_status bte_set_control(bte_problem *p, const bte_control *ctl);
 
 /* Size in bytes of the device workspace the handle needs. */
 size_t bte_workspace_bytes(const bte_problem *p);

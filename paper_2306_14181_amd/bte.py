@@ -24,7 +24,7 @@ OBJ_KEFF_X = 0
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "ERR_NOT_CONVERGED",
                 5: "ERR_NONFINITE", 6: "ERR_CFL", 7: "ERR_STATE"}
 
-EXPORTS = ["bte_setup", "bte_workspace_bytes", "bte_num_unknowns", "bte_num_cells", "bte_num_directions",
+EXPORTS = ["bte_setup", "bte_set_control", "bte_workspace_bytes", "bte_num_unknowns", "bte_num_cells", "bte_num_directions",
            "bte_bind", "bte_set_fields", "bte_moments", "bte_residual", "bte_transient_step",
            "bte_steady_solve", "bte_keff", "bte_adjoint", "bte_get_directions", "bte_last_error",
            "bte_destroy"]
@@ -56,11 +56,12 @@ class Control(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("cg_iters", C.c_int), ("eps_T", C.c_double), ("eps_q", C.c_double),
-                ("converged", C.c_int), ("ms_total", C.c_double)]
+                ("converged", C.c_int), ("ms_total", C.c_double), ("ms_sweep", C.c_double),
+                ("ms_walls", C.c_double), ("ms_post", C.c_double), ("ms_cg", C.c_double),
+                ("sweep_launches", C.c_int)]
 
     def as_dict(self):
-        return dict(iters=self.iters, cg_iters=self.cg_iters, eps_T=self.eps_T, eps_q=self.eps_q,
-                    converged=bool(self.converged), ms_total=self.ms_total)
+        return {k: (bool(getattr(self, k)) if k == "converged" else getattr(self, k)) for k, _ in self._fields_}
 
 
 _lib = None
@@ -78,6 +79,7 @@ def load():
     sig = {
         "bte_setup": ([C.POINTER(Geometry), C.c_int, C.POINTER(Material), C.POINTER(Control),
                        C.POINTER(vp)], st),
+        "bte_set_control": ([vp, C.POINTER(Control)], st),
         "bte_workspace_bytes": ([vp], C.c_size_t),
         "bte_num_unknowns": ([vp], C.c_size_t),
         "bte_num_cells": ([vp], C.c_int),
@@ -129,6 +131,20 @@ def _geometry_struct(g):
     return s, keep
 
 
+def _control_struct(control):
+    c = Control()
+    c.precision = int(control.get("precision", F32))
+    c.scheme = int(control.get("scheme", SYNTHETIC))
+    c.limiter = int(control.get("limiter", LIM_NONE))
+    c.residual_temp = float(control.get("residual_temp", 1e-5))
+    c.residual_flux = float(control.get("residual_flux", 1e-3))
+    c.max_iter = int(control.get("max_iter", 10000))
+    c.cg_rtol = float(control.get("cg_rtol", 1e-10))
+    c.cg_max_iter = int(control.get("cg_max_iter", 2000))
+    c.dt = float(control.get("dt", 0.0))
+    return c
+
+
 class Problem:
     """One problem (a geometry or a batch of geometries) bound to a device workspace.
 
@@ -157,16 +173,8 @@ class Problem:
         m.n_theta = int(material["n_theta"])
         m.n_phi = int(material.get("n_phi", 1))
         m.T_ref = float(material["Tref"])
-        c = Control()
-        c.precision = int(control.get("precision", F32))
-        c.scheme = int(control.get("scheme", SYNTHETIC))
-        c.limiter = int(control.get("limiter", LIM_NONE))
-        c.residual_temp = float(control.get("residual_temp", 1e-5))
-        c.residual_flux = float(control.get("residual_flux", 1e-3))
-        c.max_iter = int(control.get("max_iter", 10000))
-        c.cg_rtol = float(control.get("cg_rtol", 1e-10))
-        c.cg_max_iter = int(control.get("cg_max_iter", 2000))
-        c.dt = float(control.get("dt", 0.0))
+        c = _control_struct(control)
+        self.control = dict(control)
         self.precision = c.precision
         self.dtype = torch.float64 if c.precision == F64 else torch.float32
         h = C.c_void_p()
@@ -178,6 +186,9 @@ class Problem:
                 lib.bte_destroy(h)
                 self._h = None
             raise BteError(st, msg)
+        self._finish_init(lib, h, m, structs)
+
+    def _finish_init(self, lib, h, m, structs):
         self.n_cells = lib.bte_num_cells(h)
         self.n_dirs = lib.bte_num_directions(h)
         self.n_bands = m.n_bands
@@ -209,6 +220,11 @@ class Problem:
                 and x.is_contiguous() and x.numel() == self.n_cells * width):
             raise ValueError("expected a contiguous float64 cuda tensor with %d elements" % (self.n_cells * width))
         return _ptr(x)
+
+    def set_control(self, **kw):
+        """Update control fields (precision excluded)."""
+        self.control.update(kw)
+        self._check(load().bte_set_control(self._h, C.byref(_control_struct(self.control))))
 
     def zeros(self):
         return torch.zeros(self.n_unknowns, dtype=self.dtype, device=self.device)

@@ -510,6 +510,21 @@ bte_status bte_setup(const bte_geometry *geo, int n_geo, const bte_material *mat
     return BTE_OK;
 }
 
+bte_status bte_set_control(bte_problem *p, const bte_control *ctl)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!ctl) FAIL(p, BTE_ERR_ARG, "null control");
+    if (ctl->precision != p->ctl.precision) FAIL(p, BTE_ERR_ARG, "precision cannot change after setup");
+    if (ctl->scheme != BTE_SEQUENTIAL && ctl->scheme != BTE_SYNTHETIC) FAIL(p, BTE_ERR_ARG, "bad scheme");
+    if (ctl->limiter < 0 || ctl->limiter > 2) FAIL(p, BTE_ERR_ARG, "bad limiter");
+    p->ctl = *ctl;
+    if (p->ctl.max_iter <= 0) p->ctl.max_iter = 10000;
+    if (p->ctl.cg_max_iter <= 0) p->ctl.cg_max_iter = 2000;
+    if (!(p->ctl.cg_rtol > 0)) p->ctl.cg_rtol = 1e-10;
+    p->dev.limiter = p->ctl.limiter;
+    return BTE_OK;
+}
+
 size_t bte_workspace_bytes(const bte_problem *p) { return p ? p->ws_bytes : 0; }
 size_t bte_num_unknowns(const bte_problem *p) { return p ? p->nelem() : 0; }
 int bte_num_cells(const bte_problem *p) { return p ? p->nc : 0; }
@@ -705,17 +720,32 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
     std::vector<double> feps(5 * (size_t)p->nfilm);
     const int np = p->noct * p->nchunk_oct;
     bte_status ret = BTE_ERR_NOT_CONVERGED;
+    // phase timers: events on the solve stream, read after the per-iteration sync
+    hipEvent_t ev[5];
+    for (auto &x : ev) HIPCHK(p, hipEventCreate(&x));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]);
+        }
+    } evg{ev};
     for (int iter = 1; iter <= p->ctl.max_iter; ++iter) {
         const T *ein = buf[cur];
         T *eout = buf[1 - cur];
+        HIPCHK(p, hipEventRecord(ev[0], s));
         launch_walls<T>(d, ein, p->dpend, p->d_wrec, p->d_wden, p->din, p->nw, s);
+        HIPCHK(p, hipEventRecord(ev[1], s));
         for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
             const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
             launch_sweep<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt, p->tdim, p->na_oct,
                             p->nchunk_oct, p->part, s);
+            st.sweep_launches += cnt > 0;
         }
+        HIPCHK(p, hipEventRecord(ev[2], s));
         launch_steady_post(d, p->part, np, p->TL, p->TLkin, p->T1, p->q1, p->r, synthetic, s);
         launch_film_eps(d, p->T0, p->T1, p->q0, p->q1, p->feps, s);
+        HIPCHK(p, hipEventRecord(ev[3], s));
         HIPCHK(p, hipGetLastError());
         if (synthetic) {
             int it = run_cg(p, 1, p->r, p->delta, p->ctl.cg_rtol, p->ctl.cg_max_iter, s);
@@ -725,8 +755,17 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
         } else {
             launch_tl_update(nc, p->TLkin, nullptr, p->TL, nullptr, s);
         }
+        HIPCHK(p, hipEventRecord(ev[4], s));
         HIPCHK(p, hipMemcpyAsync(feps.data(), p->feps, 8 * feps.size(), hipMemcpyDeviceToHost, s));
         HIPCHK(p, hipStreamSynchronize(s));
+        {
+            float ms[4];
+            for (int i = 0; i < 4; ++i) HIPCHK(p, hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
+            st.ms_walls += ms[0];
+            st.ms_sweep += ms[1];
+            st.ms_post += ms[2];
+            st.ms_cg += ms[3];
+        }
         double eT = 0, eq = 0;
         bool finite = true;
         for (int f = 0; f < p->nfilm; ++f) {
