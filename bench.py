@@ -71,6 +71,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256, help="cells per side (256 = the benchmark workload)")
     ap.add_argument("--cg-rtol", type=float, default=1e-6)
+    ap.add_argument("--cg-max-iter", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -90,7 +91,7 @@ def main():
     cfg = I.config1(n=args.n)
     geo, mat = cfg["geometry"], cfg["material"]
     P = torch.as_tensor(cfg["P"], device="cuda")
-    base_ctl = dict(scheme=B.SYNTHETIC, limiter=B.LIM_NONE, cg_rtol=args.cg_rtol, cg_max_iter=4000)
+    base_ctl = dict(scheme=B.SYNTHETIC, limiter=B.LIM_NONE, cg_rtol=args.cg_rtol, cg_max_iter=args.cg_max_iter)
 
     results = {}
     precs = [B.F32] if args.no_fp64 else [B.F32, B.F64]
@@ -156,7 +157,7 @@ def main():
         "dtype": "f32 (e), f64 (moments, CG)",
         "data": "synthetic (seeded bands, Gaussian source)",
         "config": {"workload": "square2d_source: 256x256 cells, 1 um, 20 bands, 128 directions, synthetic scheme",
-                   "n": args.n, "cg_rtol": args.cg_rtol},
+                   "n": args.n, "cg_rtol": args.cg_rtol, "cg_max_iter": args.cg_max_iter},
         "roofline": {
             "bound": "hbm",
             "kernel": "k_sweep<float> (all tile-wavefront launches of one sweep)",

@@ -230,12 +230,13 @@ class Problem:
         return torch.zeros(self.n_unknowns, dtype=self.dtype, device=self.device)
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
             try:
                 torch.cuda.synchronize(self.device)
+                _lib.bte_destroy(h)
             except Exception:
                 pass
-            load().bte_destroy(self._h)
             self._h = None
 
     # -------------------------------------------------------------------- API

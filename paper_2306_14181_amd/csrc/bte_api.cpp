@@ -23,19 +23,22 @@ template <typename T> void launch_moments(const Dev &, const T *, const double *
 template <typename T>
 void launch_walls(const Dev &, const T *, const double *, const int *, const double *, double *, int, hipStream_t);
 template <typename T>
-void launch_transient(const Dev &, const T *, T *, const double *, const double *, double, double, double *, int,
-                      hipStream_t);
-template <typename T>
 void launch_residual(const Dev &, const T *, T *, const double *, const double *, int, hipStream_t);
 template <typename T>
-void launch_sweep(const Dev &, const T *, T *, const double *, const double *, const double *, const SweepItem *, int,
-                  int, int3, int, int, double *, hipStream_t);
+hipError_t launch_sweep_tile(const Dev &, const T *, T *, const double *, const double *, const double *,
+                             const SweepItem *, int, int, int3, int, int, int, double *, hipStream_t);
+template <typename T>
+hipError_t launch_transient_tile(const Dev &, const T *, T *, const double *, const double *, const TileItem *, int,
+                                 int3, int, int, int, double, double, double *, hipStream_t);
+hipError_t tile_kernels_init(size_t);
+size_t tile_smem_size(int, int, int);
 template <typename T> void launch_set_equilibrium(const Dev &, T *, const double *, hipStream_t);
 template <typename T> void launch_apply_shift(const Dev &, const T *, T *, const double *, const double *, hipStream_t);
 void launch_keff(const Dev &, const double *, double *, hipStream_t);
 void launch_cell_setup(const Dev &, double *, double *, double *, const double[3], const double[3], hipStream_t);
 void launch_finalize(const Dev &, const double *, int, double, double *, double *, double *, double *, double *,
                      double *, hipStream_t);
+void launch_finalize_tl(const Dev &, const double *, int, double *, hipStream_t);
 void launch_steady_post(const Dev &, const double *, int, const double *, double *, double *, double *, double *, int,
                         hipStream_t);
 void launch_film_eps(const Dev &, const double *, const double *, const double *, const double *, double *,
@@ -43,10 +46,10 @@ void launch_film_eps(const Dev &, const double *, const double *, const double *
 void launch_film_mean(const Dev &, const double *, double *, hipStream_t);
 void launch_sub_film_mean(const Dev &, double *, const double *, hipStream_t);
 void launch_tl_update(int, const double *, const double *, double *, double *, hipStream_t);
-int cg_nblk(const Dev &);
-void launch_cg_init(const Dev &, const CgArgs &, const double *, hipStream_t);
-void launch_cg_iter(const Dev &, const CgArgs &, int, hipStream_t);
+void launch_cg_coef(const Dev &, const CgArgs &, double *, double *, hipStream_t);
 void launch_diff_rhs(const Dev &, const CgArgs &, double *, hipStream_t);
+int cg_persist_blocks(const Dev &);
+hipError_t launch_cg_persist(const Dev &, const CgArgs &, const double *, int, hipStream_t);
 }  // namespace bte
 
 using namespace bte;
@@ -110,6 +113,8 @@ struct bte_problem {
     int nchunk_oct = 0;
     std::vector<SweepItem> items;
     std::vector<int> diag_off;
+    std::vector<TileItem> titems;   // transient: (geometry, octant, tile)
+    int tile_cap = 0;               // star slots of a full tile
     int floating_any = 0, thermal_any = 0;
     // workspace
     size_t ws_bytes = 0;
@@ -123,6 +128,7 @@ struct bte_problem {
     bool fields_set = false;
     // device pointers
     double *S = nullptr, *kdif = nullptr, *kcor = nullptr, *gamma = nullptr, *P = nullptr;
+    double *cdif = nullptr, *ccor = nullptr, *ddif = nullptr, *dcor = nullptr;
     double *TL = nullptr, *TLkin = nullptr, *T0 = nullptr, *T1 = nullptr, *q0 = nullptr, *q1 = nullptr;
     double *r = nullptr, *delta = nullptr, *dpend = nullptr, *fmean = nullptr, *feps = nullptr;
     double *cg_x = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr, *cg_diag = nullptr;
@@ -130,6 +136,7 @@ struct bte_problem {
     double *din = nullptr, *part = nullptr;
     void *e2 = nullptr;
     SweepItem *d_items = nullptr;
+    TileItem *d_titems = nullptr;
     int *d_wrec = nullptr;
     double *d_wden = nullptr;
     int npart_max = 0;
@@ -172,6 +179,7 @@ bte_status build_geometry(bte_problem *p, const bte_geometry *geo, int n_geo)
             fm.h[a] = fm.len[a] / fm.n[a];
             fm.ih[a] = 1.0 / fm.h[a];
             fm.pdT[a] = a < g.dim ? g.periodic_dT[a] : 0.0;
+            fm.periodic[a] = a < g.dim && g.bc[2 * a] == BTE_BC_PERIODIC;
             ncell *= fm.n[a];
         }
         if (ncell + cell0 > 0x7fffffffLL / 8) FAIL(p, BTE_ERR_ARG, "too many cells");
@@ -352,6 +360,7 @@ void build_schedule(bte_problem *p)
     // tiles of 64 cells: 64 (1D), 8x8 (2D), 4x4x4 (3D)
     if (p->dim == 1) p->tdim = make_int3(64, 1, 1);
     else if (p->dim == 2) p->tdim = make_int3(8, 8, 1);
+    else if (p->ctl.precision == BTE_F64) p->tdim = make_int3(4, 4, 2);   // LDS: 64 KiB star for FP64
     else p->tdim = make_int3(4, 4, 4);
     const int lanes_oct = p->na_oct * p->nl;
     p->nchunk_oct = (lanes_oct + 63) / 64;
@@ -382,6 +391,21 @@ void build_schedule(bte_problem *p)
         }
     }
     std::stable_sort(recs.begin(), recs.end(), [](const Rec &a, const Rec &b) { return a.d < b.d; });
+    p->titems.clear();
+    for (int f = 0; f < p->nfilm; ++f) {
+        const Film &fm = p->films[f];
+        const int ntile = ((fm.n[0] + p->tdim.x - 1) / p->tdim.x) * ((fm.n[1] + p->tdim.y - 1) / p->tdim.y) *
+                          ((fm.n[2] + p->tdim.z - 1) / p->tdim.z);
+        for (int o = 0; o < p->noct; ++o)
+            for (int t = 0; t < ntile; ++t) p->titems.push_back({f, o, t, 0});
+    }
+    {
+        const int e[3] = {p->tdim.x, p->tdim.y, p->tdim.z};
+        const int cells = e[0] * e[1] * e[2];
+        int halo = 0;
+        for (int a = 0; a < p->dim; ++a) halo += 3 * cells / e[a];
+        p->tile_cap = cells + halo;
+    }
     p->items.clear();
     p->diag_off.assign(maxd + 2, 0);
     for (auto &r : recs) {
@@ -414,11 +438,16 @@ void plan_workspace(bte_problem *p)
     add("wrec", 4 * p->wrec.size());
     add("wden", 8 * 6);
     add("items", sizeof(SweepItem) * p->items.size());
+    add("titems", sizeof(TileItem) * p->titems.size());
     for (const char *n : {"gamma", "P", "S", "TL", "TLkin", "T0", "T1", "q0", "q1", "r", "delta", "dpend", "cg_x",
                           "cg_r", "cg_z", "cg_p", "cg_Ap", "cg_diag"})
         add(n, 8 * nc);
     add("kdif", 8 * 3 * nc);
     add("kcor", 8 * 3 * nc);
+    add("cdif", 8 * 6 * nc);
+    add("ccor", 8 * 6 * nc);
+    add("ddif", 8 * nc);
+    add("dcor", 8 * nc);
     add("fmean", 8 * p->nfilm);
     add("feps", 8 * 5 * p->nfilm);
     add("cg_part", 8 * 4 * (size_t)((nc + kBlock - 1) / kBlock));
@@ -439,6 +468,10 @@ template <typename X> X *wsptr(bte_problem *p, const char *name)
 }
 
 }  // namespace
+
+namespace {
+void cell_setup(bte_problem *p, hipStream_t s);
+}
 
 extern "C" {
 
@@ -554,6 +587,9 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     HIPCHK(p, up("wrec", p->wrec.data(), 4 * p->wrec.size()));
     HIPCHK(p, up("wden", p->wden, 8 * 6));
     HIPCHK(p, up("items", p->items.data(), sizeof(SweepItem) * p->items.size()));
+    HIPCHK(p, up("titems", p->titems.data(), sizeof(TileItem) * p->titems.size()));
+    if (tile_smem_size(p->tile_cap, (int)p->esize(), 1) > 160 * 1024) FAIL(p, BTE_ERR_UNSUPPORTED, "tile LDS");
+    HIPCHK(p, tile_kernels_init(160 * 1024));
     Dev &d = p->dev;
     d.dim = p->dim;
     d.nc = p->nc;
@@ -583,6 +619,10 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     d.S = p->S;
     p->kdif = wsptr<double>(p, "kdif");
     p->kcor = wsptr<double>(p, "kcor");
+    p->cdif = wsptr<double>(p, "cdif");
+    p->ccor = wsptr<double>(p, "ccor");
+    p->ddif = wsptr<double>(p, "ddif");
+    p->dcor = wsptr<double>(p, "dcor");
     p->TL = wsptr<double>(p, "TL");
     p->TLkin = wsptr<double>(p, "TLkin");
     p->T0 = wsptr<double>(p, "T0");
@@ -606,12 +646,13 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     p->part = wsptr<double>(p, "part");
     p->e2 = wsptr<void>(p, "e2");
     p->d_items = wsptr<SweepItem>(p, "items");
+    p->d_titems = wsptr<TileItem>(p, "titems");
     p->d_wrec = wsptr<int>(p, "wrec");
     p->d_wden = wsptr<double>(p, "wden");
     // default fields: no source, no extra scattering
     HIPCHK(p, hipMemset(p->gamma, 0, 8 * (size_t)p->nc));
     HIPCHK(p, hipMemset(p->P, 0, 8 * (size_t)p->nc));
-    launch_cell_setup(p->dev, p->S, p->kdif, p->kcor, p->M, p->H, nullptr);
+    cell_setup(p, nullptr);
     HIPCHK(p, hipGetLastError());
     HIPCHK(p, hipDeviceSynchronize());
     p->fields_set = true;
@@ -629,7 +670,7 @@ bte_status bte_set_fields(bte_problem *p, const double *P_dev, const double *gam
     if (gamma_dev) HIPCHK(p, hipMemcpyAsync(p->gamma, gamma_dev, nb, hipMemcpyDeviceToDevice, s));
     else HIPCHK(p, hipMemsetAsync(p->gamma, 0, nb, s));
     p->dev.P = P_dev ? p->P : nullptr;
-    launch_cell_setup(p->dev, p->S, p->kdif, p->kcor, p->M, p->H, s);
+    cell_setup(p, s);
     HIPCHK(p, hipGetLastError());
     return BTE_OK;
 }
@@ -640,6 +681,37 @@ bte_status bte_set_fields(bte_problem *p, const double *P_dev, const double *gam
 
 namespace {
 
+// CG arguments of the heat-diffusion (corr = 0) or correction (corr = 1) operator
+CgArgs cg_args(bte_problem *p, int corr)
+{
+    CgArgs g{};
+    g.kax = corr ? p->kcor : p->kdif;
+    g.coef = corr ? p->ccor : p->cdif;
+    g.dg = corr ? p->dcor : p->ddif;
+    double cv = 0;
+    for (int l = 0; l < p->nl; ++l) cv += p->C4[l] * 4.0 * M_PI * p->v[l];
+    for (int a = 0; a < 3; ++a) g.Hm[a] = cv * p->H[a] / (2.0 * M_PI);
+    g.corr = corr;
+    g.r = p->cg_r;
+    g.z = p->cg_z;
+    g.p = p->cg_p;
+    g.Ap = p->cg_Ap;
+    g.diag = p->cg_diag;
+    g.part = p->cg_part;
+    g.scal = p->cg_scal;
+    return g;
+}
+
+// per-cell quantities that depend on gamma: S, conductivities, CG couplings
+void cell_setup(bte_problem *p, hipStream_t s)
+{
+    launch_cell_setup(p->dev, p->S, p->kdif, p->kcor, p->M, p->H, s);
+    for (int corr = 0; corr < 2; ++corr) {
+        CgArgs g = cg_args(p, corr);
+        launch_cg_coef(p->dev, g, corr ? p->ccor : p->cdif, corr ? p->dcor : p->ddif, s);
+    }
+}
+
 template <typename T> bte_status moments_to(bte_problem *p, const T *e, const double *dpend, hipStream_t s)
 {
     // one partial per cell in part[0]
@@ -648,50 +720,25 @@ template <typename T> bte_status moments_to(bte_problem *p, const T *e, const do
 }
 
 // Jacobi-preconditioned CG on the heat-diffusion (corr = 0) or correction
-// (corr = 1) operator; b is projected per floating geometry beforehand, x is
-// projected afterwards.  Returns iterations, -1 on HIP error.
-int run_cg(bte_problem *p, int corr, double *b, double *x_out, double rtol, int maxit, hipStream_t s)
+// (corr = 1) operator in one cooperative launch; b is projected per floating
+// geometry beforehand, x afterwards.  Asynchronous: the iteration count is
+// accumulated on the device (cg_scal[9]).  Returns false on a HIP error.
+bool run_cg(bte_problem *p, int corr, double *b, double *x_out, double rtol, int maxit, hipStream_t s)
 {
     const Dev &d = p->dev;
     if (p->floating_any) {
         launch_film_mean(d, b, p->fmean, s);
         launch_sub_film_mean(d, b, p->fmean, s);
     }
-    CgArgs g;
-    g.kax = corr ? p->kcor : p->kdif;
-    double cv = 0;
-    for (int l = 0; l < p->nl; ++l) cv += p->C4[l] * 4.0 * M_PI * p->v[l];
-    for (int a = 0; a < 3; ++a) g.Hm[a] = cv * p->H[a] / (2.0 * M_PI);
-    g.corr = corr;
-    g.x = p->cg_x;
-    g.r = p->cg_r;
-    g.z = p->cg_z;
-    g.p = p->cg_p;
-    g.Ap = p->cg_Ap;
-    g.diag = p->cg_diag;
-    g.part = p->cg_part;
-    g.scal = p->cg_scal;
+    CgArgs g = cg_args(p, corr);
+    g.x = x_out;
     g.rtol2 = rtol * rtol;
-    launch_cg_init(d, g, b, s);
-    int it = 0;
-    const int poll = 8;
-    double sc[16];
-    while (it < maxit) {
-        int n = std::min(poll, maxit - it);
-        for (int i = 0; i < n; ++i) launch_cg_iter(d, g, it + i, s);
-        it += n;
-        if (hipMemcpyAsync(sc, p->cg_scal, sizeof sc, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
-        if (hipStreamSynchronize(s) != hipSuccess) return -1;
-        if (sc[5] != 0.0) break;
-    }
-    if (hipMemcpyAsync(sc, p->cg_scal, sizeof sc, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
-    if (hipStreamSynchronize(s) != hipSuccess) return -1;
+    if (launch_cg_persist(d, g, b, maxit, s) != hipSuccess) return false;
     if (p->floating_any) {
-        launch_film_mean(d, p->cg_x, p->fmean, s);
-        launch_sub_film_mean(d, p->cg_x, p->fmean, s);
+        launch_film_mean(d, x_out, p->fmean, s);
+        launch_sub_film_mean(d, x_out, p->fmean, s);
     }
-    if (hipMemcpyAsync(x_out, p->cg_x, 8 * (size_t)p->nc, hipMemcpyDeviceToDevice, s) != hipSuccess) return -1;
-    return (int)sc[6];
+    return hipGetLastError() == hipSuccess;
 }
 
 template <typename T>
@@ -705,14 +752,13 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
     T *buf[2] = {e, (T *)p->e2};
     int cur = 0;
     HIPCHK(p, hipMemsetAsync(p->dpend, 0, 8 * (size_t)nc, s));
+    HIPCHK(p, hipMemsetAsync(p->cg_scal, 0, 8 * 16, s));
     if (init) {
-        CgArgs g{};
-        g.kax = p->kdif;
-        g.corr = 0;
+        CgArgs g = cg_args(p, 0);
         launch_diff_rhs(d, g, p->r, s);
-        int it = run_cg(p, 0, p->r, p->T0, 1e-13, 200000, s);
-        if (it < 0) FAIL(p, BTE_ERR_HIP, "CG failed");
+        if (!run_cg(p, 0, p->r, p->T0, 1e-13, 200000, s)) FAIL(p, BTE_ERR_HIP, "CG failed");
         launch_set_equilibrium<T>(d, e, p->T0, s);
+        HIPCHK(p, hipMemsetAsync(p->cg_scal, 0, 8 * 16, s));   // count correction CG only
     }
     // moments of the start field
     launch_moments<T>(d, e, nullptr, p->part, s);
@@ -738,8 +784,8 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
         HIPCHK(p, hipEventRecord(ev[1], s));
         for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
             const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
-            launch_sweep<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt, p->tdim, p->na_oct,
-                            p->nchunk_oct, p->part, s);
+            HIPCHK(p, launch_sweep_tile<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt, p->tdim,
+                                           p->na_oct, p->nchunk_oct, p->tile_cap, p->part, s));
             st.sweep_launches += cnt > 0;
         }
         HIPCHK(p, hipEventRecord(ev[2], s));
@@ -748,9 +794,8 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
         HIPCHK(p, hipEventRecord(ev[3], s));
         HIPCHK(p, hipGetLastError());
         if (synthetic) {
-            int it = run_cg(p, 1, p->r, p->delta, p->ctl.cg_rtol, p->ctl.cg_max_iter, s);
-            if (it < 0) FAIL(p, BTE_ERR_HIP, "CG failed");
-            st.cg_iters += it;
+            if (!run_cg(p, 1, p->r, p->delta, p->ctl.cg_rtol, p->ctl.cg_max_iter, s))
+                FAIL(p, BTE_ERR_HIP, "CG failed");
             launch_tl_update(nc, p->TLkin, p->delta, p->TL, p->dpend, s);
         } else {
             launch_tl_update(nc, p->TLkin, nullptr, p->TL, nullptr, s);
@@ -810,6 +855,11 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
     launch_apply_shift<T>(d, buf[cur], e, synthetic ? p->dpend : nullptr, fshift, s);
     HIPCHK(p, hipGetLastError());
     HIPCHK(p, hipStreamSynchronize(s));
+    {
+        double sc[16];
+        HIPCHK(p, hipMemcpy(sc, p->cg_scal, sizeof sc, hipMemcpyDeviceToHost));
+        st.cg_iters = (int)sc[9];
+    }
     st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = st;
     if (ret == BTE_ERR_NOT_CONVERGED) p->err = "not converged within max_iter";
@@ -824,10 +874,8 @@ bte_status transient_impl(bte_problem *p, T *e, int n_steps, double t0, const do
     const double dt = p->ctl.dt;
     T *buf[2] = {e, (T *)p->e2};
     int cur = 0;
-    const int cpb = 4;
     launch_moments<T>(d, e, nullptr, p->part, s);
     launch_finalize(d, p->part, 1, p->Tref, nullptr, nullptr, nullptr, p->TL, nullptr, nullptr, s);
-    const int nchunk = (p->nk + kBlock - 1) / kBlock;
     for (int n = 0; n < n_steps; ++n) {
         const double t = t0 + n * dt;
         double src = 1.0;
@@ -836,8 +884,10 @@ bte_status transient_impl(bte_problem *p, T *e, int n_steps, double t0, const do
             src = std::exp(-4.0 * std::log(2.0) * x * x / (pulse[1] * pulse[1]));
         }
         launch_walls<T>(d, buf[cur], nullptr, p->d_wrec, p->d_wden, p->din, p->nw, s);
-        launch_transient<T>(d, buf[cur], buf[1 - cur], p->TL, p->din, src, dt, p->part, cpb, s);
-        launch_finalize(d, p->part, nchunk, p->Tref, nullptr, nullptr, nullptr, p->TL, nullptr, nullptr, s);
+        HIPCHK(p, launch_transient_tile<T>(d, buf[cur], buf[1 - cur], p->TL, p->din, p->d_titems,
+                                           (int)p->titems.size(), p->tdim, p->na_oct, p->nchunk_oct, p->tile_cap,
+                                           src, dt, p->part, s));
+        launch_finalize_tl(d, p->part, p->noct, p->TL, s);
         cur = 1 - cur;
     }
     if (cur != 0) HIPCHK(p, hipMemcpyAsync(e, buf[cur], p->esize() * p->nelem(), hipMemcpyDeviceToDevice, s));

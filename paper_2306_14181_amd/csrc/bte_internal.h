@@ -41,6 +41,7 @@ struct Film {
     int cell0, ncell;        // first cell and number of cells in the global numbering
     int nsolid;
     int floating;            // no thermalizing wall: gauge fixed by zero mean T - T_ref
+    int periodic[3];         // axis is periodic
 };
 
 // Everything a kernel needs to evaluate the discrete operators.
@@ -70,9 +71,16 @@ struct SweepItem {
     int film, oct, chunk, tile;
 };
 
+// One work item of the transient step: a tile of one geometry for every lane of one octant.
+struct TileItem {
+    int film, oct, tile, pad;
+};
+
 // Arguments of the conjugate-gradient kernels.
 struct CgArgs {
     const double *kax;      // [3][nc] per-axis conductivity
+    const double *coef;     // [6][nc] coupling to the neighbour across each face (0: none)
+    const double *dg;       // [nc] diagonal (faces plus thermalizing walls)
     double Hm[3];           // wall emission conductance sum C v H_a/(2pi) (correction operator only)
     int corr;               // 1: correction operator, 0: heat diffusion
     double *x, *r, *z, *p, *Ap, *diag;

@@ -6,6 +6,10 @@
 // getTQ) are accumulated in FP64 and reduced deterministically: a butterfly
 // within each 64-wide wavefront, then a fixed-order sum over the block's
 // wavefronts, then a fixed-order sum over k-chunks in a finalize kernel.
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+
 #include "bte_internal.h"
 #include "bte_stencil.h"
 
@@ -129,6 +133,16 @@ __global__ void k_finalize(Dev d, const double *__restrict__ part, int np, doubl
     if (qmag) qmag[c] = solid ? sqrt(s[2] * s[2] + s[3] * s[3] + s[4] * s[4]) : 0.0;
 }
 
+// T_L deviation from per-octant partials of sum w e/tau (transient step)
+__global__ void k_finalize_tl(Dev d, const double *__restrict__ part, int np, double *__restrict__ TLdev)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.nc) return;
+    double s = 0;
+    for (int p = 0; p < np; ++p) s += part[(size_t)p * d.nc + c];
+    TLdev[c] = (d.code[c] & kSolidBit) ? s / d.S[c] : 0.0;
+}
+
 // ---------------------------------------------------------------- diffuse walls
 
 // Incoming value of each diffuse wall record (Sec. 2.2, eq. diff_bound, with
@@ -174,57 +188,6 @@ __global__ __launch_bounds__(kBlock) void k_walls(Dev d, const T *__restrict__ e
     }
 }
 
-// ------------------------------------------------------------ transient step
-
-// Explicit step (Sec. 4.1, eq. disretized_transientBTE with V and dt placed
-// dimensionally): e' = e + dt [ -(1/V) sum_f e_f v s.n S - (e - C T_L/4pi)/tau + Q ],
-// with FP64 moment partials of e' per (k-chunk, cell).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_transient(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
-                                                       const double *__restrict__ TLdev, const double *__restrict__ din,
-                                                       double src, double dt, double *__restrict__ part, int nchunk,
-                                                       int ngroup, int cpb)
-{
-    __shared__ double sh[4 * kMomN];
-    const int lb = xcd_logical_block();
-    const int chunk = lb / ngroup, grp = lb - chunk * ngroup;
-    if (chunk >= nchunk) return;
-    const int k = chunk * kBlock + threadIdx.x;
-    const bool active = k < d.nk;
-    const LaneConst L = lane_const(d, active ? k : 0);
-    const int c0 = grp * cpb;
-    for (int ci = 0; ci < cpb; ++ci) {
-        const int c = c0 + ci;
-        if (c >= d.nc) break;
-        const uint32_t code = d.code[c];
-        double acc[kMomN] = {0, 0, 0, 0, 0};
-        if (!(code & kSolidBit)) {
-            if (active) eout[(size_t)c * d.nk + k] = ein[(size_t)c * d.nk + k];
-        } else {
-            const Film &fm = d.film[d.fid[c]];
-            const double itc = L.itau + d.gamma[c];
-            const double qsrc = d.P ? src * d.P[c] / d.Ctot : 0.0;
-            const double tl = TLdev[c];
-            if (active) {
-                const T ec = ein[(size_t)c * d.nk + k];
-                const StencilOut<T> so = stencil<T>(ein, nullptr, din, d, fm, c, code, L, ec);
-                const T e0 = (T)(L.C4 * tl);
-                const T en = ec + (T)dt * (-so.D - (ec - e0) * (T)itc + (T)(L.C4 * qsrc));
-                eout[(size_t)c * d.nk + k] = en;
-                const double x = L.w * (double)en;
-                acc[0] = x;
-                acc[1] = x * itc;
-                acc[2] = x * L.v * L.s[0];
-                acc[3] = x * L.v * L.s[1];
-                acc[4] = x * L.v * L.s[2];
-            }
-        }
-        block_sum<kMomN>(acc, sh);
-        if (threadIdx.x == 0)
-            for (int i = 0; i < kMomN; ++i) part[((size_t)chunk * d.nc + c) * kMomN + i] = acc[i];
-    }
-}
-
 // Steady residual R(e) with e0 from TLdev (right-hand side of eq. B_BTE).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_residual(Dev d, const T *__restrict__ e, T *__restrict__ R,
@@ -252,148 +215,6 @@ __global__ __launch_bounds__(kBlock) void k_residual(Dev d, const T *__restrict_
         const StencilOut<T> so = stencil<T>(e, nullptr, din, d, fm, c, code, L, ec);
         const T e0 = (T)(L.C4 * TLdev[c]);
         R[(size_t)c * d.nk + k] = -so.D - (ec - e0) * (T)itc + (T)(L.C4 * qsrc);
-    }
-}
-
-// ------------------------------------------------------------------- sweep
-//
-// One source-iteration transport solve in delta form (eq. disretized_BTE;
-// stiffness matrix A and right-hand side b of Sec. 3.5):  A de = b with
-// b = R(e^n; T_L^n), A_ii = 1/tau + sum_a |v s_a|/h_a, A_ij = -|v s_a|/h_a for
-// the upwind neighbour across an interior face (walls and periodic faces
-// are lagged into b).  A is lower-triangular in the upwind order of each
-// octant, so the solve is a sweep.  Cells are grouped in tiles; tiles on
-// one wavefront (hyperplane) of an octant are independent and run in one
-// launch, successive wavefronts in successive launches.  A 256-thread block
-// handles one tile for 64 (direction, band) lanes of one octant:
-//   phase A (4 wavefronts): b for every cell of the tile, plus the inflow of
-//     the already-swept upstream tiles, into LDS;
-//   phase B (wavefront 0): the upwind recurrence across the tile's cells;
-//   phase C (4 wavefronts): e^{n+1} = e^n + de and FP64 moment partials.
-constexpr int kTileCells = 64;
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
-                                                   const double *__restrict__ dpend, const double *__restrict__ TLdev,
-                                                   const double *__restrict__ din, const SweepItem *__restrict__ items,
-                                                   int item0, int3 tdim, int na_oct, int nchunk_oct,
-                                                   double *__restrict__ part)
-{
-    __shared__ T bsh[kTileCells][64];
-    __shared__ T esh[kTileCells][64];
-    __shared__ int cell_sh[kTileCells];
-    __shared__ int upin_sh[kTileCells][3];   // in-tile upwind flow index per axis or -1
-    __shared__ double gam_sh[kTileCells];
-
-    const SweepItem it = items[item0 + blockIdx.x];
-    const Film &fm = d.film[it.film];
-    const int wave = threadIdx.x >> 6, t = threadIdx.x & 63;
-    const int kbeg = it.oct * na_oct * d.nl;
-    const int kend = kbeg + na_oct * d.nl;
-    const int k = kbeg + it.chunk * 64 + t;
-    const bool active = k < kend;
-    const LaneConst L = lane_const(d, active ? k : kbeg);
-
-    // octant flow signs from a representative direction of the octant
-    int sg[3];
-    for (int a = 0; a < 3; ++a) sg[a] = d.s[3 * (it.oct * na_oct) + a] > 0 ? 1 : -1;
-
-    // tile origin and extent in film coordinates
-    const int ntx = (fm.n[0] + tdim.x - 1) / tdim.x, nty = (fm.n[1] + tdim.y - 1) / tdim.y;
-    const int tx = it.tile % ntx, ty = (it.tile / ntx) % nty, tz = it.tile / (ntx * nty);
-    const int x0 = tx * tdim.x, y0 = ty * tdim.y, z0 = tz * tdim.z;
-    const int ex = min(tdim.x, fm.n[0] - x0), ey = min(tdim.y, fm.n[1] - y0), ez = min(tdim.z, fm.n[2] - z0);
-    const int ncell = ex * ey * ez;
-
-    // flow-ordered enumeration of the tile's cells
-    if (threadIdx.x < ncell) {
-        const int i = threadIdx.x;
-        const int fx = i % ex, fy = (i / ex) % ey, fz = i / (ex * ey);
-        const int ix = x0 + (sg[0] > 0 ? fx : ex - 1 - fx);
-        const int iy = y0 + (sg[1] > 0 ? fy : ey - 1 - fy);
-        const int iz = z0 + (d.dim > 2 ? (sg[2] > 0 ? fz : ez - 1 - fz) : fz);
-        const int c = fm.cell0 + ix + fm.n[0] * (iy + fm.n[1] * iz);
-        cell_sh[i] = c;
-        const uint32_t code = d.code[c];
-        const int f[3] = {fx, fy, fz};
-        const int stride[3] = {1, ex, ex * ey};
-        for (int a = 0; a < 3; ++a) {
-            int u = -1;
-            if (a < d.dim && f[a] > 0) {
-                const uint32_t ab = axis_bits(code, a);
-                if (side_is_cell(ab, -sg[a]) && !side_wraps(ab, -sg[a])) u = i - stride[a];
-            }
-            upin_sh[i][a] = u;
-        }
-        gam_sh[i] = d.gamma[c];
-    }
-    __syncthreads();
-
-    // phase A
-    for (int i = wave; i < ncell; i += 4) {
-        const int c = cell_sh[i];
-        const uint32_t code = d.code[c];
-        T b = (T)0, ec = (T)0;
-        if ((code & kSolidBit) && active) {
-            const T C4 = (T)L.C4;
-            ec = ld_e(ein, dpend, d, c, k, C4);
-            const StencilOut<T> so = stencil<T>(ein, dpend, din, d, fm, c, code, L, ec);
-            const double itc = L.itau + d.gamma[c];
-            b = -so.D - (ec - (T)(L.C4 * TLdev[c])) * (T)itc;
-            if (d.P) b += (T)(L.C4 * d.P[c] / d.Ctot);
-            for (int a = 0; a < d.dim; ++a)
-                if (so.jup[a] >= 0 && upin_sh[i][a] < 0) b += so.cup[a] * (eout[(size_t)so.jup[a] * d.nk + k] - so.eup[a]);
-        } else if (active) {
-            ec = ein[(size_t)c * d.nk + k];
-        }
-        bsh[i][t] = b;
-        esh[i][t] = ec;
-    }
-    __syncthreads();
-
-    // phase B
-    if (wave == 0 && active) {
-        T cpl[3];
-        T A0 = (T)0;
-        for (int a = 0; a < 3; ++a) {
-            cpl[a] = a < d.dim ? (T)(L.v * fabs(L.s[a]) * fm.ih[a]) : (T)0;
-            A0 += cpl[a];
-        }
-        for (int i = 0; i < ncell; ++i) {
-            if (!(d.code[cell_sh[i]] & kSolidBit)) {
-                bsh[i][t] = (T)0;
-                continue;
-            }
-            T num = bsh[i][t];
-            for (int a = 0; a < d.dim; ++a) {
-                const int u = upin_sh[i][a];
-                if (u >= 0) num += cpl[a] * bsh[u][t];
-            }
-            bsh[i][t] = num / (A0 + (T)(L.itau + gam_sh[i]));
-        }
-    }
-    __syncthreads();
-
-    // phase C
-    const int pidx = it.oct * nchunk_oct + it.chunk;
-    for (int i = wave; i < ncell; i += 4) {
-        const int c = cell_sh[i];
-        double acc[kMomN] = {0, 0, 0, 0, 0};
-        if (active) {
-            const T en = esh[i][t] + bsh[i][t];
-            eout[(size_t)c * d.nk + k] = en;
-            if (d.code[c] & kSolidBit) {
-                const double x = L.w * (double)en;
-                acc[0] = x;
-                acc[1] = x * (L.itau + gam_sh[i]);
-                acc[2] = x * L.v * L.s[0];
-                acc[3] = x * L.v * L.s[1];
-                acc[4] = x * L.v * L.s[2];
-            }
-        }
-        wave_sum<kMomN>(acc);
-        if (t == 0)
-            for (int q = 0; q < kMomN; ++q) part[((size_t)pidx * d.nc + c) * kMomN + q] = acc[q];
     }
 }
 
@@ -538,32 +359,53 @@ __device__ inline double wall_cond(const Dev &d, const CgArgs &g, int c, int a, 
     return 1.0 / (1.0 / kd + 1.0 / g.Hm[a]);
 }
 
-// row c of L applied to x (x may be null: diagonal only)
+// row c of L applied to x (x may be null: diagonal only), from the
+// precomputed face couplings and diagonal
 __device__ inline double lap_row(const Dev &d, const CgArgs &g, int c, const double *__restrict__ x, double *dg)
 {
+    const double di = g.dg[c];
+    if (dg) *dg = di;
+    if (!x) return 0.0;
+    double acc = di * x[c];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const double cf = g.coef[f * d.nc + c];
+        if (cf != 0.0) acc -= cf * x[d.nb[f * d.nc + c]];
+    }
+    return acc;
+}
+
+// Face couplings and diagonal of the diffusion operator per unit volume:
+// harmonic-mean face conductivity k_f / h^2 between solid neighbours (periodic
+// faces wrap), a thermalizing wall adds its conductance / h to the diagonal,
+// other walls nothing.
+__global__ void k_cg_coef(Dev d, CgArgs g, double *coef, double *dgo)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.nc) return;
     const uint32_t code = d.code[c];
-    const Film &fm = d.film[d.fid[c]];
-    double acc = 0.0, diag = 0.0;
-    for (int a = 0; a < d.dim; ++a) {
-        const double ih2 = fm.ih[a] * fm.ih[a];
-        const double ki = g.kax[a * d.nc + c];
-        const uint32_t ab = axis_bits(code, a);
-        for (int side = -1; side <= 1; side += 2) {
-            if (side_is_cell(ab, side)) {
-                const int j = d.nb[face_of(a, side) * d.nc + c];
-                const double kj = g.kax[a * d.nc + j];
-                const double kf = 2.0 * ki * kj / (ki + kj) * ih2;
-                if (x) acc += kf * (x[c] - x[j]);
-                diag += kf;
-            } else if (side_wall(ab, side) == 0) {
-                const double wc = wall_cond(d, g, c, a, fm) * fm.ih[a];
-                if (x) acc += wc * x[c];
-                diag += wc;
+    for (int f = 0; f < 6; ++f) coef[f * d.nc + c] = 0.0;
+    double diag = 0.0;
+    if (code & kSolidBit) {
+        const Film &fm = d.film[d.fid[c]];
+        for (int a = 0; a < d.dim; ++a) {
+            const double ih2 = fm.ih[a] * fm.ih[a];
+            const double ki = g.kax[a * d.nc + c];
+            const uint32_t ab = axis_bits(code, a);
+            for (int side = -1; side <= 1; side += 2) {
+                if (side_is_cell(ab, side)) {
+                    const int j = d.nb[face_of(a, side) * d.nc + c];
+                    const double kj = g.kax[a * d.nc + j];
+                    const double kf = 2.0 * ki * kj / (ki + kj) * ih2;
+                    coef[face_of(a, side) * d.nc + c] = kf;
+                    diag += kf;
+                } else if (side_wall(ab, side) == 0) {
+                    diag += wall_cond(d, g, c, a, fm) * fm.ih[a];
+                }
             }
         }
     }
-    if (dg) *dg = diag;
-    return acc;
+    dgo[c] = (code & kSolidBit) && diag > 0 ? diag : 1.0;
 }
 
 __device__ inline double blk_sum1(double v, double *sh)
@@ -573,133 +415,106 @@ __device__ inline double blk_sum1(double v, double *sh)
     return a[0];
 }
 
-// init: x = 0, r = b (already projected), z = r/diag, p = z, partials of r.z and r.r
-__global__ __launch_bounds__(kBlock) void k_cg_init(Dev d, CgArgs g, const double *__restrict__ b)
+// The whole Jacobi-preconditioned CG in one cooperative launch: cells are
+// strided over the grid, the two dot products of an iteration are reduced
+// per block and summed in block order by every block after a grid barrier
+// (deterministic), and the convergence test runs on the device.  scal[6]
+// receives the iteration count and scal[9] accumulates it over calls.
+__device__ inline void block_sum2(double &a, double &b, double *sh)
 {
-    __shared__ double sh[8];
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    double rz = 0, rr = 0;
-    if (c < d.nc) {
-        const bool solid = d.code[c] & kSolidBit;
-        double dg = 1.0;
-        if (solid) lap_row(d, g, c, nullptr, &dg);
-        if (!(dg > 0)) dg = 1.0;
-        const double rc = solid ? b[c] : 0.0;
-        g.diag[c] = dg;
-        g.x[c] = 0.0;
-        g.r[c] = rc;
-        g.z[c] = rc / dg;
-        g.p[c] = rc / dg;
-        rz = rc * rc / dg;
-        rr = rc * rc;
-    }
-    rz = blk_sum1(rz, sh);
-    rr = blk_sum1(rr, sh);
-    if (threadIdx.x == 0) {
-        g.part[2 * blockIdx.x] = rz;
-        g.part[2 * blockIdx.x + 1] = rr;
-    }
+    double v[2] = {a, b};
+    block_sum<2>(v, sh);
+    a = v[0];
+    b = v[1];
 }
 
-__global__ void k_cg_init2(CgArgs g, int nblk)
+__global__ __launch_bounds__(kBlock) void k_cg_persist(Dev d, CgArgs g, const double *__restrict__ b, int maxit)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double rz = 0, rr = 0;
-    for (int i = 0; i < nblk; ++i) {
-        rz += g.part[2 * i];
-        rr += g.part[2 * i + 1];
-    }
-    g.scal[7] = rz;
-    g.scal[1] = rr;
-    g.scal[5] = (rr > 0.0 && rz > 0.0) ? 0.0 : 1.0;
-    g.scal[6] = 0.0;
-}
-
-// Ap = L p, partial p.Ap
-__global__ __launch_bounds__(kBlock) void k_cg_a(Dev d, CgArgs g)
-{
-    __shared__ double sh[8];
-    if (g.scal[5] != 0.0) return;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    double pap = 0;
-    if (c < d.nc) {
-        const double y = (d.code[c] & kSolidBit) ? lap_row(d, g, c, g.p, nullptr) : 0.0;
-        g.Ap[c] = y;
-        pap = g.p[c] * y;
-    }
-    pap = blk_sum1(pap, sh);
-    if (threadIdx.x == 0) g.part[2 * blockIdx.x] = pap;
-}
-
-// alpha = rz / pAp; x += alpha p; r -= alpha Ap; z = r/diag; partials r.z, r.r
-__global__ __launch_bounds__(kBlock) void k_cg_b(Dev d, CgArgs g, int nblk, int parity)
-{
-    __shared__ double sh[8];
-    __shared__ double alpha_sh;
-    if (g.scal[5] != 0.0) return;
-    if (threadIdx.x == 0) {
-        double pap = 0;
-        for (int i = 0; i < nblk; ++i) pap += g.part[2 * i];
-        alpha_sh = (pap > 0.0) ? g.scal[7 + parity] / pap : 0.0;
-        if (blockIdx.x == 0) g.scal[2] = pap;
-    }
-    __syncthreads();
-    const double alpha = alpha_sh;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    double rz = 0, rr = 0;
-    if (c < d.nc) {
-        g.x[c] += alpha * g.p[c];
-        const double rc = g.r[c] - alpha * g.Ap[c];
-        g.r[c] = rc;
-        const double zc = rc / g.diag[c];
-        g.z[c] = zc;
-        rz = rc * zc;
-        rr = rc * rc;
-    }
-    __syncthreads();
-    rz = blk_sum1(rz, sh);
-    rr = blk_sum1(rr, sh);
-    if (threadIdx.x == 0) {
-        g.part[2 * nblk + 2 * blockIdx.x] = rz;
-        g.part[2 * nblk + 2 * blockIdx.x + 1] = rr;
-    }
-}
-
-// beta = rz_new / rz; p = z + beta p; convergence / breakdown flag
-__global__ __launch_bounds__(kBlock) void k_cg_c(Dev d, CgArgs g, int nblk, int parity)
-{
-    __shared__ double beta_sh, done_sh;
-    if (g.scal[5] != 0.0) return;
-    if (threadIdx.x == 0) {
-        double rz = 0, rr = 0;
-        for (int i = 0; i < nblk; ++i) {
-            rz += g.part[2 * nblk + 2 * i];
-            rr += g.part[2 * nblk + 2 * i + 1];
+    namespace cgr = cooperative_groups;
+    cgr::grid_group grid = cgr::this_grid();
+    __shared__ double sh[16];
+    __shared__ double red[2];
+    const int nblk = gridDim.x;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = nblk * blockDim.x;
+    double *pa = g.part, *pb = g.part + 2 * nblk;
+    auto grid_sum2 = [&](double a, double c, double *buf) {
+        block_sum2(a, c, sh);
+        if (threadIdx.x == 0) {
+            buf[2 * blockIdx.x] = a;
+            buf[2 * blockIdx.x + 1] = c;
         }
-        const double rz_old = g.scal[7 + parity];
-        const bool done = !(g.scal[2] > 0.0) || rr <= g.rtol2 * g.scal[1] || !(rz > 0.0);
-        beta_sh = done ? 0.0 : rz / rz_old;
-        done_sh = done ? 1.0 : 0.0;
-        if (blockIdx.x == 0) g.scal[8 - parity] = rz;
-    }
-    __syncthreads();
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < d.nc && done_sh == 0.0) g.p[c] = g.z[c] + beta_sh * g.p[c];
-}
-
-// bookkeeping after k_cg_c of one iteration (single thread): count, done flag
-__global__ void k_cg_tick(CgArgs g, int nblk)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (g.scal[5] != 0.0) return;
+        grid.sync();
+        if (threadIdx.x == 0) {
+            double s0 = 0, s1 = 0;
+            for (int i = 0; i < nblk; ++i) {
+                s0 += buf[2 * i];
+                s1 += buf[2 * i + 1];
+            }
+            red[0] = s0;
+            red[1] = s1;
+        }
+        __syncthreads();
+    };
+    double *__restrict__ X = g.x;
+    double *__restrict__ Rv = g.r;
+    double *__restrict__ Z = g.z;
+    double *__restrict__ Pv = g.p;
+    double *__restrict__ AP = g.Ap;
+    const double *__restrict__ DG = g.dg;
     double rz = 0, rr = 0;
-    for (int i = 0; i < nblk; ++i) {
-        rz += g.part[2 * nblk + 2 * i];
-        rr += g.part[2 * nblk + 2 * i + 1];
+    for (int c = tid; c < d.nc; c += nthr) {
+        const bool solid = d.code[c] & kSolidBit;
+        const double dg = DG[c];
+        const double rc = solid ? b[c] : 0.0;
+        X[c] = 0.0;
+        Rv[c] = rc;
+        Z[c] = rc / dg;
+        Pv[c] = rc / dg;
+        rz += rc * rc / dg;
+        rr += rc * rc;
     }
-    g.scal[6] += 1.0;
-    g.scal[3] = rr;
-    if (!(g.scal[2] > 0.0) || rr <= g.rtol2 * g.scal[1] || !(rz > 0.0)) g.scal[5] = 1.0;
+    grid_sum2(rz, rr, pa);
+    rz = red[0];
+    const double bn2 = red[1];
+    int it = 0;
+    if (bn2 > 0.0 && rz > 0.0) {
+        grid.sync();   // p visible to every block
+        while (it < maxit) {
+            double pap = 0;
+            for (int c = tid; c < d.nc; c += nthr) {
+                const double y = lap_row(d, g, c, Pv, nullptr);
+                AP[c] = y;
+                pap += Pv[c] * y;
+            }
+            grid_sum2(pap, 0.0, pa);
+            pap = red[0];
+            if (!(pap > 0.0)) break;
+            ++it;
+            const double alpha = rz / pap;
+            double rz2 = 0, rr2 = 0;
+            for (int c = tid; c < d.nc; c += nthr) {
+                X[c] += alpha * Pv[c];
+                const double rc = Rv[c] - alpha * AP[c];
+                Rv[c] = rc;
+                const double zc = rc / DG[c];
+                Z[c] = zc;
+                rz2 += rc * zc;
+                rr2 += rc * rc;
+            }
+            grid_sum2(rz2, rr2, pb);
+            rz2 = red[0];
+            rr2 = red[1];
+            if (rr2 <= g.rtol2 * bn2 || !(rz2 > 0.0)) break;
+            const double beta = rz2 / rz;
+            rz = rz2;
+            for (int c = tid; c < d.nc; c += nthr) Pv[c] = Z[c] + beta * Pv[c];
+            grid.sync();
+        }
+    }
+    if (tid == 0) {
+        g.scal[6] = it;
+        g.scal[9] += it;
+    }
 }
 
 // right-hand side of the heat-diffusion initial guess: P plus thermalizing
@@ -770,31 +585,11 @@ static inline void stream_grid(const Dev &d, int cpb, int &nchunk, int &ngroup, 
 }
 
 template <typename T>
-void launch_transient(const Dev &d, const T *ein, T *eout, const double *TLdev, const double *din, double src,
-                      double dt, double *part, int cpb, hipStream_t s)
-{
-    int nchunk, ngroup, grid;
-    stream_grid(d, cpb, nchunk, ngroup, grid);
-    hipLaunchKernelGGL(k_transient<T>, dim3(grid), dim3(kBlock), 0, s, d, ein, eout, TLdev, din, src, dt, part,
-                       nchunk, ngroup, cpb);
-}
-
-template <typename T>
 void launch_residual(const Dev &d, const T *e, T *R, const double *TLdev, const double *din, int cpb, hipStream_t s)
 {
     int nchunk, ngroup, grid;
     stream_grid(d, cpb, nchunk, ngroup, grid);
     hipLaunchKernelGGL(k_residual<T>, dim3(grid), dim3(kBlock), 0, s, d, e, R, TLdev, din, nchunk, ngroup, cpb);
-}
-
-template <typename T>
-void launch_sweep(const Dev &d, const T *ein, T *eout, const double *dpend, const double *TLdev, const double *din,
-                  const SweepItem *items, int item0, int count, int3 tdim, int na_oct, int nchunk_oct, double *part,
-                  hipStream_t s)
-{
-    if (count > 0)
-        hipLaunchKernelGGL(k_sweep<T>, dim3(count), dim3(kBlock), 0, s, d, ein, eout, dpend, TLdev, din, items,
-                           item0, tdim, na_oct, nchunk_oct, part);
 }
 
 template <typename T>
@@ -818,11 +613,7 @@ void launch_keff(const Dev &d, const double *q, double *keff, hipStream_t s)
     template void launch_moments<T>(const Dev &, const T *, const double *, double *, hipStream_t);                  \
     template void launch_walls<T>(const Dev &, const T *, const double *, const int *, const double *, double *,     \
                                   int, hipStream_t);                                                                 \
-    template void launch_transient<T>(const Dev &, const T *, T *, const double *, const double *, double, double,   \
-                                      double *, int, hipStream_t);                                                   \
     template void launch_residual<T>(const Dev &, const T *, T *, const double *, const double *, int, hipStream_t); \
-    template void launch_sweep<T>(const Dev &, const T *, T *, const double *, const double *, const double *,       \
-                                  const SweepItem *, int, int, int3, int, int, double *, hipStream_t);               \
     template void launch_set_equilibrium<T>(const Dev &, T *, const double *, hipStream_t);                          \
     template void launch_apply_shift<T>(const Dev &, const T *, T *, const double *, const double *, hipStream_t);
 BTE_INST(float)
@@ -841,6 +632,11 @@ void launch_finalize(const Dev &d, const double *part, int np, double Tref, doub
 {
     const int grid = (d.nc + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kBlock), 0, s, d, part, np, Tref, T, TL, q, TLdev, Tdev, qmag);
+}
+
+void launch_finalize_tl(const Dev &d, const double *part, int np, double *TLdev, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize_tl, dim3((d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, part, np, TLdev);
 }
 
 void launch_steady_post(const Dev &d, const double *part, int np, const double *TLn, double *TLkin, double *Tnew,
@@ -872,23 +668,39 @@ void launch_tl_update(int n, const double *TLkin, const double *delta, double *T
     hipLaunchKernelGGL(k_tl_update, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, TLkin, delta, TL, dpend);
 }
 
-// CG driver pieces
-int cg_nblk(const Dev &d) { return (d.nc + kBlock - 1) / kBlock; }
-
-void launch_cg_init(const Dev &d, const CgArgs &g, const double *b, hipStream_t s)
+// blocks of the persistent CG: co-resident (cooperative launch); a grid
+// barrier costs more with more blocks, so use about one block per 16 cells
+// per thread (the operator work per iteration is tiny), at most 64.
+int cg_persist_blocks(const Dev &d)
 {
-    const int nb = cg_nblk(d);
-    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(kBlock), 0, s, d, g, b);
-    hipLaunchKernelGGL(k_cg_init2, dim3(1), dim3(64), 0, s, g, nb);
+    static int max_coresident = 0;
+    if (!max_coresident) {
+        int dev = 0, ncu = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return -1;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg_persist, kBlock, 0) != hipSuccess) return -1;
+        max_coresident = ncu * per;
+    }
+    const int need = (d.nc + 16 * kBlock - 1) / (16 * kBlock);
+    return std::max(1, std::min(std::min(need, 64), max_coresident));
 }
 
-void launch_cg_iter(const Dev &d, const CgArgs &g, int iter, hipStream_t s)
+hipError_t launch_cg_persist(const Dev &d, const CgArgs &g, const double *b, int maxit, hipStream_t s)
 {
-    const int nb = cg_nblk(d);
-    hipLaunchKernelGGL(k_cg_a, dim3(nb), dim3(kBlock), 0, s, d, g);
-    hipLaunchKernelGGL(k_cg_b, dim3(nb), dim3(kBlock), 0, s, d, g, nb, iter & 1);
-    hipLaunchKernelGGL(k_cg_c, dim3(nb), dim3(kBlock), 0, s, d, g, nb, iter & 1);
-    hipLaunchKernelGGL(k_cg_tick, dim3(1), dim3(64), 0, s, g, nb);
+    const int nb = cg_persist_blocks(d);
+    if (nb < 1) return hipErrorInvalidValue;
+    Dev dd = d;
+    CgArgs gg = g;
+    const double *bb = b;
+    int mi = maxit;
+    void *args[] = {&dd, &gg, &bb, &mi};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_cg_persist), dim3(nb), dim3(kBlock), args, 0,
+                                      s);
+}
+
+void launch_cg_coef(const Dev &d, const CgArgs &g, double *coef, double *dg, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_coef, dim3((d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, g, coef, dg);
 }
 
 void launch_diff_rhs(const Dev &d, const CgArgs &g, double *b, hipStream_t s)
