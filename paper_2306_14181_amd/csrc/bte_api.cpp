@@ -109,7 +109,9 @@ struct bte_problem {
     double M[3] = {0, 0, 0}, H[3] = {0, 0, 0};
     int nw = 0;
     // sweep schedule
-    int3 tdim{1, 1, 1};
+    int3 tdim{1, 1, 1};      // sweep tiles
+    int3 tdim_tr{1, 1, 1};   // transient tiles
+    int tile_cap_tr = 0;
     int nchunk_oct = 0;
     std::vector<SweepItem> items;
     std::vector<int> diag_off;
@@ -362,6 +364,10 @@ void build_schedule(bte_problem *p)
     else if (p->dim == 2) p->tdim = make_int3(8, 8, 1);
     else if (p->ctl.precision == BTE_F64) p->tdim = make_int3(4, 4, 2);   // LDS: 64 KiB star for FP64
     else p->tdim = make_int3(4, 4, 4);
+    // transient tiles: no recurrence, so size them for LDS occupancy (4-5 blocks per CU)
+    if (p->dim == 1) p->tdim_tr = make_int3(64, 1, 1);
+    else if (p->dim == 2) p->tdim_tr = make_int3(8, 8, 1);
+    else p->tdim_tr = make_int3(4, 4, 2);
     const int lanes_oct = p->na_oct * p->nl;
     p->nchunk_oct = (lanes_oct + 63) / 64;
     struct Rec {
@@ -394,18 +400,20 @@ void build_schedule(bte_problem *p)
     p->titems.clear();
     for (int f = 0; f < p->nfilm; ++f) {
         const Film &fm = p->films[f];
-        const int ntile = ((fm.n[0] + p->tdim.x - 1) / p->tdim.x) * ((fm.n[1] + p->tdim.y - 1) / p->tdim.y) *
-                          ((fm.n[2] + p->tdim.z - 1) / p->tdim.z);
+        const int ntile = ((fm.n[0] + p->tdim_tr.x - 1) / p->tdim_tr.x) *
+                          ((fm.n[1] + p->tdim_tr.y - 1) / p->tdim_tr.y) * ((fm.n[2] + p->tdim_tr.z - 1) / p->tdim_tr.z);
         for (int o = 0; o < p->noct; ++o)
             for (int t = 0; t < ntile; ++t) p->titems.push_back({f, o, t, 0});
     }
-    {
-        const int e[3] = {p->tdim.x, p->tdim.y, p->tdim.z};
+    auto cap_of = [&](int3 td) {
+        const int e[3] = {td.x, td.y, td.z};
         const int cells = e[0] * e[1] * e[2];
         int halo = 0;
         for (int a = 0; a < p->dim; ++a) halo += 3 * cells / e[a];
-        p->tile_cap = cells + halo;
-    }
+        return cells + halo;
+    };
+    p->tile_cap = cap_of(p->tdim);
+    p->tile_cap_tr = cap_of(p->tdim_tr);
     p->items.clear();
     p->diag_off.assign(maxd + 2, 0);
     for (auto &r : recs) {
@@ -885,7 +893,7 @@ bte_status transient_impl(bte_problem *p, T *e, int n_steps, double t0, const do
         }
         launch_walls<T>(d, buf[cur], nullptr, p->d_wrec, p->d_wden, p->din, p->nw, s);
         HIPCHK(p, launch_transient_tile<T>(d, buf[cur], buf[1 - cur], p->TL, p->din, p->d_titems,
-                                           (int)p->titems.size(), p->tdim, p->na_oct, p->nchunk_oct, p->tile_cap,
+                                           (int)p->titems.size(), p->tdim_tr, p->na_oct, p->nchunk_oct, p->tile_cap_tr,
                                            src, dt, p->part, s));
         launch_finalize_tl(d, p->part, p->noct, p->TL, s);
         cur = 1 - cur;

@@ -198,6 +198,17 @@ __device__ inline void tile_load(const TileCtx t, TileSmem<T> &S, const T *__res
     }
 }
 
+// Limited slope times h (a difference) from the one-sided differences
+// dl = e_m - e_{m-1}, dr = e_{m+1} - e_m: MC = minmod(2 dl, 2 dr, (dl + dr)/2),
+// MINMOD = minmod(dl, dr); the face value is e_m + lim/2.
+template <typename T, int LIM> __device__ inline T lim_diff(T dl, T dr)
+{
+    T m;
+    if (LIM == LIM_MC) m = fmin(fmin((T)2 * fabs(dl), (T)2 * fabs(dr)), (T)0.5 * fabs(dl + dr));
+    else m = fmin(fabs(dl), fabs(dr));
+    return dl * dr > (T)0 ? copysign(m, dl) : (T)0;
+}
+
 // Lane constants of one (direction, band) lane.
 template <typename T> struct LaneT {
     int k, al, l;
@@ -291,9 +302,8 @@ __device__ inline T tile_flux(const Dev &d, const Film &fm, const TileCtx t, con
                 // e_f = e_m + (h/2) (e_{m+1} - e_{m-1}) / (2h) on both faces
                 delta = (ec - e1) + (T)0.25 * ((ed - e1) - (ec - e2));
             } else {
-                const T hh = L.hh[a], ih = L.ih[a];
-                delta = (ec + hh * slope_flow<T>(LIM, true, true, e1, ec, ed, ih)) -
-                        (e1 + hh * slope_flow<T>(LIM, true, true, e2, e1, ec, ih));
+                const T d0 = e1 - e2, d1 = ec - e1, d2 = ed - ec;
+                delta = d1 + (T)0.5 * (lim_diff<T, LIM>(d1, d2) - lim_diff<T, LIM>(d0, d1));
             }
         } else {
             const int sg = a == 0 ? t.sg0 : (a == 1 ? t.sg1 : t.sg2);
