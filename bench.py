@@ -14,8 +14,15 @@ directions x bands x steps / wall time of the timed steps, FP32 storage of
 the energy deviation with FP64 moments.  The FP64 path is timed the same
 way, and both are run to convergence to report their relative difference.
 
-Prints one JSON line.  --gpus N > 1 is not supported on this build.
+--workload transient3d times the explicit transient step instead: 64^3
+cube of (2 um)^3, 40 bands, 128 directions, MC limiter, dt = 0.5 ps, laser
+pulse; a step is one explicit step of every (cell, direction, band).
+
+--copy-calibration runs a plain 2 GiB device copy (for scaling HBM counters).
+
+Prints one JSON line.  --gpus N > 1 is not supported (one GPU only).
 """
+import hashlib
 import argparse
 import json
 import os
@@ -27,6 +34,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("bte_tiled.hip", "bte_tile.h", "bte_stencil.h", "bte_internal.h")
 BYTES_PER_UPDATE = {0: 8.0, 1: 16.0}   # read e^n + write e^{n+1}
 
 
@@ -45,8 +53,8 @@ def run_steps(B, prob, e, steps, init):
 
 
 def cpu_baseline(cfg, seconds_hint=30.0):
-    """Oracle (FP64 C, OpenMP) on a bounded sample: one source iteration of the
-    same workload (sweep, moments, synthetic correction), started from the
+    """Oracle (FP64 C, OpenMP) on a bounded sample: three source iterations of
+    the same workload (sweep, moments, synthetic correction), started from the
     heat-diffusion state (computed untimed)."""
     import numpy as np
     import oracle as O
@@ -55,21 +63,148 @@ def cpu_baseline(cfg, seconds_hint=30.0):
     e0 = (case.C[None, None, :] * Td[:, None, None] / (4 * np.pi) * np.ones((1, case.na, 1))).reshape(-1)
     del Td
     t0 = time.perf_counter()
-    e1, st = O.steady(case, scheme=1, tol_T=0.0, tol_q=0.0, max_iter=1, cg_rtol=1e-6, e=e0)
+    iters = 3
+    e1, st = O.steady(case, scheme=1, tol_T=0.0, tol_q=0.0, max_iter=iters, cg_rtol=1e-6, e=e0)
     dt = time.perf_counter() - t0
-    updates = case.nc * case.na * case.nl
+    updates = case.nc * case.na * case.nl * iters
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=updates / dt, unit="cell*dir*band updates/s", cores=threads, kind="oracle",
-                sample="1 source iteration (sweep + FP64 moments + CG correction) of the 256x256 x 128 dir x "
-                       "20 band workload, %.1f s" % dt)
+                sample="%d source iterations (sweep + FP64 moments + CG correction) of the 256x256 x 128 dir x "
+                       "20 band workload, %.1f s" % (iters, dt))
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2306_14181_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch unit of `kernel` from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    kernel sources changed since the counters were taken."""
+    f = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        d = json.load(fh)
+    r = d.get(kernel)
+    if not r or r.get("source_hash") != kernel_source_hash():
+        return None
+    return r["bytes_per_unit"]
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 29   # 2 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": dt * 1e3,
+                      "GBs": 8 * n / dt / 1e9}), flush=True)
+
+
+def bench_transient(args):
+    import numpy as np
+    import torch
+
+    import bte_inputs as I
+    from paper_2306_14181_amd import bte as B
+
+    torch.cuda.set_device(0)
+    n = args.n or 64
+    cfg = I.config2(n=n)
+    P = torch.as_tensor(cfg["P"], device="cuda")
+    res = {}
+    for prec in ([B.F32] if args.no_fp64 else [B.F32, B.F64]):
+        prob = B.Problem(cfg["geometry"], cfg["material"], dict(precision=prec, limiter=B.LIM_MC, dt=cfg["dt"]))
+        prob.set_fields(P, None)
+        e = prob.zeros()
+        prob.transient_step(e, args.warmup, 0.0, cfg["pulse"])
+        prob.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob.transient_step(e, args.steps, args.warmup * cfg["dt"], cfg["pulse"])
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        st = prob.last_stats()
+        upd = prob.n_unknowns
+        T, _, _ = prob.moments(e)
+        res[prec] = dict(t=t, st=st, upd=upd, T=T.cpu().numpy())
+        log("transient prec %d: %d steps %.3f s, transport %.1f ms, walls %.1f ms, T_L %.1f ms"
+            % (prec, args.steps, t, st["ms_sweep"], st["ms_walls"], st["ms_post"]))
+        del prob, e
+        torch.cuda.empty_cache()
+    r = res[B.F32]
+    value = r["upd"] * args.steps / r["t"]
+    kern_ms = r["st"]["ms_sweep"] / args.steps
+    achieved = BYTES_PER_UPDATE[B.F32] * r["upd"] / (kern_ms * 1e-3) / 1e9
+    traffic = counter_traffic("k_transient_tile<float,3,1>")
+    out = {
+        "metric": "cell*dir*band updates/s (FP32 state, FP64 moments) of explicit transient steps",
+        "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * r["t"] / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (e), f64 (moments)", "data": "synthetic (seeded bands, laser pulse)",
+        "config": {"workload": "cube3d_laser: %d^3 cells, 2 um, 40 bands, 128 directions, MC limiter, dt 0.5 ps"
+                   % n, "n": n},
+        "roofline": {"bound": "hbm", "kernel": "k_transient_tile<float,3,MC> (one launch per step)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "avg_launch_ms": kern_ms,
+                     "bytes_per_launch": BYTES_PER_UPDATE[B.F32] * r["upd"]},
+        "phase_ms_per_step": {"transport": kern_ms, "walls": r["st"]["ms_walls"] / args.steps,
+                              "T_L": r["st"]["ms_post"] / args.steps},
+    }
+    if B.F64 in res:
+        r64 = res[B.F64]
+        T32, T64 = r["T"], r64["T"]
+        out["fp64"] = {"value": r64["upd"] * args.steps / r64["t"], "ms_per_step": 1e3 * r64["t"] / args.steps,
+                       "transport_GBs": BYTES_PER_UPDATE[B.F64] * r64["upd"] * args.steps
+                       / (r64["st"]["ms_sweep"] * 1e-3) / 1e9}
+        out["accuracy"] = {"T_rel_err_fp32_vs_fp64": float(np.abs(T32 - T64).max()
+                                                           / max(np.abs(T64 - 300.0).max(), 1e-300)),
+                           "after_steps": args.warmup + args.steps}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_transient()
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_transient():
+    """Oracle transient steps on a bounded sample: 6 steps of the same physics
+    on a 32^3 grid (one full 64^3 step takes minutes on the CPU)."""
+    import numpy as np
+    import bte_inputs as I
+    import oracle as O
+    cfg = I.config2(n=32)
+    case = O.Case(cfg["geometry"], cfg["material"], P=cfg["P"], limiter=cfg["limiter"])
+    e = np.zeros(case.nc * case.na * case.nl)
+    steps = 6
+    t0 = time.perf_counter()
+    O.transient(case, e, steps, cfg["dt"], 0.0, cfg["pulse"])
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=case.nc * case.na * case.nl * steps / dt, unit="cell*dir*band updates/s", cores=threads,
+                kind="oracle", sample="%d explicit steps of the laser workload on a 32^3 grid, %.1f s" % (steps, dt))
 
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=("steady2d", "transient3d"), default="steady2d")
+    ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--n", type=int, default=256, help="cells per side (256 = the benchmark workload)")
+    ap.add_argument("--n", type=int, default=None,
+                    help="cells per side (default: 256 for steady2d, 64 for transient3d)")
     ap.add_argument("--cg-rtol", type=float, default=1e-6)
     ap.add_argument("--cg-max-iter", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -80,6 +215,12 @@ def main():
         print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU sharding is not implemented",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.workload == "transient3d":
+        bench_transient(args)
+        return
 
     import numpy as np
     import torch
@@ -88,6 +229,7 @@ def main():
     from paper_2306_14181_amd import bte as B
 
     torch.cuda.set_device(0)
+    args.n = args.n or 256
     cfg = I.config1(n=args.n)
     geo, mat = cfg["geometry"], cfg["material"]
     P = torch.as_tensor(cfg["P"], device="cuda")
@@ -160,13 +302,14 @@ def main():
                    "n": args.n, "cg_rtol": args.cg_rtol, "cg_max_iter": args.cg_max_iter},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep<float> (all tile-wavefront launches of one sweep)",
+            "kernel": "k_sweep_tile<float,2,NONE> (the 63 tile-diagonal launches of one sweep)",
             "achieved": r32["achieved"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": r32["achieved"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": counter_traffic("k_sweep_tile<float,2,0>"),
             "avg_launch_ms": r32["sweep_launch_ms"],
+            "bytes_per_sweep": BYTES_PER_UPDATE[B.F32] * r32["updates"],
         },
         "phase_ms_per_step": {k: r32["st"][k] / args.steps for k in ("ms_sweep", "ms_walls", "ms_post", "ms_cg")},
     }

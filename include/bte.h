@@ -191,6 +191,17 @@ bte_status bte_keff(bte_problem *p, const void *e_dev, double *keff_dev, void *s
 bte_status bte_adjoint(bte_problem *p, const void *e_dev, int objective, double *dJ_dgamma_dev,
                        bte_solve_stats *stats, void *stream);
 
+/* Device timers of bte_transient_step (off by default).  With on != 0 every
+ * step records HIP events around its wall, transport and T_L kernels, and
+ * the call waits for its own work to finish before it returns, so that the
+ * times can be read; the call is then synchronous. */
+bte_status bte_set_timing(bte_problem *p, int on);
+
+/* Statistics of the last bte_steady_solve, or of the last timed
+ * bte_transient_step (iters = steps, ms_sweep = transport kernels, ms_walls =
+ * wall kernels, ms_post = T_L updates). */
+bte_status bte_last_stats(const bte_problem *p, bte_solve_stats *out);
+
 /* Host copy of the direction table: s[n_dir][3], w[n_dir]. */
 bte_status bte_get_directions(const bte_problem *p, double *s_host, double *w_host);
 

@@ -26,8 +26,8 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "E
 
 EXPORTS = ["bte_setup", "bte_set_control", "bte_workspace_bytes", "bte_num_unknowns", "bte_num_cells", "bte_num_directions",
            "bte_bind", "bte_set_fields", "bte_moments", "bte_residual", "bte_transient_step",
-           "bte_steady_solve", "bte_keff", "bte_adjoint", "bte_get_directions", "bte_last_error",
-           "bte_destroy"]
+           "bte_steady_solve", "bte_keff", "bte_adjoint", "bte_set_timing", "bte_last_stats",
+           "bte_get_directions", "bte_last_error", "bte_destroy"]
 
 
 class BteError(RuntimeError):
@@ -92,6 +92,8 @@ def load():
         "bte_steady_solve": ([vp, vp, C.c_int, C.POINTER(SolveStats), vp], st),
         "bte_keff": ([vp, vp, vp, vp], st),
         "bte_adjoint": ([vp, vp, C.c_int, vp, C.POINTER(SolveStats), vp], st),
+        "bte_set_timing": ([vp, C.c_int], st),
+        "bte_last_stats": ([vp, C.POINTER(SolveStats)], st),
         "bte_get_directions": ([vp, dp, dp], st),
         "bte_last_error": ([vp], C.c_char_p),
         "bte_destroy": ([vp], None),
@@ -269,6 +271,15 @@ class Problem:
             pl = (C.c_double * 2)(float(pulse[0]), float(pulse[1]))
         self._check(load().bte_transient_step(self._h, self._e(e), int(n_steps), float(t0), pl, _stream()))
         return e
+
+    def set_timing(self, on=True):
+        """Device timers for transient_step (makes it synchronous)."""
+        self._check(load().bte_set_timing(self._h, int(bool(on))))
+
+    def last_stats(self):
+        st = SolveStats()
+        self._check(load().bte_last_stats(self._h, C.byref(st)))
+        return st.as_dict()
 
     def steady_solve(self, e, init=True, allow_not_converged=False):
         st = SolveStats()

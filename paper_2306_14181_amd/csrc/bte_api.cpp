@@ -142,7 +142,15 @@ struct bte_problem {
     int *d_wrec = nullptr;
     double *d_wden = nullptr;
     int npart_max = 0;
+    // optional device timers of the transient step (bte_set_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> tev;
+    bte_solve_stats last{};
 
+    ~bte_problem()
+    {
+        for (hipEvent_t e : tev) (void)hipEventDestroy(e);
+    }
     size_t esize() const { return ctl.precision == BTE_F64 ? 8 : 4; }
     size_t nelem() const { return (size_t)nc * nk; }
 };
@@ -869,6 +877,7 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
         st.cg_iters = (int)sc[9];
     }
     st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    p->last = st;
     if (stats) *stats = st;
     if (ret == BTE_ERR_NOT_CONVERGED) p->err = "not converged within max_iter";
     if (ret == BTE_ERR_NONFINITE) p->err = "non-finite convergence measure";
@@ -882,6 +891,16 @@ bte_status transient_impl(bte_problem *p, T *e, int n_steps, double t0, const do
     const double dt = p->ctl.dt;
     T *buf[2] = {e, (T *)p->e2};
     int cur = 0;
+    const auto h0 = std::chrono::steady_clock::now();
+    // with timing on: events before the walls, before and after the transport
+    // kernel and after the T_L update of every step
+    const bool timing = p->timing && n_steps > 0;
+    if (timing)
+        while (p->tev.size() < 4 * (size_t)n_steps) {
+            hipEvent_t x;
+            HIPCHK(p, hipEventCreate(&x));
+            p->tev.push_back(x);
+        }
     launch_moments<T>(d, e, nullptr, p->part, s);
     launch_finalize(d, p->part, 1, p->Tref, nullptr, nullptr, nullptr, p->TL, nullptr, nullptr, s);
     for (int n = 0; n < n_steps; ++n) {
@@ -891,15 +910,34 @@ bte_status transient_impl(bte_problem *p, T *e, int n_steps, double t0, const do
             const double x = t - pulse[0];
             src = std::exp(-4.0 * std::log(2.0) * x * x / (pulse[1] * pulse[1]));
         }
+        if (timing) HIPCHK(p, hipEventRecord(p->tev[4 * n], s));
         launch_walls<T>(d, buf[cur], nullptr, p->d_wrec, p->d_wden, p->din, p->nw, s);
+        if (timing) HIPCHK(p, hipEventRecord(p->tev[4 * n + 1], s));
         HIPCHK(p, launch_transient_tile<T>(d, buf[cur], buf[1 - cur], p->TL, p->din, p->d_titems,
                                            (int)p->titems.size(), p->tdim_tr, p->na_oct, p->nchunk_oct, p->tile_cap_tr,
                                            src, dt, p->part, s));
+        if (timing) HIPCHK(p, hipEventRecord(p->tev[4 * n + 2], s));
         launch_finalize_tl(d, p->part, p->noct, p->TL, s);
+        if (timing) HIPCHK(p, hipEventRecord(p->tev[4 * n + 3], s));
         cur = 1 - cur;
     }
     if (cur != 0) HIPCHK(p, hipMemcpyAsync(e, buf[cur], p->esize() * p->nelem(), hipMemcpyDeviceToDevice, s));
     HIPCHK(p, hipGetLastError());
+    if (timing) {
+        bte_solve_stats st{};
+        HIPCHK(p, hipEventSynchronize(p->tev[4 * (size_t)n_steps - 1]));
+        for (int n = 0; n < n_steps; ++n) {
+            float ms[3];
+            for (int i = 0; i < 3; ++i) HIPCHK(p, hipEventElapsedTime(&ms[i], p->tev[4 * n + i], p->tev[4 * n + i + 1]));
+            st.ms_walls += ms[0];
+            st.ms_sweep += ms[1];
+            st.ms_post += ms[2];
+        }
+        st.iters = n_steps;
+        st.sweep_launches = n_steps;
+        st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
+        p->last = st;
+    }
     return BTE_OK;
 }
 
@@ -1008,6 +1046,20 @@ bte_status bte_get_directions(const bte_problem *p, double *s_host, double *w_ho
 }
 
 const char *bte_last_error(const bte_problem *p) { return p ? p->err.c_str() : "null handle"; }
+
+bte_status bte_set_timing(bte_problem *p, int on)
+{
+    if (!p) return BTE_ERR_ARG;
+    p->timing = on != 0;
+    return BTE_OK;
+}
+
+bte_status bte_last_stats(const bte_problem *p, bte_solve_stats *out)
+{
+    if (!p || !out) return BTE_ERR_ARG;
+    *out = p->last;
+    return BTE_OK;
+}
 
 void bte_destroy(bte_problem *p) { delete p; }
 
