@@ -106,6 +106,8 @@ typedef struct {
     double cg_rtol;          /* relative residual of the CG solves          */
     int cg_max_iter;         /* CG iteration cap per solve (<= 0: 2000)     */
     double dt;               /* transient time step, s (0: steady only)     */
+    int adjoint;             /* != 0: reserve workspace for bte_adjoint (two
+                                more buffers the size of e); fixed at setup */
 } bte_control;
 
 typedef struct {
@@ -183,11 +185,20 @@ bte_status bte_steady_solve(bte_problem *p, void *e_dev, int init, bte_solve_sta
  * keff_dev: device double[n_geo].  Requires periodic_dT[0] != 0. */
 bte_status bte_keff(bte_problem *p, const void *e_dev, double *keff_dev, void *stream);
 
-/* Adjoint of the steady problem for J = k_eff (objective BTE_OBJ_KEFF_X):
- * solves (dR/de)^T psi = -dJ/de with reversed-direction sweeps and returns
- * dJ/dgamma per cell (device double[n_cells]).  e must be a converged
- * steady solution for the current fields.  Limiter must be NONE.
- * Synchronous. */
+/* Adjoint of the steady problem for J = k_eff (objective BTE_OBJ_KEFF_X,
+ * the functional of bte_keff, summed over the geometries of a batch):
+ * solves (dR/de)^T psi = -dJ/de, where R is the steady residual of
+ * bte_residual (Sec. 3.3 / 3.5 with the closures of Sec. 2.2), by the
+ * transpose of the forward iteration: sweeps in the reversed direction of
+ * every lane with the transposed boundary and scattering closures and, for
+ * the synthetic scheme, the same CG correction.  Writes dJ/dgamma per cell
+ * (device double[n_cells], pores 0) for the extra scattering rate of
+ * bte_set_fields.  e must be a converged steady solution for the current
+ * fields.  Requires control.adjoint != 0 at setup, limiter NONE and
+ * periodic_dT[0] != 0.  Stops when |J^T psi + g| <= residual_temp |g| for
+ * every geometry (2-norms over all unknowns) or after max_iter sweeps
+ * (BTE_ERR_NOT_CONVERGED, gradient of the last iterate written).
+ * stats: iters = sweeps, eps_T = final relative residual.  Synchronous. */
 bte_status bte_adjoint(bte_problem *p, const void *e_dev, int objective, double *dJ_dgamma_dev,
                        bte_solve_stats *stats, void *stream);
 

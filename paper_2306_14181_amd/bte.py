@@ -51,7 +51,7 @@ class Material(C.Structure):
 class Control(C.Structure):
     _fields_ = [("precision", C.c_int), ("scheme", C.c_int), ("limiter", C.c_int),
                 ("residual_temp", C.c_double), ("residual_flux", C.c_double), ("max_iter", C.c_int),
-                ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int), ("dt", C.c_double)]
+                ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int), ("dt", C.c_double), ("adjoint", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -144,6 +144,7 @@ def _control_struct(control):
     c.cg_rtol = float(control.get("cg_rtol", 1e-10))
     c.cg_max_iter = int(control.get("cg_max_iter", 2000))
     c.dt = float(control.get("dt", 0.0))
+    c.adjoint = int(bool(control.get("adjoint", False)))
     return c
 
 
@@ -153,7 +154,7 @@ class Problem:
     geometries: dict or list of dicts (dim, n, len, solid, bc, bcT, pdT, pore_bc)
     material:   dict(C, v, tau, n_theta, n_phi, Tref)
     control:    dict(precision, scheme, limiter, residual_temp, residual_flux,
-                     max_iter, cg_rtol, cg_max_iter, dt)
+                     max_iter, cg_rtol, cg_max_iter, dt, adjoint)
     """
 
     def __init__(self, geometries, material, control, device="cuda"):
@@ -292,8 +293,10 @@ class Problem:
         self._check(load().bte_keff(self._h, self._e(e), _ptr(k), _stream()))
         return k
 
-    def adjoint(self, e, objective=OBJ_KEFF_X):
+    def adjoint(self, e, objective=OBJ_KEFF_X, allow_not_converged=False):
+        """dJ/dgamma per cell (float64 tensor) and the adjoint solve statistics."""
         g = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)
         st = SolveStats()
-        self._check(load().bte_adjoint(self._h, self._e(e), int(objective), _ptr(g), C.byref(st), _stream()))
+        ok = (BTE_OK, BTE_ERR_NOT_CONVERGED) if allow_not_converged else (BTE_OK,)
+        self._check(load().bte_adjoint(self._h, self._e(e), int(objective), _ptr(g), C.byref(st), _stream()), ok)
         return g, st.as_dict()

@@ -31,6 +31,20 @@ template <typename T>
 hipError_t launch_transient_tile(const Dev &, const T *, T *, const double *, const double *, const TileItem *, int,
                                  int3, int, int, int, double, double, double *, hipStream_t);
 hipError_t tile_kernels_init(size_t);
+template <typename T>
+hipError_t launch_sweep_adj(const Dev &, const T *, T *, const double *, const double *, const SweepItem *, int, int,
+                            int3, int, int, int, double *, hipStream_t);
+template <typename T>
+void launch_walls_adj(const Dev &, const T *, const int *, const double *, double *, int, hipStream_t);
+template <typename T>
+hipError_t launch_adj_res(const Dev &, const T *, const double *, const double *, const TileItem *, int, int3, int, int,
+                          int, double *, hipStream_t);
+void launch_adj_post(const Dev &, const double *, int, double *, double *, hipStream_t);
+void launch_adj_phi(const Dev &, const double *, int, double *, hipStream_t);
+template <typename T>
+void launch_adj_grad(const Dev &, const T *, const T *, const double *, const double *, const double *, double *,
+                     hipStream_t);
+hipError_t adj_kernels_init(size_t);
 size_t tile_smem_size(int, int, int);
 template <typename T> void launch_set_equilibrium(const Dev &, T *, const double *, hipStream_t);
 template <typename T> void launch_apply_shift(const Dev &, const T *, T *, const double *, const double *, hipStream_t);
@@ -137,6 +151,9 @@ struct bte_problem {
     double *cg_part = nullptr, *cg_scal = nullptr;
     double *din = nullptr, *part = nullptr;
     void *e2 = nullptr;
+    void *psi = nullptr, *psi2 = nullptr;                       // adjoint iterates (ctl.adjoint)
+    double *adjX = nullptr, *adjT = nullptr, *adjTL = nullptr;   // adjoint closure term, forward T and T_L
+    double *adju = nullptr, *adjr2 = nullptr;
     SweepItem *d_items = nullptr;
     TileItem *d_titems = nullptr;
     int *d_wrec = nullptr;
@@ -473,6 +490,11 @@ void plan_workspace(bte_problem *p)
     p->npart_max = std::max(nchunk_stream, p->noct * p->nchunk_oct);
     add("part", 8 * (size_t)kMomN * nc * p->npart_max);
     add("e2", p->esize() * p->nelem());
+    for (const char *n : {"adjX", "adjT", "adjTL", "adju", "adjr2"}) add(n, 8 * nc);
+    if (p->ctl.adjoint) {
+        add("psi", p->esize() * p->nelem());
+        add("psi2", p->esize() * p->nelem());
+    }
     p->ws_bytes = off;
 }
 
@@ -566,6 +588,7 @@ bte_status bte_set_control(bte_problem *p, const bte_control *ctl)
     if (ctl->precision != p->ctl.precision) FAIL(p, BTE_ERR_ARG, "precision cannot change after setup");
     if (ctl->scheme != BTE_SEQUENTIAL && ctl->scheme != BTE_SYNTHETIC) FAIL(p, BTE_ERR_ARG, "bad scheme");
     if (ctl->limiter < 0 || ctl->limiter > 2) FAIL(p, BTE_ERR_ARG, "bad limiter");
+    if ((ctl->adjoint != 0) != (p->ctl.adjoint != 0)) FAIL(p, BTE_ERR_ARG, "adjoint cannot change after setup");
     p->ctl = *ctl;
     if (p->ctl.max_iter <= 0) p->ctl.max_iter = 10000;
     if (p->ctl.cg_max_iter <= 0) p->ctl.cg_max_iter = 2000;
@@ -606,6 +629,7 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     HIPCHK(p, up("titems", p->titems.data(), sizeof(TileItem) * p->titems.size()));
     if (tile_smem_size(p->tile_cap, (int)p->esize(), 1) > 160 * 1024) FAIL(p, BTE_ERR_UNSUPPORTED, "tile LDS");
     HIPCHK(p, tile_kernels_init(160 * 1024));
+    HIPCHK(p, adj_kernels_init(160 * 1024));
     Dev &d = p->dev;
     d.dim = p->dim;
     d.nc = p->nc;
@@ -661,6 +685,13 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     p->din = wsptr<double>(p, "din");
     p->part = wsptr<double>(p, "part");
     p->e2 = wsptr<void>(p, "e2");
+    p->psi = wsptr<void>(p, "psi");
+    p->psi2 = wsptr<void>(p, "psi2");
+    p->adjX = wsptr<double>(p, "adjX");
+    p->adjT = wsptr<double>(p, "adjT");
+    p->adjTL = wsptr<double>(p, "adjTL");
+    p->adju = wsptr<double>(p, "adju");
+    p->adjr2 = wsptr<double>(p, "adjr2");
     p->d_items = wsptr<SweepItem>(p, "items");
     p->d_titems = wsptr<TileItem>(p, "titems");
     p->d_wrec = wsptr<int>(p, "wrec");
@@ -941,6 +972,127 @@ bte_status transient_impl(bte_problem *p, T *e, int n_steps, double t0, const do
     return BTE_OK;
 }
 
+// Adjoint of the steady problem for J = k_eff (x): transposed synthetic
+// iteration (see bte_adjoint.hip), then the gradient pass.  Stops when the
+// residual |J^T psi + g| / |g| of every geometry is <= ctl.residual_temp.
+template <typename T>
+bte_status adjoint_impl(bte_problem *p, const T *e, double *grad, bte_solve_stats *stats, hipStream_t s)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    const Dev &d = p->dev;
+    const int nc = p->nc;
+    const int synthetic = p->ctl.scheme == BTE_SYNTHETIC;
+    bte_solve_stats st{};
+    T *buf[2] = {(T *)p->psi, (T *)p->psi2};
+    int cur = 0;
+    // forward T and T_L deviations of e
+    launch_moments<T>(d, e, nullptr, p->part, s);
+    launch_finalize(d, p->part, 1, p->Tref, nullptr, nullptr, nullptr, p->adjTL, p->adjT, nullptr, s);
+    HIPCHK(p, hipMemsetAsync(buf[0], 0, p->esize() * p->nelem(), s));
+    HIPCHK(p, hipMemsetAsync(p->adjX, 0, 8 * (size_t)nc, s));
+    HIPCHK(p, hipMemsetAsync(p->cg_scal, 0, 8 * 16, s));
+    // |g|^2 per geometry: g = (L_x / (dT_x N_cells)) w v s_x on solid cells
+    double sws = 0, svv = 0;
+    for (int al = 0; al < p->na; ++al) sws += p->w[al] * p->w[al] * p->s[3 * al] * p->s[3 * al];
+    for (int l = 0; l < p->nl; ++l) svv += p->v[l] * p->v[l];
+    std::vector<double> g2(p->nfilm), mres(p->nfilm);
+    for (int f = 0; f < p->nfilm; ++f) {
+        const Film &fm = p->films[f];
+        const double gf = fm.len[0] / (fm.pdT[0] * fm.ncell);
+        g2[f] = gf * gf * fm.nsolid * sws * svv;
+    }
+    const int np = p->noct * p->nchunk_oct;
+    bte_status ret = BTE_ERR_NOT_CONVERGED;
+    hipEvent_t ev[5];
+    for (auto &x : ev) HIPCHK(p, hipEventCreate(&x));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]);
+        }
+    } evg{ev};
+    for (int iter = 0;; ++iter) {
+        const T *pin = buf[cur];
+        T *pout = buf[1 - cur];
+        HIPCHK(p, hipEventRecord(ev[0], s));
+        launch_walls_adj<T>(d, pin, p->d_wrec, p->d_wden, p->din, p->nw, s);
+        HIPCHK(p, hipEventRecord(ev[1], s));
+        HIPCHK(p, launch_adj_res<T>(d, pin, p->adjX, p->din, p->d_titems, (int)p->titems.size(), p->tdim_tr,
+                                    p->na_oct, p->nchunk_oct, p->tile_cap_tr, p->part, s));
+        launch_adj_post(d, p->part, p->noct, p->adju, p->adjr2, s);
+        launch_film_mean(d, p->adjr2, p->fmean, s);
+        HIPCHK(p, hipEventRecord(ev[2], s));
+        HIPCHK(p, hipMemcpyAsync(mres.data(), p->fmean, 8 * mres.size(), hipMemcpyDeviceToHost, s));
+        HIPCHK(p, hipStreamSynchronize(s));
+        {
+            float ms[2];
+            for (int i = 0; i < 2; ++i) HIPCHK(p, hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
+            st.ms_walls += ms[0];
+            st.ms_post += ms[1];
+        }
+        double eps = 0;
+        bool finite = true;
+        for (int f = 0; f < p->nfilm; ++f) {
+            const double r = std::sqrt(mres[f] * p->films[f].nsolid / g2[f]);
+            if (!std::isfinite(r)) finite = false;
+            eps = std::max(eps, r);
+        }
+        st.eps_T = eps;
+        if (!finite) {
+            ret = BTE_ERR_NONFINITE;
+            p->err = "non-finite adjoint residual";
+            break;
+        }
+        if (eps <= p->ctl.residual_temp) {
+            st.converged = 1;
+            ret = BTE_OK;
+            break;
+        }
+        if (iter >= p->ctl.max_iter) {
+            p->err = "adjoint: max_iter reached";
+            break;
+        }
+        const double *X = p->adjX;
+        HIPCHK(p, hipEventRecord(ev[2], s));
+        if (synthetic) {
+            // v = L^-1 P^T y; the sweep's isotropic term becomes X + v
+            if (!run_cg(p, 1, p->adju, p->delta, p->ctl.cg_rtol, p->ctl.cg_max_iter, s))
+                FAIL(p, BTE_ERR_HIP, "CG failed");
+            launch_tl_update(nc, p->adjX, p->delta, p->TL, nullptr, s);
+            X = p->TL;
+        }
+        HIPCHK(p, hipEventRecord(ev[3], s));
+        for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
+            const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
+            HIPCHK(p, launch_sweep_adj<T>(d, pin, pout, X, p->din, p->d_items, i0, cnt, p->tdim, p->na_oct,
+                                          p->nchunk_oct, p->tile_cap, p->part, s));
+            st.sweep_launches += cnt > 0;
+        }
+        launch_adj_phi(d, p->part, np, p->adjX, s);
+        HIPCHK(p, hipEventRecord(ev[4], s));
+        HIPCHK(p, hipEventSynchronize(ev[4]));
+        {
+            float ms[2];
+            for (int i = 0; i < 2; ++i) HIPCHK(p, hipEventElapsedTime(&ms[i], ev[2 + i], ev[3 + i]));
+            st.ms_cg += ms[0];
+            st.ms_sweep += ms[1];
+        }
+        cur = 1 - cur;
+        st.iters = iter + 1;
+    }
+    launch_adj_grad<T>(d, e, buf[cur], p->adjT, p->adjTL, p->adjX, grad, s);
+    HIPCHK(p, hipGetLastError());
+    double cgit = 0;
+    HIPCHK(p, hipMemcpyAsync(&cgit, p->cg_scal + 9, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(p, hipStreamSynchronize(s));
+    st.cg_iters = (int)cgit;
+    st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    p->last = st;
+    if (stats) *stats = st;
+    return ret;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1031,10 +1183,21 @@ bte_status bte_keff(bte_problem *p, const void *e_dev, double *keff_dev, void *s
     return BTE_OK;
 }
 
-bte_status bte_adjoint(bte_problem *p, const void *, int, double *, bte_solve_stats *, void *)
+bte_status bte_adjoint(bte_problem *p, const void *e_dev, int objective, double *dJ_dgamma_dev,
+                       bte_solve_stats *stats, void *stream)
 {
     if (!p) return BTE_ERR_ARG;
-    FAIL(p, BTE_ERR_UNSUPPORTED, "adjoint not built yet");
+    if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
+    if (!e_dev || !dJ_dgamma_dev) FAIL(p, BTE_ERR_ARG, "null e or gradient");
+    if (objective != BTE_OBJ_KEFF_X) FAIL(p, BTE_ERR_ARG, "unknown objective %d", objective);
+    if (!p->ctl.adjoint) FAIL(p, BTE_ERR_STATE, "control.adjoint was 0 at setup: no adjoint workspace");
+    if (p->ctl.limiter != BTE_LIM_NONE) FAIL(p, BTE_ERR_UNSUPPORTED, "the adjoint needs limiter NONE");
+    for (const Film &fm : p->films)
+        if (fm.pdT[0] == 0.0) FAIL(p, BTE_ERR_ARG, "k_eff needs periodic_dT[0] != 0");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->ctl.precision == BTE_F64)
+        return adjoint_impl<double>(p, (const double *)e_dev, dJ_dgamma_dev, stats, s);
+    return adjoint_impl<float>(p, (const float *)e_dev, dJ_dgamma_dev, stats, s);
 }
 
 bte_status bte_get_directions(const bte_problem *p, double *s_host, double *w_host)
