@@ -197,6 +197,9 @@ class Problem:
         self.n_bands = m.n_bands
         self.n_unknowns = lib.bte_num_unknowns(h)
         self.n_geo = len(structs)
+        ncell = [int(st.n[0]) * int(st.n[1]) * int(st.n[2]) for st in structs]
+        self.cell_geometry = torch.repeat_interleave(torch.arange(self.n_geo, device=self.device),
+                                                     torch.tensor(ncell, device=self.device))
         nbytes = lib.bte_workspace_bytes(h)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
@@ -300,3 +303,33 @@ class Problem:
         ok = (BTE_OK, BTE_ERR_NOT_CONVERGED) if allow_not_converged else (BTE_OK,)
         self._check(load().bte_adjoint(self._h, self._e(e), int(objective), _ptr(g), C.byref(st), _stream()), ok)
         return g, st.as_dict()
+
+
+class KeffSteady(torch.autograd.Function):
+    """k_eff of every geometry of a problem as a function of the per-cell extra
+    scattering rate gamma (float64 tensor of n_cells on the problem's device).
+
+    forward: bte_set_fields(P, gamma), steady solve from the heat-diffusion
+    guess, bte_keff.  backward: one bte_adjoint solve; geometries are
+    independent, so the gradient of sum_f w_f k_f is w_{f(c)} dk/dgamma_c.
+    The problem must be built with limiter NONE and control adjoint=True.
+
+        k = KeffSteady.apply(gamma, prob, P)
+    """
+
+    @staticmethod
+    def forward(ctx, gamma, prob, P=None):
+        prob.set_fields(P, gamma.detach().to(torch.float64).contiguous())
+        e = prob.zeros()
+        prob.steady_solve(e, init=True)
+        k = prob.keff(e)
+        ctx.prob, ctx.e = prob, e
+        return k
+
+    @staticmethod
+    def backward(ctx, grad_k):
+        prob = ctx.prob
+        g, _ = prob.adjoint(ctx.e)
+        w = grad_k.to(torch.float64)[prob.cell_geometry]
+        return g * w, None, None
+
