@@ -47,6 +47,25 @@ def test_quadrature_symmetry(dim, nt, nph):
             assert abs((w * s[:, a] * s[:, b]).sum()) < 1e-13
 
 
+def test_quadrature_nodes_match_closed_forms():
+    """Gauss-Legendre nodes/weights from their closed forms (golden fixture)
+    mapped to theta in (0, pi/2) as Sec. 3.2 prescribes: the 1D direction set
+    is cos(theta) per hemisphere with w proportional to w_theta sin(theta)."""
+    import os
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "gauss_legendre.txt"))
+    for n in (2, 3, 4):
+        x, wg = rows[rows[:, 0] == n, 1], rows[rows[:, 0] == n, 2]
+        th = (x + 1) * np.pi / 4
+        wt = 2 * np.pi * wg * np.pi / 4 * np.sin(th)
+        wt *= 2 * np.pi / wt.sum()          # each hemisphere carries 2 pi
+        s, w = O.quadrature(1, n, 1)
+        hemi = s[:, 0] > 0
+        order = np.argsort(-np.cos(th))
+        np.testing.assert_allclose(np.sort(s[hemi, 0])[::-1], np.cos(th)[order], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(w[hemi][np.argsort(-s[hemi, 0])], wt[order], rtol=1e-14)
+        np.testing.assert_allclose(np.sort(-s[~hemi, 0])[::-1], np.cos(th)[order], rtol=0, atol=1e-15)
+
+
 def test_quadrature_moments_close_to_sphere():
     # 1D: 8 Gauss-Legendre theta nodes per hemisphere integrate mu^2 almost exactly
     s, w = O.quadrature(1, 8, 1)
