@@ -202,6 +202,28 @@ bte_status bte_keff(bte_problem *p, const void *e_dev, double *keff_dev, void *s
 bte_status bte_adjoint(bte_problem *p, const void *e_dev, int objective, double *dJ_dgamma_dev,
                        bte_solve_stats *stats, void *stream);
 
+/* Transient adjoint (reverse mode of n_steps explicit steps, Sec. 4.1,
+ * Algorithm 2) for J = sum_c a_c T_c(e^N) / sum_c a_c, the weighted mean
+ * local temperature after the last step.  e0_dev: start state (not
+ * modified); weights_dev: device double[n_cells] a_c >= 0 with a positive
+ * sum; pulse as in bte_transient_step.  The forward pass keeps e every
+ * `every` steps in ckpt_dev (device memory of at least
+ * bte_transient_adjoint_bytes(p, n_steps, every) bytes, 256-byte aligned,
+ * owned by the caller and overwritten); the backward pass recomputes one
+ * segment of `every` states at a time and runs the transposed steps with the
+ * gradient accumulated on the fly.  Writes J (host, may be NULL) and
+ * dJ/dgamma per cell (device double[n_cells]).  Requires control.adjoint != 0
+ * at setup, limiter NONE and a stable dt (BTE_ERR_CFL).  Synchronous. */
+bte_status bte_transient_adjoint(bte_problem *p, const void *e0_dev, int n_steps, double t0,
+                                 const double *pulse, const double *weights_dev, int every,
+                                 void *ckpt_dev, size_t ckpt_bytes, double *J_host,
+                                 double *dJ_dgamma_dev, bte_solve_stats *stats, void *stream);
+
+/* Bytes of the checkpoint buffer of bte_transient_adjoint:
+ * (ceil(n_steps / every) + every) states of e plus one double per cell and
+ * checkpoint (0 on invalid arguments). */
+size_t bte_transient_adjoint_bytes(const bte_problem *p, int n_steps, int every);
+
 /* Device timers of bte_transient_step (off by default).  With on != 0 every
  * step records HIP events around its wall, transport and T_L kernels, and
  * the call waits for its own work to finish before it returns, so that the

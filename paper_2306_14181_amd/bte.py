@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "E
 
 EXPORTS = ["bte_setup", "bte_set_control", "bte_workspace_bytes", "bte_num_unknowns", "bte_num_cells", "bte_num_directions",
            "bte_bind", "bte_set_fields", "bte_moments", "bte_residual", "bte_transient_step",
-           "bte_steady_solve", "bte_keff", "bte_adjoint", "bte_set_timing", "bte_last_stats",
+           "bte_steady_solve", "bte_keff", "bte_adjoint", "bte_transient_adjoint", "bte_transient_adjoint_bytes",
+           "bte_set_timing", "bte_last_stats",
            "bte_get_directions", "bte_last_error", "bte_destroy"]
 
 
@@ -92,6 +93,9 @@ def load():
         "bte_steady_solve": ([vp, vp, C.c_int, C.POINTER(SolveStats), vp], st),
         "bte_keff": ([vp, vp, vp, vp], st),
         "bte_adjoint": ([vp, vp, C.c_int, vp, C.POINTER(SolveStats), vp], st),
+        "bte_transient_adjoint": ([vp, vp, C.c_int, C.c_double, dp, vp, C.c_int, vp, C.c_size_t, dp, vp,
+                                   C.POINTER(SolveStats), vp], st),
+        "bte_transient_adjoint_bytes": ([vp, C.c_int, C.c_int], C.c_size_t),
         "bte_set_timing": ([vp, C.c_int], st),
         "bte_last_stats": ([vp, C.POINTER(SolveStats)], st),
         "bte_get_directions": ([vp, dp, dp], st),
@@ -276,6 +280,26 @@ class Problem:
         self._check(load().bte_transient_step(self._h, self._e(e), int(n_steps), float(t0), pl, _stream()))
         return e
 
+    def transient_adjoint(self, e0, n_steps, weights, t0=0.0, pulse=None, every=50):
+        """J = sum a T(e^N) / sum a after n_steps explicit steps from e0, and
+        dJ/dgamma per cell (checkpoints every `every` steps)."""
+        lib = load()
+        nbytes = lib.bte_transient_adjoint_bytes(self._h, int(n_steps), int(every))
+        if nbytes == 0:
+            raise ValueError("invalid n_steps / every")
+        ck = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = (ck.data_ptr() + 255) & ~255
+        a = self._cells(weights)
+        g = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)
+        J = C.c_double(0.0)
+        pl = None if pulse is None else (C.c_double * 2)(float(pulse[0]), float(pulse[1]))
+        st = SolveStats()
+        self._check(lib.bte_transient_adjoint(self._h, self._e(e0), int(n_steps), float(t0), pl, a, int(every),
+                                              C.c_void_p(base), C.c_size_t(nbytes), C.byref(J), _ptr(g),
+                                              C.byref(st), _stream()))
+        del ck
+        return J.value, g, st.as_dict()
+
     def set_timing(self, on=True):
         """Device timers for transient_step (makes it synchronous)."""
         self._check(load().bte_set_timing(self._h, int(bool(on))))
@@ -333,3 +357,26 @@ class KeffSteady(torch.autograd.Function):
         w = grad_k.to(torch.float64)[prob.cell_geometry]
         return g * w, None, None
 
+
+
+class TaveTransient(torch.autograd.Function):
+    """Weighted mean local temperature J = sum a T / sum a after n_steps
+    explicit steps from rest (e = 0), as a function of the per-cell extra
+    scattering rate gamma.  The forward call runs bte_transient_adjoint, which
+    returns J and dJ/dgamma together (checkpoints every `every` steps);
+    backward scales the stored gradient.  Limiter NONE, control adjoint=True.
+
+        J = TaveTransient.apply(gamma, prob, P, n_steps, weights, t0, pulse, every)
+    """
+
+    @staticmethod
+    def forward(ctx, gamma, prob, P, n_steps, weights, t0=0.0, pulse=None, every=50):
+        prob.set_fields(P, gamma.detach().to(torch.float64).contiguous())
+        J, g, _ = prob.transient_adjoint(prob.zeros(), n_steps, weights, t0, pulse, every)
+        ctx.save_for_backward(g)
+        return torch.tensor(J, dtype=torch.float64, device=gamma.device)
+
+    @staticmethod
+    def backward(ctx, grad_J):
+        (g,) = ctx.saved_tensors
+        return g * grad_J.to(torch.float64), None, None, None, None, None, None, None

@@ -188,6 +188,164 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(Dev d, const T *__restrict_
     }
 }
 
+
+// Transposed explicit step of the transient adjoint (reverse mode of
+// e^{k+1} = e^k + dt R(e^k)):  lam^k = lam^{k+1} + dt J^T lam^{k+1}, with the
+// forward state e^k read alongside for the gradient.  Per (octant, cell) the
+// block writes five partial sums, part[(oct * 5 + q) * nc + cell]:
+//   q = 0: sum C/(4 pi) (1/tau) lam^k        (closure term of the next step)
+//   q = 1: sum lam^{k+1} e^k,  q = 2: sum lam^{k+1} C/(4 pi)
+//   q = 3: sum w e^k,          q = 4: sum w (1/tau) e^k   (T and T_L of e^k)
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_adj_step(Dev d, const T *__restrict__ lam, T *__restrict__ lout,
+                                                  const T *__restrict__ ek, const double *__restrict__ X,
+                                                  const double *__restrict__ dinA,
+                                                  const TileItem *__restrict__ items, int nitems, int3 tdim,
+                                                  int na_oct, int nchunk_oct, int cap, double dt,
+                                                  double *__restrict__ part)
+{
+    extern __shared__ __align__(16) char smem[];
+    TileSmem<T> S = tile_smem<T>(smem, cap, false);
+    const int nb = gridDim.x, bb = blockIdx.x;
+    const int lb = (bb & 7) * (nb >> 3) + (bb >> 3);
+    if (lb >= nitems) return;
+    const TileItem it = items[lb];
+    const Film &fm = d.film[it.film];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const TileCtx t = tile_make(fm, d.dim, octant_sign(d, it.oct, na_oct, 0), octant_sign(d, it.oct, na_oct, 1),
+                                octant_sign(d, it.oct, na_oct, 2), it.tile, tdim);
+    tile_tables<T>(t, fm, d, S, X, nullptr, false);
+    for (int i = threadIdx.x; i < 5 * 64; i += blockDim.x) S.mom[i] = 0.0;
+    __syncthreads();
+    tile_modes<T>(t, d, S, true);
+    const int loct = it.oct ^ ((1 << d.dim) - 1);
+    const int kbeg = loct * na_oct * d.nl, kend = kbeg + na_oct * d.nl;
+    const T tdt = (T)dt;
+    for (int ch = 0; ch < nchunk_oct; ++ch) {
+        const int k = kbeg + ch * 64 + lane;
+        const bool active = k < kend;
+        const LaneT<T> L = lane_make<T>(d, fm, active ? k : kbeg);
+        T wsa[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) wsa[a] = (T)(L.w * fabs(d.s[3 * L.al + a]));
+        const double c4 = d.C4[L.l], it0 = d.itau[L.l];
+        tile_load<T>(t, S, lam, k, active, L.C4);
+        __syncthreads();
+        for (int i = wave; i < t.nt; i += 4) {
+            const int c = uni(S.cell[i]);
+            const bool solid = uni(S.code[i]) & kSolidBit;
+            double acc[5] = {0, 0, 0, 0, 0};
+            if (active) {
+                if (solid) {
+                    int up_out[3];
+                    const T tf = tile_flux_adj<T, DIM>(d, t, S, i, L, wsa, lane, lam, dinA, up_out);
+                    const T lc = S.box[i * 64 + lane];
+                    const T itc = L.itau + (T)S.gam[i];
+                    const T ln = lc + tdt * (tf - lc * itc + (T)L.w * itc * (T)S.tl[i]);
+                    lout[(size_t)c * d.nk + k] = ln;
+                    const double x = (double)ek[(size_t)c * d.nk + k];
+                    const double itd = it0 + S.gam[i];
+                    acc[0] = c4 * itd * (double)ln;
+                    acc[1] = (double)lc * x;
+                    acc[2] = (double)lc * c4;
+                    acc[3] = L.w * x;
+                    acc[4] = L.w * itd * x;
+                } else {
+                    lout[(size_t)c * d.nk + k] = (T)0;
+                }
+            }
+            wave_sum_t<5>(acc);
+            if (lane == 0)
+#pragma unroll
+                for (int q = 0; q < 5; ++q) S.mom[5 * i + q] += acc[q];
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < t.nt; i += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) part[((size_t)it.oct * 5 + q) * d.nc + S.cell[i]] = S.mom[5 * i + q];
+}
+
+// Per cell after a transposed step: the next closure term Xn = Phi(lam^k) and
+//   grad += dt (-sum lam e + T_L sum lam C/4pi + C_tot (T - T_L) X)
+// with T, T_L the deviations of e^k and X = Phi(lam^{k+1}) (dR/dgamma as in
+// the steady gradient).
+__global__ void k_adj_step_post(Dev d, const double *__restrict__ part, int noct, const double *__restrict__ X,
+                                double *__restrict__ Xn, double *__restrict__ grad, double dt)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.nc) return;
+    double s[5] = {0, 0, 0, 0, 0};
+    for (int o = 0; o < noct; ++o)
+        for (int q = 0; q < 5; ++q) s[q] += part[((size_t)o * 5 + q) * d.nc + c];
+    if (!(d.code[c] & kSolidBit)) {
+        Xn[c] = 0.0;
+        return;
+    }
+    const double Sc = d.S[c];
+    const double Td = s[3] / d.Ctot, TLd = s[4] / Sc;
+    grad[c] += dt * (-s[1] + TLd * s[2] + d.Ctot * (Td - TLd) * X[c]);
+    Xn[c] = s[0] / Sc;
+}
+
+// lam^N = dJ/de^N for J = sum_c a_c T_c / sum_c a_c:  a_c w / (A C_tot)
+template <typename T>
+__global__ void k_adj_tave_init(Dev d, const double *__restrict__ a, double inv_sum_a, T *__restrict__ lam)
+{
+    const size_t n = (size_t)d.nc * d.nk;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i / d.nk), k = (int)(i - (size_t)c * d.nk);
+        const int al = k / d.nl;
+        lam[i] = (d.code[c] & kSolidBit) ? (T)(a[c] * inv_sum_a * d.w[al] / d.Ctot) : (T)0;
+    }
+}
+
+// Phi(lam) = sum C/(4 pi) (1/tau) lam / S per cell (one block per cell)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj_phi_cell(Dev d, const T *__restrict__ lam, double *__restrict__ X)
+{
+    __shared__ double sh[4];
+    const int c = blockIdx.x;
+    double acc = 0;
+    const bool solid = d.code[c] & kSolidBit;
+    if (solid) {
+        const double g = d.gamma[c];
+        for (int k = threadIdx.x; k < d.nk; k += kBlock) {
+            const int l = k % d.nl;
+            acc += d.C4[l] * (d.itau[l] + g) * (double)lam[(size_t)c * d.nk + k];
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) X[c] = solid ? (sh[0] + sh[1] + sh[2] + sh[3]) / d.S[c] : 0.0;
+}
+
+// J = sum a T / sum a, T absolute (one block; T from the moments)
+__global__ __launch_bounds__(kBlock) void k_tave(Dev d, const double *__restrict__ a, const double *__restrict__ T,
+                                                 double *__restrict__ out)
+{
+    __shared__ double sh[8];
+    double x = 0, y = 0;
+    for (int c = threadIdx.x; c < d.nc; c += kBlock) {
+        x += a[c] * T[c];
+        y += a[c];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        x += __shfl_xor(x, off, 64);
+        y += __shfl_xor(y, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[threadIdx.x >> 6] = x;
+        sh[4 + (threadIdx.x >> 6)] = y;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = (sh[0] + sh[1] + sh[2] + sh[3]) / (sh[4] + sh[5] + sh[6] + sh[7]);
+        out[1] = sh[4] + sh[5] + sh[6] + sh[7];
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <typename T>
@@ -234,6 +392,52 @@ void launch_adj_grad(const Dev &d, const T *e, const T *psi, const double *Tdev,
     hipLaunchKernelGGL(k_adj_grad<T>, dim3(d.nc), dim3(kBlock), 0, s, d, e, psi, Tdev, TLdev, X, grad);
 }
 
+
+template <typename T, int DIM>
+void adj_step_launch(const Dev &d, const T *lam, T *lout, const T *ek, const double *X, const double *dinA,
+                     const TileItem *items, int nitems, int3 tdim, int na_oct, int nchunk_oct, int cap, double dt,
+                     double *part, hipStream_t s)
+{
+    const size_t sm = tile_smem_bytes(cap, sizeof(T), false);
+    const int grid = (nitems + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_adj_step<T, DIM>), dim3(grid), dim3(256), sm, s, d, lam, lout, ek, X, dinA, items, nitems,
+                       tdim, na_oct, nchunk_oct, cap, dt, part);
+}
+
+template <typename T>
+hipError_t launch_adj_step(const Dev &d, const T *lam, T *lout, const T *ek, const double *X, const double *dinA,
+                           const TileItem *items, int nitems, int3 tdim, int na_oct, int nchunk_oct, int cap,
+                           double dt, double *part, hipStream_t s)
+{
+    if (d.dim == 1) adj_step_launch<T, 1>(d, lam, lout, ek, X, dinA, items, nitems, tdim, na_oct, nchunk_oct, cap, dt, part, s);
+    if (d.dim == 2) adj_step_launch<T, 2>(d, lam, lout, ek, X, dinA, items, nitems, tdim, na_oct, nchunk_oct, cap, dt, part, s);
+    if (d.dim == 3) adj_step_launch<T, 3>(d, lam, lout, ek, X, dinA, items, nitems, tdim, na_oct, nchunk_oct, cap, dt, part, s);
+    return hipGetLastError();
+}
+
+void launch_adj_step_post(const Dev &d, const double *part, int noct, const double *X, double *Xn, double *grad,
+                          double dt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_step_post, dim3((d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, part, noct, X, Xn,
+                       grad, dt);
+}
+
+template <typename T>
+void launch_adj_tave_init(const Dev &d, const double *a, double inv_sum_a, T *lam, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_tave_init<T>, dim3(4096), dim3(kBlock), 0, s, d, a, inv_sum_a, lam);
+}
+
+template <typename T> void launch_adj_phi_cell(const Dev &d, const T *lam, double *X, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_phi_cell<T>, dim3(d.nc), dim3(kBlock), 0, s, d, lam, X);
+}
+
+void launch_tave(const Dev &d, const double *a, const double *T, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tave, dim3(1), dim3(kBlock), 0, s, d, a, T, out);
+}
+
 template <typename T> hipError_t set_lds_adj(size_t bytes)
 {
     hipError_t r = hipSuccess, x;
@@ -242,6 +446,12 @@ template <typename T> hipError_t set_lds_adj(size_t bytes)
     if ((x = hipFuncSetAttribute(reinterpret_cast<const void *>(k_adj_res<T, 2>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) r = x;
     if ((x = hipFuncSetAttribute(reinterpret_cast<const void *>(k_adj_res<T, 3>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) r = x;
+    if ((x = hipFuncSetAttribute(reinterpret_cast<const void *>(k_adj_step<T, 1>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) r = x;
+    if ((x = hipFuncSetAttribute(reinterpret_cast<const void *>(k_adj_step<T, 2>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) r = x;
+    if ((x = hipFuncSetAttribute(reinterpret_cast<const void *>(k_adj_step<T, 3>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) r = x;
     return r;
 }
@@ -264,5 +474,16 @@ template void launch_adj_grad<float>(const Dev &, const float *, const float *, 
                                      const double *, double *, hipStream_t);
 template void launch_adj_grad<double>(const Dev &, const double *, const double *, const double *, const double *,
                                       const double *, double *, hipStream_t);
+
+template hipError_t launch_adj_step<float>(const Dev &, const float *, float *, const float *, const double *,
+                                           const double *, const TileItem *, int, int3, int, int, int, double, double *,
+                                           hipStream_t);
+template hipError_t launch_adj_step<double>(const Dev &, const double *, double *, const double *, const double *,
+                                            const double *, const TileItem *, int, int3, int, int, int, double,
+                                            double *, hipStream_t);
+template void launch_adj_tave_init<float>(const Dev &, const double *, double, float *, hipStream_t);
+template void launch_adj_tave_init<double>(const Dev &, const double *, double, double *, hipStream_t);
+template void launch_adj_phi_cell<float>(const Dev &, const float *, double *, hipStream_t);
+template void launch_adj_phi_cell<double>(const Dev &, const double *, double *, hipStream_t);
 
 }  // namespace bte

@@ -45,6 +45,14 @@ template <typename T>
 void launch_adj_grad(const Dev &, const T *, const T *, const double *, const double *, const double *, double *,
                      hipStream_t);
 hipError_t adj_kernels_init(size_t);
+template <typename T>
+hipError_t launch_adj_step(const Dev &, const T *, T *, const T *, const double *, const double *, const TileItem *,
+                           int, int3, int, int, int, double, double *, hipStream_t);
+void launch_adj_step_post(const Dev &, const double *, int, const double *, double *, double *, double,
+                          hipStream_t);
+template <typename T> void launch_adj_tave_init(const Dev &, const double *, double, T *, hipStream_t);
+template <typename T> void launch_adj_phi_cell(const Dev &, const T *, double *, hipStream_t);
+void launch_tave(const Dev &, const double *, const double *, double *, hipStream_t);
 size_t tile_smem_size(int, int, int);
 template <typename T> void launch_set_equilibrium(const Dev &, T *, const double *, hipStream_t);
 template <typename T> void launch_apply_shift(const Dev &, const T *, T *, const double *, const double *, hipStream_t);
@@ -915,6 +923,35 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
     return ret;
 }
 
+// Source factor of the pulse {t_centre, FWHM} at time t (1 without a pulse)
+double pulse_factor(const double *pulse, double t)
+{
+    if (!pulse) return 1.0;
+    const double x = t - pulse[0];
+    return std::exp(-4.0 * std::log(2.0) * x * x / (pulse[1] * pulse[1]));
+}
+
+// One explicit step ein -> eout (Sec. 4.1); p->TL holds T_L of ein on entry
+// and of eout on exit.  ev: 4 events (before walls, before and after the
+// transport kernel, after T_L) or null.
+template <typename T>
+hipError_t one_step(bte_problem *p, const T *ein, T *eout, double src, hipEvent_t *ev, hipStream_t s)
+{
+    const Dev &d = p->dev;
+    hipError_t r;
+    if (ev && (r = hipEventRecord(ev[0], s)) != hipSuccess) return r;
+    launch_walls<T>(d, ein, nullptr, p->d_wrec, p->d_wden, p->din, p->nw, s);
+    if (ev && (r = hipEventRecord(ev[1], s)) != hipSuccess) return r;
+    if ((r = launch_transient_tile<T>(d, ein, eout, p->TL, p->din, p->d_titems, (int)p->titems.size(), p->tdim_tr,
+                                      p->na_oct, p->nchunk_oct, p->tile_cap_tr, src, p->ctl.dt, p->part, s)) !=
+        hipSuccess)
+        return r;
+    if (ev && (r = hipEventRecord(ev[2], s)) != hipSuccess) return r;
+    launch_finalize_tl(d, p->part, p->noct, p->TL, s);
+    if (ev && (r = hipEventRecord(ev[3], s)) != hipSuccess) return r;
+    return hipGetLastError();
+}
+
 template <typename T>
 bte_status transient_impl(bte_problem *p, T *e, int n_steps, double t0, const double *pulse, hipStream_t s)
 {
@@ -935,21 +972,8 @@ bte_status transient_impl(bte_problem *p, T *e, int n_steps, double t0, const do
     launch_moments<T>(d, e, nullptr, p->part, s);
     launch_finalize(d, p->part, 1, p->Tref, nullptr, nullptr, nullptr, p->TL, nullptr, nullptr, s);
     for (int n = 0; n < n_steps; ++n) {
-        const double t = t0 + n * dt;
-        double src = 1.0;
-        if (pulse) {
-            const double x = t - pulse[0];
-            src = std::exp(-4.0 * std::log(2.0) * x * x / (pulse[1] * pulse[1]));
-        }
-        if (timing) HIPCHK(p, hipEventRecord(p->tev[4 * n], s));
-        launch_walls<T>(d, buf[cur], nullptr, p->d_wrec, p->d_wden, p->din, p->nw, s);
-        if (timing) HIPCHK(p, hipEventRecord(p->tev[4 * n + 1], s));
-        HIPCHK(p, launch_transient_tile<T>(d, buf[cur], buf[1 - cur], p->TL, p->din, p->d_titems,
-                                           (int)p->titems.size(), p->tdim_tr, p->na_oct, p->nchunk_oct, p->tile_cap_tr,
-                                           src, dt, p->part, s));
-        if (timing) HIPCHK(p, hipEventRecord(p->tev[4 * n + 2], s));
-        launch_finalize_tl(d, p->part, p->noct, p->TL, s);
-        if (timing) HIPCHK(p, hipEventRecord(p->tev[4 * n + 3], s));
+        const double src = pulse_factor(pulse, t0 + n * dt);
+        HIPCHK(p, one_step<T>(p, buf[cur], buf[1 - cur], src, timing ? &p->tev[4 * n] : nullptr, s));
         cur = 1 - cur;
     }
     if (cur != 0) HIPCHK(p, hipMemcpyAsync(e, buf[cur], p->esize() * p->nelem(), hipMemcpyDeviceToDevice, s));
@@ -1093,6 +1117,100 @@ bte_status adjoint_impl(bte_problem *p, const T *e, double *grad, bte_solve_stat
     return ret;
 }
 
+// Transient adjoint (reverse mode of the explicit steps, Sec. 4.1) for
+// J = sum_c a_c T_c(e^N) / sum_c a_c.  The forward pass keeps e every `every`
+// steps (ck[0 .. nseg)); the backward pass recomputes one segment at a time
+// into ck[nseg .. nseg + every) and runs the transposed steps on it.
+template <typename T>
+bte_status tadj_impl(bte_problem *p, const T *e0, int n_steps, double t0, const double *pulse, const double *a,
+                     int every, char *ck, double *J_host, double *grad, bte_solve_stats *stats, hipStream_t s)
+{
+    auto h0 = std::chrono::steady_clock::now();
+    const Dev &d = p->dev;
+    const size_t bytes = p->esize() * p->nelem();
+    const int nseg = (n_steps + every - 1) / every;
+    const double dt = p->ctl.dt;
+    auto CK = [&](int i) { return reinterpret_cast<T *>(ck + (size_t)i * bytes); };
+    auto SG = [&](int j) { return reinterpret_cast<T *>(ck + (size_t)(nseg + j) * bytes); };
+    // T_L of each checkpoint, so that a recomputed segment repeats the
+    // forward pass bit for bit
+    auto CTL = [&](int i) {
+        return reinterpret_cast<double *>(ck + (size_t)(nseg + every) * bytes) + (size_t)i * p->nc;
+    };
+    const size_t tlb = 8 * (size_t)p->nc;
+    T *buf[2] = {(T *)p->psi, (T *)p->psi2};
+    // forward pass with checkpoints
+    HIPCHK(p, hipMemcpyAsync(CK(0), e0, bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(p, hipMemcpyAsync(buf[0], e0, bytes, hipMemcpyDeviceToDevice, s));
+    launch_moments<T>(d, e0, nullptr, p->part, s);
+    launch_finalize(d, p->part, 1, p->Tref, nullptr, nullptr, nullptr, p->TL, nullptr, nullptr, s);
+    HIPCHK(p, hipMemcpyAsync(CTL(0), p->TL, tlb, hipMemcpyDeviceToDevice, s));
+    int c = 0;
+    for (int n = 0; n < n_steps; ++n) {
+        HIPCHK(p, one_step<T>(p, buf[c], buf[1 - c], pulse_factor(pulse, t0 + n * dt), nullptr, s));
+        c = 1 - c;
+        if ((n + 1) % every == 0 && n + 1 < n_steps) {
+            HIPCHK(p, hipMemcpyAsync(CK((n + 1) / every), buf[c], bytes, hipMemcpyDeviceToDevice, s));
+            HIPCHK(p, hipMemcpyAsync(CTL((n + 1) / every), p->TL, tlb, hipMemcpyDeviceToDevice, s));
+        }
+    }
+    // J from the final state
+    launch_moments<T>(d, buf[c], nullptr, p->part, s);
+    launch_finalize(d, p->part, 1, p->Tref, p->T1, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+    launch_tave(d, a, p->T1, p->fmean, s);
+    double jt[2];
+    HIPCHK(p, hipMemcpyAsync(jt, p->fmean, 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(p, hipStreamSynchronize(s));
+    if (!(jt[1] > 0)) FAIL(p, BTE_ERR_ARG, "weights must have a positive sum");
+    if (J_host) *J_host = jt[0];
+    // backward pass
+    T *lam[2] = {buf[0], buf[1]};
+    double *X[2] = {p->adjX, p->adju};
+    launch_adj_tave_init<T>(d, a, 1.0 / jt[1], lam[0], s);
+    launch_adj_phi_cell<T>(d, lam[0], X[0], s);
+    HIPCHK(p, hipMemsetAsync(grad, 0, 8 * (size_t)p->nc, s));
+    int lc = 0;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int start = sg * every, len = std::min(every, n_steps - start);
+        HIPCHK(p, hipMemcpyAsync(SG(0), CK(sg), bytes, hipMemcpyDeviceToDevice, s));
+        HIPCHK(p, hipMemcpyAsync(p->TL, CTL(sg), tlb, hipMemcpyDeviceToDevice, s));
+        for (int j = 1; j < len; ++j)
+            HIPCHK(p, one_step<T>(p, SG(j - 1), SG(j), pulse_factor(pulse, t0 + (start + j - 1) * dt), nullptr, s));
+        for (int j = len - 1; j >= 0; --j) {
+            launch_walls_adj<T>(d, lam[lc], p->d_wrec, p->d_wden, p->din, p->nw, s);
+            HIPCHK(p, launch_adj_step<T>(d, lam[lc], lam[1 - lc], SG(j), X[lc], p->din, p->d_titems,
+                                         (int)p->titems.size(), p->tdim_tr, p->na_oct, p->nchunk_oct,
+                                         p->tile_cap_tr, dt, p->part, s));
+            launch_adj_step_post(d, p->part, p->noct, X[lc], X[1 - lc], grad, dt, s);
+            lc = 1 - lc;
+        }
+    }
+    HIPCHK(p, hipGetLastError());
+    HIPCHK(p, hipStreamSynchronize(s));
+    bte_solve_stats st{};
+    st.iters = n_steps;
+    st.converged = 1;
+    st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
+    p->last = st;
+    if (stats) *stats = st;
+    return BTE_OK;
+}
+
+// dt stability check shared by the transient calls
+bte_status check_cfl(bte_problem *p)
+{
+    if (!(p->ctl.dt > 0)) FAIL(p, BTE_ERR_ARG, "control.dt must be > 0");
+    double adv = 0;
+    for (const Film &fm : p->films) {
+        double x = 0;
+        for (int q = 0; q < p->dim; ++q) x += fm.ih[q];
+        adv = std::max(adv, x);
+    }
+    if (p->ctl.dt * p->itau_max >= 1.0 || p->ctl.dt * p->vmax * adv >= 1.0)
+        FAIL(p, BTE_ERR_CFL, "dt violates dt/tau_min < 1 or dt v_max sum_a 1/h_a < 1");
+    return BTE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1139,16 +1257,11 @@ bte_status bte_transient_step(bte_problem *p, void *e_dev, int n_steps, double t
     if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
     if (!e_dev) FAIL(p, BTE_ERR_ARG, "e is null");
     if (n_steps < 0) FAIL(p, BTE_ERR_ARG, "n_steps < 0");
-    if (!(p->ctl.dt > 0)) FAIL(p, BTE_ERR_ARG, "control.dt must be > 0");
     if (pulse && !(pulse[1] > 0)) FAIL(p, BTE_ERR_ARG, "pulse FWHM must be > 0");
-    double adv = 0;
-    for (const Film &fm : p->films) {
-        double a = 0;
-        for (int q = 0; q < p->dim; ++q) a += fm.ih[q];
-        adv = std::max(adv, a);
+    {
+        const bte_status cs = check_cfl(p);
+        if (cs != BTE_OK) return cs;
     }
-    if (p->ctl.dt * p->itau_max >= 1.0 || p->ctl.dt * p->vmax * adv >= 1.0)
-        FAIL(p, BTE_ERR_CFL, "dt violates dt/tau_min < 1 or dt v_max sum_a 1/h_a < 1");
     hipStream_t s = (hipStream_t)stream;
     if (p->ctl.precision == BTE_F64) return transient_impl<double>(p, (double *)e_dev, n_steps, t0, pulse, s);
     return transient_impl<float>(p, (float *)e_dev, n_steps, t0, pulse, s);
@@ -1198,6 +1311,41 @@ bte_status bte_adjoint(bte_problem *p, const void *e_dev, int objective, double 
     if (p->ctl.precision == BTE_F64)
         return adjoint_impl<double>(p, (const double *)e_dev, dJ_dgamma_dev, stats, s);
     return adjoint_impl<float>(p, (const float *)e_dev, dJ_dgamma_dev, stats, s);
+}
+
+size_t bte_transient_adjoint_bytes(const bte_problem *p, int n_steps, int every)
+{
+    if (!p || n_steps < 1 || every < 1) return 0;
+    every = std::min(every, n_steps);
+    const size_t nseg = (size_t)(n_steps + every - 1) / every;
+    return (nseg + (size_t)every) * p->esize() * p->nelem() + nseg * 8 * (size_t)p->nc;
+}
+
+bte_status bte_transient_adjoint(bte_problem *p, const void *e0_dev, int n_steps, double t0, const double *pulse,
+                                 const double *weights_dev, int every, void *ckpt_dev, size_t ckpt_bytes,
+                                 double *J_host, double *dJ_dgamma_dev, bte_solve_stats *stats, void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
+    if (!e0_dev || !weights_dev || !ckpt_dev || !dJ_dgamma_dev) FAIL(p, BTE_ERR_ARG, "null argument");
+    if (n_steps < 1 || every < 1) FAIL(p, BTE_ERR_ARG, "n_steps and every must be >= 1");
+    if (!p->ctl.adjoint) FAIL(p, BTE_ERR_STATE, "control.adjoint was 0 at setup: no adjoint workspace");
+    if (p->ctl.limiter != BTE_LIM_NONE) FAIL(p, BTE_ERR_UNSUPPORTED, "the adjoint needs limiter NONE");
+    if (pulse && !(pulse[1] > 0)) FAIL(p, BTE_ERR_ARG, "pulse FWHM must be > 0");
+    {
+        const bte_status cs = check_cfl(p);
+        if (cs != BTE_OK) return cs;
+    }
+    every = std::min(every, n_steps);
+    const size_t need = bte_transient_adjoint_bytes(p, n_steps, every);
+    if (ckpt_bytes < need) FAIL(p, BTE_ERR_ARG, "checkpoint buffer too small (%zu < %zu)", ckpt_bytes, need);
+    if ((uintptr_t)ckpt_dev & 255) FAIL(p, BTE_ERR_ARG, "checkpoint buffer must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->ctl.precision == BTE_F64)
+        return tadj_impl<double>(p, (const double *)e0_dev, n_steps, t0, pulse, weights_dev, every, (char *)ckpt_dev,
+                                 J_host, dJ_dgamma_dev, stats, s);
+    return tadj_impl<float>(p, (const float *)e0_dev, n_steps, t0, pulse, weights_dev, every, (char *)ckpt_dev,
+                            J_host, dJ_dgamma_dev, stats, s);
 }
 
 bte_status bte_get_directions(const bte_problem *p, double *s_host, double *w_host)
