@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_adj_res(Dev d, const T *__restrict__ ps
         for (int a = 0; a < 3; ++a) wsa[a] = (T)(L.w * fabs(d.s[3 * L.al + a]));
         const T gl = (T)(gfac * L.wv[0]);
         const double c4 = d.C4[L.l];
-        tile_load<T>(t, S, psi, k, active, L.C4);
+        tile_load<T>(t, S, psi, k, active, L.C4, static_cast<const T *>(d.zrow));
         __syncthreads();
         for (int i = wave; i < t.nt; i += 4) {
             const bool solid = uni(S.code[i]) & kSolidBit;
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_adj_step(Dev d, const T *__restrict__ l
 #pragma unroll
         for (int a = 0; a < 3; ++a) wsa[a] = (T)(L.w * fabs(d.s[3 * L.al + a]));
         const double c4 = d.C4[L.l], it0 = d.itau[L.l];
-        tile_load<T>(t, S, lam, k, active, L.C4);
+        tile_load<T>(t, S, lam, k, active, L.C4, static_cast<const T *>(d.zrow));
         __syncthreads();
         for (int i = wave; i < t.nt; i += 4) {
             const int c = uni(S.cell[i]);

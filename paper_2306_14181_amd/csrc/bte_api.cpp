@@ -46,6 +46,9 @@ void launch_adj_grad(const Dev &, const T *, const T *, const double *, const do
                      hipStream_t);
 hipError_t adj_kernels_init(size_t);
 template <typename T>
+hipError_t launch_sweep2d(const Dev &, const T *, T *, const double *, const double *, const double *,
+                          const SweepItem *, int, int, int, int, double *, hipStream_t);
+template <typename T>
 hipError_t launch_adj_step(const Dev &, const T *, T *, const T *, const double *, const double *, const TileItem *,
                            int, int3, int, int, int, double, double *, hipStream_t);
 void launch_adj_step_post(const Dev &, const double *, int, const double *, double *, double *, double,
@@ -498,6 +501,7 @@ void plan_workspace(bte_problem *p)
     p->npart_max = std::max(nchunk_stream, p->noct * p->nchunk_oct);
     add("part", 8 * (size_t)kMomN * nc * p->npart_max);
     add("e2", p->esize() * p->nelem());
+    add("zrow", 8 * (size_t)p->nk);
     for (const char *n : {"adjX", "adjT", "adjTL", "adju", "adjr2"}) add(n, 8 * nc);
     if (p->ctl.adjoint) {
         add("psi", p->esize() * p->nelem());
@@ -665,6 +669,7 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     d.gamma = p->gamma;
     d.P = nullptr;
     d.S = p->S;
+    d.zrow = wsptr<void>(p, "zrow");
     p->kdif = wsptr<double>(p, "kdif");
     p->kcor = wsptr<double>(p, "kcor");
     p->cdif = wsptr<double>(p, "cdif");
@@ -705,6 +710,7 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     p->d_wrec = wsptr<int>(p, "wrec");
     p->d_wden = wsptr<double>(p, "wden");
     // default fields: no source, no extra scattering
+    HIPCHK(p, hipMemset(wsptr<void>(p, "zrow"), 0, 8 * (size_t)p->nk));
     HIPCHK(p, hipMemset(p->gamma, 0, 8 * (size_t)p->nc));
     HIPCHK(p, hipMemset(p->P, 0, 8 * (size_t)p->nc));
     cell_setup(p, nullptr);
@@ -839,8 +845,12 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
         HIPCHK(p, hipEventRecord(ev[1], s));
         for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
             const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
-            HIPCHK(p, launch_sweep_tile<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt, p->tdim,
-                                           p->na_oct, p->nchunk_oct, p->tile_cap, p->part, s));
+            if (p->dim == 2)
+                HIPCHK(p, launch_sweep2d<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt, p->na_oct,
+                                            p->nchunk_oct, p->part, s));
+            else
+                HIPCHK(p, launch_sweep_tile<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt, p->tdim,
+                                               p->na_oct, p->nchunk_oct, p->tile_cap, p->part, s));
             st.sweep_launches += cnt > 0;
         }
         HIPCHK(p, hipEventRecord(ev[2], s));

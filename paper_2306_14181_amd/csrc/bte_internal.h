@@ -64,6 +64,8 @@ struct Dev {
     const double *gamma;     // [nc]
     const double *P;         // [nc]
     const double *S;         // [nc] sum_lambda C (1/tau + gamma)
+    const void *zrow;        // [nk] zeros of the working precision: loads of a
+                             // missing cell read here instead of branching
 };
 
 // One work item of the sweep: a tile of one geometry for 64 lanes of one octant.

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_sweep_tile(Dev d, const T *__restrict__
     tile_tables<T>(t, fm, d, S, TLdev, dpend, !ADJ);
     __syncthreads();
     tile_modes<T>(t, d, S, ADJ);
-    tile_load<T>(t, S, ein, k, active, L.C4, eout);
+    tile_load<T>(t, S, ein, k, active, L.C4, static_cast<const T *>(d.zrow), eout);
     __syncthreads();
 
     T wsa[3] = {(T)0, (T)0, (T)0};
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_transient_tile(Dev d, const T *__restri
         const int k = kbeg + ch * 64 + lane;
         const bool active = k < kend;
         const LaneT<T> L = lane_make<T>(d, fm, active ? k : kbeg);
-        tile_load<T>(t, S, ein, k, active, L.C4);
+        tile_load<T>(t, S, ein, k, active, L.C4, static_cast<const T *>(d.zrow));
         __syncthreads();
         for (int i = wave; i < t.nt; i += 4) {
             const int c = uni(S.cell[i]);

@@ -181,25 +181,28 @@ __device__ inline void tile_modes(const TileCtx t, const Dev &d, TileSmem<T> &S,
 
 // Stage the star for lane k (wave w loads slots w, w+4, ...) in register
 // batches.  If eout is given (sweep), the increments e^{n+1} - e^n of the
-// first upwind halo layer (not periodic) go to `dup`.
+// first upwind halo layer (not periodic) go to `dup`.  The loads are
+// unconditional: a missing cell reads the zero row, an inactive lane reads
+// element 0 of a valid row (never stored), and the batch index is clamped;
+// a load under a branch would be waited for before the branch joins.
 template <typename T, int NB = 16>
 __device__ inline void tile_load(const TileCtx t, TileSmem<T> &S, const T *__restrict__ e, int k, bool active, T C4,
-                                 const T *__restrict__ eout = nullptr)
+                                 const T *__restrict__ zrow, const T *__restrict__ eout = nullptr)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kk = active ? k : 0;
     for (int s0 = wave; s0 < t.nslot; s0 += 4 * NB) {
         T v[NB], w[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-            const int s = s0 + 4 * j;
-            v[j] = (T)0;
+            const int s = min(s0 + 4 * j, t.nslot - 1);
+            const long long off = S.slot_off[s];
+            const T *row = off >= 0 ? e + off : zrow;
+            v[j] = row[kk];
             w[j] = (T)0;
-            if (s < t.nslot) {
-                const long long off = S.slot_off[s];
-                if (active && off >= 0) {
-                    v[j] = e[off + k];
-                    if (eout && S.slot_up1[s] >= 0) w[j] = eout[off + k];
-                }
+            if (eout) {
+                const T *ro = (off >= 0 && S.slot_up1[s] >= 0) ? eout + off : zrow;
+                w[j] = ro[kk];
             }
         }
 #pragma unroll
