@@ -70,6 +70,28 @@ __device__ inline int cell2(const Dev &d, const Frame2 &F, int f0, int f1, doubl
     return (d.code[c] & kSolidBit) ? c : -1;
 }
 
+// Same without the pore test: the cell at (f0, f1) whatever it holds (its
+// value is only used where the codes of the neighbours say it is solid).
+__device__ inline int cell2_any(const Frame2 &F, int f0, int f1, double &jump)
+{
+    int i0 = F.o0 + (F.sg0 > 0 ? f0 : F.e0 - 1 - f0);
+    int i1 = F.o1 + (F.sg1 > 0 ? f1 : F.e1 - 1 - f1);
+    jump = 0.0;
+    if (i0 < 0 || i0 >= F.n0) {
+        if (!F.per0) return -1;
+        jump += (i0 < 0 ? 1.0 : -1.0) * F.pdT0;
+        i0 = i0 < 0 ? i0 + F.n0 : i0 - F.n0;
+        if (i0 < 0 || i0 >= F.n0) i0 = ((i0 % F.n0) + F.n0) % F.n0;
+    }
+    if (i1 < 0 || i1 >= F.n1) {
+        if (!F.per1) return -1;
+        jump += (i1 < 0 ? 1.0 : -1.0) * F.pdT1;
+        i1 = i1 < 0 ? i1 + F.n1 : i1 - F.n1;
+        if (i1 < 0 || i1 >= F.n1) i1 = ((i1 % F.n1) + F.n1) % F.n1;
+    }
+    return F.cell0 + i0 + F.n0 * i1;
+}
+
 // Halo positions, one per lane: h < 8: row -2, h < 16: row -1, h < 24: row
 // e1 (downwind), h < 48: x halo of row r = (h - 24) / 3 at f0 = -2, -1, e0.
 __device__ inline bool halo_pos(const Frame2 &F, int h, int &f0, int &f1)
@@ -153,298 +175,282 @@ __device__ inline T delta_general(const Dev &d, const Film &fm, const T *__restr
 // Per tile cell mode word (built once per wave, read as a uniform value)
 enum : uint32_t {
     W_SOLID = 1u, W_FX = 2u, W_FY = 4u,        // solid; interior stencil along x / y
-    W_CX = 8u, W_CY = 16u                      // implicit coupling to the upwind cell along x / y
+    W_CX = 8u, W_CY = 16u,                     // implicit coupling to the upwind cell along x / y
+    W_HU20 = 32u, W_HU21 = 64u                 // second upwind cell exists along x / y
 };
 
 template <typename T, int LIM>
-__global__ __launch_bounds__(64) void k_sweep2d(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
-                                                const double *__restrict__ dpend, const double *__restrict__ TLdev,
-                                                const double *__restrict__ din,
-                                                const SweepItem *__restrict__ items, int item0, int na_oct,
-                                                int nchunk_oct, double *__restrict__ part)
+__global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
+                                                 const double *__restrict__ dpend, const double *__restrict__ TLdev,
+                                                 const double *__restrict__ din,
+                                                 const SweepItem *__restrict__ items, int item0, int na_oct,
+                                                 int nchunk_oct, double *__restrict__ part)
 {
     __shared__ double lc[64][kMomN + 1];
-    __shared__ T xs[64 * 65];        // [lane][cell], padded: conflict-free both ways
-    __shared__ T wx[kTX + 3][64];    // row window of the general path: x halo + row
-    __shared__ T wy[3][kTX][64];     // rows f1-2, f1-1, f1+1
-    __shared__ T gd[kTX][64];        // flux divergence of general cells
-
+    __shared__ T dls[kTY][kTX][64];      // increments of each row (upwind recurrence hand-off)
+    __shared__ T xs[kTY][kTX][64];       // new values of each row (moment reduction)
     const SweepItem it = items[item0 + blockIdx.x];
     const Film &fm = d.film[it.film];
-    const int lane = threadIdx.x;
+    const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;   // wavefront r owns tile row r
     const int kbeg = it.oct * na_oct * d.nl, kend = kbeg + na_oct * d.nl;
     const int k = kbeg + it.chunk * 64 + lane;
     const bool active = k < kend;
     const int nk = d.nk;
     const LaneT<T> L = lane_make<T>(d, fm, active ? k : kbeg);
-    lc[lane][0] = active ? L.w : 0.0;
-    lc[lane][1] = active ? L.witau : 0.0;
-    lc[lane][2] = active ? L.wv[0] : 0.0;
-    lc[lane][3] = active ? L.wv[1] : 0.0;
-    lc[lane][4] = active ? L.wv[2] : 0.0;
+    if (r == 0) {
+        lc[lane][0] = active ? L.w : 0.0;
+        lc[lane][1] = active ? L.witau : 0.0;
+        lc[lane][2] = active ? L.wv[0] : 0.0;
+        lc[lane][3] = active ? L.wv[1] : 0.0;
+        lc[lane][4] = active ? L.wv[2] : 0.0;
+    }
     const Frame2 F = frame2(fm, octant_sign(d, it.oct, na_oct, 0), octant_sign(d, it.oct, na_oct, 1), it.tile);
     const int e0 = F.e0, e1 = F.e1;
     const int sg0 = F.sg0, sg1 = F.sg1;
     const int sx = sg0 > 0 ? 1 : -1;
     const int rowstep = sg1 > 0 ? F.n0 : -F.n0;
     const int cbase = F.cell0 + (sg0 > 0 ? F.o0 : F.o0 + e0 - 1) + F.n0 * (sg1 > 0 ? F.o1 : F.o1 + e1 - 1);
+    const bool myrow = r < e1;
 
-    // ---- cell records, one cell per lane, broadcast with readlane:
-    //   tile cell t = f0 + 8 f1 in lane t: global cell (any; -1 outside the
-    //   tile), mode word, T_L, gamma, P/C_tot, pending correction;
-    //   halo cell h (see halo_pos) in lane h: solid cell or -1, correction
-    //   (pending correction + periodic jump).
-    int t_c = -1;
-    uint32_t t_w = 0;
-    T t_tl = 0, t_gam = 0, t_qs = 0, t_x = 0;
-    int h_c = -1;
-    T h_x = 0;
+    // ---- cell records, one cell per lane (every wavefront builds the same),
+    // broadcast with readlane: tile cell t = f0 + 8 f1 in lane t; halo cell
+    // h (see halo_pos) in lane h.  Indices are arithmetic, so the stencil
+    // loads below need no record; the per-cell loads are one parallel batch
+    // and the second-upwind flags come from the neighbouring lanes' codes.
+    int t_c = -1, h_c = -1;
+    double h_j = 0;
     {
         const int f0 = lane & 7, f1 = lane >> 3;
-        if (f0 < e0 && f1 < e1) {
-            const int c = cbase + rowstep * f1 + sx * f0;
-            t_c = c;
-            const uint32_t code = d.code[c];
-            if (code & kSolidBit) {
-                const uint32_t ab0 = axis_bits(code, 0), ab1 = axis_bits(code, 1);
-                const bool hu0 = side_is_cell(ab0, -sg0), hu1 = side_is_cell(ab1, -sg1);
-                bool hu20 = false, hu21 = false;
-                if (hu0) hu20 = side_is_cell(axis_bits(d.code[d.nb[face_of(0, -sg0) * d.nc + c]], 0), -sg0);
-                if (hu1) hu21 = side_is_cell(axis_bits(d.code[d.nb[face_of(1, -sg1) * d.nc + c]], 1), -sg1);
-                uint32_t w = W_SOLID;
-                if (hu0 && hu20 && side_is_cell(ab0, sg0)) w |= W_FX;
-                if (hu1 && hu21 && side_is_cell(ab1, sg1)) w |= W_FY;
-                if (hu0 && !side_wraps(ab0, -sg0)) w |= W_CX;
-                if (hu1 && !side_wraps(ab1, -sg1)) w |= W_CY;
-                t_w = w;
-                t_tl = TLdev ? (T)TLdev[c] : (T)0;
-                t_gam = (T)d.gamma[c];
-                t_qs = d.P ? (T)(d.P[c] / d.Ctot) : (T)0;   // P is null without a heat source
-                t_x = dpend ? (T)dpend[c] : (T)0;
-            }
-        }
+        if (f0 < e0 && f1 < e1) t_c = cbase + rowstep * f1 + sx * f0;
         int h0, h1;
-        if (halo_pos(F, lane, h0, h1)) {
-            double jmp;
-            h_c = cell2(d, F, h0, h1, jmp);
-            if (h_c >= 0) h_x = (T)((dpend ? dpend[h_c] : 0.0) + jmp);
-        }
+        if (halo_pos(F, lane, h0, h1)) h_c = cell2_any(F, h0, h1, h_j);
+    }
+    // raw stencil values of this wavefront's row window, issued first (the
+    // row index is clamped for wavefronts past the tile: loaded, unused)
+    const int kk = active ? k : kbeg;
+    const T *zrow = static_cast<const T *>(d.zrow);
+    const int rr = myrow ? r : e1 - 1;
+    auto row_c = [&](int q, int j) -> int {
+        if (q >= 0 && q < e1) return j < e0 ? cbase + rowstep * q + sx * j : -1;
+        return rl(h_c, q == -2 ? j : (q == -1 ? 8 + j : 16 + j));
+    };
+    auto ldc = [&](const T *base, int c) -> T {
+        const T *row = c >= 0 ? base + (size_t)c * nk : zrow;
+        return row[kk];
+    };
+    T ym2[kTX], ym1[kTX], yp1[kTX], dr[kTX], ecr[kTX];
+#pragma unroll
+    for (int j = 0; j < kTX; ++j) {
+        ym2[j] = ldc(ein, row_c(rr - 2, j));
+        const int cm1 = row_c(rr - 1, j);
+        ym1[j] = ldc(ein, cm1);
+        ecr[j] = ldc(ein, row_c(rr, j));
+        yp1[j] = ldc(ein, row_c(rr + 1, j));
+        dr[j] = ldc(eout, rr == 0 ? cm1 : -1);
+    }
+    const int hx = 24 + 3 * rr;
+    const int cx0 = rl(h_c, hx), cx1 = rl(h_c, hx + 1), cx2 = rl(h_c, hx + 2);
+    T xh0 = ldc(ein, cx0), xh1 = ldc(ein, cx1), xh2 = ldc(ein, cx2);
+    const T dxr = ldc(eout, cx1);
+
+    uint32_t t_code = 0, h_code = 0;
+    double t_xd = 0, t_tld = 0, t_gamd = 0, t_qsd = 0, h_xd = 0;
+    if (t_c >= 0) {
+        t_code = d.code[t_c];
+        t_xd = dpend ? dpend[t_c] : 0.0;
+        t_tld = TLdev ? TLdev[t_c] : 0.0;
+        t_gamd = d.gamma[t_c];
+        t_qsd = d.P ? d.P[t_c] : 0.0;   // P is null without a heat source
+    }
+    if (h_c >= 0) {
+        h_code = d.code[h_c];
+        h_xd = dpend ? dpend[h_c] : 0.0;
     }
     auto rlt = [&](T v, int l) -> T {
         if constexpr (sizeof(T) == 4) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
         else return rl((double)v, l);
     };
-    // slot s: tile cell (s < 64) or halo cell 64 + h
-    auto slot_c = [&](int s) { return s < 64 ? rl(t_c, s) : rl(h_c, s - 64); };
-    auto slot_x = [&](int s) { return s < 64 ? rlt(t_x, s) : rlt(h_x, s - 64); };
-
+    // mode words (needs the codes of the upwind neighbours: lanes t - 1 /
+    // t - 8 of the tile, or the x-halo / row -1 halo lanes)
+    uint32_t t_w = 0;
+    T t_tl, t_gam, t_qs, t_x, h_x;
+    {
+        const int f0 = lane & 7, f1 = lane >> 3;
+        const uint32_t cxa = (uint32_t)__shfl((int)t_code, lane - 1, 64);
+        const uint32_t cxb = (uint32_t)__shfl((int)h_code, 24 + 3 * f1 + 1, 64);
+        const uint32_t cya = (uint32_t)__shfl((int)t_code, lane - 8, 64);
+        const uint32_t cyb = (uint32_t)__shfl((int)h_code, 8 + f0, 64);
+        const uint32_t cu0 = f0 >= 1 ? cxa : cxb, cu1 = f1 >= 1 ? cya : cyb;
+        const uint32_t code = t_code;
+        if (t_c >= 0 && (code & kSolidBit)) {
+            const uint32_t ab0 = axis_bits(code, 0), ab1 = axis_bits(code, 1);
+            const bool hu0 = side_is_cell(ab0, -sg0), hu1 = side_is_cell(ab1, -sg1);
+            const bool hu20 = hu0 && side_is_cell(axis_bits(cu0, 0), -sg0);
+            const bool hu21 = hu1 && side_is_cell(axis_bits(cu1, 1), -sg1);
+            uint32_t w = W_SOLID;
+            if (hu20) w |= W_HU20;
+            if (hu21) w |= W_HU21;
+            if (hu20 && side_is_cell(ab0, sg0)) w |= W_FX;
+            if (hu21 && side_is_cell(ab1, sg1)) w |= W_FY;
+            if (hu0 && !side_wraps(ab0, -sg0)) w |= W_CX;
+            if (hu1 && !side_wraps(ab1, -sg1)) w |= W_CY;
+            t_w = w;
+        }
+        const bool sol = t_w & W_SOLID;
+        t_tl = sol ? (T)t_tld : (T)0;
+        t_gam = sol ? (T)t_gamd : (T)0;
+        t_qs = sol ? (T)(t_qsd / d.Ctot) : (T)0;
+        t_x = sol ? (T)t_xd : (T)0;
+        h_x = (T)(h_xd + h_j);
+    }
     const T C4 = L.C4, cp0 = L.cpl[0], cp1 = L.cpl[1];
     const T A0 = cp0 + cp1 + L.itau;
-    // Loads are unconditional (a missing cell or an inactive lane reads a
-    // valid element and the value is dropped afterwards): a load under a
-    // branch would be waited for before the branch joins, and the wavefront
-    // would then pay the full memory latency once per load.
-    // A missing cell reads the zero row (and has no correction); inactive
-    // lanes read a valid element whose value is never stored.  Values are
-    // prefetched raw (the load is not consumed) one row ahead of their use;
-    // the pending correction and periodic jump (C/4pi x) are added when the
-    // row becomes current.
-    const int kk = active ? k : kbeg;
-    const T *zrow = static_cast<const T *>(d.zrow);
-    auto raw = [&](const T *base, int slot) -> T {
-        const int c = slot_c(slot);
-        const T *row = c >= 0 ? base + (size_t)c * nk : zrow;
-        return row[kk];
+    // Loads are unconditional: a missing cell reads the zero row (and has no
+    // correction), an inactive lane reads a valid element that is never
+    // stored.  A load under a branch would be waited for before the branch
+    // joins, one memory latency per load.
+    // correction of row q (-2 .. e1) at x position j (0 .. 7)
+    auto row_x = [&](int q, int j) -> T {
+        if (q >= 0 && q < e1) return rlt(t_x, 8 * q + j);
+        return rlt(h_x, q == -2 ? j : (q == -1 ? 8 + j : 16 + j));
     };
-    // tile row r < e1: the cell index is arithmetic (pores are read too and
-    // masked by the codes)
-    auto raw_tile = [&](int r, int j) -> T {
-        const T *row = j < e0 ? ein + (size_t)(cbase + rowstep * r + sx * j) * nk : zrow;
-        return row[kk];
-    };
-    auto corr = [&](int slot) -> T { return C4 * slot_x(slot); };
-    auto row_slot = [&](int r, int j) { return r < e1 ? 8 * r + j : 64 + 16 + j; };
 
-    // window: rows f1-2, f1-1, f1 (cur), f1+1 (yp1) as final values; raw
-    // prefetch of row f1+2 and of the x halo (-2, -1, e0) and x-upwind
-    // increment of row f1+1; increments of row f1-1 (dpr)
-    T ym2[kTX], ym1[kTX], cur[kTX], yp1[kTX], pr2[kTX], dpr[kTX];
-    T xh0, xh1, xh2, dupx, pxh0, pxh1, pxh2, pdup;
-#pragma unroll
-    for (int j = 0; j < kTX; ++j) {
-        ym2[j] = raw(ein, 64 + j);
-        ym1[j] = raw(ein, 64 + 8 + j);
-        dpr[j] = raw(eout, 64 + 8 + j);
-        cur[j] = raw_tile(0, j);
-        yp1[j] = e1 > 1 ? raw_tile(1, j) : raw(ein, 64 + 16 + j);
-    }
-    pxh0 = raw(ein, 64 + 24);
-    pxh1 = raw(ein, 64 + 25);
-    pxh2 = raw(ein, 64 + 26);
-    pdup = raw(eout, 64 + 25);
-#pragma unroll
-    for (int j = 0; j < kTX; ++j) {
-        ym2[j] += corr(64 + j);
-        ym1[j] += corr(64 + 8 + j);
-        dpr[j] = dpr[j] - ym1[j];
-        cur[j] += corr(j);
-        yp1[j] += corr(row_slot(1, j));
-    }
-
-    for (int f1 = 0; f1 < e1; ++f1) {
-        const int hx = 64 + 24 + 3 * f1;
-        // current x halo from the prefetch
-        xh0 = pxh0 + corr(hx);
-        xh1 = pxh1 + corr(hx + 1);
-        xh2 = pxh2 + corr(hx + 2);
-        dupx = pdup - xh1;
-        // prefetch (unconditional, clamped: a load under a branch would be
-        // waited for at the join): row f1 + 2, the downwind halo row when
-        // f1 + 2 == e1; the x halo of row f1 + 1
-        {
-            const int r2 = f1 + 2;
-#pragma unroll
-            for (int j = 0; j < kTX; ++j) pr2[j] = r2 < e1 ? raw_tile(r2, j) : raw(ein, 64 + 16 + j);
-            const int hn = f1 + 1 < e1 ? hx + 3 : hx;
-            pxh0 = raw(ein, hn);
-            pxh1 = raw(ein, hn + 1);
-            pxh2 = raw(ein, hn + 2);
-            pdup = raw(eout, hn + 1);
-        }
-
-        // flux divergence: interior cells here, the others (walls, pores,
-        // missing neighbours) in one loop over the row window in LDS
-        T D[kTX];
-        uint32_t gmask = 0;
+    // ---- this wavefront's row: stencil rows, right-hand side (in parallel)
+    T num[kTX], ec[kTX], rden[kTX];
+    T dupx = (T)0, dpr0[kTX];
+    if (myrow) {
 #pragma unroll
         for (int j = 0; j < kTX; ++j) {
-            D[j] = (T)0;
-            const uint32_t w = (uint32_t)rl((int)t_w, 8 * f1 + j);
-            if ((w & (W_SOLID | W_FX | W_FY)) == (W_SOLID | W_FX | W_FY)) {
-                const T ex2 = j >= 2 ? cur[j - 2] : (j == 1 ? xh1 : xh0);
-                const T ex1 = j >= 1 ? cur[j - 1] : xh1;
-                const T exd = j + 1 < e0 ? cur[j + 1] : xh2;
-                D[j] = cp0 * delta_fast<T, LIM>(ex2, ex1, cur[j], exd) +
-                       cp1 * delta_fast<T, LIM>(ym2[j], ym1[j], cur[j], yp1[j]);
-            } else if (w & W_SOLID) {
-                gmask |= 1u << j;
-            }
+            ym2[j] += C4 * row_x(r - 2, j);
+            ym1[j] += C4 * row_x(r - 1, j);
+            ec[j] = ecr[j] + C4 * row_x(r, j);
+            yp1[j] += C4 * row_x(r + 1, j);
+            dpr0[j] = dr[j] - ym1[j];   // y-upwind increments (row 0 only)
         }
-        if (gmask) {
-            wx[0][lane] = xh0;
-            wx[1][lane] = xh1;
+        xh0 += C4 * rlt(h_x, hx);
+        xh1 += C4 * rlt(h_x, hx + 1);
+        xh2 += C4 * rlt(h_x, hx + 2);
+        dupx = dxr - xh1;
+
 #pragma unroll
-            for (int j = 0; j < kTX; ++j) {
-                wx[j + 2][lane] = cur[j];
-                wy[0][j][lane] = ym2[j];
-                wy[1][j][lane] = ym1[j];
-                wy[2][j][lane] = yp1[j];
-            }
-            wx[e0 + 2][lane] = xh2;
-            for (uint32_t m = gmask; m; m &= m - 1) {
-                const int j = __builtin_ctz(m);
-                const int t = 8 * f1 + j;
-                const int c = rl(t_c, t);
-                const uint32_t code = d.code[c];
-                const uint32_t ab0 = axis_bits(code, 0), ab1 = axis_bits(code, 1);
-                const uint32_t w = (uint32_t)rl((int)t_w, t);
-                const bool hu0 = side_is_cell(ab0, -sg0), hd0 = side_is_cell(ab0, sg0);
-                const bool hu1 = side_is_cell(ab1, -sg1), hd1 = side_is_cell(ab1, sg1);
-                // second upwind cell: from the upwind cell's code
-                const int cu0 = hu0 ? d.nb[face_of(0, -sg0) * d.nc + c] : -1;
-                const int cu1 = hu1 ? d.nb[face_of(1, -sg1) * d.nc + c] : -1;
-                const bool hu20 = cu0 >= 0 && side_is_cell(axis_bits(d.code[cu0], 0), -sg0);
-                const bool hu21 = cu1 >= 0 && side_is_cell(axis_bits(d.code[cu1], 1), -sg1);
-                const T ex2 = wx[j][lane], ex1 = wx[j + 1][lane], ec = wx[j + 2][lane], exd = wx[j + 3][lane];
-                const T ey2 = wy[0][j][lane], ey1 = wy[1][j][lane], eyd = wy[2][j][lane];
-                const double xc = (double)rlt(t_x, t);
+        for (int j = 0; j < kTX; ++j) {
+            const int t = 8 * r + j;
+            const uint32_t w = (uint32_t)rl((int)t_w, t);
+            num[j] = (T)0;
+            rden[j] = (T)0;
+            if (w & W_SOLID) {
+                const T ex2 = j >= 2 ? ec[j - 2] : (j == 1 ? xh1 : xh0);
+                const T ex1 = j >= 1 ? ec[j - 1] : xh1;
+                const T exd = j + 1 < e0 ? ec[j + 1] : xh2;
                 T dx, dy;
                 if (w & W_FX) {
-                    dx = delta_fast<T, LIM>(ex2, ex1, ec, exd);
+                    dx = delta_fast<T, LIM>(ex2, ex1, ec[j], exd);
                 } else {
-                    // downwind cell and its correction (the x halo or the next cell of the row)
-                    const int sd = j + 1 < e0 ? t + 1 : hx + 2;
-                    const int cd = hd0 ? slot_c(sd) : -1;
-                    dx = delta_general<T, LIM>(d, fm, ein, din, c, code, 0, sg0, hu0, hu20, hd0, ex2, ex1, ec, exd,
-                                               cd, (double)slot_x(sd), xc, L.al, L.l, k, active, C4, L.hh[0], L.ih[0], nk);
+                    const int c = rl(t_c, t);
+                    const uint32_t code = (uint32_t)rl((int)t_code, t);
+                    const uint32_t ab0 = axis_bits(code, 0);
+                    const bool hu0 = side_is_cell(ab0, -sg0), hd0 = side_is_cell(ab0, sg0);
+                    const bool hu20 = w & W_HU20;
+                    const int cd = hd0 ? (j + 1 < e0 ? rl(t_c, t + 1) : cx2) : -1;
+                    const double xd = j + 1 < e0 ? (double)rlt(t_x, t + 1) : (double)rlt(h_x, hx + 2);
+                    dx = delta_general<T, LIM>(d, fm, ein, din, c, code, 0, sg0, hu0, hu20, hd0, ex2, ex1, ec[j], exd,
+                                               cd, xd, (double)rlt(t_x, t), L.al, L.l, k, active, C4, L.hh[0],
+                                               L.ih[0], nk);
                 }
                 if (w & W_FY) {
-                    dy = delta_fast<T, LIM>(ey2, ey1, ec, eyd);
+                    dy = delta_fast<T, LIM>(ym2[j], ym1[j], ec[j], yp1[j]);
                 } else {
-                    const int sd = f1 + 1 < e1 ? t + 8 : 64 + 16 + j;
-                    const int cd = hd1 ? slot_c(sd) : -1;
-                    dy = delta_general<T, LIM>(d, fm, ein, din, c, code, 1, sg1, hu1, hu21, hd1, ey2, ey1, ec, eyd,
-                                               cd, (double)slot_x(sd), xc, L.al, L.l, k, active, C4, L.hh[1], L.ih[1], nk);
+                    const int c = rl(t_c, t);
+                    const uint32_t code = (uint32_t)rl((int)t_code, t);
+                    const uint32_t ab1 = axis_bits(code, 1);
+                    const bool hu1 = side_is_cell(ab1, -sg1), hd1 = side_is_cell(ab1, sg1);
+                    const bool hu21 = w & W_HU21;
+                    const int cd = hd1 ? row_c(r + 1, j) : -1;
+                    const double xd = (double)row_x(r + 1, j);
+                    dy = delta_general<T, LIM>(d, fm, ein, din, c, code, 1, sg1, hu1, hu21, hd1, ym2[j], ym1[j], ec[j],
+                                               yp1[j], cd, xd, (double)rlt(t_x, t), L.al, L.l, k, active, C4,
+                                               L.hh[1], L.ih[1], nk);
                 }
-                gd[j][lane] = cp0 * dx + cp1 * dy;
+                const T gam = rlt(t_gam, t);
+                const T itc = L.itau + gam;
+                num[j] = -(cp0 * dx + cp1 * dy) - (ec[j] - C4 * rlt(t_tl, t)) * itc + C4 * rlt(t_qs, t);
+                const T den = A0 + gam;
+                if constexpr (sizeof(T) == 4) rden[j] = __builtin_amdgcn_rcpf(den);
+                else rden[j] = (T)1 / den;
             }
-#pragma unroll
-            for (int j = 0; j < kTX; ++j)
-                if (gmask & (1u << j)) D[j] = gd[j][lane];
-        }
-
-        // right-hand side and upwind recurrence along the row
-        const int b = cbase + rowstep * f1;
-        T dl = dupx;   // increment of the upwind x neighbour
-#pragma unroll
-        for (int j = 0; j < kTX; ++j) {
-            if (j < e0) {
-                const int t = 8 * f1 + j;
-                const int c = b + sx * j;
-                const uint32_t w = (uint32_t)rl((int)t_w, t);
-                T en = (T)0;
-                if (w & W_SOLID) {
-                    const T ec = cur[j];
-                    const T gam = rlt(t_gam, t);
-                    const T itc = L.itau + gam;
-                    T num = -D[j] - (ec - C4 * rlt(t_tl, t)) * itc + C4 * rlt(t_qs, t);
-                    // implicit upwind couplings (not across periodic faces)
-                    if (w & W_CX) num += cp0 * dl;
-                    if (w & W_CY) num += cp1 * dpr[j];
-                    const T den = A0 + gam;
-                    T dlt;
-                    if constexpr (sizeof(T) == 4) dlt = num * __builtin_amdgcn_rcpf(den);
-                    else dlt = num / den;
-                    en = ec + dlt;
-                    dl = dlt;
-                    dpr[j] = dlt;
-                    if (active) eout[(size_t)c * nk + k] = en;
-                } else {
-                    dl = (T)0;
-                    dpr[j] = (T)0;
-                    if (active) eout[(size_t)c * nk + k] = ein[(size_t)c * nk + k];
-                }
-                xs[lane * 65 + t] = active ? en : (T)0;
-            }
-        }
-        // advance the window
-        const int s2 = row_slot(min(f1 + 2, e1), 0);
-#pragma unroll
-        for (int j = 0; j < kTX; ++j) {
-            ym2[j] = ym1[j];
-            ym1[j] = cur[j];
-            cur[j] = yp1[j];
-            yp1[j] = pr2[j] + corr(s2 + j);
         }
     }
-    __syncthreads();
-    // moment partials: lane = tile cell (f0 + 8 f1), sum over the 64 lanes
-    {
-        const int c = t_c;
-        if (c >= 0) {
-            double acc[kMomN] = {0, 0, 0, 0, 0};
-            if (t_w & W_SOLID) {
-#pragma unroll 4
-                for (int l2 = 0; l2 < 64; ++l2) {
-                    const double x = (double)xs[l2 * 65 + lane];
+
+    // ---- upwind recurrence, row after row (the only serial part)
+    T dlt[kTX];
+    for (int s = 0; s < e1; ++s) {
+        if (r == s) {
+            T dl = dupx;   // increment of the upwind x neighbour
 #pragma unroll
-                    for (int m = 0; m < kMomN; ++m) acc[m] += lc[l2][m] * x;
+            for (int j = 0; j < kTX; ++j) {
+                const uint32_t w = (uint32_t)rl((int)t_w, 8 * r + j);
+                T dv = (T)0;
+                if (w & W_SOLID) {
+                    T nm = num[j];
+                    if (w & W_CX) nm += cp0 * dl;
+                    if (w & W_CY) nm += cp1 * (s == 0 ? dpr0[j] : dls[s - 1][j][lane]);
+                    dv = nm * rden[j];
                 }
-                acc[1] += d.gamma[c] * acc[0];
+                dl = dv;
+                dlt[j] = dv;
+                dls[s][j][lane] = dv;
             }
-            double *o = part + ((size_t)(it.oct * nchunk_oct + it.chunk) * d.nc + c) * kMomN;
+        }
+        __syncthreads();
+    }
+
+    // ---- new values, moment partials of the row
+    if (myrow) {
+        const int b = cbase + rowstep * r;
 #pragma unroll
-            for (int m = 0; m < kMomN; ++m) o[m] = acc[m];
+        for (int j = 0; j < kTX; ++j) {
+            T en = (T)0;
+            if (j < e0) {
+                const int c = b + sx * j;
+                const uint32_t w = (uint32_t)rl((int)t_w, 8 * r + j);
+                if (w & W_SOLID) {
+                    en = ec[j] + dlt[j];
+                    if (active) eout[(size_t)c * nk + k] = en;
+                } else if (active) {
+                    eout[(size_t)c * nk + k] = ein[(size_t)c * nk + k];
+                }
+            }
+            xs[r][j][lane] = active ? en : (T)0;
+        }
+        // lane = 8 cell + part: part sums 8 of the 64 lanes
+        const int j = lane >> 3, p = lane & 7;
+        double acc[kMomN] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int l2 = 8 * p + q;
+            const double x = (double)xs[r][j][l2];
+#pragma unroll
+            for (int m = 0; m < kMomN; ++m) acc[m] += lc[l2][m] * x;
+        }
+#pragma unroll
+        for (int m = 0; m < kMomN; ++m) {
+            double v = acc[m];
+            v += __shfl_xor(v, 1, 64);
+            v += __shfl_xor(v, 2, 64);
+            v += __shfl_xor(v, 4, 64);
+            acc[m] = v;
+        }
+        const int t = 8 * r + j;
+        const int c = __shfl(t_c, t, 64);
+        const uint32_t w = (uint32_t)__shfl((int)t_w, t, 64);
+        if (p == 0 && j < e0 && c >= 0) {
+            double *o = part + ((size_t)(it.oct * nchunk_oct + it.chunk) * d.nc + c) * kMomN;
+            const bool sol = w & W_SOLID;
+            o[0] = sol ? acc[0] : 0.0;
+            o[1] = sol ? acc[1] + d.gamma[c] * acc[0] : 0.0;
+            o[2] = sol ? acc[2] : 0.0;
+            o[3] = sol ? acc[3] : 0.0;
+            o[4] = sol ? acc[4] : 0.0;
         }
     }
 }
@@ -454,7 +460,7 @@ void sweep2d_launch(const Dev &d, const T *ein, T *eout, const double *dpend, co
                     const SweepItem *items, int item0, int count, int na_oct, int nchunk_oct, double *part,
                     hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sweep2d<T, LIM>), dim3(count), dim3(64), 0, s, d, ein, eout, dpend, TLdev, din, items,
+    hipLaunchKernelGGL((k_sweep2d<T, LIM>), dim3(count), dim3(64 * kTY), 0, s, d, ein, eout, dpend, TLdev, din, items,
                        item0, na_oct, nchunk_oct, part);
 }
 
