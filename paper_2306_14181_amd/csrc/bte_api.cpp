@@ -73,8 +73,8 @@ void launch_sub_film_mean(const Dev &, double *, const double *, hipStream_t);
 void launch_tl_update(int, const double *, const double *, double *, double *, hipStream_t);
 void launch_cg_coef(const Dev &, const CgArgs &, double *, double *, hipStream_t);
 void launch_diff_rhs(const Dev &, const CgArgs &, double *, hipStream_t);
-int cg_persist_blocks(const Dev &);
-hipError_t launch_cg_persist(const Dev &, const CgArgs &, const double *, int, hipStream_t);
+void launch_cg_begin(const Dev &, const CgArgs &, const double *, hipStream_t);
+void launch_cg_iters(const Dev &, const CgArgs &, int, int, hipStream_t);
 }  // namespace bte
 
 using namespace bte;
@@ -781,9 +781,10 @@ template <typename T> bte_status moments_to(bte_problem *p, const T *e, const do
 }
 
 // Jacobi-preconditioned CG on the heat-diffusion (corr = 0) or correction
-// (corr = 1) operator in one cooperative launch; b is projected per floating
-// geometry beforehand, x afterwards.  Asynchronous: the iteration count is
-// accumulated on the device (cg_scal[9]).  Returns false on a HIP error.
+// (corr = 1) operator, two launches per iteration; b is projected per
+// floating geometry beforehand, x afterwards.  Asynchronous when maxit fits
+// one chunk of launches; the iteration count is accumulated on the device
+// (cg_scal[9]).  Returns false on a HIP error.
 bool run_cg(bte_problem *p, int corr, double *b, double *x_out, double rtol, int maxit, hipStream_t s)
 {
     const Dev &d = p->dev;
@@ -794,7 +795,19 @@ bool run_cg(bte_problem *p, int corr, double *b, double *x_out, double rtol, int
     CgArgs g = cg_args(p, corr);
     g.x = x_out;
     g.rtol2 = rtol * rtol;
-    if (launch_cg_persist(d, g, b, maxit, s) != hipSuccess) return false;
+    // two launches per iteration, enqueued in chunks; between chunks the host
+    // reads the done flag (one synchronisation per chunk)
+    launch_cg_begin(d, g, b, s);
+    constexpr int kChunk = 64;
+    for (int it0 = 0; it0 < maxit; it0 += kChunk) {
+        launch_cg_iters(d, g, it0, std::min(kChunk, maxit - it0), s);
+        if (it0 + kChunk < maxit) {
+            double done = 0;
+            if (hipMemcpyAsync(&done, p->cg_scal + 5, 8, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+            if (hipStreamSynchronize(s) != hipSuccess) return false;
+            if (done != 0.0) break;
+        }
+    }
     if (p->floating_any) {
         launch_film_mean(d, x_out, p->fmean, s);
         launch_sub_film_mean(d, x_out, p->fmean, s);

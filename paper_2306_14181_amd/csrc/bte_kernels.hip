@@ -6,8 +6,6 @@
 // getTQ) are accumulated in FP64 and reduced deterministically: a butterfly
 // within each 64-wide wavefront, then a fixed-order sum over the block's
 // wavefronts, then a fixed-order sum over k-chunks in a finalize kernel.
-#include <hip/hip_cooperative_groups.h>
-
 #include <algorithm>
 
 #include "bte_internal.h"
@@ -275,15 +273,19 @@ __global__ __launch_bounds__(kBlock) void k_film_eps(Dev d, const double *__rest
     const Film &fm = d.film[blockIdx.x];
     double a[5] = {0, 0, 0, 0, 0};
     double mT = 0, mq = 0;
+    // branch-free body (pores contribute zeros) so that the loads of
+    // consecutive iterations overlap
+#pragma unroll 4
     for (int i = threadIdx.x; i < fm.ncell; i += kBlock) {
         const int c = fm.cell0 + i;
-        if (!(d.code[c] & kSolidBit)) continue;
-        const double dT = T0[c] - T1[c], dq = q0[c] - q1[c];
+        const double sl = (d.code[c] & kSolidBit) ? 1.0 : 0.0;
+        const double t1 = T1[c], u1 = q1[c];
+        const double dT = (T0[c] - t1) * sl, dq = (q0[c] - u1) * sl;
         a[0] += dT * dT;
         a[2] += dq * dq;
-        a[4] += T1[c];
-        mT = fmax(mT, fabs(T1[c]));
-        mq = fmax(mq, fabs(q1[c]));
+        a[4] += t1 * sl;
+        mT = fmax(mT, fabs(t1) * sl);
+        mq = fmax(mq, fabs(u1) * sl);
     }
     // maxima: butterfly max then block max
     for (int off = 32; off > 0; off >>= 1) {
@@ -315,9 +317,10 @@ __global__ __launch_bounds__(kBlock) void k_film_mean(Dev d, const double *__res
     __shared__ double sh[4];
     const Film &fm = d.film[blockIdx.x];
     double a[1] = {0};
+#pragma unroll 4
     for (int i = threadIdx.x; i < fm.ncell; i += kBlock) {
         const int c = fm.cell0 + i;
-        if (d.code[c] & kSolidBit) a[0] += x[c];
+        a[0] += (d.code[c] & kSolidBit) ? x[c] : 0.0;
     }
     block_sum<1>(a, sh);
     if (threadIdx.x == 0) mean[blockIdx.x] = a[0] / fm.nsolid;
@@ -415,105 +418,162 @@ __device__ inline double blk_sum1(double v, double *sh)
     return a[0];
 }
 
-// The whole Jacobi-preconditioned CG in one cooperative launch: cells are
-// strided over the grid, the two dot products of an iteration are reduced
-// per block and summed in block order by every block after a grid barrier
-// (deterministic), and the convergence test runs on the device.  scal[6]
-// receives the iteration count and scal[9] accumulates it over calls.
-__device__ inline void block_sum2(double &a, double &b, double *sh)
+// ---- CG with ordinary launches (two per iteration).  The launch boundary
+// is the grid-wide barrier, which costs far less than a cooperative grid
+// barrier on this part.  Every block reduces the block partials of the
+// previous launch itself, in the same fixed order, so all blocks take the
+// same decisions.  Uses p_{k+1} = z + beta p_k and A p_{k+1} = A z + beta A p_k
+// so that one launch updates both.  scal: [1] |b|^2, [5] done, [6] iterations
+// of this solve, [7 + parity] r.z, [9] iterations accumulated.
+__device__ inline void part_sum2(const double *__restrict__ part, int n, double *sh, double &a, double &b)
+{
+    double v[2] = {0, 0};
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+        v[0] += part[2 * i];
+        v[1] += part[2 * i + 1];
+    }
+    block_sum<2>(v, sh);
+    if (threadIdx.x == 0) {
+        sh[0] = v[0];
+        sh[1] = v[1];
+    }
+    __syncthreads();
+    a = sh[0];
+    b = sh[1];
+    __syncthreads();
+}
+
+__device__ inline void write_part2(double *part, double a, double b, double *sh)
 {
     double v[2] = {a, b};
     block_sum<2>(v, sh);
-    a = v[0];
-    b = v[1];
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = v[0];
+        part[2 * blockIdx.x + 1] = v[1];
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_persist(Dev d, CgArgs g, const double *__restrict__ b, int maxit)
+// x = 0, r = b, z = r / diag, p = z; partials (r.z, r.r) -> partB
+__global__ __launch_bounds__(kBlock) void k_cg_start(Dev d, CgArgs g, const double *__restrict__ b)
 {
-    namespace cgr = cooperative_groups;
-    cgr::grid_group grid = cgr::this_grid();
     __shared__ double sh[16];
-    __shared__ double red[2];
-    const int nblk = gridDim.x;
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = nblk * blockDim.x;
-    double *pa = g.part, *pb = g.part + 2 * nblk;
-    auto grid_sum2 = [&](double a, double c, double *buf) {
-        block_sum2(a, c, sh);
-        if (threadIdx.x == 0) {
-            buf[2 * blockIdx.x] = a;
-            buf[2 * blockIdx.x + 1] = c;
-        }
-        grid.sync();
-        if (threadIdx.x == 0) {
-            double s0 = 0, s1 = 0;
-            for (int i = 0; i < nblk; ++i) {
-                s0 += buf[2 * i];
-                s1 += buf[2 * i + 1];
-            }
-            red[0] = s0;
-            red[1] = s1;
-        }
-        __syncthreads();
-    };
-    double *__restrict__ X = g.x;
-    double *__restrict__ Rv = g.r;
-    double *__restrict__ Z = g.z;
-    double *__restrict__ Pv = g.p;
-    double *__restrict__ AP = g.Ap;
-    const double *__restrict__ DG = g.dg;
+    const int nthr = gridDim.x * kBlock;
     double rz = 0, rr = 0;
-    for (int c = tid; c < d.nc; c += nthr) {
-        const bool solid = d.code[c] & kSolidBit;
-        const double dg = DG[c];
-        const double rc = solid ? b[c] : 0.0;
-        X[c] = 0.0;
-        Rv[c] = rc;
-        Z[c] = rc / dg;
-        Pv[c] = rc / dg;
-        rz += rc * rc / dg;
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < d.nc; c += nthr) {
+        const double rc = (d.code[c] & kSolidBit) ? b[c] : 0.0;
+        const double zc = rc / g.dg[c];
+        g.x[c] = 0.0;
+        g.r[c] = rc;
+        g.z[c] = zc;
+        g.p[c] = zc;
+        rz += rc * zc;
         rr += rc * rc;
     }
-    grid_sum2(rz, rr, pa);
-    rz = red[0];
-    const double bn2 = red[1];
-    int it = 0;
-    if (bn2 > 0.0 && rz > 0.0) {
-        grid.sync();   // p visible to every block
-        while (it < maxit) {
-            double pap = 0;
-            for (int c = tid; c < d.nc; c += nthr) {
-                const double y = lap_row(d, g, c, Pv, nullptr);
-                AP[c] = y;
-                pap += Pv[c] * y;
-            }
-            grid_sum2(pap, 0.0, pa);
-            pap = red[0];
-            if (!(pap > 0.0)) break;
-            ++it;
-            const double alpha = rz / pap;
-            double rz2 = 0, rr2 = 0;
-            for (int c = tid; c < d.nc; c += nthr) {
-                X[c] += alpha * Pv[c];
-                const double rc = Rv[c] - alpha * AP[c];
-                Rv[c] = rc;
-                const double zc = rc / DG[c];
-                Z[c] = zc;
-                rz2 += rc * zc;
-                rr2 += rc * rc;
-            }
-            grid_sum2(rz2, rr2, pb);
-            rz2 = red[0];
-            rr2 = red[1];
-            if (rr2 <= g.rtol2 * bn2 || !(rz2 > 0.0)) break;
-            const double beta = rz2 / rz;
-            rz = rz2;
-            for (int c = tid; c < d.nc; c += nthr) Pv[c] = Z[c] + beta * Pv[c];
-            grid.sync();
-        }
+    write_part2(g.part + 2 * gridDim.x, rz, rr, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        g.scal[5] = 0.0;
+        g.scal[6] = 0.0;
     }
-    if (tid == 0) {
-        g.scal[6] = it;
-        g.scal[9] += it;
+}
+
+// |b|^2 and r.z from partB; Ap = A p; partial p.Ap -> partA
+__global__ __launch_bounds__(kBlock) void k_cg_ap0(Dev d, CgArgs g)
+{
+    __shared__ double sh[16];
+    const int nb = gridDim.x, nthr = nb * kBlock;
+    double rz, bn2;
+    part_sum2(g.part + 2 * nb, nb, sh, rz, bn2);
+    if (!(bn2 > 0.0) || !(rz > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            g.scal[1] = bn2;
+            g.scal[5] = 1.0;
+        }
+        return;
+    }
+    double pap = 0;
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < d.nc; c += nthr) {
+        const double y = lap_row(d, g, c, g.p, nullptr);
+        g.Ap[c] = y;
+        pap += g.p[c] * y;
+    }
+    write_part2(g.part, pap, 0.0, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        g.scal[1] = bn2;
+        g.scal[7] = rz;
+    }
+}
+
+// alpha = r.z / p.Ap; x += alpha p; r -= alpha Ap; z = r / diag; partials (r.z, r.r) -> partB
+__global__ __launch_bounds__(kBlock) void k_cg_step_a(Dev d, CgArgs g, int it)
+{
+    __shared__ double sh[16];
+    if (g.scal[5] != 0.0) return;
+    const int nb = gridDim.x, nthr = nb * kBlock;
+    double pap, unused;
+    part_sum2(g.part, nb, sh, pap, unused);
+    if (!(pap > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) g.scal[5] = 1.0;
+        return;
+    }
+    const double alpha = g.scal[7 + (it & 1)] / pap;
+    double rz = 0, rr = 0;
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < d.nc; c += nthr) {
+        g.x[c] += alpha * g.p[c];
+        const double rc = g.r[c] - alpha * g.Ap[c];
+        const double zc = rc / g.dg[c];
+        g.r[c] = rc;
+        g.z[c] = zc;
+        rz += rc * zc;
+        rr += rc * rc;
+    }
+    write_part2(g.part + 2 * nb, rz, rr, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        g.scal[6] = it + 1;
+        g.scal[9] += 1.0;
+    }
+}
+
+// convergence test; beta = r.z_new / r.z; p = z + beta p; Ap = A z + beta Ap;
+// partial p.Ap -> partA
+__global__ __launch_bounds__(kBlock) void k_cg_step_b(Dev d, CgArgs g, int it)
+{
+    __shared__ double sh[16];
+    if (g.scal[5] != 0.0) return;
+    const int nb = gridDim.x, nthr = nb * kBlock;
+    double rz2, rr2;
+    part_sum2(g.part + 2 * nb, nb, sh, rz2, rr2);
+    if (rr2 <= g.rtol2 * g.scal[1] || !(rz2 > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) g.scal[5] = 1.0;
+        return;
+    }
+    const double beta = rz2 / g.scal[7 + (it & 1)];
+    double pap = 0;
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < d.nc; c += nthr) {
+        const double pc = g.z[c] + beta * g.p[c];
+        const double y = lap_row(d, g, c, g.z, nullptr) + beta * g.Ap[c];
+        g.p[c] = pc;
+        g.Ap[c] = y;
+        pap += pc * y;
+    }
+    write_part2(g.part, pap, 0.0, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) g.scal[7 + ((it + 1) & 1)] = rz2;
+}
+
+int cg_blocks(const Dev &d) { return std::max(1, std::min(256, (d.nc + kBlock - 1) / kBlock)); }
+
+void launch_cg_begin(const Dev &d, const CgArgs &g, const double *b, hipStream_t s)
+{
+    const int nb = cg_blocks(d);
+    hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(kBlock), 0, s, d, g, b);
+    hipLaunchKernelGGL(k_cg_ap0, dim3(nb), dim3(kBlock), 0, s, d, g);
+}
+
+void launch_cg_iters(const Dev &d, const CgArgs &g, int it0, int n, hipStream_t s)
+{
+    const int nb = cg_blocks(d);
+    for (int it = it0; it < it0 + n; ++it) {
+        hipLaunchKernelGGL(k_cg_step_a, dim3(nb), dim3(kBlock), 0, s, d, g, it);
+        hipLaunchKernelGGL(k_cg_step_b, dim3(nb), dim3(kBlock), 0, s, d, g, it);
     }
 }
 
@@ -666,36 +726,6 @@ void launch_sub_film_mean(const Dev &d, double *x, const double *mean, hipStream
 void launch_tl_update(int n, const double *TLkin, const double *delta, double *TL, double *dpend, hipStream_t s)
 {
     hipLaunchKernelGGL(k_tl_update, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, TLkin, delta, TL, dpend);
-}
-
-// blocks of the persistent CG: co-resident (cooperative launch); a grid
-// barrier costs more with more blocks, so use about one block per 16 cells
-// per thread (the operator work per iteration is tiny), at most 64.
-int cg_persist_blocks(const Dev &d)
-{
-    static int max_coresident = 0;
-    if (!max_coresident) {
-        int dev = 0, ncu = 0, per = 0;
-        if (hipGetDevice(&dev) != hipSuccess) return -1;
-        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg_persist, kBlock, 0) != hipSuccess) return -1;
-        max_coresident = ncu * per;
-    }
-    const int need = (d.nc + 16 * kBlock - 1) / (16 * kBlock);
-    return std::max(1, std::min(std::min(need, 64), max_coresident));
-}
-
-hipError_t launch_cg_persist(const Dev &d, const CgArgs &g, const double *b, int maxit, hipStream_t s)
-{
-    const int nb = cg_persist_blocks(d);
-    if (nb < 1) return hipErrorInvalidValue;
-    Dev dd = d;
-    CgArgs gg = g;
-    const double *bb = b;
-    int mi = maxit;
-    void *args[] = {&dd, &gg, &bb, &mi};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_cg_persist), dim3(nb), dim3(kBlock), args, 0,
-                                      s);
 }
 
 void launch_cg_coef(const Dev &d, const CgArgs &g, double *coef, double *dg, hipStream_t s)
