@@ -18,6 +18,13 @@ way, and both are run to convergence to report their relative difference.
 cube of (2 um)^3, 40 bands, 128 directions, MC limiter, dt = 0.5 ps, laser
 pulse; a step is one explicit step of every (cell, direction, band).
 
+--workload porous2d_batch solves the batch of 64 porous films (sides 32 to
+256 cells, 64 directions, 20 bands) to convergence in one problem and
+reports k_eff per film; --workload porous3d_adjoint solves the 48^3 porous
+cube (96 directions, 40 bands, per-cell gamma) and its adjoint d k_eff /
+d gamma; --workload tadjoint3d runs the transient adjoint of 500 explicit
+steps on a 32^3 cube with checkpoints every 50 steps.
+
 --copy-calibration runs a plain 2 GiB device copy (for scaling HBM counters).
 
 Prints one JSON line.  --gpus N > 1 is not supported (one GPU only).
@@ -196,9 +203,130 @@ def cpu_baseline_transient():
                 kind="oracle", sample="%d explicit steps of the laser workload on a 32^3 grid, %.1f s" % (steps, dt))
 
 
+def bench_batch(args):
+    """64 porous films in one problem, FP32, converged steady solve."""
+    import numpy as np
+    import torch
+    import bte_inputs as I
+    from paper_2306_14181_amd import bte as B
+    torch.cuda.set_device(0)
+    cfg = I.config3()
+    films, mat = cfg["films"], cfg["material"]
+    prob = B.Problem(films, mat, dict(precision=B.F32, scheme=B.SYNTHETIC, limiter=B.LIM_NONE,
+                                      residual_temp=1e-6, residual_flux=1e-5, max_iter=args.max_iter,
+                                      cg_rtol=1e-6, cg_max_iter=40))
+    e = prob.zeros()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = prob.steady_solve(e, init=True, allow_not_converged=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    k = prob.keff(e).cpu().numpy()
+    solid = sum(int(np.count_nonzero(g["solid"])) for g in films)
+    upd = prob.n_cells * prob.n_dirs * prob.n_bands * st["iters"]
+    log("batch: %d films, %d cells (%d solid), %d iterations %.2f s, sweep %.0f ms, cg %.0f ms"
+        % (len(films), prob.n_cells, solid, st["iters"], t, st["ms_sweep"], st["ms_cg"]))
+    out = {"metric": "cell*dir*band updates/s of the batched steady solve (FP32 state, FP64 moments)",
+           "value": upd / t, "unit": "updates/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32 (e), f64 (moments, CG)",
+           "data": "synthetic (seeded porous films)",
+           "config": {"workload": "porous2d_batch: 64 films, sides 32-256, dx 1 um/256, 64 directions, 20 bands",
+                      "cells": prob.n_cells, "solid_cells": solid, "unknowns": prob.n_unknowns},
+           "iterations": st["iters"], "converged": st["converged"], "eps_T": st["eps_T"], "eps_q": st["eps_q"],
+           "solve_s": t,
+           "ms_per_iteration": 1e3 * t / max(st["iters"], 1),
+           "phase_ms_per_iteration": {kk: st[kk] / max(st["iters"], 1) for kk in ("ms_sweep", "ms_walls", "ms_post", "ms_cg")},
+           "sweep_GBs": BYTES_PER_UPDATE[B.F32] * prob.n_unknowns * st["iters"] / (st["ms_sweep"] * 1e-3) / 1e9,
+           "keff": {"min": float(k.min()), "mean": float(k.mean()), "max": float(k.max())}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args):
+    """48^3 porous cube: FP32 forward steady solve and the adjoint gradient."""
+    import numpy as np
+    import torch
+    import bte_inputs as I
+    from paper_2306_14181_amd import bte as B
+    torch.cuda.set_device(0)
+    cfg = I.config4()
+    g, mat = cfg["geometry"], cfg["material"]
+    ctl = dict(precision=B.F32, scheme=B.SYNTHETIC, limiter=B.LIM_NONE, adjoint=True, residual_temp=1e-6,
+               residual_flux=1e-5, max_iter=args.max_iter, cg_rtol=1e-6, cg_max_iter=40)
+    prob = B.Problem(g, mat, ctl)
+    prob.set_fields(None, torch.as_tensor(cfg["gamma"], device="cuda"))
+    e = prob.zeros()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = prob.steady_solve(e, init=True, allow_not_converged=True)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    k = prob.keff(e).item()
+    prob.set_control(**dict(ctl, residual_temp=1e-5))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grad, sa = prob.adjoint(e, allow_not_converged=True)
+    torch.cuda.synchronize()
+    ta = time.perf_counter() - t0
+    gr = grad.cpu().numpy()
+    upd = prob.n_unknowns
+    log("adjoint3d: forward %d its %.2f s, adjoint %d sweeps %.2f s (residual %.1e)"
+        % (st["iters"], tf, sa["iters"], ta, sa["eps_T"]))
+    out = {"metric": "forward and adjoint steady solves of the porous cube (FP32 state)",
+           "value": upd * (st["iters"] + sa["iters"]) / (tf + ta), "unit": "updates/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32 (e, psi), f64 (moments, CG, gradient)",
+           "data": "synthetic (seeded spherical pores, gamma ~ U[0, 1e11] 1/s)",
+           "config": {"workload": "porous3d_adjoint: 48^3 cells of (1 um)^3, porosity 0.2, 96 directions, 40 bands",
+                      "unknowns": upd},
+           "forward": {"iterations": st["iters"], "converged": st["converged"], "solve_s": tf,
+                       "ms_sweep_per_iteration": st["ms_sweep"] / max(st["iters"], 1), "keff": k},
+           "adjoint": {"sweeps": sa["iters"], "converged": sa["converged"], "relative_residual": sa["eps_T"],
+                       "solve_s": ta, "ms_sweep_per_iteration": sa["ms_sweep"] / max(sa["iters"], 1)},
+           "adjoint_over_forward_time": ta / tf,
+           "grad": {"min": float(gr.min()), "max": float(gr.max()), "sum": float(gr.sum())}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_tadjoint(args):
+    """Transient adjoint: 500 explicit steps of the laser physics on 32^3,
+    checkpoints every 50 steps, objective = weighted top-layer temperature."""
+    import torch
+    import bte_inputs as I
+    from paper_2306_14181_amd import bte as B
+    torch.cuda.set_device(0)
+    cfg = I.config2(n=32)
+    g, mat = cfg["geometry"], cfg["material"]
+    prob = B.Problem(g, mat, dict(precision=B.F32, limiter=B.LIM_NONE, dt=cfg["dt"], adjoint=True))
+    P = torch.as_tensor(cfg["P"], device="cuda")
+    prob.set_fields(P, torch.zeros(prob.n_cells, dtype=torch.float64, device="cuda"))
+    w = torch.as_tensor(cfg["hist_weights"], device="cuda")
+    n = 500
+    e = prob.zeros()
+    prob.transient_step(e, 5, 0.0, cfg["pulse"])
+    e = prob.zeros()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.transient_step(e, n, 0.0, cfg["pulse"])
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    J, grad, st = prob.transient_adjoint(prob.zeros(), n, w, 0.0, cfg["pulse"], every=50)
+    torch.cuda.synchronize()
+    ta = time.perf_counter() - t0
+    log("tadjoint3d: forward %d steps %.3f s, adjoint (forward + recompute + reverse) %.3f s" % (n, tf, ta))
+    out = {"metric": "transient adjoint cost (checkpointed reverse mode) over the forward run",
+           "value": ta / tf, "unit": "ratio", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f32 (e, lambda), f64 (moments, gradient)", "data": "synthetic (seeded bands, laser pulse)",
+           "config": {"workload": "tadjoint3d: 32^3 cells of (2 um)^3, 128 directions, 40 bands, 500 steps, "
+                                  "checkpoints every 50, limiter NONE"},
+           "forward_s": tf, "adjoint_s": ta, "J": J,
+           "forward_updates_per_s": prob.n_unknowns * n / tf}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=("steady2d", "transient3d"), default="steady2d")
+    ap.add_argument("--workload", choices=("steady2d", "transient3d", "porous2d_batch", "porous3d_adjoint",
+                                           "tadjoint3d"), default="steady2d")
+    ap.add_argument("--max-iter", type=int, default=1000, help="iteration cap of the converged solves")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
@@ -220,6 +348,15 @@ def main():
         return
     if args.workload == "transient3d":
         bench_transient(args)
+        return
+    if args.workload == "porous2d_batch":
+        bench_batch(args)
+        return
+    if args.workload == "porous3d_adjoint":
+        bench_adjoint(args)
+        return
+    if args.workload == "tadjoint3d":
+        bench_tadjoint(args)
         return
 
     import numpy as np
