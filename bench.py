@@ -212,7 +212,7 @@ def bench_batch(args):
     torch.cuda.set_device(0)
     cfg = I.config3()
     films, mat = cfg["films"], cfg["material"]
-    prob = B.Problem(films, mat, dict(precision=B.F32, scheme=B.SYNTHETIC, limiter=B.LIM_NONE,
+    prob = B.Problem(films, mat, dict(precision=B.F32, scheme=B.SYNTHETIC, limiter=cfg["limiter"],
                                       residual_temp=1e-6, residual_flux=1e-5, max_iter=args.max_iter,
                                       cg_rtol=1e-6, cg_max_iter=40))
     e = prob.zeros()
@@ -229,7 +229,7 @@ def bench_batch(args):
     out = {"metric": "cell*dir*band updates/s of the batched steady solve (FP32 state, FP64 moments)",
            "value": upd / t, "unit": "updates/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32 (e), f64 (moments, CG)",
            "data": "synthetic (seeded porous films)",
-           "config": {"workload": "porous2d_batch: 64 films, sides 32-256, dx 1 um/256, 64 directions, 20 bands",
+           "config": {"workload": "porous2d_batch: 64 films, sides 32-256, dx 1 um/256, 64 directions, 20 bands, minmod limiter",
                       "cells": prob.n_cells, "solid_cells": solid, "unknowns": prob.n_unknowns},
            "iterations": st["iters"], "converged": st["converged"], "eps_T": st["eps_T"], "eps_q": st["eps_q"],
            "solve_s": t,

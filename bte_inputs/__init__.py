@@ -184,7 +184,13 @@ def config2(seed=2, n=64, n_bands=40, n_theta=4, n_phi=4):
 
 def config3(seed=3, n_films=64, sides=(32, 64, 128, 192, 256), n_bands=20, n_theta=2, n_phi=4):
     """Batch of 2D porous films (periodic x with dT = 1 K, periodic y, diffuse
-    pores), dx = 1 um / 256; returns a list of film geometries and one band table."""
+    pores), dx = 1 um / 256; returns a list of film geometries and one band table.
+
+    The films are solved with the minmod limiter: with the unlimited central
+    gradient, plain and synthetic source iteration both diverge on some of
+    the seeded films, and with the MC limiter the iteration settles into a
+    limit cycle (relative change per iteration about 1.5e-5) on the larger
+    ballistic films; with minmod every film converges to the FP32 floor."""
     rng = np.random.default_rng(seed)
     mat = bands(rng, n_bands, 1e-12, 1e-9)
     mat.update(n_theta=n_theta, n_phi=n_phi, Tref=300.0)
@@ -200,7 +206,7 @@ def config3(seed=3, n_films=64, sides=(32, 64, 128, 192, 256), n_bands=20, n_the
         bc = [BC_PERIODIC] * 4 + [BC_SPECULAR] * 2
         films.append(_geometry(2, (side, side), (side * dx, side * dx), bc, pdT=(1.0, 0.0, 0.0),
                                solid=solid))
-    return dict(name="porous2d_batch", films=films, material=mat, limiter=LIM_NONE,
+    return dict(name="porous2d_batch", films=films, material=mat, limiter=LIM_MINMOD,
                 scheme=SCHEME_SYNTHETIC)
 
 

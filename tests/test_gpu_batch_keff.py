@@ -38,28 +38,31 @@ def small_batch():
 _REF = {}
 
 
-def oracle_keff(geo, mat, gamma=None):
-    case = O.Case(geo, mat, gamma=gamma)
+def oracle_keff(geo, mat, gamma=None, limiter=O.LIM_NONE):
+    case = O.Case(geo, mat, gamma=gamma, limiter=limiter)
     e, st = O.steady(case, scheme=1, tol_T=1e-13, tol_q=1e-12, max_iter=5000, cg_rtol=1e-14)
     assert st["converged"], st
     return O.keff(case, e)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_batched_films_keff_matches_oracle(B, prec):
+@pytest.mark.parametrize("prec,lim", [("f64", "none"), ("f32", "none"), ("f64", "mc"), ("f32", "mc"),
+                                      ("f64", "minmod"), ("f32", "minmod")])
+def test_batched_films_keff_matches_oracle(B, prec, lim):
     cfg = small_batch()
     films, mat = cfg["films"], cfg["material"]
     p = B.F64 if prec == "f64" else B.F32
-    prob = B.Problem(films, mat, dict(precision=p, scheme=B.SYNTHETIC, limiter=B.LIM_NONE,
+    gl, ol = {"none": (B.LIM_NONE, O.LIM_NONE), "mc": (B.LIM_MC, O.LIM_MC),
+              "minmod": (B.LIM_MINMOD, O.LIM_MINMOD)}[lim]
+    prob = B.Problem(films, mat, dict(precision=p, scheme=B.SYNTHETIC, limiter=gl,
                                       residual_temp=1e-12 if p == B.F64 else 1e-7,
                                       residual_flux=1e-11 if p == B.F64 else 1e-6,
                                       max_iter=20000, cg_rtol=1e-12, cg_max_iter=5000))
     e = prob.zeros()
     st = prob.steady_solve(e, init=True, allow_not_converged=(p == B.F32))
     k = prob.keff(e).cpu().numpy()
-    if "batch" not in _REF:
-        _REF["batch"] = np.array([oracle_keff(g, mat) for g in films])
-    ref = _REF["batch"]
+    if lim not in _REF:
+        _REF[lim] = np.array([oracle_keff(g, mat, limiter=ol) for g in films])
+    ref = _REF[lim]
     print(prec, "iters", st["iters"], "k_eff", k, "oracle", ref)
     tol = 1e-9 if p == B.F64 else 1e-5
     assert np.all(np.abs(k - ref) <= tol * np.abs(ref)), (k, ref)
