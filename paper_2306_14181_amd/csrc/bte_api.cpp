@@ -47,7 +47,7 @@ void launch_adj_grad(const Dev &, const T *, const T *, const double *, const do
 hipError_t adj_kernels_init(size_t);
 template <typename T>
 hipError_t launch_sweep2d(const Dev &, const T *, T *, const double *, const double *, const double *,
-                          const SweepItem *, int, int, int, int, double *, hipStream_t);
+                          const Sweep2Item *, int, int, int, int, double *, hipStream_t);
 template <typename T>
 hipError_t launch_adj_step(const Dev &, const T *, T *, const T *, const double *, const double *, const TileItem *,
                            int, int3, int, int, int, double, double *, hipStream_t);
@@ -139,6 +139,7 @@ struct bte_problem {
     int tile_cap_tr = 0;
     int nchunk_oct = 0;
     std::vector<SweepItem> items;
+    std::vector<Sweep2Item> items2;   // two-dimensional sweep: self-contained items, same order
     std::vector<int> diag_off;
     std::vector<TileItem> titems;   // transient: (geometry, octant, tile)
     int tile_cap = 0;               // star slots of a full tile
@@ -166,6 +167,7 @@ struct bte_problem {
     double *adjX = nullptr, *adjT = nullptr, *adjTL = nullptr;   // adjoint closure term, forward T and T_L
     double *adju = nullptr, *adjr2 = nullptr;
     SweepItem *d_items = nullptr;
+    Sweep2Item *d_items2 = nullptr;
     TileItem *d_titems = nullptr;
     int *d_wrec = nullptr;
     double *d_wden = nullptr;
@@ -457,6 +459,34 @@ void build_schedule(bte_problem *p)
         p->diag_off[r.d + 1]++;
     }
     for (int d = 0; d <= maxd; ++d) p->diag_off[d + 1] += p->diag_off[d];
+    p->items2.clear();
+    if (p->dim == 2) {
+        for (const SweepItem &it : p->items) {
+            const Film &fm = p->films[it.film];
+            Sweep2Item q{};
+            q.oct = it.oct;
+            q.chunk = it.chunk;
+            q.film = it.film;
+            const bool pos0 = p->s[3 * (it.oct * p->na_oct) + 0] > 0, pos1 = p->s[3 * (it.oct * p->na_oct) + 1] > 0;
+            q.flags = (fm.periodic[0] ? 1 : 0) | (fm.periodic[1] ? 2 : 0) | (pos0 ? 4 : 0) | (pos1 ? 8 : 0);
+            const int nt0 = (fm.n[0] + p->tdim.x - 1) / p->tdim.x;
+            q.o0 = (it.tile % nt0) * p->tdim.x;
+            q.o1 = (it.tile / nt0) * p->tdim.y;
+            q.e0 = std::min(p->tdim.x, fm.n[0] - q.o0);
+            q.e1 = std::min(p->tdim.y, fm.n[1] - q.o1);
+            q.n0 = fm.n[0];
+            q.n1 = fm.n[1];
+            q.cell0 = fm.cell0;
+            q.pdT0 = fm.pdT[0];
+            q.pdT1 = fm.pdT[1];
+            q.h0 = fm.h[0];
+            q.h1 = fm.h[1];
+            q.ih0 = fm.ih[0];
+            q.ih1 = fm.ih[1];
+            for (int f = 0; f < 4; ++f) q.wallT[f] = fm.wallT[f];
+            p->items2.push_back(q);
+        }
+    }
 }
 
 void plan_workspace(bte_problem *p)
@@ -482,6 +512,7 @@ void plan_workspace(bte_problem *p)
     add("wrec", 4 * p->wrec.size());
     add("wden", 8 * 6);
     add("items", sizeof(SweepItem) * p->items.size());
+    add("items2", sizeof(Sweep2Item) * p->items2.size());
     add("titems", sizeof(TileItem) * p->titems.size());
     for (const char *n : {"gamma", "P", "S", "TL", "TLkin", "T0", "T1", "q0", "q1", "r", "delta", "dpend", "cg_x",
                           "cg_r", "cg_z", "cg_p", "cg_Ap", "cg_diag"})
@@ -638,6 +669,7 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     HIPCHK(p, up("wrec", p->wrec.data(), 4 * p->wrec.size()));
     HIPCHK(p, up("wden", p->wden, 8 * 6));
     HIPCHK(p, up("items", p->items.data(), sizeof(SweepItem) * p->items.size()));
+    if (!p->items2.empty()) HIPCHK(p, up("items2", p->items2.data(), sizeof(Sweep2Item) * p->items2.size()));
     HIPCHK(p, up("titems", p->titems.data(), sizeof(TileItem) * p->titems.size()));
     if (tile_smem_size(p->tile_cap, (int)p->esize(), 1) > 160 * 1024) FAIL(p, BTE_ERR_UNSUPPORTED, "tile LDS");
     HIPCHK(p, tile_kernels_init(160 * 1024));
@@ -706,6 +738,7 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     p->adju = wsptr<double>(p, "adju");
     p->adjr2 = wsptr<double>(p, "adjr2");
     p->d_items = wsptr<SweepItem>(p, "items");
+    p->d_items2 = wsptr<Sweep2Item>(p, "items2");
     p->d_titems = wsptr<TileItem>(p, "titems");
     p->d_wrec = wsptr<int>(p, "wrec");
     p->d_wden = wsptr<double>(p, "wden");
@@ -859,7 +892,7 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
         for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
             const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
             if (p->dim == 2)
-                HIPCHK(p, launch_sweep2d<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt, p->na_oct,
+                HIPCHK(p, launch_sweep2d<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items2, i0, cnt, p->na_oct,
                                             p->nchunk_oct, p->part, s));
             else
                 HIPCHK(p, launch_sweep_tile<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt, p->tdim,

@@ -73,6 +73,18 @@ struct SweepItem {
     int film, oct, chunk, tile;
 };
 
+// Self-contained work item of the two-dimensional sweep: the tile frame and
+// the geometry constants it needs, so that a block reaches its stencil
+// loads after a single dependent load.
+struct Sweep2Item {
+    int oct, chunk, film, flags;   // flags: bit0/1 periodic x/y, bit2/3 octant sign of x/y positive
+    int o0, o1, e0, e1;            // tile origin and extent (cells) in the geometry
+    int n0, n1, cell0, pad;        // geometry size and first cell
+    double pdT0, pdT1;             // periodic temperature drops along x, y
+    double h0, h1, ih0, ih1;       // cell size and inverse along x, y
+    double wallT[4];               // thermalizing wall temperatures minus T_ref, faces -x, +x, -y, +y
+};
+
 // One work item of the transient step: a tile of one geometry for every lane of one octant.
 struct TileItem {
     int film, oct, tile, pad;

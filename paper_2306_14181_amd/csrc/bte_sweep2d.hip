@@ -28,50 +28,28 @@ struct Frame2 {
     double pdT0, pdT1;
 };
 
-__device__ inline Frame2 frame2(const Film &fm, int sg0, int sg1, int tile)
+__device__ inline Frame2 frame2(const Sweep2Item &it)
 {
     Frame2 F;
-    F.n0 = fm.n[0];
-    F.n1 = fm.n[1];
-    const int nt0 = (F.n0 + kTX - 1) / kTX;
-    const int tc0 = tile % nt0, tc1 = tile / nt0;
-    F.o0 = tc0 * kTX;
-    F.o1 = tc1 * kTY;
-    F.e0 = min(kTX, F.n0 - F.o0);
-    F.e1 = min(kTY, F.n1 - F.o1);
-    F.sg0 = sg0;
-    F.sg1 = sg1;
-    F.cell0 = fm.cell0;
-    F.per0 = fm.periodic[0];
-    F.per1 = fm.periodic[1];
-    F.pdT0 = fm.pdT[0];
-    F.pdT1 = fm.pdT[1];
+    F.o0 = it.o0;
+    F.o1 = it.o1;
+    F.e0 = it.e0;
+    F.e1 = it.e1;
+    F.n0 = it.n0;
+    F.n1 = it.n1;
+    F.cell0 = it.cell0;
+    F.per0 = it.flags & 1;
+    F.per1 = (it.flags >> 1) & 1;
+    F.sg0 = (it.flags & 4) ? 1 : -1;
+    F.sg1 = (it.flags & 8) ? 1 : -1;
+    F.pdT0 = it.pdT0;
+    F.pdT1 = it.pdT1;
     return F;
 }
 
-// Global cell of flow position (f0, f1) and the periodic jump of the value
-// there (units of C/4pi); -1 outside a non-periodic domain or in a pore.
-__device__ inline int cell2(const Dev &d, const Frame2 &F, int f0, int f1, double &jump)
-{
-    int i0 = F.o0 + (F.sg0 > 0 ? f0 : F.e0 - 1 - f0);
-    int i1 = F.o1 + (F.sg1 > 0 ? f1 : F.e1 - 1 - f1);
-    jump = 0.0;
-    if (i0 < 0 || i0 >= F.n0) {
-        if (!F.per0) return -1;
-        jump += (i0 < 0 ? 1.0 : -1.0) * F.pdT0;   // the low face adds +C dT/4pi
-        i0 = ((i0 % F.n0) + F.n0) % F.n0;
-    }
-    if (i1 < 0 || i1 >= F.n1) {
-        if (!F.per1) return -1;
-        jump += (i1 < 0 ? 1.0 : -1.0) * F.pdT1;
-        i1 = ((i1 % F.n1) + F.n1) % F.n1;
-    }
-    const int c = F.cell0 + i0 + F.n0 * i1;
-    return (d.code[c] & kSolidBit) ? c : -1;
-}
-
-// Same without the pore test: the cell at (f0, f1) whatever it holds (its
-// value is only used where the codes of the neighbours say it is solid).
+// The cell at flow position (f0, f1) whatever it holds (its value is only
+// used where the codes of the neighbours say it is solid) and the periodic
+// jump of the value there (units of C/4pi); -1 outside a non-periodic domain.
 __device__ inline int cell2_any(const Frame2 &F, int f0, int f1, double &jump)
 {
     int i0 = F.o0 + (F.sg0 > 0 ? f0 : F.e0 - 1 - f0);
@@ -79,7 +57,7 @@ __device__ inline int cell2_any(const Frame2 &F, int f0, int f1, double &jump)
     jump = 0.0;
     if (i0 < 0 || i0 >= F.n0) {
         if (!F.per0) return -1;
-        jump += (i0 < 0 ? 1.0 : -1.0) * F.pdT0;
+        jump += (i0 < 0 ? 1.0 : -1.0) * F.pdT0;   // the low face adds +C dT/4pi
         i0 = i0 < 0 ? i0 + F.n0 : i0 - F.n0;
         if (i0 < 0 || i0 >= F.n0) i0 = ((i0 % F.n0) + F.n0) % F.n0;
     }
@@ -119,15 +97,6 @@ __device__ inline double rl(double v, int lane)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// value of the lane's element at a broadcast cell c (with correction x in
-// units of C/4pi), 0 if c < 0
-template <typename T>
-__device__ inline T ldc(const T *__restrict__ e, int c, int nk, int k, bool active, T C4, double x)
-{
-    if (c < 0 || !active) return (T)0;
-    return e[(size_t)c * nk + k] + C4 * (T)x;
-}
-
 }  // namespace
 
 // Limited or least-squares slope difference of the fast path: face value
@@ -140,71 +109,89 @@ __device__ inline T delta_fast(T e2, T e1, T ec, T ed)
     return d1 + (T)0.5 * (lim_diff<T, LIM>(d1, d2) - lim_diff<T, LIM>(d0, d1));
 }
 
-// General face-value difference of one axis (missing neighbours, walls).
+// Face-value difference of one axis on the general path (missing
+// neighbours, walls).  fin_wall is the inflow face value when the upwind
+// side is a wall (thermalizing, diffuse: prepared by the caller); a specular
+// wall reads the mirror lane here.
 template <typename T, int LIM>
-__device__ inline T delta_general(const Dev &d, const Film &fm, const T *__restrict__ e,
-                                  const double *__restrict__ din, int c, uint32_t code, int a, int sg, bool hu,
-                                  bool hu2, bool hd, T e2, T e1, T ec, T ed, int cd, double xd, double xc, int al,
-                                  int l, int k, bool active, T C4, T hh, T ih, int nk)
+__device__ inline T delta_general(const Dev &d, const T *__restrict__ e, int c, uint32_t code, int a, int sg,
+                                  bool hu, bool hu2, bool hd, T e2, T e1, T ec, T ed, T fin_wall, int cd, double xd,
+                                  double xc, int al, int l, bool active, T C4, T hh, T ih, int nk)
 {
     const T fout = ec + hh * slope_flow<T>(LIM, hu, hd, e1, ec, ed, ih);
     T fin;
     if (hu) {
         fin = e1 + hh * slope_flow<T>(LIM, hu2, true, e2, e1, ec, ih);
+    } else if (side_wall(axis_bits(code, a), -sg) == 1) {
+        // specular: outgoing face value of the mirror direction, whose
+        // upwind side is this lane's downwind side
+        const int km = d.mirror[a * d.na + al] * d.nl + l;
+        const T em = active ? e[(size_t)c * nk + km] + C4 * (T)xc : (T)0;
+        T gm = (T)0;
+        if (LIM == LIM_NONE && hd && active) gm = (em - (e[(size_t)cd * nk + km] + C4 * (T)xd)) * ih;
+        fin = em + hh * gm;
     } else {
-        const int su = -sg;
-        const int kind = side_wall(axis_bits(code, a), su);
-        if (kind == 0) {
-            const double Tw = side_outer(code, a, su) ? fm.wallT[face_of(a, su)] : d.poreT;
-            fin = C4 * (T)Tw;
-        } else if (kind == 1) {
-            const int km = d.mirror[a * d.na + al] * d.nl + l;
-            const T em = active ? e[(size_t)c * nk + km] + C4 * (T)xc : (T)0;
-            T gm = (T)0;
-            if (LIM == LIM_NONE && hd && active) gm = (em - (e[(size_t)cd * nk + km] + C4 * (T)xd)) * ih;
-            fin = em + hh * gm;
-        } else {
-            const int rec = diffuse_index(d, c, code, face_of(a, su));
-            fin = (T)din[(size_t)rec * d.nl + l];
-        }
+        fin = fin_wall;
     }
-    (void)k;
     return fout - fin;
+}
+
+// Number of diffuse-wall records of a cell that precede face f (records are
+// numbered cell by cell in face order -x, +x, -y, +y).
+__device__ inline int diffuse_rank2(uint32_t code, int f)
+{
+    int n = 0;
+    for (int g = 0; g < f; ++g) {
+        const uint32_t ab = axis_bits(code, g >> 1);
+        const int side = (g & 1) ? 1 : -1;
+        n += (!side_is_cell(ab, side) && side_wall(ab, side) == 2) ? 1 : 0;
+    }
+    return n;
 }
 
 // Per tile cell mode word (built once per wave, read as a uniform value)
 enum : uint32_t {
     W_SOLID = 1u, W_FX = 2u, W_FY = 4u,        // solid; interior stencil along x / y
     W_CX = 8u, W_CY = 16u,                     // implicit coupling to the upwind cell along x / y
-    W_HU20 = 32u, W_HU21 = 64u                 // second upwind cell exists along x / y
+    W_HU20 = 32u, W_HU21 = 64u,                // second upwind cell exists along x / y
+    W_DX = 128u, W_DY = 256u                   // diffuse wall on the upwind side along x / y
 };
 
 template <typename T, int LIM>
 __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
                                                  const double *__restrict__ dpend, const double *__restrict__ TLdev,
                                                  const double *__restrict__ din,
-                                                 const SweepItem *__restrict__ items, int item0, int na_oct,
+                                                 const Sweep2Item *__restrict__ items, int item0, int na_oct,
                                                  int nchunk_oct, double *__restrict__ part)
 {
     __shared__ double lc[64][kMomN + 1];
-    __shared__ T dls[kTY][kTX][64];      // increments of each row (upwind recurrence hand-off)
-    __shared__ T xs[kTY][kTX][64];       // new values of each row (moment reduction)
-    const SweepItem it = items[item0 + blockIdx.x];
-    const Film &fm = d.film[it.film];
+    // per tile row: [0] increments of the row (upwind recurrence hand-off),
+    // [1] new values of the row (moment reduction).  Before the recurrence
+    // the row's wavefront uses both halves to stage diffuse-wall inflow
+    // values, slot 2 x + axis.
+    __shared__ T rowbuf[kTY][2][kTX][64];
+    const Sweep2Item it = items[item0 + blockIdx.x];
     const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;   // wavefront r owns tile row r
-    const int kbeg = it.oct * na_oct * d.nl, kend = kbeg + na_oct * d.nl;
+    const int nl = d.nl, nk = d.nk;
+    const int kbeg = it.oct * na_oct * nl, kend = kbeg + na_oct * nl;
     const int k = kbeg + it.chunk * 64 + lane;
     const bool active = k < kend;
-    const int nk = d.nk;
-    const LaneT<T> L = lane_make<T>(d, fm, active ? k : kbeg);
+    const int kk = active ? k : kbeg;
+    const int al = kk / nl, l = kk - al * nl;
+    // lane constants (direction al, band l)
+    const double wq = d.w[al], vq = d.v[l], itq = d.itau[l];
+    const double s0 = d.s[3 * al], s1 = d.s[3 * al + 1], s2 = d.s[3 * al + 2];
+    const T C4 = (T)d.C4[l], itau = (T)itq;
+    const T cp0 = (T)(vq * fabs(s0) * it.ih0), cp1 = (T)(vq * fabs(s1) * it.ih1);
+    const T hh0 = (T)(0.5 * it.h0), hh1 = (T)(0.5 * it.h1), ih0 = (T)it.ih0, ih1 = (T)it.ih1;
     if (r == 0) {
-        lc[lane][0] = active ? L.w : 0.0;
-        lc[lane][1] = active ? L.witau : 0.0;
-        lc[lane][2] = active ? L.wv[0] : 0.0;
-        lc[lane][3] = active ? L.wv[1] : 0.0;
-        lc[lane][4] = active ? L.wv[2] : 0.0;
+        lc[lane][0] = active ? wq : 0.0;
+        lc[lane][1] = active ? wq * itq : 0.0;
+        lc[lane][2] = active ? wq * vq * s0 : 0.0;
+        lc[lane][3] = active ? wq * vq * s1 : 0.0;
+        lc[lane][4] = active ? wq * vq * s2 : 0.0;
     }
-    const Frame2 F = frame2(fm, octant_sign(d, it.oct, na_oct, 0), octant_sign(d, it.oct, na_oct, 1), it.tile);
+    const Frame2 F = frame2(it);
     const int e0 = F.e0, e1 = F.e1;
     const int sg0 = F.sg0, sg1 = F.sg1;
     const int sx = sg0 > 0 ? 1 : -1;
@@ -215,8 +202,10 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     // ---- cell records, one cell per lane (every wavefront builds the same),
     // broadcast with readlane: tile cell t = f0 + 8 f1 in lane t; halo cell
     // h (see halo_pos) in lane h.  Indices are arithmetic, so the stencil
-    // loads below need no record; the per-cell loads are one parallel batch
-    // and the second-upwind flags come from the neighbouring lanes' codes.
+    // loads below need no record; every load of the block depends on the
+    // work item only and is issued unconditionally (a missing cell reads the
+    // zero row, an absent field a zero), so the whole batch is in flight at
+    // once: a load under a branch is waited for before the branch joins.
     int t_c = -1, h_c = -1;
     double h_j = 0;
     {
@@ -227,8 +216,8 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     }
     // raw stencil values of this wavefront's row window, issued first (the
     // row index is clamped for wavefronts past the tile: loaded, unused)
-    const int kk = active ? k : kbeg;
     const T *zrow = static_cast<const T *>(d.zrow);
+    const double *zd = static_cast<const double *>(d.zrow);
     const int rr = myrow ? r : e1 - 1;
     auto row_c = [&](int q, int j) -> int {
         if (q >= 0 && q < e1) return j < e0 ? cbase + rowstep * q + sx * j : -1;
@@ -253,22 +242,16 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     T xh0 = ldc(ein, cx0), xh1 = ldc(ein, cx1), xh2 = ldc(ein, cx2);
     const T dxr = ldc(eout, cx1);
 
-    uint32_t t_code = 0, h_code = 0;
-    double t_xd = 0, t_tld = 0, t_gamd = 0, t_qsd = 0, h_xd = 0;
-    if (t_c >= 0) {
-        t_code = d.code[t_c];
-        t_xd = dpend ? dpend[t_c] : 0.0;
-        t_tld = TLdev ? TLdev[t_c] : 0.0;
-        t_gamd = d.gamma[t_c];
-        t_qsd = d.P ? d.P[t_c] : 0.0;   // P is null without a heat source
-    }
-    if (h_c >= 0) {
-        h_code = d.code[h_c];
-        h_xd = dpend ? dpend[h_c] : 0.0;
-    }
-    auto rlt = [&](T v, int l) -> T {
-        if constexpr (sizeof(T) == 4) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-        else return rl((double)v, l);
+    const int tcl = t_c >= 0 ? t_c : F.cell0, hcl = h_c >= 0 ? h_c : F.cell0;
+    const uint32_t t_code = t_c >= 0 ? d.code[tcl] : 0u, h_code = h_c >= 0 ? d.code[hcl] : 0u;
+    const double t_xd = *(dpend ? dpend + tcl : zd), h_xd = *(dpend ? dpend + hcl : zd);
+    const double t_tld = *(TLdev ? TLdev + tcl : zd);
+    const double t_gamd = d.gamma[tcl];
+    const double t_qsd = *(d.P ? d.P + tcl : zd);   // P is null without a heat source
+    const int t_db = d.dbase[tcl];
+    auto rlt = [&](T v, int q) -> T {
+        if constexpr (sizeof(T) == 4) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
+        else return rl((double)v, q);
     };
     // mode words (needs the codes of the upwind neighbours: lanes t - 1 /
     // t - 8 of the tile, or the x-halo / row -1 halo lanes)
@@ -294,6 +277,8 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
             if (hu21 && side_is_cell(ab1, sg1)) w |= W_FY;
             if (hu0 && !side_wraps(ab0, -sg0)) w |= W_CX;
             if (hu1 && !side_wraps(ab1, -sg1)) w |= W_CY;
+            if (!hu0 && side_wall(ab0, -sg0) == 2) w |= W_DX;
+            if (!hu1 && side_wall(ab1, -sg1) == 2) w |= W_DY;
             t_w = w;
         }
         const bool sol = t_w & W_SOLID;
@@ -303,17 +288,47 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
         t_x = sol ? (T)t_xd : (T)0;
         h_x = (T)(h_xd + h_j);
     }
-    const T C4 = L.C4, cp0 = L.cpl[0], cp1 = L.cpl[1];
-    const T A0 = cp0 + cp1 + L.itau;
-    // Loads are unconditional: a missing cell reads the zero row (and has no
-    // correction), an inactive lane reads a valid element that is never
-    // stored.  A load under a branch would be waited for before the branch
-    // joins, one memory latency per load.
-    // correction of row q (-2 .. e1) at x position j (0 .. 7)
+    const T A0 = cp0 + cp1 + itau;
     auto row_x = [&](int q, int j) -> T {
         if (q >= 0 && q < e1) return rlt(t_x, 8 * q + j);
         return rlt(h_x, q == -2 ? j : (q == -1 ? 8 + j : 16 + j));
     };
+    T *wl = &rowbuf[r][0][0][0];   // diffuse inflow staging of this row: slot 2 j + a
+
+    // ---- diffuse-wall inflow values of this row, in groups of eight loads
+    // in flight (rows without such walls skip this)
+    if (myrow) {
+        const uint64_t bx = __ballot((t_w & W_DX) != 0), by = __ballot((t_w & W_DY) != 0);
+        uint32_t need = 0;
+#pragma unroll
+        for (int j = 0; j < kTX; ++j)
+            need |= (uint32_t)(((bx >> (8 * r + j)) & 1) << (2 * j)) | (uint32_t)(((by >> (8 * r + j)) & 1) << (2 * j + 1));
+        while (need) {
+            int sl[8];
+            const double *adr[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                sl[q] = -1;
+                adr[q] = zd + l;
+                if (need) {
+                    const int slot = __builtin_ctz(need);
+                    need &= need - 1;
+                    const int j = slot >> 1, a = slot & 1, t = 8 * r + j;
+                    const uint32_t code = (uint32_t)rl((int)t_code, t);
+                    const int f = face_of(a, a == 0 ? -sg0 : -sg1);
+                    const int rec = rl(t_db, t) + diffuse_rank2(code, f);
+                    sl[q] = slot;
+                    adr[q] = din + (size_t)rec * nl + l;
+                }
+            }
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = *adr[q];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (sl[q] >= 0) wl[sl[q] * 64 + lane] = (T)v[q];
+        }
+    }
 
     // ---- this wavefront's row: stencil rows, right-hand side (in parallel)
     T num[kTX], ec[kTX], rden[kTX];
@@ -331,6 +346,10 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
         xh1 += C4 * rlt(h_x, hx + 1);
         xh2 += C4 * rlt(h_x, hx + 2);
         dupx = dxr - xh1;
+        // thermalizing wall inflow per axis (upwind face of this octant)
+        const T Tw0 = C4 * (T)(sg0 > 0 ? it.wallT[0] : it.wallT[1]);
+        const T Tw1 = C4 * (T)(sg1 > 0 ? it.wallT[2] : it.wallT[3]);
+        const T Tp = C4 * (T)d.poreT;
 
 #pragma unroll
         for (int j = 0; j < kTX; ++j) {
@@ -350,12 +369,13 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
                     const uint32_t code = (uint32_t)rl((int)t_code, t);
                     const uint32_t ab0 = axis_bits(code, 0);
                     const bool hu0 = side_is_cell(ab0, -sg0), hd0 = side_is_cell(ab0, sg0);
-                    const bool hu20 = w & W_HU20;
                     const int cd = hd0 ? (j + 1 < e0 ? rl(t_c, t + 1) : cx2) : -1;
                     const double xd = j + 1 < e0 ? (double)rlt(t_x, t + 1) : (double)rlt(h_x, hx + 2);
-                    dx = delta_general<T, LIM>(d, fm, ein, din, c, code, 0, sg0, hu0, hu20, hd0, ex2, ex1, ec[j], exd,
-                                               cd, xd, (double)rlt(t_x, t), L.al, L.l, k, active, C4, L.hh[0],
-                                               L.ih[0], nk);
+                    T fw = (side_wall(ab0, -sg0) == 0) ? (side_outer(code, 0, -sg0) ? Tw0 : Tp) : (T)0;
+                    if (w & W_DX) fw = wl[(2 * j) * 64 + lane];
+                    dx = delta_general<T, LIM>(d, ein, c, code, 0, sg0, hu0, (w & W_HU20) != 0, hd0, ex2, ex1,
+                                               ec[j], exd, fw, cd, xd, (double)rlt(t_x, t), al, l, active, C4, hh0,
+                                               ih0, nk);
                 }
                 if (w & W_FY) {
                     dy = delta_fast<T, LIM>(ym2[j], ym1[j], ec[j], yp1[j]);
@@ -364,15 +384,16 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
                     const uint32_t code = (uint32_t)rl((int)t_code, t);
                     const uint32_t ab1 = axis_bits(code, 1);
                     const bool hu1 = side_is_cell(ab1, -sg1), hd1 = side_is_cell(ab1, sg1);
-                    const bool hu21 = w & W_HU21;
                     const int cd = hd1 ? row_c(r + 1, j) : -1;
                     const double xd = (double)row_x(r + 1, j);
-                    dy = delta_general<T, LIM>(d, fm, ein, din, c, code, 1, sg1, hu1, hu21, hd1, ym2[j], ym1[j], ec[j],
-                                               yp1[j], cd, xd, (double)rlt(t_x, t), L.al, L.l, k, active, C4,
-                                               L.hh[1], L.ih[1], nk);
+                    T fw = (side_wall(ab1, -sg1) == 0) ? (side_outer(code, 1, -sg1) ? Tw1 : Tp) : (T)0;
+                    if (w & W_DY) fw = wl[(2 * j + 1) * 64 + lane];
+                    dy = delta_general<T, LIM>(d, ein, c, code, 1, sg1, hu1, (w & W_HU21) != 0, hd1, ym2[j],
+                                               ym1[j], ec[j], yp1[j], fw, cd, xd, (double)rlt(t_x, t), al, l, active,
+                                               C4, hh1, ih1, nk);
                 }
                 const T gam = rlt(t_gam, t);
-                const T itc = L.itau + gam;
+                const T itc = itau + gam;
                 num[j] = -(cp0 * dx + cp1 * dy) - (ec[j] - C4 * rlt(t_tl, t)) * itc + C4 * rlt(t_qs, t);
                 const T den = A0 + gam;
                 if constexpr (sizeof(T) == 4) rden[j] = __builtin_amdgcn_rcpf(den);
@@ -381,46 +402,49 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
         }
     }
 
-    // ---- upwind recurrence, row after row (the only serial part)
+    // ---- upwind recurrence, row after row (the only serial part): the
+    // increments of the row upwind are read before the chain starts; pores
+    // and cells past the tile edge have zero right-hand side and factor
     T dlt[kTX];
     for (int s = 0; s < e1; ++s) {
         if (r == s) {
+            const int sp = s > 0 ? s - 1 : 0;
+            T up[kTX];
+#pragma unroll
+            for (int j = 0; j < kTX; ++j) {
+                const T u = rowbuf[sp][0][j][lane];
+                up[j] = s > 0 ? u : dpr0[j];
+            }
             T dl = dupx;   // increment of the upwind x neighbour
 #pragma unroll
             for (int j = 0; j < kTX; ++j) {
-                const uint32_t w = (uint32_t)rl((int)t_w, 8 * r + j);
-                T dv = (T)0;
-                if (w & W_SOLID) {
-                    T nm = num[j];
-                    if (w & W_CX) nm += cp0 * dl;
-                    if (w & W_CY) nm += cp1 * (s == 0 ? dpr0[j] : dls[s - 1][j][lane]);
-                    dv = nm * rden[j];
-                }
+                // selects, not zero factors: an uncoupled neighbour's value
+                // may be anything (across a periodic face it is the other
+                // buffer, not yet written in this sweep)
+                const uint32_t w = (uint32_t)rl((int)t_w, 8 * s + j);
+                const T tx = (w & W_CX) ? cp0 * dl : (T)0, ty = (w & W_CY) ? cp1 * up[j] : (T)0;
+                const T dv = (num[j] + tx + ty) * rden[j];
                 dl = dv;
                 dlt[j] = dv;
-                dls[s][j][lane] = dv;
+                rowbuf[s][0][j][lane] = dv;
             }
         }
         __syncthreads();
     }
 
-    // ---- new values, moment partials of the row
+    // ---- new values, moment partials of the row (a pore cell keeps its
+    // value: its increment is zero and it has no correction)
     if (myrow) {
         const int b = cbase + rowstep * r;
+        T *xs = &rowbuf[r][1][0][0];
 #pragma unroll
         for (int j = 0; j < kTX; ++j) {
             T en = (T)0;
             if (j < e0) {
-                const int c = b + sx * j;
-                const uint32_t w = (uint32_t)rl((int)t_w, 8 * r + j);
-                if (w & W_SOLID) {
-                    en = ec[j] + dlt[j];
-                    if (active) eout[(size_t)c * nk + k] = en;
-                } else if (active) {
-                    eout[(size_t)c * nk + k] = ein[(size_t)c * nk + k];
-                }
+                en = ec[j] + dlt[j];
+                if (active) eout[(size_t)(b + sx * j) * nk + k] = en;
             }
-            xs[r][j][lane] = active ? en : (T)0;
+            xs[j * 64 + lane] = active ? en : (T)0;
         }
         // lane = 8 cell + part: part sums 8 of the 64 lanes
         const int j = lane >> 3, p = lane & 7;
@@ -428,7 +452,7 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int l2 = 8 * p + q;
-            const double x = (double)xs[r][j][l2];
+            const double x = (double)xs[j * 64 + l2];
 #pragma unroll
             for (int m = 0; m < kMomN; ++m) acc[m] += lc[l2][m] * x;
         }
@@ -443,11 +467,12 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
         const int t = 8 * r + j;
         const int c = __shfl(t_c, t, 64);
         const uint32_t w = (uint32_t)__shfl((int)t_w, t, 64);
+        const double gm = __shfl(t_gamd, t, 64);
         if (p == 0 && j < e0 && c >= 0) {
             double *o = part + ((size_t)(it.oct * nchunk_oct + it.chunk) * d.nc + c) * kMomN;
             const bool sol = w & W_SOLID;
             o[0] = sol ? acc[0] : 0.0;
-            o[1] = sol ? acc[1] + d.gamma[c] * acc[0] : 0.0;
+            o[1] = sol ? acc[1] + gm * acc[0] : 0.0;
             o[2] = sol ? acc[2] : 0.0;
             o[3] = sol ? acc[3] : 0.0;
             o[4] = sol ? acc[4] : 0.0;
@@ -457,7 +482,7 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
 
 template <typename T, int LIM>
 void sweep2d_launch(const Dev &d, const T *ein, T *eout, const double *dpend, const double *TLdev, const double *din,
-                    const SweepItem *items, int item0, int count, int na_oct, int nchunk_oct, double *part,
+                    const Sweep2Item *items, int item0, int count, int na_oct, int nchunk_oct, double *part,
                     hipStream_t s)
 {
     hipLaunchKernelGGL((k_sweep2d<T, LIM>), dim3(count), dim3(64 * kTY), 0, s, d, ein, eout, dpend, TLdev, din, items,
@@ -466,7 +491,7 @@ void sweep2d_launch(const Dev &d, const T *ein, T *eout, const double *dpend, co
 
 template <typename T>
 hipError_t launch_sweep2d(const Dev &d, const T *ein, T *eout, const double *dpend, const double *TLdev,
-                          const double *din, const SweepItem *items, int item0, int count, int na_oct,
+                          const double *din, const Sweep2Item *items, int item0, int count, int na_oct,
                           int nchunk_oct, double *part, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
@@ -481,10 +506,10 @@ hipError_t launch_sweep2d(const Dev &d, const T *ein, T *eout, const double *dpe
 }
 
 template hipError_t launch_sweep2d<float>(const Dev &, const float *, float *, const double *, const double *,
-                                          const double *, const SweepItem *, int, int, int, int, double *,
+                                          const double *, const Sweep2Item *, int, int, int, int, double *,
                                           hipStream_t);
 template hipError_t launch_sweep2d<double>(const Dev &, const double *, double *, const double *, const double *,
-                                           const double *, const SweepItem *, int, int, int, int, double *,
+                                           const double *, const Sweep2Item *, int, int, int, int, double *,
                                            hipStream_t);
 
 }  // namespace bte
