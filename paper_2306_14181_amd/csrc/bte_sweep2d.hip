@@ -99,6 +99,16 @@ __device__ inline double rl(double v, int lane)
 
 }  // namespace
 
+// Cross-lane move of a double inside a row of 16 lanes (DPP control CTRL).
+template <int CTRL>
+__device__ inline double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Limited or least-squares slope difference of the fast path: face value
 // difference f(i) - f(i-1) along the flow with all three neighbours present.
 template <typename T, int LIM>
@@ -141,10 +151,11 @@ __device__ inline T delta_general(const Dev &d, const T *__restrict__ e, int c, 
 __device__ inline int diffuse_rank2(uint32_t code, int f)
 {
     int n = 0;
-    for (int g = 0; g < f; ++g) {
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
         const uint32_t ab = axis_bits(code, g >> 1);
         const int side = (g & 1) ? 1 : -1;
-        n += (!side_is_cell(ab, side) && side_wall(ab, side) == 2) ? 1 : 0;
+        n += (g < f && !side_is_cell(ab, side) && side_wall(ab, side) == 2) ? 1 : 0;
     }
     return n;
 }
@@ -165,13 +176,22 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
                                                  int nchunk_oct, double *__restrict__ part)
 {
     __shared__ double lc[64][kMomN + 1];
-    // per tile row: [0] increments of the row (upwind recurrence hand-off),
-    // [1] new values of the row (moment reduction).  Before the recurrence
-    // the row's wavefront uses both halves to stage diffuse-wall inflow
-    // values, slot 2 x + axis.
-    __shared__ T rowbuf[kTY][2][kTX][64];
+    // Recurrence operands per tile row s and lane: sAA = right-hand side over
+    // the diagonal, sRXY[.][0] / [1] = coupling to the upwind x / y increment
+    // over the diagonal (zero where the face is not implicitly coupled), sX0 =
+    // increment of the x-upwind neighbour of the row's first cell, sY0 = the
+    // increments of the row upwind of row 0.  The recurrence overwrites sAA
+    // with the increments.  A row's sRXY area first stages its diffuse-wall
+    // inflow values (slot 2 x + axis) and last holds its new values for the
+    // moment reduction; only that row's wavefront touches it then.
+    __shared__ T sAA[kTY][64][kTX];
+    __shared__ T sRXY[kTY][2][64][kTX];
+    __shared__ T sX0[kTY][64];
+    __shared__ T sY0[64][kTX];
     const Sweep2Item it = items[item0 + blockIdx.x];
-    const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;   // wavefront r owns tile row r
+    // wavefront r owns tile row r (readfirstlane: r is known to be uniform,
+    // so everything derived from it stays scalar)
+    const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int nl = d.nl, nk = d.nk;
     const int kbeg = it.oct * na_oct * nl, kend = kbeg + na_oct * nl;
     const int k = kbeg + it.chunk * 64 + lane;
@@ -214,18 +234,32 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
         int h0, h1;
         if (halo_pos(F, lane, h0, h1)) h_c = cell2_any(F, h0, h1, h_j);
     }
-    // raw stencil values of this wavefront's row window, issued first (the
-    // row index is clamped for wavefronts past the tile: loaded, unused)
+    // cell records first (the mode words need them), then the raw stencil
+    // values of this wavefront's row window, which are waited for only when
+    // the right-hand side is formed (the row index is clamped for
+    // wavefronts past the tile: loaded, unused)
     const T *zrow = static_cast<const T *>(d.zrow);
     const double *zd = static_cast<const double *>(d.zrow);
+    const int tcl = t_c >= 0 ? t_c : F.cell0, hcl = h_c >= 0 ? h_c : F.cell0;
+    const uint32_t t_code = t_c >= 0 ? d.code[tcl] : 0u, h_code = h_c >= 0 ? d.code[hcl] : 0u;
+    const double t_xd = *(dpend ? dpend + tcl : zd), h_xd = *(dpend ? dpend + hcl : zd);
+    const double t_tld = *(TLdev ? TLdev + tcl : zd);
+    const double t_gamd = d.gamma[tcl];
+    const double t_qsd = *(d.P ? d.P + tcl : zd);   // P is null without a heat source
+    const int t_db = d.dbase[tcl];
     const int rr = myrow ? r : e1 - 1;
     auto row_c = [&](int q, int j) -> int {
-        if (q >= 0 && q < e1) return j < e0 ? cbase + rowstep * q + sx * j : -1;
-        return rl(h_c, q == -2 ? j : (q == -1 ? 8 + j : 16 + j));
+        const int tc = j < e0 ? cbase + rowstep * q + sx * j : -1;
+        const int hcv = rl(h_c, q == -2 ? j : (q == -1 ? 8 + j : 16 + j));
+        return (q >= 0 && q < e1) ? tc : hcv;
     };
+    // the row base is uniform and the lane offset a 32-bit byte count, so
+    // these are scalar-base loads with one offset register
+    const unsigned koff = (unsigned)kk * (unsigned)sizeof(T);
     auto ldc = [&](const T *base, int c) -> T {
-        const T *row = c >= 0 ? base + (size_t)c * nk : zrow;
-        return row[kk];
+        const bool ok = c >= 0;
+        const char *row = reinterpret_cast<const char *>((ok ? base : zrow) + (size_t)(ok ? c : 0) * nk);
+        return *reinterpret_cast<const T *>(row + koff);
     };
     T ym2[kTX], ym1[kTX], yp1[kTX], dr[kTX], ecr[kTX];
 #pragma unroll
@@ -242,13 +276,6 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     T xh0 = ldc(ein, cx0), xh1 = ldc(ein, cx1), xh2 = ldc(ein, cx2);
     const T dxr = ldc(eout, cx1);
 
-    const int tcl = t_c >= 0 ? t_c : F.cell0, hcl = h_c >= 0 ? h_c : F.cell0;
-    const uint32_t t_code = t_c >= 0 ? d.code[tcl] : 0u, h_code = h_c >= 0 ? d.code[hcl] : 0u;
-    const double t_xd = *(dpend ? dpend + tcl : zd), h_xd = *(dpend ? dpend + hcl : zd);
-    const double t_tld = *(TLdev ? TLdev + tcl : zd);
-    const double t_gamd = d.gamma[tcl];
-    const double t_qsd = *(d.P ? d.P + tcl : zd);   // P is null without a heat source
-    const int t_db = d.dbase[tcl];
     auto rlt = [&](T v, int q) -> T {
         if constexpr (sizeof(T) == 4) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
         else return rl((double)v, q);
@@ -290,10 +317,11 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     }
     const T A0 = cp0 + cp1 + itau;
     auto row_x = [&](int q, int j) -> T {
-        if (q >= 0 && q < e1) return rlt(t_x, 8 * q + j);
-        return rlt(h_x, q == -2 ? j : (q == -1 ? 8 + j : 16 + j));
+        const T tv = rlt(t_x, (8 * q + j) & 63);
+        const T hv = rlt(h_x, q == -2 ? j : (q == -1 ? 8 + j : 16 + j));
+        return (q >= 0 && q < e1) ? tv : hv;
     };
-    T *wl = &rowbuf[r][0][0][0];   // diffuse inflow staging of this row: slot 2 j + a
+    T *wl = &sRXY[r][0][0][0];   // diffuse inflow staging of this row: slot 2 j + a
 
     // ---- diffuse-wall inflow values of this row, in groups of eight loads
     // in flight (rows without such walls skip this)
@@ -305,11 +333,13 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
             need |= (uint32_t)(((bx >> (8 * r + j)) & 1) << (2 * j)) | (uint32_t)(((by >> (8 * r + j)) & 1) << (2 * j + 1));
         while (need) {
             int sl[8];
-            const double *adr[8];
+            const __attribute__((address_space(1))) double *adr[8];
+            const auto *gzd = (const __attribute__((address_space(1))) double *)zd;
+            const auto *gdin = (const __attribute__((address_space(1))) double *)din;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 sl[q] = -1;
-                adr[q] = zd + l;
+                adr[q] = gzd + l;
                 if (need) {
                     const int slot = __builtin_ctz(need);
                     need &= need - 1;
@@ -318,7 +348,7 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
                     const int f = face_of(a, a == 0 ? -sg0 : -sg1);
                     const int rec = rl(t_db, t) + diffuse_rank2(code, f);
                     sl[q] = slot;
-                    adr[q] = din + (size_t)rec * nl + l;
+                    adr[q] = gdin + (size_t)rec * nl + l;
                 }
             }
             double v[8];
@@ -400,43 +430,81 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
                 else rden[j] = (T)1 / den;
             }
         }
-    }
-
-    // ---- upwind recurrence, row after row (the only serial part): the
-    // increments of the row upwind are read before the chain starts; pores
-    // and cells past the tile edge have zero right-hand side and factor
-    T dlt[kTX];
-    for (int s = 0; s < e1; ++s) {
-        if (r == s) {
-            const int sp = s > 0 ? s - 1 : 0;
-            T up[kTX];
+        // recurrence operands of the row.  An uncoupled upwind increment is
+        // dropped by a select, not a zero factor: its value may be anything
+        // (across a periodic face it is the other buffer, not yet written in
+        // this sweep).
+        T aa[kTX], rxv[kTX], ryv[kTX];
 #pragma unroll
-            for (int j = 0; j < kTX; ++j) {
-                const T u = rowbuf[sp][0][j][lane];
-                up[j] = s > 0 ? u : dpr0[j];
-            }
-            T dl = dupx;   // increment of the upwind x neighbour
-#pragma unroll
-            for (int j = 0; j < kTX; ++j) {
-                // selects, not zero factors: an uncoupled neighbour's value
-                // may be anything (across a periodic face it is the other
-                // buffer, not yet written in this sweep)
-                const uint32_t w = (uint32_t)rl((int)t_w, 8 * s + j);
-                const T tx = (w & W_CX) ? cp0 * dl : (T)0, ty = (w & W_CY) ? cp1 * up[j] : (T)0;
-                const T dv = (num[j] + tx + ty) * rden[j];
-                dl = dv;
-                dlt[j] = dv;
-                rowbuf[s][0][j][lane] = dv;
-            }
+        for (int j = 0; j < kTX; ++j) {
+            const uint32_t w = (uint32_t)rl((int)t_w, 8 * r + j);
+            aa[j] = num[j] * rden[j];
+            rxv[j] = (w & W_CX) ? cp0 * rden[j] : (T)0;
+            ryv[j] = (w & W_CY) ? cp1 * rden[j] : (T)0;
+            if (r == 0) sY0[lane][j] = (w & W_CY) ? dpr0[j] : (T)0;
         }
-        __syncthreads();
+        const uint32_t w0 = (uint32_t)rl((int)t_w, 8 * r);
+#pragma unroll
+        for (int j = 0; j < kTX; ++j) {
+            sAA[r][lane][j] = aa[j];
+            sRXY[r][0][lane][j] = rxv[j];
+            sRXY[r][1][lane][j] = ryv[j];
+        }
+        sX0[r][lane] = (w0 & W_CX) ? dupx : (T)0;
     }
+    __syncthreads();
+
+    // ---- upwind recurrence over the tile (the only serial part), in one
+    // wavefront: dv(s, j) = aa + ry dv(s - 1, j) + rx dv(s, j - 1).  Only the
+    // x chain is serial (one FMA per cell); the next row's operands are read
+    // while the current row is chained.
+    if (r == 0) {
+        T up[kTX], a[kTX], x[kTX], y[kTX];
+#pragma unroll
+        for (int j = 0; j < kTX; ++j) {
+            up[j] = sY0[lane][j];
+            a[j] = sAA[0][lane][j];
+            x[j] = sRXY[0][0][lane][j];
+            y[j] = sRXY[0][1][lane][j];
+        }
+        T x0 = sX0[0][lane];
+        for (int q = 0; q < e1; ++q) {
+            const int qn = q + 1 < kTY ? q + 1 : q;
+            T na[kTX], nx[kTX], ny[kTX];
+#pragma unroll
+            for (int j = 0; j < kTX; ++j) {
+                na[j] = sAA[qn][lane][j];
+                nx[j] = sRXY[qn][0][lane][j];
+                ny[j] = sRXY[qn][1][lane][j];
+            }
+            const T nx0 = sX0[qn][lane];
+            T dl = x0;
+#pragma unroll
+            for (int j = 0; j < kTX; ++j) {
+                const T base = a[j] + y[j] * up[j];
+                dl = base + x[j] * dl;
+                up[j] = dl;
+            }
+#pragma unroll
+            for (int j = 0; j < kTX; ++j) {
+                sAA[q][lane][j] = up[j];
+                a[j] = na[j];
+                x[j] = nx[j];
+                y[j] = ny[j];
+            }
+            x0 = nx0;
+        }
+    }
+    __syncthreads();
+    T dlt[kTX];
+#pragma unroll
+    for (int j = 0; j < kTX; ++j) dlt[j] = sAA[r][lane][j];
 
     // ---- new values, moment partials of the row (a pore cell keeps its
     // value: its increment is zero and it has no correction)
     if (myrow) {
         const int b = cbase + rowstep * r;
-        T *xs = &rowbuf[r][1][0][0];
+        T *xs = &sRXY[r][0][0][0];
 #pragma unroll
         for (int j = 0; j < kTX; ++j) {
             T en = (T)0;
@@ -458,10 +526,12 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
         }
 #pragma unroll
         for (int m = 0; m < kMomN; ++m) {
+            // sum of the 8 lanes of a cell: quad butterflies, then the two
+            // quads of each half row (data-parallel-primitive moves, no LDS)
             double v = acc[m];
-            v += __shfl_xor(v, 1, 64);
-            v += __shfl_xor(v, 2, 64);
-            v += __shfl_xor(v, 4, 64);
+            v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+            v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+            v += dpp_f64<0x141>(v);   // row_half_mirror
             acc[m] = v;
         }
         const int t = 8 * r + j;
