@@ -159,7 +159,8 @@ struct bte_problem {
     double *cdif = nullptr, *ccor = nullptr, *ddif = nullptr, *dcor = nullptr;
     double *TL = nullptr, *TLkin = nullptr, *T0 = nullptr, *T1 = nullptr, *q0 = nullptr, *q1 = nullptr;
     double *r = nullptr, *delta = nullptr, *dpend = nullptr, *fmean = nullptr, *feps = nullptr;
-    double *cg_x = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr, *cg_diag = nullptr;
+    double *cg_x = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
+    double *cg_w0 = nullptr, *cg_w1 = nullptr, *cg_s1 = nullptr;
     double *cg_part = nullptr, *cg_scal = nullptr;
     double *din = nullptr, *part = nullptr;
     void *e2 = nullptr;
@@ -515,7 +516,7 @@ void plan_workspace(bte_problem *p)
     add("items2", sizeof(Sweep2Item) * p->items2.size());
     add("titems", sizeof(TileItem) * p->titems.size());
     for (const char *n : {"gamma", "P", "S", "TL", "TLkin", "T0", "T1", "q0", "q1", "r", "delta", "dpend", "cg_x",
-                          "cg_r", "cg_z", "cg_p", "cg_Ap", "cg_diag"})
+                          "cg_r", "cg_z", "cg_p", "cg_Ap", "cg_w0", "cg_w1", "cg_s1"})
         add(n, 8 * nc);
     add("kdif", 8 * 3 * nc);
     add("kcor", 8 * 3 * nc);
@@ -525,7 +526,7 @@ void plan_workspace(bte_problem *p)
     add("dcor", 8 * nc);
     add("fmean", 8 * p->nfilm);
     add("feps", 8 * 5 * p->nfilm);
-    add("cg_part", 8 * 4 * (size_t)((nc + kBlock - 1) / kBlock));
+    add("cg_part", 8 * 6 * (size_t)((nc + kBlock - 1) / kBlock));
     add("cg_scal", 8 * 16);
     add("din", 8 * (size_t)p->nw * p->nl);
     const int nchunk_stream = (p->nk + kBlock - 1) / kBlock;
@@ -724,7 +725,9 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     p->cg_z = wsptr<double>(p, "cg_z");
     p->cg_p = wsptr<double>(p, "cg_p");
     p->cg_Ap = wsptr<double>(p, "cg_Ap");
-    p->cg_diag = wsptr<double>(p, "cg_diag");
+    p->cg_w0 = wsptr<double>(p, "cg_w0");
+    p->cg_w1 = wsptr<double>(p, "cg_w1");
+    p->cg_s1 = wsptr<double>(p, "cg_s1");
     p->cg_part = wsptr<double>(p, "cg_part");
     p->cg_scal = wsptr<double>(p, "cg_scal");
     p->din = wsptr<double>(p, "din");
@@ -786,11 +789,13 @@ CgArgs cg_args(bte_problem *p, int corr)
     for (int l = 0; l < p->nl; ++l) cv += p->C4[l] * 4.0 * M_PI * p->v[l];
     for (int a = 0; a < 3; ++a) g.Hm[a] = cv * p->H[a] / (2.0 * M_PI);
     g.corr = corr;
-    g.r = p->cg_r;
-    g.z = p->cg_z;
     g.p = p->cg_p;
-    g.Ap = p->cg_Ap;
-    g.diag = p->cg_diag;
+    g.rb[0] = p->cg_r;
+    g.rb[1] = p->cg_z;
+    g.wb[0] = p->cg_w0;
+    g.wb[1] = p->cg_w1;
+    g.sb[0] = p->cg_Ap;
+    g.sb[1] = p->cg_s1;
     g.part = p->cg_part;
     g.scal = p->cg_scal;
     return g;
@@ -828,7 +833,7 @@ bool run_cg(bte_problem *p, int corr, double *b, double *x_out, double rtol, int
     CgArgs g = cg_args(p, corr);
     g.x = x_out;
     g.rtol2 = rtol * rtol;
-    // two launches per iteration, enqueued in chunks; between chunks the host
+    // one launch per iteration, enqueued in chunks; between chunks the host
     // reads the done flag (one synchronisation per chunk)
     launch_cg_begin(d, g, b, s);
     constexpr int kChunk = 64;

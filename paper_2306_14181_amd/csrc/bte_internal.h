@@ -97,9 +97,10 @@ struct CgArgs {
     const double *dg;       // [nc] diagonal (faces plus thermalizing walls)
     double Hm[3];           // wall emission conductance sum C v H_a/(2pi) (correction operator only)
     int corr;               // 1: correction operator, 0: heat diffusion
-    double *x, *r, *z, *p, *Ap, *diag;
-    double *part;           // [2][nblk][2] block partial sums
-    double *scal;           // [1] |b|^2, [2] p.Ap, [3] r.r, [5] done, [6] iterations, [7],[8] r.z by parity
+    double *x, *p;
+    double *rb[2], *wb[2], *sb[2];   // r, w = A r/diag and s = A p by iteration parity
+    double *part;           // [2][nblk][3] block partial sums by parity
+    double *scal;           // [1] |b|^2, [5] done, [6] iterations, [9] total iterations, [10..13] gamma, alpha by parity
     double rtol2;
 };
 

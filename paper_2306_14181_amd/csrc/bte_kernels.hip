@@ -362,22 +362,6 @@ __device__ inline double wall_cond(const Dev &d, const CgArgs &g, int c, int a, 
     return 1.0 / (1.0 / kd + 1.0 / g.Hm[a]);
 }
 
-// row c of L applied to x (x may be null: diagonal only), from the
-// precomputed face couplings and diagonal
-__device__ inline double lap_row(const Dev &d, const CgArgs &g, int c, const double *__restrict__ x, double *dg)
-{
-    const double di = g.dg[c];
-    if (dg) *dg = di;
-    if (!x) return 0.0;
-    double acc = di * x[c];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        const double cf = g.coef[f * d.nc + c];
-        if (cf != 0.0) acc -= cf * x[d.nb[f * d.nc + c]];
-    }
-    return acc;
-}
-
 // Face couplings and diagonal of the diffusion operator per unit volume:
 // harmonic-mean face conductivity k_f / h^2 between solid neighbours (periodic
 // faces wrap), a thermalizing wall adds its conductance / h to the diagonal,
@@ -411,170 +395,167 @@ __global__ void k_cg_coef(Dev d, CgArgs g, double *coef, double *dgo)
     dgo[c] = (code & kSolidBit) && diag > 0 ? diag : 1.0;
 }
 
-__device__ inline double blk_sum1(double v, double *sh)
+// ---- CG with one ordinary launch per iteration (Chronopoulos-Gear form of
+// Jacobi-preconditioned CG: the two inner products of an iteration come from
+// one reduction).  With u = r / diag, w = A u and s = A p:
+//   p_i = u_i + beta_i p_(i-1),  s_i = w_i + beta_i s_(i-1),
+//   x += alpha_i p_i,  r_(i+1) = r_i - alpha_i s_i,  w_(i+1) = A u_(i+1),
+//   gamma = r.u, delta = w.u (and r.r for the stopping test) of step i + 1,
+//   beta_(i+1) = gamma_(i+1) / gamma_i,
+//   alpha_(i+1) = gamma_(i+1) / (delta_(i+1) - beta_(i+1) gamma_(i+1) / alpha_i).
+// A u_(i+1) needs u_(i+1) at the neighbours: it is recomputed there from
+// r_i, w_i and s_(i-1), so r, w and s alternate between two buffers by
+// iteration parity.  The launch boundary is the grid-wide barrier (far
+// cheaper than a cooperative grid barrier on this part); every block reduces
+// the block partials of the previous launch itself, in the same fixed order,
+// so all blocks take the same decisions.
+// scal: [1] |b|^2, [5] done, [6] iterations of this solve, [9] iterations
+// accumulated, [10 + parity] gamma, [12 + parity] alpha.
+__device__ inline void part_sum3(const double *__restrict__ part, int n, double *sh, double &a, double &b, double &c)
 {
-    double a[1] = {v};
-    block_sum<1>(a, sh);
-    return a[0];
-}
-
-// ---- CG with ordinary launches (two per iteration).  The launch boundary
-// is the grid-wide barrier, which costs far less than a cooperative grid
-// barrier on this part.  Every block reduces the block partials of the
-// previous launch itself, in the same fixed order, so all blocks take the
-// same decisions.  Uses p_{k+1} = z + beta p_k and A p_{k+1} = A z + beta A p_k
-// so that one launch updates both.  scal: [1] |b|^2, [5] done, [6] iterations
-// of this solve, [7 + parity] r.z, [9] iterations accumulated.
-__device__ inline void part_sum2(const double *__restrict__ part, int n, double *sh, double &a, double &b)
-{
-    double v[2] = {0, 0};
+    double v[3] = {0, 0, 0};
     for (int i = threadIdx.x; i < n; i += kBlock) {
-        v[0] += part[2 * i];
-        v[1] += part[2 * i + 1];
+        v[0] += part[3 * i];
+        v[1] += part[3 * i + 1];
+        v[2] += part[3 * i + 2];
     }
-    block_sum<2>(v, sh);
+    block_sum<3>(v, sh);
     if (threadIdx.x == 0) {
         sh[0] = v[0];
         sh[1] = v[1];
+        sh[2] = v[2];
     }
     __syncthreads();
     a = sh[0];
     b = sh[1];
+    c = sh[2];
     __syncthreads();
 }
 
-__device__ inline void write_part2(double *part, double a, double b, double *sh)
+__device__ inline void write_part3(double *part, double a, double b, double c, double *sh)
 {
-    double v[2] = {a, b};
-    block_sum<2>(v, sh);
+    double v[3] = {a, b, c};
+    block_sum<3>(v, sh);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = v[0];
-        part[2 * blockIdx.x + 1] = v[1];
+        part[3 * blockIdx.x] = v[0];
+        part[3 * blockIdx.x + 1] = v[1];
+        part[3 * blockIdx.x + 2] = v[2];
     }
 }
 
-// x = 0, r = b, z = r / diag, p = z; partials (r.z, r.r) -> partB
+// x = 0, p = 0, s_(-1) = 0, r_0 = b (solid cells), w_0 = A (r_0 / diag);
+// partials (gamma, delta, r.r) of step 0
 __global__ __launch_bounds__(kBlock) void k_cg_start(Dev d, CgArgs g, const double *__restrict__ b)
 {
-    __shared__ double sh[16];
-    const int nthr = gridDim.x * kBlock;
-    double rz = 0, rr = 0;
+    __shared__ double sh[32];
+    const int nthr = gridDim.x * kBlock, nf = 2 * d.dim;
+    double ga = 0, de = 0, rr = 0;
     for (int c = blockIdx.x * kBlock + threadIdx.x; c < d.nc; c += nthr) {
+        const double dg = g.dg[c];
         const double rc = (d.code[c] & kSolidBit) ? b[c] : 0.0;
-        const double zc = rc / g.dg[c];
+        const double uc = rc / dg;
+        double acc = dg * uc;
+        for (int f = 0; f < nf; ++f) {
+            const double cf = g.coef[f * d.nc + c];
+            const int j = cf != 0.0 ? d.nb[f * d.nc + c] : c;   // coupled faces join solid cells
+            acc -= cf * (b[j] / g.dg[j]);
+        }
         g.x[c] = 0.0;
-        g.r[c] = rc;
-        g.z[c] = zc;
-        g.p[c] = zc;
-        rz += rc * zc;
+        g.p[c] = 0.0;
+        g.rb[0][c] = rc;
+        g.wb[0][c] = acc;
+        g.sb[1][c] = 0.0;
+        ga += rc * uc;
+        de += acc * uc;
         rr += rc * rc;
     }
-    write_part2(g.part + 2 * gridDim.x, rz, rr, sh);
+    write_part3(g.part, ga, de, rr, sh);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         g.scal[5] = 0.0;
         g.scal[6] = 0.0;
     }
 }
 
-// |b|^2 and r.z from partB; Ap = A p; partial p.Ap -> partA
-__global__ __launch_bounds__(kBlock) void k_cg_ap0(Dev d, CgArgs g)
+// step it: scalars from the partials of the previous launch, stopping test,
+// then the vector updates of step it and the partials of step it + 1
+__global__ __launch_bounds__(kBlock) void k_cg_iter(Dev d, CgArgs g, int it)
 {
-    __shared__ double sh[16];
-    const int nb = gridDim.x, nthr = nb * kBlock;
-    double rz, bn2;
-    part_sum2(g.part + 2 * nb, nb, sh, rz, bn2);
-    if (!(bn2 > 0.0) || !(rz > 0.0)) {
+    __shared__ double sh[32];
+    if (g.scal[5] != 0.0) return;
+    const int nb = gridDim.x, nthr = nb * kBlock, nf = 2 * d.dim;
+    const int cur = it & 1, nxt = cur ^ 1;
+    double ga, de, rr;
+    part_sum3(g.part + 3 * nb * cur, nb, sh, ga, de, rr);
+    const double bn2 = it == 0 ? rr : g.scal[1];
+    double alpha = 0.0, beta = 0.0;
+    bool stop = !(rr > g.rtol2 * bn2) || !(ga > 0.0);
+    if (!stop) {
+        if (it == 0) {
+            alpha = ga / de;
+        } else {
+            beta = ga / g.scal[10 + nxt];
+            alpha = ga / (de - beta * ga / g.scal[12 + nxt]);
+        }
+        stop = !(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta);
+    }
+    if (stop) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            g.scal[1] = bn2;
+            if (it == 0) g.scal[1] = bn2;
             g.scal[5] = 1.0;
         }
         return;
     }
-    double pap = 0;
+    const double *__restrict__ R = g.rb[cur];
+    const double *__restrict__ W = g.wb[cur];
+    const double *__restrict__ S = g.sb[nxt];   // s_(it-1)
+    double *__restrict__ RN = g.rb[nxt];
+    double *__restrict__ WN = g.wb[nxt];
+    double *__restrict__ SN = g.sb[cur];        // s_it
+    double gn = 0, dn = 0, rn2 = 0;
     for (int c = blockIdx.x * kBlock + threadIdx.x; c < d.nc; c += nthr) {
-        const double y = lap_row(d, g, c, g.p, nullptr);
-        g.Ap[c] = y;
-        pap += g.p[c] * y;
+        const double dg = g.dg[c];
+        const double uc = R[c] / dg;
+        const double pc = uc + beta * g.p[c];
+        const double sc = W[c] + beta * S[c];
+        g.p[c] = pc;
+        SN[c] = sc;
+        g.x[c] += alpha * pc;
+        const double rc = R[c] - alpha * sc;
+        RN[c] = rc;
+        const double un = rc / dg;
+        double acc = dg * un;
+        for (int f = 0; f < nf; ++f) {
+            const double cf = g.coef[f * d.nc + c];
+            const int j = cf != 0.0 ? d.nb[f * d.nc + c] : c;
+            const double uj = (R[j] - alpha * (W[j] + beta * S[j])) / g.dg[j];
+            acc -= cf * uj;
+        }
+        WN[c] = acc;
+        gn += rc * un;
+        dn += acc * un;
+        rn2 += rc * rc;
     }
-    write_part2(g.part, pap, 0.0, sh);
+    write_part3(g.part + 3 * nb * nxt, gn, dn, rn2, sh);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        g.scal[1] = bn2;
-        g.scal[7] = rz;
-    }
-}
-
-// alpha = r.z / p.Ap; x += alpha p; r -= alpha Ap; z = r / diag; partials (r.z, r.r) -> partB
-__global__ __launch_bounds__(kBlock) void k_cg_step_a(Dev d, CgArgs g, int it)
-{
-    __shared__ double sh[16];
-    if (g.scal[5] != 0.0) return;
-    const int nb = gridDim.x, nthr = nb * kBlock;
-    double pap, unused;
-    part_sum2(g.part, nb, sh, pap, unused);
-    if (!(pap > 0.0)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) g.scal[5] = 1.0;
-        return;
-    }
-    const double alpha = g.scal[7 + (it & 1)] / pap;
-    double rz = 0, rr = 0;
-    for (int c = blockIdx.x * kBlock + threadIdx.x; c < d.nc; c += nthr) {
-        g.x[c] += alpha * g.p[c];
-        const double rc = g.r[c] - alpha * g.Ap[c];
-        const double zc = rc / g.dg[c];
-        g.r[c] = rc;
-        g.z[c] = zc;
-        rz += rc * zc;
-        rr += rc * rc;
-    }
-    write_part2(g.part + 2 * nb, rz, rr, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (it == 0) g.scal[1] = bn2;
+        g.scal[10 + cur] = ga;
+        g.scal[12 + cur] = alpha;
         g.scal[6] = it + 1;
         g.scal[9] += 1.0;
     }
 }
 
-// convergence test; beta = r.z_new / r.z; p = z + beta p; Ap = A z + beta Ap;
-// partial p.Ap -> partA
-__global__ __launch_bounds__(kBlock) void k_cg_step_b(Dev d, CgArgs g, int it)
-{
-    __shared__ double sh[16];
-    if (g.scal[5] != 0.0) return;
-    const int nb = gridDim.x, nthr = nb * kBlock;
-    double rz2, rr2;
-    part_sum2(g.part + 2 * nb, nb, sh, rz2, rr2);
-    if (rr2 <= g.rtol2 * g.scal[1] || !(rz2 > 0.0)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) g.scal[5] = 1.0;
-        return;
-    }
-    const double beta = rz2 / g.scal[7 + (it & 1)];
-    double pap = 0;
-    for (int c = blockIdx.x * kBlock + threadIdx.x; c < d.nc; c += nthr) {
-        const double pc = g.z[c] + beta * g.p[c];
-        const double y = lap_row(d, g, c, g.z, nullptr) + beta * g.Ap[c];
-        g.p[c] = pc;
-        g.Ap[c] = y;
-        pap += pc * y;
-    }
-    write_part2(g.part, pap, 0.0, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) g.scal[7 + ((it + 1) & 1)] = rz2;
-}
-
-int cg_blocks(const Dev &d) { return std::max(1, std::min(256, (d.nc + kBlock - 1) / kBlock)); }
+int cg_blocks(const Dev &d) { return std::max(1, std::min(1024, (d.nc + kBlock - 1) / kBlock)); }
 
 void launch_cg_begin(const Dev &d, const CgArgs &g, const double *b, hipStream_t s)
 {
-    const int nb = cg_blocks(d);
-    hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(kBlock), 0, s, d, g, b);
-    hipLaunchKernelGGL(k_cg_ap0, dim3(nb), dim3(kBlock), 0, s, d, g);
+    hipLaunchKernelGGL(k_cg_start, dim3(cg_blocks(d)), dim3(kBlock), 0, s, d, g, b);
 }
 
 void launch_cg_iters(const Dev &d, const CgArgs &g, int it0, int n, hipStream_t s)
 {
     const int nb = cg_blocks(d);
-    for (int it = it0; it < it0 + n; ++it) {
-        hipLaunchKernelGGL(k_cg_step_a, dim3(nb), dim3(kBlock), 0, s, d, g, it);
-        hipLaunchKernelGGL(k_cg_step_b, dim3(nb), dim3(kBlock), 0, s, d, g, it);
-    }
+    for (int it = it0; it < it0 + n; ++it) hipLaunchKernelGGL(k_cg_iter, dim3(nb), dim3(kBlock), 0, s, d, g, it);
 }
 
 // right-hand side of the heat-diffusion initial guess: P plus thermalizing
