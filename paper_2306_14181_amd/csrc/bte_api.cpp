@@ -49,6 +49,9 @@ template <typename T>
 hipError_t launch_sweep2d(const Dev &, const T *, T *, const double *, const double *, const double *,
                           const Sweep2Item *, int, int, int, int, double *, hipStream_t);
 template <typename T>
+hipError_t launch_transient3d(const Dev &, const T *, T *, const double *, const double *, const ColItem *, int, int,
+                              int, double, double, double *, hipStream_t);
+template <typename T>
 hipError_t launch_adj_step(const Dev &, const T *, T *, const T *, const double *, const double *, const TileItem *,
                            int, int3, int, int, int, double, double *, hipStream_t);
 void launch_adj_step_post(const Dev &, const double *, int, const double *, double *, double *, double,
@@ -142,6 +145,7 @@ struct bte_problem {
     std::vector<Sweep2Item> items2;   // two-dimensional sweep: self-contained items, same order
     std::vector<int> diag_off;
     std::vector<TileItem> titems;   // transient: (geometry, octant, tile)
+    std::vector<ColItem> citems;    // three-dimensional transient: (geometry, octant, chunk, column)
     int tile_cap = 0;               // star slots of a full tile
     int floating_any = 0, thermal_any = 0;
     // workspace
@@ -170,6 +174,7 @@ struct bte_problem {
     SweepItem *d_items = nullptr;
     Sweep2Item *d_items2 = nullptr;
     TileItem *d_titems = nullptr;
+    ColItem *d_citems = nullptr;
     int *d_wrec = nullptr;
     double *d_wden = nullptr;
     int npart_max = 0;
@@ -444,6 +449,14 @@ void build_schedule(bte_problem *p)
         for (int o = 0; o < p->noct; ++o)
             for (int t = 0; t < ntile; ++t) p->titems.push_back({f, o, t, 0});
     }
+    p->citems.clear();
+    if (p->dim == 3)
+        for (int f = 0; f < p->nfilm; ++f) {
+            const Film &fm = p->films[f];
+            for (int o = 0; o < p->noct; ++o)
+                for (int ch = 0; ch < p->nchunk_oct; ++ch)
+                    for (int col = 0; col < fm.n[0] * fm.n[1]; ++col) p->citems.push_back({f, o, ch, col});
+        }
     auto cap_of = [&](int3 td) {
         const int e[3] = {td.x, td.y, td.z};
         const int cells = e[0] * e[1] * e[2];
@@ -515,6 +528,7 @@ void plan_workspace(bte_problem *p)
     add("items", sizeof(SweepItem) * p->items.size());
     add("items2", sizeof(Sweep2Item) * p->items2.size());
     add("titems", sizeof(TileItem) * p->titems.size());
+    add("citems", sizeof(ColItem) * p->citems.size());
     for (const char *n : {"gamma", "P", "S", "TL", "TLkin", "T0", "T1", "q0", "q1", "r", "delta", "dpend", "cg_x",
                           "cg_r", "cg_z", "cg_p", "cg_Ap", "cg_w0", "cg_w1", "cg_s1"})
         add(n, 8 * nc);
@@ -672,6 +686,7 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     HIPCHK(p, up("items", p->items.data(), sizeof(SweepItem) * p->items.size()));
     if (!p->items2.empty()) HIPCHK(p, up("items2", p->items2.data(), sizeof(Sweep2Item) * p->items2.size()));
     HIPCHK(p, up("titems", p->titems.data(), sizeof(TileItem) * p->titems.size()));
+    if (!p->citems.empty()) HIPCHK(p, up("citems", p->citems.data(), sizeof(ColItem) * p->citems.size()));
     if (tile_smem_size(p->tile_cap, (int)p->esize(), 1) > 160 * 1024) FAIL(p, BTE_ERR_UNSUPPORTED, "tile LDS");
     HIPCHK(p, tile_kernels_init(160 * 1024));
     HIPCHK(p, adj_kernels_init(160 * 1024));
@@ -743,6 +758,7 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     p->d_items = wsptr<SweepItem>(p, "items");
     p->d_items2 = wsptr<Sweep2Item>(p, "items2");
     p->d_titems = wsptr<TileItem>(p, "titems");
+    p->d_citems = wsptr<ColItem>(p, "citems");
     p->d_wrec = wsptr<int>(p, "wrec");
     p->d_wden = wsptr<double>(p, "wden");
     // default fields: no source, no extra scattering
@@ -1003,12 +1019,20 @@ hipError_t one_step(bte_problem *p, const T *ein, T *eout, double src, hipEvent_
     if (ev && (r = hipEventRecord(ev[0], s)) != hipSuccess) return r;
     launch_walls<T>(d, ein, nullptr, p->d_wrec, p->d_wden, p->din, p->nw, s);
     if (ev && (r = hipEventRecord(ev[1], s)) != hipSuccess) return r;
-    if ((r = launch_transient_tile<T>(d, ein, eout, p->TL, p->din, p->d_titems, (int)p->titems.size(), p->tdim_tr,
-                                      p->na_oct, p->nchunk_oct, p->tile_cap_tr, src, p->ctl.dt, p->part, s)) !=
-        hipSuccess)
-        return r;
+    // three-dimensional geometries: column kernel, partials per (octant,
+    // chunk); otherwise the tile kernel, partials per octant
+    int np = p->noct;
+    if (p->dim == 3) {
+        r = launch_transient3d<T>(d, ein, eout, p->TL, p->din, p->d_citems, (int)p->citems.size(), p->na_oct,
+                                  p->nchunk_oct, src, p->ctl.dt, p->part, s);
+        np = p->noct * p->nchunk_oct;
+    } else {
+        r = launch_transient_tile<T>(d, ein, eout, p->TL, p->din, p->d_titems, (int)p->titems.size(), p->tdim_tr,
+                                     p->na_oct, p->nchunk_oct, p->tile_cap_tr, src, p->ctl.dt, p->part, s);
+    }
+    if (r != hipSuccess) return r;
     if (ev && (r = hipEventRecord(ev[2], s)) != hipSuccess) return r;
-    launch_finalize_tl(d, p->part, p->noct, p->TL, s);
+    launch_finalize_tl(d, p->part, np, p->TL, s);
     if (ev && (r = hipEventRecord(ev[3], s)) != hipSuccess) return r;
     return hipGetLastError();
 }

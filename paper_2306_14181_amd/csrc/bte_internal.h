@@ -85,6 +85,12 @@ struct Sweep2Item {
     double wallT[4];               // thermalizing wall temperatures minus T_ref, faces -x, +x, -y, +y
 };
 
+// One work item of the three-dimensional transient step: one (x, y) column
+// of a geometry (col = x + n_x y) for 64 lanes of one octant.
+struct ColItem {
+    int film, oct, chunk, col;
+};
+
 // One work item of the transient step: a tile of one geometry for every lane of one octant.
 struct TileItem {
     int film, oct, tile, pad;

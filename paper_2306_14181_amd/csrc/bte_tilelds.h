@@ -231,6 +231,26 @@ template <typename T, int LIM> __device__ inline T lim_diff(T dl, T dr)
     return dl * dr > (T)0 ? copysign(m, dl) : (T)0;
 }
 
+// Cross-lane move of a double inside a row of 16 lanes (DPP control CTRL).
+template <int CTRL>
+__device__ inline double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Limited or least-squares slope difference of the fast path: face value
+// difference f(i) - f(i-1) along the flow with all three neighbours present.
+template <typename T, int LIM>
+__device__ inline T delta_fast(T e2, T e1, T ec, T ed)
+{
+    if (LIM == LIM_NONE) return (ec - e1) + (T)0.25 * ((ed - e1) - (ec - e2));
+    const T d0 = e1 - e2, d1 = ec - e1, d2 = ed - ec;
+    return d1 + (T)0.5 * (lim_diff<T, LIM>(d1, d2) - lim_diff<T, LIM>(d0, d1));
+}
+
 // Lane constants of one (direction, band) lane.
 template <typename T> struct LaneT {
     int k, al, l;

@@ -1,0 +1,350 @@
+// bte_transient3d.hip -- explicit transient step (Sec. 4.1, the forward-Euler
+// second-order finite-volume update of the BTE) on three-dimensional
+// geometries.
+//
+// One wavefront per (x, y) column of cells, octant and chunk of 64
+// (direction, band) lanes.  The wavefront walks its column along z in the
+// flow direction of the octant, so the z stencil (two upwind cells, the
+// cell, the downwind cell) is a window of four registers that shifts by one
+// load per cell, and the limited z slope of the upwind cell is carried from
+// the previous cell.  The x and y neighbours are read from the cache
+// hierarchy: neighbouring columns are walked by neighbouring wavefronts of
+// the same XCD at the same time.  The cell itself is the same for all 64
+// lanes, so its geometry code, T_L, scattering rate and source are scalar
+// loads, issued one cell ahead like the stencil values.  The FP64 partial
+// sum w e/tau of the T_L update is reduced over the 64 lanes per cell and
+// written per (octant, chunk, cell).
+#include "bte_internal.h"
+#include "bte_stencil.h"
+#include "bte_tilelds.h"
+
+namespace bte {
+
+namespace {
+
+__device__ inline double rl_d(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wavefront (the same value in every lane):
+// butterflies inside each row of 16 lanes, then the four row sums.
+__device__ inline double wave_total(double v)
+{
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
+    return (rl_d(v, 0) + rl_d(v, 16)) + (rl_d(v, 32) + rl_d(v, 48));
+}
+
+// Position i along an axis of n cells: itself inside, the periodic image
+// outside (jump +1 past the low face, -1 past the high face, in units of
+// C dT / 4pi), -1 outside a non-periodic domain.
+__device__ inline int wrap_pos(int i, int n, int per, int &jump)
+{
+    jump = 0;
+    if (i >= 0 && i < n) return i;
+    if (!per) return -1;
+    jump = i < 0 ? 1 : -1;
+    const int r = i < 0 ? i + n : i - n;
+    return (r >= 0 && r < n) ? r : ((i % n) + n) % n;   // the modulo only for axes of one or two cells
+}
+
+// Face-value difference of one axis on the general path (missing
+// neighbours, walls): outgoing face value minus incoming face value, the
+// incoming one from the upwind cell or from the wall (thermalizing,
+// specular: the mirror direction's outgoing value, diffuse: the wall record).
+template <typename T, int LIM>
+__device__ inline T delta_wall3(const Dev &d, const Film &fm, const T *__restrict__ e, const double *__restrict__ din,
+                                int c, uint32_t code, int a, int sg, bool hu, bool hu2, bool hd, T e2, T e1, T ec,
+                                T ed, int cd, T xd, int al, int l, T C4, T hh, T ih)
+{
+    const T fout = ec + hh * slope_flow<T>(LIM, hu, hd, e1, ec, ed, ih);
+    T fin;
+    if (hu) {
+        fin = e1 + hh * slope_flow<T>(LIM, hu2, true, e2, e1, ec, ih);
+    } else {
+        const int su = -sg;
+        const int kind = side_wall(axis_bits(code, a), su);
+        if (kind == 0) {
+            const double Tw = side_outer(code, a, su) ? fm.wallT[face_of(a, su)] : d.poreT;
+            fin = C4 * (T)Tw;
+        } else if (kind == 1) {
+            const int km = d.mirror[a * d.na + al] * d.nl + l;
+            const T em = e[(size_t)c * d.nk + km];
+            T gm = (T)0;
+            if (LIM == LIM_NONE && hd) gm = (em - (e[(size_t)cd * d.nk + km] + xd)) * ih;
+            fin = em + hh * gm;
+        } else {
+            const int rec = diffuse_index(d, c, code, face_of(a, su));
+            fin = (T)din[(size_t)rec * d.nl + l];
+        }
+    }
+    return fout - fin;
+}
+
+}  // namespace
+
+template <typename T, int LIM>
+__global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
+                                                     const double *__restrict__ TLdev,
+                                                     const double *__restrict__ din,
+                                                     const ColItem *__restrict__ items, int nitems, int na_oct,
+                                                     int nchunk_oct, double src, double dt,
+                                                     double *__restrict__ part)
+{
+    // four wavefronts per block; logical blocks are contiguous per XCD so
+    // that neighbouring columns share an L2
+    const int nb = gridDim.x, bb = blockIdx.x;
+    const int lb = (bb & 7) * (nb >> 3) + (bb >> 3);
+    const int wi = lb * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wi >= nitems) return;
+    const int lane = threadIdx.x & 63;
+    const ColItem it = items[wi];
+    const Film &fm = d.film[it.film];
+    const int sg0 = octant_sign(d, it.oct, na_oct, 0), sg1 = octant_sign(d, it.oct, na_oct, 1),
+              sg2 = octant_sign(d, it.oct, na_oct, 2);
+    const int nl = d.nl, nk = d.nk, nc = d.nc;
+    const int kbeg = it.oct * na_oct * nl, kend = kbeg + na_oct * nl;
+    const int k = kbeg + it.chunk * 64 + lane;
+    const bool active = k < kend;
+    const int kk = active ? k : kbeg;
+    const LaneT<T> L = lane_make<T>(d, fm, kk);
+    const T C4 = L.C4;
+    const int n0 = fm.n[0], n1 = fm.n[1], n2 = fm.n[2], plane = n0 * n1;
+    const int x = it.col % n0, y = it.col / n0;
+    const int cb = fm.cell0 + x + n0 * y;   // cell of (x, y, 0)
+    const T *zrow = static_cast<const T *>(d.zrow);
+    const double *zd = static_cast<const double *>(d.zrow);
+    const unsigned koff = (unsigned)kk * (unsigned)sizeof(T);
+    // uniform row base, 32-bit lane offset; a missing cell reads the zero row
+    auto ld = [&](const T *base, int c) -> T {
+        const bool ok = c >= 0;
+        const char *row = reinterpret_cast<const char *>((ok ? base : zrow) + (size_t)(ok ? c : 0) * nk);
+        return *reinterpret_cast<const T *>(row + koff);
+    };
+
+    // x and y stencil columns (fixed along z): cell at z = 0 or -1, and the
+    // periodic jump of their values
+    int jx1, jx2, jxd, jy1, jy2, jyd;
+    const int px1 = wrap_pos(x - sg0, n0, fm.periodic[0], jx1), px2 = wrap_pos(x - 2 * sg0, n0, fm.periodic[0], jx2),
+              pxd = wrap_pos(x + sg0, n0, fm.periodic[0], jxd);
+    const int py1 = wrap_pos(y - sg1, n1, fm.periodic[1], jy1), py2 = wrap_pos(y - 2 * sg1, n1, fm.periodic[1], jy2),
+              pyd = wrap_pos(y + sg1, n1, fm.periodic[1], jyd);
+    const int bx1 = px1 >= 0 ? fm.cell0 + px1 + n0 * y : -1, bx2 = px2 >= 0 ? fm.cell0 + px2 + n0 * y : -1,
+              bxd = pxd >= 0 ? fm.cell0 + pxd + n0 * y : -1;
+    const int by1 = py1 >= 0 ? fm.cell0 + x + n0 * py1 : -1, by2 = py2 >= 0 ? fm.cell0 + x + n0 * py2 : -1,
+              byd = pyd >= 0 ? fm.cell0 + x + n0 * pyd : -1;
+    const T kx1 = C4 * (T)(jx1 * fm.pdT[0]), kx2 = C4 * (T)(jx2 * fm.pdT[0]), kxd = C4 * (T)(jxd * fm.pdT[0]);
+    const T ky1 = C4 * (T)(jy1 * fm.pdT[1]), ky2 = C4 * (T)(jy2 * fm.pdT[1]), kyd = C4 * (T)(jyd * fm.pdT[1]);
+    // cell of the column at flow index f (geometric z = f or n2 - 1 - f),
+    // -1 outside a non-periodic column; its jump in units of C dT / 4pi
+    auto zcell = [&](int f, int &jz) -> int {
+        const int zg = wrap_pos(sg2 > 0 ? f : n2 - 1 - f, n2, fm.periodic[2], jz);
+        return zg >= 0 ? cb + plane * zg : -1;
+    };
+    auto zval = [&](int f) -> T {
+        int jz;
+        const int c = zcell(f, jz);
+        return ld(ein, c) + C4 * (T)(jz * fm.pdT[2]);
+    };
+    auto plus = [](int base, int off) { return base >= 0 ? base + off : -1; };
+
+    // z window (flow order) with its jumps, and the geometry code of the
+    // z-upwind cell
+    T ez2 = zval(-2), ez1 = zval(-1), ec = zval(0), ezd = zval(1);
+    uint32_t code_zu = 0;
+    {
+        int jz;
+        const int cu = zcell(-1, jz);
+        const uint32_t v = d.code[cu >= 0 ? cu : cb];
+        code_zu = cu >= 0 ? v : 0u;
+    }
+    // limited z slope of the upwind cell (carried from cell to cell)
+    T lz_up = (LIM == LIM_NONE) ? (T)0 : lim_diff<T, LIM>(ez1 - ez2, ec - ez1);
+
+    const T tdt = (T)dt, tsrc = (T)src;
+    const T itau = L.itau;
+    const T cp0 = L.cpl[0], cp1 = L.cpl[1], cp2 = L.cpl[2];
+    double *__restrict__ pout = part + (size_t)(it.oct * nchunk_oct + it.chunk) * nc;
+
+    // Values prefetched one cell ahead: the six x / y neighbours of the
+    // next plane and the column value three cells downstream (it enters the
+    // window after the next cell).  Two sets alternate (the loop is unrolled
+    // by hand) so that no register copy has to wait for a load in flight.
+    struct Pre {
+        T nz, x1, x2, xd, y1, y2, yd;
+    };
+    // x / y neighbour rows of flow index 0 and the step between planes
+    // (absent neighbours: the zero row, step 0), advanced cell by cell
+    const long long zstep = (long long)(sg2 > 0 ? plane : -plane) * nk;
+    const int z0 = sg2 > 0 ? 0 : n2 - 1;
+    auto row0 = [&](int b) -> const T * { return b >= 0 ? ein + (size_t)(b + plane * z0) * nk : zrow; };
+    const T *rx1 = row0(bx1), *rx2 = row0(bx2), *rxd = row0(bxd);
+    const T *ry1 = row0(by1), *ry2 = row0(by2), *ryd = row0(byd);
+    const long long sx1 = bx1 >= 0 ? zstep : 0, sx2 = bx2 >= 0 ? zstep : 0, sxd = bxd >= 0 ? zstep : 0;
+    const long long sy1 = by1 >= 0 ? zstep : 0, sy2 = by2 >= 0 ? zstep : 0, syd = byd >= 0 ? zstep : 0;
+    const T *rc0 = ein + (size_t)(cb + plane * z0) * nk;   // the column's own row at flow index 0
+    auto at = [&](const T *row) -> T { return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(row) + koff); };
+    // loads for the cell after flow index f (x / y neighbours) and the
+    // column value at flow index f + 3
+    auto prefetch = [&](int f, Pre &q) {
+        const long long fn = f + 1 < n2 ? f + 1 : f;
+        q.x1 = at(rx1 + fn * sx1);
+        q.x2 = at(rx2 + fn * sx2);
+        q.xd = at(rxd + fn * sxd);
+        q.y1 = at(ry1 + fn * sy1);
+        q.y2 = at(ry2 + fn * sy2);
+        q.yd = at(ryd + fn * syd);
+        // inside the column: plain row; past its end (last three cells):
+        // periodic image with its jump, or zero
+        const T *rz;
+        T jz = (T)0;
+        if (f + 3 < n2) {
+            rz = rc0 + (long long)(f + 3) * zstep;
+        } else {
+            int j;
+            const int c = zcell(f + 3, j);
+            rz = c >= 0 ? ein + (size_t)c * nk : zrow;
+            jz = C4 * (T)(j * fm.pdT[2]);
+        }
+        q.nz = at(rz) + jz;
+    };
+    // Per-cell records, one cell of a run of 64 along the column per lane
+    // (unconditional loads: an absent neighbour reads the cell's own code
+    // and is masked), broadcast with readlane.
+    uint32_t r_code = 0, r_cxu = 0, r_cyu = 0;
+    double r_tl = 0, r_gam = 0, r_p = 0;
+    auto records = [&](int f0) {
+        const int fl = min(f0 + lane, n2 - 1);
+        const int o = plane * (sg2 > 0 ? fl : n2 - 1 - fl);
+        const int c = cb + o;
+        r_code = d.code[c];
+        const uint32_t cxu = d.code[bx1 >= 0 ? bx1 + o : c], cyu = d.code[by1 >= 0 ? by1 + o : c];
+        r_cxu = bx1 >= 0 ? cxu : 0u;
+        r_cyu = by1 >= 0 ? cyu : 0u;
+        r_tl = TLdev[c];
+        r_gam = d.gamma[c];
+        r_p = *(d.P ? d.P + c : zd);   // P is null without a heat source
+    };
+
+    auto step = [&](int f, const Pre &in, Pre &out) {
+        const int z = sg2 > 0 ? f : n2 - 1 - f;
+        const int zo = plane * z;
+        const int c = cb + zo;
+        prefetch(f, out);
+        const int q = f & 63;
+        const uint32_t code = (uint32_t)__builtin_amdgcn_readlane((int)r_code, q);
+        const uint32_t code_xu = (uint32_t)__builtin_amdgcn_readlane((int)r_cxu, q);
+        const uint32_t code_yu = (uint32_t)__builtin_amdgcn_readlane((int)r_cyu, q);
+        const double tl = rl_d(r_tl, q), gam = rl_d(r_gam, q);
+        const double qs = rl_d(r_p, q) / d.Ctot;
+        const bool solid = code & kSolidBit;
+        const T ex1 = in.x1 + kx1, ex2 = in.x2 + kx2, exd = in.xd + kxd;
+        const T ey1 = in.y1 + ky1, ey2 = in.y2 + ky2, eyd = in.yd + kyd;
+        // z slope of this cell (also the upwind slope of the next cell)
+        const T lz = (LIM == LIM_NONE) ? (T)0 : lim_diff<T, LIM>(ec - ez1, ezd - ec);
+        T en = ec;
+        double acc = 0.0;
+        if (solid) {
+            const uint32_t ab0 = axis_bits(code, 0), ab1 = axis_bits(code, 1), ab2 = axis_bits(code, 2);
+            const bool hu0 = side_is_cell(ab0, -sg0), hd0 = side_is_cell(ab0, sg0);
+            const bool hu1 = side_is_cell(ab1, -sg1), hd1 = side_is_cell(ab1, sg1);
+            const bool hu2 = side_is_cell(ab2, -sg2), hd2 = side_is_cell(ab2, sg2);
+            const bool hu20 = hu0 && side_is_cell(axis_bits(code_xu, 0), -sg0);
+            const bool hu21 = hu1 && side_is_cell(axis_bits(code_yu, 1), -sg1);
+            const bool hu22 = hu2 && side_is_cell(axis_bits(code_zu, 2), -sg2);
+            T dx, dy, dz;
+            if (hu0 && hu20 && hd0) {
+                dx = delta_fast<T, LIM>(ex2, ex1, ec, exd);
+            } else {
+                dx = delta_wall3<T, LIM>(d, fm, ein, din, c, code, 0, sg0, hu0, hu20, hd0, ex2, ex1, ec, exd,
+                                         plus(bxd, zo), kxd, L.al, L.l, C4, L.hh[0], L.ih[0]);
+            }
+            if (hu1 && hu21 && hd1) {
+                dy = delta_fast<T, LIM>(ey2, ey1, ec, eyd);
+            } else {
+                dy = delta_wall3<T, LIM>(d, fm, ein, din, c, code, 1, sg1, hu1, hu21, hd1, ey2, ey1, ec, eyd,
+                                         plus(byd, zo), kyd, L.al, L.l, C4, L.hh[1], L.ih[1]);
+            }
+            if (hu2 && hu22 && hd2) {
+                if (LIM == LIM_NONE) dz = delta_fast<T, LIM>(ez2, ez1, ec, ezd);
+                else dz = (ec - ez1) + (T)0.5 * (lz - lz_up);
+            } else {
+                int jd;
+                const int cdz = zcell(f + 1, jd);
+                dz = delta_wall3<T, LIM>(d, fm, ein, din, c, code, 2, sg2, hu2, hu22, hd2, ez2, ez1, ec, ezd, cdz,
+                                         C4 * (T)(jd * fm.pdT[2]), L.al, L.l, C4, L.hh[2], L.ih[2]);
+            }
+            const T D = cp0 * dx + cp1 * dy + cp2 * dz;
+            const T itc = itau + (T)gam;
+            en = ec + tdt * (-D - (ec - C4 * (T)tl) * itc + C4 * tsrc * (T)qs);
+            acc = active ? (L.witau + L.w * gam) * (double)en : 0.0;
+        }
+        if (active) eout[(size_t)c * nk + k] = en;
+        const double tot = wave_total(acc);
+        if (solid && lane == 0) pout[c] = tot;
+        // shift the window to the next cell (the value two cells ahead was
+        // prefetched by the previous cell, into `in`)
+        ez2 = ez1;
+        ez1 = ec;
+        ec = ezd;
+        ezd = in.nz;
+        lz_up = lz;
+        code_zu = code;
+    };
+
+    Pre A, B;
+    prefetch(-1, A);   // the first cell's x / y neighbours and the value at flow index 2
+    for (int f0 = 0; f0 < n2; f0 += 64) {
+        records(f0);
+        const int f1 = min(f0 + 64, n2);
+        int f = f0;
+        for (; f + 1 < f1; f += 2) {
+            step(f, A, B);
+            step(f + 1, B, A);
+        }
+        if (f < f1) {
+            step(f, A, B);
+            A = B;
+        }
+    }
+}
+
+template <typename T, int LIM>
+void transient3d_launch(const Dev &d, const T *ein, T *eout, const double *TLdev, const double *din,
+                        const ColItem *items, int nitems, int na_oct, int nchunk_oct, double src, double dt,
+                        double *part, hipStream_t s)
+{
+    const int blocks = ((nitems + 3) / 4 + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_transient3d<T, LIM>), dim3(blocks), dim3(256), 0, s, d, ein, eout, TLdev, din, items,
+                       nitems, na_oct, nchunk_oct, src, dt, part);
+}
+
+template <typename T>
+hipError_t launch_transient3d(const Dev &d, const T *ein, T *eout, const double *TLdev, const double *din,
+                              const ColItem *items, int nitems, int na_oct, int nchunk_oct, double src, double dt,
+                              double *part, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (d.limiter == LIM_NONE)
+        transient3d_launch<T, LIM_NONE>(d, ein, eout, TLdev, din, items, nitems, na_oct, nchunk_oct, src, dt, part, s);
+    else if (d.limiter == LIM_MC)
+        transient3d_launch<T, LIM_MC>(d, ein, eout, TLdev, din, items, nitems, na_oct, nchunk_oct, src, dt, part, s);
+    else
+        transient3d_launch<T, LIM_MINMOD>(d, ein, eout, TLdev, din, items, nitems, na_oct, nchunk_oct, src, dt, part,
+                                          s);
+    return hipGetLastError();
+}
+
+template hipError_t launch_transient3d<float>(const Dev &, const float *, float *, const double *, const double *,
+                                              const ColItem *, int, int, int, double, double, double *, hipStream_t);
+template hipError_t launch_transient3d<double>(const Dev &, const double *, double *, const double *, const double *,
+                                               const ColItem *, int, int, int, double, double, double *,
+                                               hipStream_t);
+
+}  // namespace bte
