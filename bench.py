@@ -45,8 +45,8 @@ HBM_PEAK_GBS = 8000.0
 # is used only while their hash matches)
 KERNEL_SOURCES = {
     "k_sweep2d<float,0>": ("bte_sweep2d.hip", "bte_tilelds.h", "bte_tile.h", "bte_stencil.h", "bte_internal.h"),
-    "k_transient_tile<float,3,1>": ("bte_tiled.hip", "bte_tilelds.h", "bte_tile.h", "bte_stencil.h",
-                                    "bte_adjflux.h", "bte_internal.h"),
+    "k_transient3d<float,1>": ("bte_transient3d.hip", "bte_tilelds.h", "bte_tile.h", "bte_stencil.h",
+                               "bte_internal.h"),
 }
 BYTES_PER_UPDATE = {0: 8.0, 1: 16.0}   # read e^n + write e^{n+1}
 
@@ -162,7 +162,7 @@ def bench_transient(args):
     value = r["upd"] * args.steps / r["t"]
     kern_ms = r["st"]["ms_sweep"] / args.steps
     achieved = BYTES_PER_UPDATE[B.F32] * r["upd"] / (kern_ms * 1e-3) / 1e9
-    traffic = counter_traffic("k_transient_tile<float,3,1>")
+    traffic = counter_traffic("k_transient3d<float,1>")
     out = {
         "metric": "cell*dir*band updates/s (FP32 state, FP64 moments) of explicit transient steps",
         "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -170,7 +170,7 @@ def bench_transient(args):
         "vs_baseline": None, "dtype": "f32 (e), f64 (moments)", "data": "synthetic (seeded bands, laser pulse)",
         "config": {"workload": "cube3d_laser: %d^3 cells, 2 um, 40 bands, 128 directions, MC limiter, dt 0.5 ps"
                    % n, "n": n},
-        "roofline": {"bound": "hbm", "kernel": "k_transient_tile<float,3,MC> (one launch per step)",
+        "roofline": {"bound": "hbm", "kernel": "k_transient3d<float,MC> (one launch per step)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_launch_ms": kern_ms,
                      "bytes_per_launch": BYTES_PER_UPDATE[B.F32] * r["upd"]},

@@ -223,12 +223,20 @@ __device__ inline void tile_load(const TileCtx t, TileSmem<T> &S, const T *__res
 // Limited slope times h (a difference) from the one-sided differences
 // dl = e_m - e_{m-1}, dr = e_{m+1} - e_m: MC = minmod(2 dl, 2 dr, (dl + dr)/2),
 // MINMOD = minmod(dl, dr); the face value is e_m + lim/2.
+// In single precision both are medians: minmod(a, b) = med3(a, b, 0) and
+// MC(a, b) = med3(4 minmod(a, b), a + b, 0) / 2 (the scalings are exact).
 template <typename T, int LIM> __device__ inline T lim_diff(T dl, T dr)
 {
-    T m;
-    if (LIM == LIM_MC) m = fmin(fmin((T)2 * fabs(dl), (T)2 * fabs(dr)), (T)0.5 * fabs(dl + dr));
-    else m = fmin(fabs(dl), fabs(dr));
-    return dl * dr > (T)0 ? copysign(m, dl) : (T)0;
+    if constexpr (sizeof(T) == 4) {
+        const float mm = __builtin_amdgcn_fmed3f(dl, dr, 0.0f);
+        if (LIM == LIM_MC) return 0.5f * __builtin_amdgcn_fmed3f(4.0f * mm, dl + dr, 0.0f);
+        return mm;
+    } else {
+        T m;
+        if (LIM == LIM_MC) m = fmin(fmin((T)2 * fabs(dl), (T)2 * fabs(dr)), (T)0.5 * fabs(dl + dr));
+        else m = fmin(fabs(dl), fabs(dr));
+        return dl * dr > (T)0 ? copysign(m, dl) : (T)0;
+    }
 }
 
 // Cross-lane move of a double inside a row of 16 lanes (DPP control CTRL).

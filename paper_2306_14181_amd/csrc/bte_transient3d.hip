@@ -11,9 +11,10 @@
 // hierarchy: neighbouring columns are walked by neighbouring wavefronts of
 // the same XCD at the same time.  The cell itself is the same for all 64
 // lanes, so its geometry code, T_L, scattering rate and source are scalar
-// loads, issued one cell ahead like the stencil values.  The FP64 partial
-// sum w e/tau of the T_L update is reduced over the 64 lanes per cell and
-// written per (octant, chunk, cell).
+// values, one cell per lane for runs of 64 cells, broadcast with readlane.
+// The FP64 partial sum w e/tau of the T_L update is reduced over the 64
+// lanes (a transposed reduction through LDS every eight cells) and written
+// per (octant, chunk, cell).
 #include "bte_internal.h"
 #include "bte_stencil.h"
 #include "bte_tilelds.h"
@@ -28,17 +29,6 @@ __device__ inline double rl_d(double v, int lane)
     const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Sum over the 64 lanes of a wavefront (the same value in every lane):
-// butterflies inside each row of 16 lanes, then the four row sums.
-__device__ inline double wave_total(double v)
-{
-    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
-    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
-    v += dpp_f64<0x141>(v);   // row_half_mirror
-    v += dpp_f64<0x140>(v);   // row_mirror
-    return (rl_d(v, 0) + rl_d(v, 16)) + (rl_d(v, 32) + rl_d(v, 48));
 }
 
 // Position i along an axis of n cells: itself inside, the periodic image
@@ -97,6 +87,9 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
                                                      int nchunk_oct, double src, double dt,
                                                      double *__restrict__ part)
 {
+    // T_L partials of eight consecutive cells of each wavefront, reduced
+    // transposed (lane = 8 cell + part) every eight cells
+    __shared__ double red[4][8][64];
     // four wavefronts per block; logical blocks are contiguous per XCD so
     // that neighbouring columns share an L2
     const int nb = gridDim.x, bb = blockIdx.x;
@@ -184,22 +177,30 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
     const long long zstep = (long long)(sg2 > 0 ? plane : -plane) * nk;
     const int z0 = sg2 > 0 ? 0 : n2 - 1;
     auto row0 = [&](int b) -> const T * { return b >= 0 ? ein + (size_t)(b + plane * z0) * nk : zrow; };
-    const T *rx1 = row0(bx1), *rx2 = row0(bx2), *rxd = row0(bxd);
+    const T *rx1 = row0(bx1), *rx2 = row0(bx2), *rxd = row0(bxd);   // rows of the cell being prefetched
     const T *ry1 = row0(by1), *ry2 = row0(by2), *ryd = row0(byd);
     const long long sx1 = bx1 >= 0 ? zstep : 0, sx2 = bx2 >= 0 ? zstep : 0, sxd = bxd >= 0 ? zstep : 0;
     const long long sy1 = by1 >= 0 ? zstep : 0, sy2 = by2 >= 0 ? zstep : 0, syd = byd >= 0 ? zstep : 0;
     const T *rc0 = ein + (size_t)(cb + plane * z0) * nk;   // the column's own row at flow index 0
     auto at = [&](const T *row) -> T { return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(row) + koff); };
-    // loads for the cell after flow index f (x / y neighbours) and the
-    // column value at flow index f + 3
+    // loads for the cell after flow index f (x / y neighbours: the running
+    // row pointers are advanced by one plane per cell, not past the column)
+    // and the column value at flow index f + 3
     auto prefetch = [&](int f, Pre &q) {
-        const long long fn = f + 1 < n2 ? f + 1 : f;
-        q.x1 = at(rx1 + fn * sx1);
-        q.x2 = at(rx2 + fn * sx2);
-        q.xd = at(rxd + fn * sxd);
-        q.y1 = at(ry1 + fn * sy1);
-        q.y2 = at(ry2 + fn * sy2);
-        q.yd = at(ryd + fn * syd);
+        if (f + 1 < n2 && f >= 0) {
+            rx1 += sx1;
+            rx2 += sx2;
+            rxd += sxd;
+            ry1 += sy1;
+            ry2 += sy2;
+            ryd += syd;
+        }
+        q.x1 = at(rx1);
+        q.x2 = at(rx2);
+        q.xd = at(rxd);
+        q.y1 = at(ry1);
+        q.y2 = at(ry2);
+        q.yd = at(ryd);
         // inside the column: plain row; past its end (last three cells):
         // periodic image with its jump, or zero
         const T *rz;
@@ -218,7 +219,8 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
     // (unconditional loads: an absent neighbour reads the cell's own code
     // and is masked), broadcast with readlane.
     uint32_t r_code = 0, r_cxu = 0, r_cyu = 0;
-    double r_tl = 0, r_gam = 0, r_p = 0;
+    double r_gam = 0;
+    T r_tlT = (T)0, r_gamT = (T)0, r_qsT = (T)0;
     auto records = [&](int f0) {
         const int fl = min(f0 + lane, n2 - 1);
         const int o = plane * (sg2 > 0 ? fl : n2 - 1 - fl);
@@ -227,10 +229,16 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
         const uint32_t cxu = d.code[bx1 >= 0 ? bx1 + o : c], cyu = d.code[by1 >= 0 ? by1 + o : c];
         r_cxu = bx1 >= 0 ? cxu : 0u;
         r_cyu = by1 >= 0 ? cyu : 0u;
-        r_tl = TLdev[c];
         r_gam = d.gamma[c];
-        r_p = *(d.P ? d.P + c : zd);   // P is null without a heat source
+        r_tlT = (T)TLdev[c];
+        r_gamT = (T)r_gam;
+        r_qsT = (T)(*(d.P ? d.P + c : zd) / d.Ctot);   // P is null without a heat source
     };
+    auto rlt = [&](T v, int q) -> T {
+        if constexpr (sizeof(T) == 4) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
+        else return rl_d(v, q);
+    };
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
     auto step = [&](int f, const Pre &in, Pre &out) {
         const int z = sg2 > 0 ? f : n2 - 1 - f;
@@ -241,8 +249,7 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
         const uint32_t code = (uint32_t)__builtin_amdgcn_readlane((int)r_code, q);
         const uint32_t code_xu = (uint32_t)__builtin_amdgcn_readlane((int)r_cxu, q);
         const uint32_t code_yu = (uint32_t)__builtin_amdgcn_readlane((int)r_cyu, q);
-        const double tl = rl_d(r_tl, q), gam = rl_d(r_gam, q);
-        const double qs = rl_d(r_p, q) / d.Ctot;
+        const T tlT = rlt(r_tlT, q), gamT = rlt(r_gamT, q), qsT = rlt(r_qsT, q);
         const bool solid = code & kSolidBit;
         const T ex1 = in.x1 + kx1, ex2 = in.x2 + kx2, exd = in.xd + kxd;
         const T ey1 = in.y1 + ky1, ey2 = in.y2 + ky2, eyd = in.yd + kyd;
@@ -281,13 +288,26 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
                                          C4 * (T)(jd * fm.pdT[2]), L.al, L.l, C4, L.hh[2], L.ih[2]);
             }
             const T D = cp0 * dx + cp1 * dy + cp2 * dz;
-            const T itc = itau + (T)gam;
-            en = ec + tdt * (-D - (ec - C4 * (T)tl) * itc + C4 * tsrc * (T)qs);
-            acc = active ? (L.witau + L.w * gam) * (double)en : 0.0;
+            const T itc = itau + gamT;
+            en = ec + tdt * (-D - (ec - C4 * tlT) * itc + C4 * tsrc * qsT);
+            acc = active ? (L.witau + L.w * rl_d(r_gam, q)) * (double)en : 0.0;
         }
         if (active) eout[(size_t)c * nk + k] = en;
-        const double tot = wave_total(acc);
-        if (solid && lane == 0) pout[c] = tot;
+        // partial of this cell into the transposed buffer; every eighth cell
+        // (and at the end of the column) the eight cells are reduced
+        red[wv][f & 7][lane] = acc;
+        if ((f & 7) == 7 || f == n2 - 1) {
+            const int j = lane >> 3, pp = lane & 7, fb = f & ~7;
+            double v = 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v += red[wv][j][8 * pp + i];
+            v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+            v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+            v += dpp_f64<0x141>(v);   // row_half_mirror
+            const int fj = fb + j;
+            // (pores get a zero partial: the T_L update ignores them)
+            if (pp == 0 && fj <= f) pout[cb + plane * (sg2 > 0 ? fj : n2 - 1 - fj)] = v;
+        }
         // shift the window to the next cell (the value two cells ahead was
         // prefetched by the previous cell, into `in`)
         ez2 = ez1;
