@@ -69,9 +69,10 @@ void launch_finalize(const Dev &, const double *, int, double, double *, double 
 void launch_finalize_tl(const Dev &, const double *, int, double *, hipStream_t);
 void launch_steady_post(const Dev &, const double *, int, const double *, double *, double *, double *, double *, int,
                         hipStream_t);
-void launch_film_eps(const Dev &, const double *, const double *, const double *, const double *, double *,
-                     hipStream_t);
-void launch_film_mean(const Dev &, const double *, double *, hipStream_t);
+int film_segments(int max_cells);
+void launch_film_eps(const Dev &, const double *, const double *, const double *, const double *, double *, double *,
+                     int, hipStream_t);
+void launch_film_mean(const Dev &, const double *, double *, double *, int, hipStream_t);
 void launch_sub_film_mean(const Dev &, double *, const double *, hipStream_t);
 void launch_tl_update(int, const double *, const double *, double *, double *, hipStream_t);
 void launch_cg_coef(const Dev &, const CgArgs &, double *, double *, hipStream_t);
@@ -163,6 +164,8 @@ struct bte_problem {
     double *cdif = nullptr, *ccor = nullptr, *ddif = nullptr, *dcor = nullptr;
     double *TL = nullptr, *TLkin = nullptr, *T0 = nullptr, *T1 = nullptr, *q0 = nullptr, *q1 = nullptr;
     double *r = nullptr, *delta = nullptr, *dpend = nullptr, *fmean = nullptr, *feps = nullptr;
+    double *fpart = nullptr;   // per-geometry reduction partials, 5 x nfilm x fseg
+    int fseg = 1;              // segments of the largest geometry
     double *cg_x = nullptr, *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
     double *cg_w0 = nullptr, *cg_w1 = nullptr, *cg_s1 = nullptr;
     double *cg_part = nullptr, *cg_scal = nullptr;
@@ -540,6 +543,12 @@ void plan_workspace(bte_problem *p)
     add("dcor", 8 * nc);
     add("fmean", 8 * p->nfilm);
     add("feps", 8 * 5 * p->nfilm);
+    {
+        int mx = 1;
+        for (const Film &fm : p->films) mx = std::max(mx, fm.ncell);
+        p->fseg = film_segments(mx);
+    }
+    add("fpart", 8 * 5 * (size_t)p->nfilm * p->fseg);
     add("cg_part", 8 * 6 * (size_t)((nc + kBlock - 1) / kBlock));
     add("cg_scal", 8 * 16);
     add("din", 8 * (size_t)p->nw * p->nl);
@@ -735,6 +744,7 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     p->dpend = wsptr<double>(p, "dpend");
     p->fmean = wsptr<double>(p, "fmean");
     p->feps = wsptr<double>(p, "feps");
+    p->fpart = wsptr<double>(p, "fpart");
     p->cg_x = wsptr<double>(p, "cg_x");
     p->cg_r = wsptr<double>(p, "cg_r");
     p->cg_z = wsptr<double>(p, "cg_z");
@@ -843,7 +853,7 @@ bool run_cg(bte_problem *p, int corr, double *b, double *x_out, double rtol, int
 {
     const Dev &d = p->dev;
     if (p->floating_any) {
-        launch_film_mean(d, b, p->fmean, s);
+        launch_film_mean(d, b, p->fmean, p->fpart, p->fseg, s);
         launch_sub_film_mean(d, b, p->fmean, s);
     }
     CgArgs g = cg_args(p, corr);
@@ -863,7 +873,7 @@ bool run_cg(bte_problem *p, int corr, double *b, double *x_out, double rtol, int
         }
     }
     if (p->floating_any) {
-        launch_film_mean(d, x_out, p->fmean, s);
+        launch_film_mean(d, x_out, p->fmean, p->fpart, p->fseg, s);
         launch_sub_film_mean(d, x_out, p->fmean, s);
     }
     return hipGetLastError() == hipSuccess;
@@ -922,7 +932,7 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
         }
         HIPCHK(p, hipEventRecord(ev[2], s));
         launch_steady_post(d, p->part, np, p->TL, p->TLkin, p->T1, p->q1, p->r, synthetic, s);
-        launch_film_eps(d, p->T0, p->T1, p->q0, p->q1, p->feps, s);
+        launch_film_eps(d, p->T0, p->T1, p->q0, p->q1, p->feps, p->fpart, p->fseg, s);
         HIPCHK(p, hipEventRecord(ev[3], s));
         HIPCHK(p, hipGetLastError());
         if (synthetic) {
@@ -974,7 +984,7 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
     // shift to zero mean T - T_ref (T0 now holds the last moments)
     double *fshift = nullptr;
     if (p->floating_any) {
-        launch_film_mean(d, p->T0, p->fmean, s);
+        launch_film_mean(d, p->T0, p->fmean, p->fpart, p->fseg, s);
         // only floating films are shifted: zero the others on the host side
         std::vector<double> fm(p->nfilm);
         HIPCHK(p, hipMemcpyAsync(fm.data(), p->fmean, 8 * fm.size(), hipMemcpyDeviceToHost, s));
@@ -1130,7 +1140,7 @@ bte_status adjoint_impl(bte_problem *p, const T *e, double *grad, bte_solve_stat
         HIPCHK(p, launch_adj_res<T>(d, pin, p->adjX, p->din, p->d_titems, (int)p->titems.size(), p->tdim_tr,
                                     p->na_oct, p->nchunk_oct, p->tile_cap_tr, p->part, s));
         launch_adj_post(d, p->part, p->noct, p->adju, p->adjr2, s);
-        launch_film_mean(d, p->adjr2, p->fmean, s);
+        launch_film_mean(d, p->adjr2, p->fmean, p->fpart, p->fseg, s);
         HIPCHK(p, hipEventRecord(ev[2], s));
         HIPCHK(p, hipMemcpyAsync(mres.data(), p->fmean, 8 * mres.size(), hipMemcpyDeviceToHost, s));
         HIPCHK(p, hipStreamSynchronize(s));

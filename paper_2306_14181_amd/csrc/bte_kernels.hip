@@ -263,20 +263,28 @@ __global__ void k_steady_post(Dev d, const double *__restrict__ part, int np, co
     if (synthetic) r[c] = solid ? d.S[c] * (tl - TLn[c]) : 0.0;
 }
 
-// Per-geometry convergence measures (Sec. 3.4): one block per geometry.
+// Per-geometry convergence measures (Sec. 3.4), in two stages: blocks of
+// kFilmSeg cells of a geometry write partials, then one wavefront per
+// geometry combines them in a fixed order.
 // out[f] = {sum dT^2, max|T-Tref|, sum d|q|^2, max|q|, sum (T-Tref)}.
-__global__ __launch_bounds__(kBlock) void k_film_eps(Dev d, const double *__restrict__ T0, const double *__restrict__ T1,
-                                                      const double *__restrict__ q0, const double *__restrict__ q1,
-                                                      double *__restrict__ out)
+constexpr int kFilmSeg = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_film_eps_part(Dev d, const double *__restrict__ T0,
+                                                           const double *__restrict__ T1,
+                                                           const double *__restrict__ q0,
+                                                           const double *__restrict__ q1, double *__restrict__ part)
 {
     __shared__ double sh[4 * 5];
-    const Film &fm = d.film[blockIdx.x];
+    __shared__ double shm[8];
+    const int f = blockIdx.y, sgm = blockIdx.x;
+    const Film &fm = d.film[f];
+    const int i0 = sgm * kFilmSeg, i1 = min(fm.ncell, i0 + kFilmSeg);
     double a[5] = {0, 0, 0, 0, 0};
     double mT = 0, mq = 0;
     // branch-free body (pores contribute zeros) so that the loads of
     // consecutive iterations overlap
 #pragma unroll 4
-    for (int i = threadIdx.x; i < fm.ncell; i += kBlock) {
+    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
         const int c = fm.cell0 + i;
         const double sl = (d.code[c] & kSolidBit) ? 1.0 : 0.0;
         const double t1 = T1[c], u1 = q1[c];
@@ -287,12 +295,10 @@ __global__ __launch_bounds__(kBlock) void k_film_eps(Dev d, const double *__rest
         mT = fmax(mT, fabs(t1) * sl);
         mq = fmax(mq, fabs(u1) * sl);
     }
-    // maxima: butterfly max then block max
     for (int off = 32; off > 0; off >>= 1) {
         mT = fmax(mT, __shfl_xor(mT, off, 64));
         mq = fmax(mq, __shfl_xor(mq, off, 64));
     }
-    __shared__ double shm[8];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) {
         shm[wave] = mT;
@@ -300,30 +306,65 @@ __global__ __launch_bounds__(kBlock) void k_film_eps(Dev d, const double *__rest
     }
     block_sum<5>(a, sh);
     if (threadIdx.x == 0) {
-        double MT = fmax(fmax(shm[0], shm[1]), fmax(shm[2], shm[3]));
-        double MQ = fmax(fmax(shm[4], shm[5]), fmax(shm[6], shm[7]));
-        double *o = out + 5 * blockIdx.x;
+        double *o = part + 5 * ((size_t)f * gridDim.x + sgm);
         o[0] = a[0];
-        o[1] = MT;
+        o[1] = fmax(fmax(shm[0], shm[1]), fmax(shm[2], shm[3]));
         o[2] = a[2];
-        o[3] = MQ;
+        o[3] = fmax(fmax(shm[4], shm[5]), fmax(shm[6], shm[7]));
         o[4] = a[4];
     }
 }
 
-// Per-geometry mean over solid cells of x (one block per geometry).
-__global__ __launch_bounds__(kBlock) void k_film_mean(Dev d, const double *__restrict__ x, double *__restrict__ mean)
+__global__ __launch_bounds__(64) void k_film_eps_fin(const double *__restrict__ part, int nseg,
+                                                     double *__restrict__ out)
+{
+    const int f = blockIdx.x, lane = threadIdx.x;
+    double a[5] = {0, 0, 0, 0, 0};
+    for (int s = lane; s < nseg; s += 64) {
+        const double *p = part + 5 * ((size_t)f * nseg + s);
+        a[0] += p[0];
+        a[1] = fmax(a[1], p[1]);
+        a[2] += p[2];
+        a[3] = fmax(a[3], p[3]);
+        a[4] += p[4];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a[0] += __shfl_xor(a[0], off, 64);
+        a[1] = fmax(a[1], __shfl_xor(a[1], off, 64));
+        a[2] += __shfl_xor(a[2], off, 64);
+        a[3] = fmax(a[3], __shfl_xor(a[3], off, 64));
+        a[4] += __shfl_xor(a[4], off, 64);
+    }
+    if (lane == 0)
+        for (int i = 0; i < 5; ++i) out[5 * f + i] = a[i];
+}
+
+// Per-geometry mean over solid cells of x, in the same two stages.
+__global__ __launch_bounds__(kBlock) void k_film_mean_part(Dev d, const double *__restrict__ x,
+                                                            double *__restrict__ part)
 {
     __shared__ double sh[4];
-    const Film &fm = d.film[blockIdx.x];
+    const int f = blockIdx.y, sgm = blockIdx.x;
+    const Film &fm = d.film[f];
+    const int i0 = sgm * kFilmSeg, i1 = min(fm.ncell, i0 + kFilmSeg);
     double a[1] = {0};
 #pragma unroll 4
-    for (int i = threadIdx.x; i < fm.ncell; i += kBlock) {
+    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
         const int c = fm.cell0 + i;
         a[0] += (d.code[c] & kSolidBit) ? x[c] : 0.0;
     }
     block_sum<1>(a, sh);
-    if (threadIdx.x == 0) mean[blockIdx.x] = a[0] / fm.nsolid;
+    if (threadIdx.x == 0) part[(size_t)f * gridDim.x + sgm] = a[0];
+}
+
+__global__ __launch_bounds__(64) void k_film_mean_fin(Dev d, const double *__restrict__ part, int nseg,
+                                                      double *__restrict__ mean)
+{
+    const int f = blockIdx.x, lane = threadIdx.x;
+    double a = 0;
+    for (int s = lane; s < nseg; s += 64) a += part[(size_t)f * nseg + s];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if (lane == 0) mean[f] = a / d.film[f].nsolid;
 }
 
 // x -= mean of its geometry, only for floating geometries (no thermalizing wall)
@@ -688,15 +729,20 @@ void launch_steady_post(const Dev &d, const double *part, int np, const double *
                        synthetic);
 }
 
+int film_segments(int max_cells) { return std::max(1, (max_cells + kFilmSeg - 1) / kFilmSeg); }
+
+// part: scratch of 5 * nfilm * nseg doubles, nseg = film_segments(largest geometry)
 void launch_film_eps(const Dev &d, const double *T0, const double *T1, const double *q0, const double *q1,
-                     double *out, hipStream_t s)
+                     double *out, double *part, int nseg, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_film_eps, dim3(d.nfilm), dim3(kBlock), 0, s, d, T0, T1, q0, q1, out);
+    hipLaunchKernelGGL(k_film_eps_part, dim3(nseg, d.nfilm), dim3(kBlock), 0, s, d, T0, T1, q0, q1, part);
+    hipLaunchKernelGGL(k_film_eps_fin, dim3(d.nfilm), dim3(64), 0, s, part, nseg, out);
 }
 
-void launch_film_mean(const Dev &d, const double *x, double *mean, hipStream_t s)
+void launch_film_mean(const Dev &d, const double *x, double *mean, double *part, int nseg, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_film_mean, dim3(d.nfilm), dim3(kBlock), 0, s, d, x, mean);
+    hipLaunchKernelGGL(k_film_mean_part, dim3(nseg, d.nfilm), dim3(kBlock), 0, s, d, x, part);
+    hipLaunchKernelGGL(k_film_mean_fin, dim3(d.nfilm), dim3(64), 0, s, d, part, nseg, mean);
 }
 
 void launch_sub_film_mean(const Dev &d, double *x, const double *mean, hipStream_t s)
