@@ -121,6 +121,9 @@ typedef struct {
     double ms_post;          /* device time of moments/defect/eps kernels  */
     double ms_cg;            /* device time of the synthetic correction    */
     int sweep_launches;      /* kernel launches issued for the sweeps      */
+    double updates;          /* (cell, direction, band) updates performed by the
+                                sweeps or steps: converged geometries of a
+                                batch are no longer swept                   */
 } bte_solve_stats;
 
 typedef struct bte_problem bte_problem;

@@ -59,7 +59,7 @@ class SolveStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("cg_iters", C.c_int), ("eps_T", C.c_double), ("eps_q", C.c_double),
                 ("converged", C.c_int), ("ms_total", C.c_double), ("ms_sweep", C.c_double),
                 ("ms_walls", C.c_double), ("ms_post", C.c_double), ("ms_cg", C.c_double),
-                ("sweep_launches", C.c_int)]
+                ("sweep_launches", C.c_int), ("updates", C.c_double)]
 
     def as_dict(self):
         return {k: (bool(getattr(self, k)) if k == "converged" else getattr(self, k)) for k, _ in self._fields_}

@@ -74,7 +74,8 @@ void launch_film_eps(const Dev &, const double *, const double *, const double *
                      int, hipStream_t);
 void launch_film_mean(const Dev &, const double *, double *, double *, int, hipStream_t);
 void launch_sub_film_mean(const Dev &, double *, const double *, hipStream_t);
-void launch_tl_update(int, const double *, const double *, double *, double *, hipStream_t);
+void launch_tl_update(int, const double *, const double *, double *, double *, const int *, const int *,
+                      hipStream_t);
 void launch_cg_coef(const Dev &, const CgArgs &, double *, double *, hipStream_t);
 void launch_diff_rhs(const Dev &, const CgArgs &, double *, hipStream_t);
 void launch_cg_begin(const Dev &, const CgArgs &, const double *, hipStream_t);
@@ -549,6 +550,7 @@ void plan_workspace(bte_problem *p)
         p->fseg = film_segments(mx);
     }
     add("fpart", 8 * 5 * (size_t)p->nfilm * p->fseg);
+    add("fdone", 4 * (size_t)p->nfilm);
     add("cg_part", 8 * 6 * (size_t)((nc + kBlock - 1) / kBlock));
     add("cg_scal", 8 * 16);
     add("din", 8 * (size_t)p->nw * p->nl);
@@ -727,6 +729,7 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     d.P = nullptr;
     d.S = p->S;
     d.zrow = wsptr<void>(p, "zrow");
+    d.fdone = wsptr<int>(p, "fdone");
     p->kdif = wsptr<double>(p, "kdif");
     p->kcor = wsptr<double>(p, "kcor");
     p->cdif = wsptr<double>(p, "cdif");
@@ -773,6 +776,7 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     p->d_wden = wsptr<double>(p, "wden");
     // default fields: no source, no extra scattering
     HIPCHK(p, hipMemset(wsptr<void>(p, "zrow"), 0, 8 * (size_t)p->nk));
+    HIPCHK(p, hipMemset(wsptr<void>(p, "fdone"), 0, 4 * (size_t)p->nfilm));
     HIPCHK(p, hipMemset(p->gamma, 0, 8 * (size_t)p->nc));
     HIPCHK(p, hipMemset(p->P, 0, 8 * (size_t)p->nc));
     cell_setup(p, nullptr);
@@ -902,6 +906,12 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
     launch_moments<T>(d, e, nullptr, p->part, s);
     launch_finalize(d, p->part, 1, p->Tref, nullptr, nullptr, nullptr, p->TL, p->T0, p->q0, s);
     std::vector<double> feps(5 * (size_t)p->nfilm);
+    // per-geometry convergence: a converged geometry is no longer swept or
+    // corrected (its field, T_L and pending correction stay as they were
+    // when it met the tolerances)
+    std::vector<int> fdone(p->nfilm, 0);
+    int ndone = 0;
+    int *fdone_dev = const_cast<int *>(d.fdone);
     const int np = p->noct * p->nchunk_oct;
     bte_status ret = BTE_ERR_NOT_CONVERGED;
     // phase timers: events on the solve stream, read after the per-iteration sync
@@ -914,9 +924,12 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
             for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]);
         }
     } evg{ev};
+    double active_cells = 0;
+    for (const Film &fm : p->films) active_cells += fm.ncell;
     for (int iter = 1; iter <= p->ctl.max_iter; ++iter) {
         const T *ein = buf[cur];
         T *eout = buf[1 - cur];
+        st.updates += active_cells * (double)p->nk;
         HIPCHK(p, hipEventRecord(ev[0], s));
         launch_walls<T>(d, ein, p->dpend, p->d_wrec, p->d_wden, p->din, p->nw, s);
         HIPCHK(p, hipEventRecord(ev[1], s));
@@ -938,9 +951,9 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
         if (synthetic) {
             if (!run_cg(p, 1, p->r, p->delta, p->ctl.cg_rtol, p->ctl.cg_max_iter, s))
                 FAIL(p, BTE_ERR_HIP, "CG failed");
-            launch_tl_update(nc, p->TLkin, p->delta, p->TL, p->dpend, s);
+            launch_tl_update(nc, p->TLkin, p->delta, p->TL, p->dpend, d.fid, d.fdone, s);
         } else {
-            launch_tl_update(nc, p->TLkin, nullptr, p->TL, nullptr, s);
+            launch_tl_update(nc, p->TLkin, nullptr, p->TL, nullptr, d.fid, d.fdone, s);
         }
         HIPCHK(p, hipEventRecord(ev[4], s));
         HIPCHK(p, hipMemcpyAsync(feps.data(), p->feps, 8 * feps.size(), hipMemcpyDeviceToHost, s));
@@ -955,7 +968,9 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
         }
         double eT = 0, eq = 0;
         bool finite = true;
+        std::vector<int> newly;
         for (int f = 0; f < p->nfilm; ++f) {
+            if (fdone[f]) continue;
             const Film &fm = p->films[f];
             const double *o = &feps[5 * f];
             double a = std::sqrt(o[0] / fm.nsolid) / (o[1] > 1e-300 ? o[1] : 1.0);
@@ -963,6 +978,7 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
             if (!std::isfinite(a) || !std::isfinite(b)) finite = false;
             eT = std::max(eT, a);
             eq = std::max(eq, b);
+            if (a <= p->ctl.residual_temp && b <= p->ctl.residual_flux) newly.push_back(f);
         }
         std::swap(p->T0, p->T1);
         std::swap(p->q0, p->q1);
@@ -974,12 +990,27 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
             ret = BTE_ERR_NONFINITE;
             break;
         }
-        if (eT <= p->ctl.residual_temp && eq <= p->ctl.residual_flux) {
+        if (ndone + (int)newly.size() == p->nfilm) {
             st.converged = 1;
             ret = BTE_OK;
             break;
         }
+        if (!newly.empty()) {
+            // both buffers hold the converged field of these geometries from now on
+            for (int f : newly) {
+                const Film &fm = p->films[f];
+                const size_t off = (size_t)fm.cell0 * p->nk, cnt = (size_t)fm.ncell * p->nk;
+                HIPCHK(p, hipMemcpyAsync(buf[1 - cur] + off, buf[cur] + off, cnt * sizeof(T), hipMemcpyDeviceToDevice,
+                                         s));
+                fdone[f] = 1;
+                ++ndone;
+                active_cells -= fm.ncell;
+            }
+            HIPCHK(p, hipMemcpyAsync(fdone_dev, fdone.data(), 4 * fdone.size(), hipMemcpyHostToDevice, s));
+        }
     }
+    // later calls (and the adjoint) sweep every geometry again
+    HIPCHK(p, hipMemsetAsync(fdone_dev, 0, 4 * (size_t)p->nfilm, s));
     // final field: pending correction and, for floating geometries, the gauge
     // shift to zero mean T - T_ref (T0 now holds the last moments)
     double *fshift = nullptr;
@@ -1085,6 +1116,7 @@ bte_status transient_impl(bte_problem *p, T *e, int n_steps, double t0, const do
         }
         st.iters = n_steps;
         st.sweep_launches = n_steps;
+        st.updates = (double)n_steps * (double)p->nelem();
         st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
         p->last = st;
     }
@@ -1178,7 +1210,7 @@ bte_status adjoint_impl(bte_problem *p, const T *e, double *grad, bte_solve_stat
             // v = L^-1 P^T y; the sweep's isotropic term becomes X + v
             if (!run_cg(p, 1, p->adju, p->delta, p->ctl.cg_rtol, p->ctl.cg_max_iter, s))
                 FAIL(p, BTE_ERR_HIP, "CG failed");
-            launch_tl_update(nc, p->adjX, p->delta, p->TL, nullptr, s);
+            launch_tl_update(nc, p->adjX, p->delta, p->TL, nullptr, nullptr, nullptr, s);
             X = p->TL;
         }
         HIPCHK(p, hipEventRecord(ev[3], s));
@@ -1199,6 +1231,7 @@ bte_status adjoint_impl(bte_problem *p, const T *e, double *grad, bte_solve_stat
         }
         cur = 1 - cur;
         st.iters = iter + 1;
+        st.updates += (double)p->nelem();
     }
     launch_adj_grad<T>(d, e, buf[cur], p->adjT, p->adjTL, p->adjX, grad, s);
     HIPCHK(p, hipGetLastError());
@@ -1284,6 +1317,7 @@ bte_status tadj_impl(bte_problem *p, const T *e0, int n_steps, double t0, const 
     HIPCHK(p, hipStreamSynchronize(s));
     bte_solve_stats st{};
     st.iters = n_steps;
+    st.updates = 3.0 * (double)n_steps * (double)p->nelem();   // forward, recompute, transposed steps
     st.converged = 1;
     st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
     p->last = st;

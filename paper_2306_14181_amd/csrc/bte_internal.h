@@ -66,6 +66,7 @@ struct Dev {
     const double *S;         // [nc] sum_lambda C (1/tau + gamma)
     const void *zrow;        // [nk] zeros of the working precision: loads of a
                              // missing cell read here instead of branching
+    const int *fdone;        // [nfilm] 1: geometry converged, its steady sweep is skipped
 };
 
 // One work item of the sweep: a tile of one geometry for 64 lanes of one octant.

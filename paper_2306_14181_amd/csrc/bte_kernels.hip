@@ -260,7 +260,8 @@ __global__ void k_steady_post(Dev d, const double *__restrict__ part, int np, co
     TLkin[c] = tl;
     Tnew[c] = solid ? s[0] / d.Ctot : 0.0;
     qnew[c] = solid ? sqrt(s[2] * s[2] + s[3] * s[3] + s[4] * s[4]) : 0.0;
-    if (synthetic) r[c] = solid ? d.S[c] * (tl - TLn[c]) : 0.0;
+    // a converged geometry gets no further correction
+    if (synthetic) r[c] = (solid && !d.fdone[d.fid[c]]) ? d.S[c] * (tl - TLn[c]) : 0.0;
 }
 
 // Per-geometry convergence measures (Sec. 3.4), in two stages: blocks of
@@ -376,12 +377,15 @@ __global__ void k_sub_film_mean(Dev d, double *__restrict__ x, const double *__r
     if (d.film[f].floating && (d.code[c] & kSolidBit)) x[c] -= mean[f];
 }
 
-// T_L^{n+1} = T_L^kin + delta, pending correction = delta
+// T_L^{n+1} = T_L^kin + delta, pending correction = delta (cells of
+// converged geometries keep both, when fid / fdone are given)
 __global__ void k_tl_update(int n, const double *__restrict__ TLkin, const double *__restrict__ delta,
-                            double *__restrict__ TL, double *__restrict__ dpend)
+                            double *__restrict__ TL, double *__restrict__ dpend, const int *__restrict__ fid,
+                            const int *__restrict__ fdone)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
+    if (fdone && fdone[fid[c]]) return;
     const double dl = delta ? delta[c] : 0.0;
     TL[c] = TLkin[c] + dl;
     if (dpend) dpend[c] = dl;
@@ -750,9 +754,11 @@ void launch_sub_film_mean(const Dev &d, double *x, const double *mean, hipStream
     hipLaunchKernelGGL(k_sub_film_mean, dim3((d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, x, mean);
 }
 
-void launch_tl_update(int n, const double *TLkin, const double *delta, double *TL, double *dpend, hipStream_t s)
+void launch_tl_update(int n, const double *TLkin, const double *delta, double *TL, double *dpend, const int *fid,
+                      const int *fdone, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tl_update, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, TLkin, delta, TL, dpend);
+    hipLaunchKernelGGL(k_tl_update, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, TLkin, delta, TL, dpend,
+                       fid, fdone);
 }
 
 void launch_cg_coef(const Dev &d, const CgArgs &g, double *coef, double *dg, hipStream_t s)

@@ -169,6 +169,7 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     __shared__ T sX0[kTY][64];
     __shared__ T sY0[64][kTX];
     const Sweep2Item it = items[item0 + blockIdx.x];
+    if (d.fdone[it.film]) return;   // converged geometry (uniform over the block)
     // wavefront r owns tile row r (readfirstlane: r is known to be uniform,
     // so everything derived from it stays scalar)
     const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;

@@ -63,7 +63,9 @@ def test_batched_films_keff_matches_oracle(B, prec, lim):
     if lim not in _REF:
         _REF[lim] = np.array([oracle_keff(g, mat, limiter=ol) for g in films])
     ref = _REF[lim]
-    print(prec, "iters", st["iters"], "k_eff", k, "oracle", ref)
+    print(prec, "iters", st["iters"], "updates", st["updates"], "k_eff", k, "oracle", ref)
+    # converged films leave the sweep: never more updates than every film for every iteration
+    assert 0 < st["updates"] <= prob.n_unknowns * st["iters"]
     tol = 1e-9 if p == B.F64 else 1e-5
     assert np.all(np.abs(k - ref) <= tol * np.abs(ref)), (k, ref)
 
