@@ -233,6 +233,13 @@ size_t bte_transient_adjoint_bytes(const bte_problem *p, int n_steps, int every)
  * times can be read; the call is then synchronous. */
 bte_status bte_set_timing(bte_problem *p, int on);
 
+/* HIP graphs in bte_steady_solve (on by default).  With on != 0 the
+ * tile-diagonal launches of one sweep (one graph per buffer parity) and, when
+ * control.cg_max_iter <= 64, the launches of one synthetic-correction CG solve
+ * are captured once per solve call and replayed every source iteration; the
+ * results are the same as with plain launches. */
+bte_status bte_set_graphs(bte_problem *p, int on);
+
 /* Statistics of the last bte_steady_solve, or of the last timed
  * bte_transient_step (iters = steps, ms_sweep = transport kernels, ms_walls =
  * wall kernels, ms_post = T_L updates). */

@@ -187,9 +187,15 @@ struct bte_problem {
     std::vector<hipEvent_t> tev;
     bte_solve_stats last{};
 
+    // HIP graphs of the steady iteration (bte_set_graphs), captured on a
+    // private stream (the caller's may be the null stream, which cannot be
+    // captured) and replayed on the caller's stream
+    bool graphs = true;
+    hipStream_t cstream = nullptr;
     ~bte_problem()
     {
         for (hipEvent_t e : tev) (void)hipEventDestroy(e);
+        if (cstream) (void)hipStreamDestroy(cstream);
     }
     size_t esize() const { return ctl.precision == BTE_F64 ? 8 : 4; }
     size_t nelem() const { return (size_t)nc * nk; }
@@ -853,6 +859,8 @@ template <typename T> bte_status moments_to(bte_problem *p, const T *e, const do
 // floating geometry beforehand, x afterwards.  Asynchronous when maxit fits
 // one chunk of launches; the iteration count is accumulated on the device
 // (cg_scal[9]).  Returns false on a HIP error.
+constexpr int kCgChunk = 64;
+
 bool run_cg(bte_problem *p, int corr, double *b, double *x_out, double rtol, int maxit, hipStream_t s)
 {
     const Dev &d = p->dev;
@@ -866,7 +874,7 @@ bool run_cg(bte_problem *p, int corr, double *b, double *x_out, double rtol, int
     // one launch per iteration, enqueued in chunks; between chunks the host
     // reads the done flag (one synchronisation per chunk)
     launch_cg_begin(d, g, b, s);
-    constexpr int kChunk = 64;
+    constexpr int kChunk = kCgChunk;
     for (int it0 = 0; it0 < maxit; it0 += kChunk) {
         launch_cg_iters(d, g, it0, std::min(kChunk, maxit - it0), s);
         if (it0 + kChunk < maxit) {
@@ -881,6 +889,39 @@ bool run_cg(bte_problem *p, int corr, double *b, double *x_out, double rtol, int
         launch_sub_film_mean(d, x_out, p->fmean, s);
     }
     return hipGetLastError() == hipSuccess;
+}
+
+// A captured launch sequence, instantiated once and replayed.
+struct Graph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    hipStream_t s = nullptr;
+    ~Graph()
+    {
+        if (x) {
+            (void)hipStreamSynchronize(s);   // no replay of it is left in flight
+            (void)hipGraphExecDestroy(x);
+        }
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
+// Capture the work `enqueue(cs)` puts on the capture stream cs into `gr`
+// (first call) and replay it on stream s (every call).  Kernels only:
+// nothing here records a memset.
+template <typename F> hipError_t graph_run(Graph &gr, hipStream_t cs, hipStream_t s, F &&enqueue)
+{
+    hipError_t r;
+    if (!gr.x) {
+        gr.s = s;
+        if ((r = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return r;
+        const bool ok = enqueue(cs);
+        r = hipStreamEndCapture(cs, &gr.g);
+        if (!ok && r == hipSuccess) r = hipErrorUnknown;
+        if (r != hipSuccess) return r;
+        if ((r = hipGraphInstantiate(&gr.x, gr.g, nullptr, nullptr, 0)) != hipSuccess) return r;
+    }
+    return hipGraphLaunch(gr.x, s);
 }
 
 template <typename T>
@@ -926,6 +967,8 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
     } evg{ev};
     double active_cells = 0;
     for (const Film &fm : p->films) active_cells += fm.ncell;
+    Graph gsweep[2], gcg;   // captured in this call, replayed by its iterations
+    if (p->graphs && !p->cstream) HIPCHK(p, hipStreamCreateWithFlags(&p->cstream, hipStreamNonBlocking));
     for (int iter = 1; iter <= p->ctl.max_iter; ++iter) {
         const T *ein = buf[cur];
         T *eout = buf[1 - cur];
@@ -933,24 +976,39 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
         HIPCHK(p, hipEventRecord(ev[0], s));
         launch_walls<T>(d, ein, p->dpend, p->d_wrec, p->d_wden, p->din, p->nw, s);
         HIPCHK(p, hipEventRecord(ev[1], s));
-        for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
-            const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
-            if (p->dim == 2)
-                HIPCHK(p, launch_sweep2d<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items2, i0, cnt, p->na_oct,
-                                            p->nchunk_oct, p->part, s));
-            else
-                HIPCHK(p, launch_sweep_tile<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt, p->tdim,
-                                               p->na_oct, p->nchunk_oct, p->tile_cap, p->part, s));
-            st.sweep_launches += cnt > 0;
+        auto sweep = [&](hipStream_t q) -> bool {
+            for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
+                const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
+                const hipError_t r =
+                    p->dim == 2 ? launch_sweep2d<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items2, i0, cnt,
+                                                    p->na_oct, p->nchunk_oct, p->part, q)
+                                : launch_sweep_tile<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt,
+                                                       p->tdim, p->na_oct, p->nchunk_oct, p->tile_cap, p->part, q);
+                if (r != hipSuccess) return false;
+            }
+            return true;
+        };
+        if (p->graphs) {
+            HIPCHK(p, graph_run(gsweep[cur], p->cstream, s, sweep));
+        } else if (!sweep(s)) {
+            FAIL(p, BTE_ERR_HIP, "sweep launch failed");
         }
+        for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) st.sweep_launches += p->diag_off[dg + 1] > p->diag_off[dg];
         HIPCHK(p, hipEventRecord(ev[2], s));
         launch_steady_post(d, p->part, np, p->TL, p->TLkin, p->T1, p->q1, p->r, synthetic, s);
         launch_film_eps(d, p->T0, p->T1, p->q0, p->q1, p->feps, p->fpart, p->fseg, s);
         HIPCHK(p, hipEventRecord(ev[3], s));
         HIPCHK(p, hipGetLastError());
         if (synthetic) {
-            if (!run_cg(p, 1, p->r, p->delta, p->ctl.cg_rtol, p->ctl.cg_max_iter, s))
+            // a CG solve without host checks (cg_max_iter <= one chunk) is a
+            // fixed launch sequence: replayed from a graph
+            if (p->graphs && p->ctl.cg_max_iter <= kCgChunk) {
+                HIPCHK(p, graph_run(gcg, p->cstream, s, [&](hipStream_t q) {
+                    return run_cg(p, 1, p->r, p->delta, p->ctl.cg_rtol, p->ctl.cg_max_iter, q);
+                }));
+            } else if (!run_cg(p, 1, p->r, p->delta, p->ctl.cg_rtol, p->ctl.cg_max_iter, s)) {
                 FAIL(p, BTE_ERR_HIP, "CG failed");
+            }
             launch_tl_update(nc, p->TLkin, p->delta, p->TL, p->dpend, d.fid, d.fdone, s);
         } else {
             launch_tl_update(nc, p->TLkin, nullptr, p->TL, nullptr, d.fid, d.fdone, s);
@@ -1486,6 +1544,13 @@ bte_status bte_get_directions(const bte_problem *p, double *s_host, double *w_ho
 }
 
 const char *bte_last_error(const bte_problem *p) { return p ? p->err.c_str() : "null handle"; }
+
+bte_status bte_set_graphs(bte_problem *p, int on)
+{
+    if (!p) return BTE_ERR_ARG;
+    p->graphs = on != 0;
+    return BTE_OK;
+}
 
 bte_status bte_set_timing(bte_problem *p, int on)
 {

@@ -1,0 +1,61 @@
+"""HIP graphs of the steady iteration give the same results as plain
+launches: the sweep graphs (one per buffer parity) and the CG graph are
+replayed every source iteration, with the host's convergence check and
+synchronisation between replays; the final fields must be bitwise equal to
+those of the same solve with plain launches."""
+import numpy as np
+import pytest
+
+import bte_inputs as I
+from tests.helpers import small_cases
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_14181_amd import bte
+    bte.load()
+    return bte
+
+
+def dev(x):
+    return None if x is None else torch.as_tensor(np.asarray(x, dtype=np.float64), device="cuda")
+
+
+def solve(B, geo, mat, P, gam, prec, lim, graphs, cg_max_iter):
+    prob = B.Problem(geo, mat, dict(precision=prec, scheme=B.SYNTHETIC, limiter=lim, residual_temp=1e-9,
+                                    residual_flux=1e-8, max_iter=400, cg_rtol=1e-10, cg_max_iter=cg_max_iter))
+    prob.set_graphs(graphs)
+    prob.set_fields(dev(P), dev(gam))
+    e = prob.zeros()
+    st = prob.steady_solve(e, init=True, allow_not_converged=True)
+    torch.cuda.synchronize()
+    return e.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("name", ["walls2d", "periodic2d", "box3d"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_graph_replays_equal_plain_launches(B, name, prec):
+    cases = small_cases()
+    if name not in cases:
+        pytest.skip("case not defined")
+    g, m, P, gam = cases[name]
+    p = B.F64 if prec == "f64" else B.F32
+    a, sa = solve(B, g, m, P, gam, p, B.LIM_NONE, False, 30)
+    b, sb = solve(B, g, m, P, gam, p, B.LIM_NONE, True, 30)
+    assert sa["iters"] == sb["iters"] and sa["iters"] > 2
+    assert np.array_equal(a, b)
+
+
+def test_graph_batch_with_masks_equals_plain_launches(B):
+    cfg = I.config3(seed=5, n_films=5, sides=(16, 24, 32), n_bands=4, n_theta=1, n_phi=2)
+    films, mat = cfg["films"], cfg["material"]
+    a, sa = solve(B, films, mat, None, None, B.F32, B.LIM_MINMOD, False, 40)
+    b, sb = solve(B, films, mat, None, None, B.F32, B.LIM_MINMOD, True, 40)
+    assert sa["iters"] == sb["iters"] and sa["updates"] == sb["updates"]
+    assert np.array_equal(a, b)
