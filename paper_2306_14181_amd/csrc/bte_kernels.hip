@@ -523,12 +523,53 @@ __global__ __launch_bounds__(kBlock) void k_cg_start(Dev d, CgArgs g, const doub
 
 // step it: scalars from the partials of the previous launch, stopping test,
 // then the vector updates of step it and the partials of step it + 1
+// Everything one cell of k_cg_iter reads: none of it depends on the
+// scalars of the step, so the first cell's loads are issued before the
+// reduction of the previous launch's partials.
+struct CgCell {
+    double dg, R, W, S, p, x;
+    double cf[6], Rj[6], Wj[6], Sj[6], dgj[6];
+};
+
+__device__ inline void cg_cell_load(const Dev &d, const CgArgs &g, const double *__restrict__ R,
+                                    const double *__restrict__ W, const double *__restrict__ S, int c, CgCell &q)
+{
+    q.dg = g.dg[c];
+    q.R = R[c];
+    q.W = W[c];
+    q.S = S[c];
+    q.p = g.p[c];
+    q.x = g.x[c];
+    int j[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {   // unused faces have a zero coupling: they read the cell itself
+        q.cf[f] = g.coef[f * d.nc + c];
+        j[f] = q.cf[f] != 0.0 ? d.nb[f * d.nc + c] : c;
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        q.Rj[f] = R[j[f]];
+        q.Wj[f] = W[j[f]];
+        q.Sj[f] = S[j[f]];
+        q.dgj[f] = g.dg[j[f]];
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_cg_iter(Dev d, CgArgs g, int it)
 {
     __shared__ double sh[32];
     if (g.scal[5] != 0.0) return;
-    const int nb = gridDim.x, nthr = nb * kBlock, nf = 2 * d.dim;
+    const int nb = gridDim.x, nthr = nb * kBlock;
     const int cur = it & 1, nxt = cur ^ 1;
+    const double *__restrict__ R = g.rb[cur];
+    const double *__restrict__ W = g.wb[cur];
+    const double *__restrict__ S = g.sb[nxt];   // s_(it-1)
+    double *__restrict__ RN = g.rb[nxt];
+    double *__restrict__ WN = g.wb[nxt];
+    double *__restrict__ SN = g.sb[cur];        // s_it
+    const int c0 = blockIdx.x * kBlock + threadIdx.x;
+    CgCell q;
+    cg_cell_load(d, g, R, W, S, c0 < d.nc ? c0 : 0, q);
     double ga, de, rr;
     part_sum3(g.part + 3 * nb * cur, nb, sh, ga, de, rr);
     const double bn2 = it == 0 ? rr : g.scal[1];
@@ -550,31 +591,21 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Dev d, CgArgs g, int it)
         }
         return;
     }
-    const double *__restrict__ R = g.rb[cur];
-    const double *__restrict__ W = g.wb[cur];
-    const double *__restrict__ S = g.sb[nxt];   // s_(it-1)
-    double *__restrict__ RN = g.rb[nxt];
-    double *__restrict__ WN = g.wb[nxt];
-    double *__restrict__ SN = g.sb[cur];        // s_it
     double gn = 0, dn = 0, rn2 = 0;
-    for (int c = blockIdx.x * kBlock + threadIdx.x; c < d.nc; c += nthr) {
-        const double dg = g.dg[c];
-        const double uc = R[c] / dg;
-        const double pc = uc + beta * g.p[c];
-        const double sc = W[c] + beta * S[c];
+    for (int c = c0; c < d.nc; c += nthr) {
+        if (c != c0) cg_cell_load(d, g, R, W, S, c, q);
+        const double uc = q.R / q.dg;
+        const double pc = uc + beta * q.p;
+        const double sc = q.W + beta * q.S;
         g.p[c] = pc;
         SN[c] = sc;
-        g.x[c] += alpha * pc;
-        const double rc = R[c] - alpha * sc;
+        g.x[c] = q.x + alpha * pc;
+        const double rc = q.R - alpha * sc;
         RN[c] = rc;
-        const double un = rc / dg;
-        double acc = dg * un;
-        for (int f = 0; f < nf; ++f) {
-            const double cf = g.coef[f * d.nc + c];
-            const int j = cf != 0.0 ? d.nb[f * d.nc + c] : c;
-            const double uj = (R[j] - alpha * (W[j] + beta * S[j])) / g.dg[j];
-            acc -= cf * uj;
-        }
+        const double un = rc / q.dg;
+        double acc = q.dg * un;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) acc -= q.cf[f] * ((q.Rj[f] - alpha * (q.Wj[f] + beta * q.Sj[f])) / q.dgj[f]);
         WN[c] = acc;
         gn += rc * un;
         dn += acc * un;
