@@ -55,17 +55,18 @@ __device__ inline int cell2_any(const Frame2 &F, int f0, int f1, double &jump)
     int i0 = F.o0 + (F.sg0 > 0 ? f0 : F.e0 - 1 - f0);
     int i1 = F.o1 + (F.sg1 > 0 ? f1 : F.e1 - 1 - f1);
     jump = 0.0;
+    // each crossing of the low face adds +C dT/4pi (two on an axis of one cell)
     if (i0 < 0 || i0 >= F.n0) {
         if (!F.per0) return -1;
-        jump += (i0 < 0 ? 1.0 : -1.0) * F.pdT0;   // the low face adds +C dT/4pi
-        i0 = i0 < 0 ? i0 + F.n0 : i0 - F.n0;
-        if (i0 < 0 || i0 >= F.n0) i0 = ((i0 % F.n0) + F.n0) % F.n0;
+        const int w = periods(i0, F.n0);
+        jump -= w * F.pdT0;
+        i0 -= w * F.n0;
     }
     if (i1 < 0 || i1 >= F.n1) {
         if (!F.per1) return -1;
-        jump += (i1 < 0 ? 1.0 : -1.0) * F.pdT1;
-        i1 = i1 < 0 ? i1 + F.n1 : i1 - F.n1;
-        if (i1 < 0 || i1 >= F.n1) i1 = ((i1 % F.n1) + F.n1) % F.n1;
+        const int w = periods(i1, F.n1);
+        jump -= w * F.pdT1;
+        i1 -= w * F.n1;
     }
     return F.cell0 + i0 + F.n0 * i1;
 }

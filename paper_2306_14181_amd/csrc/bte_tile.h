@@ -126,6 +126,9 @@ __device__ inline int tile_up1(const TileCtx t, int s)
 
 // global cell of flow position f and the signed count of periodic crossings;
 // returns -1 for walls, pores and positions outside a non-periodic domain
+// Whole periods between position i and the cell range [0, n): floor(i / n).
+__host__ __device__ inline int periods(int i, int n) { return i >= 0 ? i / n : -((n - 1 - i) / n); }
+
 __device__ inline int tile_cell(const TileCtx t, const Film &fm, const Dev &d, int f0, int f1, int f2, int &jump)
 {
     int i0 = t.o0 + (t.sg0 > 0 ? f0 : t.e0 - 1 - f0);
@@ -133,20 +136,25 @@ __device__ inline int tile_cell(const TileCtx t, const Film &fm, const Dev &d, i
     int i2 = t.o2 + (t.sg2 > 0 ? f2 : t.e2 - 1 - f2);
     jump = 0;
     const int n0 = fm.n[0], n1 = fm.n[1], n2 = fm.n[2];
+    // every crossing of the low face adds +C dT/4pi, of the high face
+    // -C dT/4pi (a slot two cells out on an axis of one cell is two periods away)
     if (i0 < 0 || i0 >= n0) {
         if (!fm.periodic[0]) return -1;
-        jump += i0 < 0 ? 1 : -1;   // crossing the low face adds +C dT/4pi
-        i0 = (i0 + n0) % n0;
+        const int w = periods(i0, n0);
+        jump -= w;
+        i0 -= w * n0;
     }
     if (i1 < 0 || i1 >= n1) {
         if (!fm.periodic[1]) return -1;
-        jump += i1 < 0 ? 1 : -1;
-        i1 = (i1 + n1) % n1;
+        const int w = periods(i1, n1);
+        jump -= w;
+        i1 -= w * n1;
     }
     if (i2 < 0 || i2 >= n2) {
         if (!fm.periodic[2]) return -1;
-        jump += i2 < 0 ? 1 : -1;
-        i2 = (i2 + n2) % n2;
+        const int w = periods(i2, n2);
+        jump -= w;
+        i2 -= w * n2;
     }
     const int c = fm.cell0 + i0 + n0 * (i1 + n1 * i2);
     return (d.code[c] & kSolidBit) ? c : -1;

@@ -32,16 +32,16 @@ __device__ inline double rl_d(double v, int lane)
 }
 
 // Position i along an axis of n cells: itself inside, the periodic image
-// outside (jump +1 past the low face, -1 past the high face, in units of
-// C dT / 4pi), -1 outside a non-periodic domain.
+// outside (jump +1 per crossing of the low face, -1 per crossing of the high
+// face, in units of C dT / 4pi), -1 outside a non-periodic domain.
 __device__ inline int wrap_pos(int i, int n, int per, int &jump)
 {
     jump = 0;
     if (i >= 0 && i < n) return i;
     if (!per) return -1;
-    jump = i < 0 ? 1 : -1;
-    const int r = i < 0 ? i + n : i - n;
-    return (r >= 0 && r < n) ? r : ((i % n) + n) % n;   // the modulo only for axes of one or two cells
+    const int w = periods(i, n);
+    jump = -w;
+    return i - w * n;
 }
 
 // Face-value difference of one axis on the general path (missing
