@@ -54,6 +54,9 @@ hipError_t launch_transient3d(const Dev &, const T *, T *, const double *, const
 template <typename T>
 hipError_t launch_adj_step(const Dev &, const T *, T *, const T *, const double *, const double *, const TileItem *,
                            int, int3, int, int, int, double, double *, hipStream_t);
+template <typename T>
+hipError_t launch_adj_step3d(const Dev &, const T *, T *, const T *, const double *, const double *, const ColItem *,
+                             int, int, int, double, double *, hipStream_t);
 void launch_adj_step_post(const Dev &, const double *, int, const double *, double *, double *, double,
                           hipStream_t);
 template <typename T> void launch_adj_tave_init(const Dev &, const double *, double, T *, hipStream_t);
@@ -1364,10 +1367,17 @@ bte_status tadj_impl(bte_problem *p, const T *e0, int n_steps, double t0, const 
             HIPCHK(p, one_step<T>(p, SG(j - 1), SG(j), pulse_factor(pulse, t0 + (start + j - 1) * dt), nullptr, s));
         for (int j = len - 1; j >= 0; --j) {
             launch_walls_adj<T>(d, lam[lc], p->d_wrec, p->d_wden, p->din, p->nw, s);
-            HIPCHK(p, launch_adj_step<T>(d, lam[lc], lam[1 - lc], SG(j), X[lc], p->din, p->d_titems,
-                                         (int)p->titems.size(), p->tdim_tr, p->na_oct, p->nchunk_oct,
-                                         p->tile_cap_tr, dt, p->part, s));
-            launch_adj_step_post(d, p->part, p->noct, X[lc], X[1 - lc], grad, dt, s);
+            int np = p->noct;
+            if (p->dim == 3) {
+                HIPCHK(p, launch_adj_step3d<T>(d, lam[lc], lam[1 - lc], SG(j), X[lc], p->din, p->d_citems,
+                                               (int)p->citems.size(), p->na_oct, p->nchunk_oct, dt, p->part, s));
+                np = p->noct * p->nchunk_oct;
+            } else {
+                HIPCHK(p, launch_adj_step<T>(d, lam[lc], lam[1 - lc], SG(j), X[lc], p->din, p->d_titems,
+                                             (int)p->titems.size(), p->tdim_tr, p->na_oct, p->nchunk_oct,
+                                             p->tile_cap_tr, dt, p->part, s));
+            }
+            launch_adj_step_post(d, p->part, np, X[lc], X[1 - lc], grad, dt, s);
             lc = 1 - lc;
         }
     }

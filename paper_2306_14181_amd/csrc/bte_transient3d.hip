@@ -335,6 +335,304 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
     }
 }
 
+// Transposed explicit step of the transient adjoint (reverse mode of
+// e^{k+1} = e^k + dt R(e^k)) on three-dimensional geometries, column by
+// column like k_transient3d:  lam^k = lam^{k+1} + dt J^T lam^{k+1} with the
+// forward state e^k read alongside for the gradient.  The item's octant
+// fixes the frame; the lanes are those of the opposite octant, so in this
+// frame the transposed stencil has the forward shape (two cells "upwind",
+// one "downwind") and the same interior coefficients (central slopes, no
+// limiter, no jumps: the transposed operator is linear).  Walls: a specular
+// wall feeds the mirror lane's lam, a diffuse wall the record dinA (k_walls_adj)
+// with weight w |s_a|, at the wall cell (3/2 or 1) and at its neighbour (-1/2).
+// Per (octant, chunk, cell) five partial sums go to
+// part[((octant * nchunk + chunk) * 5 + q) * nc + cell]:
+//   q = 0: sum C/(4 pi) (1/tau) lam^k,  q = 1: sum lam^{k+1} e^k,
+//   q = 2: sum lam^{k+1} C/(4 pi),      q = 3: sum w e^k,  q = 4: sum w (1/tau) e^k.
+namespace {
+
+// One axis of (J^T lam) on the general path (missing neighbours, walls).
+template <typename T>
+__device__ inline T adj_axis3(const Dev &d, const T *__restrict__ lam, const double *__restrict__ dinA, int c,
+                              uint32_t code, int c1, uint32_t code1, int a, int sg, bool hu, bool hu2, bool hd,
+                              bool hd2, T lc, T a1, T a2, T ad, int al, int l, T cpl, T wsa)
+{
+    const T cjj = hu ? (hd ? (T)1 : (T)0.5) : (hd ? (T)1.5 : (T)1);
+    T tx = cjj * (hu ? a1 - lc : -lc);
+    if (hd) tx += (hd2 ? (T)0.25 : (T)0.5) * (lc - ad);
+    if (hu) tx += hu2 ? (T)-0.25 * (a2 - a1) : (T)0.5 * a1;
+    T out = cpl * tx;
+    if (!hu) {
+        // wall on the frame's upwind side of this cell
+        const int kind = side_wall(axis_bits(code, a), -sg);
+        const T cw = hd ? (T)1.5 : (T)1;
+        if (kind == 1) {
+            const int km = d.mirror[a * d.na + al] * d.nl + l;
+            out += cpl * cw * lam[(size_t)c * d.nk + km];
+        } else if (kind == 2) {
+            const int rec = diffuse_index(d, c, code, face_of(a, -sg));
+            out += wsa * cw * (T)dinA[(size_t)rec * d.nl + l];
+        }
+    } else if (!hu2 && c1 >= 0) {
+        // wall on the frame's upwind side of the upwind cell
+        const int kind2 = side_wall(axis_bits(code1, a), -sg);
+        if (kind2 == 1) {
+            const int km = d.mirror[a * d.na + al] * d.nl + l;
+            out -= (T)0.5 * cpl * lam[(size_t)c1 * d.nk + km];
+        } else if (kind2 == 2) {
+            const int rec = diffuse_index(d, c1, code1, face_of(a, -sg));
+            out -= (T)0.5 * wsa * (T)dinA[(size_t)rec * d.nl + l];
+        }
+    }
+    return out;
+}
+
+}  // namespace
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__ lam, T *__restrict__ lout,
+                                                    const T *__restrict__ ek, const double *__restrict__ X,
+                                                    const double *__restrict__ dinA,
+                                                    const ColItem *__restrict__ items, int nitems, int na_oct,
+                                                    int nchunk_oct, double dt, double *__restrict__ part)
+{
+    // five partials of four consecutive cells per wavefront, reduced
+    // transposed (lane = 16 cell + part) every four cells
+    __shared__ double red[4][5][4][64];
+    const int nb = gridDim.x, bb = blockIdx.x;
+    const int lb = (bb & 7) * (nb >> 3) + (bb >> 3);
+    const int wi = lb * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wi >= nitems) return;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const ColItem it = items[wi];
+    const Film &fm = d.film[it.film];
+    const int sg0 = octant_sign(d, it.oct, na_oct, 0), sg1 = octant_sign(d, it.oct, na_oct, 1),
+              sg2 = octant_sign(d, it.oct, na_oct, 2);
+    const int nl = d.nl, nk = d.nk, nc = d.nc;
+    const int loct = it.oct ^ 7;
+    const int kbeg = loct * na_oct * nl, kend = kbeg + na_oct * nl;
+    const int k = kbeg + it.chunk * 64 + lane;
+    const bool active = k < kend;
+    const int kk = active ? k : kbeg;
+    const LaneT<T> L = lane_make<T>(d, fm, kk);
+    T wsa[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) wsa[a] = (T)(L.w * fabs(d.s[3 * L.al + a]));
+    const double c4 = d.C4[L.l], it0 = d.itau[L.l];
+    const int n0 = fm.n[0], n1 = fm.n[1], n2 = fm.n[2], plane = n0 * n1;
+    const int x = it.col % n0, y = it.col / n0;
+    const int cb = fm.cell0 + x + n0 * y;
+    const T *zrow = static_cast<const T *>(d.zrow);
+    const unsigned koff = (unsigned)kk * (unsigned)sizeof(T);
+    auto at = [&](const T *row) -> T { return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(row) + koff); };
+    int jx;
+    const int px1 = wrap_pos(x - sg0, n0, fm.periodic[0], jx), px2 = wrap_pos(x - 2 * sg0, n0, fm.periodic[0], jx),
+              pxd = wrap_pos(x + sg0, n0, fm.periodic[0], jx);
+    const int py1 = wrap_pos(y - sg1, n1, fm.periodic[1], jx), py2 = wrap_pos(y - 2 * sg1, n1, fm.periodic[1], jx),
+              pyd = wrap_pos(y + sg1, n1, fm.periodic[1], jx);
+    const int bx1 = px1 >= 0 ? fm.cell0 + px1 + n0 * y : -1, bx2 = px2 >= 0 ? fm.cell0 + px2 + n0 * y : -1,
+              bxd = pxd >= 0 ? fm.cell0 + pxd + n0 * y : -1;
+    const int by1 = py1 >= 0 ? fm.cell0 + x + n0 * py1 : -1, by2 = py2 >= 0 ? fm.cell0 + x + n0 * py2 : -1,
+              byd = pyd >= 0 ? fm.cell0 + x + n0 * pyd : -1;
+    auto zcell = [&](int f) -> int {
+        int jz;
+        const int zg = wrap_pos(sg2 > 0 ? f : n2 - 1 - f, n2, fm.periodic[2], jz);
+        return zg >= 0 ? cb + plane * zg : -1;
+    };
+    auto zval = [&](int f) -> T {
+        const int c = zcell(f);
+        return at(c >= 0 ? lam + (size_t)c * nk : zrow);
+    };
+    auto plus = [](int base, int off) { return base >= 0 ? base + off : -1; };
+
+    T z2 = zval(-2), z1 = zval(-1), zc = zval(0), zd = zval(1);
+    const T tdt = (T)dt;
+    const T itau = L.itau;
+
+    struct Pre {
+        T nz, x1, x2, xd, y1, y2, yd, e;
+    };
+    const long long zstep = (long long)(sg2 > 0 ? plane : -plane) * nk;
+    const int z0 = sg2 > 0 ? 0 : n2 - 1;
+    auto row0 = [&](const T *base, int b) -> const T * { return b >= 0 ? base + (size_t)(b + plane * z0) * nk : zrow; };
+    const T *rx1 = row0(lam, bx1), *rx2 = row0(lam, bx2), *rxd = row0(lam, bxd);
+    const T *ry1 = row0(lam, by1), *ry2 = row0(lam, by2), *ryd = row0(lam, byd);
+    const T *re = row0(ek, cb);
+    const long long sx1 = bx1 >= 0 ? zstep : 0, sx2 = bx2 >= 0 ? zstep : 0, sxd = bxd >= 0 ? zstep : 0;
+    const long long sy1 = by1 >= 0 ? zstep : 0, sy2 = by2 >= 0 ? zstep : 0, syd = byd >= 0 ? zstep : 0;
+    const T *rc0 = lam + (size_t)(cb + plane * z0) * nk;
+    auto prefetch = [&](int f, Pre &q) {
+        if (f + 1 < n2 && f >= 0) {
+            rx1 += sx1;
+            rx2 += sx2;
+            rxd += sxd;
+            ry1 += sy1;
+            ry2 += sy2;
+            ryd += syd;
+            re += zstep;
+        }
+        q.x1 = at(rx1);
+        q.x2 = at(rx2);
+        q.xd = at(rxd);
+        q.y1 = at(ry1);
+        q.y2 = at(ry2);
+        q.yd = at(ryd);
+        q.e = at(re);
+        const T *rz;
+        if (f + 3 < n2) {
+            rz = rc0 + (long long)(f + 3) * zstep;
+        } else {
+            const int c = zcell(f + 3);
+            rz = c >= 0 ? lam + (size_t)c * nk : zrow;
+        }
+        q.nz = at(rz);
+    };
+    // per-cell records of a run of 64 cells, one per lane: codes of the cell
+    // and of its frame-upwind / frame-downwind neighbours along x, y, z,
+    // the closure term X and gamma
+    uint32_t r_code = 0, r_cxu = 0, r_cyu = 0, r_cxd = 0, r_cyd = 0, r_czu = 0, r_czd = 0;
+    double r_X = 0, r_gam = 0;
+    auto records = [&](int f0) {
+        const int fl = min(f0 + lane, n2 - 1);
+        const int o = plane * (sg2 > 0 ? fl : n2 - 1 - fl);
+        const int c = cb + o;
+        r_code = d.code[c];
+        const uint32_t cxu = d.code[bx1 >= 0 ? bx1 + o : c], cyu = d.code[by1 >= 0 ? by1 + o : c];
+        const uint32_t cxd = d.code[bxd >= 0 ? bxd + o : c], cyd = d.code[byd >= 0 ? byd + o : c];
+        r_cxu = bx1 >= 0 ? cxu : 0u;
+        r_cyu = by1 >= 0 ? cyu : 0u;
+        r_cxd = bxd >= 0 ? cxd : 0u;
+        r_cyd = byd >= 0 ? cyd : 0u;
+        const int cu = zcell(fl - 1), cd = zcell(fl + 1);
+        const uint32_t czu = d.code[cu >= 0 ? cu : c], czd = d.code[cd >= 0 ? cd : c];
+        r_czu = cu >= 0 ? czu : 0u;
+        r_czd = cd >= 0 ? czd : 0u;
+        r_X = X[c];
+        r_gam = d.gamma[c];
+    };
+    auto rlu = [&](uint32_t v, int q) -> uint32_t { return (uint32_t)__builtin_amdgcn_readlane((int)v, q); };
+    double *__restrict__ pbase = part + (size_t)((it.oct * nchunk_oct + it.chunk) * 5) * nc;
+
+    auto step = [&](int f, const Pre &in, Pre &out) {
+        const int zo = plane * (sg2 > 0 ? f : n2 - 1 - f);
+        const int c = cb + zo;
+        prefetch(f, out);
+        const int q = f & 63;
+        const uint32_t code = rlu(r_code, q);
+        const bool solid = code & kSolidBit;
+        T ln = (T)0;
+        double acc[5] = {0, 0, 0, 0, 0};
+        if (solid) {
+            const uint32_t cxu = rlu(r_cxu, q), cyu = rlu(r_cyu, q), czu = rlu(r_czu, q);
+            const uint32_t cxd = rlu(r_cxd, q), cyd = rlu(r_cyd, q), czd = rlu(r_czd, q);
+            const double Xc = rl_d(r_X, q), gam = rl_d(r_gam, q);
+            const uint32_t ab0 = axis_bits(code, 0), ab1 = axis_bits(code, 1), ab2 = axis_bits(code, 2);
+            const bool hu0 = side_is_cell(ab0, -sg0), hd0 = side_is_cell(ab0, sg0);
+            const bool hu1 = side_is_cell(ab1, -sg1), hd1 = side_is_cell(ab1, sg1);
+            const bool hu2 = side_is_cell(ab2, -sg2), hd2 = side_is_cell(ab2, sg2);
+            const bool hu20 = hu0 && side_is_cell(axis_bits(cxu, 0), -sg0);
+            const bool hu21 = hu1 && side_is_cell(axis_bits(cyu, 1), -sg1);
+            const bool hu22 = hu2 && side_is_cell(axis_bits(czu, 2), -sg2);
+            const bool hd20 = hd0 && side_is_cell(axis_bits(cxd, 0), sg0);
+            const bool hd21 = hd1 && side_is_cell(axis_bits(cyd, 1), sg1);
+            const bool hd22 = hd2 && side_is_cell(axis_bits(czd, 2), sg2);
+            T tf;
+            {
+                T tx;
+                if (hu0 && hu20 && hd0 && hd20) tx = L.cpl[0] * ((in.x1 - zc) + (T)0.25 * ((zc - in.xd) - (in.x2 - in.x1)));
+                else
+                    tx = adj_axis3<T>(d, lam, dinA, c, code, plus(bx1, zo), cxu, 0, sg0, hu0, hu20, hd0, hd20, zc,
+                                      in.x1, in.x2, in.xd, L.al, L.l, L.cpl[0], wsa[0]);
+                T ty;
+                if (hu1 && hu21 && hd1 && hd21) ty = L.cpl[1] * ((in.y1 - zc) + (T)0.25 * ((zc - in.yd) - (in.y2 - in.y1)));
+                else
+                    ty = adj_axis3<T>(d, lam, dinA, c, code, plus(by1, zo), cyu, 1, sg1, hu1, hu21, hd1, hd21, zc,
+                                      in.y1, in.y2, in.yd, L.al, L.l, L.cpl[1], wsa[1]);
+                T tz;
+                if (hu2 && hu22 && hd2 && hd22) tz = L.cpl[2] * ((z1 - zc) + (T)0.25 * ((zc - zd) - (z2 - z1)));
+                else
+                    tz = adj_axis3<T>(d, lam, dinA, c, code, zcell(f - 1), czu, 2, sg2, hu2, hu22, hd2, hd22, zc, z1,
+                                      z2, zd, L.al, L.l, L.cpl[2], wsa[2]);
+                tf = (tx + ty) + tz;
+            }
+            const T itc = itau + (T)gam;
+            ln = zc + tdt * (tf - zc * itc + (T)L.w * itc * (T)Xc);
+            if (active) {
+                const double xe = (double)in.e, itd = it0 + gam;
+                acc[0] = c4 * itd * (double)ln;
+                acc[1] = (double)zc * xe;
+                acc[2] = (double)zc * c4;
+                acc[3] = L.w * xe;
+                acc[4] = L.w * itd * xe;
+            }
+        }
+        if (active) lout[(size_t)c * nk + k] = ln;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) red[wv][m][f & 3][lane] = acc[m];
+        if ((f & 3) == 3 || f == n2 - 1) {
+            const int j = lane >> 4, pp = lane & 15, fb = f & ~3;
+            const int fj = fb + j;
+            double v[5];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                double t = 0.0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) t += red[wv][m][j][4 * pp + i];
+                t += dpp_f64<0xB1>(t);    // quad_perm [1,0,3,2]
+                t += dpp_f64<0x4E>(t);    // quad_perm [2,3,0,1]
+                t += dpp_f64<0x141>(t);   // row_half_mirror
+                t += dpp_f64<0x140>(t);   // row_mirror
+                v[m] = t;
+            }
+            if (pp == 0 && fj <= f) {
+                const int cj = cb + plane * (sg2 > 0 ? fj : n2 - 1 - fj);
+#pragma unroll
+                for (int m = 0; m < 5; ++m) pbase[(size_t)m * nc + cj] = v[m];
+            }
+        }
+        z2 = z1;
+        z1 = zc;
+        zc = zd;
+        zd = in.nz;
+    };
+
+    Pre A, B;
+    prefetch(-1, A);
+    for (int f0 = 0; f0 < n2; f0 += 64) {
+        records(f0);
+        const int f1 = min(f0 + 64, n2);
+        int f = f0;
+        for (; f + 1 < f1; f += 2) {
+            step(f, A, B);
+            step(f + 1, B, A);
+        }
+        if (f < f1) {
+            step(f, A, B);
+            A = B;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_adj_step3d(const Dev &d, const T *lam, T *lout, const T *ek, const double *X, const double *dinA,
+                             const ColItem *items, int nitems, int na_oct, int nchunk_oct, double dt, double *part,
+                             hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    const int blocks = ((nitems + 3) / 4 + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_adj_step3d<T>), dim3(blocks), dim3(256), 0, s, d, lam, lout, ek, X, dinA, items, nitems,
+                       na_oct, nchunk_oct, dt, part);
+    return hipGetLastError();
+}
+
+template hipError_t launch_adj_step3d<float>(const Dev &, const float *, float *, const float *, const double *,
+                                             const double *, const ColItem *, int, int, int, double, double *,
+                                             hipStream_t);
+template hipError_t launch_adj_step3d<double>(const Dev &, const double *, double *, const double *, const double *,
+                                              const double *, const ColItem *, int, int, int, double, double *,
+                                              hipStream_t);
+
 template <typename T, int LIM>
 void transient3d_launch(const Dev &d, const T *ein, T *eout, const double *TLdev, const double *din,
                         const ColItem *items, int nitems, int na_oct, int nchunk_oct, double src, double dt,

@@ -45,6 +45,24 @@ def cases():
     g3, m3, _, gam3 = small_cases()["periodic2d"]
     w3 = rng.uniform(0, 1, 90) * (np.asarray(g3["solid"]) > 0)
     out["periodic2d"] = (g3, m3, rng.uniform(0, 1e17, 90), gam3, w3, 0.2e-12, 16, (1e-12, 2e-12))
+    # three-dimensional column paths: periodic x / y with pores, specular,
+    # diffuse and thermalizing walls; a periodic z axis with pores; a column
+    # longer than one 64-cell run of per-cell records
+    g4, m4, P4, gam4 = small_cases()["box3d"]
+    w4 = rng.uniform(0, 1, 270) * (np.asarray(g4["solid"]) > 0)
+    out["box3d"] = (g4, m4, P4, gam4, w4, 0.2e-12, 12, (1e-12, 2e-12))
+    solid = np.ones(4 * 3 * 5, dtype=np.uint8)
+    solid[[5, 17, 30, 46]] = 0
+    g5 = geo(3, (4, 3, 5), (0.2e-6, 0.15e-6, 0.25e-6),
+             [I.BC_SPECULAR, I.BC_DIFFUSE, I.BC_THERMAL, I.BC_SPECULAR, I.BC_PERIODIC, I.BC_PERIODIC],
+             pdT=(0, 0, 0.4), bcT=[300, 300, 299.5, 300, 300, 300], solid=solid)
+    out["zper3d"] = (g5, mat(b, 1, 2), rng.uniform(0, 1e17, 60), rng.uniform(0, 1e11, 60),
+                     rng.uniform(0, 1, 60) * solid, 0.2e-12, 10, (1e-12, 2e-12))
+    g6 = geo(3, (2, 2, 70), (0.1e-6, 0.1e-6, 3.5e-6),
+             [I.BC_SPECULAR, I.BC_DIFFUSE, I.BC_SPECULAR, I.BC_SPECULAR, I.BC_THERMAL, I.BC_DIFFUSE],
+             bcT=[300, 300, 300, 300, 300.5, 300])
+    out["tall3d"] = (g6, mat(b, 1, 2), rng.uniform(0, 1e17, 280), rng.uniform(0, 1e11, 280),
+                     rng.uniform(0, 1, 280), 0.3e-12, 8, (1e-12, 2e-12))
     return out
 
 
@@ -68,7 +86,7 @@ def gpu_run(B, name, prec, every):
     return J, grad.cpu().numpy(), prob
 
 
-@pytest.mark.parametrize("name", ["laser3d", "walls2d", "periodic2d"])
+@pytest.mark.parametrize("name", ["laser3d", "walls2d", "periodic2d", "box3d", "zper3d", "tall3d"])
 def test_transient_adjoint_fp64_matches_oracle(B, name):
     Jr, gr = oracle_ref(name)
     J, g, _ = gpu_run(B, name, B.F64, every=7)
@@ -76,9 +94,10 @@ def test_transient_adjoint_fp64_matches_oracle(B, name):
     assert rel_err(g, gr) < 1e-10, rel_err(g, gr)
 
 
-def test_transient_adjoint_fp32_matches_oracle(B):
-    Jr, gr = oracle_ref("laser3d")
-    J, g, _ = gpu_run(B, "laser3d", B.F32, every=5)
+@pytest.mark.parametrize("name", ["laser3d", "box3d"])
+def test_transient_adjoint_fp32_matches_oracle(B, name):
+    Jr, gr = oracle_ref(name)
+    J, g, _ = gpu_run(B, name, B.F32, every=5)
     assert abs(J - Jr) <= 1e-6 * abs(Jr), (J, Jr)
     assert rel_err(g, gr) < 1e-4, rel_err(g, gr)
 
