@@ -346,6 +346,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true", help="plain launches instead of HIP graph replays")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU sharding is not implemented",
@@ -384,6 +385,7 @@ def main():
     precs = [B.F32] if args.no_fp64 else [B.F32, B.F64]
     for prec in precs:
         prob = B.Problem(geo, mat, dict(base_ctl, precision=prec))
+        prob.set_graphs(not args.no_graphs)
         prob.set_fields(P, None)
         e = prob.zeros()
         updates = prob.n_cells * prob.n_dirs * prob.n_bands

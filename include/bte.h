@@ -240,6 +240,14 @@ bte_status bte_set_timing(bte_problem *p, int on);
  * results are the same as with plain launches. */
 bte_status bte_set_graphs(bte_problem *p, int on);
 
+/* Launch form of the two-dimensional steady sweep (the transport sweep of
+ * Algorithm 1, Sec. 3.3-3.5).  The sweep is one launch per tile diagonal;
+ * on == 0 confirms that and returns BTE_OK.  A single work-queue launch
+ * (blocks taking the tiles in diagonal order, each waiting for its upwind
+ * tiles) is not available: on != 0 returns BTE_ERR_UNSUPPORTED and changes
+ * nothing. */
+bte_status bte_set_persistent(bte_problem *p, int on);
+
 /* Statistics of the last bte_steady_solve, or of the last timed
  * bte_transient_step (iters = steps, ms_sweep = transport kernels, ms_walls =
  * wall kernels, ms_post = T_L updates). */

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "E
 EXPORTS = ["bte_setup", "bte_set_control", "bte_workspace_bytes", "bte_num_unknowns", "bte_num_cells", "bte_num_directions",
            "bte_bind", "bte_set_fields", "bte_moments", "bte_residual", "bte_transient_step",
            "bte_steady_solve", "bte_keff", "bte_adjoint", "bte_transient_adjoint", "bte_transient_adjoint_bytes",
-           "bte_set_timing", "bte_set_graphs", "bte_last_stats",
+           "bte_set_timing", "bte_set_graphs", "bte_set_persistent", "bte_last_stats",
            "bte_get_directions", "bte_last_error", "bte_destroy"]
 
 
@@ -98,6 +98,7 @@ def load():
         "bte_transient_adjoint_bytes": ([vp, C.c_int, C.c_int], C.c_size_t),
         "bte_set_timing": ([vp, C.c_int], st),
         "bte_set_graphs": ([vp, C.c_int], st),
+        "bte_set_persistent": ([vp, C.c_int], st),
         "bte_last_stats": ([vp, C.POINTER(SolveStats)], st),
         "bte_get_directions": ([vp, dp, dp], st),
         "bte_last_error": ([vp], C.c_char_p),
@@ -308,6 +309,11 @@ class Problem:
     def set_graphs(self, on=True):
         """Capture the steady sweep and CG launches in HIP graphs (default on)."""
         self._check(load().bte_set_graphs(self._h, int(bool(on))))
+
+    def set_persistent(self, on=False):
+        """Launch form of the two-dimensional sweep: one launch per tile diagonal (on=False); the
+        work-queue form (on=True) is not available and raises BteError."""
+        self._check(load().bte_set_persistent(self._h, int(bool(on))))
 
     def last_stats(self):
         st = SolveStats()

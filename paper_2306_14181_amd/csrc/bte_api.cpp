@@ -1562,6 +1562,13 @@ bte_status bte_set_graphs(bte_problem *p, int on)
     return BTE_OK;
 }
 
+bte_status bte_set_persistent(bte_problem *p, int on)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (on) FAIL(p, BTE_ERR_UNSUPPORTED, "the work-queue form of the sweep is not available");
+    return BTE_OK;
+}
+
 bte_status bte_set_timing(bte_problem *p, int on)
 {
     if (!p) return BTE_ERR_ARG;
