@@ -262,6 +262,14 @@ def bench_adjoint(args):
     prob = B.Problem(g, mat, ctl)
     prob.set_fields(None, torch.as_tensor(cfg["gamma"], device="cuda"))
     e = prob.zeros()
+    tune = []
+    if not args.no_autotune:
+        # tile shape of the LDS-tile sweeps (forward and adjoint), chosen by timing every candidate
+        tune = prob.autotune(reps=2, scratch=e)
+        for x in tune:
+            log("autotune %s tile %s: %.2f ms per sweep%s" % ("sweep" if x["kind"] == B.TUNE_SWEEP else "step",
+                                                               "x".join(map(str, x["tile"])), x["ms"],
+                                                               "  (kept)" if x["chosen"] else ""))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = prob.steady_solve(e, init=True, allow_not_converged=True)
@@ -289,6 +297,7 @@ def bench_adjoint(args):
            "adjoint": {"sweeps": sa["iters"], "converged": sa["converged"], "relative_residual": sa["eps_T"],
                        "solve_s": ta, "ms_sweep_per_iteration": sa["ms_sweep"] / max(sa["iters"], 1)},
            "adjoint_over_forward_time": ta / tf,
+           "autotune": [{"tile": list(x["tile"]), "ms_per_sweep": x["ms"], "chosen": x["chosen"]} for x in tune],
            "grad": {"min": float(gr.min()), "max": float(gr.max()), "sum": float(gr.sum())}}
     print(json.dumps(out), flush=True)
 
@@ -347,6 +356,7 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-graphs", action="store_true", help="plain launches instead of HIP graph replays")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU sharding is not implemented",

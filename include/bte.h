@@ -248,6 +248,46 @@ bte_status bte_set_graphs(bte_problem *p, int on);
  * nothing. */
 bte_status bte_set_persistent(bte_problem *p, int on);
 
+/* Tile shapes of the LDS-tile kernels.  The paper's solver runs on CPUs
+ * (Sec. 3.5: MPI ranks over directions, then bands) and has no counterpart; these
+ * calls only choose how the same arithmetic is blocked on the GPU:
+ *   BTE_TUNE_SWEEP     tiles of the steady and adjoint sweeps in one and
+ *                      three dimensions (two-dimensional sweeps use a fixed
+ *                      8x8 register tile and have no choice);
+ *   BTE_TUNE_TRANSIENT tiles of the explicit step and its transpose in one
+ *                      and two dimensions (three-dimensional steps walk
+ *                      columns and have no choice).
+ * Candidates hold at most 64 cells and their LDS star fits one compute
+ * unit; the results of a sweep or step do not depend on the shape beyond
+ * floating-point summation order. */
+typedef enum { BTE_TUNE_SWEEP = 0, BTE_TUNE_TRANSIENT = 1 } bte_tune_kind;
+
+typedef struct {
+    int kind;        /* bte_tune_kind                                     */
+    int tile[3];     /* cells per tile along x, y, z                      */
+    double ms;       /* mean device time of one sweep / step (ms)        */
+    int chosen;      /* 1: the shape kept                                  */
+} bte_tune_entry;
+
+/* Candidate shapes of one kind (at most `cap` written to tiles[3 * i ..]);
+ * *n = number of candidates (0 or 1: nothing to choose).  Host only. */
+bte_status bte_tile_candidates(const bte_problem *p, int kind, int *tiles, int cap, int *n);
+
+/* Use tile shape tile[3] for `kind` from now on.  The shape must be one of
+ * bte_tile_candidates (else BTE_ERR_ARG, nothing changed).  Needs a bound
+ * workspace (the work lists are rebuilt and uploaded; synchronous). */
+bte_status bte_set_tiles(bte_problem *p, int kind, const int *tile);
+
+/* Autotuner: for every kind with more than one candidate, time `reps`
+ * sweeps (or steps) with each candidate after one untimed run, keep the
+ * fastest and report every candidate in entries[0 .. *n) (at most cap).
+ * e_scratch: device buffer of bte_num_unknowns() elements of the problem's
+ * precision, overwritten (it is the input state of the timed runs); the
+ * diffuse-wall records, T_L and pending-correction fields are cleared.
+ * Needs a bound workspace; synchronous on `stream`. */
+bte_status bte_autotune(bte_problem *p, void *e_scratch, int reps, bte_tune_entry *entries, int cap, int *n,
+                        void *stream);
+
 /* Statistics of the last bte_steady_solve, or of the last timed
  * bte_transient_step (iters = steps, ms_sweep = transport kernels, ms_walls =
  * wall kernels, ms_post = T_L updates). */

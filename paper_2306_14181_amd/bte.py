@@ -20,6 +20,7 @@ BC_THERMAL, BC_SPECULAR, BC_DIFFUSE, BC_PERIODIC = 0, 1, 2, 3
 SEQUENTIAL, SYNTHETIC = 0, 1
 LIM_NONE, LIM_MC, LIM_MINMOD = 0, 1, 2
 OBJ_KEFF_X = 0
+TUNE_SWEEP, TUNE_TRANSIENT = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "ERR_NOT_CONVERGED",
                 5: "ERR_NONFINITE", 6: "ERR_CFL", 7: "ERR_STATE"}
@@ -27,7 +28,8 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "E
 EXPORTS = ["bte_setup", "bte_set_control", "bte_workspace_bytes", "bte_num_unknowns", "bte_num_cells", "bte_num_directions",
            "bte_bind", "bte_set_fields", "bte_moments", "bte_residual", "bte_transient_step",
            "bte_steady_solve", "bte_keff", "bte_adjoint", "bte_transient_adjoint", "bte_transient_adjoint_bytes",
-           "bte_set_timing", "bte_set_graphs", "bte_set_persistent", "bte_last_stats",
+           "bte_set_timing", "bte_set_graphs", "bte_set_persistent", "bte_tile_candidates", "bte_set_tiles",
+           "bte_autotune", "bte_last_stats",
            "bte_get_directions", "bte_last_error", "bte_destroy"]
 
 
@@ -65,6 +67,10 @@ class SolveStats(C.Structure):
         return {k: (bool(getattr(self, k)) if k == "converged" else getattr(self, k)) for k, _ in self._fields_}
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("kind", C.c_int), ("tile", C.c_int * 3), ("ms", C.c_double), ("chosen", C.c_int)]
+
+
 _lib = None
 
 
@@ -99,6 +105,9 @@ def load():
         "bte_set_timing": ([vp, C.c_int], st),
         "bte_set_graphs": ([vp, C.c_int], st),
         "bte_set_persistent": ([vp, C.c_int], st),
+        "bte_tile_candidates": ([vp, C.c_int, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int)], st),
+        "bte_set_tiles": ([vp, C.c_int, C.POINTER(C.c_int)], st),
+        "bte_autotune": ([vp, vp, C.c_int, C.POINTER(TuneEntry), C.c_int, C.POINTER(C.c_int), vp], st),
         "bte_last_stats": ([vp, C.POINTER(SolveStats)], st),
         "bte_get_directions": ([vp, dp, dp], st),
         "bte_last_error": ([vp], C.c_char_p),
@@ -314,6 +323,27 @@ class Problem:
         """Launch form of the two-dimensional sweep: one launch per tile diagonal (on=False); the
         work-queue form (on=True) is not available and raises BteError."""
         self._check(load().bte_set_persistent(self._h, int(bool(on))))
+
+    def tile_candidates(self, kind):
+        """Candidate tile shapes (x, y, z) of TUNE_SWEEP or TUNE_TRANSIENT, the default first."""
+        n = C.c_int()
+        buf = (C.c_int * 96)()
+        self._check(load().bte_tile_candidates(self._h, int(kind), buf, 32, C.byref(n)))
+        return [tuple(buf[3 * i:3 * i + 3]) for i in range(min(n.value, 32))]
+
+    def set_tiles(self, kind, tile):
+        """Use tile shape `tile` (one of tile_candidates(kind))."""
+        t = (C.c_int * 3)(*tile)
+        self._check(load().bte_set_tiles(self._h, int(kind), t))
+
+    def autotune(self, reps=3, scratch=None):
+        """Time every candidate tile shape, keep the fastest; returns one dict per candidate.
+        `scratch` (a state tensor, overwritten) defaults to a fresh one."""
+        e = self.zeros() if scratch is None else scratch
+        out = (TuneEntry * 64)()
+        n = C.c_int()
+        self._check(load().bte_autotune(self._h, self._e(e), int(reps), out, 64, C.byref(n), _stream()))
+        return [dict(kind=x.kind, tile=tuple(x.tile), ms=x.ms, chosen=bool(x.chosen)) for x in out[:min(n.value, 64)]]
 
     def last_stats(self):
         st = SolveStats()

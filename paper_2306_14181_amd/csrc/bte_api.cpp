@@ -144,6 +144,7 @@ struct bte_problem {
     // sweep schedule
     int3 tdim{1, 1, 1};      // sweep tiles
     int3 tdim_tr{1, 1, 1};   // transient tiles
+    size_t items_cap = 0, titems_cap = 0;   // work-list room for every candidate tile shape
     int tile_cap_tr = 0;
     int nchunk_oct = 0;
     std::vector<SweepItem> items;
@@ -414,17 +415,83 @@ bte_status build_quadrature(bte_problem *p, int n_theta, int n_phi)
     return BTE_OK;
 }
 
+// star slots of a tile: the tile and, per axis, two upwind and one downwind layer
+int tile_cap_of(const bte_problem *p, int3 td)
+{
+    const int e[3] = {td.x, td.y, td.z};
+    const int cells = e[0] * e[1] * e[2];
+    int halo = 0;
+    for (int a = 0; a < p->dim; ++a) halo += 3 * cells / e[a];
+    return cells + halo;
+}
+
+// Tile shapes the LDS-tile kernels may use for one kind (bte_tune_kind), the
+// default shape first: at most 64 cells (the kernels keep 64-entry per-cell
+// tables), a star within the 160 KiB of LDS of a compute unit and, for the
+// sweep, at most 48 cells in the first upwind halo layers of all axes (the
+// LDS buffer of upwind increments has 48 rows).
+std::vector<int3> tile_candidates(const bte_problem *p, int kind)
+{
+    std::vector<int3> c;
+    if (kind == BTE_TUNE_SWEEP) {
+        if (p->dim == 1) c = {make_int3(64, 1, 1), make_int3(32, 1, 1), make_int3(16, 1, 1)};
+        else if (p->dim == 2) c = {make_int3(8, 8, 1)};   // fixed by the register sweep
+        else if (p->ctl.precision == BTE_F64)
+            c = {make_int3(4, 4, 2), make_int3(4, 2, 4), make_int3(2, 4, 4), make_int3(3, 3, 3),
+                 make_int3(3, 3, 2), make_int3(8, 4, 1), make_int3(4, 8, 1), make_int3(8, 2, 2),
+                 make_int3(2, 2, 2), make_int3(4, 4, 3)};
+        else
+            // 4x4x3 first: its star leaves room for two blocks per compute unit
+            c = {make_int3(4, 4, 3), make_int3(4, 4, 4), make_int3(4, 3, 4), make_int3(3, 4, 4),
+                 make_int3(4, 4, 2), make_int3(4, 2, 4), make_int3(2, 4, 4), make_int3(4, 3, 3),
+                 make_int3(3, 3, 4), make_int3(6, 4, 2), make_int3(3, 3, 3), make_int3(3, 3, 2),
+                 make_int3(8, 4, 1), make_int3(8, 2, 2)};
+    } else {
+        if (p->dim == 1) c = {make_int3(64, 1, 1), make_int3(32, 1, 1)};
+        else if (p->dim == 2)
+            c = {make_int3(8, 8, 1), make_int3(16, 4, 1), make_int3(4, 16, 1), make_int3(8, 4, 1),
+                 make_int3(16, 2, 1)};
+        else c = {make_int3(4, 4, 2)};   // unused by the column walk; the transposed 1D/2D form only
+    }
+    const bool sweep = kind == BTE_TUNE_SWEEP;
+    std::vector<int3> ok;
+    for (const int3 &t : c) {
+        const int e[3] = {t.x, t.y, t.z}, cells = t.x * t.y * t.z;
+        int up1 = 0;
+        for (int a = 0; a < p->dim; ++a) up1 += cells / e[a];
+        if (cells <= 64 && (!sweep || up1 <= 48) &&
+            tile_smem_size(tile_cap_of(p, t), (int)p->esize(), sweep) <= 160 * 1024)
+            ok.push_back(t);
+    }
+    return ok;
+}
+
+// work items of a tile shape: sweep (per octant and chunk) and transient (per octant)
+size_t count_tiles(const bte_problem *p, int3 td)
+{
+    size_t n = 0;
+    for (const Film &fm : p->films)
+        n += (size_t)((fm.n[0] + td.x - 1) / td.x) * ((fm.n[1] + td.y - 1) / td.y) * ((fm.n[2] + td.z - 1) / td.z);
+    return n;
+}
+
+// default shapes (the first candidates) and the work-list room for all candidates
+void choose_default_tiles(bte_problem *p)
+{
+    const int lanes_oct = p->na_oct * p->nl;
+    const int nchunk = (lanes_oct + 63) / 64;
+    p->tdim = tile_candidates(p, BTE_TUNE_SWEEP)[0];
+    p->tdim_tr = tile_candidates(p, BTE_TUNE_TRANSIENT)[0];
+    p->items_cap = p->titems_cap = 0;
+    for (const int3 &t : tile_candidates(p, BTE_TUNE_SWEEP))
+        p->items_cap = std::max(p->items_cap, count_tiles(p, t) * p->noct * nchunk);
+    for (const int3 &t : tile_candidates(p, BTE_TUNE_TRANSIENT))
+        p->titems_cap = std::max(p->titems_cap, count_tiles(p, t) * p->noct);
+}
+
+// Work lists of the current tile shapes (p->tdim, p->tdim_tr)
 void build_schedule(bte_problem *p)
 {
-    // tiles of 64 cells: 64 (1D), 8x8 (2D), 4x4x4 (3D)
-    if (p->dim == 1) p->tdim = make_int3(64, 1, 1);
-    else if (p->dim == 2) p->tdim = make_int3(8, 8, 1);
-    else if (p->ctl.precision == BTE_F64) p->tdim = make_int3(4, 4, 2);   // LDS: 64 KiB star for FP64
-    else p->tdim = make_int3(4, 4, 4);
-    // transient tiles: no recurrence, so size them for LDS occupancy (4-5 blocks per CU)
-    if (p->dim == 1) p->tdim_tr = make_int3(64, 1, 1);
-    else if (p->dim == 2) p->tdim_tr = make_int3(8, 8, 1);
-    else p->tdim_tr = make_int3(4, 4, 2);
     const int lanes_oct = p->na_oct * p->nl;
     p->nchunk_oct = (lanes_oct + 63) / 64;
     struct Rec {
@@ -470,15 +537,8 @@ void build_schedule(bte_problem *p)
                 for (int ch = 0; ch < p->nchunk_oct; ++ch)
                     for (int col = 0; col < fm.n[0] * fm.n[1]; ++col) p->citems.push_back({f, o, ch, col});
         }
-    auto cap_of = [&](int3 td) {
-        const int e[3] = {td.x, td.y, td.z};
-        const int cells = e[0] * e[1] * e[2];
-        int halo = 0;
-        for (int a = 0; a < p->dim; ++a) halo += 3 * cells / e[a];
-        return cells + halo;
-    };
-    p->tile_cap = cap_of(p->tdim);
-    p->tile_cap_tr = cap_of(p->tdim_tr);
+    p->tile_cap = tile_cap_of(p, p->tdim);
+    p->tile_cap_tr = tile_cap_of(p, p->tdim_tr);
     p->items.clear();
     p->diag_off.assign(maxd + 2, 0);
     for (auto &r : recs) {
@@ -538,9 +598,9 @@ void plan_workspace(bte_problem *p)
     add("dbase", 4 * nc);
     add("wrec", 4 * p->wrec.size());
     add("wden", 8 * 6);
-    add("items", sizeof(SweepItem) * p->items.size());
+    add("items", sizeof(SweepItem) * p->items_cap);
     add("items2", sizeof(Sweep2Item) * p->items2.size());
-    add("titems", sizeof(TileItem) * p->titems.size());
+    add("titems", sizeof(TileItem) * p->titems_cap);
     add("citems", sizeof(ColItem) * p->citems.size());
     for (const char *n : {"gamma", "P", "S", "TL", "TLkin", "T0", "T1", "q0", "q1", "r", "delta", "dpend", "cg_x",
                           "cg_r", "cg_z", "cg_p", "cg_Ap", "cg_w0", "cg_w1", "cg_s1"})
@@ -653,6 +713,7 @@ bte_status bte_setup(const bte_geometry *geo, int n_geo, const bte_material *mat
     if ((st = build_geometry(p, geo, n_geo)) != BTE_OK) return bail(st);
     if ((st = build_quadrature(p, mat->n_theta, mat->n_phi)) != BTE_OK) return bail(st);
     p->nk = p->na * p->nl;
+    choose_default_tiles(p);
     build_schedule(p);
     plan_workspace(p);
     *out = p;
@@ -1567,6 +1628,135 @@ bte_status bte_set_persistent(bte_problem *p, int on)
     if (!p) return BTE_ERR_ARG;
     if (on) FAIL(p, BTE_ERR_UNSUPPORTED, "the work-queue form of the sweep is not available");
     return BTE_OK;
+}
+
+bte_status bte_tile_candidates(const bte_problem *p, int kind, int *tiles, int cap, int *n)
+{
+    if (!p || !n || (kind != BTE_TUNE_SWEEP && kind != BTE_TUNE_TRANSIENT) || cap < 0 || (cap > 0 && !tiles))
+        return BTE_ERR_ARG;
+    const std::vector<int3> c = tile_candidates(p, kind);
+    for (int i = 0; i < (int)c.size() && i < cap; ++i) {
+        tiles[3 * i] = c[i].x;
+        tiles[3 * i + 1] = c[i].y;
+        tiles[3 * i + 2] = c[i].z;
+    }
+    *n = (int)c.size();
+    return BTE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// switch one kind to tile shape t (a candidate) and upload the new work lists
+bte_status use_tiles(bte_problem *p, int kind, int3 t)
+{
+    if (kind == BTE_TUNE_SWEEP) p->tdim = t;
+    else p->tdim_tr = t;
+    build_schedule(p);
+    if (p->items.size() > p->items_cap || p->titems.size() > p->titems_cap)
+        FAIL(p, BTE_ERR_STATE, "work list larger than its reserved room");
+    HIPCHK(p, hipMemcpy(p->d_items, p->items.data(), sizeof(SweepItem) * p->items.size(), hipMemcpyHostToDevice));
+    HIPCHK(p, hipMemcpy(p->d_titems, p->titems.data(), sizeof(TileItem) * p->titems.size(), hipMemcpyHostToDevice));
+    if (!p->items2.empty())
+        HIPCHK(p, hipMemcpy(p->d_items2, p->items2.data(), sizeof(Sweep2Item) * p->items2.size(),
+                            hipMemcpyHostToDevice));
+    return BTE_OK;
+}
+
+// one sweep (kind 0) or one explicit step (kind 1) of the LDS-tile kernels
+// from ein into e2, nothing else
+template <typename T> hipError_t tune_run(bte_problem *p, int kind, const T *ein, hipStream_t s)
+{
+    const Dev &d = p->dev;
+    T *eout = static_cast<T *>(p->e2);
+    if (kind == BTE_TUNE_TRANSIENT)
+        return launch_transient_tile<T>(d, ein, eout, p->TL, p->din, p->d_titems, (int)p->titems.size(),
+                                        p->tdim_tr, p->na_oct, p->nchunk_oct, p->tile_cap_tr, 0.0, p->ctl.dt,
+                                        p->part, s);
+    for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
+        const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
+        const hipError_t r = launch_sweep_tile<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt,
+                                                  p->tdim, p->na_oct, p->nchunk_oct, p->tile_cap, p->part, s);
+        if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+bte_status autotune_impl(bte_problem *p, const T *ein, int reps, bte_tune_entry *out, int cap, int *n,
+                         hipStream_t s)
+{
+    hipEvent_t ev[2];
+    for (auto &x : ev) HIPCHK(p, hipEventCreate(&x));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } evg{ev};
+    int m = 0;
+    for (int kind : {BTE_TUNE_SWEEP, BTE_TUNE_TRANSIENT}) {
+        const std::vector<int3> c = tile_candidates(p, kind);
+        if (c.size() < 2) continue;
+        // the column walk takes the three-dimensional steps, the register
+        // tile the two-dimensional sweeps: their shapes are not timed
+        if (kind == BTE_TUNE_TRANSIENT && p->dim == 3) continue;
+        std::vector<double> ms(c.size());
+        size_t best = 0;
+        for (size_t i = 0; i < c.size(); ++i) {
+            bte_status st = use_tiles(p, kind, c[i]);
+            if (st != BTE_OK) return st;
+            HIPCHK(p, tune_run<T>(p, kind, ein, s));
+            HIPCHK(p, hipEventRecord(ev[0], s));
+            for (int r = 0; r < reps; ++r) HIPCHK(p, tune_run<T>(p, kind, ein, s));
+            HIPCHK(p, hipEventRecord(ev[1], s));
+            HIPCHK(p, hipEventSynchronize(ev[1]));
+            float t = 0;
+            HIPCHK(p, hipEventElapsedTime(&t, ev[0], ev[1]));
+            ms[i] = t / reps;
+            if (ms[i] < ms[best]) best = i;
+        }
+        bte_status st = use_tiles(p, kind, c[best]);
+        if (st != BTE_OK) return st;
+        for (size_t i = 0; i < c.size(); ++i, ++m)
+            if (m < cap) out[m] = bte_tune_entry{kind, {c[i].x, c[i].y, c[i].z}, ms[i], i == best ? 1 : 0};
+    }
+    *n = m;
+    return BTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bte_status bte_set_tiles(bte_problem *p, int kind, const int *tile)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!tile || (kind != BTE_TUNE_SWEEP && kind != BTE_TUNE_TRANSIENT)) FAIL(p, BTE_ERR_ARG, "bad tile request");
+    if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
+    for (const int3 &t : tile_candidates(p, kind))
+        if (t.x == tile[0] && t.y == tile[1] && t.z == tile[2]) return use_tiles(p, kind, t);
+    FAIL(p, BTE_ERR_ARG, "tile %dx%dx%d is not a candidate", tile[0], tile[1], tile[2]);
+}
+
+bte_status bte_autotune(bte_problem *p, void *e_scratch, int reps, bte_tune_entry *entries, int cap, int *n,
+                        void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!e_scratch || !n || reps < 1 || cap < 0 || (cap > 0 && !entries)) FAIL(p, BTE_ERR_ARG, "bad arguments");
+    if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
+    hipStream_t s = (hipStream_t)stream;
+    // defined inputs for the timed runs
+    HIPCHK(p, hipMemsetAsync(e_scratch, 0, p->esize() * p->nelem(), s));
+    HIPCHK(p, hipMemsetAsync(p->TL, 0, 8 * (size_t)p->nc, s));
+    HIPCHK(p, hipMemsetAsync(p->dpend, 0, 8 * (size_t)p->nc, s));
+    if (p->nw) HIPCHK(p, hipMemsetAsync(p->din, 0, 8 * (size_t)p->nw * p->nl, s));
+    if (p->ctl.precision == BTE_F64)
+        return autotune_impl<double>(p, static_cast<const double *>(e_scratch), reps, entries, cap, n, s);
+    return autotune_impl<float>(p, static_cast<const float *>(e_scratch), reps, entries, cap, n, s);
 }
 
 bte_status bte_set_timing(bte_problem *p, int on)

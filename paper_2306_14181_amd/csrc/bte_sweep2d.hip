@@ -170,7 +170,10 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     __shared__ T sX0[kTY][64];
     __shared__ T sY0[64][kTX];
     const Sweep2Item it = items[item0 + blockIdx.x];
-    if (d.fdone[it.film]) return;   // converged geometry (uniform over the block)
+    // converged geometry of a batch (uniform over the block); a single
+    // geometry is never swept once converged, so its blocks skip this load
+    // and reach their stencil loads one round trip earlier
+    if (d.nfilm > 1 && d.fdone[it.film]) return;
     // wavefront r owns tile row r (readfirstlane: r is known to be uniform,
     // so everything derived from it stays scalar)
     const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_sweep_tile(Dev d, const T *__restrict__
     extern __shared__ __align__(16) char smem[];
     TileSmem<T> S = tile_smem<T>(smem, cap, true);
     const SweepItem it = items[item0 + blockIdx.x];
-    if (!ADJ && d.fdone[it.film]) return;   // converged geometry (uniform over the block)
+    if (!ADJ && d.nfilm > 1 && d.fdone[it.film]) return;   // converged geometry of a batch (uniform)
     const Film &fm = d.film[it.film];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int loct = ADJ ? (it.oct ^ ((1 << d.dim) - 1)) : it.oct;

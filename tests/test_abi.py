@@ -104,3 +104,31 @@ def test_device_calls_need_a_workspace(lib):
     assert lib.bte_steady_solve(h, dummy, 1, None, None) == 7
     assert lib.bte_bind(h, dummy, C.c_size_t(16)) == 1
     lib.bte_destroy(h)
+
+
+@pytest.mark.parametrize("dim,prec", [(1, 0), (2, 0), (2, 1), (3, 0), (3, 1)])
+def test_tile_candidates(lib, dim, prec):
+    """Candidate tile shapes: the default first, at most 64 cells each, and a
+    choice only where the kernels are LDS-tiled (sweeps in 1D/3D, explicit
+    steps in 1D/2D); no shape can be set before a workspace is bound."""
+    b = I.bands(0, 3)
+    g = geo(dim, (8,) * dim, (1e-7,) * dim, [I.BC_SPECULAR] * 6)
+    st, h = _setup(lib, g, mat(b, 2, 2), {"precision": prec})
+    assert st == 0, lib.bte_last_error(h)
+    got = {}
+    for kind in (0, 1):
+        buf = (C.c_int * 96)()
+        n = C.c_int()
+        assert lib.bte_tile_candidates(h, kind, buf, 32, C.byref(n)) == 0
+        shapes = [tuple(buf[3 * i:3 * i + 3]) for i in range(n.value)]
+        assert all(x * y * z <= 64 and min(x, y, z) >= 1 for x, y, z in shapes)
+        assert all(s[dim:] == (1,) * (3 - dim) for s in shapes)
+        got[kind] = shapes
+    default_sweep = {1: (64, 1, 1), 2: (8, 8, 1), 3: (4, 4, 2) if prec else (4, 4, 3)}[dim]
+    assert got[0][0] == default_sweep
+    assert (len(got[0]) > 1) == (dim != 2)
+    assert (len(got[1]) > 1) == (dim != 3)
+    t = (C.c_int * 3)(*got[0][0])
+    assert lib.bte_set_tiles(h, 0, t) == 7   # BTE_ERR_STATE: no workspace
+    assert lib.bte_set_tiles(h, 5, t) == 1   # BTE_ERR_ARG
+    lib.bte_destroy(h)
