@@ -246,15 +246,30 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
         const char *row = reinterpret_cast<const char *>((ok ? base : zrow) + (size_t)(ok ? c : 0) * nk);
         return *reinterpret_cast<const T *>(row + koff);
     };
+    // The cells of a row (tile row or halo row) are consecutive along x, so
+    // each row's address is formed once and stepped by one cell per j; a
+    // missing row, or j past a ragged tile's end, reads the zero row.
+    const long long cstep = (long long)sx * nk * (long long)sizeof(T);
+    const char *zc = reinterpret_cast<const char *>(zrow);
+    auto rowp = [&](const T *base, int q) -> const char * {
+        const int c = (q >= 0 && q < e1) ? cbase + rowstep * q : rl(h_c, q == -2 ? 0 : (q == -1 ? 8 : 16));
+        return c >= 0 ? reinterpret_cast<const char *>(base + (size_t)c * nk) : nullptr;
+    };
+    const char *pm2 = rowp(ein, rr - 2), *pm1 = rowp(ein, rr - 1), *pc0 = rowp(ein, rr), *pp1 = rowp(ein, rr + 1);
+    const char *pdr = rr == 0 ? rowp(eout, -1) : nullptr;
     T ym2[kTX], ym1[kTX], yp1[kTX], dr[kTX], ecr[kTX];
 #pragma unroll
     for (int j = 0; j < kTX; ++j) {
-        ym2[j] = ldc(ein, row_c(rr - 2, j));
-        const int cm1 = row_c(rr - 1, j);
-        ym1[j] = ldc(ein, cm1);
-        ecr[j] = ldc(ein, row_c(rr, j));
-        yp1[j] = ldc(ein, row_c(rr + 1, j));
-        dr[j] = ldc(eout, rr == 0 ? cm1 : -1);
+        const bool in = j < e0;
+        const long long o = j * cstep;
+        auto ldr = [&](const char *p) -> T {
+            return *reinterpret_cast<const T *>(((in && p) ? p + o : zc) + koff);
+        };
+        ym2[j] = ldr(pm2);
+        ym1[j] = ldr(pm1);
+        ecr[j] = ldr(pc0);
+        yp1[j] = ldr(pp1);
+        dr[j] = ldr(pdr);
     }
     const int hx = 24 + 3 * rr;
     const int cx0 = rl(h_c, hx), cx1 = rl(h_c, hx + 1), cx2 = rl(h_c, hx + 2);
