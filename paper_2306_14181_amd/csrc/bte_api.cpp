@@ -627,7 +627,7 @@ void plan_workspace(bte_problem *p)
     p->npart_max = std::max(nchunk_stream, p->noct * p->nchunk_oct);
     add("part", 8 * (size_t)kMomN * nc * p->npart_max);
     add("e2", p->esize() * p->nelem());
-    add("zrow", 8 * (size_t)p->nk);
+    add("zrow", 8 * 8 * (size_t)p->nk);   // 8 cells of zeros (a missing row of a tile)
     for (const char *n : {"adjX", "adjT", "adjTL", "adju", "adjr2"}) add(n, 8 * nc);
     if (p->ctl.adjoint) {
         add("psi", p->esize() * p->nelem());
@@ -845,7 +845,7 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     p->d_wrec = wsptr<int>(p, "wrec");
     p->d_wden = wsptr<double>(p, "wden");
     // default fields: no source, no extra scattering
-    HIPCHK(p, hipMemset(wsptr<void>(p, "zrow"), 0, 8 * (size_t)p->nk));
+    HIPCHK(p, hipMemset(wsptr<void>(p, "zrow"), 0, 8 * 8 * (size_t)p->nk));
     HIPCHK(p, hipMemset(wsptr<void>(p, "fdone"), 0, 4 * (size_t)p->nfilm));
     HIPCHK(p, hipMemset(p->gamma, 0, 8 * (size_t)p->nc));
     HIPCHK(p, hipMemset(p->P, 0, 8 * (size_t)p->nc));

@@ -64,7 +64,7 @@ struct Dev {
     const double *gamma;     // [nc]
     const double *P;         // [nc]
     const double *S;         // [nc] sum_lambda C (1/tau + gamma)
-    const void *zrow;        // [nk] zeros of the working precision: loads of a
+    const void *zrow;        // [8][nk] zeros of the working precision (8 cells): loads of a
                              // missing cell read here instead of branching
     const int *fdone;        // [nfilm] 1: geometry converged, its steady sweep is skipped
 };

@@ -246,25 +246,25 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
         const char *row = reinterpret_cast<const char *>((ok ? base : zrow) + (size_t)(ok ? c : 0) * nk);
         return *reinterpret_cast<const T *>(row + koff);
     };
-    // The cells of a row (tile row or halo row) are consecutive along x, so
-    // each row's address is formed once and stepped by one cell per j; a
-    // missing row, or j past a ragged tile's end, reads the zero row.
-    const long long cstep = (long long)sx * nk * (long long)sizeof(T);
+    // The cells of a row (tile row or halo row) are consecutive along x: a
+    // row is addressed by the scalar address of its lowest-x cell, the cell
+    // j by a per-lane byte offset (j clamped to the tile's extent, so a
+    // ragged tile re-reads its last cell), and a missing row is the zero
+    // row, 8 cells long.  No scalar work per load.
     const char *zc = reinterpret_cast<const char *>(zrow);
+    const int lo = sx > 0 ? 0 : -(e0 - 1);   // lowest-x cell relative to the row's flow-first cell
     auto rowp = [&](const T *base, int q) -> const char * {
         const int c = (q >= 0 && q < e1) ? cbase + rowstep * q : rl(h_c, q == -2 ? 0 : (q == -1 ? 8 : 16));
-        return c >= 0 ? reinterpret_cast<const char *>(base + (size_t)c * nk) : nullptr;
+        return c >= 0 ? reinterpret_cast<const char *>(base + (size_t)(c + lo) * nk) : zc;
     };
     const char *pm2 = rowp(ein, rr - 2), *pm1 = rowp(ein, rr - 1), *pc0 = rowp(ein, rr), *pp1 = rowp(ein, rr + 1);
-    const char *pdr = rr == 0 ? rowp(eout, -1) : nullptr;
+    const char *pdr = rr == 0 ? rowp(eout, -1) : zc;
     T ym2[kTX], ym1[kTX], yp1[kTX], dr[kTX], ecr[kTX];
 #pragma unroll
     for (int j = 0; j < kTX; ++j) {
-        const bool in = j < e0;
-        const long long o = j * cstep;
-        auto ldr = [&](const char *p) -> T {
-            return *reinterpret_cast<const T *>(((in && p) ? p + o : zc) + koff);
-        };
+        const int jc = j < e0 ? j : e0 - 1;
+        const unsigned o = koff + (unsigned)((sx > 0 ? jc : e0 - 1 - jc) * nk) * (unsigned)sizeof(T);
+        auto ldr = [&](const char *p) -> T { return *reinterpret_cast<const T *>(p + o); };
         ym2[j] = ldr(pm2);
         ym1[j] = ldr(pm1);
         ecr[j] = ldr(pc0);
