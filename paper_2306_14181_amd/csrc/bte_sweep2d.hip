@@ -90,13 +90,6 @@ __device__ inline bool halo_pos(const Frame2 &F, int h, int &f0, int &f1)
 }
 
 __device__ inline int rl(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
-__device__ inline double rl(double v, int lane)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 }  // namespace
 
@@ -169,6 +162,11 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     __shared__ T sRXY[kTY][2][64][kTX];
     __shared__ T sX0[kTY][64];
     __shared__ T sY0[64][kTX];
+    // Per-cell scalars of the tile in each wavefront's own copy (x = pending
+    // correction plus jump, gamma, T_L, source; halo x), read back as
+    // broadcast LDS loads rather than lane-by-lane register broadcasts.
+    __shared__ T sPC[kTY][4][64];
+    __shared__ T sHX[kTY][64];
     const Sweep2Item it = items[item0 + blockIdx.x];
     // converged geometry of a batch (uniform over the block); a single
     // geometry is never swept once converged, so its blocks skip this load
@@ -276,10 +274,6 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     T xh0 = ldc(ein, cx0), xh1 = ldc(ein, cx1), xh2 = ldc(ein, cx2);
     const T dxr = ldc(eout, cx1);
 
-    auto rlt = [&](T v, int q) -> T {
-        if constexpr (sizeof(T) == 4) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
-        else return rl((double)v, q);
-    };
     // mode words (needs the codes of the upwind neighbours: lanes t - 1 /
     // t - 8 of the tile, or the x-halo / row -1 halo lanes)
     uint32_t t_w = 0;
@@ -315,12 +309,19 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
         t_x = sol ? (T)t_xd : (T)0;
         h_x = (T)(h_xd + h_j);
     }
+    T *const px = &sPC[r][0][0], *const pgam = &sPC[r][1][0], *const ptl = &sPC[r][2][0],
+            *const pqs = &sPC[r][3][0], *const phx = &sHX[r][0];
+    px[lane] = t_x;
+    pgam[lane] = t_gam;
+    ptl[lane] = t_tl;
+    pqs[lane] = t_qs;
+    phx[lane] = h_x;
     const T A0 = cp0 + cp1 + itau;
-    auto row_x = [&](int q, int j) -> T {
-        const T tv = rlt(t_x, (8 * q + j) & 63);
-        const T hv = rlt(h_x, q == -2 ? j : (q == -1 ? 8 + j : 16 + j));
-        return (q >= 0 && q < e1) ? tv : hv;
+    // x of the cells of row q (tile row, or halo row -2, -1, e1)
+    auto row_xp = [&](int q) -> const T * {
+        return (q >= 0 && q < e1) ? px + 8 * q : phx + (q == -2 ? 0 : (q == -1 ? 8 : 16));
     };
+    auto row_x = [&](int q, int j) -> T { return row_xp(q)[j]; };
     T *wl = &sRXY[r][0][0][0];   // diffuse inflow staging of this row: slot 2 j + a
 
     // ---- diffuse-wall inflow values of this row, in groups of eight loads
@@ -364,17 +365,18 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     T num[kTX], ec[kTX], rden[kTX];
     T dupx = (T)0, dpr0[kTX];
     if (myrow) {
+        const T *xm2 = row_xp(r - 2), *xm1 = row_xp(r - 1), *xc = row_xp(r), *xp1 = row_xp(r + 1);
 #pragma unroll
         for (int j = 0; j < kTX; ++j) {
-            ym2[j] += C4 * row_x(r - 2, j);
-            ym1[j] += C4 * row_x(r - 1, j);
-            ec[j] = ecr[j] + C4 * row_x(r, j);
-            yp1[j] += C4 * row_x(r + 1, j);
+            ym2[j] += C4 * xm2[j];
+            ym1[j] += C4 * xm1[j];
+            ec[j] = ecr[j] + C4 * xc[j];
+            yp1[j] += C4 * xp1[j];
             dpr0[j] = dr[j] - ym1[j];   // y-upwind increments (row 0 only)
         }
-        xh0 += C4 * rlt(h_x, hx);
-        xh1 += C4 * rlt(h_x, hx + 1);
-        xh2 += C4 * rlt(h_x, hx + 2);
+        xh0 += C4 * phx[hx];
+        xh1 += C4 * phx[hx + 1];
+        xh2 += C4 * phx[hx + 2];
         dupx = dxr - xh1;
         // thermalizing wall inflow per axis (upwind face of this octant)
         const T Tw0 = C4 * (T)(sg0 > 0 ? it.wallT[0] : it.wallT[1]);
@@ -400,11 +402,11 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
                     const uint32_t ab0 = axis_bits(code, 0);
                     const bool hu0 = side_is_cell(ab0, -sg0), hd0 = side_is_cell(ab0, sg0);
                     const int cd = hd0 ? (j + 1 < e0 ? rl(t_c, t + 1) : cx2) : -1;
-                    const double xd = j + 1 < e0 ? (double)rlt(t_x, t + 1) : (double)rlt(h_x, hx + 2);
+                    const double xd = j + 1 < e0 ? (double)px[t + 1] : (double)phx[hx + 2];
                     T fw = (side_wall(ab0, -sg0) == 0) ? (side_outer(code, 0, -sg0) ? Tw0 : Tp) : (T)0;
                     if (w & W_DX) fw = wl[(2 * j) * 64 + lane];
                     dx = delta_general<T, LIM>(d, ein, c, code, 0, sg0, hu0, (w & W_HU20) != 0, hd0, ex2, ex1,
-                                               ec[j], exd, fw, cd, xd, (double)rlt(t_x, t), al, l, active, C4, hh0,
+                                               ec[j], exd, fw, cd, xd, (double)px[t], al, l, active, C4, hh0,
                                                ih0, nk);
                 }
                 if (w & W_FY) {
@@ -419,12 +421,12 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
                     T fw = (side_wall(ab1, -sg1) == 0) ? (side_outer(code, 1, -sg1) ? Tw1 : Tp) : (T)0;
                     if (w & W_DY) fw = wl[(2 * j + 1) * 64 + lane];
                     dy = delta_general<T, LIM>(d, ein, c, code, 1, sg1, hu1, (w & W_HU21) != 0, hd1, ym2[j],
-                                               ym1[j], ec[j], yp1[j], fw, cd, xd, (double)rlt(t_x, t), al, l, active,
+                                               ym1[j], ec[j], yp1[j], fw, cd, xd, (double)px[t], al, l, active,
                                                C4, hh1, ih1, nk);
                 }
-                const T gam = rlt(t_gam, t);
+                const T gam = pgam[t];
                 const T itc = itau + gam;
-                num[j] = -(cp0 * dx + cp1 * dy) - (ec[j] - C4 * rlt(t_tl, t)) * itc + C4 * rlt(t_qs, t);
+                num[j] = -(cp0 * dx + cp1 * dy) - (ec[j] - C4 * ptl[t]) * itc + C4 * pqs[t];
                 const T den = A0 + gam;
                 if constexpr (sizeof(T) == 4) rden[j] = __builtin_amdgcn_rcpf(den);
                 else rden[j] = (T)1 / den;
