@@ -147,16 +147,8 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
     };
     auto plus = [](int base, int off) { return base >= 0 ? base + off : -1; };
 
-    // z window (flow order) with its jumps, and the geometry code of the
-    // z-upwind cell
+    // z window (flow order) with its jumps
     T ez2 = zval(-2), ez1 = zval(-1), ec = zval(0), ezd = zval(1);
-    uint32_t code_zu = 0;
-    {
-        int jz;
-        const int cu = zcell(-1, jz);
-        const uint32_t v = d.code[cu >= 0 ? cu : cb];
-        code_zu = cu >= 0 ? v : 0u;
-    }
     // limited z slope of the upwind cell (carried from cell to cell)
     T lz_up = (LIM == LIM_NONE) ? (T)0 : lim_diff<T, LIM>(ez1 - ez2, ec - ez1);
 
@@ -182,6 +174,7 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
     const long long sx1 = bx1 >= 0 ? zstep : 0, sx2 = bx2 >= 0 ? zstep : 0, sxd = bxd >= 0 ? zstep : 0;
     const long long sy1 = by1 >= 0 ? zstep : 0, sy2 = by2 >= 0 ? zstep : 0, syd = byd >= 0 ? zstep : 0;
     const T *rc0 = ein + (size_t)(cb + plane * z0) * nk;   // the column's own row at flow index 0
+    const T *rzr = rc0 + zstep;                            // row at flow index f + 3, before the advance
     auto at = [&](const T *row) -> T { return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(row) + koff); };
     // loads for the cell after flow index f (x / y neighbours: the running
     // row pointers are advanced by one plane per cell, not past the column)
@@ -201,12 +194,13 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
         q.y1 = at(ry1);
         q.y2 = at(ry2);
         q.yd = at(ryd);
-        // inside the column: plain row; past its end (last three cells):
-        // periodic image with its jump, or zero
+        // inside the column: plain row (a running pointer); past its end
+        // (last three cells): periodic image with its jump, or zero
+        rzr += zstep;
         const T *rz;
         T jz = (T)0;
         if (f + 3 < n2) {
-            rz = rc0 + (long long)(f + 3) * zstep;
+            rz = rzr;
         } else {
             int j;
             const int c = zcell(f + 3, j);
@@ -218,7 +212,10 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
     // Per-cell records, one cell of a run of 64 along the column per lane
     // (unconditional loads: an absent neighbour reads the cell's own code
     // and is masked), broadcast with readlane.
-    uint32_t r_code = 0, r_cxu = 0, r_cyu = 0;
+    // r_mode: bit 0 solid, bit 1 every axis has both upwind cells and the
+    // downwind cell (the interior stencil), computed here once per cell so
+    // that a cell's uniform decision is one broadcast and one branch.
+    uint32_t r_code = 0, r_cxu = 0, r_cyu = 0, r_czu = 0, r_mode = 0;
     double r_gam = 0;
     T r_tlT = (T)0, r_gamT = (T)0, r_qsT = (T)0;
     auto records = [&](int f0) {
@@ -229,6 +226,22 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
         const uint32_t cxu = d.code[bx1 >= 0 ? bx1 + o : c], cyu = d.code[by1 >= 0 ? by1 + o : c];
         r_cxu = bx1 >= 0 ? cxu : 0u;
         r_cyu = by1 >= 0 ? cyu : 0u;
+        {
+            int jz;
+            const int cu = zcell(fl - 1, jz);
+            const uint32_t v = d.code[cu >= 0 ? cu : c];
+            r_czu = cu >= 0 ? v : 0u;
+        }
+        {
+            const uint32_t ab0 = axis_bits(r_code, 0), ab1 = axis_bits(r_code, 1), ab2 = axis_bits(r_code, 2);
+            const bool fx = side_is_cell(ab0, -sg0) && side_is_cell(ab0, sg0) &&
+                            side_is_cell(axis_bits(r_cxu, 0), -sg0);
+            const bool fy = side_is_cell(ab1, -sg1) && side_is_cell(ab1, sg1) &&
+                            side_is_cell(axis_bits(r_cyu, 1), -sg1);
+            const bool fz = side_is_cell(ab2, -sg2) && side_is_cell(ab2, sg2) &&
+                            side_is_cell(axis_bits(r_czu, 2), -sg2);
+            r_mode = ((r_code & kSolidBit) ? 1u : 0u) | ((fx && fy && fz) ? 2u : 0u);
+        }
         r_gam = d.gamma[c];
         r_tlT = (T)TLdev[c];
         r_gamT = (T)r_gam;
@@ -246,11 +259,9 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
         const int c = cb + zo;
         prefetch(f, out);
         const int q = f & 63;
-        const uint32_t code = (uint32_t)__builtin_amdgcn_readlane((int)r_code, q);
-        const uint32_t code_xu = (uint32_t)__builtin_amdgcn_readlane((int)r_cxu, q);
-        const uint32_t code_yu = (uint32_t)__builtin_amdgcn_readlane((int)r_cyu, q);
+        const uint32_t mode = (uint32_t)__builtin_amdgcn_readlane((int)r_mode, q);
         const T tlT = rlt(r_tlT, q), gamT = rlt(r_gamT, q), qsT = rlt(r_qsT, q);
-        const bool solid = code & kSolidBit;
+        const bool solid = mode & 1u;
         const T ex1 = in.x1 + kx1, ex2 = in.x2 + kx2, exd = in.xd + kxd;
         const T ey1 = in.y1 + ky1, ey2 = in.y2 + ky2, eyd = in.yd + kyd;
         // z slope of this cell (also the upwind slope of the next cell)
@@ -258,6 +269,18 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
         T en = ec;
         double acc = 0.0;
         if (solid) {
+          T dx, dy, dz;
+          if (mode & 2u) {
+            // interior stencil on every axis
+            dx = delta_fast<T, LIM>(ex2, ex1, ec, exd);
+            dy = delta_fast<T, LIM>(ey2, ey1, ec, eyd);
+            if (LIM == LIM_NONE) dz = delta_fast<T, LIM>(ez2, ez1, ec, ezd);
+            else dz = (ec - ez1) + (T)0.5 * (lz - lz_up);
+          } else {
+            const uint32_t code = (uint32_t)__builtin_amdgcn_readlane((int)r_code, q);
+            const uint32_t code_xu = (uint32_t)__builtin_amdgcn_readlane((int)r_cxu, q);
+            const uint32_t code_yu = (uint32_t)__builtin_amdgcn_readlane((int)r_cyu, q);
+            const uint32_t code_zu = (uint32_t)__builtin_amdgcn_readlane((int)r_czu, q);
             const uint32_t ab0 = axis_bits(code, 0), ab1 = axis_bits(code, 1), ab2 = axis_bits(code, 2);
             const bool hu0 = side_is_cell(ab0, -sg0), hd0 = side_is_cell(ab0, sg0);
             const bool hu1 = side_is_cell(ab1, -sg1), hd1 = side_is_cell(ab1, sg1);
@@ -265,7 +288,6 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
             const bool hu20 = hu0 && side_is_cell(axis_bits(code_xu, 0), -sg0);
             const bool hu21 = hu1 && side_is_cell(axis_bits(code_yu, 1), -sg1);
             const bool hu22 = hu2 && side_is_cell(axis_bits(code_zu, 2), -sg2);
-            T dx, dy, dz;
             if (hu0 && hu20 && hd0) {
                 dx = delta_fast<T, LIM>(ex2, ex1, ec, exd);
             } else {
@@ -287,6 +309,7 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
                 dz = delta_wall3<T, LIM>(d, fm, ein, din, c, code, 2, sg2, hu2, hu22, hd2, ez2, ez1, ec, ezd, cdz,
                                          C4 * (T)(jd * fm.pdT[2]), L.al, L.l, C4, L.hh[2], L.ih[2]);
             }
+          }
             const T D = cp0 * dx + cp1 * dy + cp2 * dz;
             const T itc = itau + gamT;
             en = ec + tdt * (-D - (ec - C4 * tlT) * itc + C4 * tsrc * qsT);
@@ -315,7 +338,6 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
         ec = ezd;
         ezd = in.nz;
         lz_up = lz;
-        code_zu = code;
     };
 
     Pre A, B;
