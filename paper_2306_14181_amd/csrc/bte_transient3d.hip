@@ -513,7 +513,7 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
     // per-cell records of a run of 64 cells, one per lane: codes of the cell
     // and of its frame-upwind / frame-downwind neighbours along x, y, z,
     // the closure term X and gamma
-    uint32_t r_code = 0, r_cxu = 0, r_cyu = 0, r_cxd = 0, r_cyd = 0, r_czu = 0, r_czd = 0;
+    uint32_t r_code = 0, r_cxu = 0, r_cyu = 0, r_cxd = 0, r_cyd = 0, r_czu = 0, r_czd = 0, r_mode = 0;
     double r_X = 0, r_gam = 0;
     auto records = [&](int f0) {
         const int fl = min(f0 + lane, n2 - 1);
@@ -532,6 +532,15 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
         r_czd = cd >= 0 ? czd : 0u;
         r_X = X[c];
         r_gam = d.gamma[c];
+        // bit 0 solid, bit 1 the interior transposed stencil on every axis
+        // (two cells on each side where the forward stencil reaches)
+        auto inner = [&](int a, int sg, uint32_t cu_, uint32_t cd_) {
+            const uint32_t ab = axis_bits(r_code, a);
+            return side_is_cell(ab, -sg) && side_is_cell(ab, sg) && side_is_cell(axis_bits(cu_, a), -sg) &&
+                   side_is_cell(axis_bits(cd_, a), sg);
+        };
+        const bool all = inner(0, sg0, r_cxu, r_cxd) && inner(1, sg1, r_cyu, r_cyd) && inner(2, sg2, r_czu, r_czd);
+        r_mode = ((r_code & kSolidBit) ? 1u : 0u) | (all ? 2u : 0u);
     };
     auto rlu = [&](uint32_t v, int q) -> uint32_t { return (uint32_t)__builtin_amdgcn_readlane((int)v, q); };
     double *__restrict__ pbase = part + (size_t)((it.oct * nchunk_oct + it.chunk) * 5) * nc;
@@ -541,14 +550,23 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
         const int c = cb + zo;
         prefetch(f, out);
         const int q = f & 63;
-        const uint32_t code = rlu(r_code, q);
-        const bool solid = code & kSolidBit;
+        const uint32_t mode = rlu(r_mode, q);
+        const bool solid = mode & 1u;
         T ln = (T)0;
         double acc[5] = {0, 0, 0, 0, 0};
         if (solid) {
+          const double Xc = rl_d(r_X, q), gam = rl_d(r_gam, q);
+          T tf;
+          if (mode & 2u) {
+            // interior transposed stencil on every axis
+            const T tx = L.cpl[0] * ((in.x1 - zc) + (T)0.25 * ((zc - in.xd) - (in.x2 - in.x1)));
+            const T ty = L.cpl[1] * ((in.y1 - zc) + (T)0.25 * ((zc - in.yd) - (in.y2 - in.y1)));
+            const T tz = L.cpl[2] * ((z1 - zc) + (T)0.25 * ((zc - zd) - (z2 - z1)));
+            tf = (tx + ty) + tz;
+          } else {
+            const uint32_t code = rlu(r_code, q);
             const uint32_t cxu = rlu(r_cxu, q), cyu = rlu(r_cyu, q), czu = rlu(r_czu, q);
             const uint32_t cxd = rlu(r_cxd, q), cyd = rlu(r_cyd, q), czd = rlu(r_czd, q);
-            const double Xc = rl_d(r_X, q), gam = rl_d(r_gam, q);
             const uint32_t ab0 = axis_bits(code, 0), ab1 = axis_bits(code, 1), ab2 = axis_bits(code, 2);
             const bool hu0 = side_is_cell(ab0, -sg0), hd0 = side_is_cell(ab0, sg0);
             const bool hu1 = side_is_cell(ab1, -sg1), hd1 = side_is_cell(ab1, sg1);
@@ -559,7 +577,6 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
             const bool hd20 = hd0 && side_is_cell(axis_bits(cxd, 0), sg0);
             const bool hd21 = hd1 && side_is_cell(axis_bits(cyd, 1), sg1);
             const bool hd22 = hd2 && side_is_cell(axis_bits(czd, 2), sg2);
-            T tf;
             {
                 T tx;
                 if (hu0 && hu20 && hd0 && hd20) tx = L.cpl[0] * ((in.x1 - zc) + (T)0.25 * ((zc - in.xd) - (in.x2 - in.x1)));
@@ -578,6 +595,7 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
                                       z2, zd, L.al, L.l, L.cpl[2], wsa[2]);
                 tf = (tx + ty) + tz;
             }
+          }
             const T itc = itau + (T)gam;
             ln = zc + tdt * (tf - zc * itc + (T)L.w * itc * (T)Xc);
             if (active) {
