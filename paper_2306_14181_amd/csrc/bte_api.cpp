@@ -778,6 +778,9 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     d.nl = p->nl;
     d.nk = p->nk;
     d.nfilm = p->nfilm;
+    d.jumps = 0;
+    for (const Film &fm : p->films)
+        for (int a = 0; a < 3; ++a) d.jumps |= (fm.periodic[a] && fm.pdT[a] != 0.0) ? 1 : 0;
     d.limiter = p->ctl.limiter;
     d.Ctot = p->Ctot;
     d.poreT = 0.0;

@@ -47,6 +47,7 @@ struct Film {
 // Everything a kernel needs to evaluate the discrete operators.
 struct Dev {
     int dim, nc, na, nl, nk, nfilm;
+    int jumps;               // 1: some geometry has a periodic axis with a temperature drop
     int limiter;
     double Ctot;             // sum_lambda C
     double poreT;            // thermalizing pore wall temperature minus T_ref

@@ -79,7 +79,9 @@ __device__ inline T delta_wall3(const Dev &d, const Film &fm, const T *__restric
 
 }  // namespace
 
-template <typename T, int LIM>
+// JMP = false when no geometry has a periodic temperature drop: the jump
+// terms are then zero and are not added.
+template <typename T, int LIM, bool JMP>
 __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
                                                      const double *__restrict__ TLdev,
                                                      const double *__restrict__ din,
@@ -132,8 +134,9 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
               bxd = pxd >= 0 ? fm.cell0 + pxd + n0 * y : -1;
     const int by1 = py1 >= 0 ? fm.cell0 + x + n0 * py1 : -1, by2 = py2 >= 0 ? fm.cell0 + x + n0 * py2 : -1,
               byd = pyd >= 0 ? fm.cell0 + x + n0 * pyd : -1;
-    const T kx1 = C4 * (T)(jx1 * fm.pdT[0]), kx2 = C4 * (T)(jx2 * fm.pdT[0]), kxd = C4 * (T)(jxd * fm.pdT[0]);
-    const T ky1 = C4 * (T)(jy1 * fm.pdT[1]), ky2 = C4 * (T)(jy2 * fm.pdT[1]), kyd = C4 * (T)(jyd * fm.pdT[1]);
+    auto jump = [&](int j, double pdT) -> T { return JMP ? C4 * (T)(j * pdT) : (T)0; };
+    const T kx1 = jump(jx1, fm.pdT[0]), kx2 = jump(jx2, fm.pdT[0]), kxd = jump(jxd, fm.pdT[0]);
+    const T ky1 = jump(jy1, fm.pdT[1]), ky2 = jump(jy2, fm.pdT[1]), kyd = jump(jyd, fm.pdT[1]);
     // cell of the column at flow index f (geometric z = f or n2 - 1 - f),
     // -1 outside a non-periodic column; its jump in units of C dT / 4pi
     auto zcell = [&](int f, int &jz) -> int {
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
     auto zval = [&](int f) -> T {
         int jz;
         const int c = zcell(f, jz);
-        return ld(ein, c) + C4 * (T)(jz * fm.pdT[2]);
+        return JMP ? ld(ein, c) + jump(jz, fm.pdT[2]) : ld(ein, c);
     };
     auto plus = [](int base, int off) { return base >= 0 ? base + off : -1; };
 
@@ -205,9 +208,9 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
             int j;
             const int c = zcell(f + 3, j);
             rz = c >= 0 ? ein + (size_t)c * nk : zrow;
-            jz = C4 * (T)(j * fm.pdT[2]);
+            jz = jump(j, fm.pdT[2]);
         }
-        q.nz = at(rz) + jz;
+        q.nz = JMP ? at(rz) + jz : at(rz);
     };
     // Per-cell records, one cell of a run of 64 along the column per lane
     // (unconditional loads: an absent neighbour reads the cell's own code
@@ -262,8 +265,8 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
         const uint32_t mode = (uint32_t)__builtin_amdgcn_readlane((int)r_mode, q);
         const T tlT = rlt(r_tlT, q), gamT = rlt(r_gamT, q), qsT = rlt(r_qsT, q);
         const bool solid = mode & 1u;
-        const T ex1 = in.x1 + kx1, ex2 = in.x2 + kx2, exd = in.xd + kxd;
-        const T ey1 = in.y1 + ky1, ey2 = in.y2 + ky2, eyd = in.yd + kyd;
+        const T ex1 = JMP ? in.x1 + kx1 : in.x1, ex2 = JMP ? in.x2 + kx2 : in.x2, exd = JMP ? in.xd + kxd : in.xd;
+        const T ey1 = JMP ? in.y1 + ky1 : in.y1, ey2 = JMP ? in.y2 + ky2 : in.y2, eyd = JMP ? in.yd + kyd : in.yd;
         // z slope of this cell (also the upwind slope of the next cell)
         const T lz = (LIM == LIM_NONE) ? (T)0 : lim_diff<T, LIM>(ec - ez1, ezd - ec);
         T en = ec;
@@ -307,7 +310,7 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
                 int jd;
                 const int cdz = zcell(f + 1, jd);
                 dz = delta_wall3<T, LIM>(d, fm, ein, din, c, code, 2, sg2, hu2, hu22, hd2, ez2, ez1, ec, ezd, cdz,
-                                         C4 * (T)(jd * fm.pdT[2]), L.al, L.l, C4, L.hh[2], L.ih[2]);
+                                         jump(jd, fm.pdT[2]), L.al, L.l, C4, L.hh[2], L.ih[2]);
             }
           }
             const T D = cp0 * dx + cp1 * dy + cp2 * dz;
@@ -679,8 +682,12 @@ void transient3d_launch(const Dev &d, const T *ein, T *eout, const double *TLdev
                         double *part, hipStream_t s)
 {
     const int blocks = ((nitems + 3) / 4 + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_transient3d<T, LIM>), dim3(blocks), dim3(256), 0, s, d, ein, eout, TLdev, din, items,
-                       nitems, na_oct, nchunk_oct, src, dt, part);
+    if (d.jumps)
+        hipLaunchKernelGGL((k_transient3d<T, LIM, true>), dim3(blocks), dim3(256), 0, s, d, ein, eout, TLdev, din,
+                           items, nitems, na_oct, nchunk_oct, src, dt, part);
+    else
+        hipLaunchKernelGGL((k_transient3d<T, LIM, false>), dim3(blocks), dim3(256), 0, s, d, ein, eout, TLdev, din,
+                           items, nitems, na_oct, nchunk_oct, src, dt, part);
 }
 
 template <typename T>
