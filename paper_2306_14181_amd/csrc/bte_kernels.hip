@@ -83,9 +83,98 @@ __global__ void k_cell_setup(Dev d, double *S, double *kdif, double *kcor, doubl
 
 // ------------------------------------------------------------------- moments
 
+// Moments of e per cell (eqs. BTE_get_e0 and getTQ: sum w e, sum w e (1/tau +
+// gamma), sum w v s_a e) into part[c * 5 + m].  One wavefront per cell, four
+// cells per block; a lane reads 16 consecutive bytes (4 FP32 or 2 FP64
+// elements) per load, 64 lanes a contiguous 1 KiB, and the direction and
+// band of its elements advance incrementally; the quadrature and band
+// constants come from LDS tables loaded once per block.  FP64 accumulation,
+// then a butterfly over the 64 lanes.  Needs a 16-byte aligned e, nk a
+// multiple of the vector width and the tables to fit (k_moments_block
+// otherwise).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_moments(Dev d, const T *__restrict__ e, const double *__restrict__ dpend,
-                                                     double *__restrict__ part)
+__global__ __launch_bounds__(256) void k_moments_wave(Dev d, const T *__restrict__ e,
+                                                      const double *__restrict__ dpend, double *__restrict__ part)
+{
+    constexpr int kV = 16 / (int)sizeof(T);
+    extern __shared__ double tab[];
+    const int na = d.na, nl = d.nl, nk = d.nk;
+    double *tw = tab, *ts0 = tab + na, *ts1 = tab + 2 * na, *ts2 = tab + 3 * na;
+    double *tv = tab + 4 * na, *tit = tv + nl, *tc4 = tv + 2 * nl;
+    for (int i = threadIdx.x; i < na; i += blockDim.x) {
+        tw[i] = d.w[i];
+        ts0[i] = d.s[3 * i];
+        ts1[i] = d.s[3 * i + 1];
+        ts2[i] = d.s[3 * i + 2];
+    }
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+        tv[i] = d.v[i];
+        tit[i] = d.itau[i];
+        tc4[i] = d.C4[i];
+    }
+    __syncthreads();
+    const int c = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (c >= d.nc) return;
+    const int lane = threadIdx.x & 63;
+    double acc[kMomN] = {0, 0, 0, 0, 0};
+    if (d.code[c] & kSolidBit) {
+        const double g = d.gamma[c];
+        const double dp = dpend ? dpend[c] : 0.0;
+        // (direction, band) of the lane's first element and the advance per
+        // step of 64 kV elements
+        const int k0 = kV * lane, step = 64 * kV;
+        int al = k0 / nl, l = k0 - al * nl;
+        const int dA = step / nl, dL = step - dA * nl;
+        const T *row = e + (size_t)c * nk;
+        for (int kb = k0; kb < nk; kb += step) {
+            T v[kV];
+            if constexpr (kV == 4) {
+                const float4 q = *reinterpret_cast<const float4 *>(row + kb);
+                v[0] = q.x;
+                v[1] = q.y;
+                v[2] = q.z;
+                v[3] = q.w;
+            } else {
+                const double2 q = *reinterpret_cast<const double2 *>(row + kb);
+                v[0] = q.x;
+                v[1] = q.y;
+            }
+            int a = al, b = l;
+#pragma unroll
+            for (int u = 0; u < kV; ++u) {
+                const double x = (double)v[u] + tc4[b] * dp;
+                const double wx = tw[a] * x;
+                acc[0] += wx;
+                acc[1] += wx * (tit[b] + g);
+                const double vw = wx * tv[b];
+                acc[2] += vw * ts0[a];
+                acc[3] += vw * ts1[a];
+                acc[4] += vw * ts2[a];
+                if (++b == nl) {
+                    b = 0;
+                    ++a;
+                }
+            }
+            al += dA;
+            l += dL;
+            if (l >= nl) {
+                l -= nl;
+                ++al;
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < kMomN; ++m)
+        for (int off = 32; off > 0; off >>= 1) acc[m] += __shfl_xor(acc[m], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int m = 0; m < kMomN; ++m) part[(size_t)c * kMomN + m] = acc[m];
+}
+
+// General form: one block per cell.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_moments_block(Dev d, const T *__restrict__ e,
+                                                          const double *__restrict__ dpend, double *__restrict__ part)
 {
     __shared__ double sh[4 * kMomN];
     const int c = blockIdx.x;
@@ -683,7 +772,12 @@ __global__ __launch_bounds__(kBlock) void k_keff(Dev d, const double *__restrict
 template <typename T>
 void launch_moments(const Dev &d, const T *e, const double *dpend, double *part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_moments<T>, dim3(d.nc), dim3(kBlock), 0, s, d, e, dpend, part);
+    constexpr int kV = 16 / (int)sizeof(T);
+    const size_t tab = 8 * (4 * (size_t)d.na + 3 * (size_t)d.nl);
+    if (d.nk % kV == 0 && tab <= 48 * 1024 && (reinterpret_cast<uintptr_t>(e) & 15) == 0)
+        hipLaunchKernelGGL(k_moments_wave<T>, dim3((d.nc + 3) / 4), dim3(256), tab, s, d, e, dpend, part);
+    else
+        hipLaunchKernelGGL(k_moments_block<T>, dim3(d.nc), dim3(kBlock), 0, s, d, e, dpend, part);
 }
 
 template <typename T>
