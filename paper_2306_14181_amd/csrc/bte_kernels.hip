@@ -126,8 +126,9 @@ __global__ __launch_bounds__(256) void k_moments_wave(Dev d, const T *__restrict
         int al = k0 / nl, l = k0 - al * nl;
         const int dA = step / nl, dL = step - dA * nl;
         const T *row = e + (size_t)c * nk;
-        for (int kb = k0; kb < nk; kb += step) {
-            T v[kV];
+        // two vector loads in flight per lane (the second clamped to the
+        // row's last vector when past its end, and then not accumulated)
+        auto load = [&](int kb, T (&v)[kV]) {
             if constexpr (kV == 4) {
                 const float4 q = *reinterpret_cast<const float4 *>(row + kb);
                 v[0] = q.x;
@@ -139,10 +140,13 @@ __global__ __launch_bounds__(256) void k_moments_wave(Dev d, const T *__restrict
                 v[0] = q.x;
                 v[1] = q.y;
             }
+        };
+        const bool corr = dp != 0.0;   // uniform: the C/(4 pi) table is read only with a pending correction
+        auto accumulate = [&](const T (&v)[kV]) {
             int a = al, b = l;
 #pragma unroll
             for (int u = 0; u < kV; ++u) {
-                const double x = (double)v[u] + tc4[b] * dp;
+                const double x = corr ? (double)v[u] + tc4[b] * dp : (double)v[u];
                 const double wx = tw[a] * x;
                 acc[0] += wx;
                 acc[1] += wx * (tit[b] + g);
@@ -161,6 +165,14 @@ __global__ __launch_bounds__(256) void k_moments_wave(Dev d, const T *__restrict
                 l -= nl;
                 ++al;
             }
+        };
+        for (int kb = k0; kb < nk; kb += 2 * step) {
+            const int kb2 = kb + step < nk ? kb + step : nk - kV;
+            T v0[kV], v1[kV];
+            load(kb, v0);
+            load(kb2, v1);
+            accumulate(v0);
+            if (kb + step < nk) accumulate(v1);
         }
     }
 #pragma unroll
