@@ -408,8 +408,21 @@ def main():
             % (args.steps, t, st["ms_sweep"], st["ms_walls"], st["ms_post"], st["ms_cg"], st["cg_iters"]))
         sweep_launch_ms = st["ms_sweep"] / max(st["sweep_launches"], 1)
         achieved = BYTES_PER_UPDATE[prec] * updates * args.steps / (st["ms_sweep"] * 1e-3) / 1e9
+        # the standalone moment reduction (bte_moments: the moment kernel and
+        # the per-cell finalize) over the resident state, HIP events
+        prob.moments(e)
+        m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        nm = 10
+        m0.record()
+        for _ in range(nm):
+            prob.moments(e)
+        m1.record()
+        torch.cuda.synchronize()
+        mom_ms = m0.elapsed_time(m1) / nm
+        mom_GBs = BYTES_PER_UPDATE[prec] / 2 * updates / (mom_ms * 1e-3) / 1e9
+        log("moments: %.3f ms per call, %.0f GB/s" % (mom_ms, mom_GBs))
         results[prec] = dict(t=t, st=st, updates=updates, achieved=achieved, prob=prob, e=e,
-                             sweep_launch_ms=sweep_launch_ms)
+                             sweep_launch_ms=sweep_launch_ms, mom_ms=mom_ms, mom_GBs=mom_GBs)
         if args.no_accuracy:
             del prob, e
             torch.cuda.empty_cache()
@@ -469,6 +482,9 @@ def main():
             "bytes_per_sweep": BYTES_PER_UPDATE[B.F32] * r32["updates"],
         },
         "phase_ms_per_step": {k: r32["st"][k] / args.steps for k in ("ms_sweep", "ms_walls", "ms_post", "ms_cg")},
+        "moment_reduction": {"kernel": "k_moments_wave<float> + k_finalize (bte_moments)", "ms": r32["mom_ms"],
+                             "achieved": r32["mom_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": r32["mom_GBs"] / HBM_PEAK_GBS, "bytes": BYTES_PER_UPDATE[B.F32] / 2 * r32["updates"]},
     }
     if B.F64 in results:
         r64 = results[B.F64]

@@ -659,9 +659,12 @@ __device__ inline void cg_cell_load(const Dev &d, const CgArgs &g, const double 
 __global__ __launch_bounds__(kBlock) void k_cg_iter(Dev d, CgArgs g, int it)
 {
     __shared__ double sh[32];
-    if (g.scal[5] != 0.0) return;
     const int nb = gridDim.x, nthr = nb * kBlock;
     const int cur = it & 1, nxt = cur ^ 1;
+    // the solve's flag and scalars are loaded together with the first
+    // cell's values; the flag is tested once the partials are reduced (a
+    // finished solve's launches then return without writing)
+    const double done = g.scal[5], bn2s = g.scal[1], gprev = g.scal[10 + nxt], aprev = g.scal[12 + nxt];
     const double *__restrict__ R = g.rb[cur];
     const double *__restrict__ W = g.wb[cur];
     const double *__restrict__ S = g.sb[nxt];   // s_(it-1)
@@ -673,15 +676,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_iter(Dev d, CgArgs g, int it)
     cg_cell_load(d, g, R, W, S, c0 < d.nc ? c0 : 0, q);
     double ga, de, rr;
     part_sum3(g.part + 3 * nb * cur, nb, sh, ga, de, rr);
-    const double bn2 = it == 0 ? rr : g.scal[1];
+    if (done != 0.0) return;
+    const double bn2 = it == 0 ? rr : bn2s;
     double alpha = 0.0, beta = 0.0;
     bool stop = !(rr > g.rtol2 * bn2) || !(ga > 0.0);
     if (!stop) {
         if (it == 0) {
             alpha = ga / de;
         } else {
-            beta = ga / g.scal[10 + nxt];
-            alpha = ga / (de - beta * ga / g.scal[12 + nxt]);
+            beta = ga / gprev;
+            alpha = ga / (de - beta * ga / aprev);
         }
         stop = !(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta);
     }
