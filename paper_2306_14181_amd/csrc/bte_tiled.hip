@@ -139,6 +139,25 @@ __global__ __launch_bounds__(256) void k_sweep_tile(Dev d, const T *__restrict__
     tile_load<T>(t, S, ein, k, active, L.C4, static_cast<const T *>(d.zrow), eout);
     __syncthreads();
 
+    // lane constants of the moment partials (phase C), FP64: forward
+    // w, w/tau, w v s_a; adjoint C/(4 pi) /tau, C/(4 pi)
+    constexpr int NM = ADJ ? 2 : kMomN;
+    double *const lc = S.mom;   // [64][NM]
+    if (wave == 0) {
+        double cst[kMomN];
+        if constexpr (ADJ) {
+            cst[0] = d.C4[L.l] * d.itau[L.l];
+            cst[1] = d.C4[L.l];
+        } else {
+            cst[0] = L.w;
+            cst[1] = L.witau;
+            cst[2] = L.wv[0];
+            cst[3] = L.wv[1];
+            cst[4] = L.wv[2];
+        }
+#pragma unroll
+        for (int m = 0; m < NM; ++m) lc[lane * NM + m] = active ? cst[m] : 0.0;
+    }
     T wsa[3] = {(T)0, (T)0, (T)0};
     T gl = (T)0;
     if (ADJ) {
@@ -178,37 +197,78 @@ __global__ __launch_bounds__(256) void k_sweep_tile(Dev d, const T *__restrict__
             if (u0 >= 0) num += cp0 * S.bsh[u0 * 64 + lane];
             if (DIM > 1 && u1 >= 0) num += cp1 * S.bsh[u1 * 64 + lane];
             if (DIM > 2 && u2 >= 0) num += cp2 * S.bsh[u2 * 64 + lane];
-            S.bsh[i * 64 + lane] = num / (A0 + (T)S.gam[i]);
+            const T den = A0 + (T)S.gam[i];
+            if constexpr (sizeof(T) == 4) S.bsh[i * 64 + lane] = num * __builtin_amdgcn_rcpf(den);
+            else S.bsh[i * 64 + lane] = num / den;
         }
     }
     __syncthreads();
 
+    // phase C: new values, and the moment partials of each wavefront's cells
+    // (i = wave + 4 m) by a transposed reduction: 8 cells' values are staged
+    // in LDS (the upwind-increment buffer, free after phase A), then lane
+    // 8 j + p sums cell j over lanes 8 p .. 8 p + 7 and three data-parallel
+    // moves finish the 64-lane sums.
     const int pidx = it.oct * nchunk_oct + it.chunk;
-    for (int i = wave; i < t.nt; i += 4) {
-        const int c = uni(S.cell[i]);
-        const bool solid = uni(S.code[i]) & kSolidBit;
-        double acc[kMomN] = {0, 0, 0, 0, 0};
-        if (active) {
-            if (solid) {
-                const T en = S.box[i * 64 + lane] + S.bsh[i * 64 + lane];
-                eout[(size_t)c * d.nk + k] = en;
-                const double x = (double)en;
-                if constexpr (ADJ) {
-                    acc[0] = d.C4[L.l] * (d.itau[L.l] + S.gam[i]) * x;
-                } else {
-                    acc[0] = L.w * x;
-                    acc[1] = (L.witau + L.w * S.gam[i]) * x;
-                    acc[2] = L.wv[0] * x;
-                    acc[3] = L.wv[1] * x;
-                    acc[4] = L.wv[2] * x;
+    T *const xs = S.dup + (size_t)wave * 8 * 64;
+    const int nmine = (t.nt - wave + 3) / 4;
+    for (int m0 = 0; m0 < nmine; m0 += 8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            T xv = (T)0;
+            const int m = m0 + j;
+            if (m < nmine) {
+                const int i = wave + 4 * m;
+                const int c = uni(S.cell[i]);
+                const bool solid = uni(S.code[i]) & kSolidBit;
+                if (active) {
+                    if (solid) {
+                        const T en = S.box[i * 64 + lane] + S.bsh[i * 64 + lane];
+                        eout[(size_t)c * d.nk + k] = en;
+                        xv = en;
+                    } else {
+                        eout[(size_t)c * d.nk + k] = ein[(size_t)c * d.nk + k];
+                    }
                 }
+            }
+            xs[j * 64 + lane] = xv;
+        }
+        const int j = lane >> 3, p8 = lane & 7;
+        double acc[NM];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) acc[m] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int l2 = 8 * p8 + q;
+            const double x = (double)xs[j * 64 + l2];
+#pragma unroll
+            for (int m = 0; m < NM; ++m) acc[m] += lc[l2 * NM + m] * x;
+        }
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            double v = acc[m];
+            v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+            v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+            v += dpp_f64<0x141>(v);   // row_half_mirror
+            acc[m] = v;
+        }
+        // every lane of the 8-lane group j now holds cell j's total
+        const int mj = m0 + j;
+        if (p8 == 0 && mj < nmine) {
+            const int i = wave + 4 * mj;
+            const int c = S.cell[i];
+            const double g = S.gam[i];
+            double *o = part + ((size_t)pidx * d.nc + c) * kMomN;
+            if constexpr (ADJ) {
+                o[0] = acc[0] + g * acc[1];
             } else {
-                eout[(size_t)c * d.nk + k] = ein[(size_t)c * d.nk + k];
+                o[0] = acc[0];
+                o[1] = acc[1] + g * acc[0];
+                o[2] = acc[2];
+                o[3] = acc[3];
+                o[4] = acc[4];
             }
         }
-        wave_sum_t<kMomN>(acc);
-        if (lane == 0)
-            for (int q = 0; q < kMomN; ++q) part[((size_t)pidx * d.nc + c) * kMomN + q] = acc[q];
     }
 }
 
