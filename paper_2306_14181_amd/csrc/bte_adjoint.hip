@@ -67,6 +67,8 @@ __global__ __launch_bounds__(256) void k_adj_res(Dev d, const T *__restrict__ ps
                                                  double *__restrict__ part)
 {
     extern __shared__ __align__(16) char smem[];
+    __shared__ T sy[4][8][64];
+    __shared__ double sc4[64];
     TileSmem<T> S = tile_smem<T>(smem, cap, false);
     const int nb = gridDim.x, bb = blockIdx.x;
     const int lb = (bb & 7) * (nb >> 3) + (bb >> 3);
@@ -91,25 +93,48 @@ __global__ __launch_bounds__(256) void k_adj_res(Dev d, const T *__restrict__ ps
 #pragma unroll
         for (int a = 0; a < 3; ++a) wsa[a] = (T)(L.w * fabs(d.s[3 * L.al + a]));
         const T gl = (T)(gfac * L.wv[0]);
-        const double c4 = d.C4[L.l];
+        if (wave == 0) sc4[lane] = active ? d.C4[L.l] : 0.0;
         tile_load<T>(t, S, psi, k, active, L.C4, static_cast<const T *>(d.zrow));
         __syncthreads();
-        for (int i = wave; i < t.nt; i += 4) {
-            const bool solid = uni(S.code[i]) & kSolidBit;
-            double acc[2] = {0, 0};
-            if (active && solid) {
-                int up_out[3];
-                const T tf = tile_flux_adj<T, DIM>(d, t, S, i, L, wsa, lane, psi, dinA, up_out);
-                const T ec = S.box[i * 64 + lane];
-                const T itc = L.itau + (T)S.gam[i];
-                const double y = (double)(tf - ec * itc + (T)L.w * itc * (T)S.tl[i] + gl);
-                acc[0] = c4 * y;
-                acc[1] = y * y;
+        T *const ys = &sy[wave][0][0];
+        const int nmine = (t.nt - wave + 3) / 4;   // cells i = wave + 4 m
+        for (int m0 = 0; m0 < nmine; m0 += 8) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int m = m0 + j;
+                T y = (T)0;
+                if (m < nmine) {
+                    const int i = wave + 4 * m;
+                    if (active && (uni(S.code[i]) & kSolidBit)) {
+                        int up_out[3];
+                        const T tf = tile_flux_adj<T, DIM>(d, t, S, i, L, wsa, lane, psi, dinA, up_out);
+                        const T ec = S.box[i * 64 + lane];
+                        const T itc = L.itau + (T)S.gam[i];
+                        y = tf - ec * itc + (T)L.w * itc * (T)S.tl[i] + gl;
+                    }
+                }
+                ys[j * 64 + lane] = y;
             }
-            wave_sum_t<2>(acc);
-            if (lane == 0) {
-                S.mom[2 * i] += acc[0];
-                S.mom[2 * i + 1] += acc[1];
+            const int j = lane >> 3, p8 = lane & 7;
+            double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int l2 = 8 * p8 + q;
+                const double y = (double)ys[j * 64 + l2];
+                a0 += sc4[l2] * y;
+                a1 += y * y;
+            }
+            a0 += dpp_f64<0xB1>(a0);
+            a0 += dpp_f64<0x4E>(a0);
+            a0 += dpp_f64<0x141>(a0);
+            a1 += dpp_f64<0xB1>(a1);
+            a1 += dpp_f64<0x4E>(a1);
+            a1 += dpp_f64<0x141>(a1);
+            const int mj = m0 + j;
+            if (p8 == 0 && mj < nmine) {
+                const int i = wave + 4 * mj;
+                S.mom[2 * i] += a0;
+                S.mom[2 * i + 1] += a1;
             }
         }
         __syncthreads();
@@ -441,12 +466,14 @@ void launch_tave(const Dev &d, const double *a, const double *T, double *out, hi
 template <typename T> hipError_t set_lds_adj(size_t bytes)
 {
     hipError_t r = hipSuccess, x;
+    // k_adj_res also has static LDS (its staging of 8 cells per wavefront)
+    const int res_bytes = (int)bytes - (int)(sizeof(T) * 4 * 8 * 64 + 8 * 64);
     if ((x = hipFuncSetAttribute(reinterpret_cast<const void *>(k_adj_res<T, 1>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) r = x;
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, res_bytes)) != hipSuccess) r = x;
     if ((x = hipFuncSetAttribute(reinterpret_cast<const void *>(k_adj_res<T, 2>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) r = x;
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, res_bytes)) != hipSuccess) r = x;
     if ((x = hipFuncSetAttribute(reinterpret_cast<const void *>(k_adj_res<T, 3>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) r = x;
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, res_bytes)) != hipSuccess) r = x;
     if ((x = hipFuncSetAttribute(reinterpret_cast<const void *>(k_adj_step<T, 1>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess) r = x;
     if ((x = hipFuncSetAttribute(reinterpret_cast<const void *>(k_adj_step<T, 2>),
