@@ -89,6 +89,10 @@ using namespace bte;
 
 namespace {
 
+// Width (in columns) of the strips in which the three-dimensional column
+// walks are ordered.
+constexpr int kColStrip = 16;
+
 // Gauss-Legendre nodes/weights on [-1, 1], ascending (Newton on P_n).
 void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
 {
@@ -529,13 +533,21 @@ void build_schedule(bte_problem *p)
         for (int o = 0; o < p->noct; ++o)
             for (int t = 0; t < ntile; ++t) p->titems.push_back({f, o, t, 0});
     }
+    // Columns of one (geometry, octant, chunk) in strips of kColStrip along
+    // x, each strip row by row: the y neighbours of a column are then walked
+    // kColStrip and 2 kColStrip items earlier or later, close enough that
+    // their values are still in the XCD's L2 (row by row over the whole
+    // width they were 64 and 128 columns apart, and were fetched again).
     p->citems.clear();
     if (p->dim == 3)
         for (int f = 0; f < p->nfilm; ++f) {
             const Film &fm = p->films[f];
             for (int o = 0; o < p->noct; ++o)
                 for (int ch = 0; ch < p->nchunk_oct; ++ch)
-                    for (int col = 0; col < fm.n[0] * fm.n[1]; ++col) p->citems.push_back({f, o, ch, col});
+                    for (int x0 = 0; x0 < fm.n[0]; x0 += kColStrip)
+                        for (int y = 0; y < fm.n[1]; ++y)
+                            for (int x = x0; x < std::min(x0 + kColStrip, fm.n[0]); ++x)
+                                p->citems.push_back({f, o, ch, x + fm.n[0] * y});
         }
     p->tile_cap = tile_cap_of(p, p->tdim);
     p->tile_cap_tr = tile_cap_of(p, p->tdim_tr);
