@@ -211,6 +211,84 @@ def cpu_baseline_transient():
                 kind="oracle", sample="%d explicit steps of the laser workload on a 32^3 grid, %.1f s" % (steps, dt))
 
 
+def bench_ttg(args):
+    """Transient thermal grating at the paper's size (1000 cells, 512
+    directions, gray, periodic) in three regimes, each run to t* = t / tau =
+    2: explicit-step rate and the grating amplitude against the continuous
+    gray solution."""
+    import numpy as np
+    import torch
+
+    import bte_inputs as I
+    from paper_2306_14181_amd import bte as B
+    from tests.helpers import ttg_continuous_amplitude
+
+    torch.cuda.set_device(0)
+    x = (np.arange(1000) + 0.5) * 1e-9
+    runs = []
+    for xi in (0.1, 1.0, 10.0):
+        cfg = I.ttg(xi)
+        m = cfg["material"]
+        steps = int(round(2.0 * cfg["tau"] / cfg["dt"]))
+        ac = float(ttg_continuous_amplitude([2.0], m["v"][0], cfg["tau"], 1e-6)[0])
+        for prec in ([B.F32] if args.no_fp64 else [B.F32, B.F64]):
+            prob = B.Problem(cfg["geometry"], m, dict(precision=prec, limiter=B.LIM_NONE, dt=cfg["dt"]))
+            prob.set_fields(None, None)
+            e0 = (m["C"][0] * (cfg["T0"] - 300.0) / (4 * np.pi))[:, None] * np.ones(512)[None, :]
+            e = torch.as_tensor(e0.reshape(-1), device="cuda").to(prob.dtype)
+            w = prob.zeros()
+            w.copy_(e)
+            prob.transient_step(w, args.warmup)   # warm-up on a copy
+            prob.set_timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            prob.transient_step(e, steps)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            st = prob.last_stats()
+            T, _, _ = prob.moments(e)
+            amp = 2.0 * float(np.mean((T.cpu().numpy() - 300.0) * np.cos(2 * np.pi * x / 1e-6)))
+            runs.append(dict(xi=xi, prec=prec, steps=steps, t=t, kern_ms=st["ms_sweep"] / steps,
+                             upd=prob.n_unknowns, amp=amp, cont=ac))
+            log("ttg xi %.1f prec %d: %d steps %.3f s (%.1f us per step, transport %.1f us), A/A0 %.5f, "
+                "continuous %.5f" % (xi, prec, steps, t, 1e6 * t / steps, 1e3 * st["ms_sweep"] / steps, amp, ac))
+            del prob, e, w
+    f32 = [r for r in runs if r["prec"] == B.F32]
+    upd = sum(r["upd"] * r["steps"] for r in f32)
+    tt = sum(r["t"] for r in f32)
+    kern_ms = sum(r["kern_ms"] * r["steps"] for r in f32) / sum(r["steps"] for r in f32)
+    achieved = BYTES_PER_UPDATE[B.F32] * f32[0]["upd"] / (kern_ms * 1e-3) / 1e9
+    out = {
+        "metric": "cell*dir*band updates/s (FP32 state, FP64 moments) of explicit transient steps",
+        "value": upd / tt, "unit": "updates/s", "n_gpus": 1, "steps": sum(r["steps"] for r in f32),
+        "warmup": args.warmup, "ms_per_step": 1e3 * tt / sum(r["steps"] for r in f32), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (e), f64 (moments)",
+        "data": "synthetic (gray band, cosine grating)",
+        "config": {"workload": "ttg1d: 1000 cells, one 1 um period, 512 directions, 1 band, xi 0.1 / 1 / 10 "
+                   "to t* = 2, no limiter"},
+        "roofline": {"bound": "hbm", "kernel": "k_transient_tile<float,1D,NONE> (one launch per step)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "avg_launch_ms": kern_ms,
+                     "bytes_per_launch": BYTES_PER_UPDATE[B.F32] * f32[0]["upd"],
+                     "note": "4 MB state: resident in L2, launch-latency bound"},
+        "amplitude_at_t2": [{"xi": r["xi"], "precision": "f32" if r["prec"] == B.F32 else "f64",
+                             "A_over_A0": r["amp"], "continuous": r["cont"]} for r in runs],
+    }
+    if not args.no_cpu_baseline:
+        import oracle as O
+        cfg = I.ttg(1.0)
+        case = O.Case(cfg["geometry"], cfg["material"])
+        e0 = (cfg["material"]["C"][0] * (cfg["T0"] - 300.0) / (4 * np.pi))[:, None] * np.ones(case.na)[None, :]
+        n = 1000
+        t0 = time.perf_counter()
+        O.transient(case, e0.reshape(-1), n, cfg["dt"])
+        dt = time.perf_counter() - t0
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = dict(value=case.nc * case.na * n / dt, unit="cell*dir*band updates/s", cores=threads,
+                                   kind="oracle", sample="%d explicit steps of the xi = 1 grating, %.1f s" % (n, dt))
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args):
     """64 porous films in one problem, FP32, converged steady solve."""
     import numpy as np
@@ -344,7 +422,7 @@ def bench_tadjoint(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=("steady2d", "transient3d", "porous2d_batch", "porous3d_adjoint",
-                                           "tadjoint3d"), default="steady2d")
+                                           "tadjoint3d", "ttg1d"), default="steady2d")
     ap.add_argument("--max-iter", type=int, default=1000, help="iteration cap of the converged solves")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--gpus", type=int, default=1)
@@ -378,6 +456,9 @@ def main():
         return
     if args.workload == "tadjoint3d":
         bench_tadjoint(args)
+        return
+    if args.workload == "ttg1d":
+        bench_ttg(args)
         return
 
     import numpy as np

@@ -451,7 +451,9 @@ std::vector<int3> tile_candidates(const bte_problem *p, int kind)
                  make_int3(3, 3, 4), make_int3(6, 4, 2), make_int3(3, 3, 3), make_int3(3, 3, 2),
                  make_int3(8, 4, 1), make_int3(8, 2, 2)};
     } else {
-        if (p->dim == 1) c = {make_int3(64, 1, 1), make_int3(32, 1, 1)};
+        if (p->dim == 1)
+            c = {make_int3(64, 1, 1), make_int3(32, 1, 1), make_int3(16, 1, 1), make_int3(8, 1, 1),
+                 make_int3(4, 1, 1)};
         else if (p->dim == 2)
             c = {make_int3(8, 8, 1), make_int3(16, 4, 1), make_int3(4, 16, 1), make_int3(8, 4, 1),
                  make_int3(16, 2, 1)};
@@ -485,7 +487,16 @@ void choose_default_tiles(bte_problem *p)
     const int lanes_oct = p->na_oct * p->nl;
     const int nchunk = (lanes_oct + 63) / 64;
     p->tdim = tile_candidates(p, BTE_TUNE_SWEEP)[0];
-    p->tdim_tr = tile_candidates(p, BTE_TUNE_TRANSIENT)[0];
+    // explicit steps in 1D: each block walks its octant's chunks in turn, so
+    // a short domain needs short tiles to give the chip enough blocks; take
+    // the largest tile that still yields two blocks per compute unit
+    const std::vector<int3> tc = tile_candidates(p, BTE_TUNE_TRANSIENT);
+    p->tdim_tr = tc[0];
+    if (p->dim == 1)
+        for (const int3 &t : tc) {
+            p->tdim_tr = t;
+            if (count_tiles(p, t) * (size_t)p->noct >= 512) break;
+        }
     p->items_cap = p->titems_cap = 0;
     for (const int3 &t : tile_candidates(p, BTE_TUNE_SWEEP))
         p->items_cap = std::max(p->items_cap, count_tiles(p, t) * p->noct * nchunk);

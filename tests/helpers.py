@@ -54,3 +54,51 @@ def small_cases():
                         pdT=(0.5, 0, 0), bcT=[300, 300, 300, 300, 299.0, 300], solid=solid),
                     mat(b2, 1, 2), rng.uniform(0, 1e17, 270), rng.uniform(0, 1e11, 270))
     return out
+
+
+# ------------------------------------------------ transient thermal grating
+
+def ttg_discrete_mode(mu, w, v, tau, n_cells, period, dt, n_steps, c, amplitude):
+    """Temperature deviation T_i - Tref after n_steps of the explicit scheme
+    on a gray transient grating, computed in Fourier space (independent of
+    the oracle).  On a periodic uniform grid a single mode exp(i theta j),
+    theta = 2 pi / n, stays a single mode: with the central least-squares
+    slope the face difference of the second-order upwind flux has the symbol
+      S = 1 + (e^{i theta} - e^{-i theta}) / 4 - e^{-i theta} - (1 - e^{-2 i theta}) / 4
+    for s_x > 0 (its conjugate for s_x < 0), so each direction's complex
+    amplitude a obeys forward Euler on
+      da/dt = -(v |mu| / h) S a + (sum_b w_b a_b / 4 pi - a) / tau
+    (gray: e0 = C T_L / 4 pi and T_L = sum w e / C).  The initial state is
+    the equilibrium of amplitude cos(2 pi x / period) at the cell centres,
+    i.e. a = (C amplitude / 4 pi) e^{i theta / 2} for every direction."""
+    n = n_cells
+    h = period / n
+    th = 2.0 * np.pi / n
+    z = np.exp(1j * th)
+    S = 1.0 + (z - 1.0 / z) / 4.0 - 1.0 / z - (1.0 - z ** -2) / 4.0
+    Sd = np.where(np.asarray(mu) > 0, S, np.conj(S))
+    lam = v * np.abs(mu) * Sd / h
+    w = np.asarray(w, dtype=np.float64)
+    a = np.full(len(w), c * amplitude / (4.0 * np.pi) * np.exp(0.5j * th), dtype=np.complex128)
+    for _ in range(n_steps):
+        a = a + dt * (-lam * a + ((w @ a) / (4.0 * np.pi) - a) / tau)
+    phase = np.exp(1j * th * np.arange(n))
+    return np.real((w @ a) * phase) / c
+
+
+def ttg_continuous_amplitude(xi_tau_t, v, tau, period, n_mu=2000):
+    """A(t)/A0 of the gray transient grating with continuous space, time and
+    angle (the reference solution the paper compares against): per
+    direction cosine mu the mode amplitude obeys
+      da/dt = -i q v mu a + (1/2 int a dmu' - a) / tau,  q = 2 pi / period,
+    a(0) = 1, solved exactly (matrix exponential) on n_mu Gauss-Legendre
+    nodes in mu; A/A0 = 1/2 sum w a.  xi_tau_t: times in units of tau."""
+    from scipy.linalg import expm
+    mu, wq = np.polynomial.legendre.leggauss(n_mu)
+    q = 2.0 * np.pi / period
+    M = -1j * q * v * np.diag(mu) + (0.5 * np.outer(np.ones(n_mu), wq) - np.eye(n_mu)) / tau
+    out = []
+    for ts in xi_tau_t:
+        a = expm(M * (ts * tau)) @ np.ones(n_mu)
+        out.append(float(np.real(0.5 * wq @ a)))
+    return np.array(out)

@@ -362,6 +362,27 @@ def test_ttg_diffusive_decay():
     assert abs(amp / expect - 1) < 0.02
 
 
+@pytest.mark.parametrize("xi", [0.5, 5.0])
+def test_ttg_paper_size_matches_fourier_mode(xi):
+    """The transient grating at the paper's size (1000 cells, 512
+    directions, gray, periodic): on a uniform periodic grid one Fourier mode
+    stays one mode, so the explicit second-order upwind scheme with
+    relaxation reduces to a 512 x 512 complex recurrence (derived from the
+    face-value symbol, not from the oracle's code).  The oracle's field must
+    equal it to rounding."""
+    from tests.helpers import ttg_discrete_mode
+    cfg = I.ttg(xi)
+    case = O.Case(cfg["geometry"], cfg["material"])
+    c = cfg["material"]["C"][0]
+    e = (c * (cfg["T0"] - 300.0) / FOURPI)[:, None] * np.ones(case.na)[None, :]
+    n_steps = 60
+    e, _ = O.transient(case, e.reshape(-1), n_steps, cfg["dt"])
+    T, _, _ = O.moments(case, e)
+    ref = ttg_discrete_mode(case.s[:, 0], case.w, cfg["material"]["v"][0], cfg["tau"], 1000, 1e-6, cfg["dt"],
+                            n_steps, c, cfg["amplitude"])
+    assert np.abs((T - 300.0) - ref).max() < 1e-12 * cfg["amplitude"]
+
+
 # -------------------------------------------------------------------- adjoint
 
 def test_adjoint_dot_product():
