@@ -41,7 +41,6 @@
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
 #endif
-#define FOURPI (4.0 * M_PI)
 
 enum { BC_THERMAL = 0, BC_SPECULAR = 1, BC_DIFFUSE = 2, BC_PERIODIC = 3 };
 enum { LIM_NONE = 0, LIM_MC = 1, LIM_MINMOD = 2 };
@@ -58,18 +57,25 @@ typedef struct {
     double pore_T;          /* wall temperature if pore_bc is thermalizing */
     int na;
     const double *s;        /* [na][3] unit directions */
-    const double *w;        /* [na] solid-angle weights (sum 4*pi) */
+    const double *w;        /* [na] angular weights (sum omega) */
     int nl;
     const double *C, *v, *tau;  /* [nl] band heat capacity, speed, relaxation time */
     double Tref;
     const double *gamma;    /* [nc] extra scattering rate (1/s) or NULL */
     const double *P;        /* [nc] volumetric heat (W/m^3) or NULL */
     int limiter;
+    double omega;           /* total angle of the direction set: 4 pi (bulk
+                               material, 0 means 4 pi) or 2 pi (two-dimensional
+                               material: in-plane directions, Sec. 2.1) */
 } orc_case;
 
 /* ------------------------------------------------------------------ basics */
 
 static int nc_of(const orc_case *p) { return p->n[0] * p->n[1] * p->n[2]; }
+/* Omega: the angular integral that replaces 4 pi in the equilibrium
+ * e0 = C T / Omega (eq. BTE_get_e0 and the remark on two-dimensional
+ * materials after it) and everywhere an isotropic value is formed */
+static double omega(const orc_case *p) { return p->omega > 0 ? p->omega : 4.0 * M_PI; }
 static double hx(const orc_case *p, int a) { return p->len[a] / p->n[a]; }
 static int is_solid(const orc_case *p, int c) { return p->solid ? p->solid[c] != 0 : 1; }
 static size_t nal(const orc_case *p) { return (size_t)p->na * p->nl; }
@@ -104,7 +110,7 @@ typedef struct {
     int is_cell;   /* 1: neighbouring solid cell; 0: wall */
     int cell;
     int wrapped;   /* reached through a periodic face */
-    int jump;      /* +1/-1: neighbour value gets +/- C*pdT/4pi */
+    int jump;      /* +1/-1: neighbour value gets +/- C*pdT/Omega */
     int bc;        /* wall type */
     double Tw;     /* wall temperature (absolute) */
 } nbr_t;
@@ -126,7 +132,7 @@ static nbr_t neighbour(const orc_case *p, int c, int a, int side)
         }
         k = (k + p->n[a]) % p->n[a];
         r.wrapped = 1;
-        /* crossing the high face lands on the low side: e(x+L) = e(x) - C dT/4pi */
+        /* crossing the high face lands on the low side: e(x+L) = e(x) - C dT/Omega */
         r.jump = side > 0 ? -1 : +1;
     }
     idx[a] = k;
@@ -142,7 +148,7 @@ static nbr_t neighbour(const orc_case *p, int c, int a, int side)
 /* value of a neighbour cell as seen from across the face (periodic jump applied) */
 static double nval(const orc_case *p, const double *e, nbr_t nb, int a, int al, int l)
 {
-    return E(p, e, nb.cell, al, l) + nb.jump * p->C[l] * p->pdT[a] / FOURPI;
+    return E(p, e, nb.cell, al, l) + nb.jump * p->C[l] * p->pdT[a] / omega(p);
 }
 
 /* ---------------------------------------------------------- reconstruction */
@@ -264,7 +270,7 @@ static double wall_in(const orc_case *p, const double *e, const walls_t *W, nbr_
 {
     switch (nb.bc) {
     case BC_THERMAL:
-        return p->C[l] * (nb.Tw - p->Tref) / FOURPI;
+        return p->C[l] * (nb.Tw - p->Tref) / omega(p);
     case BC_SPECULAR:
         /* s' = s - 2(s.n)n : flip the normal component */
         return face_val(p, e, c, a, side, W->mirror[a * p->na + al], l);
@@ -281,7 +287,7 @@ static double inflow(const orc_case *p, const double *e, const walls_t *W, int c
 {
     nbr_t nb = neighbour(p, c, a, side);
     if (nb.is_cell) {
-        double jumpv = nb.jump * p->C[l] * p->pdT[a] / FOURPI;
+        double jumpv = nb.jump * p->C[l] * p->pdT[a] / omega(p);
         return face_val(p, e, nb.cell, a, -side, al, l) + jumpv;
     }
     return wall_in(p, e, W, nb, c, a, side, al, l);
@@ -351,12 +357,12 @@ int orc_moments(const orc_case *p, const double *e, double *T, double *TL, doubl
 
 static double src_term(const orc_case *p, int c, int l, double scale)
 {
-    /* heat split over bands by heat capacity and over 4 pi (total sum_{alpha,lambda} w Q = P) */
+    /* heat split over bands by heat capacity and over Omega (total sum_{alpha,lambda} w Q = P) */
     if (!p->P) return 0.0;
-    return scale * p->P[c] * p->C[l] / (FOURPI * Ctot(p));
+    return scale * p->P[c] * p->C[l] / (omega(p) * Ctot(p));
 }
 
-/* R = -(1/V) sum_f F - (e - e0)/tau + Q, with e0 = C T_L/4pi.
+/* R = -(1/V) sum_f F - (e - e0)/tau + Q, with e0 = C T_L/Omega.
  * TLdev: per-cell lattice temperature deviation to use in e0 (NULL: from e). */
 int orc_residual(const orc_case *p, const double *e, const double *TLdev, double src_scale, double *R)
 {
@@ -372,7 +378,7 @@ int orc_residual(const orc_case *p, const double *e, const double *TLdev, double
         for (int al = 0; al < p->na; al++)
             for (int l = 0; l < p->nl; l++) {
                 double t = tau_cl(p, c, l);
-                double e0 = p->C[l] * tl / FOURPI;
+                double e0 = p->C[l] * tl / omega(p);
                 R[base + (size_t)al * p->nl + l] = -flux_div(p, e, &W, c, al, l)
                     - (E(p, e, c, al, l) - e0) / t + src_term(p, c, l, src_scale);
             }
@@ -476,30 +482,30 @@ static double sum_Cv(const orc_case *p)
 
 /* Per-axis conductivity.
  * Heat diffusion (corr = 0): k_a,i = sum_lambda C v^2 tau_i,lambda M_aa with
- * M_aa = sum_alpha w s_a^2 / 4pi (bulk conductivity of the discrete quadrature).
+ * M_aa = sum_alpha w s_a^2 / Omega (bulk conductivity of the discrete quadrature).
  * Synthetic correction (corr = 1): the same plus the conduction that the
  * first-order upwind increment of the delta-form sweep gives an isotropic
- * change, sum_lambda C v h_a H_a / 4pi with H_a = sum_{s_a > 0} w s_a. */
+ * change, sum_lambda C v h_a H_a / Omega with H_a = sum_{s_a > 0} w s_a. */
 static double k_axis(const orc_case *p, int c, int a, int corr)
 {
     double m = 0;
     for (int al = 0; al < p->na; al++) m += p->w[al] * p->s[3 * al + a] * p->s[3 * al + a];
-    m /= FOURPI;
+    m /= omega(p);
     double k = 0;
     for (int l = 0; l < p->nl; l++) k += p->C[l] * p->v[l] * p->v[l] * tau_cl(p, c, l);
     k *= m;
-    if (corr) k += sum_Cv(p) * hx(p, a) * hemi_flux(p, a) / FOURPI;
+    if (corr) k += sum_Cv(p) * hx(p, a) * hemi_flux(p, a) / omega(p);
     return k;
 }
 
 /* Conductance (per unit area) between cell c and a thermalizing wall on axis a:
  * half-cell conduction 2k/h; for the correction in series with the wall's
- * emission conductance sum C v H_a / (2 pi) (first-moment / Marshak closure). */
+ * emission conductance 2 sum C v H_a / Omega (first-moment / Marshak closure). */
 static double wall_cond(const orc_case *p, int c, int a, int corr)
 {
     double kd = 2.0 * k_axis(p, c, a, corr) / hx(p, a);
     if (!corr) return kd;
-    double g = sum_Cv(p) * hemi_flux(p, a) / (2.0 * M_PI);
+    double g = 2.0 * sum_Cv(p) * hemi_flux(p, a) / omega(p);
     return 1.0 / (1.0 / kd + 1.0 / g);
 }
 
@@ -677,24 +683,24 @@ static void eps_of(const orc_case *p, const double *T0, const double *q0, const 
     *eq = sqrt(sq / ns) / (mq > 1e-300 ? mq : 1.0);
 }
 
-/* isotropic equilibrium e = C Tdev/4pi for every direction */
+/* isotropic equilibrium e = C Tdev/Omega for every direction */
 static void set_equilibrium(const orc_case *p, const double *Tdev, double *e)
 {
     int nc = nc_of(p);
     for (int c = 0; c < nc; c++)
         for (int al = 0; al < p->na; al++)
             for (int l = 0; l < p->nl; l++)
-                e[((size_t)c * p->na + al) * p->nl + l] = is_solid(p, c) ? p->C[l] * Tdev[c] / FOURPI : 0.0;
+                e[((size_t)c * p->na + al) * p->nl + l] = is_solid(p, c) ? p->C[l] * Tdev[c] / omega(p) : 0.0;
 }
 
 /* Steady solve (Algorithm 1).
- *   scheme 0 = sequential: e0 <- C T_L(e^{n+1})/4pi
+ *   scheme 0 = sequential: e0 <- C T_L(e^{n+1})/Omega
  *   scheme 1 = synthetic, in correction form:
  *        T_L^{n+1} = T_L^kin(e^{n+1}) + delta,   L_corr delta = P - div q^{n+1},
  *     where the face flux of iterate n+1 is that of the delta-form equation
  *     (second order on e^n, first-order upwind on the increment), so that the
  *     defect equals S_i (T_L^kin(e^{n+1}) - T_L^n) per cell.  The correction
- *     shifts the isotropic part of the distribution too: e^{n+1} += C delta/4pi.
+ *     shifts the isotropic part of the distribution too: e^{n+1} += C delta/Omega.
  *     L_corr is the diffusion operator with the sweep's upwind conduction
  *     added to k and a first-moment wall conductance at thermalizing walls;
  *     these only change the path to the fixed point (delta = 0 there), and
@@ -734,7 +740,7 @@ int orc_steady(const orc_case *p, int scheme, double tol_T, double tol_q, int ma
             /* the correction moves the isotropic part of the whole distribution */
             for (int c = 0; c < nc; c++)
                     for (size_t k = 0; k < nal(p); k++)
-                        if (is_solid(p, c)) e1[(size_t)c * nal(p) + k] += p->C[k % p->nl] * dl[c] / FOURPI;
+                        if (is_solid(p, c)) e1[(size_t)c * nal(p) + k] += p->C[k % p->nl] * dl[c] / omega(p);
         } else {
             memcpy(TL, TLk, sizeof(double) * nc);
         }
@@ -752,7 +758,7 @@ int orc_steady(const orc_case *p, int scheme, double tol_T, double tol_q, int ma
         m /= ns;
         for (int c = 0; c < nc; c++)
             for (size_t k = 0; k < nal(p); k++)
-                if (is_solid(p, c)) e[(size_t)c * nal(p) + k] -= p->C[k % p->nl] * m / FOURPI;
+                if (is_solid(p, c)) e[(size_t)c * nal(p) + k] -= p->C[k % p->nl] * m / omega(p);
     }
     free(e1); free(TL); free(TLk); free(T0); free(T1); free(q0); free(q1); free(r); free(dl);
     return 0;
@@ -864,11 +870,11 @@ int orc_apply_jac_T(const orc_case *p, const double *x, double *y)
     for (int c = 0; c < nc; c++) {
         if (!is_solid(p, c)) continue;
         double Sc = S_of(p, c);
-        /* closure: row (c,al,l) has + C_l/(4 pi tau_cl) * T_L, T_L = sum w e/tau / S */
+        /* closure: row (c,al,l) has + C_l/(Omega tau_cl) * T_L, T_L = sum w e/tau / S */
         double acc = 0;
         for (int al = 0; al < p->na; al++)
             for (int l = 0; l < p->nl; l++)
-                acc += x[IX(p, c, al, l)] * p->C[l] / (FOURPI * tau_cl(p, c, l));
+                acc += x[IX(p, c, al, l)] * p->C[l] / (omega(p) * tau_cl(p, c, l));
         for (int al = 0; al < p->na; al++)
             for (int l = 0; l < p->nl; l++) {
                 double v = acc * p->w[al] / tau_cl(p, c, l) / Sc - x[IX(p, c, al, l)] / tau_cl(p, c, l);
@@ -911,7 +917,7 @@ int orc_apply_jac_T(const orc_case *p, const double *x, double *y)
 }
 
 /* dR_{c,al,l}/dgamma_c, contracted with psi:  out[c] = sum_{al,l} psi dR/dgamma_c
- *   dR/dgamma_c = -(e - e0) + C/(4 pi tau) dT_L/dgamma_c,
+ *   dR/dgamma_c = -(e - e0) + C/(Omega tau) dT_L/dgamma_c,
  *   dT_L/dgamma_c = Ctot (T_c - T_L,c)/S_c  (both as deviations). */
 int orc_dR_dgamma(const orc_case *p, const double *e, const double *psi, double *out)
 {
@@ -929,7 +935,7 @@ int orc_dR_dgamma(const orc_case *p, const double *e, const double *psi, double 
         for (int al = 0; al < p->na; al++)
             for (int l = 0; l < p->nl; l++) {
                 double t = tau_cl(p, c, l);
-                double d = -(E(p, e, c, al, l) - p->C[l] * tl / FOURPI) + p->C[l] / (FOURPI * t) * dTL;
+                double d = -(E(p, e, c, al, l) - p->C[l] * tl / omega(p)) + p->C[l] / (omega(p) * t) * dTL;
                 acc += psi[IX(p, c, al, l)] * d;
             }
         out[c] = acc;

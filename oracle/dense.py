@@ -30,7 +30,7 @@ def assemble(case, src_scale=1.0):
 def equilibrium_mode(case):
     """Uniform equilibrium shift e = C/(4 pi) on solid cells (null mode of floating domains)."""
     solid = np.ones(case.nc) if case.solid is None else case.solid.astype(np.float64)
-    return (solid[:, None, None] * np.ones(case.na)[None, :, None] * (case.C / (4 * np.pi))[None, None, :]).reshape(-1)
+    return (solid[:, None, None] * np.ones(case.na)[None, :, None] * (case.C / case.omega)[None, None, :]).reshape(-1)
 
 
 def solid_unknowns(case):

@@ -9,6 +9,17 @@ of the discrete scattering operator).  Directions are ordered octant-major
 then phi (ascending).  For a one-dimensional slab the polar axis is x and the
 azimuth is integrated: n_theta nodes per hemisphere, w = 2 pi w_theta sin(theta),
 s = (cos(theta), 0, 0); hemisphere 0 has s_x > 0.
+
+Two-dimensional materials (material_dim = 2; Sec. 2.1 replaces the solid
+angle by the in-plane polar angle, Sec. 5 MaterialDimension): directions lie
+in the x-y plane, s = (cos(theta), sin(theta), 0), with n_theta
+Gauss-Legendre nodes of theta in (0, pi/2) per quadrant, weight w_theta,
+mirrored to the four quadrants (bits 1 = s_x < 0, 2 = s_y < 0) and
+renormalised to 2 pi; on a one-dimensional slab the two signs of s_y merge:
+s = (+-cos(theta), 0, 0) with w = 2 w_theta per hemisphere.  The total angle
+Omega (4 pi or 2 pi) replaces 4 pi wherever an isotropic value is formed
+(e0 = C T_L / Omega, wall emission, source split, periodic jump).  Only
+one- and two-dimensional geometries take two-dimensional materials.
 """
 import ctypes as C
 import os
@@ -83,7 +94,7 @@ class _CCase(C.Structure):
         ("nl", C.c_int), ("C", C.POINTER(C.c_double)), ("v", C.POINTER(C.c_double)),
         ("tau", C.POINTER(C.c_double)), ("Tref", C.c_double),
         ("gamma", C.POINTER(C.c_double)), ("P", C.POINTER(C.c_double)),
-        ("limiter", C.c_int),
+        ("limiter", C.c_int), ("omega", C.c_double),
     ]
 
 
@@ -92,11 +103,31 @@ class _CStats(C.Structure):
                 ("eps_q", C.c_double), ("converged", C.c_int)]
 
 
-def quadrature(dim, n_theta, n_phi):
+def quadrature(dim, n_theta, n_phi, material_dim=3):
     """Directions s[na,3] and weights w[na] (see module docstring)."""
     xt, wt = np.polynomial.legendre.leggauss(n_theta)
     theta = (xt + 1.0) * np.pi / 4.0
     wt = wt * np.pi / 4.0
+    if material_dim == 2:
+        if dim not in (1, 2):
+            raise ValueError("two-dimensional materials take 1D or 2D geometries")
+        s, w = [], []
+        if dim == 1:
+            for sg in (1.0, -1.0):
+                for k in range(n_theta):
+                    s.append((sg * np.cos(theta[k]), 0.0, 0.0))
+                    w.append(2.0 * wt[k])
+        else:
+            for o in range(4):
+                sx = -1.0 if o & 1 else 1.0
+                sy = -1.0 if o & 2 else 1.0
+                for k in range(n_theta):
+                    s.append((sx * np.cos(theta[k]), sy * np.sin(theta[k]), 0.0))
+                    w.append(wt[k])
+        s = np.array(s, dtype=np.float64)
+        w = np.array(w, dtype=np.float64)
+        w *= 2.0 * np.pi / w.sum()
+        return s, w
     if dim == 1:
         s, w = [], []
         for sg in (1.0, -1.0):
@@ -132,7 +163,8 @@ class Case:
 
     geometry: dict(dim, n(3), len(3), solid (uint8 [nc]) or None, bc(6),
               bcT(6) absolute K, pdT(3), pore_bc)
-    material: dict(C, v, tau arrays, n_theta, n_phi, Tref)
+    material: dict(C, v, tau arrays, n_theta, n_phi, Tref, optional
+              material_dim: 3 (default) or 2)
     """
 
     def __init__(self, geometry, material, P=None, gamma=None, limiter=LIM_NONE):
@@ -142,7 +174,9 @@ class Case:
         self.len = [float(x) for x in g["len"]]
         self.nc = self.n[0] * self.n[1] * self.n[2]
         self.solid = None if g.get("solid") is None else np.ascontiguousarray(g["solid"], dtype=np.uint8)
-        self.s, self.w = quadrature(self.dim, int(m["n_theta"]), int(m.get("n_phi", 1)))
+        self.material_dim = int(m.get("material_dim", 3))
+        self.omega = 2.0 * np.pi if self.material_dim == 2 else 4.0 * np.pi
+        self.s, self.w = quadrature(self.dim, int(m["n_theta"]), int(m.get("n_phi", 1)), self.material_dim)
         self.C = np.ascontiguousarray(m["C"], dtype=np.float64)
         self.v = np.ascontiguousarray(m["v"], dtype=np.float64)
         self.tau = np.ascontiguousarray(m["tau"], dtype=np.float64)
@@ -175,6 +209,7 @@ class Case:
         c.gamma = _dp(self.gamma)
         c.P = _dp(self.P)
         c.limiter = self.limiter
+        c.omega = self.omega
         return c
 
     def with_(self, **kw):

@@ -58,7 +58,7 @@ def small_cases():
 
 # ------------------------------------------------ transient thermal grating
 
-def ttg_discrete_mode(mu, w, v, tau, n_cells, period, dt, n_steps, c, amplitude):
+def ttg_discrete_mode(mu, w, v, tau, n_cells, period, dt, n_steps, c, amplitude, omega=4.0 * np.pi):
     """Temperature deviation T_i - Tref after n_steps of the explicit scheme
     on a gray transient grating, computed in Fourier space (independent of
     the oracle).  On a periodic uniform grid a single mode exp(i theta j),
@@ -70,7 +70,8 @@ def ttg_discrete_mode(mu, w, v, tau, n_cells, period, dt, n_steps, c, amplitude)
       da/dt = -(v |mu| / h) S a + (sum_b w_b a_b / 4 pi - a) / tau
     (gray: e0 = C T_L / 4 pi and T_L = sum w e / C).  The initial state is
     the equilibrium of amplitude cos(2 pi x / period) at the cell centres,
-    i.e. a = (C amplitude / 4 pi) e^{i theta / 2} for every direction."""
+    i.e. a = (C amplitude / 4 pi) e^{i theta / 2} for every direction.  For a
+    two-dimensional material the total angle omega = 2 pi replaces 4 pi."""
     n = n_cells
     h = period / n
     th = 2.0 * np.pi / n
@@ -79,9 +80,9 @@ def ttg_discrete_mode(mu, w, v, tau, n_cells, period, dt, n_steps, c, amplitude)
     Sd = np.where(np.asarray(mu) > 0, S, np.conj(S))
     lam = v * np.abs(mu) * Sd / h
     w = np.asarray(w, dtype=np.float64)
-    a = np.full(len(w), c * amplitude / (4.0 * np.pi) * np.exp(0.5j * th), dtype=np.complex128)
+    a = np.full(len(w), c * amplitude / omega * np.exp(0.5j * th), dtype=np.complex128)
     for _ in range(n_steps):
-        a = a + dt * (-lam * a + ((w @ a) / (4.0 * np.pi) - a) / tau)
+        a = a + dt * (-lam * a + ((w @ a) / omega - a) / tau)
     phase = np.exp(1j * th * np.arange(n))
     return np.real((w @ a) * phase) / c
 
