@@ -71,7 +71,8 @@ typedef enum { BTE_OBJ_KEFF_X = 0 } bte_objective;
  * conditions).  Faces are ordered -x,+x,-y,+y,-z,+z; faces of axes beyond
  * `dim` are ignored.  Periodic faces come in pairs.  periodic_dT[a] is the
  * temperature drop imposed across a periodic axis (Sec. 2.2 (iv)): incoming
- * values on the low face get +C dT/4pi, on the high face -C dT/4pi.
+ * values on the low face get +C dT/4pi, on the high face -C dT/4pi (2 pi in
+ * place of 4 pi for a two-dimensional material, see bte_material).
  * Faces between solid cells and pores (solid[c] == 0) use pore_bc. */
 typedef struct {
     int dim;                 /* 1, 2 or 3                                  */
@@ -84,7 +85,15 @@ typedef struct {
     int pore_bc;             /* BTE_BC_DIFFUSE or BTE_BC_SPECULAR          */
 } bte_geometry;
 
-/* Phonon bands (PHONON input: BandNumber, Ntheta, Nphi; Sec. 3.1-3.2) */
+/* Phonon bands (PHONON input: BandNumber, Ntheta, Nphi, MaterialDimension;
+ * Sec. 3.1-3.2, Sec. 5).  material_dim 0 or 3: bulk material, directions on
+ * the sphere, total angle 4 pi.  material_dim 2: two-dimensional material
+ * (Sec. 2.1, the remark after eq. BTE_get_e0: the solid angle becomes the
+ * in-plane polar angle): n_theta Gauss-Legendre directions per quadrant in
+ * the x-y plane (n_phi ignored), total angle 2 pi, e0 = C T_L / 2 pi and
+ * 2 pi in place of 4 pi in every isotropic value (wall emission, source
+ * split, periodic jump); accepted for 1D and 2D geometries only
+ * (BTE_ERR_ARG for 3D). */
 typedef struct {
     int n_bands;
     const double *C;         /* host [n_bands] heat capacity, J m^-3 K^-1 */
@@ -92,6 +101,7 @@ typedef struct {
     const double *tau;       /* host [n_bands] relaxation time, s         */
     int n_theta, n_phi;      /* Gauss-Legendre nodes per octant (1D: per hemisphere, n_phi ignored) */
     double T_ref;            /* reference temperature, K                  */
+    int material_dim;        /* 0 or 3: bulk; 2: two-dimensional material */
 } bte_material;
 
 /* Control (CONTROL input, Sec. 5: IterativeScheme, MaxNumIter,

@@ -48,7 +48,7 @@ class Geometry(C.Structure):
 class Material(C.Structure):
     _fields_ = [("n_bands", C.c_int), ("C", C.POINTER(C.c_double)), ("v", C.POINTER(C.c_double)),
                 ("tau", C.POINTER(C.c_double)), ("n_theta", C.c_int), ("n_phi", C.c_int),
-                ("T_ref", C.c_double)]
+                ("T_ref", C.c_double), ("material_dim", C.c_int)]
 
 
 class Control(C.Structure):
@@ -191,6 +191,7 @@ class Problem:
         m.n_theta = int(material["n_theta"])
         m.n_phi = int(material.get("n_phi", 1))
         m.T_ref = float(material["Tref"])
+        m.material_dim = int(material.get("material_dim", 3))
         c = _control_struct(control)
         self.control = dict(control)
         self.precision = c.precision

@@ -138,6 +138,7 @@ struct bte_problem {
     int dim = 0, nfilm = 0, nc = 0, na = 0, nl = 0, nk = 0, noct = 0, na_oct = 0;
     bte_control ctl{};
     double Tref = 0, Ctot = 0, vmax = 0, itau_max = 0;
+    double omega = 4.0 * M_PI;   // total angle: 2 pi for a two-dimensional material
     std::vector<Film> films;
     std::vector<uint32_t> code;
     std::vector<int> nb, fid, dbase, wrec, mirror;
@@ -339,9 +340,9 @@ bte_status build_geometry(bte_problem *p, const bte_geometry *geo, int n_geo)
     return BTE_OK;
 }
 
-bte_status build_quadrature(bte_problem *p, int n_theta, int n_phi)
+bte_status build_quadrature(bte_problem *p, int n_theta, int n_phi, bool planar)
 {
-    if (n_theta < 1 || (p->dim > 1 && n_phi < 1)) FAIL(p, BTE_ERR_ARG, "n_theta/n_phi must be >= 1");
+    if (n_theta < 1 || (p->dim > 1 && !planar && n_phi < 1)) FAIL(p, BTE_ERR_ARG, "n_theta/n_phi must be >= 1");
     std::vector<double> xt, wt, xp, wp;
     gauss_legendre(n_theta, xt, wt);
     std::vector<double> th(n_theta), wth(n_theta);
@@ -351,7 +352,20 @@ bte_status build_quadrature(bte_problem *p, int n_theta, int n_phi)
     }
     p->s.clear();
     p->w.clear();
-    if (p->dim == 1) {
+    if (planar) {
+        // two-dimensional material: in-plane directions at angle th from x,
+        // quadrant bits 1 = s_x < 0, 2 = s_y < 0; a slab merges the two
+        // signs of s_y (weight 2 w_th per hemisphere)
+        const int nq = p->dim == 1 ? 2 : 4;
+        for (int o = 0; o < nq; ++o)
+            for (int i = 0; i < n_theta; ++i) {
+                p->s.push_back((o & 1 ? -1.0 : 1.0) * std::cos(th[i]));
+                p->s.push_back(p->dim == 1 ? 0.0 : (o & 2 ? -1.0 : 1.0) * std::sin(th[i]));
+                p->s.push_back(0.0);
+                p->w.push_back(p->dim == 1 ? 2.0 * wth[i] : wth[i]);
+            }
+        p->noct = nq;
+    } else if (p->dim == 1) {
         for (int h = 0; h < 2; ++h)
             for (int i = 0; i < n_theta; ++i) {
                 p->s.push_back((h ? -1.0 : 1.0) * std::cos(th[i]));
@@ -377,7 +391,7 @@ bte_status build_quadrature(bte_problem *p, int n_theta, int n_phi)
     p->na_oct = p->na / p->noct;
     double sw = 0;
     for (double x : p->w) sw += x;
-    for (double &x : p->w) x *= 4.0 * M_PI / sw;   // exact 4 pi: equilibrium is a fixed point
+    for (double &x : p->w) x *= p->omega / sw;   // exact total angle: equilibrium is a fixed point
     p->mirror.assign(3 * (size_t)p->na, 0);
     for (int a = 0; a < 3; ++a)
         for (int al = 0; al < p->na; ++al) {
@@ -404,7 +418,7 @@ bte_status build_quadrature(bte_problem *p, int n_theta, int n_phi)
             m += p->w[al] * sa * sa;
             if (sa > 0) h += p->w[al] * sa;
         }
-        p->M[a] = m / (4.0 * M_PI);
+        p->M[a] = m / p->omega;
         p->H[a] = h;
     }
     for (int f = 0; f < 6; ++f) {
@@ -715,6 +729,16 @@ bte_status bte_setup(const bte_geometry *geo, int n_geo, const bte_material *mat
     if (p->ctl.max_iter <= 0) p->ctl.max_iter = 10000;
     if (p->ctl.cg_max_iter <= 0) p->ctl.cg_max_iter = 2000;
     if (!(p->ctl.cg_rtol > 0)) p->ctl.cg_rtol = 1e-10;
+    if (mat->material_dim != 0 && mat->material_dim != 2 && mat->material_dim != 3) {
+        p->err = "material_dim must be 0, 2 or 3";
+        return bail(BTE_ERR_ARG);
+    }
+    const bool planar = mat->material_dim == 2;
+    if (planar && geo[0].dim == 3) {
+        p->err = "a two-dimensional material takes a 1D or 2D geometry";
+        return bail(BTE_ERR_ARG);
+    }
+    p->omega = planar ? 2.0 * M_PI : 4.0 * M_PI;
     p->Tref = mat->T_ref;
     p->nl = mat->n_bands;
     p->C4.resize(p->nl);
@@ -726,7 +750,7 @@ bte_status bte_setup(const bte_geometry *geo, int n_geo, const bte_material *mat
             p->err = "band properties must satisfy C > 0, v >= 0, tau > 0";
             return bail(BTE_ERR_ARG);
         }
-        p->C4[l] = mat->C[l] * kInvFourPi;
+        p->C4[l] = mat->C[l] / p->omega;
         p->v[l] = mat->v[l];
         p->itau[l] = 1.0 / mat->tau[l];
         p->Ctot += mat->C[l];
@@ -734,7 +758,7 @@ bte_status bte_setup(const bte_geometry *geo, int n_geo, const bte_material *mat
         p->itau_max = std::max(p->itau_max, p->itau[l]);
     }
     if ((st = build_geometry(p, geo, n_geo)) != BTE_OK) return bail(st);
-    if ((st = build_quadrature(p, mat->n_theta, mat->n_phi)) != BTE_OK) return bail(st);
+    if ((st = build_quadrature(p, mat->n_theta, mat->n_phi, planar)) != BTE_OK) return bail(st);
     p->nk = p->na * p->nl;
     choose_default_tiles(p);
     build_schedule(p);
@@ -806,6 +830,7 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
         for (int a = 0; a < 3; ++a) d.jumps |= (fm.periodic[a] && fm.pdT[a] != 0.0) ? 1 : 0;
     d.limiter = p->ctl.limiter;
     d.Ctot = p->Ctot;
+    d.omega = p->omega;
     d.poreT = 0.0;
     d.s = wsptr<double>(p, "s");
     d.w = wsptr<double>(p, "w");
@@ -912,8 +937,9 @@ CgArgs cg_args(bte_problem *p, int corr)
     g.coef = corr ? p->ccor : p->cdif;
     g.dg = corr ? p->dcor : p->ddif;
     double cv = 0;
-    for (int l = 0; l < p->nl; ++l) cv += p->C4[l] * 4.0 * M_PI * p->v[l];
-    for (int a = 0; a < 3; ++a) g.Hm[a] = cv * p->H[a] / (2.0 * M_PI);
+    for (int l = 0; l < p->nl; ++l) cv += p->C4[l] * p->omega * p->v[l];
+    // wall emission conductance of the correction (first-moment closure)
+    for (int a = 0; a < 3; ++a) g.Hm[a] = 2.0 * cv * p->H[a] / p->omega;
     g.corr = corr;
     g.p = p->cg_p;
     g.rb[0] = p->cg_r;

@@ -7,8 +7,6 @@
 
 namespace bte {
 
-constexpr double kFourPi = 12.566370614359172953850573533118;
-constexpr double kInvFourPi = 1.0 / kFourPi;
 constexpr int kBlock = 256;          // threads per block of the streaming kernels
 constexpr int kMomN = 5;             // moment partials: sum w e, sum w e/tau, q_x, q_y, q_z
 
@@ -50,11 +48,12 @@ struct Dev {
     int jumps;               // 1: some geometry has a periodic axis with a temperature drop
     int limiter;
     double Ctot;             // sum_lambda C
+    double omega;            // total angle of the direction set: 4 pi, or 2 pi for a two-dimensional material
     double poreT;            // thermalizing pore wall temperature minus T_ref
     const double *s;         // [na][3]
     const double *w;         // [na]
     const int *mirror;       // [3][na]
-    const double *C4;        // [nl] C/(4 pi)
+    const double *C4;        // [nl] C/omega (C/(4 pi) for a bulk material)
     const double *v;         // [nl]
     const double *itau;      // [nl] 1/tau
     const Film *film;        // [nfilm]

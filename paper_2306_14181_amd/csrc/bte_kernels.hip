@@ -55,9 +55,10 @@ __device__ inline int xcd_logical_block()
 // ------------------------------------------------------------------- per cell
 
 // S_c = sum C (1/tau + gamma_c); per-axis conductivities of the heat-diffusion
-// operator, k = sum C v^2 tau_c M_aa (M_aa = sum w s_a^2 / 4pi), and of the
+// operator, k = sum C v^2 tau_c M_aa (M_aa = sum w s_a^2 / Omega, Omega the total
+// angle: 4 pi, or 2 pi for a two-dimensional material), and of the
 // correction operator, which adds the conduction of the sweep's first-order
-// upwind increment, sum C v h_a H_a / 4pi (H_a = sum_{s_a>0} w s_a).
+// upwind increment, sum C v h_a H_a / Omega (H_a = sum_{s_a>0} w s_a).
 __global__ void k_cell_setup(Dev d, double *S, double *kdif, double *kcor, double m0, double m1, double m2,
                              double H0, double H1, double H2)
 {
@@ -66,7 +67,7 @@ __global__ void k_cell_setup(Dev d, double *S, double *kdif, double *kcor, doubl
     const double g = d.gamma ? d.gamma[c] : 0.0;
     double sm = 0, k = 0, cv = 0;
     for (int l = 0; l < d.nl; ++l) {
-        const double C = d.C4[l] * kFourPi;
+        const double C = d.C4[l] * d.omega;
         const double it = d.itau[l] + g;
         sm += C * it;
         k += C * d.v[l] * d.v[l] / it;
@@ -77,7 +78,7 @@ __global__ void k_cell_setup(Dev d, double *S, double *kdif, double *kcor, doubl
     const Film &fm = d.film[d.fid[c]];
     for (int a = 0; a < 3; ++a) {
         kdif[a * d.nc + c] = k * m[a];
-        kcor[a * d.nc + c] = k * m[a] + cv * fm.h[a] * H[a] / kFourPi;
+        kcor[a * d.nc + c] = k * m[a] + cv * fm.h[a] * H[a] / d.omega;
     }
 }
 

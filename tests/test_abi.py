@@ -40,6 +40,7 @@ def _setup(lib, g, m, ctl=None):
     mm.n_bands = len(bands[0])
     mm.C, mm.v, mm.tau = [b.ctypes.data_as(C.POINTER(C.c_double)) for b in bands]
     mm.n_theta, mm.n_phi, mm.T_ref = m["n_theta"], m.get("n_phi", 1), m["Tref"]
+    mm.material_dim = int(m.get("material_dim", 3))
     c = bte.Control()
     for k, v in (ctl or {}).items():
         setattr(c, k, v)
@@ -64,6 +65,40 @@ def test_directions_match_oracle_quadrature(lib, dim, nt, nph):
     np.testing.assert_allclose(w, wo, rtol=1e-14)
     assert lib.bte_num_unknowns(h) == 4 ** dim * na * 2
     assert lib.bte_workspace_bytes(h) > 0
+    lib.bte_destroy(h)
+
+
+@pytest.mark.parametrize("dim,nt", [(1, 8), (2, 1), (2, 5)])
+def test_two_dimensional_material_directions_match_oracle(lib, dim, nt):
+    """In-plane directions of a two-dimensional material (total angle 2 pi)."""
+    b = I.bands(0, 2)
+    g = geo(dim, (4,) * dim, (1e-7,) * dim, [I.BC_SPECULAR] * 6)
+    m = mat(b, nt, 1)
+    m["material_dim"] = 2
+    st, h = _setup(lib, g, m)
+    assert st == 0, lib.bte_last_error(h)
+    na = lib.bte_num_directions(h)
+    s = np.empty((na, 3))
+    w = np.empty(na)
+    assert lib.bte_get_directions(h, s.ctypes.data_as(C.POINTER(C.c_double)),
+                                  w.ctypes.data_as(C.POINTER(C.c_double))) == 0
+    so, wo = O.quadrature(dim, nt, 1, material_dim=2)
+    np.testing.assert_allclose(s, so, atol=2e-15)
+    np.testing.assert_allclose(w, wo, rtol=1e-14)
+    lib.bte_destroy(h)
+
+
+@pytest.mark.parametrize("md", [1, 4, 2])
+def test_material_dimension_checked(lib, md):
+    """material_dim must be 0, 2 or 3, and a two-dimensional material needs
+    a 1D or 2D geometry."""
+    b = I.bands(0, 2)
+    g = geo(3, (4, 4, 4), (1e-7,) * 3, [I.BC_SPECULAR] * 6)
+    m = mat(b, 2, 2)
+    m["material_dim"] = md
+    st, h = _setup(lib, g, m)
+    assert st == 1   # BTE_ERR_ARG
+    assert lib.bte_last_error(h)
     lib.bte_destroy(h)
 
 
