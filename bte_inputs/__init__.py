@@ -251,6 +251,20 @@ def ttg(xi, n_cells=1000, n_theta=256, period=1e-6, v=1e3, c=C_TOTAL, amplitude=
                 tau=tau, amplitude=amplitude)
 
 
+def modes(seed, n_modes, frac_zero_v=0.02, c_total=C_TOTAL):
+    """Seeded synthetic mode-level list (stand-in for first-principles
+    phonon data): group speed v ~ U[0, 8e3] m/s with a fraction of
+    zero-speed modes, log10 tau ~ U[-13, -8], C ~ U(0, 1] rescaled to sum
+    c_total.  Draw order: v, zero-speed mask, log10 tau, C."""
+    rng = np.random.default_rng(seed)
+    v = rng.uniform(0.0, 8e3, n_modes)
+    v[rng.random(n_modes) < frac_zero_v] = 0.0
+    tau = 10.0 ** rng.uniform(-13.0, -8.0, n_modes)
+    c = 1.0 - rng.random(n_modes)
+    c *= c_total / c.sum()
+    return dict(C=c, v=v, tau=tau)
+
+
 def random_field(seed, size, scale=1.0):
     """Seeded uniform random array in [-scale, scale) (test perturbations)."""
     rng = np.random.default_rng(seed)

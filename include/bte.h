@@ -303,6 +303,27 @@ bte_status bte_autotune(bte_problem *p, void *e_scratch, int reps, bte_tune_entr
  * wall kernels, ms_post = T_L updates). */
 bte_status bte_last_stats(const bte_problem *p, bte_solve_stats *out);
 
+/* Mean-free-path band discretisation (Sec. 3.2, eq. banddis): from a
+ * mode-level list (heat capacity C >= 0 in J m^-3 K^-1, group speed v >= 0
+ * in m/s, relaxation time tau > 0 in s, all host arrays of n_modes) to
+ * n_bands bands of the PHONON input.  The mean free path Lambda = v tau of
+ * the modes with Lambda > 0 spans [Lambda_min, Lambda_max]; that range is
+ * cut into n_bands intervals of equal width in log(Lambda) (band k holds
+ * Lambda_k <= v tau < Lambda_{k+1}, the last interval also Lambda_max;
+ * modes with v = 0 join band 0).  Per band:
+ *   C_b = sum C,  v_b = sum C v / sum C,  tau_b = sum C v^2 tau / (v_b sum C v),
+ * so that C_b, C_b v_b and C_b v_b^2 tau_b are the band's sums of C, C v and
+ * C v^2 tau.  Empty intervals are dropped: *n_out (<= n_bands) bands are
+ * written to C_out, v_out, tau_out (host arrays of n_bands), in ascending
+ * mean free path; band_of_mode (host, n_modes, may be NULL) receives each
+ * mode's band index in that numbering (-1 for a mode of an interval dropped
+ * because its sum C v is zero).  BTE_ERR_ARG: n_modes < 1,
+ * n_bands < 1, a null array, a negative C or v, a non-positive tau, or no
+ * mode with Lambda > 0.  Host computation: no problem handle, no device. */
+bte_status bte_band_discretize(const double *C, const double *v, const double *tau, long long n_modes,
+                               int n_bands, double *C_out, double *v_out, double *tau_out, int *n_out,
+                               int *band_of_mode);
+
 /* Host copy of the direction table: s[n_dir][3], w[n_dir]. */
 bte_status bte_get_directions(const bte_problem *p, double *s_host, double *w_host);
 

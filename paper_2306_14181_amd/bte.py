@@ -8,6 +8,7 @@ the import of this module fails loudly -- there is no CPU fallback.
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,7 +31,7 @@ EXPORTS = ["bte_setup", "bte_set_control", "bte_workspace_bytes", "bte_num_unkno
            "bte_steady_solve", "bte_keff", "bte_adjoint", "bte_transient_adjoint", "bte_transient_adjoint_bytes",
            "bte_set_timing", "bte_set_graphs", "bte_set_persistent", "bte_tile_candidates", "bte_set_tiles",
            "bte_autotune", "bte_last_stats",
-           "bte_get_directions", "bte_last_error", "bte_destroy"]
+           "bte_get_directions", "bte_band_discretize", "bte_last_error", "bte_destroy"]
 
 
 class BteError(RuntimeError):
@@ -110,6 +111,8 @@ def load():
         "bte_autotune": ([vp, vp, C.c_int, C.POINTER(TuneEntry), C.c_int, C.POINTER(C.c_int), vp], st),
         "bte_last_stats": ([vp, C.POINTER(SolveStats)], st),
         "bte_get_directions": ([vp, dp, dp], st),
+        "bte_band_discretize": ([dp, dp, dp, C.c_longlong, C.c_int, dp, dp, dp, C.POINTER(C.c_int),
+                                 C.POINTER(C.c_int)], st),
         "bte_last_error": ([vp], C.c_char_p),
         "bte_destroy": ([vp], None),
     }
@@ -119,6 +122,27 @@ def load():
         f.restype = res
     _lib = lib
     return lib
+
+
+def band_discretize(C_mode, v_mode, tau_mode, n_bands):
+    """Mean-free-path band discretisation of a mode-level list (eq. banddis,
+    computed by bte_band_discretize).  Returns a material dict part
+    {"C", "v", "tau"} of the non-empty bands and each mode's band index."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (C_mode, v_mode, tau_mode)]
+    n = len(arrs[0])
+    if any(len(a) != n for a in arrs):
+        raise ValueError("C, v, tau must have the same length")
+    outs = [np.zeros(max(int(n_bands), 1)) for _ in range(3)]
+    band = np.zeros(max(n, 1), dtype=np.int32)
+    nout = C.c_int(0)
+    dptr = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    st = load().bte_band_discretize(dptr(arrs[0]), dptr(arrs[1]), dptr(arrs[2]), n, int(n_bands),
+                                    dptr(outs[0]), dptr(outs[1]), dptr(outs[2]), C.byref(nout),
+                                    band.ctypes.data_as(C.POINTER(C.c_int)))
+    if st != 0:
+        raise BteError(st, "bte_band_discretize: invalid mode list or band count")
+    k = nout.value
+    return dict(C=outs[0][:k].copy(), v=outs[1][:k].copy(), tau=outs[2][:k].copy()), band[:n].copy()
 
 
 def _ptr(t):
