@@ -138,7 +138,7 @@ def bench_transient(args):
 
     torch.cuda.set_device(0)
     n = args.n or 64
-    cfg = I.config2(n=n)
+    cfg = I.cube3d_laser_case(n=n)
     P = torch.as_tensor(cfg["P"], device="cuda")
     res = {}
     for prec in ([B.F32] if args.no_fp64 else [B.F32, B.F64]):
@@ -199,7 +199,7 @@ def cpu_baseline_transient():
     import numpy as np
     import bte_inputs as I
     import oracle as O
-    cfg = I.config2(n=32)
+    cfg = I.cube3d_laser_case(n=32)
     case = O.Case(cfg["geometry"], cfg["material"], P=cfg["P"], limiter=cfg["limiter"])
     e = np.zeros(case.nc * case.na * case.nl)
     steps = 6
@@ -296,7 +296,7 @@ def bench_batch(args):
     import bte_inputs as I
     from paper_2306_14181_amd import bte as B
     torch.cuda.set_device(0)
-    cfg = I.config3()
+    cfg = I.porous2d_batch_case()
     films, mat = cfg["films"], cfg["material"]
     prob = B.Problem(films, mat, dict(precision=B.F32, scheme=B.SYNTHETIC, limiter=cfg["limiter"],
                                       residual_temp=1e-6, residual_flux=1e-5, max_iter=args.max_iter,
@@ -335,7 +335,7 @@ def bench_adjoint(args):
     import bte_inputs as I
     from paper_2306_14181_amd import bte as B
     torch.cuda.set_device(0)
-    cfg = I.config4()
+    cfg = I.porous3d_adjoint_case()
     g, mat = cfg["geometry"], cfg["material"]
     ctl = dict(precision=B.F32, scheme=B.SYNTHETIC, limiter=B.LIM_NONE, adjoint=True, residual_temp=1e-6,
                residual_flux=1e-5, max_iter=args.max_iter, cg_rtol=1e-6, cg_max_iter=40)
@@ -389,7 +389,7 @@ def bench_tadjoint(args):
     import bte_inputs as I
     from paper_2306_14181_amd import bte as B
     torch.cuda.set_device(0)
-    cfg = I.config2(n=32)
+    cfg = I.cube3d_laser_case(n=32)
     g, mat = cfg["geometry"], cfg["material"]
     prob = B.Problem(g, mat, dict(precision=B.F32, limiter=B.LIM_NONE, dt=cfg["dt"], adjoint=True))
     P = torch.as_tensor(cfg["P"], device="cuda")
@@ -469,7 +469,7 @@ def main():
 
     torch.cuda.set_device(0)
     args.n = args.n or 256
-    cfg = I.config1(n=args.n)
+    cfg = I.square2d_source_case(n=args.n)
     geo, mat = cfg["geometry"], cfg["material"]
     P = torch.as_tensor(cfg["P"], device="cuda")
     base_ctl = dict(scheme=B.SYNTHETIC, limiter=B.LIM_NONE, cg_rtol=args.cg_rtol, cg_max_iter=args.cg_max_iter)

@@ -117,7 +117,7 @@ def porous(rng, dim, n, dx, porosity, r_lo=0.05, r_hi=0.15, ligament=2, max_trie
 
 # ------------------------------------------------------------------ workloads
 
-def config0(seed=0, n_cells=200, n_bands=10):
+def slab1d_case(seed=0, n_cells=200, n_bands=10):
     """1D cross-plane slab, L = 100 nm, walls at 301 K / 299 K, Tref 300 K,
     16 polar directions (8 per hemisphere), FP64 steady synthetic."""
     rng = np.random.default_rng(seed)
@@ -130,7 +130,7 @@ def config0(seed=0, n_cells=200, n_bands=10):
                 limiter=LIM_NONE, scheme=SCHEME_SYNTHETIC, tol_T=1e-10)
 
 
-def config1(seed=1, n=256, n_bands=20, n_theta=2, n_phi=8):
+def square2d_source_case(seed=1, n=256, n_bands=20, n_theta=2, n_phi=8):
     """2D 1 um square, 256^2 cells; heat sink y=0 edge at 300 K, other edges
     diffuse; Gaussian source (sigma 50 nm, peak 1e17 W/m^3) at the centre."""
     rng = np.random.default_rng(seed)
@@ -166,7 +166,7 @@ def tave_weights(geo, w0=200e-9):
     return np.where(top & (r2 < 4 * w0 * w0), np.exp(-2 * r2 / (w0 * w0)), 0.0)
 
 
-def config2(seed=2, n=64, n_bands=40, n_theta=4, n_phi=4):
+def cube3d_laser_case(seed=2, n=64, n_bands=40, n_theta=4, n_phi=4):
     """3D (2 um)^3 cube, n^3 cells, top (+z) face diffuse, other faces at
     300 K; Gaussian laser pulse (200 nm spot, 10 ps FWHM centred at 20 ps);
     dt = 0.5 ps explicit steps; MC limiter."""
@@ -182,7 +182,7 @@ def config2(seed=2, n=64, n_bands=40, n_theta=4, n_phi=4):
                 hist_weights=tave_weights(geo))
 
 
-def config3(seed=3, n_films=64, sides=(32, 64, 128, 192, 256), n_bands=20, n_theta=2, n_phi=4):
+def porous2d_batch_case(seed=3, n_films=64, sides=(32, 64, 128, 192, 256), n_bands=20, n_theta=2, n_phi=4):
     """Batch of 2D porous films (periodic x with dT = 1 K, periodic y, diffuse
     pores), dx = 1 um / 256; returns a list of film geometries and one band table.
 
@@ -210,7 +210,7 @@ def config3(seed=3, n_films=64, sides=(32, 64, 128, 192, 256), n_bands=20, n_the
                 scheme=SCHEME_SYNTHETIC)
 
 
-def config4(seed=4, n=48, n_bands=40, n_theta=3, n_phi=4, porosity=0.2):
+def porous3d_adjoint_case(seed=4, n=48, n_bands=40, n_theta=3, n_phi=4, porosity=0.2):
     """3D (1 um)^3 porous cube (spherical pores), periodic xyz with dT = 1 K
     along x, per-cell extra scattering rate gamma ~ U[0, 1e11] 1/s."""
     rng = np.random.default_rng(seed)

@@ -32,7 +32,7 @@ def dev(x):
 
 
 def small_batch():
-    return I.config3(seed=5, n_films=6, sides=(16, 24, 32), n_bands=4, n_theta=1, n_phi=2)
+    return I.porous2d_batch_case(seed=5, n_films=6, sides=(16, 24, 32), n_bands=4, n_theta=1, n_phi=2)
 
 
 _REF = {}
@@ -112,7 +112,7 @@ def test_keff_bulk_closed_form(B):
 def test_autograd_gradient_matches_central_differences(B):
     """KeffSteady backward (adjoint) against central differences of the GPU
     k_eff on a small porous 3D cube (h = 1e-4 relative, FP64)."""
-    cfg = I.config4(seed=9, n=10, n_bands=4, n_theta=1, n_phi=2)
+    cfg = I.porous3d_adjoint_case(seed=9, n=10, n_bands=4, n_theta=1, n_phi=2)
     g, m, gam0 = cfg["geometry"], cfg["material"], cfg["gamma"]
     ctl = dict(precision=B.F64, scheme=B.SYNTHETIC, limiter=B.LIM_NONE, adjoint=True, residual_temp=1e-13,
                residual_flux=1e-12, max_iter=20000, cg_rtol=1e-12, cg_max_iter=5000)

@@ -60,7 +60,7 @@ _SWEEP = {}
 
 def sweep_reference():
     if "ref" not in _SWEEP:
-        cfg = I.config1()
+        cfg = I.square2d_source_case()
         case = O.Case(cfg["geometry"], cfg["material"], P=cfg["P"])
         e0 = anisotropic_state(case, 101)
         e1, st = O.steady(case, scheme=0, tol_T=0.0, tol_q=0.0, max_iter=1, e=e0.astype(np.float64))
@@ -88,7 +88,7 @@ def test_full_size_sweep_matches_oracle(B, prec):
 
 
 def test_full_size_transient_step_matches_oracle(B):
-    cfg = I.config2()
+    cfg = I.cube3d_laser_case()
     case = O.Case(cfg["geometry"], cfg["material"], P=cfg["P"], limiter=O.LIM_MC)
     e0 = anisotropic_state(case, 202)
     prob = B.Problem(cfg["geometry"], cfg["material"], dict(precision=B.F32, limiter=B.LIM_MC, dt=cfg["dt"]))
@@ -112,7 +112,7 @@ def test_full_size_transient_step_matches_oracle(B):
 
 
 def test_full_size_adjoint_against_central_differences(B):
-    cfg = I.config4()
+    cfg = I.porous3d_adjoint_case()
     g, m, gam0 = cfg["geometry"], cfg["material"], cfg["gamma"]
     ctl = dict(precision=B.F64, scheme=B.SYNTHETIC, limiter=B.LIM_NONE, adjoint=True, residual_temp=1e-12,
                residual_flux=1e-11, max_iter=5000, cg_rtol=1e-12, cg_max_iter=2000)

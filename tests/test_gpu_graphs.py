@@ -60,7 +60,7 @@ def test_graph_replays_equal_plain_launches(B, name, prec):
 
 
 def test_graph_batch_with_masks_equals_plain_launches(B):
-    cfg = I.config3(seed=5, n_films=5, sides=(16, 24, 32), n_bands=4, n_theta=1, n_phi=2)
+    cfg = I.porous2d_batch_case(seed=5, n_films=5, sides=(16, 24, 32), n_bands=4, n_theta=1, n_phi=2)
     films, mat = cfg["films"], cfg["material"]
     a, sa = solve(B, films, mat, None, None, B.F32, B.LIM_MINMOD, False, 40)
     b, sb = solve(B, films, mat, None, None, B.F32, B.LIM_MINMOD, True, 40)
@@ -92,7 +92,7 @@ def test_queue_sweep_equals_diagonal_launches(B, name, prec, lim, graphs):
 def test_queue_sweep_many_items_per_block(B):
     # 64 x 64 cells: 64 tiles x 4 octants x 10 chunks = 2560 items, several
     # per resident block of the queue launch
-    cfg = I.config1(n=64)
+    cfg = I.square2d_source_case(n=64)
     for prec in (B.F32, B.F64):
         a, sa = solve(B, cfg["geometry"], cfg["material"], cfg["P"], None, prec, B.LIM_NONE, True, 30,
                       persistent=False, max_iter=12)
@@ -104,7 +104,7 @@ def test_queue_sweep_many_items_per_block(B):
 
 @QUEUE_SKIP
 def test_queue_sweep_batch_with_masks(B):
-    cfg = I.config3(seed=5, n_films=5, sides=(16, 24, 32), n_bands=4, n_theta=1, n_phi=2)
+    cfg = I.porous2d_batch_case(seed=5, n_films=5, sides=(16, 24, 32), n_bands=4, n_theta=1, n_phi=2)
     films, mat = cfg["films"], cfg["material"]
     a, sa = solve(B, films, mat, None, None, B.F32, B.LIM_MINMOD, True, 40, persistent=False)
     b, sb = solve(B, films, mat, None, None, B.F32, B.LIM_MINMOD, True, 40, persistent=True)

@@ -156,7 +156,7 @@ def test_steady_converged(B, name, prec):
 def test_slab_config_fp64(B):
     """The 1D cross-plane slab workload at its full size (200 cells, 10 bands,
     16 directions), steady synthetic FP64 to eps_T < 1e-10."""
-    cfg = I.config0()
+    cfg = I.slab1d_case()
     case = O.Case(cfg["geometry"], cfg["material"])
     prob = B.Problem(cfg["geometry"], cfg["material"],
                      dict(precision=1, scheme=1, residual_temp=1e-12, residual_flux=1e-10, cg_rtol=1e-12))

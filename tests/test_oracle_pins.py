@@ -236,7 +236,7 @@ def test_diffusive_limit_approaches_fourier():
 
 
 def test_slab_antisymmetry_and_face_flux_conservation():
-    cfg = I.config0(n_cells=60)
+    cfg = I.slab1d_case(n_cells=60)
     case = O.Case(cfg["geometry"], cfg["material"])
     e, st = O.steady(case, scheme=1, tol_T=1e-13, tol_q=1e-13, max_iter=5000)
     assert st["converged"]
