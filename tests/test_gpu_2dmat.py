@@ -211,3 +211,29 @@ def test_ttg_paper_size_against_mode_recurrence(B, prec):
     err = float(np.abs(T.cpu().numpy() - 300.0 - ref).max())
     print(prec, "2D-material grating, steps", n, "err", err)
     assert err < (1e-10 if prec == "f64" else 2e-5) * cfg["amplitude"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batched_films_keff(B, prec):
+    """A batch of porous films of a two-dimensional material: k_eff of every
+    film against the oracle's own solve of that film."""
+    cfg = I.porous2d_batch_case(seed=5, n_films=4, sides=(16, 24), n_bands=4, n_theta=2, n_phi=1)
+    films, m = cfg["films"], dict(cfg["material"], material_dim=2)
+    p = B.F64 if prec == "f64" else B.F32
+    prob = B.Problem(films, m, dict(precision=p, scheme=B.SYNTHETIC, limiter=B.LIM_NONE,
+                                    residual_temp=1e-12 if p == B.F64 else 1e-7,
+                                    residual_flux=1e-11 if p == B.F64 else 1e-6,
+                                    max_iter=20000, cg_rtol=1e-12, cg_max_iter=5000))
+    e = prob.zeros()
+    prob.steady_solve(e, init=True, allow_not_converged=(p == B.F32))
+    k = prob.keff(e).cpu().numpy()
+    ref = []
+    for g in films:
+        case = O.Case(g, m)
+        eo, st = O.steady(case, scheme=1, tol_T=1e-13, tol_q=1e-12, max_iter=5000, cg_rtol=1e-14)
+        assert st["converged"], st
+        ref.append(O.keff(case, eo))
+    ref = np.array(ref)
+    print(prec, "k_eff", k, "oracle", ref)
+    tol = 1e-9 if p == B.F64 else 1e-5
+    assert np.all(np.abs(k - ref) <= tol * np.abs(ref)), (k, ref)
