@@ -57,6 +57,9 @@ hipError_t launch_adj_step(const Dev &, const T *, T *, const T *, const double 
 template <typename T>
 hipError_t launch_adj_step3d(const Dev &, const T *, T *, const T *, const double *, const double *, const ColItem *,
                              int, int, int, double, double *, hipStream_t);
+template <typename T>
+hipError_t launch_adj_res3d(const Dev &, const T *, const double *, const double *, const ColItem *, int, int, int,
+                            double *, hipStream_t);
 void launch_adj_step_post(const Dev &, const double *, int, const double *, double *, double *, double,
                           hipStream_t);
 template <typename T> void launch_adj_tave_init(const Dev &, const double *, double, T *, hipStream_t);
@@ -1343,9 +1346,16 @@ bte_status adjoint_impl(bte_problem *p, const T *e, double *grad, bte_solve_stat
         HIPCHK(p, hipEventRecord(ev[0], s));
         launch_walls_adj<T>(d, pin, p->d_wrec, p->d_wden, p->din, p->nw, s);
         HIPCHK(p, hipEventRecord(ev[1], s));
-        HIPCHK(p, launch_adj_res<T>(d, pin, p->adjX, p->din, p->d_titems, (int)p->titems.size(), p->tdim_tr,
-                                    p->na_oct, p->nchunk_oct, p->tile_cap_tr, p->part, s));
-        launch_adj_post(d, p->part, p->noct, p->adju, p->adjr2, s);
+        if (p->dim == 3) {
+            // column walk: partials per (octant, chunk, cell)
+            HIPCHK(p, launch_adj_res3d<T>(d, pin, p->adjX, p->din, p->d_citems, (int)p->citems.size(), p->na_oct,
+                                          p->nchunk_oct, p->part, s));
+            launch_adj_post(d, p->part, np, p->adju, p->adjr2, s);
+        } else {
+            HIPCHK(p, launch_adj_res<T>(d, pin, p->adjX, p->din, p->d_titems, (int)p->titems.size(), p->tdim_tr,
+                                        p->na_oct, p->nchunk_oct, p->tile_cap_tr, p->part, s));
+            launch_adj_post(d, p->part, p->noct, p->adju, p->adjr2, s);
+        }
         launch_film_mean(d, p->adjr2, p->fmean, p->fpart, p->fseg, s);
         HIPCHK(p, hipEventRecord(ev[2], s));
         HIPCHK(p, hipMemcpyAsync(mres.data(), p->fmean, 8 * mres.size(), hipMemcpyDeviceToHost, s));

@@ -414,7 +414,13 @@ __device__ inline T adj_axis3(const Dev &d, const T *__restrict__ lam, const dou
 
 }  // namespace
 
-template <typename T>
+// RES: the transposed residual of the steady adjoint iteration instead of a
+// transposed step (no output field, no forward state):
+//   y = J^T psi - psi / tau_c + w X / tau_c + g,  g = w v_x L_x / (dT N_cells)
+// (the k_eff objective of a geometry with a drop along x), and per
+// (octant, chunk, cell) the two partials sum C/(4 pi) y and sum y^2 at
+// part[((octant * nchunk + chunk) * 2 + q) * nc + cell].
+template <typename T, bool RES>
 __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__ lam, T *__restrict__ lout,
                                                     const T *__restrict__ ek, const double *__restrict__ X,
                                                     const double *__restrict__ dinA,
@@ -483,7 +489,7 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
     auto row0 = [&](const T *base, int b) -> const T * { return b >= 0 ? base + (size_t)(b + plane * z0) * nk : zrow; };
     const T *rx1 = row0(lam, bx1), *rx2 = row0(lam, bx2), *rxd = row0(lam, bxd);
     const T *ry1 = row0(lam, by1), *ry2 = row0(lam, by2), *ryd = row0(lam, byd);
-    const T *re = row0(ek, cb);
+    const T *re = RES ? lam : row0(ek, cb);
     const long long sx1 = bx1 >= 0 ? zstep : 0, sx2 = bx2 >= 0 ? zstep : 0, sxd = bxd >= 0 ? zstep : 0;
     const long long sy1 = by1 >= 0 ? zstep : 0, sy2 = by2 >= 0 ? zstep : 0, syd = byd >= 0 ? zstep : 0;
     const T *rc0 = lam + (size_t)(cb + plane * z0) * nk;
@@ -495,7 +501,7 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
             ry1 += sy1;
             ry2 += sy2;
             ryd += syd;
-            re += zstep;
+            if constexpr (!RES) re += zstep;
         }
         q.x1 = at(rx1);
         q.x2 = at(rx2);
@@ -503,7 +509,8 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
         q.y1 = at(ry1);
         q.y2 = at(ry2);
         q.yd = at(ryd);
-        q.e = at(re);
+        if constexpr (!RES) q.e = at(re);
+        else q.e = (T)0;
         const T *rz;
         if (f + 3 < n2) {
             rz = rc0 + (long long)(f + 3) * zstep;
@@ -546,7 +553,10 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
         r_mode = ((r_code & kSolidBit) ? 1u : 0u) | (all ? 2u : 0u);
     };
     auto rlu = [&](uint32_t v, int q) -> uint32_t { return (uint32_t)__builtin_amdgcn_readlane((int)v, q); };
-    double *__restrict__ pbase = part + (size_t)((it.oct * nchunk_oct + it.chunk) * 5) * nc;
+    constexpr int NP = RES ? 2 : 5;
+    double *__restrict__ pbase = part + (size_t)((it.oct * nchunk_oct + it.chunk) * NP) * nc;
+    const double gfac = fm.pdT[0] != 0.0 ? fm.len[0] / (fm.pdT[0] * fm.ncell) : 0.0;
+    const T gl = (T)(gfac * L.wv[0]);
 
     auto step = [&](int f, const Pre &in, Pre &out) {
         const int zo = plane * (sg2 > 0 ? f : n2 - 1 - f);
@@ -600,25 +610,34 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
             }
           }
             const T itc = itau + (T)gam;
-            ln = zc + tdt * (tf - zc * itc + (T)L.w * itc * (T)Xc);
-            if (active) {
-                const double xe = (double)in.e, itd = it0 + gam;
-                acc[0] = c4 * itd * (double)ln;
-                acc[1] = (double)zc * xe;
-                acc[2] = (double)zc * c4;
-                acc[3] = L.w * xe;
-                acc[4] = L.w * itd * xe;
+            if constexpr (RES) {
+                const T yr = tf - zc * itc + (T)L.w * itc * (T)Xc + gl;
+                if (active) {
+                    acc[0] = c4 * (double)yr;
+                    acc[1] = (double)yr * (double)yr;
+                }
+            } else {
+                ln = zc + tdt * (tf - zc * itc + (T)L.w * itc * (T)Xc);
+                if (active) {
+                    const double xe = (double)in.e, itd = it0 + gam;
+                    acc[0] = c4 * itd * (double)ln;
+                    acc[1] = (double)zc * xe;
+                    acc[2] = (double)zc * c4;
+                    acc[3] = L.w * xe;
+                    acc[4] = L.w * itd * xe;
+                }
             }
         }
-        if (active) lout[(size_t)c * nk + k] = ln;
+        if constexpr (!RES)
+            if (active) lout[(size_t)c * nk + k] = ln;
 #pragma unroll
-        for (int m = 0; m < 5; ++m) red[wv][m][f & 3][lane] = acc[m];
+        for (int m = 0; m < NP; ++m) red[wv][m][f & 3][lane] = acc[m];
         if ((f & 3) == 3 || f == n2 - 1) {
             const int j = lane >> 4, pp = lane & 15, fb = f & ~3;
             const int fj = fb + j;
-            double v[5];
+            double v[NP];
 #pragma unroll
-            for (int m = 0; m < 5; ++m) {
+            for (int m = 0; m < NP; ++m) {
                 double t = 0.0;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) t += red[wv][m][j][4 * pp + i];
@@ -631,7 +650,7 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
             if (pp == 0 && fj <= f) {
                 const int cj = cb + plane * (sg2 > 0 ? fj : n2 - 1 - fj);
 #pragma unroll
-                for (int m = 0; m < 5; ++m) pbase[(size_t)m * nc + cj] = v[m];
+                for (int m = 0; m < NP; ++m) pbase[(size_t)m * nc + cj] = v[m];
             }
         }
         z2 = z1;
@@ -664,10 +683,26 @@ hipError_t launch_adj_step3d(const Dev &d, const T *lam, T *lout, const T *ek, c
 {
     if (nitems <= 0) return hipSuccess;
     const int blocks = ((nitems + 3) / 4 + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_adj_step3d<T>), dim3(blocks), dim3(256), 0, s, d, lam, lout, ek, X, dinA, items, nitems,
-                       na_oct, nchunk_oct, dt, part);
+    hipLaunchKernelGGL((k_adj_step3d<T, false>), dim3(blocks), dim3(256), 0, s, d, lam, lout, ek, X, dinA, items,
+                       nitems, na_oct, nchunk_oct, dt, part);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_adj_res3d(const Dev &d, const T *psi, const double *X, const double *dinA, const ColItem *items,
+                            int nitems, int na_oct, int nchunk_oct, double *part, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    const int blocks = ((nitems + 3) / 4 + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_adj_step3d<T, true>), dim3(blocks), dim3(256), 0, s, d, psi, nullptr, nullptr, X, dinA,
+                       items, nitems, na_oct, nchunk_oct, 0.0, part);
+    return hipGetLastError();
+}
+
+template hipError_t launch_adj_res3d<float>(const Dev &, const float *, const double *, const double *,
+                                            const ColItem *, int, int, int, double *, hipStream_t);
+template hipError_t launch_adj_res3d<double>(const Dev &, const double *, const double *, const double *,
+                                             const ColItem *, int, int, int, double *, hipStream_t);
 
 template hipError_t launch_adj_step3d<float>(const Dev &, const float *, float *, const float *, const double *,
                                              const double *, const ColItem *, int, int, int, double, double *,
