@@ -140,8 +140,15 @@ typedef struct bte_problem bte_problem;
 
 /* Build a problem for n_geo geometries of identical dimension sharing one
  * material and control (n_geo > 1: a batch of independent films, solved
- * together).  All inputs are host memory and are copied.  On success *out
- * receives the handle; bind a workspace before any device call. */
+ * together).  Follows the inputs of Sec. 5 (CONTROL, GEOMETRY, PHONON) and
+ * the precomputation of Algorithm 1 (Sec. 3.5): the band table (Sec. 3.1),
+ * the direction set and weights of eq. directiondis (Sec. 3.2), per-cell
+ * relaxation times and boundary tables (Sec. 2.2).  All inputs are host
+ * memory and are copied.  Errors: BTE_ERR_ARG for an invalid dimension,
+ * cell count, length, boundary code, unpaired periodic face, band table or
+ * quadrature size (*out is still set so bte_last_error can report; destroy
+ * it); nothing is allocated on the device.  On success *out receives the
+ * handle; bind a workspace before any device call. */
 bte_status bte_setup(const bte_geometry *geo, int n_geo, const bte_material *mat,
                      const bte_control *ctl, bte_problem **out);
 
@@ -193,9 +200,13 @@ bte_status bte_transient_step(bte_problem *p, void *e_dev, int n_steps, double t
 bte_status bte_steady_solve(bte_problem *p, void *e_dev, int init, bte_solve_stats *stats,
                             void *stream);
 
-/* Effective conductivity along x (W/m/K) of each geometry from e:
- * k = (L_x / dT_x) * (1/N_cells) * sum_solid q_x (pores count as zero).
- * keff_dev: device double[n_geo].  Requires periodic_dT[0] != 0. */
+/* Effective conductivity along x (W/m/K) of each geometry from e: the
+ * conductivity kappa = q_x L / (T_1 - T_2) of the verification cases
+ * (Sec. 3.6) with the mean flux of a porous film (Sec. 6.1):
+ * k = (L_x / dT_x) * (1/N_cells) * sum_solid q_x (pores count as zero),
+ * q from eq. getTQ.  keff_dev: device double[n_geo], written
+ * asynchronously on `stream`.  BTE_ERR_ARG if periodic_dT[0] == 0 for a
+ * geometry (nothing written). */
 bte_status bte_keff(bte_problem *p, const void *e_dev, double *keff_dev, void *stream);
 
 /* Adjoint of the steady problem for J = k_eff (objective BTE_OBJ_KEFF_X,
@@ -303,7 +314,7 @@ bte_status bte_autotune(bte_problem *p, void *e_scratch, int reps, bte_tune_entr
  * wall kernels, ms_post = T_L updates). */
 bte_status bte_last_stats(const bte_problem *p, bte_solve_stats *out);
 
-/* Mean-free-path band discretisation (Sec. 3.2, eq. banddis): from a
+/* Mean-free-path band discretisation (Sec. 3.1, eq. banddis): from a
  * mode-level list (heat capacity C >= 0 in J m^-3 K^-1, group speed v >= 0
  * in m/s, relaxation time tau > 0 in s, all host arrays of n_modes) to
  * n_bands bands of the PHONON input.  The mean free path Lambda = v tau of

@@ -1,4 +1,4 @@
-"""Mean-free-path band discretisation, written from Sec. 3.2, eq. banddis
+"""Mean-free-path band discretisation, written from Sec. 3.1, eq. banddis
 (test infrastructure only, like the rest of oracle/).
 
 The mode list (C, v, tau) is isotropic (the paper's assumption).  The mean

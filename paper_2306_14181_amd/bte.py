@@ -400,25 +400,32 @@ class KeffSteady(torch.autograd.Function):
     scattering rate gamma (float64 tensor of n_cells on the problem's device).
 
     forward: bte_set_fields(P, gamma), steady solve from the heat-diffusion
-    guess, bte_keff.  backward: one bte_adjoint solve; geometries are
-    independent, so the gradient of sum_f w_f k_f is w_{f(c)} dk/dgamma_c.
-    The problem must be built with limiter NONE and control adjoint=True.
+    guess, bte_keff.  backward: bte_set_fields with the forward's own P and
+    gamma (another forward or set_fields on the same problem may have run in
+    between; the problem keeps these fields afterwards), then one bte_adjoint
+    solve; geometries are independent, so the gradient of sum_f w_f k_f is
+    w_{f(c)} dk/dgamma_c.  The problem must be built with limiter NONE and
+    control adjoint=True.
 
         k = KeffSteady.apply(gamma, prob, P)
     """
 
     @staticmethod
     def forward(ctx, gamma, prob, P=None):
-        prob.set_fields(P, gamma.detach().to(torch.float64).contiguous())
+        gam = gamma.detach().to(torch.float64).contiguous().clone()
+        Pf = None if P is None else P.detach().to(torch.float64).contiguous().clone()
+        prob.set_fields(Pf, gam)
         e = prob.zeros()
         prob.steady_solve(e, init=True)
         k = prob.keff(e)
-        ctx.prob, ctx.e = prob, e
+        ctx.prob, ctx.e, ctx.gamma, ctx.P = prob, e, gam, Pf
         return k
 
     @staticmethod
     def backward(ctx, grad_k):
         prob = ctx.prob
+        # the adjoint linearises about e for the fields e was solved with
+        prob.set_fields(ctx.P, ctx.gamma)
         g, _ = prob.adjoint(ctx.e)
         w = grad_k.to(torch.float64)[prob.cell_geometry]
         return g * w, None, None

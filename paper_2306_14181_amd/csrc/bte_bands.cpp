@@ -1,4 +1,4 @@
-// bte_bands.cpp -- mean-free-path band discretisation (Sec. 3.2, eq.
+// bte_bands.cpp -- mean-free-path band discretisation (Sec. 3.1, eq.
 // banddis): the step that turns a mode-level list of phonon properties into
 // the bands of the PHONON input.  Host code: one pass to find the range of
 // the mean free path, one pass that bins every mode and accumulates the

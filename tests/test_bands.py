@@ -1,4 +1,4 @@
-"""Mean-free-path band discretisation (Sec. 3.2, eq. banddis).
+"""Mean-free-path band discretisation (Sec. 3.1, eq. banddis).
 
 Oracle pins (from the equation, not re-typed): the band sums conserve the
 total heat capacity, sum C v and the bulk conductivity sum C v^2 tau; each
