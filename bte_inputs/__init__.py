@@ -166,15 +166,17 @@ def tave_weights(geo, w0=200e-9):
     return np.where(top & (r2 < 4 * w0 * w0), np.exp(-2 * r2 / (w0 * w0)), 0.0)
 
 
-def cube3d_laser_case(seed=2, n=64, n_bands=40, n_theta=4, n_phi=4):
+def cube3d_laser_case(seed=2, n=64, n_bands=40, n_theta=4, n_phi=4, length=2e-6):
     """3D (2 um)^3 cube, n^3 cells, top (+z) face diffuse, other faces at
     300 K; Gaussian laser pulse (200 nm spot, 10 ps FWHM centred at 20 ps);
-    dt = 0.5 ps explicit steps; MC limiter."""
+    dt = 0.5 ps explicit steps; MC limiter.  `length` shrinks the cube (a
+    reduced grid with the cell size, and so the Courant numbers, of the
+    64^3 case: length = n * 2 um / 64)."""
     rng = np.random.default_rng(seed)
     mat = bands(rng, n_bands, 1e-12, 1e-9)
     mat.update(n_theta=n_theta, n_phi=n_phi, Tref=300.0)
     bc = [BC_THERMAL] * 5 + [BC_DIFFUSE]
-    L = 2e-6
+    L = float(length)
     geo = _geometry(3, (n, n, n), (L, L, L), bc)
     P = laser_profile(geo)
     return dict(name="cube3d_laser", geometry=geo, material=mat, P=P, gamma=None,

@@ -117,7 +117,8 @@ def test_residual(B, name, prec, lim):
     eg = to_gpu(prob, seeded_e(case, 2))
     e = host(eg)
     R = host(prob.residual(eg))
-    assert rel_err(R, O.residual(case, e)) < (1e-11 if prec == 1 else 2e-5)
+    err = rel_err(R, O.residual(case, e))
+    assert err < (1e-11 if prec == 1 else 1e-5), (name, lim, err)
 
 
 @pytest.mark.parametrize("lim", [O.LIM_NONE, O.LIM_MC])
@@ -138,7 +139,7 @@ def test_transient_steps(B, name, prec, lim):
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("name", CASES)
 def test_steady_converged(B, name, prec, scheme):
-    tolT = 1e-12 if prec == 1 else 1e-7
+    tolT = 2e-13 if prec == 1 else 1e-7
     case, prob = build(B, name, prec, scheme=scheme, max_iter=8000, residual_temp=tolT, residual_flux=tolT * 10,
                        cg_rtol=1e-12)
     eg = prob.zeros()
@@ -147,10 +148,10 @@ def test_steady_converged(B, name, prec, scheme):
     eo, _ = O.steady(case, scheme=1, tol_T=1e-13, tol_q=1e-13, max_iter=20000, cg_rtol=1e-13)
     T, TL, q = prob.moments(eg)
     To, TLo, qo = O.moments(case, eo)
-    tol = 1e-10 if prec == 1 else 1e-5
-    assert rel_err(host(T), To, 300) < tol
-    assert rel_err(host(TL), TLo, 300) < tol
-    assert rel_err(host(q), qo) < (1e-9 if prec == 1 else 1e-4)
+    tol = 1e-11 if prec == 1 else 1e-5
+    errs = (rel_err(host(T), To, 300), rel_err(host(TL), TLo, 300), rel_err(host(q), qo))
+    print(name, prec, scheme, "steady T, T_L, q rel err", errs, "iters", st["iters"])
+    assert max(errs) < tol, (name, prec, scheme, errs)
 
 
 def test_keff_and_steady_adjoint(B):
@@ -167,12 +168,12 @@ def test_keff_and_steady_adjoint(B):
     eg = prob.zeros()
     prob.steady_solve(eg, init=True)
     k = prob.keff(eg).item()
-    assert abs(k - O.keff(case, e)) < 1e-10 * abs(O.keff(case, e))
+    assert abs(k - O.keff(case, e)) < 1e-11 * abs(O.keff(case, e)), (k, O.keff(case, e))
     prob.set_control(precision=B.F64, scheme=1, limiter=B.LIM_NONE, adjoint=True, residual_temp=1e-13,
                      max_iter=20000, cg_rtol=1e-12, cg_max_iter=5000)
     grad, st = prob.adjoint(eg)
     assert st["converged"], st
-    assert rel_err(host(grad), grad_ref) < 1e-9
+    assert rel_err(host(grad), grad_ref) < 1e-11, rel_err(host(grad), grad_ref)
 
 
 @pytest.mark.parametrize("name", ["walls2d", "periodic2d", "slab1d"])
@@ -189,7 +190,7 @@ def test_transient_adjoint(B, name):
     prob.set_fields(dev(P), dev(gam))
     J, grad, st = prob.transient_adjoint(prob.zeros(), n, dev(w), 0.0, pulse, every=5)
     assert abs(J - J_ref) < 1e-11 * max(abs(J_ref), 1e-300)
-    assert rel_err(grad.cpu().numpy(), grad_ref) < 1e-9
+    assert rel_err(grad.cpu().numpy(), grad_ref) < 1e-11, rel_err(grad.cpu().numpy(), grad_ref)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -210,7 +211,7 @@ def test_ttg_paper_size_against_mode_recurrence(B, prec):
                             cfg["amplitude"], omega=2 * np.pi)
     err = float(np.abs(T.cpu().numpy() - 300.0 - ref).max())
     print(prec, "2D-material grating, steps", n, "err", err)
-    assert err < (1e-10 if prec == "f64" else 2e-5) * cfg["amplitude"]
+    assert err < (1e-11 if prec == "f64" else 1e-5) * cfg["amplitude"], err
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -235,5 +236,5 @@ def test_batched_films_keff(B, prec):
         ref.append(O.keff(case, eo))
     ref = np.array(ref)
     print(prec, "k_eff", k, "oracle", ref)
-    tol = 1e-9 if p == B.F64 else 1e-5
-    assert np.all(np.abs(k - ref) <= tol * np.abs(ref)), (k, ref)
+    tol = 1e-11 if p == B.F64 else 1e-5
+    assert np.all(np.abs(k - ref) <= tol * np.abs(ref)), (k, ref, np.abs(k / ref - 1).max())

@@ -54,8 +54,8 @@ def test_batched_films_keff_matches_oracle(B, prec, lim):
     gl, ol = {"none": (B.LIM_NONE, O.LIM_NONE), "mc": (B.LIM_MC, O.LIM_MC),
               "minmod": (B.LIM_MINMOD, O.LIM_MINMOD)}[lim]
     prob = B.Problem(films, mat, dict(precision=p, scheme=B.SYNTHETIC, limiter=gl,
-                                      residual_temp=1e-12 if p == B.F64 else 1e-7,
-                                      residual_flux=1e-11 if p == B.F64 else 1e-6,
+                                      residual_temp=2e-13 if p == B.F64 else 1e-7,
+                                      residual_flux=2e-12 if p == B.F64 else 1e-6,
                                       max_iter=20000, cg_rtol=1e-12, cg_max_iter=5000))
     e = prob.zeros()
     st = prob.steady_solve(e, init=True, allow_not_converged=(p == B.F32))
@@ -66,8 +66,8 @@ def test_batched_films_keff_matches_oracle(B, prec, lim):
     print(prec, "iters", st["iters"], "updates", st["updates"], "k_eff", k, "oracle", ref)
     # converged films leave the sweep: never more updates than every film for every iteration
     assert 0 < st["updates"] <= prob.n_unknowns * st["iters"]
-    tol = 1e-9 if p == B.F64 else 1e-5
-    assert np.all(np.abs(k - ref) <= tol * np.abs(ref)), (k, ref)
+    tol = 1e-11 if p == B.F64 else 1e-5
+    assert np.all(np.abs(k - ref) <= tol * np.abs(ref)), (k, ref, np.abs(k / ref - 1).max())
 
 
 def test_batched_equals_separate_solves(B):
@@ -87,8 +87,9 @@ def test_batched_equals_separate_solves(B):
         one.steady_solve(e1, init=True)
         T1, _, q1 = one.moments(e1)
         n = one.n_cells
-        assert rel_err(T[off:off + n].cpu().numpy(), T1.cpu().numpy(), 300.0) < 1e-10
-        assert rel_err(q[off:off + n].cpu().numpy(), q1.cpu().numpy()) < 1e-9
+        errs = (rel_err(T[off:off + n].cpu().numpy(), T1.cpu().numpy(), 300.0),
+                rel_err(q[off:off + n].cpu().numpy(), q1.cpu().numpy()))
+        assert max(errs) < 1e-11, errs
         off += n
 
 

@@ -7,8 +7,12 @@ times (the same tiles, columns, chunks and launches):
   the oracle's sweep of the same state;
 * one explicit step of the 64^3 laser cube, 128 directions, 40 bands, MC
   limiter, FP32, element by element against the oracle's step;
-* the adjoint gradient d k_eff / d gamma of the 48^3 porous cube (FP64)
-  against central differences of the GPU k_eff on sampled cells.
+* one source iteration of the 48^3 porous cube (40 bands, 96 directions,
+  pores, per-cell scattering rates), FP32 and FP64, element by element
+  against the oracle's sweep;
+* the adjoint gradient d k_eff / d gamma of the 48^3 porous cube, FP32
+  forward and adjoint against the FP64 ones, and against central
+  differences of the FP64 k_eff on 20 random cells.
 
 Bars as in the small-case parity tests: FP32 storage 1e-5, FP64 1e-11
 (relative to the largest magnitude of the reference).
@@ -111,29 +115,92 @@ def test_full_size_transient_step_matches_oracle(B):
     assert err < 1e-5, err
 
 
+_POROUS = {}
+
+
+def porous_reference():
+    """One plain source iteration of the 48^3 porous cube (gamma field, 40
+    bands, 96 directions) from a seeded anisotropic state, by the oracle."""
+    if "ref" not in _POROUS:
+        cfg = I.porous3d_adjoint_case()
+        case = O.Case(cfg["geometry"], cfg["material"], gamma=cfg["gamma"])
+        e0 = anisotropic_state(case, 303)
+        e1, st = O.steady(case, scheme=0, tol_T=0.0, tol_q=0.0, max_iter=1, e=e0.astype(np.float64))
+        assert st["iters"] == 1
+        _POROUS["ref"] = (cfg, e0, e1)
+    return _POROUS["ref"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_full_size_porous3d_sweep_matches_oracle(B, prec):
+    """The 3D steady sweep at the porous-cube size, in the tile shape the
+    library chooses for it (periodic x, y and z, spherical pores, per-cell
+    scattering rates), element by element against the oracle's sweep."""
+    cfg, e0, e1 = porous_reference()
+    p = B.F32 if prec == "f32" else B.F64
+    prob = B.Problem(cfg["geometry"], cfg["material"], dict(precision=p, scheme=B.SEQUENTIAL, limiter=B.LIM_NONE,
+                                                            max_iter=1, residual_temp=0.0, residual_flux=0.0))
+    prob.set_fields(None, torch.as_tensor(cfg["gamma"], device="cuda"))
+    e = torch.as_tensor(e0, device="cuda").to(prob.dtype)
+    st = prob.steady_solve(e, init=False, allow_not_converged=True)
+    assert st["iters"] == 1
+    g = e.double().cpu().numpy()
+    del e, prob
+    torch.cuda.empty_cache()
+    err = rel(g, e1)
+    print(prec, "porous 48^3 sweep rel err", err)
+    assert err < (1e-5 if p == B.F32 else 1e-11), err
+
+
+def _keff_solve(B, prob, gamma, e_start=None):
+    prob.set_fields(None, torch.as_tensor(gamma, device="cuda"))
+    e = prob.zeros() if e_start is None else e_start.clone()
+    st = prob.steady_solve(e, init=e_start is None)
+    assert st["converged"], st
+    return prob.keff(e).item(), e
+
+
 def test_full_size_adjoint_against_central_differences(B):
+    """d k_eff / d gamma of the 48^3 porous cube: the FP32 forward solve and
+    adjoint behind KeffSteady against the FP64 adjoint (every cell, 1e-5 of
+    max |grad|), and both against central differences of the FP64 k_eff on
+    20 random solid cells (h = 1e-4 gamma_c, at least 1e6 1/s).  A single
+    cell moves k_eff by ~1e-9 of itself, so the difference quotient of two
+    FP64 solves converged to eps_T 1e-13 resolves the derivative to ~1e-5
+    of max |grad|; the FD bar is 1e-4 of max |grad|."""
     cfg = I.porous3d_adjoint_case()
     g, m, gam0 = cfg["geometry"], cfg["material"], cfg["gamma"]
-    ctl = dict(precision=B.F64, scheme=B.SYNTHETIC, limiter=B.LIM_NONE, adjoint=True, residual_temp=1e-12,
-               residual_flux=1e-11, max_iter=5000, cg_rtol=1e-12, cg_max_iter=2000)
-    prob = B.Problem(g, m, ctl)
+    ctl = dict(scheme=B.SYNTHETIC, limiter=B.LIM_NONE, adjoint=True, max_iter=5000, cg_rtol=1e-12,
+               cg_max_iter=2000)
+    p32 = B.Problem(g, m, dict(ctl, precision=B.F32, residual_temp=1e-7, residual_flux=1e-6))
     gamma = torch.as_tensor(gam0, device="cuda").requires_grad_(True)
-    k = B.KeffSteady.apply(gamma, prob, None)
-    k.sum().backward()
-    grad = gamma.grad.cpu().numpy()
+    k32 = B.KeffSteady.apply(gamma, p32, None)
+    k32.sum().backward()
+    grad32 = gamma.grad.cpu().numpy()
+    del p32
+    torch.cuda.empty_cache()
+    p64 = B.Problem(g, m, dict(ctl, precision=B.F64, residual_temp=1e-13, residual_flux=1e-12))
+    k64, e64 = _keff_solve(B, p64, gam0)
+    grad64, st = p64.adjoint(e64)
+    assert st["converged"], st
+    grad64 = grad64.cpu().numpy()
     solid = np.asarray(g["solid"]).astype(bool)
-    assert np.all(grad[~solid] == 0.0)
+    assert np.all(grad32[~solid] == 0.0) and np.all(grad64[~solid] == 0.0)
+    gmax = np.abs(grad64).max()
+    err = float(np.abs(grad32 - grad64).max() / gmax)
+    print("k_eff FP32", k32.item(), "FP64", k64, "grad FP32 vs FP64", err)
+    assert abs(k32.item() / k64 - 1) < 1e-5 and err < 1e-5, (k32.item(), k64, err)
     rng = np.random.default_rng(44)
-    for c in rng.choice(np.flatnonzero(solid), 4, replace=False):
+    worst = 0.0
+    for c in rng.choice(np.flatnonzero(solid), 20, replace=False):
         h = 1e-4 * max(gam0[c], 1e10)
         ks = []
         for sg in (1, -1):
             g2 = gam0.copy()
             g2[c] += sg * h
-            prob.set_fields(None, torch.as_tensor(g2, device="cuda"))
-            e = prob.zeros()
-            prob.steady_solve(e, init=True)
-            ks.append(prob.keff(e).item())
+            ks.append(_keff_solve(B, p64, g2, e64)[0])
         fd = (ks[0] - ks[1]) / (2 * h)
-        print("cell", c, "fd", fd, "adjoint", grad[c])
-        assert abs(fd - grad[c]) <= 1e-4 * np.abs(grad).max(), (c, fd, grad[c])
+        worst = max(worst, abs(fd - grad32[c]) / gmax, abs(fd - grad64[c]) / gmax)
+        print("cell", c, "fd", fd, "adjoint FP64", grad64[c], "FP32", grad32[c])
+    print("worst FD deviation / max |grad|", worst)
+    assert worst <= 1e-4, worst

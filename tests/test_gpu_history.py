@@ -1,0 +1,57 @@
+"""The laser-heating transient (Algorithm 2, Sec. 4.1) over its full 2000
+explicit steps, on a reduced 8^3 grid that keeps the cell size of the 64^3
+case (31.25 nm: the same Courant numbers and dt / tau_min) and every other
+part of its physics: 40 seeded bands, 4 x 4 directions per octant, MC
+limiter, diffuse top face, thermalizing other faces, the Gaussian pulse,
+dt = 0.5 ps.  The GPU runs the steps in chunks of 10 and reads the weighted
+mean top temperature after each chunk; the reference is the oracle's run
+stored by tests/golden/make_laser_history.py (pinned to the live oracle by
+tests/test_golden_history.py).
+
+Bars (relative to the largest temperature rise of the reference): history
+and final temperature field within 1e-11 in FP64 storage and 1e-5 in FP32
+storage (FP64 moments).
+"""
+import numpy as np
+import pytest
+
+from tests.golden import make_laser_history as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_14181_amd import bte
+    bte.load()
+    return bte
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_laser_history_2000_steps(B, prec):
+    hist_ref, T_ref = G.load()
+    cfg, _ = G.case()
+    p = B.F64 if prec == "f64" else B.F32
+    prob = B.Problem(cfg["geometry"], cfg["material"], dict(precision=p, limiter=B.LIM_MC, dt=cfg["dt"]))
+    prob.set_fields(torch.as_tensor(cfg["P"], device="cuda"), None)
+    w = torch.as_tensor(cfg["hist_weights"], device="cuda")
+    e = prob.zeros()
+    chunk = 10
+    hist = []
+    for k in range(G.N_STEPS // chunk):
+        prob.transient_step(e, chunk, k * chunk * cfg["dt"], cfg["pulse"])
+        T, _, _ = prob.moments(e)
+        hist.append(((w * T).sum() / w.sum()).item())
+    hist = np.array(hist)
+    ref = hist_ref[chunk - 1::chunk]
+    rise = np.abs(hist_ref - 300.0).max()
+    err_h = float(np.abs(hist - ref).max() / rise)
+    T = T.cpu().numpy()
+    err_T = float(np.abs(T - T_ref).max() / np.abs(T_ref - 300.0).max())
+    print(prec, "history err", err_h, "final T err", err_T, "peak rise", rise)
+    tol = 1e-11 if p == B.F64 else 1e-5
+    assert err_h < tol and err_T < tol, (err_h, err_T)

@@ -86,8 +86,9 @@ def test_residual(B, name, prec, lim):
     e = host(eg)
     R = host(prob.residual(eg))
     Ro = O.residual(case, e)
-    tol = 1e-11 if prec == 1 else 2e-5
-    assert rel_err(R, Ro) < tol
+    tol = 1e-11 if prec == 1 else 1e-5
+    err = rel_err(R, Ro)
+    assert err < tol, (name, lim, err)
 
 
 @pytest.mark.parametrize("lim", [O.LIM_NONE, O.LIM_MC])
@@ -132,13 +133,16 @@ def test_sweep_iterates_fp64(B, name, scheme):
     assert st["iters"] == 3
     eo, sto = O.steady(case, scheme=scheme, tol_T=0.0, tol_q=0.0, max_iter=3, cg_rtol=1e-13, cg_maxit=20000,
                        e=e.copy())
-    assert rel_err(host(eg), eo) < 1e-10
+    err = rel_err(host(eg), eo)
+    assert err < 1e-11, (name, scheme, err)
 
 
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("name", CASES)
 def test_steady_converged(B, name, prec):
-    tolT = 1e-12 if prec == 1 else 1e-7
+    # FP64: stop at 2e-13 (the FP64 floor of eps_T is ~5e-14), so that the
+    # iterate is within ~1e-11 of the fixed point also for slow contraction
+    tolT = 2e-13 if prec == 1 else 1e-7
     case, prob = build(B, name, prec, scheme=1, max_iter=4000, residual_temp=tolT, residual_flux=tolT * 10,
                        cg_rtol=1e-12)
     eg = prob.zeros()
@@ -147,10 +151,10 @@ def test_steady_converged(B, name, prec):
     eo, sto = O.steady(case, scheme=1, tol_T=1e-13, tol_q=1e-13, max_iter=20000, cg_rtol=1e-13)
     T, TL, q = prob.moments(eg)
     To, TLo, qo = O.moments(case, eo)
-    tol = 1e-10 if prec == 1 else 1e-5
-    assert rel_err(host(T), To, 300) < tol
-    assert rel_err(host(TL), TLo, 300) < tol
-    assert rel_err(host(q), qo) < (1e-9 if prec == 1 else 1e-4)
+    tol = 1e-11 if prec == 1 else 1e-5
+    errs = (rel_err(host(T), To, 300), rel_err(host(TL), TLo, 300), rel_err(host(q), qo))
+    print(name, prec, "steady T, T_L, q rel err", errs, "iters", st["iters"])
+    assert max(errs) < tol, (name, prec, errs)
 
 
 def test_slab_config_fp64(B):
@@ -166,5 +170,5 @@ def test_slab_config_fp64(B):
     eo, _ = O.steady(case, scheme=1, tol_T=1e-13, tol_q=1e-12, max_iter=20000, cg_rtol=1e-13)
     T, TL, q = prob.moments(eg)
     To, TLo, qo = O.moments(case, eo)
-    assert rel_err(host(T), To, 300) < 1e-11
-    assert rel_err(host(q), qo) < 1e-9
+    errs = (rel_err(host(T), To, 300), rel_err(host(q), qo))
+    assert max(errs) < 1e-11, errs

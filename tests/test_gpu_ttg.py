@@ -85,5 +85,5 @@ def test_ttg_against_mode_recurrence_and_continuous_solution(B, xi, prec):
         err = float(np.abs(dT - ref).max()) / cfg["amplitude"]
         amp = 2.0 * np.mean(dT * np.cos(2 * np.pi * x / 1e-6)) / cfg["amplitude"]
         print(prec, "xi", xi, "t*", ts, "steps", n, "mode err", err, "A/A0", amp, "continuous", ac)
-        assert err < (1e-10 if prec == "f64" else 2e-4), err
+        assert err < (1e-11 if prec == "f64" else 1e-5), err
         assert abs(amp - ac) < 1e-3, (amp, ac)
