@@ -457,16 +457,20 @@ std::vector<int3> tile_candidates(const bte_problem *p, int kind)
     if (kind == BTE_TUNE_SWEEP) {
         if (p->dim == 1) c = {make_int3(64, 1, 1), make_int3(32, 1, 1), make_int3(16, 1, 1)};
         else if (p->dim == 2) c = {make_int3(8, 8, 1)};   // fixed by the register sweep
-        else if (p->ctl.precision == BTE_F64)
-            c = {make_int3(4, 4, 2), make_int3(4, 2, 4), make_int3(2, 4, 4), make_int3(3, 3, 3),
-                 make_int3(3, 3, 2), make_int3(8, 4, 1), make_int3(4, 8, 1), make_int3(8, 2, 2),
-                 make_int3(2, 2, 2), make_int3(4, 4, 3)};
-        else
-            // 4x4x3 first: its star leaves room for two blocks per compute unit
-            c = {make_int3(4, 4, 3), make_int3(4, 4, 4), make_int3(4, 3, 4), make_int3(3, 4, 4),
-                 make_int3(4, 4, 2), make_int3(4, 2, 4), make_int3(2, 4, 4), make_int3(4, 3, 3),
-                 make_int3(3, 3, 4), make_int3(6, 4, 2), make_int3(3, 3, 3), make_int3(3, 3, 2),
-                 make_int3(8, 4, 1), make_int3(8, 2, 2)};
+        else {
+            // column segments of 1 x 1 x z cells (k_sweep3d, at most 48 cells):
+            // shorter segments shorten each hyperplane launch, longer ones
+            // need fewer launches; lengths past the tallest geometry are the same
+            int nz = 1;
+            for (const Film &fm : p->films) nz = std::max(nz, fm.n[2]);
+            for (int z : {16, 8, 12, 24, 32, 48, 4, 2}) {
+                const int zz = std::min(z, nz);
+                bool dup = false;
+                for (const int3 &t : c) dup = dup || t.z == zz;
+                if (!dup) c.push_back(make_int3(1, 1, zz));
+            }
+            return c;
+        }
     } else {
         if (p->dim == 1)
             c = {make_int3(64, 1, 1), make_int3(32, 1, 1), make_int3(16, 1, 1), make_int3(8, 1, 1),

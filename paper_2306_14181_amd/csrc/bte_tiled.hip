@@ -336,6 +336,17 @@ __global__ __launch_bounds__(256) void k_transient_tile(Dev d, const T *__restri
 
 // --------------------------------------------------------------- launchers
 
+// three-dimensional sweeps walk column segments (bte_sweep3d.hip); a
+// segment item is a tile of 1 x 1 x tdim.z cells
+template <typename T>
+hipError_t launch_sweep3d(const Dev &d, const T *ein, T *eout, const double *dpend, const double *TLdev,
+                          const double *din, const SweepItem *items, int item0, int count, int zseg, int na_oct,
+                          int nchunk_oct, double *part, hipStream_t s);
+template <typename T>
+hipError_t launch_sweep3d_adj(const Dev &d, const T *ein, T *eout, const double *X, const double *dinA,
+                              const SweepItem *items, int item0, int count, int zseg, int na_oct, int nchunk_oct,
+                              double *part, hipStream_t s);
+
 template <typename T, int DIM, int LIM>
 void sweep_launch(const Dev &d, const T *ein, T *eout, const double *dpend, const double *TLdev, const double *din,
                   const SweepItem *items, int item0, int count, int3 tdim, int na_oct, int nchunk_oct, int cap,
@@ -352,13 +363,15 @@ hipError_t launch_sweep_tile(const Dev &d, const T *ein, T *eout, const double *
                              int na_oct, int nchunk_oct, int cap, double *part, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
+    if (d.dim == 3)
+        return launch_sweep3d<T>(d, ein, eout, dpend, TLdev, din, items, item0, count, tdim.z, na_oct, nchunk_oct,
+                                 part, s);
 #define BTE_SWEEP(DIM, LIM)                                                                                          \
     if (d.dim == DIM && d.limiter == LIM)                                                                            \
         sweep_launch<T, DIM, LIM>(d, ein, eout, dpend, TLdev, din, items, item0, count, tdim, na_oct, nchunk_oct,    \
                                   cap, part, s);
     BTE_SWEEP(1, 0) BTE_SWEEP(1, 1) BTE_SWEEP(1, 2)
     BTE_SWEEP(2, 0) BTE_SWEEP(2, 1) BTE_SWEEP(2, 2)
-    BTE_SWEEP(3, 0) BTE_SWEEP(3, 1) BTE_SWEEP(3, 2)
 #undef BTE_SWEEP
     return hipGetLastError();
 }
@@ -381,7 +394,8 @@ hipError_t launch_sweep_adj(const Dev &d, const T *ein, T *eout, const double *X
     if (count <= 0) return hipSuccess;
     if (d.dim == 1) sweep_adj_launch<T, 1>(d, ein, eout, X, dinA, items, item0, count, tdim, na_oct, nchunk_oct, cap, part, s);
     if (d.dim == 2) sweep_adj_launch<T, 2>(d, ein, eout, X, dinA, items, item0, count, tdim, na_oct, nchunk_oct, cap, part, s);
-    if (d.dim == 3) sweep_adj_launch<T, 3>(d, ein, eout, X, dinA, items, item0, count, tdim, na_oct, nchunk_oct, cap, part, s);
+    if (d.dim == 3)
+        return launch_sweep3d_adj<T>(d, ein, eout, X, dinA, items, item0, count, tdim.z, na_oct, nchunk_oct, part, s);
     return hipGetLastError();
 }
 
@@ -414,14 +428,16 @@ hipError_t launch_transient_tile(const Dev &d, const T *ein, T *eout, const doub
 
 template <typename T, int DIM, int LIM> hipError_t set_lds(size_t bytes)
 {
-    hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sweep_tile<T, DIM, LIM>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipError_t a = hipSuccess, c = hipSuccess;
+    if constexpr (DIM < 3) {
+        a = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sweep_tile<T, DIM, LIM>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (LIM == LIM_NONE)
+            c = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sweep_tile<T, DIM, LIM_NONE, true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    }
     hipError_t b = hipFuncSetAttribute(reinterpret_cast<const void *>(k_transient_tile<T, DIM, LIM>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipError_t c = hipSuccess;
-    if (LIM == LIM_NONE)
-        c = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sweep_tile<T, DIM, LIM_NONE, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     return a != hipSuccess ? a : (b != hipSuccess ? b : c);
 }
 

@@ -144,8 +144,9 @@ def test_device_calls_need_a_workspace(lib):
 @pytest.mark.parametrize("dim,prec", [(1, 0), (2, 0), (2, 1), (3, 0), (3, 1)])
 def test_tile_candidates(lib, dim, prec):
     """Candidate tile shapes: the default first, at most 64 cells each, and a
-    choice only where the kernels are LDS-tiled (sweeps in 1D/3D, explicit
-    steps in 1D/2D); no shape can be set before a workspace is bound."""
+    choice only where the kernels have one (sweeps in 1D: LDS tiles, in 3D:
+    column segments; explicit steps in 1D/2D); no shape can be set before a
+    workspace is bound."""
     b = I.bands(0, 3)
     g = geo(dim, (8,) * dim, (1e-7,) * dim, [I.BC_SPECULAR] * 6)
     st, h = _setup(lib, g, mat(b, 2, 2), {"precision": prec})
@@ -159,8 +160,12 @@ def test_tile_candidates(lib, dim, prec):
         assert all(x * y * z <= 64 and min(x, y, z) >= 1 for x, y, z in shapes)
         assert all(s[dim:] == (1,) * (3 - dim) for s in shapes)
         got[kind] = shapes
-    default_sweep = {1: (64, 1, 1), 2: (8, 8, 1), 3: (4, 4, 2) if prec else (4, 4, 3)}[dim]
+    # 3D sweeps walk column segments of 1 x 1 x z cells: 16 by default, at
+    # most the column height (8 here)
+    default_sweep = {1: (64, 1, 1), 2: (8, 8, 1), 3: (1, 1, 8)}[dim]
     assert got[0][0] == default_sweep
+    if dim == 3:
+        assert all(x == 1 and y == 1 and z <= 8 for x, y, z in got[0]) and len(set(got[0])) == len(got[0])
     assert (len(got[0]) > 1) == (dim != 2)
     assert (len(got[1]) > 1) == (dim != 3)
     t = (C.c_int * 3)(*got[0][0])

@@ -163,33 +163,23 @@ def _keff_solve(B, prob, gamma, e_start=None):
 def test_full_size_adjoint_against_central_differences(B):
     """d k_eff / d gamma of the 48^3 porous cube: the FP32 forward solve and
     adjoint behind KeffSteady against the FP64 adjoint (every cell, 1e-5 of
-    max |grad|), and both against central differences of the FP64 k_eff on
-    20 random solid cells (h = 1e-4 gamma_c, at least 1e6 1/s).  A single
-    cell moves k_eff by ~1e-9 of itself, so the difference quotient of two
-    FP64 solves converged to eps_T 1e-13 resolves the derivative to ~1e-5
-    of max |grad|; the FD bar is 1e-4 of max |grad|."""
+    max |grad|), and the FP64 adjoint against central differences of the
+    FP64 k_eff on 20 random solid cells (h = 1e-4 gamma_c, at least 1e6 1/s).
+    A single cell moves k_eff by ~1e-9 of itself, so the difference quotient
+    of two FP64 solves converged to eps_T 1e-13 resolves the derivative to
+    ~1e-5 of max |grad|; the FD bar is 1e-4 of max |grad|."""
     cfg = I.porous3d_adjoint_case()
     g, m, gam0 = cfg["geometry"], cfg["material"], cfg["gamma"]
     ctl = dict(scheme=B.SYNTHETIC, limiter=B.LIM_NONE, adjoint=True, max_iter=5000, cg_rtol=1e-12,
                cg_max_iter=2000)
-    p32 = B.Problem(g, m, dict(ctl, precision=B.F32, residual_temp=1e-7, residual_flux=1e-6))
-    gamma = torch.as_tensor(gam0, device="cuda").requires_grad_(True)
-    k32 = B.KeffSteady.apply(gamma, p32, None)
-    k32.sum().backward()
-    grad32 = gamma.grad.cpu().numpy()
-    del p32
-    torch.cuda.empty_cache()
+    solid = np.asarray(g["solid"]).astype(bool)
     p64 = B.Problem(g, m, dict(ctl, precision=B.F64, residual_temp=1e-13, residual_flux=1e-12))
     k64, e64 = _keff_solve(B, p64, gam0)
     grad64, st = p64.adjoint(e64)
     assert st["converged"], st
     grad64 = grad64.cpu().numpy()
-    solid = np.asarray(g["solid"]).astype(bool)
-    assert np.all(grad32[~solid] == 0.0) and np.all(grad64[~solid] == 0.0)
     gmax = np.abs(grad64).max()
-    err = float(np.abs(grad32 - grad64).max() / gmax)
-    print("k_eff FP32", k32.item(), "FP64", k64, "grad FP32 vs FP64", err)
-    assert abs(k32.item() / k64 - 1) < 1e-5 and err < 1e-5, (k32.item(), k64, err)
+    assert np.all(grad64[~solid] == 0.0)
     rng = np.random.default_rng(44)
     worst = 0.0
     for c in rng.choice(np.flatnonzero(solid), 20, replace=False):
@@ -200,7 +190,21 @@ def test_full_size_adjoint_against_central_differences(B):
             g2[c] += sg * h
             ks.append(_keff_solve(B, p64, g2, e64)[0])
         fd = (ks[0] - ks[1]) / (2 * h)
-        worst = max(worst, abs(fd - grad32[c]) / gmax, abs(fd - grad64[c]) / gmax)
-        print("cell", c, "fd", fd, "adjoint FP64", grad64[c], "FP32", grad32[c])
+        worst = max(worst, abs(fd - grad64[c]) / gmax)
+        print("cell", c, "fd", fd, "adjoint FP64", grad64[c])
     print("worst FD deviation / max |grad|", worst)
     assert worst <= 1e-4, worst
+    del p64, e64
+    torch.cuda.empty_cache()
+    # FP32 forward (to its floor, eps_T 1e-7) and FP32 adjoint (to 2e-6: the
+    # FP32 evaluation of |J^T psi + g| / |g| stalls near 1e-6) behind autograd
+    p32 = B.Problem(g, m, dict(ctl, precision=B.F32, residual_temp=1e-7, residual_flux=1e-6))
+    gamma = torch.as_tensor(gam0, device="cuda").requires_grad_(True)
+    k32 = B.KeffSteady.apply(gamma, p32, None)
+    p32.set_control(residual_temp=2e-6)
+    k32.sum().backward()
+    grad32 = gamma.grad.cpu().numpy()
+    assert np.all(grad32[~solid] == 0.0)
+    err = float(np.abs(grad32 - grad64).max() / gmax)
+    print("k_eff FP32", k32.item(), "FP64", k64, "grad FP32 vs FP64", err)
+    assert abs(k32.item() / k64 - 1) < 1e-5 and err < 1e-5, (k32.item(), k64, err)
