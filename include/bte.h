@@ -180,6 +180,22 @@ bte_status bte_set_fields(bte_problem *p, const double *P_dev, const double *gam
 bte_status bte_moments(bte_problem *p, const void *e_dev, double *T_dev, double *TL_dev,
                        double *q_dev, void *stream);
 
+/* No-allocation moments, for callers that cannot allocate device memory or
+ * grow a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, outputs and
+ * asynchrony as bte_moments; the FP64 moment partials (5 doubles per cell)
+ * live in a static device array of BTE_STATIC_MAX_CELLS * 40 bytes (32 MiB)
+ * that the library holds on every GPU it runs on until the process ends,
+ * and the call allocates nothing.  Errors: BTE_ERR_ARG if the problem has
+ * more than BTE_STATIC_MAX_CELLS cells (nothing written), BTE_ERR_STATE
+ * without a bound workspace (the problem's tables live there).  Every call
+ * on a GPU shares that GPU's array, which keeps the last call's contents;
+ * every partial a call reads it writes first, so nothing needs clearing, but
+ * calls that overlap on one GPU (other streams or host threads) race. */
+#define BTE_STATIC_MAX_CELLS 838860
+bte_status bte_moments_static(bte_problem *p, const void *e_dev, double *T_dev, double *TL_dev,
+                              double *q_dev, void *stream);
+
 /* Steady residual R(e) = -(1/V) sum_f e_f v s.n S - (e - C T_L/4pi)/tau + Q
  * (right-hand side of eq. B_BTE with T_L from e), same layout/precision
  * as e.  Asynchronous. */

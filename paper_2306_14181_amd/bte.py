@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "E
                 5: "ERR_NONFINITE", 6: "ERR_CFL", 7: "ERR_STATE"}
 
 EXPORTS = ["bte_setup", "bte_set_control", "bte_workspace_bytes", "bte_num_unknowns", "bte_num_cells", "bte_num_directions",
-           "bte_bind", "bte_set_fields", "bte_moments", "bte_residual", "bte_transient_step",
+           "bte_bind", "bte_set_fields", "bte_moments", "bte_moments_static", "bte_residual", "bte_transient_step",
            "bte_steady_solve", "bte_keff", "bte_adjoint", "bte_transient_adjoint", "bte_transient_adjoint_bytes",
            "bte_set_timing", "bte_set_graphs", "bte_set_persistent", "bte_tile_candidates", "bte_set_tiles",
            "bte_autotune", "bte_last_stats",
@@ -95,6 +95,7 @@ def load():
         "bte_bind": ([vp, vp, C.c_size_t], st),
         "bte_set_fields": ([vp, vp, vp, vp], st),
         "bte_moments": ([vp, vp, vp, vp, vp, vp], st),
+        "bte_moments_static": ([vp, vp, vp, vp, vp, vp], st),
         "bte_residual": ([vp, vp, vp, vp], st),
         "bte_transient_step": ([vp, vp, C.c_int, C.c_double, dp, vp], st),
         "bte_steady_solve": ([vp, vp, C.c_int, C.POINTER(SolveStats), vp], st),
@@ -302,6 +303,15 @@ class Problem:
         TL = torch.empty_like(T)
         q = torch.empty(self.n_cells * 3, dtype=torch.float64, device=self.device)
         self._check(load().bte_moments(self._h, self._e(e), _ptr(T), _ptr(TL), _ptr(q), _stream()))
+        return T, TL, q.view(-1, 3)
+
+    def moments_static(self, e):
+        """moments() through bte_moments_static: the library's static device
+        scratch instead of the workspace (allocates nothing in the library)."""
+        T = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)
+        TL = torch.empty_like(T)
+        q = torch.empty(self.n_cells * 3, dtype=torch.float64, device=self.device)
+        self._check(load().bte_moments_static(self._h, self._e(e), _ptr(T), _ptr(TL), _ptr(q), _stream()))
         return T, TL, q.view(-1, 3)
 
     def residual(self, e):

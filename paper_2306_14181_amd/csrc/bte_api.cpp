@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1548,6 +1549,67 @@ bte_status bte_moments(bte_problem *p, const void *e_dev, double *T_dev, double 
     if (p->ctl.precision == BTE_F64) launch_moments<double>(p->dev, (const double *)e_dev, nullptr, p->part, s);
     else launch_moments<float>(p->dev, (const float *)e_dev, nullptr, p->part, s);
     launch_finalize(p->dev, p->part, 1, p->Tref, T_dev, TL_dev, q_dev, nullptr, nullptr, nullptr, s);
+    HIPCHK(p, hipGetLastError());
+    return BTE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Scratch of bte_moments_static: the FP64 moment partials (kMomN per cell)
+// in a static device array, one copy on every GPU the library runs on, held
+// until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is a stand-in, not a device address): the address
+// is looked up once per device with hipGetSymbolAddress and kept.
+constexpr size_t kStaticScratchBytes = (size_t)BTE_STATIC_MAX_CELLS * kMomN * sizeof(double);
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up on the first
+// call on each device), or null with the HIP error in *err
+double *static_scratch(hipError_t *err)
+{
+    int dev = 0;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+bte_status bte_moments_static(bte_problem *p, const void *e_dev, double *T_dev, double *TL_dev, double *q_dev,
+                              void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
+    if (!e_dev) FAIL(p, BTE_ERR_ARG, "e is null");
+    if (p->nc > BTE_STATIC_MAX_CELLS)
+        FAIL(p, BTE_ERR_ARG, "%d cells exceed the static scratch of bte_moments_static (%d cells)", p->nc,
+             BTE_STATIC_MAX_CELLS);
+    hipError_t herr = hipSuccess;
+    double *part = static_scratch(&herr);
+    if (!part) FAIL(p, BTE_ERR_HIP, "static scratch: %s", hipGetErrorString(herr));
+    hipStream_t s = (hipStream_t)stream;
+    // every partial the finalize kernel reads is written first: nothing has
+    // to be cleared
+    if (p->ctl.precision == BTE_F64) launch_moments<double>(p->dev, (const double *)e_dev, nullptr, part, s);
+    else launch_moments<float>(p->dev, (const float *)e_dev, nullptr, part, s);
+    launch_finalize(p->dev, part, 1, p->Tref, T_dev, TL_dev, q_dev, nullptr, nullptr, nullptr, s);
     HIPCHK(p, hipGetLastError());
     return BTE_OK;
 }
