@@ -49,6 +49,8 @@ KERNEL_SOURCES = {
                            "bte_api.cpp"),
     "k_transient3d<float,1>": ("bte_transient3d.hip", "bte_tilelds.h", "bte_tile.h", "bte_stencil.h",
                                "bte_internal.h", "bte_api.cpp"),
+    "k_sweep3d<float,0>": ("bte_sweep3d.hip", "bte_col3d.h", "bte_tilelds.h", "bte_tile.h", "bte_stencil.h",
+                           "bte_internal.h", "bte_api.cpp"),
 }
 BYTES_PER_UPDATE = {0: 8.0, 1: 16.0}   # read e^n + write e^{n+1}
 
@@ -67,6 +69,29 @@ def run_steps(B, prob, e, steps, init):
     return time.perf_counter() - t0, st
 
 
+def host_cpu():
+    """CPU model, sockets, physical cores and hardware threads of the host
+    (lscpu), and the OpenMP threads the oracle runs with."""
+    info = {}
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        kv = {}
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        sockets = int(kv.get("Socket(s)", "0") or 0)
+        cps = int(kv.get("Core(s) per socket", "0") or 0)
+        info = dict(model=kv.get("Model name"), sockets=sockets, physical_cores=sockets * cps,
+                    hardware_threads=int(kv.get("CPU(s)", "0") or 0))
+    except Exception as ex:   # lscpu missing: report what Python knows
+        info = dict(model=None, error=str(ex))
+    info["affinity_cpus"] = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    info["omp_threads"] = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return info
+
+
 def cpu_baseline(cfg, seconds_hint=30.0):
     """Oracle (FP64 C, OpenMP) on a bounded sample: three source iterations of
     the same workload (sweep, moments, synthetic correction), started from the
@@ -83,7 +108,7 @@ def cpu_baseline(cfg, seconds_hint=30.0):
     dt = time.perf_counter() - t0
     updates = case.nc * case.na * case.nl * iters
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=updates / dt, unit="cell*dir*band updates/s", cores=threads, kind="oracle",
+    return dict(value=updates / dt, unit="cell*dir*band updates/s", cores=threads, kind="oracle", host=host_cpu(),
                 sample="%d source iterations (sweep + FP64 moments + CG correction) of the 256x256 x 128 dir x "
                        "20 band workload, %.1f s" % (iters, dt))
 
@@ -208,7 +233,7 @@ def cpu_baseline_transient():
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=case.nc * case.na * case.nl * steps / dt, unit="cell*dir*band updates/s", cores=threads,
-                kind="oracle", sample="%d explicit steps of the laser workload on a 32^3 grid, %.1f s" % (steps, dt))
+                kind="oracle", host=host_cpu(), sample="%d explicit steps of the laser workload on a 32^3 grid, %.1f s" % (steps, dt))
 
 
 def bench_ttg(args):
@@ -285,6 +310,7 @@ def bench_ttg(args):
         dt = time.perf_counter() - t0
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = dict(value=case.nc * case.na * n / dt, unit="cell*dir*band updates/s", cores=threads,
+                                   host=host_cpu(),
                                    kind="oracle", sample="%d explicit steps of the xi = 1 grating, %.1f s" % (n, dt))
     print(json.dumps(out), flush=True)
 
@@ -364,6 +390,14 @@ def bench_adjoint(args):
     ta = time.perf_counter() - t0
     gr = grad.cpu().numpy()
     upd = prob.n_unknowns
+    # roofline of the transport sweeps: algorithmic bytes (read e^n + write
+    # e^{n+1} of every solid cell, direction and band) over the device time
+    # of one sweep (HIP events around the hyperplane launches on the stream)
+    solid = int(np.asarray(g["solid"]).astype(bool).sum())
+    sweep_bytes = BYTES_PER_UPDATE[B.F32] * solid * prob.n_dirs * prob.n_bands
+    fwd_ms = st["ms_sweep"] / max(st["iters"], 1)
+    adj_ms = sa["ms_sweep"] / max(sa["iters"], 1)
+    roof = lambda ms: sweep_bytes / (ms * 1e-3) / 1e9
     log("adjoint3d: forward %d its %.2f s, adjoint %d sweeps %.2f s (residual %.1e)"
         % (st["iters"], tf, sa["iters"], ta, sa["eps_T"]))
     out = {"metric": "forward and adjoint steady solves of the porous cube (FP32 state)",
@@ -377,6 +411,14 @@ def bench_adjoint(args):
            "adjoint": {"sweeps": sa["iters"], "converged": sa["converged"], "relative_residual": sa["eps_T"],
                        "solve_s": ta, "ms_sweep_per_iteration": sa["ms_sweep"] / max(sa["iters"], 1)},
            "adjoint_over_forward_time": ta / tf,
+           "roofline": {"bound": "hbm", "kernel": "k_sweep3d<float,NONE> (the hyperplane launches of one sweep)",
+                        "achieved": roof(fwd_ms), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": roof(fwd_ms) / HBM_PEAK_GBS, "traffic": counter_traffic("k_sweep3d<float,0>"),
+                        "avg_sweep_ms": fwd_ms, "launches_per_sweep": st["sweep_launches"] / max(st["iters"], 1),
+                        "bytes_per_sweep": sweep_bytes, "solid_cells": solid},
+           "adjoint_roofline": {"kernel": "k_sweep3d<float,NONE,ADJ> (transposed sweep)", "achieved": roof(adj_ms),
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": roof(adj_ms) / HBM_PEAK_GBS,
+                                "avg_sweep_ms": adj_ms},
            "autotune": [{"tile": list(x["tile"]), "ms_per_sweep": x["ms"], "chosen": x["chosen"]} for x in tune],
            "grad": {"min": float(gr.min()), "max": float(gr.max()), "sum": float(gr.sum())}}
     print(json.dumps(out), flush=True)
