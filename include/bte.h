@@ -351,6 +351,31 @@ bte_status bte_band_discretize(const double *C, const double *v, const double *t
                                int n_bands, double *C_out, double *v_out, double *tau_out, int *n_out,
                                int *band_of_mode);
 
+/* Mean-free-path band discretisation on the device (Sec. 3.1, eq. banddis):
+ * the computation of bte_band_discretize with the mode list and the results
+ * in device memory, for mode lists produced or kept on the GPU.
+ * C, v, tau: device double[n_modes] (1 <= n_modes <= 2^31 - 1);
+ * C_out, v_out, tau_out: device double[n_bands]; band_of_mode: device
+ * int[n_modes], required (it holds each mode's interval during the call and
+ * each mode's band index, or -1, at the end); scratch: device memory of at
+ * least bte_band_discretize_scratch_bytes(n_bands) bytes, 256-byte aligned,
+ * owned by the caller.  *n_out (host) receives the number of bands.  The
+ * intervals and band values are those of bte_band_discretize (the interval
+ * of a mode from the FP64 logarithm of its mean free path; band sums over
+ * the modes of an interval in a fixed order, so repeated calls give
+ * identical bits; the order differs from the host routine's, so values agree
+ * to rounding).  The list is validated on the device first: BTE_ERR_ARG for a
+ * null pointer, n_modes or n_bands out of range, a small or misaligned
+ * scratch, a negative C or v, a non-positive tau or no mode with v tau > 0,
+ * with nothing written to C_out, v_out, tau_out or band_of_mode.
+ * Synchronous on `stream` (two small device-to-host reads). */
+bte_status bte_band_discretize_dev(const double *C, const double *v, const double *tau, long long n_modes,
+                                   int n_bands, double *C_out, double *v_out, double *tau_out, int *n_out,
+                                   int *band_of_mode, void *scratch, size_t scratch_bytes, void *stream);
+
+/* Bytes of the scratch of bte_band_discretize_dev (0 if n_bands < 1). */
+size_t bte_band_discretize_scratch_bytes(int n_bands);
+
 /* Host copy of the direction table: s[n_dir][3], w[n_dir]. */
 bte_status bte_get_directions(const bte_problem *p, double *s_host, double *w_host);
 

@@ -31,7 +31,8 @@ EXPORTS = ["bte_setup", "bte_set_control", "bte_workspace_bytes", "bte_num_unkno
            "bte_steady_solve", "bte_keff", "bte_adjoint", "bte_transient_adjoint", "bte_transient_adjoint_bytes",
            "bte_set_timing", "bte_set_graphs", "bte_set_persistent", "bte_tile_candidates", "bte_set_tiles",
            "bte_autotune", "bte_last_stats",
-           "bte_get_directions", "bte_band_discretize", "bte_last_error", "bte_destroy"]
+           "bte_get_directions", "bte_band_discretize", "bte_band_discretize_dev",
+           "bte_band_discretize_scratch_bytes", "bte_last_error", "bte_destroy"]
 
 
 class BteError(RuntimeError):
@@ -114,6 +115,9 @@ def load():
         "bte_get_directions": ([vp, dp, dp], st),
         "bte_band_discretize": ([dp, dp, dp, C.c_longlong, C.c_int, dp, dp, dp, C.POINTER(C.c_int),
                                  C.POINTER(C.c_int)], st),
+        "bte_band_discretize_dev": ([vp, vp, vp, C.c_longlong, C.c_int, vp, vp, vp, C.POINTER(C.c_int), vp, vp,
+                                     C.c_size_t, vp], st),
+        "bte_band_discretize_scratch_bytes": ([C.c_int], C.c_size_t),
         "bte_last_error": ([vp], C.c_char_p),
         "bte_destroy": ([vp], None),
     }
@@ -144,6 +148,33 @@ def band_discretize(C_mode, v_mode, tau_mode, n_bands):
         raise BteError(st, "bte_band_discretize: invalid mode list or band count")
     k = nout.value
     return dict(C=outs[0][:k].copy(), v=outs[1][:k].copy(), tau=outs[2][:k].copy()), band[:n].copy()
+
+
+def band_discretize_dev(C_mode, v_mode, tau_mode, n_bands):
+    """band_discretize with the mode list on the device (float64 cuda tensors;
+    bte_band_discretize_dev).  Returns ({"C", "v", "tau"} float64 cuda tensors of
+    the non-empty bands, band index of every mode as an int32 cuda tensor)."""
+    lib = load()
+    mode = [t.detach().to(torch.float64).contiguous() for t in (C_mode, v_mode, tau_mode)]
+    n = mode[0].numel()
+    if any(t.numel() != n or t.device.type != "cuda" for t in mode):
+        raise ValueError("C, v, tau must be cuda tensors of the same length")
+    dev = mode[0].device
+    nb_cap = max(int(n_bands), 1)
+    outs = [torch.zeros(nb_cap, dtype=torch.float64, device=dev) for _ in range(3)]
+    band = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    nbytes = lib.bte_band_discretize_scratch_bytes(int(n_bands))
+    scratch = torch.empty(max(nbytes, 1) + 256, dtype=torch.uint8, device=dev)
+    base = (scratch.data_ptr() + 255) & ~255
+    nout = C.c_int(0)
+    st = lib.bte_band_discretize_dev(*[C.c_void_p(t.data_ptr()) for t in mode], n, int(n_bands),
+                                     *[C.c_void_p(t.data_ptr()) for t in outs], C.byref(nout),
+                                     C.c_void_p(band.data_ptr()), C.c_void_p(base), C.c_size_t(nbytes),
+                                     C.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+    if st != 0:
+        raise BteError(st, "bte_band_discretize_dev: invalid mode list, band count or scratch")
+    k = nout.value
+    return dict(C=outs[0][:k], v=outs[1][:k], tau=outs[2][:k]), band[:n]
 
 
 def _ptr(t):
