@@ -452,6 +452,18 @@ int tile_cap_of(const bte_problem *p, int3 td)
 // tables), a star within the 160 KiB of LDS of a compute unit and, for the
 // sweep, at most 48 cells in the first upwind halo layers of all axes (the
 // LDS buffer of upwind increments has 48 rows).
+// A 3D sweep segment addresses its rows by 32-bit byte offsets from the
+// lowest row of the segment's planes: (zseg + 1) planes of every geometry
+// must span less than 4 GiB, and one plane less than 2 GiB.
+bool seg_fits(const bte_problem *p, int zseg)
+{
+    for (const Film &fm : p->films) {
+        const double plane = (double)fm.n[0] * fm.n[1] * p->nk * (double)p->esize();
+        if (plane >= 2147483648.0 || (zseg + 1) * plane >= 4294967296.0) return false;
+    }
+    return true;
+}
+
 std::vector<int3> tile_candidates(const bte_problem *p, int kind)
 {
     std::vector<int3> c;
@@ -464,12 +476,13 @@ std::vector<int3> tile_candidates(const bte_problem *p, int kind)
             // need fewer launches; lengths past the tallest geometry are the same
             int nz = 1;
             for (const Film &fm : p->films) nz = std::max(nz, fm.n[2]);
-            for (int z : {16, 8, 12, 24, 32, 48, 4, 2}) {
+            for (int z : {16, 8, 12, 24, 32, 48, 4, 2, 1}) {
                 const int zz = std::min(z, nz);
                 bool dup = false;
                 for (const int3 &t : c) dup = dup || t.z == zz;
-                if (!dup) c.push_back(make_int3(1, 1, zz));
+                if (!dup && seg_fits(p, zz) && (zz > 1 || c.empty())) c.push_back(make_int3(1, 1, zz));
             }
+            if (c.empty()) c.push_back(make_int3(1, 1, 1));   // too large: refused by the solves
             return c;
         }
     } else {
@@ -1051,6 +1064,8 @@ template <typename F> hipError_t graph_run(Graph &gr, hipStream_t cs, hipStream_
 template <typename T>
 bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, hipStream_t s)
 {
+    if (p->dim == 3 && !seg_fits(p, p->tdim.z))
+        FAIL(p, BTE_ERR_UNSUPPORTED, "a z plane of a geometry is too large for the 3D sweep's 32-bit row offsets");
     auto t0 = std::chrono::steady_clock::now();
     const Dev &d = p->dev;
     const int nc = p->nc;
@@ -1311,6 +1326,8 @@ bte_status transient_impl(bte_problem *p, T *e, int n_steps, double t0, const do
 template <typename T>
 bte_status adjoint_impl(bte_problem *p, const T *e, double *grad, bte_solve_stats *stats, hipStream_t s)
 {
+    if (p->dim == 3 && !seg_fits(p, p->tdim.z))
+        FAIL(p, BTE_ERR_UNSUPPORTED, "a z plane of a geometry is too large for the 3D sweep's 32-bit row offsets");
     auto t0 = std::chrono::steady_clock::now();
     const Dev &d = p->dev;
     const int nc = p->nc;

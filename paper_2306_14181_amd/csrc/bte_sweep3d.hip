@@ -202,17 +202,25 @@ __global__ __launch_bounds__(256) void k_sweep3d(Dev d, const T *__restrict__ ei
     auto rlu = [&](uint32_t v, int q) -> uint32_t { return (uint32_t)__builtin_amdgcn_readlane((int)v, q); };
 
     // ---- stencil rows.  The x / y neighbour rows (and the new values of the
-    // x- and y-upwind cells) are walked by running pointers from the first
-    // cell of the segment, one plane per cell; an absent neighbour reads the
-    // zero row with a zero step.
-    const long long zstep = (long long)(sg2 > 0 ? plane : -plane) * nk;
+    // x- and y-upwind cells) are addressed from one base per buffer (the
+    // lowest of the rows involved, at the segment's lowest plane) by 32-bit
+    // byte offsets that move one plane per cell; an absent neighbour points
+    // at the column's own row (its value is never used: the mode bits say it
+    // is absent), so every offset moves by the same step.
+    const int own = cb;
+    auto pick = [&](int b) { return b >= 0 ? b : own; };
+    const int cx1 = pick(bx1), cx2 = pick(bx2), cxd = pick(bxd), cy1 = pick(by1), cy2 = pick(by2), cyd = pick(byd);
+    const int cmin = min(min(min(cx1, cx2), min(cxd, cy1)), min(min(cy2, cyd), own));
+    const size_t rowb = (size_t)nk * sizeof(T);
+    const size_t basecell = (size_t)cmin + (size_t)plane * gz0;
+    const char *eb = reinterpret_cast<const char *>(ein) + basecell * rowb;
+    const char *ob = reinterpret_cast<const char *>(eout) + basecell * rowb;
     const int zgb = sg2 > 0 ? fb : n2 - 1 - fb;
-    auto row0 = [&](const T *base, int b) -> const T * { return b >= 0 ? base + (size_t)(b + plane * zgb) * nk : zrow; };
-    const T *rx1 = row0(ein, bx1), *rx2 = row0(ein, bx2), *rxd = row0(ein, bxd);
-    const T *ry1 = row0(ein, by1), *ry2 = row0(ein, by2), *ryd = row0(ein, byd);
-    const T *ox1 = row0(eout, bx1), *oy1 = row0(eout, by1);
-    const long long sx1 = bx1 >= 0 ? zstep : 0, sx2 = bx2 >= 0 ? zstep : 0, sxd = bxd >= 0 ? zstep : 0;
-    const long long sy1 = by1 >= 0 ? zstep : 0, sy2 = by2 >= 0 ? zstep : 0, syd = byd >= 0 ? zstep : 0;
+    const unsigned zb0 = (unsigned)((size_t)(zgb - gz0) * plane * rowb);
+    const int zstepb = (sg2 > 0 ? 1 : -1) * (int)((size_t)plane * rowb);
+    auto off0 = [&](int c) -> unsigned { return (unsigned)((size_t)(c - cmin) * rowb) + zb0 + koff; };
+    unsigned vx1 = off0(cx1), vx2 = off0(cx2), vxd = off0(cxd), vy1 = off0(cy1), vy2 = off0(cy2), vyd = off0(cyd);
+    auto atb = [&](const char *b, unsigned o) -> T { return *reinterpret_cast<const T *>(b + o); };
     auto zraw = [&](int f) -> T {
         int jz;
         const int c = zcell(f, jz);
@@ -231,24 +239,22 @@ __global__ __launch_bounds__(256) void k_sweep3d(Dev d, const T *__restrict__ ei
     // cells) and the raw column value at fn + 1; the running pointers stop
     // at the segment's last cell
     auto prefetch = [&](int fn, Pre &q) {
-        q.x1 = at(rx1);
-        q.x2 = at(rx2);
-        q.xd = at(rxd);
-        q.y1 = at(ry1);
-        q.y2 = at(ry2);
-        q.yd = at(ryd);
-        q.ux = at(ox1);
-        q.uy = at(oy1);
+        q.x1 = atb(eb, vx1);
+        q.x2 = atb(eb, vx2);
+        q.xd = atb(eb, vxd);
+        q.y1 = atb(eb, vy1);
+        q.y2 = atb(eb, vy2);
+        q.yd = atb(eb, vyd);
+        q.ux = atb(ob, vx1);
+        q.uy = atb(ob, vy1);
         q.nz = zraw(fn + 1);
         if (fn + 1 < fe) {
-            rx1 += sx1;
-            rx2 += sx2;
-            rxd += sxd;
-            ry1 += sy1;
-            ry2 += sy2;
-            ryd += syd;
-            ox1 += sx1;
-            oy1 += sy1;
+            vx1 += zstepb;
+            vx2 += zstepb;
+            vxd += zstepb;
+            vy1 += zstepb;
+            vy2 += zstepb;
+            vyd += zstepb;
         }
     };
 
@@ -438,6 +444,10 @@ __global__ __launch_bounds__(256) void k_sweep3d(Dev d, const T *__restrict__ ei
 
 // --------------------------------------------------------------- launchers
 
+// Segment lengths the kernel takes (the host also keeps (zseg + 1) planes
+// of rows of every geometry below 4 GiB: the row offsets are 32-bit).
+static bool sweep3d_fits(const Dev &, int zseg, size_t) { return zseg >= 1 && zseg <= 48; }
+
 template <typename T, int LIM, bool ADJ, bool ADD>
 void sweep3d_launch(const Dev &d, const T *ein, T *eout, const double *dpend, const double *TLdev, const double *din,
                     const SweepItem *items, int item0, int count, int zseg, int na_oct, int nchunk_oct, double *part,
@@ -455,7 +465,7 @@ hipError_t launch_sweep3d(const Dev &d, const T *ein, T *eout, const double *dpe
                           int nchunk_oct, double *part, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    if (zseg < 1 || zseg > 48) return hipErrorInvalidValue;
+    if (!sweep3d_fits(d, zseg, sizeof(T))) return hipErrorInvalidValue;
     const bool add = dpend != nullptr || d.jumps;
 #define BTE_S3(LIM)                                                                                                  \
     if (d.limiter == LIM) {                                                                                          \
@@ -478,7 +488,7 @@ hipError_t launch_sweep3d_adj(const Dev &d, const T *ein, T *eout, const double 
                               double *part, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    if (zseg < 1 || zseg > 48) return hipErrorInvalidValue;
+    if (!sweep3d_fits(d, zseg, sizeof(T))) return hipErrorInvalidValue;
     sweep3d_launch<T, LIM_NONE, true, false>(d, ein, eout, nullptr, X, dinA, items, item0, count, zseg, na_oct,
                                              nchunk_oct, part, s);
     return hipGetLastError();
