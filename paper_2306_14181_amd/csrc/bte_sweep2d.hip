@@ -2,16 +2,18 @@
 // geometries (the steady transport sweep of Sec. 3.3-3.5, Algorithm 1, in
 // delta form with the first-order upwind implicit operator).
 //
-// One wavefront per work item (tile of TX x TY cells, octant, chunk of 64
-// (direction, band) lanes).  The tile is walked row by row in the flow
-// frame of the octant: a window of four rows of e (two upwind rows, the
-// current row with its x halo, the next row) lives in registers, so the
-// stencil of every cell is read from registers, the right-hand side and the
-// upwind recurrence of a row are computed together, and no barrier is needed
-// inside the tile.  Everything that depends only on the cell (global index,
-// geometry code, T_L, scattering rate, source, pending correction) is loaded
-// once, one cell per lane, and broadcast with readlane.  The FP64 moment
-// partials of a row are reduced through a small LDS transpose.
+// One block per work item (tile of up to 8 x 8 cells, octant, chunk of 64
+// (direction, band) lanes) with four wavefronts of two tile rows each.  A
+// wavefront keeps the window of its rows in registers (two upwind rows, its
+// rows with their x halo, the next row), so the stencil of every cell is
+// read from registers, and forms the right-hand side of its rows; the upwind
+// recurrence (serial along x and y) then runs wavefront after wavefront,
+// each handing the increments of its last row to the next through LDS.
+// Everything that depends only on the cell (global index, geometry code,
+// T_L, scattering rate, source, pending correction) is loaded once, one
+// cell per lane, and read back with readlane or broadcast LDS loads.  The
+// FP64 moment partials of a row are reduced through a small LDS transpose.
+// At 124 VGPRs and 26 KiB of LDS (FP32) four blocks share a compute unit.
 #include "bte_internal.h"
 #include "bte_stencil.h"
 #include "bte_tile.h"
@@ -22,6 +24,8 @@ namespace bte {
 namespace {
 
 constexpr int kTX = 8, kTY = 8;
+constexpr int kRW = 2;           // tile rows per wavefront
+constexpr int kWT = kTY / kRW;   // wavefronts per tile (one block)
 
 struct Frame2 {
     int o0, o1, e0, e1, sg0, sg1, n0, n1, cell0, per0, per1;
@@ -143,38 +147,33 @@ enum : uint32_t {
 };
 
 template <typename T, int LIM>
-__global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
-                                                 const double *__restrict__ dpend, const double *__restrict__ TLdev,
-                                                 const double *__restrict__ din,
-                                                 const Sweep2Item *__restrict__ items, int item0, int na_oct,
-                                                 int nchunk_oct, double *__restrict__ part)
+__global__ __launch_bounds__(64 * kWT, 4) void k_sweep2d(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
+                                                      const double *__restrict__ dpend,
+                                                      const double *__restrict__ TLdev,
+                                                      const double *__restrict__ din,
+                                                      const Sweep2Item *__restrict__ items, int item0, int na_oct,
+                                                      int nchunk_oct, double *__restrict__ part)
 {
     __shared__ double lc[64][kMomN + 1];
-    // Recurrence operands per tile row s and lane: sAA = right-hand side over
-    // the diagonal, sRXY[.][0] / [1] = coupling to the upwind x / y increment
-    // over the diagonal (zero where the face is not implicitly coupled), sX0 =
-    // increment of the x-upwind neighbour of the row's first cell, sY0 = the
-    // increments of the row upwind of row 0.  The recurrence overwrites sAA
-    // with the increments.  A row's sRXY area first stages its diffuse-wall
-    // inflow values (slot 2 x + axis) and last holds its new values for the
-    // moment reduction; only that row's wavefront touches it then.
-    __shared__ T sAA[kTY][64][kTX];
-    __shared__ T sRXY[kTY][2][64][kTX];
-    __shared__ T sX0[kTY][64];
-    __shared__ T sY0[64][kTX];
-    // Per-cell scalars of the tile in each wavefront's own copy (x = pending
-    // correction plus jump, gamma, T_L, source; halo x), read back as
-    // broadcast LDS loads rather than lane-by-lane register broadcasts.
-    __shared__ T sPC[kTY][4][64];
-    __shared__ T sHX[kTY][64];
+    // increments of the last row of wavefront w, read by wavefront w + 1
+    __shared__ T sH[64][kTX];
+    // Per wavefront: a staging area of one row (diffuse inflow values, slot
+    // 2 j + axis; then the row's new values for the moment transpose) and
+    // the per-cell scalars of the tile (x = pending correction plus jump,
+    // gamma, T_L, source; halo x), read back as broadcast LDS loads rather
+    // than lane-by-lane register broadcasts.
+    __shared__ T sStg[kWT][16][64];
+    __shared__ T sPC[kWT][4][64];
+    __shared__ T sHX[kWT][64];
     const Sweep2Item it = items[item0 + blockIdx.x];
     // converged geometry of a batch (uniform over the block); a single
     // geometry is never swept once converged, so its blocks skip this load
     // and reach their stencil loads one round trip earlier
     if (d.nfilm > 1 && d.fdone[it.film]) return;
-    // wavefront r owns tile row r (readfirstlane: r is known to be uniform,
-    // so everything derived from it stays scalar)
-    const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    // wavefront w owns tile rows r0 .. r0 + kRW - 1 (readfirstlane: w is
+    // known to be uniform, so everything derived from it stays scalar)
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int r0 = kRW * w;
     const int nl = d.nl, nk = d.nk;
     const int kbeg = it.oct * na_oct * nl, kend = kbeg + na_oct * nl;
     const int k = kbeg + it.chunk * 64 + lane;
@@ -187,7 +186,7 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     const T C4 = (T)d.C4[l], itau = (T)itq;
     const T cp0 = (T)(vq * fabs(s0) * it.ih0), cp1 = (T)(vq * fabs(s1) * it.ih1);
     const T hh0 = (T)(0.5 * it.h0), hh1 = (T)(0.5 * it.h1), ih0 = (T)it.ih0, ih1 = (T)it.ih1;
-    if (r == 0) {
+    if (w == 0) {
         lc[lane][0] = active ? wq : 0.0;
         lc[lane][1] = active ? wq * itq : 0.0;
         lc[lane][2] = active ? wq * vq * s0 : 0.0;
@@ -200,10 +199,13 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     const int sx = sg0 > 0 ? 1 : -1;
     const int rowstep = sg1 > 0 ? F.n0 : -F.n0;
     const int cbase = F.cell0 + (sg0 > 0 ? F.o0 : F.o0 + e0 - 1) + F.n0 * (sg1 > 0 ? F.o1 : F.o1 + e1 - 1);
-    const bool myrow = r < e1;
+    // rows of this wavefront inside the tile, and the first of them clamped
+    // to the tile (a wavefront past the tile loads, and then skips)
+    const int nrow = e1 - r0 < 0 ? 0 : (e1 - r0 > kRW ? kRW : e1 - r0);
+    const int rb = r0 < e1 ? r0 : e1 - 1;
 
     // ---- cell records, one cell per lane (every wavefront builds the same),
-    // broadcast with readlane: tile cell t = f0 + 8 f1 in lane t; halo cell
+    // read back with readlane: tile cell t = f0 + 8 f1 in lane t; halo cell
     // h (see halo_pos) in lane h.  Indices are arithmetic, so the stencil
     // loads below need no record; every load of the block depends on the
     // work item only and is issued unconditionally (a missing cell reads the
@@ -219,8 +221,7 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     }
     // cell records first (the mode words need them), then the raw stencil
     // values of this wavefront's row window, which are waited for only when
-    // the right-hand side is formed (the row index is clamped for
-    // wavefronts past the tile: loaded, unused)
+    // the right-hand side is formed
     const T *zrow = static_cast<const T *>(d.zrow);
     const double *zd = static_cast<const double *>(d.zrow);
     const int tcl = t_c >= 0 ? t_c : F.cell0, hcl = h_c >= 0 ? h_c : F.cell0;
@@ -230,7 +231,6 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     const double t_gamd = d.gamma[tcl];
     const double t_qsd = *(d.P ? d.P + tcl : zd);   // P is null without a heat source
     const int t_db = d.dbase[tcl];
-    const int rr = myrow ? r : e1 - 1;
     auto row_c = [&](int q, int j) -> int {
         const int tc = j < e0 ? cbase + rowstep * q + sx * j : -1;
         const int hcv = rl(h_c, q == -2 ? j : (q == -1 ? 8 + j : 16 + j));
@@ -247,32 +247,44 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
     // The cells of a row (tile row or halo row) are consecutive along x: a
     // row is addressed by the scalar address of its lowest-x cell, the cell
     // j by a per-lane byte offset (j clamped to the tile's extent, so a
-    // ragged tile re-reads its last cell), and a missing row is the zero
-    // row, 8 cells long.  No scalar work per load.
+    // ragged tile re-reads its last cell); a missing row, or a row past the
+    // downwind halo, is the zero row, 8 cells long.  No scalar work per load.
     const char *zc = reinterpret_cast<const char *>(zrow);
     const int lo = sx > 0 ? 0 : -(e0 - 1);   // lowest-x cell relative to the row's flow-first cell
     auto rowp = [&](const T *base, int q) -> const char * {
+        if (q > e1) return zc;
         const int c = (q >= 0 && q < e1) ? cbase + rowstep * q : rl(h_c, q == -2 ? 0 : (q == -1 ? 8 : 16));
         return c >= 0 ? reinterpret_cast<const char *>(base + (size_t)(c + lo) * nk) : zc;
     };
-    const char *pm2 = rowp(ein, rr - 2), *pm1 = rowp(ein, rr - 1), *pc0 = rowp(ein, rr), *pp1 = rowp(ein, rr + 1);
-    const char *pdr = rr == 0 ? rowp(eout, -1) : zc;
-    T ym2[kTX], ym1[kTX], yp1[kTX], dr[kTX], ecr[kTX];
+    // window: rows rb - 2 .. rb + kRW (y[i] holds row rb - 2 + i), the x
+    // halo of this wavefront's rows, the new x-upwind values of its rows and
+    // (first wavefront) the new values of the row upwind of the tile
+    constexpr int kWin = kRW + 3;
+    T y[kWin][kTX], dr[kTX];
+    {
+        const char *pr[kWin];
 #pragma unroll
-    for (int j = 0; j < kTX; ++j) {
-        const int jc = j < e0 ? j : e0 - 1;
-        const unsigned o = koff + (unsigned)((sx > 0 ? jc : e0 - 1 - jc) * nk) * (unsigned)sizeof(T);
-        auto ldr = [&](const char *p) -> T { return *reinterpret_cast<const T *>(p + o); };
-        ym2[j] = ldr(pm2);
-        ym1[j] = ldr(pm1);
-        ecr[j] = ldr(pc0);
-        yp1[j] = ldr(pp1);
-        dr[j] = ldr(pdr);
+        for (int i = 0; i < kWin; ++i) pr[i] = rowp(ein, rb - 2 + i);
+        const char *pdr = rb == 0 ? rowp(eout, -1) : zc;
+#pragma unroll
+        for (int j = 0; j < kTX; ++j) {
+            const int jc = j < e0 ? j : e0 - 1;
+            const unsigned o = koff + (unsigned)((sx > 0 ? jc : e0 - 1 - jc) * nk) * (unsigned)sizeof(T);
+#pragma unroll
+            for (int i = 0; i < kWin; ++i) y[i][j] = *reinterpret_cast<const T *>(pr[i] + o);
+            dr[j] = *reinterpret_cast<const T *>(pdr + o);
+        }
     }
-    const int hx = 24 + 3 * rr;
-    const int cx0 = rl(h_c, hx), cx1 = rl(h_c, hx + 1), cx2 = rl(h_c, hx + 2);
-    T xh0 = ldc(ein, cx0), xh1 = ldc(ein, cx1), xh2 = ldc(ein, cx2);
-    const T dxr = ldc(eout, cx1);
+    T xh[kRW][3], dxr[kRW];
+#pragma unroll
+    for (int i = 0; i < kRW; ++i) {
+        const int hx = 24 + 3 * (rb + i);   // lanes past the tile's halo hold no cell (zero row)
+        const int c0 = rl(h_c, hx), c1 = rl(h_c, hx + 1), c2 = rl(h_c, hx + 2);
+        xh[i][0] = ldc(ein, c0);
+        xh[i][1] = ldc(ein, c1);
+        xh[i][2] = ldc(ein, c2);
+        dxr[i] = ldc(eout, c1);
+    }
 
     // mode words (needs the codes of the upwind neighbours: lanes t - 1 /
     // t - 8 of the tile, or the x-halo / row -1 halo lanes)
@@ -291,16 +303,16 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
             const bool hu0 = side_is_cell(ab0, -sg0), hu1 = side_is_cell(ab1, -sg1);
             const bool hu20 = hu0 && side_is_cell(axis_bits(cu0, 0), -sg0);
             const bool hu21 = hu1 && side_is_cell(axis_bits(cu1, 1), -sg1);
-            uint32_t w = W_SOLID;
-            if (hu20) w |= W_HU20;
-            if (hu21) w |= W_HU21;
-            if (hu20 && side_is_cell(ab0, sg0)) w |= W_FX;
-            if (hu21 && side_is_cell(ab1, sg1)) w |= W_FY;
-            if (hu0 && !side_wraps(ab0, -sg0)) w |= W_CX;
-            if (hu1 && !side_wraps(ab1, -sg1)) w |= W_CY;
-            if (!hu0 && side_wall(ab0, -sg0) == 2) w |= W_DX;
-            if (!hu1 && side_wall(ab1, -sg1) == 2) w |= W_DY;
-            t_w = w;
+            uint32_t wd = W_SOLID;
+            if (hu20) wd |= W_HU20;
+            if (hu21) wd |= W_HU21;
+            if (hu20 && side_is_cell(ab0, sg0)) wd |= W_FX;
+            if (hu21 && side_is_cell(ab1, sg1)) wd |= W_FY;
+            if (hu0 && !side_wraps(ab0, -sg0)) wd |= W_CX;
+            if (hu1 && !side_wraps(ab1, -sg1)) wd |= W_CY;
+            if (!hu0 && side_wall(ab0, -sg0) == 2) wd |= W_DX;
+            if (!hu1 && side_wall(ab1, -sg1) == 2) wd |= W_DY;
+            t_w = wd;
         }
         const bool sol = t_w & W_SOLID;
         t_tl = sol ? (T)t_tld : (T)0;
@@ -309,8 +321,8 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
         t_x = sol ? (T)t_xd : (T)0;
         h_x = (T)(h_xd + h_j);
     }
-    T *const px = &sPC[r][0][0], *const pgam = &sPC[r][1][0], *const ptl = &sPC[r][2][0],
-            *const pqs = &sPC[r][3][0], *const phx = &sHX[r][0];
+    T *const px = &sPC[w][0][0], *const pgam = &sPC[w][1][0], *const ptl = &sPC[w][2][0],
+            *const pqs = &sPC[w][3][0], *const phx = &sHX[w][0];
     px[lane] = t_x;
     pgam[lane] = t_gam;
     ptl[lane] = t_tl;
@@ -322,79 +334,101 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
         return (q >= 0 && q < e1) ? px + 8 * q : phx + (q == -2 ? 0 : (q == -1 ? 8 : 16));
     };
     auto row_x = [&](int q, int j) -> T { return row_xp(q)[j]; };
-    T *wl = &sRXY[r][0][0][0];   // diffuse inflow staging of this row: slot 2 j + a
+    T *const wl = &sStg[w][0][0];   // staging of one row of this wavefront
 
-    // ---- diffuse-wall inflow values of this row, in groups of eight loads
-    // in flight (rows without such walls skip this)
-    if (myrow) {
-        const uint64_t bx = __ballot((t_w & W_DX) != 0), by = __ballot((t_w & W_DY) != 0);
-        uint32_t need = 0;
+    // corrected window and x halo
 #pragma unroll
-        for (int j = 0; j < kTX; ++j)
-            need |= (uint32_t)(((bx >> (8 * r + j)) & 1) << (2 * j)) | (uint32_t)(((by >> (8 * r + j)) & 1) << (2 * j + 1));
-        while (need) {
-            int sl[8];
-            const __attribute__((address_space(1))) double *adr[8];
-            const auto *gzd = (const __attribute__((address_space(1))) double *)zd;
-            const auto *gdin = (const __attribute__((address_space(1))) double *)din;
+    for (int i = 0; i < kWin; ++i) {
+        const T *xr = row_xp(rb - 2 + i);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                sl[q] = -1;
-                adr[q] = gzd + l;
-                if (need) {
-                    const int slot = __builtin_ctz(need);
-                    need &= need - 1;
-                    const int j = slot >> 1, a = slot & 1, t = 8 * r + j;
-                    const uint32_t code = (uint32_t)rl((int)t_code, t);
-                    const int f = face_of(a, a == 0 ? -sg0 : -sg1);
-                    const int rec = rl(t_db, t) + diffuse_rank2(code, f);
-                    sl[q] = slot;
-                    adr[q] = gdin + (size_t)rec * nl + l;
-                }
-            }
-            double v[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = *adr[q];
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (sl[q] >= 0) wl[sl[q] * 64 + lane] = (T)v[q];
-        }
+        for (int j = 0; j < kTX; ++j) y[i][j] += C4 * xr[j];
     }
-
-    // ---- this wavefront's row: stencil rows, right-hand side (in parallel)
-    T num[kTX], ec[kTX], rden[kTX];
-    T dupx = (T)0, dpr0[kTX];
-    if (myrow) {
-        const T *xm2 = row_xp(r - 2), *xm1 = row_xp(r - 1), *xc = row_xp(r), *xp1 = row_xp(r + 1);
+    // the first wavefront's seeds: increments of the row upwind of the tile
+    // (the previous launch's values; an uncoupled one is dropped by a select:
+    // across a periodic face it is the other buffer), handed over like the
+    // increments of the other wavefronts
+    if (w == 0) {
 #pragma unroll
         for (int j = 0; j < kTX; ++j) {
-            ym2[j] += C4 * xm2[j];
-            ym1[j] += C4 * xm1[j];
-            ec[j] = ecr[j] + C4 * xc[j];
-            yp1[j] += C4 * xp1[j];
-            dpr0[j] = dr[j] - ym1[j];   // y-upwind increments (row 0 only)
+            const uint32_t wd = (uint32_t)rl((int)t_w, j);
+            sH[lane][j] = (wd & W_CY) ? dr[j] - y[1][j] : (T)0;
         }
-        xh0 += C4 * phx[hx];
-        xh1 += C4 * phx[hx + 1];
-        xh2 += C4 * phx[hx + 2];
-        dupx = dxr - xh1;
-        // thermalizing wall inflow per axis (upwind face of this octant)
-        const T Tw0 = C4 * (T)(sg0 > 0 ? it.wallT[0] : it.wallT[1]);
-        const T Tw1 = C4 * (T)(sg1 > 0 ? it.wallT[2] : it.wallT[3]);
-        const T Tp = C4 * (T)d.poreT;
+    }
+    T dupx[kRW];
+#pragma unroll
+    for (int i = 0; i < kRW; ++i) {
+        const int hx = 24 + 3 * (rb + i);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) xh[i][m] += C4 * phx[hx + m];
+        dupx[i] = dxr[i] - xh[i][1];
+    }
+    // thermalizing wall inflow per axis (upwind face of this octant)
+    const T Tw0 = C4 * (T)(sg0 > 0 ? it.wallT[0] : it.wallT[1]);
+    const T Tw1 = C4 * (T)(sg1 > 0 ? it.wallT[2] : it.wallT[3]);
+    const T Tp = C4 * (T)d.poreT;
 
+    // ---- right-hand side of this wavefront's rows and the operands of
+    // their recurrence, dv = aa + ry dv(y-upwind) + rx dv(x-upwind) with
+    // rx = cp0 rden, ry = cp1 rden where the face is implicitly coupled.  An
+    // uncoupled upwind increment is dropped by a zero factor (inside the
+    // tile every increment is finite; the seeds are selected)
+    T aa[kRW][kTX], rdn[kRW][kTX];
+#pragma unroll
+    for (int i = 0; i < kRW; ++i) {
+        if (i >= nrow) break;
+        const int r = rb + i;
+        // diffuse-wall inflow values of this row, in groups of eight loads
+        // in flight (rows without such walls skip this)
+        {
+            const uint64_t bx = __ballot((t_w & W_DX) != 0), by = __ballot((t_w & W_DY) != 0);
+            uint32_t need = 0;
+#pragma unroll
+            for (int j = 0; j < kTX; ++j)
+                need |= (uint32_t)(((bx >> (8 * r + j)) & 1) << (2 * j)) |
+                        (uint32_t)(((by >> (8 * r + j)) & 1) << (2 * j + 1));
+            while (need) {
+                int sl[8];
+                const __attribute__((address_space(1))) double *adr[8];
+                const auto *gzd = (const __attribute__((address_space(1))) double *)zd;
+                const auto *gdin = (const __attribute__((address_space(1))) double *)din;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    sl[q] = -1;
+                    adr[q] = gzd + l;
+                    if (need) {
+                        const int slot = __builtin_ctz(need);
+                        need &= need - 1;
+                        const int j = slot >> 1, a = slot & 1, t = 8 * r + j;
+                        const uint32_t code = (uint32_t)rl((int)t_code, t);
+                        const int f = face_of(a, a == 0 ? -sg0 : -sg1);
+                        const int rec = rl(t_db, t) + diffuse_rank2(code, f);
+                        sl[q] = slot;
+                        adr[q] = gdin + (size_t)rec * nl + l;
+                    }
+                }
+                double v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = *adr[q];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (sl[q] >= 0) wl[sl[q] * 64 + lane] = (T)v[q];
+            }
+        }
+        const T *ym2 = y[i], *ym1 = y[i + 1], *ec = y[i + 2], *yp1 = y[i + 3];
+        const T xh0 = xh[i][0], xh1 = xh[i][1], xh2 = xh[i][2];
+        const int hx = 24 + 3 * r;
+        const int cx2 = rl(h_c, hx + 2);
 #pragma unroll
         for (int j = 0; j < kTX; ++j) {
             const int t = 8 * r + j;
-            const uint32_t w = (uint32_t)rl((int)t_w, t);
-            num[j] = (T)0;
-            rden[j] = (T)0;
-            if (w & W_SOLID) {
+            const uint32_t wd = (uint32_t)rl((int)t_w, t);
+            T num = (T)0, rden = (T)0;
+            if (wd & W_SOLID) {
                 const T ex2 = j >= 2 ? ec[j - 2] : (j == 1 ? xh1 : xh0);
                 const T ex1 = j >= 1 ? ec[j - 1] : xh1;
                 const T exd = j + 1 < e0 ? ec[j + 1] : xh2;
                 T dx, dy;
-                if (w & W_FX) {
+                if (wd & W_FX) {
                     dx = delta_fast<T, LIM>(ex2, ex1, ec[j], exd);
                 } else {
                     const int c = rl(t_c, t);
@@ -404,12 +438,12 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
                     const int cd = hd0 ? (j + 1 < e0 ? rl(t_c, t + 1) : cx2) : -1;
                     const double xd = j + 1 < e0 ? (double)px[t + 1] : (double)phx[hx + 2];
                     T fw = (side_wall(ab0, -sg0) == 0) ? (side_outer(code, 0, -sg0) ? Tw0 : Tp) : (T)0;
-                    if (w & W_DX) fw = wl[(2 * j) * 64 + lane];
-                    dx = delta_general<T, LIM>(d, ein, c, code, 0, sg0, hu0, (w & W_HU20) != 0, hd0, ex2, ex1,
+                    if (wd & W_DX) fw = wl[(2 * j) * 64 + lane];
+                    dx = delta_general<T, LIM>(d, ein, c, code, 0, sg0, hu0, (wd & W_HU20) != 0, hd0, ex2, ex1,
                                                ec[j], exd, fw, cd, xd, (double)px[t], al, l, active, C4, hh0,
                                                ih0, nk);
                 }
-                if (w & W_FY) {
+                if (wd & W_FY) {
                     dy = delta_fast<T, LIM>(ym2[j], ym1[j], ec[j], yp1[j]);
                 } else {
                     const int c = rl(t_c, t);
@@ -419,102 +453,68 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
                     const int cd = hd1 ? row_c(r + 1, j) : -1;
                     const double xd = (double)row_x(r + 1, j);
                     T fw = (side_wall(ab1, -sg1) == 0) ? (side_outer(code, 1, -sg1) ? Tw1 : Tp) : (T)0;
-                    if (w & W_DY) fw = wl[(2 * j + 1) * 64 + lane];
-                    dy = delta_general<T, LIM>(d, ein, c, code, 1, sg1, hu1, (w & W_HU21) != 0, hd1, ym2[j],
+                    if (wd & W_DY) fw = wl[(2 * j + 1) * 64 + lane];
+                    dy = delta_general<T, LIM>(d, ein, c, code, 1, sg1, hu1, (wd & W_HU21) != 0, hd1, ym2[j],
                                                ym1[j], ec[j], yp1[j], fw, cd, xd, (double)px[t], al, l, active,
                                                C4, hh1, ih1, nk);
                 }
                 const T gam = pgam[t];
                 const T itc = itau + gam;
-                num[j] = -(cp0 * dx + cp1 * dy) - (ec[j] - C4 * ptl[t]) * itc + C4 * pqs[t];
+                num = -(cp0 * dx + cp1 * dy) - (ec[j] - C4 * ptl[t]) * itc + C4 * pqs[t];
                 const T den = A0 + gam;
-                if constexpr (sizeof(T) == 4) rden[j] = __builtin_amdgcn_rcpf(den);
-                else rden[j] = (T)1 / den;
+                if constexpr (sizeof(T) == 4) rden = __builtin_amdgcn_rcpf(den);
+                else rden = (T)1 / den;
             }
-        }
-        // recurrence operands of the row.  An uncoupled upwind increment is
-        // dropped by a select, not a zero factor: its value may be anything
-        // (across a periodic face it is the other buffer, not yet written in
-        // this sweep).
-        T aa[kTX], rxv[kTX], ryv[kTX];
-#pragma unroll
-        for (int j = 0; j < kTX; ++j) {
-            const uint32_t w = (uint32_t)rl((int)t_w, 8 * r + j);
-            aa[j] = num[j] * rden[j];
-            rxv[j] = (w & W_CX) ? cp0 * rden[j] : (T)0;
-            ryv[j] = (w & W_CY) ? cp1 * rden[j] : (T)0;
-            if (r == 0) sY0[lane][j] = (w & W_CY) ? dpr0[j] : (T)0;
-        }
-        const uint32_t w0 = (uint32_t)rl((int)t_w, 8 * r);
-#pragma unroll
-        for (int j = 0; j < kTX; ++j) {
-            sAA[r][lane][j] = aa[j];
-            sRXY[r][0][lane][j] = rxv[j];
-            sRXY[r][1][lane][j] = ryv[j];
-        }
-        sX0[r][lane] = (w0 & W_CX) ? dupx : (T)0;
-    }
-    __syncthreads();
-
-    // ---- upwind recurrence over the tile (the only serial part), in one
-    // wavefront: dv(s, j) = aa + ry dv(s - 1, j) + rx dv(s, j - 1).  Only the
-    // x chain is serial (one FMA per cell); the next row's operands are read
-    // while the current row is chained.
-    if (r == 0) {
-        T up[kTX], a[kTX], x[kTX], y[kTX];
-#pragma unroll
-        for (int j = 0; j < kTX; ++j) {
-            up[j] = sY0[lane][j];
-            a[j] = sAA[0][lane][j];
-            x[j] = sRXY[0][0][lane][j];
-            y[j] = sRXY[0][1][lane][j];
-        }
-        T x0 = sX0[0][lane];
-        for (int q = 0; q < e1; ++q) {
-            const int qn = q + 1 < kTY ? q + 1 : q;
-            T na[kTX], nx[kTX], ny[kTX];
-#pragma unroll
-            for (int j = 0; j < kTX; ++j) {
-                na[j] = sAA[qn][lane][j];
-                nx[j] = sRXY[qn][0][lane][j];
-                ny[j] = sRXY[qn][1][lane][j];
-            }
-            const T nx0 = sX0[qn][lane];
-            T dl = x0;
-#pragma unroll
-            for (int j = 0; j < kTX; ++j) {
-                const T base = a[j] + y[j] * up[j];
-                dl = base + x[j] * dl;
-                up[j] = dl;
-            }
-#pragma unroll
-            for (int j = 0; j < kTX; ++j) {
-                sAA[q][lane][j] = up[j];
-                a[j] = na[j];
-                x[j] = nx[j];
-                y[j] = ny[j];
-            }
-            x0 = nx0;
+            aa[i][j] = num * rden;
+            rdn[i][j] = rden;
         }
     }
-    __syncthreads();
-    T dlt[kTX];
-#pragma unroll
-    for (int j = 0; j < kTX; ++j) dlt[j] = sAA[r][lane][j];
 
-    // ---- new values, moment partials of the row (a pore cell keeps its
+    // ---- upwind recurrence over the tile, handed from wavefront to
+    // wavefront (the only serial part; one FMA pair per cell)
+    T dv[kRW][kTX];
+#pragma unroll
+    for (int s = 0; s < kWT; ++s) {
+        if (w == s && nrow > 0) {
+            T up[kTX];
+#pragma unroll
+            for (int j = 0; j < kTX; ++j) up[j] = sH[lane][j];
+#pragma unroll
+            for (int i = 0; i < kRW; ++i) {
+                if (i >= nrow) break;
+                const uint32_t w0 = (uint32_t)rl((int)t_w, 8 * (rb + i));
+                T dl = (w0 & W_CX) ? dupx[i] : (T)0;
+#pragma unroll
+                for (int j = 0; j < kTX; ++j) {
+                    const uint32_t wd = (uint32_t)rl((int)t_w, 8 * (rb + i) + j);
+                    const T rxv = (wd & W_CX) ? cp0 * rdn[i][j] : (T)0;
+                    const T ryv = (wd & W_CY) ? cp1 * rdn[i][j] : (T)0;
+                    dl = aa[i][j] + ryv * up[j] + rxv * dl;
+                    up[j] = dl;
+                    dv[i][j] = dl;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kTX; ++j) sH[lane][j] = up[j];
+        }
+        if (s + 1 < kWT) __syncthreads();
+    }
+
+    // ---- new values, moment partials of the rows (a pore cell keeps its
     // value: its increment is zero and it has no correction)
-    if (myrow) {
+#pragma unroll
+    for (int i = 0; i < kRW; ++i) {
+        if (i >= nrow) break;
+        const int r = rb + i;
         const int b = cbase + rowstep * r;
-        T *xs = &sRXY[r][0][0][0];
 #pragma unroll
         for (int j = 0; j < kTX; ++j) {
             T en = (T)0;
             if (j < e0) {
-                en = ec[j] + dlt[j];
+                en = y[i + 2][j] + dv[i][j];
                 if (active) eout[(size_t)(b + sx * j) * nk + k] = en;
             }
-            xs[j * 64 + lane] = active ? en : (T)0;
+            wl[j * 64 + lane] = active ? en : (T)0;
         }
         // lane = 8 cell + part: part sums 8 of the 64 lanes
         const int j = lane >> 3, p = lane & 7;
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int l2 = 8 * p + q;
-            const double x = (double)xs[j * 64 + l2];
+            const double x = (double)wl[j * 64 + l2];
 #pragma unroll
             for (int m = 0; m < kMomN; ++m) acc[m] += lc[l2][m] * x;
         }
@@ -538,11 +538,11 @@ __global__ __launch_bounds__(512) void k_sweep2d(Dev d, const T *__restrict__ ei
         }
         const int t = 8 * r + j;
         const int c = __shfl(t_c, t, 64);
-        const uint32_t w = (uint32_t)__shfl((int)t_w, t, 64);
+        const uint32_t wd = (uint32_t)__shfl((int)t_w, t, 64);
         const double gm = __shfl(t_gamd, t, 64);
         if (p == 0 && j < e0 && c >= 0) {
             double *o = part + ((size_t)(it.oct * nchunk_oct + it.chunk) * d.nc + c) * kMomN;
-            const bool sol = w & W_SOLID;
+            const bool sol = wd & W_SOLID;
             o[0] = sol ? acc[0] : 0.0;
             o[1] = sol ? acc[1] + gm * acc[0] : 0.0;
             o[2] = sol ? acc[2] : 0.0;
@@ -557,7 +557,7 @@ void sweep2d_launch(const Dev &d, const T *ein, T *eout, const double *dpend, co
                     const Sweep2Item *items, int item0, int count, int na_oct, int nchunk_oct, double *part,
                     hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sweep2d<T, LIM>), dim3(count), dim3(64 * kTY), 0, s, d, ein, eout, dpend, TLdev, din, items,
+    hipLaunchKernelGGL((k_sweep2d<T, LIM>), dim3(count), dim3(64 * kWT), 0, s, d, ein, eout, dpend, TLdev, din, items,
                        item0, na_oct, nchunk_oct, part);
 }
 
