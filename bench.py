@@ -328,6 +328,14 @@ def bench_batch(args):
                                       residual_temp=1e-6, residual_flux=1e-5, max_iter=args.max_iter,
                                       cg_rtol=1e-6, cg_max_iter=40))
     e = prob.zeros()
+    tune = []
+    if not args.no_autotune:
+        # every sweep candidate (register tile with 2, 1, 4 rows per
+        # wavefront; LDS tiles) timed on one sweep of all films, fastest kept
+        tune = [x for x in prob.autotune(reps=2, scratch=e) if x["kind"] == B.TUNE_SWEEP]
+        for x in tune:
+            log("autotune sweep tile %s: %.2f ms per sweep%s" % (x["tile"], x["ms"], "  (kept)" if x["chosen"] else ""))
+        e.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = prob.steady_solve(e, init=True, allow_not_converged=True)
@@ -350,7 +358,10 @@ def bench_batch(args):
            "sweep_GBs": BYTES_PER_UPDATE[B.F32] * upd / (st["ms_sweep"] * 1e-3) / 1e9,
            "note": "updates counted per film until it converges (per-film masks); a film of n cells adds "
                    "n x 64 directions x 20 bands per iteration while it is swept",
-           "keff": {"min": float(k.min()), "mean": float(k.mean()), "max": float(k.max())}}
+           "keff": {"min": float(k.min()), "mean": float(k.mean()), "max": float(k.max())},
+           "autotune": [{"tile": list(x["tile"]), "kernel": "k_sweep2d, %d rows per wavefront" % x["tile"][2]
+                         if tuple(x["tile"][:2]) == (8, 8) else "k_sweep_tile (LDS tile)",
+                         "ms_per_sweep": x["ms"], "chosen": x["chosen"]} for x in tune]}
     print(json.dumps(out), flush=True)
 
 
@@ -523,6 +534,14 @@ def main():
         prob.set_graphs(not args.no_graphs)
         prob.set_fields(P, None)
         e = prob.zeros()
+        tune = []
+        if not args.no_autotune:
+            # the sweep candidates (register tile with 2, 1, 4 rows per
+            # wavefront; LDS tiles) timed on one sweep each, fastest kept
+            tune = [x for x in prob.autotune(reps=3, scratch=e) if x["kind"] == B.TUNE_SWEEP]
+            for x in tune:
+                log("autotune sweep tile %s: %.3f ms%s" % (x["tile"], x["ms"], "  (kept)" if x["chosen"] else ""))
+            e.zero_()
         updates = prob.n_cells * prob.n_dirs * prob.n_bands
         log("precision", prec, "unknowns", prob.n_unknowns, "workspace MB %.0f" % (prob.workspace.numel() / 1e6))
         # warmup from the heat-diffusion initial guess
@@ -547,7 +566,7 @@ def main():
         mom_GBs = BYTES_PER_UPDATE[prec] / 2 * updates / (mom_ms * 1e-3) / 1e9
         log("moments: %.3f ms per call, %.0f GB/s" % (mom_ms, mom_GBs))
         results[prec] = dict(t=t, st=st, updates=updates, achieved=achieved, prob=prob, e=e,
-                             sweep_launch_ms=sweep_launch_ms, mom_ms=mom_ms, mom_GBs=mom_GBs)
+                             sweep_launch_ms=sweep_launch_ms, mom_ms=mom_ms, mom_GBs=mom_GBs, tune=tune)
         if args.no_accuracy:
             del prob, e
             torch.cuda.empty_cache()
@@ -580,6 +599,10 @@ def main():
 
     r32 = results[B.F32]
     value = r32["updates"] * args.steps / r32["t"]
+    kept = next((tuple(x["tile"]) for x in r32["tune"] if x["chosen"]), (8, 8, 2))
+    kernel = ("k_sweep2d<float,NONE>, %d tile rows per wavefront" % kept[2] if kept[:2] == (8, 8)
+              else "k_sweep_tile<float,2,NONE>, %dx%d LDS tiles" % kept[:2])
+    launches = r32["st"]["sweep_launches"] / max(args.steps, 1)
     out = {
         "metric": "cell*dir*band updates/s (FP32 state, FP64 moments) of steady source iterations",
         "value": value,
@@ -597,16 +620,18 @@ def main():
                    "n": args.n, "cg_rtol": args.cg_rtol, "cg_max_iter": args.cg_max_iter},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sweep2d<float,NONE> (the 63 tile-diagonal launches of one sweep)",
+            "kernel": "%s (the %d tile-diagonal launches of one sweep)" % (kernel, launches),
+            "sweep_tile": list(kept),
             "achieved": r32["achieved"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": r32["achieved"] / HBM_PEAK_GBS,
-            "traffic": counter_traffic("k_sweep2d<float,0>"),
+            "traffic": counter_traffic("k_sweep2d<float,0>") if kept == (8, 8, 2) else None,
             "avg_launch_ms": r32["sweep_launch_ms"],
             "bytes_per_sweep": BYTES_PER_UPDATE[B.F32] * r32["updates"],
         },
         "phase_ms_per_step": {k: r32["st"][k] / args.steps for k in ("ms_sweep", "ms_walls", "ms_post", "ms_cg")},
+        "autotune": [{"tile": list(x["tile"]), "ms_per_sweep": x["ms"], "chosen": x["chosen"]} for x in r32["tune"]],
         "moment_reduction": {"kernel": "k_moments_wave<float> + k_finalize (bte_moments)", "ms": r32["mom_ms"],
                              "achieved": r32["mom_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": r32["mom_GBs"] / HBM_PEAK_GBS, "bytes": BYTES_PER_UPDATE[B.F32] / 2 * r32["updates"]},

@@ -48,7 +48,7 @@ void launch_adj_grad(const Dev &, const T *, const T *, const double *, const do
 hipError_t adj_kernels_init(size_t);
 template <typename T>
 hipError_t launch_sweep2d(const Dev &, const T *, T *, const double *, const double *, const double *,
-                          const Sweep2Item *, int, int, int, int, double *, hipStream_t);
+                          const Sweep2Item *, int, int, int, int, int, double *, hipStream_t);
 template <typename T>
 hipError_t launch_transient3d(const Dev &, const T *, T *, const double *, const double *, const ColItem *, int, int,
                               int, double, double, double *, hipStream_t);
@@ -447,6 +447,14 @@ int tile_cap_of(const bte_problem *p, int3 td)
     return cells + halo;
 }
 
+// Two-dimensional sweeps with 8 x 8 tiles run the register-tile kernel
+// (tdim.z = its tile rows per wavefront; a 2D geometry has one cell along z,
+// so the tiling is that of 8 x 8 x 1); any other shape runs the LDS-tile
+// kernel.  The LDS-tile kernels (and the 2D adjoint sweep, which has no
+// register form) take the shape with z = 1 then.
+bool reg2d(const bte_problem *p) { return p->dim == 2 && p->tdim.x == 8 && p->tdim.y == 8; }
+int3 lds_tdim(const bte_problem *p) { return reg2d(p) ? make_int3(8, 8, 1) : p->tdim; }
+
 // Tile shapes the LDS-tile kernels may use for one kind (bte_tune_kind), the
 // default shape first: at most 64 cells (the kernels keep 64-entry per-cell
 // tables), a star within the 160 KiB of LDS of a compute unit and, for the
@@ -469,7 +477,7 @@ std::vector<int3> tile_candidates(const bte_problem *p, int kind)
     std::vector<int3> c;
     if (kind == BTE_TUNE_SWEEP) {
         if (p->dim == 1) c = {make_int3(64, 1, 1), make_int3(32, 1, 1), make_int3(16, 1, 1)};
-        else if (p->dim == 2) c = {make_int3(8, 8, 1)};   // fixed by the register sweep
+        else if (p->dim == 2) c = {make_int3(16, 4, 1), make_int3(4, 16, 1), make_int3(8, 4, 1)};   // LDS tiles
         else {
             // column segments of 1 x 1 x z cells (k_sweep3d, at most 48 cells):
             // shorter segments shorten each hyperplane launch, longer ones
@@ -496,6 +504,13 @@ std::vector<int3> tile_candidates(const bte_problem *p, int kind)
     }
     const bool sweep = kind == BTE_TUNE_SWEEP;
     std::vector<int3> ok;
+    // two-dimensional sweeps: the register-tile kernel first (8 x 8 tiles,
+    // z = tile rows per wavefront: 2, 1, and 4 in FP32, where it needs no
+    // scratch), then the LDS-tile shapes
+    if (sweep && p->dim == 2) {
+        ok = {make_int3(8, 8, 2), make_int3(8, 8, 1)};
+        if (p->esize() == 4) ok.push_back(make_int3(8, 8, 4));
+    }
     for (const int3 &t : c) {
         const int e[3] = {t.x, t.y, t.z}, cells = t.x * t.y * t.z;
         int up1 = 0;
@@ -595,7 +610,7 @@ void build_schedule(bte_problem *p)
                             for (int x = x0; x < std::min(x0 + kColStrip, fm.n[0]); ++x)
                                 p->citems.push_back({f, o, ch, x + fm.n[0] * y});
         }
-    p->tile_cap = tile_cap_of(p, p->tdim);
+    p->tile_cap = tile_cap_of(p, lds_tdim(p));
     p->tile_cap_tr = tile_cap_of(p, p->tdim_tr);
     p->items.clear();
     p->diag_off.assign(maxd + 2, 0);
@@ -605,7 +620,7 @@ void build_schedule(bte_problem *p)
     }
     for (int d = 0; d <= maxd; ++d) p->diag_off[d + 1] += p->diag_off[d];
     p->items2.clear();
-    if (p->dim == 2) {
+    if (reg2d(p)) {
         for (const SweepItem &it : p->items) {
             const Film &fm = p->films[it.film];
             Sweep2Item q{};
@@ -657,7 +672,7 @@ void plan_workspace(bte_problem *p)
     add("wrec", 4 * p->wrec.size());
     add("wden", 8 * 6);
     add("items", sizeof(SweepItem) * p->items_cap);
-    add("items2", sizeof(Sweep2Item) * p->items2.size());
+    add("items2", sizeof(Sweep2Item) * (p->dim == 2 ? p->items_cap : 0));
     add("titems", sizeof(TileItem) * p->titems_cap);
     add("citems", sizeof(ColItem) * p->citems.size());
     for (const char *n : {"gamma", "P", "S", "TL", "TLkin", "T0", "T1", "q0", "q1", "r", "delta", "dpend", "cg_x",
@@ -1061,6 +1076,26 @@ template <typename F> hipError_t graph_run(Graph &gr, hipStream_t cs, hipStream_
     return hipGraphLaunch(gr.x, s);
 }
 
+// One forward sweep (every tile-diagonal launch) from ein into eout: the
+// register-tile kernel for 2D geometries with 8 x 8 tiles, the column
+// segments in 3D, the LDS tiles otherwise.
+template <typename T> hipError_t sweep_launches(bte_problem *p, const T *ein, T *eout, hipStream_t q)
+{
+    const Dev &d = p->dev;
+    const bool reg = reg2d(p);
+    const int3 lt = lds_tdim(p);
+    for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
+        const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
+        const hipError_t r =
+            reg ? launch_sweep2d<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items2, i0, cnt, p->tdim.z, p->na_oct,
+                                    p->nchunk_oct, p->part, q)
+                : launch_sweep_tile<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt, lt, p->na_oct,
+                                       p->nchunk_oct, p->tile_cap, p->part, q);
+        if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+}
+
 template <typename T>
 bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, hipStream_t s)
 {
@@ -1115,18 +1150,7 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
         HIPCHK(p, hipEventRecord(ev[0], s));
         launch_walls<T>(d, ein, p->dpend, p->d_wrec, p->d_wden, p->din, p->nw, s);
         HIPCHK(p, hipEventRecord(ev[1], s));
-        auto sweep = [&](hipStream_t q) -> bool {
-            for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
-                const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
-                const hipError_t r =
-                    p->dim == 2 ? launch_sweep2d<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items2, i0, cnt,
-                                                    p->na_oct, p->nchunk_oct, p->part, q)
-                                : launch_sweep_tile<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt,
-                                                       p->tdim, p->na_oct, p->nchunk_oct, p->tile_cap, p->part, q);
-                if (r != hipSuccess) return false;
-            }
-            return true;
-        };
+        auto sweep = [&](hipStream_t q) -> bool { return sweep_launches<T>(p, ein, eout, q) == hipSuccess; };
         if (p->graphs) {
             HIPCHK(p, graph_run(gsweep[cur], p->cstream, s, sweep));
         } else if (!sweep(s)) {
@@ -1422,7 +1446,7 @@ bte_status adjoint_impl(bte_problem *p, const T *e, double *grad, bte_solve_stat
         HIPCHK(p, hipEventRecord(ev[3], s));
         for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
             const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
-            HIPCHK(p, launch_sweep_adj<T>(d, pin, pout, X, p->din, p->d_items, i0, cnt, p->tdim, p->na_oct,
+            HIPCHK(p, launch_sweep_adj<T>(d, pin, pout, X, p->din, p->d_items, i0, cnt, lds_tdim(p), p->na_oct,
                                           p->nchunk_oct, p->tile_cap, p->part, s));
             st.sweep_launches += cnt > 0;
         }
@@ -1809,8 +1833,8 @@ bte_status use_tiles(bte_problem *p, int kind, int3 t)
     return BTE_OK;
 }
 
-// one sweep (kind 0) or one explicit step (kind 1) of the LDS-tile kernels
-// from ein into e2, nothing else
+// one sweep (kind 0) or one explicit step (kind 1) from ein into e2,
+// nothing else
 template <typename T> hipError_t tune_run(bte_problem *p, int kind, const T *ein, hipStream_t s)
 {
     const Dev &d = p->dev;
@@ -1819,13 +1843,7 @@ template <typename T> hipError_t tune_run(bte_problem *p, int kind, const T *ein
         return launch_transient_tile<T>(d, ein, eout, p->TL, p->din, p->d_titems, (int)p->titems.size(),
                                         p->tdim_tr, p->na_oct, p->nchunk_oct, p->tile_cap_tr, 0.0, p->ctl.dt,
                                         p->part, s);
-    for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
-        const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
-        const hipError_t r = launch_sweep_tile<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt,
-                                                  p->tdim, p->na_oct, p->nchunk_oct, p->tile_cap, p->part, s);
-        if (r != hipSuccess) return r;
-    }
-    return hipSuccess;
+    return sweep_launches<T>(p, ein, eout, s);
 }
 
 template <typename T>
@@ -1846,8 +1864,7 @@ bte_status autotune_impl(bte_problem *p, const T *ein, int reps, bte_tune_entry 
     for (int kind : {BTE_TUNE_SWEEP, BTE_TUNE_TRANSIENT}) {
         const std::vector<int3> c = tile_candidates(p, kind);
         if (c.size() < 2) continue;
-        // the column walk takes the three-dimensional steps, the register
-        // tile the two-dimensional sweeps: their shapes are not timed
+        // the column walk takes the three-dimensional steps: no shape to time
         if (kind == BTE_TUNE_TRANSIENT && p->dim == 3) continue;
         std::vector<double> ms(c.size());
         size_t best = 0;

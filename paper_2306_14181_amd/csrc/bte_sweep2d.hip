@@ -3,7 +3,8 @@
 // delta form with the first-order upwind implicit operator).
 //
 // One block per work item (tile of up to 8 x 8 cells, octant, chunk of 64
-// (direction, band) lanes) with four wavefronts of two tile rows each.  A
+// (direction, band) lanes) with 8 / kRW wavefronts of kRW tile rows each
+// (kRW = 1, 2 or 4; two by default).  A
 // wavefront keeps the window of its rows in registers (two upwind rows, its
 // rows with their x halo, the next row), so the stencil of every cell is
 // read from registers, and forms the right-hand side of its rows; the upwind
@@ -13,7 +14,8 @@
 // T_L, scattering rate, source, pending correction) is loaded once, one
 // cell per lane, and read back with readlane or broadcast LDS loads.  The
 // FP64 moment partials of a row are reduced through a small LDS transpose.
-// At 124 VGPRs and 26 KiB of LDS (FP32) four blocks share a compute unit.
+// With two rows per wavefront, at 124 VGPRs and 26 KiB of LDS (FP32), four
+// blocks share a compute unit.
 #include "bte_internal.h"
 #include "bte_stencil.h"
 #include "bte_tile.h"
@@ -24,8 +26,6 @@ namespace bte {
 namespace {
 
 constexpr int kTX = 8, kTY = 8;
-constexpr int kRW = 2;           // tile rows per wavefront
-constexpr int kWT = kTY / kRW;   // wavefronts per tile (one block)
 
 struct Frame2 {
     int o0, o1, e0, e1, sg0, sg1, n0, n1, cell0, per0, per1;
@@ -146,14 +146,20 @@ enum : uint32_t {
     W_DX = 128u, W_DY = 256u                   // diffuse wall on the upwind side along x / y
 };
 
-template <typename T, int LIM>
-__global__ __launch_bounds__(64 * kWT, 4) void k_sweep2d(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
+// Occupancy the compiler is held to (waves per SIMD) for kRW rows per
+// wavefront: four waves per SIMD at one or two rows (four blocks of four
+// wavefronts per compute unit at two rows), two at four rows.
+template <int kRW> constexpr int sweep2d_waves() { return kRW <= 2 ? 4 : 2; }
+
+template <typename T, int LIM, int kRW>
+__global__ __launch_bounds__(64 * (kTY / kRW), sweep2d_waves<kRW>()) void k_sweep2d(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
                                                       const double *__restrict__ dpend,
                                                       const double *__restrict__ TLdev,
                                                       const double *__restrict__ din,
                                                       const Sweep2Item *__restrict__ items, int item0, int na_oct,
                                                       int nchunk_oct, double *__restrict__ part)
 {
+    constexpr int kWT = kTY / kRW;   // wavefronts per tile (one block)
     __shared__ double lc[64][kMomN + 1];
     // increments of the last row of wavefront w, read by wavefront w + 1
     __shared__ T sH[64][kTX];
@@ -552,36 +558,39 @@ __global__ __launch_bounds__(64 * kWT, 4) void k_sweep2d(Dev d, const T *__restr
     }
 }
 
-template <typename T, int LIM>
+template <typename T, int LIM, int RW>
 void sweep2d_launch(const Dev &d, const T *ein, T *eout, const double *dpend, const double *TLdev, const double *din,
                     const Sweep2Item *items, int item0, int count, int na_oct, int nchunk_oct, double *part,
                     hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sweep2d<T, LIM>), dim3(count), dim3(64 * kWT), 0, s, d, ein, eout, dpend, TLdev, din, items,
-                       item0, na_oct, nchunk_oct, part);
+    hipLaunchKernelGGL((k_sweep2d<T, LIM, RW>), dim3(count), dim3(64 * (kTY / RW)), 0, s, d, ein, eout, dpend, TLdev,
+                       din, items, item0, na_oct, nchunk_oct, part);
 }
 
+// Sweep of the items [item0, item0 + count) (one tile diagonal) with rw
+// tile rows per wavefront (1, 2 or 4).
 template <typename T>
 hipError_t launch_sweep2d(const Dev &d, const T *ein, T *eout, const double *dpend, const double *TLdev,
-                          const double *din, const Sweep2Item *items, int item0, int count, int na_oct,
+                          const double *din, const Sweep2Item *items, int item0, int count, int rw, int na_oct,
                           int nchunk_oct, double *part, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    if (d.limiter == LIM_NONE)
-        sweep2d_launch<T, LIM_NONE>(d, ein, eout, dpend, TLdev, din, items, item0, count, na_oct, nchunk_oct, part, s);
-    else if (d.limiter == LIM_MC)
-        sweep2d_launch<T, LIM_MC>(d, ein, eout, dpend, TLdev, din, items, item0, count, na_oct, nchunk_oct, part, s);
-    else
-        sweep2d_launch<T, LIM_MINMOD>(d, ein, eout, dpend, TLdev, din, items, item0, count, na_oct, nchunk_oct, part,
-                                      s);
+    if (rw != 1 && rw != 2 && rw != 4) return hipErrorInvalidValue;
+#define BTE_S2(LIM, RW)                                                                                              \
+    if (d.limiter == LIM && rw == RW)                                                                                \
+        sweep2d_launch<T, LIM, RW>(d, ein, eout, dpend, TLdev, din, items, item0, count, na_oct, nchunk_oct, part, s);
+    BTE_S2(LIM_NONE, 1) BTE_S2(LIM_NONE, 2) BTE_S2(LIM_NONE, 4)
+    BTE_S2(LIM_MC, 1) BTE_S2(LIM_MC, 2) BTE_S2(LIM_MC, 4)
+    BTE_S2(LIM_MINMOD, 1) BTE_S2(LIM_MINMOD, 2) BTE_S2(LIM_MINMOD, 4)
+#undef BTE_S2
     return hipGetLastError();
 }
 
 template hipError_t launch_sweep2d<float>(const Dev &, const float *, float *, const double *, const double *,
-                                          const double *, const Sweep2Item *, int, int, int, int, double *,
+                                          const double *, const Sweep2Item *, int, int, int, int, int, double *,
                                           hipStream_t);
 template hipError_t launch_sweep2d<double>(const Dev &, const double *, double *, const double *, const double *,
-                                           const double *, const Sweep2Item *, int, int, int, int, double *,
+                                           const double *, const Sweep2Item *, int, int, int, int, int, double *,
                                            hipStream_t);
 
 }  // namespace bte

@@ -143,10 +143,12 @@ def test_device_calls_need_a_workspace(lib):
 
 @pytest.mark.parametrize("dim,prec", [(1, 0), (2, 0), (2, 1), (3, 0), (3, 1)])
 def test_tile_candidates(lib, dim, prec):
-    """Candidate tile shapes: the default first, at most 64 cells each, and a
-    choice only where the kernels have one (sweeps in 1D: LDS tiles, in 3D:
-    column segments; explicit steps in 1D/2D); no shape can be set before a
-    workspace is bound."""
+    """Candidate tile shapes: the default first and a choice for every kind
+    the kernels have one for (sweeps in 1D: LDS tiles; in 2D: the register
+    tile with 2, 1 or (FP32) 4 tile rows per wavefront, written as 8 x 8 x
+    rows, then LDS tiles; in 3D: column segments; explicit steps in 1D/2D);
+    LDS tiles have at most 64 cells; no shape can be set before a workspace
+    is bound."""
     b = I.bands(0, 3)
     g = geo(dim, (8,) * dim, (1e-7,) * dim, [I.BC_SPECULAR] * 6)
     st, h = _setup(lib, g, mat(b, 2, 2), {"precision": prec})
@@ -157,16 +159,21 @@ def test_tile_candidates(lib, dim, prec):
         n = C.c_int()
         assert lib.bte_tile_candidates(h, kind, buf, 32, C.byref(n)) == 0
         shapes = [tuple(buf[3 * i:3 * i + 3]) for i in range(n.value)]
-        assert all(x * y * z <= 64 and min(x, y, z) >= 1 for x, y, z in shapes)
-        assert all(s[dim:] == (1,) * (3 - dim) for s in shapes)
+        reg = [s for s in shapes if dim == 2 and kind == 0 and s[:2] == (8, 8)]
+        lds = [s for s in shapes if s not in reg]
+        assert all(x * y * z <= 64 and min(x, y, z) >= 1 for x, y, z in lds)
+        assert all(s[dim:] == (1,) * (3 - dim) for s in lds)
+        if dim == 2 and kind == 0:
+            assert reg == ([(8, 8, 2), (8, 8, 1), (8, 8, 4)] if prec == 0 else [(8, 8, 2), (8, 8, 1)])
+            assert shapes[:len(reg)] == reg and len(lds) >= 1
         got[kind] = shapes
     # 3D sweeps walk column segments of 1 x 1 x z cells: 16 by default, at
     # most the column height (8 here)
-    default_sweep = {1: (64, 1, 1), 2: (8, 8, 1), 3: (1, 1, 8)}[dim]
+    default_sweep = {1: (64, 1, 1), 2: (8, 8, 2), 3: (1, 1, 8)}[dim]
     assert got[0][0] == default_sweep
     if dim == 3:
         assert all(x == 1 and y == 1 and z <= 8 for x, y, z in got[0]) and len(set(got[0])) == len(got[0])
-    assert (len(got[0]) > 1) == (dim != 2)
+    assert len(got[0]) > 1
     assert (len(got[1]) > 1) == (dim != 3)
     t = (C.c_int * 3)(*got[0][0])
     assert lib.bte_set_tiles(h, 0, t) == 7   # BTE_ERR_STATE: no workspace

@@ -34,25 +34,31 @@ def candidates(B, name, prec, kind):
     return prob.tile_candidates(kind)
 
 
-@pytest.mark.parametrize("name", ["box3d", "slab1d"])
-def test_sweep_tiles_match_oracle(B, name):
-    shapes = candidates(B, name, 1, B.TUNE_SWEEP)
+@pytest.mark.parametrize("name,prec,lim", [("box3d", 1, O.LIM_NONE), ("slab1d", 1, O.LIM_NONE),
+                                            ("walls2d", 1, O.LIM_NONE), ("periodic2d", 1, O.LIM_NONE),
+                                            ("walls2d", 0, O.LIM_MC), ("periodic2d", 0, O.LIM_MINMOD)])
+def test_sweep_tiles_match_oracle(B, name, prec, lim):
+    """Every sweep candidate: LDS tiles in 1D, column segments in 3D, in 2D
+    the register tile with each number of rows per wavefront and the LDS
+    tiles (walls2d has ragged 8 x 8 tiles, every wall kind and pores)."""
+    shapes = candidates(B, name, prec, B.TUNE_SWEEP)
     assert len(shapes) >= 3
     eo = None
     for tile in shapes:
-        case, prob = build(B, name, 1, scheme=1, max_iter=3, residual_temp=0.0, residual_flux=0.0, cg_rtol=1e-13,
-                           cg_max_iter=20000)
+        case, prob = build(B, name, prec, limiter=lim, scheme=1, max_iter=3, residual_temp=0.0, residual_flux=0.0,
+                           cg_rtol=1e-13, cg_max_iter=20000)
         prob.set_tiles(B.TUNE_SWEEP, tile)
         e = seeded_e(case, 4)
         eg = to_gpu(prob, e)
+        e = host(eg)
         st = prob.steady_solve(eg, init=False, allow_not_converged=True)
         assert st["iters"] == 3
         if eo is None:
             eo, _ = O.steady(case, scheme=1, tol_T=0.0, tol_q=0.0, max_iter=3, cg_rtol=1e-13, cg_maxit=20000,
                              e=e.copy())
         err = rel_err(host(eg), eo)
-        print(name, tile, err)
-        assert err < 1e-11, (tile, err)
+        print(name, prec, lim, tile, err)
+        assert err < (1e-11 if prec == 1 else 1e-5), (tile, err)
 
 
 @pytest.mark.parametrize("prec", [1, 0])
@@ -117,9 +123,10 @@ def test_transient_adjoint_tiles_match_oracle(B):
         assert abs(J - Jr) <= 1e-12 * abs(Jr) and err < 1e-11, (shapes[i], err)
 
 
+@pytest.mark.parametrize("name", ["box3d", "walls2d"])
 @pytest.mark.parametrize("prec", [1, 0])
-def test_autotune_keeps_one_candidate(B, prec):
-    case, prob = build(B, "box3d", prec, scheme=1, max_iter=3, residual_temp=0.0, residual_flux=0.0,
+def test_autotune_keeps_one_candidate(B, prec, name):
+    case, prob = build(B, name, prec, scheme=1, max_iter=3, residual_temp=0.0, residual_flux=0.0,
                        cg_rtol=1e-13, cg_max_iter=20000)
     shapes = prob.tile_candidates(B.TUNE_SWEEP)
     ent = prob.autotune(reps=2)
