@@ -507,7 +507,10 @@ __global__ __launch_bounds__(64 * (kTY / kRW), sweep2d_waves<kRW>()) void k_swee
     }
 
     // ---- new values, moment partials of the rows (a pore cell keeps its
-    // value: its increment is zero and it has no correction)
+    // value: its increment is zero and it has no correction).  Both are
+    // streamed out (nontemporal stores): no launch reads them back through
+    // this L2, and dirty lines left in it would be written back at the end
+    // of the launch, in the gap before the next diagonal.
 #pragma unroll
     for (int i = 0; i < kRW; ++i) {
         if (i >= nrow) break;
@@ -518,7 +521,7 @@ __global__ __launch_bounds__(64 * (kTY / kRW), sweep2d_waves<kRW>()) void k_swee
             T en = (T)0;
             if (j < e0) {
                 en = y[i + 2][j] + dv[i][j];
-                if (active) eout[(size_t)(b + sx * j) * nk + k] = en;
+                if (active) __builtin_nontemporal_store(en, &eout[(size_t)(b + sx * j) * nk + k]);
             }
             wl[j * 64 + lane] = active ? en : (T)0;
         }
@@ -549,11 +552,11 @@ __global__ __launch_bounds__(64 * (kTY / kRW), sweep2d_waves<kRW>()) void k_swee
         if (p == 0 && j < e0 && c >= 0) {
             double *o = part + ((size_t)(it.oct * nchunk_oct + it.chunk) * d.nc + c) * kMomN;
             const bool sol = wd & W_SOLID;
-            o[0] = sol ? acc[0] : 0.0;
-            o[1] = sol ? acc[1] + gm * acc[0] : 0.0;
-            o[2] = sol ? acc[2] : 0.0;
-            o[3] = sol ? acc[3] : 0.0;
-            o[4] = sol ? acc[4] : 0.0;
+            __builtin_nontemporal_store(sol ? acc[0] : 0.0, &o[0]);
+            __builtin_nontemporal_store(sol ? acc[1] + gm * acc[0] : 0.0, &o[1]);
+            __builtin_nontemporal_store(sol ? acc[2] : 0.0, &o[2]);
+            __builtin_nontemporal_store(sol ? acc[3] : 0.0, &o[3]);
+            __builtin_nontemporal_store(sol ? acc[4] : 0.0, &o[4]);
         }
     }
 }

@@ -262,7 +262,8 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
             en = ec + tdt * (-D - (ec - C4 * tlT) * itc + C4 * tsrc * qsT);
             acc = active ? (L.witau + L.w * rl_d(r_gam, q)) * (double)en : 0.0;
         }
-        if (active) eout[(size_t)c * nk + k] = en;
+        // streamed out (nontemporal): the step never reads its output back
+        if (active) __builtin_nontemporal_store(en, &eout[(size_t)c * nk + k]);
         // partial of this cell into the transposed buffer; every eighth cell
         // (and at the end of the column) the eight cells are reduced
         red[wv][f & 7][lane] = acc;
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
             v += dpp_f64<0x141>(v);   // row_half_mirror
             const int fj = fb + j;
             // (pores get a zero partial: the T_L update ignores them)
-            if (pp == 0 && fj <= f) pout[cb + plane * (sg2 > 0 ? fj : n2 - 1 - fj)] = v;
+            if (pp == 0 && fj <= f) __builtin_nontemporal_store(v, &pout[cb + plane * (sg2 > 0 ? fj : n2 - 1 - fj)]);
         }
         // shift the window to the next cell (the value two cells ahead was
         // prefetched by the previous cell, into `in`)
