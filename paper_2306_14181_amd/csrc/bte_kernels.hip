@@ -184,6 +184,99 @@ __global__ __launch_bounds__(256) void k_moments_wave(Dev d, const T *__restrict
         for (int m = 0; m < kMomN; ++m) part[(size_t)c * kMomN + m] = acc[m];
 }
 
+// Band-factored form (used when the lanes of a row can keep their bands
+// from one load to the next: nl a multiple of the vector width kV, and nL
+// lanes of kV values covering a multiple of nl): the moments of a cell are
+//   sum_k w_a x,  sum_k w_a (1/tau_b + gamma) x,  sum_k w_a s_a v_b x
+// with k = (a, b), so each lane sums its kV values x (same direction a)
+// unweighted, weighted by 1/tau_b and by v_b -- band constants it holds in
+// registers for the whole row -- and only then applies the direction's
+// weights (w_a, w_a s_a) from LDS: two LDS doubles per kV values instead of
+// six per value.  One wavefront per cell; lanes nL .. 63 only load nothing.
+template <typename T>
+__global__ __launch_bounds__(256) void k_moments_band(Dev d, const T *__restrict__ e,
+                                                      const double *__restrict__ dpend, double *__restrict__ part,
+                                                      int nL)
+{
+    constexpr int kV = 16 / (int)sizeof(T);
+    extern __shared__ double tab[];   // per direction: w, w s0, w s1, w s2
+    const int na = d.na, nl = d.nl, nk = d.nk;
+    for (int i = threadIdx.x; i < na; i += blockDim.x) {
+        const double w = d.w[i];
+        tab[4 * i] = w;
+        tab[4 * i + 1] = w * d.s[3 * i];
+        tab[4 * i + 2] = w * d.s[3 * i + 1];
+        tab[4 * i + 3] = w * d.s[3 * i + 2];
+    }
+    __syncthreads();
+    const int c = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (c >= d.nc) return;
+    const int lane = threadIdx.x & 63;
+    double acc[kMomN] = {0, 0, 0, 0, 0};
+    if ((d.code[c] & kSolidBit) && lane < nL) {
+        const double g = d.gamma[c];
+        const double dp = dpend ? dpend[c] : 0.0;
+        const int k0 = kV * lane, step = kV * nL;   // step: a multiple of nl
+        const int b0 = k0 % nl, dA = step / nl;
+        int a = k0 / nl;
+        double it[kV], vb[kV], c4[kV];
+#pragma unroll
+        for (int u = 0; u < kV; ++u) {
+            it[u] = d.itau[b0 + u];
+            vb[u] = d.v[b0 + u];
+            c4[u] = d.C4[b0 + u] * dp;   // pending correction of value u
+        }
+        const T *row = e + (size_t)c * nk;
+        auto load = [&](int kb, T (&v)[kV]) {
+            if constexpr (kV == 4) {
+                const float4 q = *reinterpret_cast<const float4 *>(row + kb);
+                v[0] = q.x;
+                v[1] = q.y;
+                v[2] = q.z;
+                v[3] = q.w;
+            } else {
+                const double2 q = *reinterpret_cast<const double2 *>(row + kb);
+                v[0] = q.x;
+                v[1] = q.y;
+            }
+        };
+        auto accumulate = [&](const T (&v)[kV], int aa) {
+            double X = 0.0, Y = 0.0, V = 0.0;
+#pragma unroll
+            for (int u = 0; u < kV; ++u) {
+                const double x = (double)v[u] + c4[u];
+                X += x;
+                Y += it[u] * x;
+                V += vb[u] * x;
+            }
+            const double *t = tab + 4 * aa;
+            acc[0] += t[0] * X;
+            acc[1] += t[0] * Y;
+            acc[2] += t[1] * V;
+            acc[3] += t[2] * V;
+            acc[4] += t[3] * V;
+        };
+        // two vector loads in flight per lane (the second clamped to the
+        // row's last vector when past its end, and then not accumulated)
+        for (int kb = k0; kb < nk; kb += 2 * step) {
+            const int kb2 = kb + step < nk ? kb + step : nk - kV;
+            T v0[kV], v1[kV];
+            load(kb, v0);
+            load(kb2, v1);
+            accumulate(v0, a);
+            if (kb + step < nk) accumulate(v1, a + dA);
+            a += 2 * dA;
+        }
+        acc[1] += g * acc[0];
+    }
+#pragma unroll
+    for (int m = 0; m < kMomN; ++m)
+        for (int off = 32; off > 0; off >>= 1) acc[m] += __shfl_xor(acc[m], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int m = 0; m < kMomN; ++m) part[(size_t)c * kMomN + m] = acc[m];
+}
+
 // General form: one block per cell.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_moments_block(Dev d, const T *__restrict__ e,
@@ -791,7 +884,16 @@ void launch_moments(const Dev &d, const T *e, const double *dpend, double *part,
 {
     constexpr int kV = 16 / (int)sizeof(T);
     const size_t tab = 8 * (4 * (size_t)d.na + 3 * (size_t)d.nl);
-    if (d.nk % kV == 0 && tab <= 48 * 1024 && (reinterpret_cast<uintptr_t>(e) & 15) == 0)
+    const bool aligned = d.nk % kV == 0 && (reinterpret_cast<uintptr_t>(e) & 15) == 0;
+    // lanes per step of the band-factored form: at most 64, kV nL a multiple of nl
+    int nL = 0;
+    if (d.nl % kV == 0)
+        for (int l = 64; l >= 1 && !nL; --l)
+            if ((kV * l) % d.nl == 0) nL = l;
+    if (aligned && nL >= 32 && 8 * 4 * (size_t)d.na <= 48 * 1024)
+        hipLaunchKernelGGL(k_moments_band<T>, dim3((d.nc + 3) / 4), dim3(256), 8 * 4 * (size_t)d.na, s, d, e, dpend,
+                           part, nL);
+    else if (aligned && tab <= 48 * 1024)
         hipLaunchKernelGGL(k_moments_wave<T>, dim3((d.nc + 3) / 4), dim3(256), tab, s, d, e, dpend, part);
     else
         hipLaunchKernelGGL(k_moments_block<T>, dim3(d.nc), dim3(kBlock), 0, s, d, e, dpend, part);

@@ -76,6 +76,27 @@ def test_moments(B, name, prec):
     assert rel_err(host(q), qo) < tol
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_moments_bench_layout(B, prec):
+    """Moments with the steady workload's lanes (128 directions x 20 bands:
+    the band-factored reduction, 60 lanes of 4 / 2 values per step) on a
+    12 x 12 grid, against the oracle."""
+    import bte_inputs as I
+    cfg = I.square2d_source_case(n=12)
+    g, m = cfg["geometry"], cfg["material"]
+    case = O.Case(g, m)
+    prob = B.Problem(g, m, dict(precision=prec))
+    e = seeded_e(case, 5, smooth=False)
+    eg = to_gpu(prob, e)
+    e = host(eg)
+    T, TL, q = prob.moments(eg)
+    To, TLo, qo = O.moments(case, e)
+    for got, ref in ((T, To), (TL, TLo), (q, qo)):
+        err = rel_err(host(got), ref)
+        print(prec, err)
+        assert err < 1e-12, err
+
+
 @pytest.mark.parametrize("lim", [O.LIM_NONE, O.LIM_MC, O.LIM_MINMOD])
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("name", CASES)
