@@ -10,6 +10,11 @@ times (the same tiles, columns, chunks and launches):
 * one source iteration of the 48^3 porous cube (40 bands, 96 directions,
   pores, per-cell scattering rates), FP32 and FP64, element by element
   against the oracle's sweep;
+* one source iteration of the full batch of 64 porous films (sides 32 to
+  256, 64 directions, 20 bands, minmod limiter, periodic with a drop along
+  x, diffuse pores) swept in one problem, FP32 and FP64: the three smallest
+  films and the largest element by element against the oracle's sweep of
+  each film alone (the films are independent);
 * the adjoint gradient d k_eff / d gamma of the 48^3 porous cube: FP64
   against central differences of the FP64 k_eff on 20 random cells, and
   the FP32 forward solve and adjoint behind autograd against FP64.
@@ -150,6 +155,50 @@ def test_full_size_porous3d_sweep_matches_oracle(B, prec):
     err = rel(g, e1)
     print(prec, "porous 48^3 sweep rel err", err)
     assert err < (1e-5 if p == B.F32 else 1e-11), err
+
+
+_BATCH = {}
+
+
+def batch_reference():
+    if "ref" not in _BATCH:
+        cfg = I.porous2d_batch_case()
+        films, mat = cfg["films"], cfg["material"]
+        sizes = [int(np.prod(g["n"])) for g in films]
+        order = np.argsort(sizes, kind="stable")
+        pick = sorted(set(order[:3].tolist() + [int(order[-1])]))
+        ref = {}
+        for f in pick:
+            case = O.Case(films[f], mat, limiter=O.LIM_MINMOD)
+            e0 = anisotropic_state(case, 300 + f)
+            e1, st = O.steady(case, scheme=0, tol_T=0.0, tol_q=0.0, max_iter=1, e=e0.astype(np.float64))
+            assert st["iters"] == 1
+            ref[f] = (e0, e1)
+        _BATCH["ref"] = (cfg, sizes, ref)
+    return _BATCH["ref"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_full_size_batch_films_match_oracle(B, prec):
+    """The batched-film sweep at its benchmarked size and launch shape."""
+    cfg, sizes, ref = batch_reference()
+    p = B.F32 if prec == "f32" else B.F64
+    prob = B.Problem(cfg["films"], cfg["material"], dict(precision=p, scheme=B.SEQUENTIAL, limiter=B.LIM_MINMOD,
+                                                         max_iter=1, residual_temp=0.0, residual_flux=0.0))
+    nk = prob.n_dirs * prob.n_bands
+    start = np.concatenate([[0], np.cumsum(sizes)]) * nk
+    e = prob.zeros()
+    for f, (e0, _) in ref.items():
+        e[start[f]:start[f + 1]] = torch.as_tensor(e0, device="cuda").to(prob.dtype)
+    st = prob.steady_solve(e, init=False, allow_not_converged=True)
+    assert st["iters"] == 1
+    for f, (_, e1) in ref.items():
+        g = e[start[f]:start[f + 1]].double().cpu().numpy()
+        err = rel(g, e1)
+        print(prec, "film", f, "cells", sizes[f], "rel err", err)
+        assert err < (1e-5 if p == B.F32 else 1e-11), (f, err)
+    del e, prob
+    torch.cuda.empty_cache()
 
 
 def _keff_solve(B, prob, gamma, e_start=None):
