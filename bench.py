@@ -121,10 +121,11 @@ def kernel_source_hash(kernel):
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel):
+def counter_traffic(kernel, variant=None):
     """HBM bytes per launch unit of `kernel` from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
-    kernel sources changed since the counters were taken."""
+    kernel sources changed since the counters were taken or (`variant`:
+    tuning kind and tile shape) another variant was measured."""
     f = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(f):
         return None
@@ -133,7 +134,35 @@ def counter_traffic(kernel):
     r = d.get(kernel)
     if not r or r.get("source_hash") != kernel_source_hash(kernel):
         return None
+    if variant is not None and (r.get("kind"), tuple(r.get("tile", ()))) != (variant[0], tuple(variant[1])):
+        return None
     return r["bytes_per_unit"]
+
+
+def tune_sweep(B, prob, e, reps, one_launch):
+    """Time every 2D sweep candidate (tile shape x launch form) and keep the
+    fastest; with one_launch False only the per-diagonal launch forms compete.
+    Returns the entries of the two sweep kinds."""
+    tune = [dict(x) for x in prob.autotune(reps=reps, scratch=e)
+            if x["kind"] in (B.TUNE_SWEEP, B.TUNE_SWEEP_ONE_LAUNCH)]
+    if not one_launch:
+        tune = [x for x in tune if x["kind"] == B.TUNE_SWEEP]
+        best = min(tune, key=lambda x: x["ms"])
+        for x in tune:
+            x["chosen"] = x is best
+        prob.set_tiles(B.TUNE_SWEEP, best["tile"])
+    for x in tune:
+        x["kernel"] = sweep_kernel_name(B, x["kind"], tuple(x["tile"]))
+        log("autotune %s: %.3f ms per sweep%s" % (x["kernel"], x["ms"], "  (kept)" if x["chosen"] else ""))
+    return tune
+
+
+def sweep_kernel_name(B, kind, tile):
+    if kind == B.TUNE_SWEEP_ONE_LAUNCH:
+        return "k_sweep2d, %d tile rows per wavefront, one launch per sweep" % tile[2]
+    if tuple(tile[:2]) == (8, 8):
+        return "k_sweep2d, %d tile rows per wavefront, one launch per tile diagonal" % tile[2]
+    return "k_sweep_tile, %dx%d LDS tiles, one launch per tile diagonal" % tuple(tile[:2])
 
 
 def copy_calibration():
@@ -327,14 +356,14 @@ def bench_batch(args):
     prob = B.Problem(films, mat, dict(precision=B.F32, scheme=B.SYNTHETIC, limiter=cfg["limiter"],
                                       residual_temp=1e-6, residual_flux=1e-5, max_iter=args.max_iter,
                                       cg_rtol=1e-6, cg_max_iter=40))
+    prob.set_persistent(not args.no_persistent)
     e = prob.zeros()
     tune = []
     if not args.no_autotune:
         # every sweep candidate (register tile with 2, 1, 4 rows per
-        # wavefront; LDS tiles) timed on one sweep of all films, fastest kept
-        tune = [x for x in prob.autotune(reps=2, scratch=e) if x["kind"] == B.TUNE_SWEEP]
-        for x in tune:
-            log("autotune sweep tile %s: %.2f ms per sweep%s" % (x["tile"], x["ms"], "  (kept)" if x["chosen"] else ""))
+        # wavefront, per-diagonal launches or one launch; LDS tiles) timed
+        # on one sweep of all films, fastest kept
+        tune = tune_sweep(B, prob, e, 2, not args.no_persistent)
         e.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -359,9 +388,8 @@ def bench_batch(args):
            "note": "updates counted per film until it converges (per-film masks); a film of n cells adds "
                    "n x 64 directions x 20 bands per iteration while it is swept",
            "keff": {"min": float(k.min()), "mean": float(k.mean()), "max": float(k.max())},
-           "autotune": [{"tile": list(x["tile"]), "kernel": "k_sweep2d, %d rows per wavefront" % x["tile"][2]
-                         if tuple(x["tile"][:2]) == (8, 8) else "k_sweep_tile (LDS tile)",
-                         "ms_per_sweep": x["ms"], "chosen": x["chosen"]} for x in tune]}
+           "autotune": [{"tile": list(x["tile"]), "kernel": x["kernel"], "ms_per_sweep": x["ms"], "chosen": x["chosen"]}
+                        for x in tune]}
     print(json.dumps(out), flush=True)
 
 
@@ -490,6 +518,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-graphs", action="store_true", help="plain launches instead of HIP graph replays")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="2D sweeps with one launch per tile diagonal instead of one launch per sweep")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU sharding is not implemented",
@@ -532,15 +562,15 @@ def main():
     for prec in precs:
         prob = B.Problem(geo, mat, dict(base_ctl, precision=prec))
         prob.set_graphs(not args.no_graphs)
+        prob.set_persistent(not args.no_persistent)
         prob.set_fields(P, None)
         e = prob.zeros()
         tune = []
         if not args.no_autotune:
             # the sweep candidates (register tile with 2, 1, 4 rows per
-            # wavefront; LDS tiles) timed on one sweep each, fastest kept
-            tune = [x for x in prob.autotune(reps=3, scratch=e) if x["kind"] == B.TUNE_SWEEP]
-            for x in tune:
-                log("autotune sweep tile %s: %.3f ms%s" % (x["tile"], x["ms"], "  (kept)" if x["chosen"] else ""))
+            # wavefront, per-diagonal launches or one launch; LDS tiles)
+            # timed on one sweep each, fastest kept
+            tune = tune_sweep(B, prob, e, 3, not args.no_persistent)
             e.zero_()
         updates = prob.n_cells * prob.n_dirs * prob.n_bands
         log("precision", prec, "unknowns", prob.n_unknowns, "workspace MB %.0f" % (prob.workspace.numel() / 1e6))
@@ -599,10 +629,11 @@ def main():
 
     r32 = results[B.F32]
     value = r32["updates"] * args.steps / r32["t"]
+    launches = r32["st"]["sweep_launches"] / max(args.steps, 1)
+    kept_kind = B.TUNE_SWEEP_ONE_LAUNCH if launches == 1 else B.TUNE_SWEEP
     kept = next((tuple(x["tile"]) for x in r32["tune"] if x["chosen"]), (8, 8, 2))
     kernel = ("k_sweep2d<float,NONE>, %d tile rows per wavefront" % kept[2] if kept[:2] == (8, 8)
               else "k_sweep_tile<float,2,NONE>, %dx%d LDS tiles" % kept[:2])
-    launches = r32["st"]["sweep_launches"] / max(args.steps, 1)
     out = {
         "metric": "cell*dir*band updates/s (FP32 state, FP64 moments) of steady source iterations",
         "value": value,
@@ -620,19 +651,21 @@ def main():
                    "n": args.n, "cg_rtol": args.cg_rtol, "cg_max_iter": args.cg_max_iter},
         "roofline": {
             "bound": "hbm",
-            "kernel": "%s (the %d tile-diagonal launches of one sweep)" % (kernel, launches),
+            "kernel": "%s (%s)" % (kernel, "one launch per sweep, each block waiting for its upwind tiles"
+                                   if launches == 1 else "the %d tile-diagonal launches of one sweep" % launches),
             "sweep_tile": list(kept),
             "achieved": r32["achieved"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": r32["achieved"] / HBM_PEAK_GBS,
-            "traffic": counter_traffic("k_sweep2d<float,0>") if kept == (8, 8, 2) else None,
+            "traffic": counter_traffic("k_sweep2d<float,0>", (kept_kind, kept)),
             "avg_launch_ms": r32["sweep_launch_ms"],
             "bytes_per_sweep": BYTES_PER_UPDATE[B.F32] * r32["updates"],
         },
         "phase_ms_per_step": {k: r32["st"][k] / args.steps for k in ("ms_sweep", "ms_walls", "ms_post", "ms_cg")},
-        "autotune": [{"tile": list(x["tile"]), "ms_per_sweep": x["ms"], "chosen": x["chosen"]} for x in r32["tune"]],
-        "moment_reduction": {"kernel": "k_moments_wave<float> + k_finalize (bte_moments)", "ms": r32["mom_ms"],
+        "autotune": [{"tile": list(x["tile"]), "kernel": x["kernel"], "ms_per_sweep": x["ms"], "chosen": x["chosen"]}
+                     for x in r32["tune"]],
+        "moment_reduction": {"kernel": "k_moments_band<float> + k_finalize (bte_moments)", "ms": r32["mom_ms"],
                              "achieved": r32["mom_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": r32["mom_GBs"] / HBM_PEAK_GBS, "bytes": BYTES_PER_UPDATE[B.F32] / 2 * r32["updates"]},
     }

@@ -278,26 +278,38 @@ bte_status bte_set_timing(bte_problem *p, int on);
 bte_status bte_set_graphs(bte_problem *p, int on);
 
 /* Launch form of the two-dimensional steady sweep (the transport sweep of
- * Algorithm 1, Sec. 3.3-3.5).  The sweep is one launch per tile diagonal;
- * on == 0 confirms that and returns BTE_OK.  A single work-queue launch
- * (blocks taking the tiles in diagonal order, each waiting for its upwind
- * tiles) is not available: on != 0 returns BTE_ERR_UNSUPPORTED and changes
- * nothing. */
+ * Algorithm 1, Sec. 3.3-3.5) with the register-tile kernel (8 x 8 tiles).
+ * on == 0: one launch per tile diagonal (the default).  on != 0: one launch
+ * per sweep; each block takes a ticket (the work items in sweep order),
+ * does everything that reads only the previous iterate, then waits for the
+ * items of its x- and y-upwind tiles and reads their new values.  The
+ * results are bitwise those of the launch-per-diagonal form.  Every wait is
+ * bounded: a wait that gives up (about a second) sets an abort word, the
+ * launch ends, and bte_steady_solve returns BTE_ERR_HIP.  Errors:
+ * BTE_ERR_UNSUPPORTED for a one- or three-dimensional problem (on != 0);
+ * the LDS-tile shapes of a 2D problem keep one launch per diagonal. */
 bte_status bte_set_persistent(bte_problem *p, int on);
 
-/* Tile shapes of the LDS-tile kernels.  The paper's solver runs on CPUs
- * (Sec. 3.5: MPI ranks over directions, then bands) and has no counterpart; these
- * calls only choose how the same arithmetic is blocked on the GPU:
- *   BTE_TUNE_SWEEP     tiles of the steady and adjoint sweeps in one and
- *                      three dimensions (two-dimensional sweeps use a fixed
- *                      8x8 register tile and have no choice);
+/* Tile shapes (work decomposition) of the kernels.  The paper's solver runs
+ * on CPUs (Sec. 3.5: MPI ranks over directions, then bands) and has no
+ * counterpart; these calls only choose how the same arithmetic is blocked on
+ * the GPU:
+ *   BTE_TUNE_SWEEP     steady sweeps, one launch per tile diagonal: LDS
+ *                      tiles in 1D; in 2D the register tile 8 x 8 x r (r =
+ *                      tile rows per wavefront: 2, 1, and 4 in FP32) and
+ *                      LDS tiles (other shapes); column segments 1 x 1 x z
+ *                      in 3D;
+ *   BTE_TUNE_SWEEP_ONE_LAUNCH  2D steady sweeps in one launch per sweep
+ *                      (bte_set_persistent): the register-tile shapes;
+ *                      choosing one sets the launch form too (an empty list
+ *                      in 1D and 3D);
  *   BTE_TUNE_TRANSIENT tiles of the explicit step and its transpose in one
  *                      and two dimensions (three-dimensional steps walk
  *                      columns and have no choice).
- * Candidates hold at most 64 cells and their LDS star fits one compute
- * unit; the results of a sweep or step do not depend on the shape beyond
- * floating-point summation order. */
-typedef enum { BTE_TUNE_SWEEP = 0, BTE_TUNE_TRANSIENT = 1 } bte_tune_kind;
+ * LDS tiles hold at most 64 cells and their LDS star fits one compute unit;
+ * the results of a sweep or step do not depend on the shape beyond
+ * floating-point summation order (not at all on the launch form). */
+typedef enum { BTE_TUNE_SWEEP = 0, BTE_TUNE_TRANSIENT = 1, BTE_TUNE_SWEEP_ONE_LAUNCH = 2 } bte_tune_kind;
 
 typedef struct {
     int kind;        /* bte_tune_kind                                     */
@@ -318,6 +330,8 @@ bte_status bte_set_tiles(bte_problem *p, int kind, const int *tile);
 /* Autotuner: for every kind with more than one candidate, time `reps`
  * sweeps (or steps) with each candidate after one untimed run, keep the
  * fastest and report every candidate in entries[0 .. *n) (at most cap).
+ * The two sweep kinds are one choice: the fastest candidate of either is
+ * kept (with its launch form) and is the one marked chosen.
  * e_scratch: device buffer of bte_num_unknowns() elements of the problem's
  * precision, overwritten (it is the input state of the timed runs); the
  * diffuse-wall records, T_L and pending-correction fields are cleared.

@@ -21,7 +21,7 @@ BC_THERMAL, BC_SPECULAR, BC_DIFFUSE, BC_PERIODIC = 0, 1, 2, 3
 SEQUENTIAL, SYNTHETIC = 0, 1
 LIM_NONE, LIM_MC, LIM_MINMOD = 0, 1, 2
 OBJ_KEFF_X = 0
-TUNE_SWEEP, TUNE_TRANSIENT = 0, 1
+TUNE_SWEEP, TUNE_TRANSIENT, TUNE_SWEEP_ONE_LAUNCH = 0, 1, 2
 
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "ERR_NOT_CONVERGED",
                 5: "ERR_NONFINITE", 6: "ERR_CFL", 7: "ERR_STATE"}
@@ -386,24 +386,27 @@ class Problem:
         self._check(load().bte_set_graphs(self._h, int(bool(on))))
 
     def set_persistent(self, on=False):
-        """Launch form of the two-dimensional sweep: one launch per tile diagonal (on=False); the
-        work-queue form (on=True) is not available and raises BteError."""
+        """Launch form of the two-dimensional register-tile sweep: one launch per tile diagonal
+        (on=False) or one launch per sweep (on=True; BteError in 1D and 3D)."""
         self._check(load().bte_set_persistent(self._h, int(bool(on))))
 
     def tile_candidates(self, kind):
-        """Candidate tile shapes (x, y, z) of TUNE_SWEEP or TUNE_TRANSIENT, the default first."""
+        """Candidate tile shapes (x, y, z) of TUNE_SWEEP, TUNE_SWEEP_ONE_LAUNCH or TUNE_TRANSIENT,
+        the default first."""
         n = C.c_int()
         buf = (C.c_int * 96)()
         self._check(load().bte_tile_candidates(self._h, int(kind), buf, 32, C.byref(n)))
         return [tuple(buf[3 * i:3 * i + 3]) for i in range(min(n.value, 32))]
 
     def set_tiles(self, kind, tile):
-        """Use tile shape `tile` (one of tile_candidates(kind))."""
+        """Use tile shape `tile` (one of tile_candidates(kind)); TUNE_SWEEP_ONE_LAUNCH also turns
+        the one-launch sweep on, TUNE_SWEEP turns it off."""
         t = (C.c_int * 3)(*tile)
         self._check(load().bte_set_tiles(self._h, int(kind), t))
 
     def autotune(self, reps=3, scratch=None):
         """Time every candidate tile shape, keep the fastest; returns one dict per candidate.
+        The two sweep kinds are one choice: one entry of either is chosen (shape and launch form).
         `scratch` (a state tensor, overwritten) defaults to a fresh one."""
         e = self.zeros() if scratch is None else scratch
         out = (TuneEntry * 64)()

@@ -48,7 +48,8 @@ void launch_adj_grad(const Dev &, const T *, const T *, const double *, const do
 hipError_t adj_kernels_init(size_t);
 template <typename T>
 hipError_t launch_sweep2d(const Dev &, const T *, T *, const double *, const double *, const double *,
-                          const Sweep2Item *, int, int, int, int, int, double *, hipStream_t);
+                          const Sweep2Item *, int, int, int, int, int, double *, unsigned *, hipStream_t);
+hipError_t launch_queue_reset(unsigned *, int, hipStream_t);
 template <typename T>
 hipError_t launch_transient3d(const Dev &, const T *, T *, const double *, const double *, const ColItem *, int, int,
                               int, double, double, double *, hipStream_t);
@@ -190,6 +191,7 @@ struct bte_problem {
     double *adju = nullptr, *adjr2 = nullptr;
     SweepItem *d_items = nullptr;
     Sweep2Item *d_items2 = nullptr;
+    unsigned *d_queue = nullptr;   // one-launch 2D sweep: ticket, abort word, item flags
     TileItem *d_titems = nullptr;
     ColItem *d_citems = nullptr;
     int *d_wrec = nullptr;
@@ -204,6 +206,8 @@ struct bte_problem {
     // private stream (the caller's may be the null stream, which cannot be
     // captured) and replayed on the caller's stream
     bool graphs = true;
+    bool persistent = false;   // 2D register-tile sweeps in one launch (bte_set_persistent)
+    bool queue_ok = false;     // every item's upwind items precede it (build_schedule)
     hipStream_t cstream = nullptr;
     ~bte_problem()
     {
@@ -475,6 +479,14 @@ bool seg_fits(const bte_problem *p, int zseg)
 std::vector<int3> tile_candidates(const bte_problem *p, int kind)
 {
     std::vector<int3> c;
+    if (kind == BTE_TUNE_SWEEP_ONE_LAUNCH) {
+        // the register-tile shapes of a 2D sweep, in one launch per sweep
+        if (p->dim == 2) {
+            c = {make_int3(8, 8, 2), make_int3(8, 8, 1)};
+            if (p->esize() == 4) c.push_back(make_int3(8, 8, 4));
+        }
+        return c;
+    }
     if (kind == BTE_TUNE_SWEEP) {
         if (p->dim == 1) c = {make_int3(64, 1, 1), make_int3(32, 1, 1), make_int3(16, 1, 1)};
         else if (p->dim == 2) c = {make_int3(16, 4, 1), make_int3(4, 16, 1), make_int3(8, 4, 1)};   // LDS tiles
@@ -644,7 +656,41 @@ void build_schedule(bte_problem *p)
             q.ih0 = fm.ih[0];
             q.ih1 = fm.ih[1];
             for (int f = 0; f < 4; ++f) q.wallT[f] = fm.wallT[f];
+            q.upx = q.upy = -1;
             p->items2.push_back(q);
+        }
+        // Items of the x- and y-upwind tiles (same geometry, octant and
+        // chunk; none across the domain edge, where the coupling is a wall or
+        // a lagged periodic face) for the one-launch sweep, which waits for
+        // them.  They lie on earlier tile diagonals, hence earlier in the
+        // order; the queue form is refused if that ever fails.
+        std::vector<size_t> foff(p->nfilm + 1, 0);
+        for (int f = 0; f < p->nfilm; ++f) {
+            const Film &fm = p->films[f];
+            const size_t nt = (size_t)((fm.n[0] + 7) / 8) * ((fm.n[1] + 7) / 8);
+            foff[f + 1] = foff[f] + nt * p->noct * p->nchunk_oct;
+        }
+        std::vector<int> at(foff[p->nfilm], -1);
+        auto key = [&](int f, int o, int ch, int tile) {
+            const Film &fm = p->films[f];
+            const size_t nt = (size_t)((fm.n[0] + 7) / 8) * ((fm.n[1] + 7) / 8);
+            return foff[f] + ((size_t)o * p->nchunk_oct + ch) * nt + tile;
+        };
+        for (size_t i = 0; i < p->items.size(); ++i) {
+            const SweepItem &it = p->items[i];
+            at[key(it.film, it.oct, it.chunk, it.tile)] = (int)i;
+        }
+        p->queue_ok = true;
+        for (size_t i = 0; i < p->items.size(); ++i) {
+            const SweepItem &it = p->items[i];
+            Sweep2Item &q = p->items2[i];
+            const Film &fm = p->films[it.film];
+            const int nt0 = (fm.n[0] + 7) / 8, nt1 = (fm.n[1] + 7) / 8;
+            const int tx = it.tile % nt0, ty = it.tile / nt0;
+            const int ux = tx - ((q.flags & 4) ? 1 : -1), uy = ty - ((q.flags & 8) ? 1 : -1);
+            if (ux >= 0 && ux < nt0) q.upx = at[key(it.film, it.oct, it.chunk, ux + nt0 * ty)];
+            if (uy >= 0 && uy < nt1) q.upy = at[key(it.film, it.oct, it.chunk, tx + nt0 * uy)];
+            if (q.upx >= (int)i || q.upy >= (int)i) p->queue_ok = false;
         }
     }
 }
@@ -673,6 +719,7 @@ void plan_workspace(bte_problem *p)
     add("wden", 8 * 6);
     add("items", sizeof(SweepItem) * p->items_cap);
     add("items2", sizeof(Sweep2Item) * (p->dim == 2 ? p->items_cap : 0));
+    add("queue", 4 * (p->dim == 2 ? p->items_cap + 2 : 0));
     add("titems", sizeof(TileItem) * p->titems_cap);
     add("citems", sizeof(ColItem) * p->citems.size());
     for (const char *n : {"gamma", "P", "S", "TL", "TLkin", "T0", "T1", "q0", "q1", "r", "delta", "dpend", "cg_x",
@@ -927,6 +974,7 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     p->adjr2 = wsptr<double>(p, "adjr2");
     p->d_items = wsptr<SweepItem>(p, "items");
     p->d_items2 = wsptr<Sweep2Item>(p, "items2");
+    p->d_queue = wsptr<unsigned>(p, "queue");
     p->d_titems = wsptr<TileItem>(p, "titems");
     p->d_citems = wsptr<ColItem>(p, "citems");
     p->d_wrec = wsptr<int>(p, "wrec");
@@ -1084,11 +1132,20 @@ template <typename T> hipError_t sweep_launches(bte_problem *p, const T *ein, T 
     const Dev &d = p->dev;
     const bool reg = reg2d(p);
     const int3 lt = lds_tdim(p);
+    if (reg && p->persistent && p->queue_ok) {
+        // the whole sweep in one launch: every item waits for its upwind items
+        const int n = (int)p->items2.size();
+        hipError_t r = launch_queue_reset(p->d_queue, n, q);
+        if (r == hipSuccess)
+            r = launch_sweep2d<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items2, 0, n, p->tdim.z, p->na_oct,
+                                  p->nchunk_oct, p->part, p->d_queue, q);
+        return r;
+    }
     for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) {
         const int i0 = p->diag_off[dg], cnt = p->diag_off[dg + 1] - i0;
         const hipError_t r =
             reg ? launch_sweep2d<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items2, i0, cnt, p->tdim.z, p->na_oct,
-                                    p->nchunk_oct, p->part, q)
+                                    p->nchunk_oct, p->part, nullptr, q)
                 : launch_sweep_tile<T>(d, ein, eout, p->dpend, p->TL, p->din, p->d_items, i0, cnt, lt, p->na_oct,
                                        p->nchunk_oct, p->tile_cap, p->part, q);
         if (r != hipSuccess) return r;
@@ -1156,7 +1213,10 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
         } else if (!sweep(s)) {
             FAIL(p, BTE_ERR_HIP, "sweep launch failed");
         }
-        for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg) st.sweep_launches += p->diag_off[dg + 1] > p->diag_off[dg];
+        if (reg2d(p) && p->persistent && p->queue_ok) st.sweep_launches += 1;
+        else
+            for (size_t dg = 0; dg + 1 < p->diag_off.size(); ++dg)
+                st.sweep_launches += p->diag_off[dg + 1] > p->diag_off[dg];
         HIPCHK(p, hipEventRecord(ev[2], s));
         launch_steady_post(d, p->part, np, p->TL, p->TLkin, p->T1, p->q1, p->r, synthetic, s);
         launch_film_eps(d, p->T0, p->T1, p->q0, p->q1, p->feps, p->fpart, p->fseg, s);
@@ -1178,7 +1238,11 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
         }
         HIPCHK(p, hipEventRecord(ev[4], s));
         HIPCHK(p, hipMemcpyAsync(feps.data(), p->feps, 8 * feps.size(), hipMemcpyDeviceToHost, s));
+        unsigned qabort = 0;
+        if (reg2d(p) && p->persistent && p->queue_ok)
+            HIPCHK(p, hipMemcpyAsync(&qabort, p->d_queue + 1, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(p, hipStreamSynchronize(s));
+        if (qabort) FAIL(p, BTE_ERR_HIP, "one-launch sweep: a wait for an upwind tile gave up");
         {
             float ms[4];
             for (int i = 0; i < 4; ++i) HIPCHK(p, hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
@@ -1795,13 +1859,16 @@ bte_status bte_set_graphs(bte_problem *p, int on)
 bte_status bte_set_persistent(bte_problem *p, int on)
 {
     if (!p) return BTE_ERR_ARG;
-    if (on) FAIL(p, BTE_ERR_UNSUPPORTED, "the work-queue form of the sweep is not available");
+    if (on && p->dim != 2) FAIL(p, BTE_ERR_UNSUPPORTED, "the one-launch sweep is the 2D register-tile sweep's");
+    if (on && !p->queue_ok) FAIL(p, BTE_ERR_STATE, "sweep order: an item precedes one of its upwind items");
+    p->persistent = on != 0;
     return BTE_OK;
 }
 
 bte_status bte_tile_candidates(const bte_problem *p, int kind, int *tiles, int cap, int *n)
 {
-    if (!p || !n || (kind != BTE_TUNE_SWEEP && kind != BTE_TUNE_TRANSIENT) || cap < 0 || (cap > 0 && !tiles))
+    if (!p || !n || (kind != BTE_TUNE_SWEEP && kind != BTE_TUNE_TRANSIENT && kind != BTE_TUNE_SWEEP_ONE_LAUNCH) ||
+        cap < 0 || (cap > 0 && !tiles))
         return BTE_ERR_ARG;
     const std::vector<int3> c = tile_candidates(p, kind);
     for (int i = 0; i < (int)c.size() && i < cap; ++i) {
@@ -1820,11 +1887,19 @@ namespace {
 // switch one kind to tile shape t (a candidate) and upload the new work lists
 bte_status use_tiles(bte_problem *p, int kind, int3 t)
 {
-    if (kind == BTE_TUNE_SWEEP) p->tdim = t;
-    else p->tdim_tr = t;
+    if (kind == BTE_TUNE_SWEEP || kind == BTE_TUNE_SWEEP_ONE_LAUNCH) {
+        p->tdim = t;
+        p->persistent = kind == BTE_TUNE_SWEEP_ONE_LAUNCH;
+    } else {
+        p->tdim_tr = t;
+    }
     build_schedule(p);
     if (p->items.size() > p->items_cap || p->titems.size() > p->titems_cap)
         FAIL(p, BTE_ERR_STATE, "work list larger than its reserved room");
+    if (p->persistent && !p->queue_ok) {
+        p->persistent = false;
+        FAIL(p, BTE_ERR_STATE, "sweep order: an item precedes one of its upwind items");
+    }
     HIPCHK(p, hipMemcpy(p->d_items, p->items.data(), sizeof(SweepItem) * p->items.size(), hipMemcpyHostToDevice));
     HIPCHK(p, hipMemcpy(p->d_titems, p->titems.data(), sizeof(TileItem) * p->titems.size(), hipMemcpyHostToDevice));
     if (!p->items2.empty())
@@ -1861,11 +1936,21 @@ bte_status autotune_impl(bte_problem *p, const T *ein, int reps, bte_tune_entry 
         }
     } evg{ev};
     int m = 0;
-    for (int kind : {BTE_TUNE_SWEEP, BTE_TUNE_TRANSIENT}) {
+    // the two sweep kinds are one choice (shape and launch form); the
+    // explicit-step shapes another
+    struct Best {
+        int kind = -1;
+        int3 t{};
+        double ms = 0.0;
+        int entry = -1;
+    } best_sweep;
+    for (int kind : {BTE_TUNE_SWEEP, BTE_TUNE_SWEEP_ONE_LAUNCH, BTE_TUNE_TRANSIENT}) {
         const std::vector<int3> c = tile_candidates(p, kind);
-        if (c.size() < 2) continue;
+        const bool sweep = kind != BTE_TUNE_TRANSIENT;
+        if (c.empty() || (!sweep && c.size() < 2)) continue;
         // the column walk takes the three-dimensional steps: no shape to time
         if (kind == BTE_TUNE_TRANSIENT && p->dim == 3) continue;
+        if (kind == BTE_TUNE_SWEEP && c.size() < 2 && tile_candidates(p, BTE_TUNE_SWEEP_ONE_LAUNCH).empty()) continue;
         std::vector<double> ms(c.size());
         size_t best = 0;
         for (size_t i = 0; i < c.size(); ++i) {
@@ -1881,10 +1966,22 @@ bte_status autotune_impl(bte_problem *p, const T *ein, int reps, bte_tune_entry 
             ms[i] = t / reps;
             if (ms[i] < ms[best]) best = i;
         }
-        bte_status st = use_tiles(p, kind, c[best]);
-        if (st != BTE_OK) return st;
         for (size_t i = 0; i < c.size(); ++i, ++m)
-            if (m < cap) out[m] = bte_tune_entry{kind, {c[i].x, c[i].y, c[i].z}, ms[i], i == best ? 1 : 0};
+            if (m < cap) out[m] = bte_tune_entry{kind, {c[i].x, c[i].y, c[i].z}, ms[i], 0};
+        const int first = m - (int)c.size();
+        if (sweep) {
+            if (best_sweep.kind < 0 || ms[best] < best_sweep.ms)
+                best_sweep = Best{kind, c[best], ms[best], first + (int)best};
+        } else {
+            bte_status st = use_tiles(p, kind, c[best]);
+            if (st != BTE_OK) return st;
+            if (first + (int)best < cap) out[first + best].chosen = 1;
+        }
+    }
+    if (best_sweep.kind >= 0) {
+        bte_status st = use_tiles(p, best_sweep.kind, best_sweep.t);
+        if (st != BTE_OK) return st;
+        if (best_sweep.entry < cap) out[best_sweep.entry].chosen = 1;
     }
     *n = m;
     return BTE_OK;
@@ -1897,7 +1994,8 @@ extern "C" {
 bte_status bte_set_tiles(bte_problem *p, int kind, const int *tile)
 {
     if (!p) return BTE_ERR_ARG;
-    if (!tile || (kind != BTE_TUNE_SWEEP && kind != BTE_TUNE_TRANSIENT)) FAIL(p, BTE_ERR_ARG, "bad tile request");
+    if (!tile || (kind != BTE_TUNE_SWEEP && kind != BTE_TUNE_TRANSIENT && kind != BTE_TUNE_SWEEP_ONE_LAUNCH))
+        FAIL(p, BTE_ERR_ARG, "bad tile request");
     if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
     for (const int3 &t : tile_candidates(p, kind))
         if (t.x == tile[0] && t.y == tile[1] && t.z == tile[2]) return use_tiles(p, kind, t);

@@ -80,7 +80,8 @@ struct SweepItem {
 struct Sweep2Item {
     int oct, chunk, film, flags;   // flags: bit0/1 periodic x/y, bit2/3 octant sign of x/y positive
     int o0, o1, e0, e1;            // tile origin and extent (cells) in the geometry
-    int n0, n1, cell0, pad;        // geometry size and first cell
+    int n0, n1, cell0;             // geometry size and first cell
+    int upx, upy, pad;             // items of the x- / y-upwind tiles in the sweep order (-1: none)
     double pdT0, pdT1;             // periodic temperature drops along x, y
     double h0, h1, ih0, ih1;       // cell size and inverse along x, y
     double wallT[4];               // thermalizing wall temperatures minus T_ref, faces -x, +x, -y, +y

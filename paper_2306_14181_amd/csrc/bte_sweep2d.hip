@@ -95,6 +95,60 @@ __device__ inline bool halo_pos(const Frame2 &F, int h, int &f0, int &f1)
 
 __device__ inline int rl(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
+// Queue words of a one-launch sweep: ticket counter, abort word, then one
+// completion flag per item; all zeroed by k_queue_reset before the launch.
+//
+// Ordering without per-block cache maintenance: every new value a block
+// writes is a device-scope store (coherent beyond the XCD's L2), and every
+// wavefront waits for all its memory operations to complete (s_waitcnt 0)
+// before the block's last barrier, after which the flag is written; a
+// waiting block polls the flag with device-scope loads, passes a barrier,
+// and reads the values it needs from its upwind tiles with device-scope
+// loads.  (An agent-scope release / acquire pair per block instead writes
+// back and invalidates the whole L2 each time, which made the sweep 2.4x
+// slower than one launch per diagonal.)
+constexpr int kQueueTicket = 0, kQueueAbort = 1, kQueueDone = 2;
+constexpr int kQueueSpin = 1 << 20;   // polls before a wait gives up (about a second)
+
+// Wait until item u is published.  The wait is bounded: after kQueueSpin
+// polls (or once any block has given up) it sets the abort word and
+// returns, so the launch always ends; the host reports the abort as an
+// error.  The polls are device-scope loads, issued in the loop.
+__device__ inline void queue_wait(unsigned *q, int u)
+{
+    for (int n = 0; n < kQueueSpin; ++n) {
+        if (__hip_atomic_load(q + kQueueDone + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return;
+        if ((n & 63) == 63 && __hip_atomic_load(q + kQueueAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+            return;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __hip_atomic_store(q + kQueueAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish item u (called after the barrier that follows every wavefront's
+// completed stores).
+__device__ inline void queue_publish(unsigned *q, int u)
+{
+    __hip_atomic_store(q + kQueueDone + u, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Device-scope load and store of a state value (the one-launch sweep's
+// values that other blocks of the same launch read).
+template <typename T> __device__ inline T dev_load(const T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T> __device__ inline void dev_store(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_queue_reset(unsigned *q, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n + kQueueDone) q[i] = 0u;
+}
+
 }  // namespace
 
 // Face-value difference of one axis on the general path (missing
@@ -147,17 +201,25 @@ enum : uint32_t {
 };
 
 // Occupancy the compiler is held to (waves per SIMD) for kRW rows per
-// wavefront: four waves per SIMD at one or two rows (four blocks of four
-// wavefronts per compute unit at two rows), two at four rows.
-template <int kRW> constexpr int sweep2d_waves() { return kRW <= 2 ? 4 : 2; }
+// wavefront, FP32: four waves per SIMD at one or two rows (four blocks of
+// four wavefronts per compute unit at two rows), two at four rows; the
+// one-launch form, which keeps a few more values across its wait, three
+// (four would spill).  FP64: two (its registers allow no more without spills).
+template <typename T, int kRW, bool QUEUE> constexpr int sweep2d_waves()
+{
+    return sizeof(T) == 8 ? 2 : (kRW == 4 ? 2 : (QUEUE ? 3 : 4));
+}
 
-template <typename T, int LIM, int kRW>
-__global__ __launch_bounds__(64 * (kTY / kRW), sweep2d_waves<kRW>()) void k_sweep2d(Dev d, const T *__restrict__ ein, T *__restrict__ eout,
-                                                      const double *__restrict__ dpend,
-                                                      const double *__restrict__ TLdev,
-                                                      const double *__restrict__ din,
-                                                      const Sweep2Item *__restrict__ items, int item0, int na_oct,
-                                                      int nchunk_oct, double *__restrict__ part)
+// QUEUE: the whole sweep in one launch, one block per item: a block takes
+// a ticket (items in sweep order), does everything that reads only the
+// previous iterate, then waits for the items of its x- and y-upwind tiles
+// (queue_wait) before it reads their new values, and publishes its own
+// after its stores.  Otherwise the launch covers one tile diagonal.
+template <typename T, int LIM, int kRW, bool QUEUE>
+__global__ __launch_bounds__(64 * (kTY / kRW), (sweep2d_waves<T, kRW, QUEUE>())) void k_sweep2d(
+    Dev d, const T *__restrict__ ein, T *__restrict__ eout, const double *__restrict__ dpend,
+    const double *__restrict__ TLdev, const double *__restrict__ din, const Sweep2Item *__restrict__ items,
+    int item0, int na_oct, int nchunk_oct, double *__restrict__ part, unsigned *__restrict__ queue)
 {
     constexpr int kWT = kTY / kRW;   // wavefronts per tile (one block)
     __shared__ double lc[64][kMomN + 1];
@@ -171,11 +233,24 @@ __global__ __launch_bounds__(64 * (kTY / kRW), sweep2d_waves<kRW>()) void k_swee
     __shared__ T sStg[kWT][16][64];
     __shared__ T sPC[kWT][4][64];
     __shared__ T sHX[kWT][64];
-    const Sweep2Item it = items[item0 + blockIdx.x];
+    int item = item0 + (int)blockIdx.x;
+    if constexpr (QUEUE) {
+        // the ticket is taken first, by a running block: every item this
+        // block waits for has a smaller ticket, i.e. a block already running
+        __shared__ int s_ticket;
+        if (threadIdx.x == 0) s_ticket = (int)atomicAdd(queue + kQueueTicket, 1u);
+        __syncthreads();
+        item = s_ticket;
+    }
+    const Sweep2Item it = items[item];
     // converged geometry of a batch (uniform over the block); a single
     // geometry is never swept once converged, so its blocks skip this load
     // and reach their stencil loads one round trip earlier
-    if (d.nfilm > 1 && d.fdone[it.film]) return;
+    if (d.nfilm > 1 && d.fdone[it.film]) {
+        if constexpr (QUEUE)
+            if (threadIdx.x == 0) queue_publish(queue, item);
+        return;
+    }
     // wavefront w owns tile rows r0 .. r0 + kRW - 1 (readfirstlane: w is
     // known to be uniform, so everything derived from it stays scalar)
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -271,7 +346,7 @@ __global__ __launch_bounds__(64 * (kTY / kRW), sweep2d_waves<kRW>()) void k_swee
         const char *pr[kWin];
 #pragma unroll
         for (int i = 0; i < kWin; ++i) pr[i] = rowp(ein, rb - 2 + i);
-        const char *pdr = rb == 0 ? rowp(eout, -1) : zc;
+        const char *pdr = (rb == 0 && !QUEUE) ? rowp(eout, -1) : zc;
 #pragma unroll
         for (int j = 0; j < kTX; ++j) {
             const int jc = j < e0 ? j : e0 - 1;
@@ -289,7 +364,7 @@ __global__ __launch_bounds__(64 * (kTY / kRW), sweep2d_waves<kRW>()) void k_swee
         xh[i][0] = ldc(ein, c0);
         xh[i][1] = ldc(ein, c1);
         xh[i][2] = ldc(ein, c2);
-        dxr[i] = ldc(eout, c1);
+        dxr[i] = QUEUE ? (T)0 : ldc(eout, c1);
     }
 
     // mode words (needs the codes of the upwind neighbours: lanes t - 1 /
@@ -353,20 +428,31 @@ __global__ __launch_bounds__(64 * (kTY / kRW), sweep2d_waves<kRW>()) void k_swee
     // (the previous launch's values; an uncoupled one is dropped by a select:
     // across a periodic face it is the other buffer), handed over like the
     // increments of the other wavefronts
-    if (w == 0) {
-#pragma unroll
-        for (int j = 0; j < kTX; ++j) {
-            const uint32_t wd = (uint32_t)rl((int)t_w, j);
-            sH[lane][j] = (wd & W_CY) ? dr[j] - y[1][j] : (T)0;
-        }
-    }
     T dupx[kRW];
 #pragma unroll
     for (int i = 0; i < kRW; ++i) {
         const int hx = 24 + 3 * (rb + i);
 #pragma unroll
         for (int m = 0; m < 3; ++m) xh[i][m] += C4 * phx[hx + m];
-        dupx[i] = dxr[i] - xh[i][1];
+    }
+    // seeds: ym1 = the corrected row upwind of the tile, xh1 = the corrected
+    // x-halo values of this wavefront's rows
+    auto seeds = [&](const T (&ym1)[kTX], const T (&xh1)[kRW]) {
+        if (w == 0) {
+#pragma unroll
+            for (int j = 0; j < kTX; ++j) {
+                const uint32_t wd = (uint32_t)rl((int)t_w, j);
+                sH[lane][j] = (wd & W_CY) ? dr[j] - ym1[j] : (T)0;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kRW; ++i) dupx[i] = dxr[i] - xh1[i];
+    };
+    if constexpr (!QUEUE) {
+        T xh1[kRW];
+#pragma unroll
+        for (int i = 0; i < kRW; ++i) xh1[i] = xh[i][1];
+        seeds(y[1], xh1);
     }
     // thermalizing wall inflow per axis (upwind face of this octant)
     const T Tw0 = C4 * (T)(sg0 > 0 ? it.wallT[0] : it.wallT[1]);
@@ -476,6 +562,44 @@ __global__ __launch_bounds__(64 * (kTY / kRW), sweep2d_waves<kRW>()) void k_swee
         }
     }
 
+    if constexpr (QUEUE) {
+        // the new values of the upwind tiles: wait for their items, then read
+        // (device scope, after the barrier) the row upwind of the tile (first
+        // wavefront) and the x halo
+        if (threadIdx.x == 0) {
+            if (it.upx >= 0) queue_wait(queue, it.upx);
+            if (it.upy >= 0) queue_wait(queue, it.upy);
+        }
+        __syncthreads();
+        // (the previous iterate's values the seeds subtract are read again
+        // rather than kept live across the right-hand side)
+        T ym1[kTX], xh1[kRW];
+        if (rb == 0) {
+            const char *pdr = rowp(eout, -1), *pym = rowp(ein, -1);
+            const T *xr = row_xp(-1);
+#pragma unroll
+            for (int j = 0; j < kTX; ++j) {
+                const int jc = j < e0 ? j : e0 - 1;
+                const unsigned o = koff + (unsigned)((sx > 0 ? jc : e0 - 1 - jc) * nk) * (unsigned)sizeof(T);
+                dr[j] = dev_load(reinterpret_cast<const T *>(pdr + o));
+                ym1[j] = *reinterpret_cast<const T *>(pym + o) + C4 * xr[j];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kRW; ++i) {
+            const int hx = 24 + 3 * (rb + i);
+            const int c1 = rl(h_c, hx + 1);
+            {
+                const bool ok = c1 >= 0;
+                const char *row =
+                    reinterpret_cast<const char *>((ok ? static_cast<const T *>(eout) : zrow) + (size_t)(ok ? c1 : 0) * nk);
+                dxr[i] = dev_load(reinterpret_cast<const T *>(row + koff));
+            }
+            xh1[i] = ldc(ein, c1) + C4 * phx[hx + 1];
+        }
+        seeds(ym1, xh1);
+    }
+
     // ---- upwind recurrence over the tile, handed from wavefront to
     // wavefront (the only serial part; one FMA pair per cell)
     T dv[kRW][kTX];
@@ -521,7 +645,10 @@ __global__ __launch_bounds__(64 * (kTY / kRW), sweep2d_waves<kRW>()) void k_swee
             T en = (T)0;
             if (j < e0) {
                 en = y[i + 2][j] + dv[i][j];
-                if (active) __builtin_nontemporal_store(en, &eout[(size_t)(b + sx * j) * nk + k]);
+                if (active) {
+                    if constexpr (QUEUE) dev_store(&eout[(size_t)(b + sx * j) * nk + k], en);
+                    else __builtin_nontemporal_store(en, &eout[(size_t)(b + sx * j) * nk + k]);
+                }
             }
             wl[j * 64 + lane] = active ? en : (T)0;
         }
@@ -559,29 +686,44 @@ __global__ __launch_bounds__(64 * (kTY / kRW), sweep2d_waves<kRW>()) void k_swee
             __builtin_nontemporal_store(sol ? acc[4] : 0.0, &o[4]);
         }
     }
+    if constexpr (QUEUE) {
+        // every wavefront's stores have completed (device scope), then the
+        // barrier, then the flag
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) queue_publish(queue, item);
+    }
 }
 
 template <typename T, int LIM, int RW>
 void sweep2d_launch(const Dev &d, const T *ein, T *eout, const double *dpend, const double *TLdev, const double *din,
                     const Sweep2Item *items, int item0, int count, int na_oct, int nchunk_oct, double *part,
-                    hipStream_t s)
+                    unsigned *queue, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sweep2d<T, LIM, RW>), dim3(count), dim3(64 * (kTY / RW)), 0, s, d, ein, eout, dpend, TLdev,
-                       din, items, item0, na_oct, nchunk_oct, part);
+    if (queue)
+        hipLaunchKernelGGL((k_sweep2d<T, LIM, RW, true>), dim3(count), dim3(64 * (kTY / RW)), 0, s, d, ein, eout,
+                           dpend, TLdev, din, items, 0, na_oct, nchunk_oct, part, queue);
+    else
+        hipLaunchKernelGGL((k_sweep2d<T, LIM, RW, false>), dim3(count), dim3(64 * (kTY / RW)), 0, s, d, ein, eout,
+                           dpend, TLdev, din, items, item0, na_oct, nchunk_oct, part, queue);
 }
 
 // Sweep of the items [item0, item0 + count) (one tile diagonal) with rw
 // tile rows per wavefront (1, 2 or 4).
+// queue: null for one tile diagonal (items [item0, item0 + count)); else
+// the whole sweep in one launch (items [0, count) in sweep order, queue
+// words zeroed by launch_queue_reset on the same stream).
 template <typename T>
 hipError_t launch_sweep2d(const Dev &d, const T *ein, T *eout, const double *dpend, const double *TLdev,
                           const double *din, const Sweep2Item *items, int item0, int count, int rw, int na_oct,
-                          int nchunk_oct, double *part, hipStream_t s)
+                          int nchunk_oct, double *part, unsigned *queue, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
     if (rw != 1 && rw != 2 && rw != 4) return hipErrorInvalidValue;
 #define BTE_S2(LIM, RW)                                                                                              \
     if (d.limiter == LIM && rw == RW)                                                                                \
-        sweep2d_launch<T, LIM, RW>(d, ein, eout, dpend, TLdev, din, items, item0, count, na_oct, nchunk_oct, part, s);
+        sweep2d_launch<T, LIM, RW>(d, ein, eout, dpend, TLdev, din, items, item0, count, na_oct, nchunk_oct, part,   \
+                                   queue, s);
     BTE_S2(LIM_NONE, 1) BTE_S2(LIM_NONE, 2) BTE_S2(LIM_NONE, 4)
     BTE_S2(LIM_MC, 1) BTE_S2(LIM_MC, 2) BTE_S2(LIM_MC, 4)
     BTE_S2(LIM_MINMOD, 1) BTE_S2(LIM_MINMOD, 2) BTE_S2(LIM_MINMOD, 4)
@@ -591,9 +733,17 @@ hipError_t launch_sweep2d(const Dev &d, const T *ein, T *eout, const double *dpe
 
 template hipError_t launch_sweep2d<float>(const Dev &, const float *, float *, const double *, const double *,
                                           const double *, const Sweep2Item *, int, int, int, int, int, double *,
-                                          hipStream_t);
+                                          unsigned *, hipStream_t);
 template hipError_t launch_sweep2d<double>(const Dev &, const double *, double *, const double *, const double *,
                                            const double *, const Sweep2Item *, int, int, int, int, int, double *,
-                                           hipStream_t);
+                                           unsigned *, hipStream_t);
+
+// Zero the queue words of a one-launch sweep of n items (a kernel, not a
+// memset: the sweep launches are replayed from graphs).
+hipError_t launch_queue_reset(unsigned *queue, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_queue_reset, dim3((n + kQueueDone + 255) / 256), dim3(256), 0, s, queue, n);
+    return hipGetLastError();
+}
 
 }  // namespace bte

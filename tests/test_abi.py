@@ -146,7 +146,8 @@ def test_tile_candidates(lib, dim, prec):
     """Candidate tile shapes: the default first and a choice for every kind
     the kernels have one for (sweeps in 1D: LDS tiles; in 2D: the register
     tile with 2, 1 or (FP32) 4 tile rows per wavefront, written as 8 x 8 x
-    rows, then LDS tiles; in 3D: column segments; explicit steps in 1D/2D);
+    rows, then LDS tiles; in 3D: column segments; explicit steps in 1D/2D;
+    the one-launch sweep: the 2D register shapes);
     LDS tiles have at most 64 cells; no shape can be set before a workspace
     is bound."""
     b = I.bands(0, 3)
@@ -154,11 +155,17 @@ def test_tile_candidates(lib, dim, prec):
     st, h = _setup(lib, g, mat(b, 2, 2), {"precision": prec})
     assert st == 0, lib.bte_last_error(h)
     got = {}
-    for kind in (0, 1):
+    for kind in (0, 1, 2):
         buf = (C.c_int * 96)()
         n = C.c_int()
         assert lib.bte_tile_candidates(h, kind, buf, 32, C.byref(n)) == 0
         shapes = [tuple(buf[3 * i:3 * i + 3]) for i in range(n.value)]
+        if kind == 2:
+            # the one-launch 2D sweep: the register shapes, nothing in 1D/3D
+            assert shapes == ([] if dim != 2 else [(8, 8, 2), (8, 8, 1), (8, 8, 4)] if prec == 0
+                              else [(8, 8, 2), (8, 8, 1)])
+            got[kind] = shapes
+            continue
         reg = [s for s in shapes if dim == 2 and kind == 0 and s[:2] == (8, 8)]
         lds = [s for s in shapes if s not in reg]
         assert all(x * y * z <= 64 and min(x, y, z) >= 1 for x, y, z in lds)
@@ -178,4 +185,18 @@ def test_tile_candidates(lib, dim, prec):
     t = (C.c_int * 3)(*got[0][0])
     assert lib.bte_set_tiles(h, 0, t) == 7   # BTE_ERR_STATE: no workspace
     assert lib.bte_set_tiles(h, 5, t) == 1   # BTE_ERR_ARG
+    lib.bte_destroy(h)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_one_launch_sweep_is_the_2d_register_sweeps(lib, dim):
+    """bte_set_persistent(1): the 2D sweep in one launch (its work list
+    passed the order check at setup: every item after its upwind items);
+    refused in 1D and 3D; switching it off is always accepted."""
+    b = I.bands(0, 3)
+    g = geo(dim, (13,) * dim, (1e-7,) * dim, [I.BC_SPECULAR] * 6)
+    st, h = _setup(lib, g, mat(b, 2, 2), {"precision": 0})
+    assert st == 0, lib.bte_last_error(h)
+    assert lib.bte_set_persistent(h, 0) == 0
+    assert lib.bte_set_persistent(h, 1) == (0 if dim == 2 else 2)   # BTE_ERR_UNSUPPORTED
     lib.bte_destroy(h)

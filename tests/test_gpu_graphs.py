@@ -4,10 +4,12 @@ replayed every source iteration, with the host's convergence check and
 synchronisation between replays; the final fields must be bitwise equal to
 those of the same solve with plain launches.
 
-The tests of the work-queue form of the two-dimensional sweep (one launch
-whose blocks take the tiles in diagonal order and wait for their upwind
-tiles) are skipped: that form hung its first GPU run and was taken out; the
-entry point that selects it now refuses."""
+The one-launch form of the two-dimensional sweep (bte_set_persistent: one
+launch per sweep whose blocks take the items in sweep order by ticket and
+wait for the items of their upwind tiles) does the same arithmetic as the
+launch-per-diagonal form: its fields are bitwise equal to those, with and
+without graphs, for every rows-per-wavefront variant, batches with
+per-geometry masks included."""
 import numpy as np
 import pytest
 
@@ -68,11 +70,6 @@ def test_graph_batch_with_masks_equals_plain_launches(B):
     assert np.array_equal(a, b)
 
 
-QUEUE_SKIP = pytest.mark.skip(reason="the work-queue sweep hung its first GPU run (a steady solve of walls2d "
-                                     "timed out); it was taken out and bte_set_persistent(1) refuses")
-
-
-@QUEUE_SKIP
 @pytest.mark.parametrize("graphs", [False, True])
 @pytest.mark.parametrize("lim", ["none", "mc"])
 @pytest.mark.parametrize("name", ["walls2d", "periodic2d"])
@@ -88,21 +85,32 @@ def test_queue_sweep_equals_diagonal_launches(B, name, prec, lim, graphs):
     assert np.array_equal(a, b)
 
 
-@QUEUE_SKIP
-def test_queue_sweep_many_items_per_block(B):
-    # 64 x 64 cells: 64 tiles x 4 octants x 10 chunks = 2560 items, several
-    # per resident block of the queue launch
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_queue_sweep_square_every_row_split(B, prec):
+    # 64 x 64 cells: 64 tiles x 4 quadrants x 10 chunks = 2560 items in one
+    # launch, for each number of tile rows per wavefront
     cfg = I.square2d_source_case(n=64)
-    for prec in (B.F32, B.F64):
-        a, sa = solve(B, cfg["geometry"], cfg["material"], cfg["P"], None, prec, B.LIM_NONE, True, 30,
-                      persistent=False, max_iter=12)
-        b, sb = solve(B, cfg["geometry"], cfg["material"], cfg["P"], None, prec, B.LIM_NONE, True, 30,
-                      persistent=True, max_iter=12)
-        assert sa["iters"] == sb["iters"] == 12
-        assert np.array_equal(a, b)
+    p = B.F32 if prec == "f32" else B.F64
+    shapes = [(8, 8, 2), (8, 8, 1)] + ([(8, 8, 4)] if p == B.F32 else [])
+    for tile in shapes:
+        out = []
+        for persistent in (False, True):
+            prob = B.Problem(cfg["geometry"], cfg["material"], dict(precision=p, scheme=B.SYNTHETIC,
+                                                                    limiter=B.LIM_NONE, residual_temp=0.0,
+                                                                    residual_flux=0.0, max_iter=12, cg_rtol=1e-10,
+                                                                    cg_max_iter=30))
+            prob.set_tiles(B.TUNE_SWEEP, tile)
+            prob.set_persistent(persistent)
+            prob.set_fields(dev(cfg["P"]), None)
+            e = prob.zeros()
+            st = prob.steady_solve(e, init=True, allow_not_converged=True)
+            assert st["iters"] == 12
+            assert st["sweep_launches"] == (12 if persistent else 12 * 15)
+            out.append(e.cpu().numpy())
+        print(prec, tile, "equal", np.array_equal(out[0], out[1]))
+        assert np.array_equal(out[0], out[1]), tile
 
 
-@QUEUE_SKIP
 def test_queue_sweep_batch_with_masks(B):
     cfg = I.porous2d_batch_case(seed=5, n_films=5, sides=(16, 24, 32), n_bands=4, n_theta=1, n_phi=2)
     films, mat = cfg["films"], cfg["material"]
@@ -112,8 +120,8 @@ def test_queue_sweep_batch_with_masks(B):
     assert np.array_equal(a, b)
 
 
-def test_work_queue_sweep_is_refused(B):
-    g, m, P, gam = small_cases()["walls2d"]
+def test_one_launch_sweep_is_refused_in_3d(B):
+    g, m, P, gam = small_cases()["box3d"]
     prob = B.Problem(g, m, dict(precision=B.F32))
     prob.set_persistent(False)
     with pytest.raises(RuntimeError):

@@ -39,26 +39,31 @@ def candidates(B, name, prec, kind):
                                             ("walls2d", 0, O.LIM_MC), ("periodic2d", 0, O.LIM_MINMOD)])
 def test_sweep_tiles_match_oracle(B, name, prec, lim):
     """Every sweep candidate: LDS tiles in 1D, column segments in 3D, in 2D
-    the register tile with each number of rows per wavefront and the LDS
-    tiles (walls2d has ragged 8 x 8 tiles, every wall kind and pores)."""
-    shapes = candidates(B, name, prec, B.TUNE_SWEEP)
+    the register tile with each number of rows per wavefront (per-diagonal
+    launches and one launch per sweep) and the LDS tiles (walls2d has ragged
+    8 x 8 tiles, every wall kind and pores)."""
+    shapes = [(B.TUNE_SWEEP, t) for t in candidates(B, name, prec, B.TUNE_SWEEP)]
     assert len(shapes) >= 3
+    shapes += [(B.TUNE_SWEEP_ONE_LAUNCH, t) for t in candidates(B, name, prec, B.TUNE_SWEEP_ONE_LAUNCH)]
+    assert (len(shapes) > len(candidates(B, name, prec, B.TUNE_SWEEP))) == name.endswith("2d")
     eo = None
-    for tile in shapes:
+    for kind, tile in shapes:
         case, prob = build(B, name, prec, limiter=lim, scheme=1, max_iter=3, residual_temp=0.0, residual_flux=0.0,
                            cg_rtol=1e-13, cg_max_iter=20000)
-        prob.set_tiles(B.TUNE_SWEEP, tile)
+        prob.set_tiles(kind, tile)
         e = seeded_e(case, 4)
         eg = to_gpu(prob, e)
         e = host(eg)
         st = prob.steady_solve(eg, init=False, allow_not_converged=True)
         assert st["iters"] == 3
+        if name.endswith("2d"):   # more than one tile diagonal in these films
+            assert (st["sweep_launches"] == 3) == (kind == B.TUNE_SWEEP_ONE_LAUNCH)
         if eo is None:
             eo, _ = O.steady(case, scheme=1, tol_T=0.0, tol_q=0.0, max_iter=3, cg_rtol=1e-13, cg_maxit=20000,
                              e=e.copy())
         err = rel_err(host(eg), eo)
-        print(name, prec, lim, tile, err)
-        assert err < (1e-11 if prec == 1 else 1e-5), (tile, err)
+        print(name, prec, lim, kind, tile, err)
+        assert err < (1e-11 if prec == 1 else 1e-5), (kind, tile, err)
 
 
 @pytest.mark.parametrize("prec", [1, 0])
@@ -128,10 +133,12 @@ def test_transient_adjoint_tiles_match_oracle(B):
 def test_autotune_keeps_one_candidate(B, prec, name):
     case, prob = build(B, name, prec, scheme=1, max_iter=3, residual_temp=0.0, residual_flux=0.0,
                        cg_rtol=1e-13, cg_max_iter=20000)
-    shapes = prob.tile_candidates(B.TUNE_SWEEP)
+    kinds = (B.TUNE_SWEEP, B.TUNE_SWEEP_ONE_LAUNCH)
+    shapes = [(k, t) for k in kinds for t in prob.tile_candidates(k)]
     ent = prob.autotune(reps=2)
-    sweep = [x for x in ent if x["kind"] == B.TUNE_SWEEP]
-    assert [x["tile"] for x in sweep] == shapes
+    # the two sweep kinds are one choice: shape and launch form
+    sweep = [x for x in ent if x["kind"] in kinds]
+    assert [(x["kind"], x["tile"]) for x in sweep] == shapes
     assert sum(x["chosen"] for x in sweep) == 1 and all(x["ms"] > 0 for x in sweep)
     best = min(sweep, key=lambda x: x["ms"])
     assert best["chosen"]
@@ -139,7 +146,9 @@ def test_autotune_keeps_one_candidate(B, prec, name):
     e = seeded_e(case, 4)
     eg = to_gpu(prob, e)
     e = host(eg)
-    prob.steady_solve(eg, init=False, allow_not_converged=True)
+    st = prob.steady_solve(eg, init=False, allow_not_converged=True)
+    if name.endswith("2d"):
+        assert (st["sweep_launches"] == 3) == (best["kind"] == B.TUNE_SWEEP_ONE_LAUNCH)
     eo, _ = O.steady(case, scheme=1, tol_T=0.0, tol_q=0.0, max_iter=3, cg_rtol=1e-13, cg_maxit=20000, e=e.copy())
     err = rel_err(host(eg), eo)
     assert err < (1e-11 if prec == 1 else 1e-5), err
