@@ -26,6 +26,7 @@ namespace bte {
 namespace {
 
 constexpr int kTX = 8, kTY = 8;
+constexpr int kWS = 65;   // row stride of a staged row in the moment transpose
 
 struct Frame2 {
     int o0, o1, e0, e1, sg0, sg1, n0, n1, cell0, per0, per1;
@@ -222,7 +223,10 @@ __global__ __launch_bounds__(64 * (kTY / kRW), (sweep2d_waves<T, kRW, QUEUE>()))
     int item0, int na_oct, int nchunk_oct, double *__restrict__ part, unsigned *__restrict__ queue)
 {
     constexpr int kWT = kTY / kRW;   // wavefronts per tile (one block)
-    __shared__ double lc[64][kMomN + 1];
+    // moment weights of lane l2 = 8 p + q at lc[q][m][p]: the lanes of the
+    // row transpose below read the eight p of one (q, m) at once, eight
+    // consecutive doubles (no bank conflicts)
+    __shared__ double lc[8][kMomN][8];
     // increments of the last row of wavefront w, read by wavefront w + 1
     __shared__ T sH[64][kTX];
     // Per wavefront: a staging area of one row (diffuse inflow values, slot
@@ -268,11 +272,12 @@ __global__ __launch_bounds__(64 * (kTY / kRW), (sweep2d_waves<T, kRW, QUEUE>()))
     const T cp0 = (T)(vq * fabs(s0) * it.ih0), cp1 = (T)(vq * fabs(s1) * it.ih1);
     const T hh0 = (T)(0.5 * it.h0), hh1 = (T)(0.5 * it.h1), ih0 = (T)it.ih0, ih1 = (T)it.ih1;
     if (w == 0) {
-        lc[lane][0] = active ? wq : 0.0;
-        lc[lane][1] = active ? wq * itq : 0.0;
-        lc[lane][2] = active ? wq * vq * s0 : 0.0;
-        lc[lane][3] = active ? wq * vq * s1 : 0.0;
-        lc[lane][4] = active ? wq * vq * s2 : 0.0;
+        double *lq = &lc[lane & 7][0][lane >> 3];
+        lq[0] = active ? wq : 0.0;
+        lq[8] = active ? wq * itq : 0.0;
+        lq[16] = active ? wq * vq * s0 : 0.0;
+        lq[24] = active ? wq * vq * s1 : 0.0;
+        lq[32] = active ? wq * vq * s2 : 0.0;
     }
     const Frame2 F = frame2(it);
     const int e0 = F.e0, e1 = F.e1;
@@ -346,14 +351,14 @@ __global__ __launch_bounds__(64 * (kTY / kRW), (sweep2d_waves<T, kRW, QUEUE>()))
         const char *pr[kWin];
 #pragma unroll
         for (int i = 0; i < kWin; ++i) pr[i] = rowp(ein, rb - 2 + i);
-        const char *pdr = (rb == 0 && !QUEUE) ? rowp(eout, -1) : zc;
+        const char *pdr = rb == 0 ? rowp(eout, -1) : zc;
 #pragma unroll
         for (int j = 0; j < kTX; ++j) {
             const int jc = j < e0 ? j : e0 - 1;
             const unsigned o = koff + (unsigned)((sx > 0 ? jc : e0 - 1 - jc) * nk) * (unsigned)sizeof(T);
 #pragma unroll
             for (int i = 0; i < kWin; ++i) y[i][j] = *reinterpret_cast<const T *>(pr[i] + o);
-            dr[j] = *reinterpret_cast<const T *>(pdr + o);
+            if constexpr (!QUEUE) dr[j] = *reinterpret_cast<const T *>(pdr + o);
         }
     }
     T xh[kRW][3], dxr[kRW];
@@ -364,7 +369,7 @@ __global__ __launch_bounds__(64 * (kTY / kRW), (sweep2d_waves<T, kRW, QUEUE>()))
         xh[i][0] = ldc(ein, c0);
         xh[i][1] = ldc(ein, c1);
         xh[i][2] = ldc(ein, c2);
-        dxr[i] = QUEUE ? (T)0 : ldc(eout, c1);
+        if constexpr (!QUEUE) dxr[i] = ldc(eout, c1);
     }
 
     // mode words (needs the codes of the upwind neighbours: lanes t - 1 /
@@ -435,25 +440,31 @@ __global__ __launch_bounds__(64 * (kTY / kRW), (sweep2d_waves<T, kRW, QUEUE>()))
 #pragma unroll
         for (int m = 0; m < 3; ++m) xh[i][m] += C4 * phx[hx + m];
     }
-    // seeds: ym1 = the corrected row upwind of the tile, xh1 = the corrected
-    // x-halo values of this wavefront's rows
-    auto seeds = [&](const T (&ym1)[kTX], const T (&xh1)[kRW]) {
+    // seeds of the recurrence (the increments upwind of the tile), in two
+    // halves: the previous iterate's corrected values now (the row upwind
+    // of the tile into sH by the first wavefront, the x halo into dupx),
+    // the new values added once they are read (seeds_new): dr - ym1 and
+    // dxr - xh1, exactly as one subtraction
+    if (w == 0) {
+#pragma unroll
+        for (int j = 0; j < kTX; ++j) sH[lane][j] = -y[1][j];
+    }
+#pragma unroll
+    for (int i = 0; i < kRW; ++i) dupx[i] = -xh[i][1];
+    // (an uncoupled row seed is dropped by a select: across a periodic face
+    // it is the other buffer's value)
+    auto seeds_new = [&]() {
         if (w == 0) {
 #pragma unroll
             for (int j = 0; j < kTX; ++j) {
                 const uint32_t wd = (uint32_t)rl((int)t_w, j);
-                sH[lane][j] = (wd & W_CY) ? dr[j] - ym1[j] : (T)0;
+                sH[lane][j] = (wd & W_CY) ? sH[lane][j] + dr[j] : (T)0;
             }
         }
 #pragma unroll
-        for (int i = 0; i < kRW; ++i) dupx[i] = dxr[i] - xh1[i];
+        for (int i = 0; i < kRW; ++i) dupx[i] += dxr[i];
     };
-    if constexpr (!QUEUE) {
-        T xh1[kRW];
-#pragma unroll
-        for (int i = 0; i < kRW; ++i) xh1[i] = xh[i][1];
-        seeds(y[1], xh1);
-    }
+    if constexpr (!QUEUE) seeds_new();
     // thermalizing wall inflow per axis (upwind face of this octant)
     const T Tw0 = C4 * (T)(sg0 > 0 ? it.wallT[0] : it.wallT[1]);
     const T Tw1 = C4 * (T)(sg1 > 0 ? it.wallT[2] : it.wallT[3]);
@@ -571,33 +582,24 @@ __global__ __launch_bounds__(64 * (kTY / kRW), (sweep2d_waves<T, kRW, QUEUE>()))
             if (it.upy >= 0) queue_wait(queue, it.upy);
         }
         __syncthreads();
-        // (the previous iterate's values the seeds subtract are read again
-        // rather than kept live across the right-hand side)
-        T ym1[kTX], xh1[kRW];
         if (rb == 0) {
-            const char *pdr = rowp(eout, -1), *pym = rowp(ein, -1);
-            const T *xr = row_xp(-1);
+            const char *pdr = rowp(eout, -1);
 #pragma unroll
             for (int j = 0; j < kTX; ++j) {
                 const int jc = j < e0 ? j : e0 - 1;
                 const unsigned o = koff + (unsigned)((sx > 0 ? jc : e0 - 1 - jc) * nk) * (unsigned)sizeof(T);
                 dr[j] = dev_load(reinterpret_cast<const T *>(pdr + o));
-                ym1[j] = *reinterpret_cast<const T *>(pym + o) + C4 * xr[j];
             }
         }
 #pragma unroll
         for (int i = 0; i < kRW; ++i) {
-            const int hx = 24 + 3 * (rb + i);
-            const int c1 = rl(h_c, hx + 1);
-            {
-                const bool ok = c1 >= 0;
-                const char *row =
-                    reinterpret_cast<const char *>((ok ? static_cast<const T *>(eout) : zrow) + (size_t)(ok ? c1 : 0) * nk);
-                dxr[i] = dev_load(reinterpret_cast<const T *>(row + koff));
-            }
-            xh1[i] = ldc(ein, c1) + C4 * phx[hx + 1];
+            const int c1 = rl(h_c, 24 + 3 * (rb + i) + 1);
+            const bool ok = c1 >= 0;
+            const char *row =
+                reinterpret_cast<const char *>((ok ? static_cast<const T *>(eout) : zrow) + (size_t)(ok ? c1 : 0) * nk);
+            dxr[i] = dev_load(reinterpret_cast<const T *>(row + koff));
         }
-        seeds(ym1, xh1);
+        seeds_new();
     }
 
     // ---- upwind recurrence over the tile, handed from wavefront to
@@ -650,17 +652,17 @@ __global__ __launch_bounds__(64 * (kTY / kRW), (sweep2d_waves<T, kRW, QUEUE>()))
                     else __builtin_nontemporal_store(en, &eout[(size_t)(b + sx * j) * nk + k]);
                 }
             }
-            wl[j * 64 + lane] = active ? en : (T)0;
+            wl[j * kWS + lane] = active ? en : (T)0;
         }
-        // lane = 8 cell + part: part sums 8 of the 64 lanes
+        // lane = 8 cell + part: part sums 8 of the 64 lanes (the staged row
+        // has a stride of 65 values: the 64 lanes read 64 distinct banks)
         const int j = lane >> 3, p = lane & 7;
         double acc[kMomN] = {0, 0, 0, 0, 0};
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int l2 = 8 * p + q;
-            const double x = (double)wl[j * 64 + l2];
+            const double x = (double)wl[j * kWS + 8 * p + q];
 #pragma unroll
-            for (int m = 0; m < kMomN; ++m) acc[m] += lc[l2][m] * x;
+            for (int m = 0; m < kMomN; ++m) acc[m] += lc[q][m][p] * x;
         }
 #pragma unroll
         for (int m = 0; m < kMomN; ++m) {
