@@ -618,9 +618,11 @@ __global__ __launch_bounds__(64 * (kTY / kRW), (sweep2d_waves<T, kRW, QUEUE>()))
                 T dl = (w0 & W_CX) ? dupx[i] : (T)0;
 #pragma unroll
                 for (int j = 0; j < kTX; ++j) {
-                    const uint32_t wd = (uint32_t)rl((int)t_w, 8 * (rb + i) + j);
-                    const T rxv = (wd & W_CX) ? cp0 * rdn[i][j] : (T)0;
-                    const T ryv = (wd & W_CY) ? cp1 * rdn[i][j] : (T)0;
+                    // inside the tile the only uncoupled upwind neighbour is
+                    // a pore (or a cell past a ragged edge), whose increment
+                    // is exactly zero (aa = rden = 0): no per-cell coupling
+                    // test; the seeds on the tile's edges are selected
+                    const T rxv = cp0 * rdn[i][j], ryv = cp1 * rdn[i][j];
                     dl = aa[i][j] + ryv * up[j] + rxv * dl;
                     up[j] = dl;
                     dv[i][j] = dl;
