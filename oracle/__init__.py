@@ -12,5 +12,5 @@ Gauss-Legendre routine and marshals arguments.
 from .oracle import (  # noqa: F401
     Case, quadrature, build, lib_path, moments, residual, flux_div, sweep,
     cg, diffusion_T, steady, keff, transient, apply_jac_T, dR_dgamma, sweep_T,
-    BC_THERMAL, BC_SPECULAR, BC_DIFFUSE, BC_PERIODIC, LIM_NONE, LIM_MC, LIM_MINMOD,
+    BC_THERMAL, BC_SPECULAR, BC_DIFFUSE, BC_PERIODIC, BC_INTERFACE, LIM_NONE, LIM_MC, LIM_MINMOD,
 )

@@ -11,7 +11,8 @@
  * deterministic solver for non-gray phonon Boltzmann transport equation"):
  *   - energy-based deviational BTE with RTA closure      Sec. 2.1, eqs. BTE_origin, BTE_get_e0
  *   - boundary conditions (thermalizing, specular,
- *     diffuse, periodic with temperature jump)            Sec. 2.2
+ *     diffuse, periodic with temperature jump,
+ *     interfacial between two materials)                  Sec. 2.2 (i)-(v)
  *   - angular quadrature (computed by the Python side
  *     with numpy's Gauss-Legendre nodes)                  Sec. 3.2, eq. directiondis
  *   - delta-form finite volume discretisation with
@@ -42,7 +43,7 @@
 #define M_PI 3.14159265358979323846
 #endif
 
-enum { BC_THERMAL = 0, BC_SPECULAR = 1, BC_DIFFUSE = 2, BC_PERIODIC = 3 };
+enum { BC_THERMAL = 0, BC_SPECULAR = 1, BC_DIFFUSE = 2, BC_PERIODIC = 3, BC_INTERFACE = 4 };
 enum { LIM_NONE = 0, LIM_MC = 1, LIM_MINMOD = 2 };
 
 typedef struct {
@@ -59,7 +60,7 @@ typedef struct {
     const double *s;        /* [na][3] unit directions */
     const double *w;        /* [na] angular weights (sum omega) */
     int nl;
-    const double *C, *v, *tau;  /* [nl] band heat capacity, speed, relaxation time */
+    const double *C, *v, *tau;  /* [nmat][nl] band heat capacity, speed, relaxation time */
     double Tref;
     const double *gamma;    /* [nc] extra scattering rate (1/s) or NULL */
     const double *P;        /* [nc] volumetric heat (W/m^3) or NULL */
@@ -67,6 +68,12 @@ typedef struct {
     double omega;           /* total angle of the direction set: 4 pi (bulk
                                material, 0 means 4 pi) or 2 pi (two-dimensional
                                material: in-plane directions, Sec. 2.1) */
+    int nmat;               /* materials (0 or 1: a single one) */
+    const int *mat;         /* [nc] material of each cell, or NULL (all 0) */
+    const double *beta;     /* [nmat][nmat][nl]: beta[(a nmat + b) nl + l] is the
+                               fraction of band l's energy flux arriving at an
+                               interface from material a that crosses into b
+                               (Sec. 2.2 (v)); NULL: no transmission */
 } orc_case;
 
 /* ------------------------------------------------------------------ basics */
@@ -84,17 +91,23 @@ static double E(const orc_case *p, const double *e, int c, int al, int l)
     return e[((size_t)c * p->na + al) * p->nl + l];
 }
 
+/* band properties of the material of cell c */
+static int mat_of(const orc_case *p, int c) { return p->mat ? p->mat[c] : 0; }
+static double Cc(const orc_case *p, int c, int l) { return p->C[(size_t)mat_of(p, c) * p->nl + l]; }
+static double vc(const orc_case *p, int c, int l) { return p->v[(size_t)mat_of(p, c) * p->nl + l]; }
+
 /* effective relaxation time in cell c (Matthiessen rule with the extra rate) */
 static double tau_cl(const orc_case *p, int c, int l)
 {
     double g = p->gamma ? p->gamma[c] : 0.0;
-    return 1.0 / (1.0 / p->tau[l] + g);
+    return 1.0 / (1.0 / p->tau[(size_t)mat_of(p, c) * p->nl + l] + g);
 }
 
-static double Ctot(const orc_case *p)
+/* sum_lambda C of the material of cell c */
+static double Ctot(const orc_case *p, int c)
 {
     double s = 0;
-    for (int l = 0; l < p->nl; l++) s += p->C[l];
+    for (int l = 0; l < p->nl; l++) s += Cc(p, c, l);
     return s;
 }
 
@@ -102,13 +115,21 @@ static double Ctot(const orc_case *p)
 static double S_of(const orc_case *p, int c)
 {
     double s = 0;
-    for (int l = 0; l < p->nl; l++) s += p->C[l] / tau_cl(p, c, l);
+    for (int l = 0; l < p->nl; l++) s += Cc(p, c, l) / tau_cl(p, c, l);
     return s;
 }
 
+/* transmittance of band l from the material of cell a into that of cell b */
+static double beta_of(const orc_case *p, int a, int b, int l)
+{
+    if (!p->beta) return 0.0;
+    int nm = p->nmat > 0 ? p->nmat : 1;
+    return p->beta[((size_t)mat_of(p, a) * nm + mat_of(p, b)) * p->nl + l];
+}
+
 typedef struct {
-    int is_cell;   /* 1: neighbouring solid cell; 0: wall */
-    int cell;
+    int is_cell;   /* 1: neighbouring solid cell of the same material; 0: wall */
+    int cell;      /* the neighbour (also the cell across an interface) */
     int wrapped;   /* reached through a periodic face */
     int jump;      /* +1/-1: neighbour value gets +/- C*pdT/Omega */
     int bc;        /* wall type */
@@ -141,14 +162,20 @@ static nbr_t neighbour(const orc_case *p, int c, int a, int side)
         r.is_cell = 0; r.bc = p->pore_bc; r.Tw = p->pore_T; r.wrapped = 0; r.jump = 0;
         return r;
     }
-    r.is_cell = 1; r.cell = j;
+    r.cell = j;
+    if (mat_of(p, j) != mat_of(p, c)) {
+        /* a face between two materials is an interface (Sec. 2.2 (v)) */
+        r.is_cell = 0; r.bc = BC_INTERFACE;
+        return r;
+    }
+    r.is_cell = 1;
     return r;
 }
 
 /* value of a neighbour cell as seen from across the face (periodic jump applied) */
 static double nval(const orc_case *p, const double *e, nbr_t nb, int a, int al, int l)
 {
-    return E(p, e, nb.cell, al, l) + nb.jump * p->C[l] * p->pdT[a] / omega(p);
+    return E(p, e, nb.cell, al, l) + nb.jump * Cc(p, nb.cell, l) * p->pdT[a] / omega(p);
 }
 
 /* ---------------------------------------------------------- reconstruction */
@@ -192,7 +219,7 @@ static double face_val(const orc_case *p, const double *e, int c, int a, int sid
 /* ------------------------------------------------------------------- walls */
 
 typedef struct {
-    int *wid;        /* [nc*6] diffuse wall index or -1 */
+    int *wid;        /* [nc*6] diffuse wall or interface record index or -1 */
     int nw;
     double *din;     /* [nw][nl] incoming diffuse value */
     int *mirror;     /* [3][na] index of the mirror direction w.r.t. axis a */
@@ -224,7 +251,7 @@ static int walls_init(const orc_case *p, walls_t *W)
             int a = f / 2, side = (f & 1) ? 1 : -1;
             if (a >= p->dim || !is_solid(p, c)) continue;
             nbr_t nb = neighbour(p, c, a, side);
-            if (!nb.is_cell && nb.bc == BC_DIFFUSE) W->wid[c * 6 + f] = W->nw++;
+            if (!nb.is_cell && (nb.bc == BC_DIFFUSE || nb.bc == BC_INTERFACE)) W->wid[c * 6 + f] = W->nw++;
         }
     for (int a = 0; a < 3; a++)
         for (int al = 0; al < p->na; al++) {
@@ -240,9 +267,21 @@ static void walls_free(walls_t *W)
     free(W->wid); free(W->din); free(W->mirror);
 }
 
-/* Diffuse wall (Sec. 2.2, eq. diff_bound), discrete normalisation: the
+/* Diffuse wall (Sec. 2.2 (iii), eq. diff_bound), discrete normalisation: the
  * incoming value per band equals the outgoing energy flux through the face
- * divided by the quadrature's incoming |s.n| weight, so the net flux is zero. */
+ * divided by the quadrature's incoming |s.n| weight, so the net flux is zero.
+ *
+ * Interface (Sec. 2.2 (v)) between cell c (material A) and cell j across
+ * the face (material B): the value entering A is the diffuse part of what
+ * comes back, the fraction beta_BA of B's outgoing flux that crosses plus
+ * the fraction 1 - beta_AB of A's own outgoing flux that is reflected:
+ *   e_in,A = [beta_BA (v_B / v_A) F_B + (1 - beta_AB) F_A] / sum_{s.n<0} w |s.n|
+ * with F_X = sum over X's outgoing directions of w |s.n| e_face.  The
+ * fractions act on energy fluxes (v e), hence the ratio v_B / v_A (the
+ * printed equation omits it; with it the flux leaving A through the face
+ * equals the flux entering B for any beta and any state, without it only
+ * for equal speeds).  Face values are the second-order outgoing face
+ * values of each side, as for the diffuse wall. */
 static void walls_update(const orc_case *p, const double *e, walls_t *W)
 {
     int nc = nc_of(p);
@@ -252,14 +291,24 @@ static void walls_update(const orc_case *p, const double *e, walls_t *W)
             int id = W->wid[c * 6 + f];
             if (id < 0) continue;
             int a = f / 2, side = (f & 1) ? 1 : -1;
+            nbr_t nb = neighbour(p, c, a, side);
             for (int l = 0; l < p->nl; l++) {
-                double num = 0, den = 0;
+                double num = 0, den = 0, numb = 0;
                 for (int al = 0; al < p->na; al++) {
                     double sn = p->s[3 * al + a] * side;   /* s . n */
                     if (sn > 0) num += p->w[al] * sn * face_val(p, e, c, a, side, al, l);
-                    else if (sn < 0) den += p->w[al] * (-sn);
+                    else if (sn < 0) {
+                        den += p->w[al] * (-sn);
+                        if (nb.bc == BC_INTERFACE)
+                            numb += p->w[al] * (-sn) * face_val(p, e, nb.cell, a, -side, al, l);
+                    }
                 }
-                W->din[(size_t)id * p->nl + l] = num / den;
+                double din = num / den;
+                if (nb.bc == BC_INTERFACE) {
+                    double bab = beta_of(p, c, nb.cell, l), bba = beta_of(p, nb.cell, c, l);
+                    din = (bba * vc(p, nb.cell, l) / vc(p, c, l) * numb + (1.0 - bab) * num) / den;
+                }
+                W->din[(size_t)id * p->nl + l] = din;
             }
         }
 }
@@ -270,11 +319,12 @@ static double wall_in(const orc_case *p, const double *e, const walls_t *W, nbr_
 {
     switch (nb.bc) {
     case BC_THERMAL:
-        return p->C[l] * (nb.Tw - p->Tref) / omega(p);
+        return Cc(p, c, l) * (nb.Tw - p->Tref) / omega(p);
     case BC_SPECULAR:
         /* s' = s - 2(s.n)n : flip the normal component */
         return face_val(p, e, c, a, side, W->mirror[a * p->na + al], l);
     case BC_DIFFUSE:
+    case BC_INTERFACE:
         return W->din[(size_t)W->wid[c * 6 + 2 * a + (side > 0)] * p->nl + l];
     default:
         return 0.0;
@@ -287,7 +337,7 @@ static double inflow(const orc_case *p, const double *e, const walls_t *W, int c
 {
     nbr_t nb = neighbour(p, c, a, side);
     if (nb.is_cell) {
-        double jumpv = nb.jump * p->C[l] * p->pdT[a] / omega(p);
+        double jumpv = nb.jump * Cc(p, nb.cell, l) * p->pdT[a] / omega(p);
         return face_val(p, e, nb.cell, a, -side, al, l) + jumpv;
     }
     return wall_in(p, e, W, nb, c, a, side, al, l);
@@ -308,7 +358,7 @@ static double flux_div(const orc_case *p, const double *e, const walls_t *W, int
             fp = inflow(p, e, W, c, a, +1, al, l);
             fm = face_val(p, e, c, a, -1, al, l);
         }
-        D += p->v[l] * sa / hx(p, a) * (fp - fm);
+        D += vc(p, c, l) * sa / hx(p, a) * (fp - fm);
     }
     return D;
 }
@@ -330,7 +380,6 @@ static double TL_cell(const orc_case *p, const double *e, int c)
 int orc_moments(const orc_case *p, const double *e, double *T, double *TL, double *q)
 {
     int nc = nc_of(p);
-    double ct = Ctot(p);
 #pragma omp parallel for schedule(static)
     for (int c = 0; c < nc; c++) {
         if (!is_solid(p, c)) {
@@ -344,9 +393,9 @@ int orc_moments(const orc_case *p, const double *e, double *T, double *TL, doubl
             for (int l = 0; l < p->nl; l++) {
                 double x = p->w[al] * E(p, e, c, al, l);
                 se += x;
-                for (int a = 0; a < 3; a++) sq[a] += x * p->v[l] * p->s[3 * al + a];
+                for (int a = 0; a < 3; a++) sq[a] += x * vc(p, c, l) * p->s[3 * al + a];
             }
-        if (T) T[c] = p->Tref + se / ct;
+        if (T) T[c] = p->Tref + se / Ctot(p, c);
         if (TL) TL[c] = p->Tref + TL_cell(p, e, c);
         if (q) for (int a = 0; a < 3; a++) q[3 * c + a] = sq[a];
     }
@@ -359,7 +408,7 @@ static double src_term(const orc_case *p, int c, int l, double scale)
 {
     /* heat split over bands by heat capacity and over Omega (total sum_{alpha,lambda} w Q = P) */
     if (!p->P) return 0.0;
-    return scale * p->P[c] * p->C[l] / (omega(p) * Ctot(p));
+    return scale * p->P[c] * Cc(p, c, l) / (omega(p) * Ctot(p, c));
 }
 
 /* R = -(1/V) sum_f F - (e - e0)/tau + Q, with e0 = C T_L/Omega.
@@ -378,7 +427,7 @@ int orc_residual(const orc_case *p, const double *e, const double *TLdev, double
         for (int al = 0; al < p->na; al++)
             for (int l = 0; l < p->nl; l++) {
                 double t = tau_cl(p, c, l);
-                double e0 = p->C[l] * tl / omega(p);
+                double e0 = Cc(p, c, l) * tl / omega(p);
                 R[base + (size_t)al * p->nl + l] = -flux_div(p, e, &W, c, al, l)
                     - (E(p, e, c, al, l) - e0) / t + src_term(p, c, l, src_scale);
             }
@@ -445,7 +494,7 @@ int orc_sweep(const orc_case *p, const double *e_in, const double *TLdev, double
                         double num = b[((size_t)c * p->na + al) * p->nl + l];
                         for (int a = 0; a < p->dim; a++) {
                             if (s[a] == 0.0) continue;
-                            double ca = p->v[l] * fabs(s[a]) / hx(p, a);
+                            double ca = vc(p, c, l) * fabs(s[a]) / hx(p, a);
                             A += ca;
                             nbr_t up = neighbour(p, c, a, s[a] > 0 ? -1 : +1);
                             if (up.is_cell && !up.wrapped) num += ca * de[up.cell];
@@ -472,11 +521,11 @@ static double hemi_flux(const orc_case *p, int a)
     return h;
 }
 
-/* sum_lambda C v */
-static double sum_Cv(const orc_case *p)
+/* sum_lambda C v of the material of cell c */
+static double sum_Cv(const orc_case *p, int c)
 {
     double g = 0;
-    for (int l = 0; l < p->nl; l++) g += p->C[l] * p->v[l];
+    for (int l = 0; l < p->nl; l++) g += Cc(p, c, l) * vc(p, c, l);
     return g;
 }
 
@@ -492,9 +541,9 @@ static double k_axis(const orc_case *p, int c, int a, int corr)
     for (int al = 0; al < p->na; al++) m += p->w[al] * p->s[3 * al + a] * p->s[3 * al + a];
     m /= omega(p);
     double k = 0;
-    for (int l = 0; l < p->nl; l++) k += p->C[l] * p->v[l] * p->v[l] * tau_cl(p, c, l);
+    for (int l = 0; l < p->nl; l++) k += Cc(p, c, l) * vc(p, c, l) * vc(p, c, l) * tau_cl(p, c, l);
     k *= m;
-    if (corr) k += sum_Cv(p) * hx(p, a) * hemi_flux(p, a) / omega(p);
+    if (corr) k += sum_Cv(p, c) * hx(p, a) * hemi_flux(p, a) / omega(p);
     return k;
 }
 
@@ -505,7 +554,7 @@ static double wall_cond(const orc_case *p, int c, int a, int corr)
 {
     double kd = 2.0 * k_axis(p, c, a, corr) / hx(p, a);
     if (!corr) return kd;
-    double g = 2.0 * sum_Cv(p) * hemi_flux(p, a) / omega(p);
+    double g = 2.0 * sum_Cv(p, c) * hemi_flux(p, a) / omega(p);
     return 1.0 / (1.0 / kd + 1.0 / g);
 }
 
@@ -526,6 +575,27 @@ static double face_k(const orc_case *p, int c, int j, int a, int corr)
     return 2.0 * ki * kj / (ki + kj);
 }
 
+/* Conductance per unit area across an interface between cell c and cell j
+ * on axis a, for the diffusion operators only (initial guess and
+ * correction: they change the path to the fixed point, not the fixed
+ * point): the two half cells in series with the interface's own
+ * conductance G = (G_AB + G_BA) / 2, G_XY = sum_lambda beta_XY C_X v_X H_a
+ * / Omega (the flux crossing per kelvin of difference between the two
+ * sides' emitted equilibria).  Returned times h, the form face_k has. */
+static double iface_k(const orc_case *p, int c, int j, int a, int corr)
+{
+    double h = hx(p, a), H = hemi_flux(p, a);
+    double gab = 0, gba = 0;
+    for (int l = 0; l < p->nl; l++) {
+        gab += beta_of(p, c, j, l) * Cc(p, c, l) * vc(p, c, l);
+        gba += beta_of(p, j, c, l) * Cc(p, j, l) * vc(p, j, l);
+    }
+    double G = 0.5 * (gab + gba) * H / omega(p);
+    if (!(G > 0)) return 0.0;
+    double r = 0.5 * h / k_axis(p, c, a, corr) + 1.0 / G + 0.5 * h / k_axis(p, j, a, corr);
+    return h / r;
+}
+
 /* y = L x for the finite-volume operator -div(k grad x) per unit volume with
  * harmonic-mean face conductivity; thermalizing walls through wall_cond
  * (homogeneous here), other walls zero flux, periodic faces wrap (jumps enter
@@ -542,6 +612,7 @@ static void diff_apply(const orc_case *p, int corr, const double *x, double *y)
             for (int side = -1; side <= 1; side += 2) {
                 nbr_t nb = neighbour(p, c, a, side);
                 if (nb.is_cell) acc += face_k(p, c, nb.cell, a, corr) / (h * h) * (x[c] - x[nb.cell]);
+                else if (nb.bc == BC_INTERFACE) acc += iface_k(p, c, nb.cell, a, corr) / (h * h) * (x[c] - x[nb.cell]);
                 else if (nb.bc == BC_THERMAL) acc += wall_cond(p, c, a, corr) / h * x[c];
             }
         }
@@ -557,6 +628,7 @@ static double diff_diag(const orc_case *p, int corr, int c)
         for (int side = -1; side <= 1; side += 2) {
             nbr_t nb = neighbour(p, c, a, side);
             if (nb.is_cell) d += face_k(p, c, nb.cell, a, corr) / (h * h);
+            else if (nb.bc == BC_INTERFACE) d += iface_k(p, c, nb.cell, a, corr) / (h * h);
             else if (nb.bc == BC_THERMAL) d += wall_cond(p, c, a, corr) / h;
         }
     }
@@ -690,7 +762,7 @@ static void set_equilibrium(const orc_case *p, const double *Tdev, double *e)
     for (int c = 0; c < nc; c++)
         for (int al = 0; al < p->na; al++)
             for (int l = 0; l < p->nl; l++)
-                e[((size_t)c * p->na + al) * p->nl + l] = is_solid(p, c) ? p->C[l] * Tdev[c] / omega(p) : 0.0;
+                e[((size_t)c * p->na + al) * p->nl + l] = is_solid(p, c) ? Cc(p, c, l) * Tdev[c] / omega(p) : 0.0;
 }
 
 /* Steady solve (Algorithm 1).
@@ -740,7 +812,7 @@ int orc_steady(const orc_case *p, int scheme, double tol_T, double tol_q, int ma
             /* the correction moves the isotropic part of the whole distribution */
             for (int c = 0; c < nc; c++)
                     for (size_t k = 0; k < nal(p); k++)
-                        if (is_solid(p, c)) e1[(size_t)c * nal(p) + k] += p->C[k % p->nl] * dl[c] / omega(p);
+                        if (is_solid(p, c)) e1[(size_t)c * nal(p) + k] += Cc(p, c, (int)(k % p->nl)) * dl[c] / omega(p);
         } else {
             memcpy(TL, TLk, sizeof(double) * nc);
         }
@@ -758,7 +830,7 @@ int orc_steady(const orc_case *p, int scheme, double tol_T, double tol_q, int ma
         m /= ns;
         for (int c = 0; c < nc; c++)
             for (size_t k = 0; k < nal(p); k++)
-                if (is_solid(p, c)) e[(size_t)c * nal(p) + k] -= p->C[k % p->nl] * m / omega(p);
+                if (is_solid(p, c)) e[(size_t)c * nal(p) + k] -= Cc(p, c, (int)(k % p->nl)) * m / omega(p);
     }
     free(e1); free(TL); free(TLk); free(T0); free(T1); free(q0); free(q1); free(r); free(dl);
     return 0;
@@ -861,6 +933,7 @@ static void scatter_form(double *y, lform f, double x)
 int orc_apply_jac_T(const orc_case *p, const double *x, double *y)
 {
     if (p->limiter != LIM_NONE) return -3;
+    if (p->nmat > 1) return -4;   /* the adjoint covers one material */
     int nc = nc_of(p);
     size_t N = (size_t)nc * nal(p);
     walls_t W;
@@ -921,8 +994,9 @@ int orc_apply_jac_T(const orc_case *p, const double *x, double *y)
  *   dT_L/dgamma_c = Ctot (T_c - T_L,c)/S_c  (both as deviations). */
 int orc_dR_dgamma(const orc_case *p, const double *e, const double *psi, double *out)
 {
+    if (p->nmat > 1) return -4;   /* the adjoint covers one material */
     int nc = nc_of(p);
-    double ct = Ctot(p);
+    double ct = Ctot(p, 0);
 #pragma omp parallel for schedule(static)
     for (int c = 0; c < nc; c++) {
         if (!is_solid(p, c)) { out[c] = 0; continue; }
@@ -948,6 +1022,7 @@ int orc_dR_dgamma(const orc_case *p, const double *e, const double *psi, double 
  * the oracle's adjoint Krylov solve */
 int orc_sweep_T(const orc_case *p, const double *rhs, double *z)
 {
+    if (p->nmat > 1) return -4;   /* the adjoint covers one material */
     int nc = nc_of(p);
     int nlane = (int)nal(p);
 #pragma omp parallel

@@ -27,7 +27,7 @@ import subprocess
 
 import numpy as np
 
-BC_THERMAL, BC_SPECULAR, BC_DIFFUSE, BC_PERIODIC = 0, 1, 2, 3
+BC_THERMAL, BC_SPECULAR, BC_DIFFUSE, BC_PERIODIC, BC_INTERFACE = 0, 1, 2, 3, 4
 LIM_NONE, LIM_MC, LIM_MINMOD = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -95,6 +95,7 @@ class _CCase(C.Structure):
         ("tau", C.POINTER(C.c_double)), ("Tref", C.c_double),
         ("gamma", C.POINTER(C.c_double)), ("P", C.POINTER(C.c_double)),
         ("limiter", C.c_int), ("omega", C.c_double),
+        ("nmat", C.c_int), ("mat", C.POINTER(C.c_int)), ("beta", C.POINTER(C.c_double)),
     ]
 
 
@@ -162,13 +163,29 @@ class Case:
     """A problem instance: geometry + bands + quadrature + fields.
 
     geometry: dict(dim, n(3), len(3), solid (uint8 [nc]) or None, bc(6),
-              bcT(6) absolute K, pdT(3), pore_bc)
+              bcT(6) absolute K, pdT(3), pore_bc, optional mat (int [nc]):
+              the material of each cell)
     material: dict(C, v, tau arrays, n_theta, n_phi, Tref, optional
-              material_dim: 3 (default) or 2)
+              material_dim: 3 (default) or 2), or a list of such dicts (one
+              per material: same bands, directions and Tref)
+    beta:     with several materials, [nmat][nmat][nl] transmittances of the
+              interfaces between them (Sec. 2.2 (v)): beta[a][b][l] is the
+              fraction of band l's energy flux from material a crossing into b
     """
 
-    def __init__(self, geometry, material, P=None, gamma=None, limiter=LIM_NONE):
-        g, m = geometry, material
+    def __init__(self, geometry, material, P=None, gamma=None, limiter=LIM_NONE, beta=None):
+        g = geometry
+        mats = list(material) if isinstance(material, (list, tuple)) else [material]
+        m = mats[0]
+        for mm in mats[1:]:
+            for key in ("n_theta", "n_phi", "Tref", "material_dim"):
+                if mm.get(key) != m.get(key):
+                    raise ValueError("materials differ in %s" % key)
+            if len(mm["C"]) != len(m["C"]):
+                raise ValueError("materials differ in their number of bands")
+        self.nmat = len(mats)
+        self.mat = None if g.get("mat") is None else np.ascontiguousarray(g["mat"], dtype=np.int32)
+        self.beta = None if beta is None else np.ascontiguousarray(beta, dtype=np.float64).reshape(-1)
         self.dim = int(g["dim"])
         self.n = [int(x) for x in g["n"]]
         self.len = [float(x) for x in g["len"]]
@@ -177,11 +194,11 @@ class Case:
         self.material_dim = int(m.get("material_dim", 3))
         self.omega = 2.0 * np.pi if self.material_dim == 2 else 4.0 * np.pi
         self.s, self.w = quadrature(self.dim, int(m["n_theta"]), int(m.get("n_phi", 1)), self.material_dim)
-        self.C = np.ascontiguousarray(m["C"], dtype=np.float64)
-        self.v = np.ascontiguousarray(m["v"], dtype=np.float64)
-        self.tau = np.ascontiguousarray(m["tau"], dtype=np.float64)
+        self.C = np.ascontiguousarray(np.concatenate([np.asarray(x["C"], dtype=np.float64) for x in mats]))
+        self.v = np.ascontiguousarray(np.concatenate([np.asarray(x["v"], dtype=np.float64) for x in mats]))
+        self.tau = np.ascontiguousarray(np.concatenate([np.asarray(x["tau"], dtype=np.float64) for x in mats]))
         self.Tref = float(m["Tref"])
-        self.na, self.nl = len(self.w), len(self.C)
+        self.na, self.nl = len(self.w), len(m["C"])
         self.P = None if P is None else np.ascontiguousarray(P, dtype=np.float64)
         self.gamma = None if gamma is None else np.ascontiguousarray(gamma, dtype=np.float64)
         self.limiter = int(limiter)
@@ -210,6 +227,9 @@ class Case:
         c.P = _dp(self.P)
         c.limiter = self.limiter
         c.omega = self.omega
+        c.nmat = self.nmat
+        c.mat = self.mat.ctypes.data_as(C.POINTER(C.c_int)) if self.mat is not None else None
+        c.beta = _dp(self.beta)
         return c
 
     def with_(self, **kw):
