@@ -62,7 +62,8 @@ typedef enum {
 
 typedef enum { BTE_F32 = 0, BTE_F64 = 1 } bte_precision;          /* storage of e      */
 typedef enum { BTE_BC_THERMAL = 0, BTE_BC_SPECULAR = 1,
-               BTE_BC_DIFFUSE = 2, BTE_BC_PERIODIC = 3 } bte_bc;  /* Sec. 2.2          */
+               BTE_BC_DIFFUSE = 2, BTE_BC_PERIODIC = 3,
+               BTE_BC_INTERFACE = 4 } bte_bc;                     /* Sec. 2.2 (i)-(v)  */
 typedef enum { BTE_SEQUENTIAL = 0, BTE_SYNTHETIC = 1 } bte_scheme; /* Sec. 3.4          */
 typedef enum { BTE_LIM_NONE = 0, BTE_LIM_MC = 1, BTE_LIM_MINMOD = 2 } bte_limiter;
 typedef enum { BTE_OBJ_KEFF_X = 0 } bte_objective;
@@ -151,6 +152,52 @@ typedef struct bte_problem bte_problem;
  * handle; bind a workspace before any device call. */
 bte_status bte_setup(const bte_geometry *geo, int n_geo, const bte_material *mat,
                      const bte_control *ctl, bte_problem **out);
+
+/* An interface between two geometries of different materials (Sec. 2.2 (v)
+ * and the Ge-Si verification case of Sec. 3.6): face face_a of geometry
+ * geo_a (0..5: -x, +x, -y, +y, -z, +z) touches face face_b of geometry geo_b,
+ * the opposite face of the same axis; both faces are set to
+ * BTE_BC_INTERFACE in their geometries and hold the same cells along the
+ * other axes (same n and len there) with the same cell size along the
+ * axis too.  Cell i of one face touches cell i of the other (the other
+ * axes' indices equal).  beta_ab[l] is the fraction of band l's energy flux
+ * arriving at the interface from geo_a that crosses into geo_b, beta_ba[l]
+ * the reverse (host arrays of n_bands values in [0, 1], copied).  The
+ * value entering each side is diffuse: the crossing fraction of the other
+ * side's outgoing flux plus the reflected fraction (1 - beta) of its own,
+ * over the quadrature's incoming weight (the diffuse wall's normalisation),
+ * the fractions applied to energy fluxes (v e): energy is conserved across
+ * the face for any beta.  A solid cell facing a pore across the interface
+ * sees its own geometry's pore_bc. */
+typedef struct {
+    int geo_a, face_a;
+    int geo_b, face_b;
+    const double *beta_ab;   /* host [n_bands] */
+    const double *beta_ba;   /* host [n_bands] */
+} bte_interface;
+
+/* bte_setup with several materials: geometry g is made of material
+ * mats[geo_mat[g]] (geo_mat NULL: all of mats[0]); n_ifc interfaces join
+ * geometries of different (or equal) materials.  The materials share
+ * n_bands, n_theta, n_phi, T_ref and material_dim (band l of one is
+ * matched with band l of the other across an interface); their C, v and
+ * tau differ.  Supported: steady solves (both schemes, every limiter),
+ * bte_moments, bte_residual and bte_keff of 1D and 2D geometries; every
+ * geometry joined by an interface needs a thermalizing wall (the synthetic
+ * correction and the initial guess couple the geometries across the
+ * interfaces through the half cells in series with the interface
+ * conductance sum_l beta C v H / Omega, averaged over the two directions).
+ * BTE_ERR_UNSUPPORTED for 3D geometries with more than one material or an
+ * interface, and, on such a problem, for transient steps and both
+ * adjoints.  BTE_ERR_ARG for an invalid interface (face not set to
+ * BTE_BC_INTERFACE or used twice, faces that do not match, beta outside
+ * [0, 1]), a BTE_BC_INTERFACE face without an interface, or materials that
+ * differ in what they must share; otherwise as bte_setup.  bte_setup(geo,
+ * n, mat, ctl, out) is bte_setup_multi(geo, n, mat, 1, NULL, NULL, 0, ctl,
+ * out). */
+bte_status bte_setup_multi(const bte_geometry *geo, int n_geo, const bte_material *mats, int n_mat,
+                           const int *geo_mat, const bte_interface *ifc, int n_ifc,
+                           const bte_control *ctl, bte_problem **out);
 
 /* Replace the control of a handle (scheme, limiter, tolerances, iteration
  * caps, dt).  The precision must stay the same (it fixes the workspace). */

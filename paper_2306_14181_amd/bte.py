@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libbte.so")
 BTE_OK, BTE_ERR_ARG, BTE_ERR_UNSUPPORTED, BTE_ERR_HIP = 0, 1, 2, 3
 BTE_ERR_NOT_CONVERGED, BTE_ERR_NONFINITE, BTE_ERR_CFL, BTE_ERR_STATE = 4, 5, 6, 7
 F32, F64 = 0, 1
-BC_THERMAL, BC_SPECULAR, BC_DIFFUSE, BC_PERIODIC = 0, 1, 2, 3
+BC_THERMAL, BC_SPECULAR, BC_DIFFUSE, BC_PERIODIC, BC_INTERFACE = 0, 1, 2, 3, 4
 SEQUENTIAL, SYNTHETIC = 0, 1
 LIM_NONE, LIM_MC, LIM_MINMOD = 0, 1, 2
 OBJ_KEFF_X = 0
@@ -26,7 +26,7 @@ TUNE_SWEEP, TUNE_TRANSIENT, TUNE_SWEEP_ONE_LAUNCH = 0, 1, 2
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "ERR_NOT_CONVERGED",
                 5: "ERR_NONFINITE", 6: "ERR_CFL", 7: "ERR_STATE"}
 
-EXPORTS = ["bte_setup", "bte_set_control", "bte_workspace_bytes", "bte_num_unknowns", "bte_num_cells", "bte_num_directions",
+EXPORTS = ["bte_setup", "bte_setup_multi", "bte_set_control", "bte_workspace_bytes", "bte_num_unknowns", "bte_num_cells", "bte_num_directions",
            "bte_bind", "bte_set_fields", "bte_moments", "bte_moments_static", "bte_residual", "bte_transient_step",
            "bte_steady_solve", "bte_keff", "bte_adjoint", "bte_transient_adjoint", "bte_transient_adjoint_bytes",
            "bte_set_timing", "bte_set_graphs", "bte_set_persistent", "bte_tile_candidates", "bte_set_tiles",
@@ -51,6 +51,11 @@ class Material(C.Structure):
     _fields_ = [("n_bands", C.c_int), ("C", C.POINTER(C.c_double)), ("v", C.POINTER(C.c_double)),
                 ("tau", C.POINTER(C.c_double)), ("n_theta", C.c_int), ("n_phi", C.c_int),
                 ("T_ref", C.c_double), ("material_dim", C.c_int)]
+
+
+class Interface(C.Structure):
+    _fields_ = [("geo_a", C.c_int), ("face_a", C.c_int), ("geo_b", C.c_int), ("face_b", C.c_int),
+                ("beta_ab", C.POINTER(C.c_double)), ("beta_ba", C.POINTER(C.c_double))]
 
 
 class Control(C.Structure):
@@ -88,6 +93,8 @@ def load():
     sig = {
         "bte_setup": ([C.POINTER(Geometry), C.c_int, C.POINTER(Material), C.POINTER(Control),
                        C.POINTER(vp)], st),
+        "bte_setup_multi": ([C.POINTER(Geometry), C.c_int, C.POINTER(Material), C.c_int, C.POINTER(C.c_int),
+                             C.POINTER(Interface), C.c_int, C.POINTER(Control), C.POINTER(vp)], st),
         "bte_set_control": ([vp, C.POINTER(Control)], st),
         "bte_workspace_bytes": ([vp], C.c_size_t),
         "bte_num_unknowns": ([vp], C.c_size_t),
@@ -223,12 +230,15 @@ class Problem:
     """One problem (a geometry or a batch of geometries) bound to a device workspace.
 
     geometries: dict or list of dicts (dim, n, len, solid, bc, bcT, pdT, pore_bc)
-    material:   dict(C, v, tau, n_theta, n_phi, Tref)
+    material:   dict(C, v, tau, n_theta, n_phi, Tref), or a list of such dicts
+                (several materials: geo_mat[g] is the material of geometry g)
     control:    dict(precision, scheme, limiter, residual_temp, residual_flux,
                      max_iter, cg_rtol, cg_max_iter, dt, adjoint)
+    interfaces: list of dict(geo_a, face_a, geo_b, face_b, beta_ab, beta_ba)
+                (bte_setup_multi)
     """
 
-    def __init__(self, geometries, material, control, device="cuda"):
+    def __init__(self, geometries, material, control, device="cuda", geo_mat=None, interfaces=None):
         import numpy as np
         lib = load()
         if isinstance(geometries, dict):
@@ -240,20 +250,42 @@ class Problem:
             structs.append(s)
             self._keep.append(keep)
         garr = (Geometry * len(structs))(*structs)
-        self._bands = [np.ascontiguousarray(material[k], dtype=np.float64) for k in ("C", "v", "tau")]
-        m = Material()
-        m.n_bands = len(self._bands[0])
-        m.C, m.v, m.tau = [b.ctypes.data_as(C.POINTER(C.c_double)) for b in self._bands]
-        m.n_theta = int(material["n_theta"])
-        m.n_phi = int(material.get("n_phi", 1))
-        m.T_ref = float(material["Tref"])
-        m.material_dim = int(material.get("material_dim", 3))
+        mats = list(material) if isinstance(material, (list, tuple)) else [material]
+        self._bands = []
+        marr = (Material * len(mats))()
+        for i, mt in enumerate(mats):
+            bands = [np.ascontiguousarray(mt[k], dtype=np.float64) for k in ("C", "v", "tau")]
+            self._bands.append(bands)
+            m = marr[i]
+            m.n_bands = len(bands[0])
+            m.C, m.v, m.tau = [b.ctypes.data_as(C.POINTER(C.c_double)) for b in bands]
+            m.n_theta = int(mt["n_theta"])
+            m.n_phi = int(mt.get("n_phi", 1))
+            m.T_ref = float(mt["Tref"])
+            m.material_dim = int(mt.get("material_dim", 3))
+        m = marr[0]
+        gm = None
+        if geo_mat is not None:
+            self._geo_mat = np.ascontiguousarray(geo_mat, dtype=np.int32)
+            gm = self._geo_mat.ctypes.data_as(C.POINTER(C.c_int))
+        interfaces = interfaces or []
+        iarr = (Interface * max(len(interfaces), 1))()
+        self._ibeta = []
+        for i, q in enumerate(interfaces):
+            ab = np.ascontiguousarray(q["beta_ab"], dtype=np.float64)
+            ba = np.ascontiguousarray(q["beta_ba"], dtype=np.float64)
+            self._ibeta += [ab, ba]
+            iarr[i].geo_a, iarr[i].face_a = int(q["geo_a"]), int(q["face_a"])
+            iarr[i].geo_b, iarr[i].face_b = int(q["geo_b"]), int(q["face_b"])
+            iarr[i].beta_ab = ab.ctypes.data_as(C.POINTER(C.c_double))
+            iarr[i].beta_ba = ba.ctypes.data_as(C.POINTER(C.c_double))
         c = _control_struct(control)
         self.control = dict(control)
         self.precision = c.precision
         self.dtype = torch.float64 if c.precision == F64 else torch.float32
         h = C.c_void_p()
-        st = lib.bte_setup(garr, len(structs), C.byref(m), C.byref(c), C.byref(h))
+        st = lib.bte_setup_multi(garr, len(structs), marr, len(mats), gm, iarr, len(interfaces), C.byref(c),
+                                 C.byref(h))
         self._h = h
         if st != BTE_OK:
             msg = lib.bte_last_error(h).decode() if h else "setup failed"

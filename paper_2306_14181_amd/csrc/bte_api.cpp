@@ -147,7 +147,17 @@ struct bte_problem {
     std::vector<Film> films;
     std::vector<uint32_t> code;
     std::vector<int> nb, fid, dbase, wrec, mirror;
-    std::vector<double> s, w, C4, v, itau;
+    std::vector<double> s, w, C4, v, itau;   // band tables, [nmat][nl]
+    int nmat = 1, nifc = 0;
+    std::vector<double> Ctot_m;    // sum_lambda C per material
+    std::vector<int> wpart;        // per wall record: the cell across an interface, -1 for a diffuse wall
+    std::vector<double> wbeta;     // per wall record: [2][nl] transmittance into the cell, out of it
+    struct IfcEnd {
+        int film = -1, face = -1, ifc = -1, is_a = 0;   // the facing geometry and face
+    };
+    std::vector<IfcEnd> ifc_end;   // [nfilm * 6]
+    std::vector<bte_interface> ifcs;
+    std::vector<std::vector<double>> ifc_beta;   // per interface: [2][nl] beta_ab, beta_ba
     double wden[6] = {0, 0, 0, 0, 0, 0};
     double M[3] = {0, 0, 0}, H[3] = {0, 0, 0};
     int nw = 0;
@@ -259,8 +269,11 @@ bte_status build_geometry(bte_problem *p, const bte_geometry *geo, int n_geo)
         for (int a = 0; a < g.dim; ++a) {
             bool p0 = g.bc[2 * a] == BTE_BC_PERIODIC, p1 = g.bc[2 * a + 1] == BTE_BC_PERIODIC;
             if (p0 != p1) FAIL(p, BTE_ERR_ARG, "geometry %d: periodic faces of axis %d must come in pairs", f, a);
-            for (int s = 0; s < 2; ++s)
-                if (g.bc[2 * a + s] < 0 || g.bc[2 * a + s] > 3) FAIL(p, BTE_ERR_ARG, "geometry %d: bad bc", f);
+            for (int s = 0; s < 2; ++s) {
+                if (g.bc[2 * a + s] < 0 || g.bc[2 * a + s] > 4) FAIL(p, BTE_ERR_ARG, "geometry %d: bad bc", f);
+                if (g.bc[2 * a + s] == BTE_BC_INTERFACE && p->ifc_end[6 * f + 2 * a + s].film < 0)
+                    FAIL(p, BTE_ERR_ARG, "geometry %d: face %d is an interface of no bte_interface", f, 2 * a + s);
+            }
             if (!p0 && g.periodic_dT[a] != 0.0)
                 FAIL(p, BTE_ERR_ARG, "geometry %d: periodic_dT on a non-periodic axis", f);
         }
@@ -297,10 +310,27 @@ bte_status build_geometry(bte_problem *p, const bte_geometry *geo, int n_geo)
                     int fidx = face_of(a, side);
                     bool wraps = false, outer = false;
                     int kind = -1;
+                    int partner = -1;
                     if (k < 0 || k >= fm.n[a]) {
                         if (g.bc[fidx] == BTE_BC_PERIODIC) {
                             k = (k + fm.n[a]) % fm.n[a];
                             wraps = true;
+                        } else if (g.bc[fidx] == BTE_BC_INTERFACE) {
+                            // the facing cell of the other geometry (same
+                            // indices along the other axes); a pore there is
+                            // a pore wall of this geometry
+                            const bte_problem::IfcEnd &ie = p->ifc_end[6 * f + fidx];
+                            const Film &fo = p->films[ie.film];
+                            int jj[3] = {idx[0], idx[1], idx[2]};
+                            jj[a] = side > 0 ? 0 : fo.n[a] - 1;
+                            const int li = jj[0] + fo.n[0] * (jj[1] + fo.n[1] * jj[2]);
+                            const uint8_t *so = geo[ie.film].solid;
+                            if (!so || so[li]) {
+                                kind = kWallInterface;
+                                partner = fo.cell0 + li;
+                            } else {
+                                kind = g.pore_bc;
+                            }
                         } else {
                             kind = g.bc[fidx];
                             outer = true;
@@ -326,10 +356,14 @@ bte_status build_geometry(bte_problem *p, const bte_geometry *geo, int n_geo)
                         bits |= (uint32_t)kind << (side > 0 ? 6 : 4);
                         if (outer) code |= 1u << ((side > 0 ? 28 : 25) + a);
                         if (kind == BTE_BC_THERMAL) thermal = 1;
-                        if (kind == BTE_BC_DIFFUSE) {
+                        if (kind == BTE_BC_DIFFUSE || kind == kWallInterface) {
+                            // one inflow record per diffuse or interface face
                             if (p->dbase[c] < 0) p->dbase[c] = nw;
                             p->wrec.push_back(c);
                             p->wrec.push_back(fidx);
+                            p->wpart.push_back(partner);
+                            // the diffusion operators couple across the interface
+                            if (partner >= 0) p->nb[(size_t)fidx * nc + c] = partner;
                             ++nw;
                         }
                     }
@@ -657,6 +691,8 @@ void build_schedule(bte_problem *p)
             q.ih1 = fm.ih[1];
             for (int f = 0; f < 4; ++f) q.wallT[f] = fm.wallT[f];
             q.upx = q.upy = -1;
+            q.moff = fm.moff;
+            q.Ctot = fm.Ctot;
             p->items2.push_back(q);
         }
         // Items of the x- and y-upwind tiles (same geometry, octant and
@@ -695,6 +731,51 @@ void build_schedule(bte_problem *p)
     }
 }
 
+// Per geometry: the wall emission conductance of the correction operator
+// (2 sum C v H_a / Omega of its material) and the interface conductance of
+// each interface face (sum_lambda beta C v H_a / Omega, the mean of the two
+// directions); per wall record the transmittances into and out of its cell
+// (zero for a diffuse wall).
+void finish_materials(bte_problem *p)
+{
+    std::vector<double> cv(p->nmat, 0.0);
+    for (int m = 0; m < p->nmat; ++m)
+        for (int l = 0; l < p->nl; ++l) {
+            const size_t i = (size_t)m * p->nl + l;
+            cv[m] += p->C4[i] * p->omega * p->v[i];
+        }
+    for (int f = 0; f < p->nfilm; ++f) {
+        Film &fm = p->films[f];
+        for (int a = 0; a < 3; ++a) fm.Hm[a] = 2.0 * cv[fm.mat] * p->H[a] / p->omega;
+        for (int q = 0; q < 6; ++q) {
+            fm.gif[q] = 0.0;
+            const bte_problem::IfcEnd &ie = p->ifc_end[6 * f + q];
+            if (ie.film < 0) continue;
+            const Film &fo = p->films[ie.film];
+            const std::vector<double> &bt = p->ifc_beta[ie.ifc];
+            double g = 0.0;
+            for (int l = 0; l < p->nl; ++l) {
+                const double b_out = ie.is_a ? bt[l] : bt[p->nl + l], b_in = ie.is_a ? bt[p->nl + l] : bt[l];
+                const size_t i = (size_t)fm.moff + l, o = (size_t)fo.moff + l;
+                g += b_out * p->C4[i] * p->omega * p->v[i] + b_in * p->C4[o] * p->omega * p->v[o];
+            }
+            fm.gif[q] = 0.5 * g * p->H[q >> 1] / p->omega;
+        }
+    }
+    p->wbeta.assign(2 * (size_t)p->nl * std::max(p->nw, 1), 0.0);
+    for (int r = 0; r < p->nw; ++r) {
+        if (p->wpart[r] < 0) continue;
+        const int c = p->wrec[2 * r], fidx = p->wrec[2 * r + 1];
+        const bte_problem::IfcEnd &ie = p->ifc_end[6 * p->fid[c] + fidx];
+        const std::vector<double> &bt = p->ifc_beta[ie.ifc];
+        for (int l = 0; l < p->nl; ++l) {
+            p->wbeta[2 * (size_t)r * p->nl + l] = ie.is_a ? bt[p->nl + l] : bt[l];          // into the cell
+            p->wbeta[(2 * (size_t)r + 1) * p->nl + l] = ie.is_a ? bt[l] : bt[p->nl + l];    // out of it
+        }
+    }
+    if (p->wpart.empty()) p->wpart.assign(1, -1);
+}
+
 void plan_workspace(bte_problem *p)
 {
     p->layout.clear();
@@ -707,9 +788,11 @@ void plan_workspace(bte_problem *p)
     add("s", 8 * p->s.size());
     add("w", 8 * p->w.size());
     add("mirror", 4 * p->mirror.size());
-    add("C4", 8 * p->nl);
-    add("v", 8 * p->nl);
-    add("itau", 8 * p->nl);
+    add("C4", 8 * p->C4.size());
+    add("v", 8 * p->v.size());
+    add("itau", 8 * p->itau.size());
+    add("wpart", 4 * p->wpart.size());
+    add("wbeta", 8 * p->wbeta.size());
     add("film", sizeof(Film) * p->nfilm);
     add("code", 4 * nc);
     add("nb", 4 * 6 * nc);
@@ -774,6 +857,13 @@ extern "C" {
 bte_status bte_setup(const bte_geometry *geo, int n_geo, const bte_material *mat, const bte_control *ctl,
                      bte_problem **out)
 {
+    return bte_setup_multi(geo, n_geo, mat, 1, nullptr, nullptr, 0, ctl, out);
+}
+
+bte_status bte_setup_multi(const bte_geometry *geo, int n_geo, const bte_material *mats, int n_mat,
+                           const int *geo_mat, const bte_interface *ifc, int n_ifc, const bte_control *ctl,
+                           bte_problem **out)
+{
     if (!out) return BTE_ERR_ARG;
     *out = nullptr;
     bte_problem *p = new (std::nothrow) bte_problem();
@@ -784,17 +874,35 @@ bte_status bte_setup(const bte_geometry *geo, int n_geo, const bte_material *mat
         *out = p;
         return s;
     };
-    if (!geo || n_geo < 1 || !mat || !ctl) {
-        p->err = "null argument or n_geo < 1";
+    if (!geo || n_geo < 1 || !mats || n_mat < 1 || !ctl || n_ifc < 0 || (n_ifc > 0 && !ifc)) {
+        p->err = "null argument, n_geo < 1, n_mat < 1 or n_ifc < 0";
         return bail(BTE_ERR_ARG);
     }
+    const bte_material *mat = &mats[0];
     if (geo[0].dim < 1 || geo[0].dim > 3) {
         p->err = "dim must be 1, 2 or 3";
         return bail(BTE_ERR_ARG);
     }
-    if (mat->n_bands < 1 || mat->n_bands > 256 || !mat->C || !mat->v || !mat->tau) {
-        p->err = "n_bands must be in [1, 256] with C, v, tau given";
-        return bail(BTE_ERR_ARG);
+    for (int m = 0; m < n_mat; ++m) {
+        const bte_material &mm = mats[m];
+        if (mm.n_bands < 1 || mm.n_bands > 256 || !mm.C || !mm.v || !mm.tau) {
+            p->err = "n_bands must be in [1, 256] with C, v, tau given";
+            return bail(BTE_ERR_ARG);
+        }
+        if (mm.n_bands != mat->n_bands || mm.n_theta != mat->n_theta || mm.n_phi != mat->n_phi ||
+            mm.T_ref != mat->T_ref || mm.material_dim != mat->material_dim) {
+            p->err = "materials must share n_bands, n_theta, n_phi, T_ref and material_dim";
+            return bail(BTE_ERR_ARG);
+        }
+    }
+    for (int f = 0; f < n_geo; ++f)
+        if (geo_mat && (geo_mat[f] < 0 || geo_mat[f] >= n_mat)) {
+            p->err = "geo_mat out of range";
+            return bail(BTE_ERR_ARG);
+        }
+    if (geo[0].dim == 3 && (n_mat > 1 || n_ifc > 0)) {
+        p->err = "several materials or interfaces: 1D and 2D geometries only";
+        return bail(BTE_ERR_UNSUPPORTED);
     }
     p->ctl = *ctl;
     if (p->ctl.precision != BTE_F32 && p->ctl.precision != BTE_F64) {
@@ -824,24 +932,90 @@ bte_status bte_setup(const bte_geometry *geo, int n_geo, const bte_material *mat
     p->omega = planar ? 2.0 * M_PI : 4.0 * M_PI;
     p->Tref = mat->T_ref;
     p->nl = mat->n_bands;
-    p->C4.resize(p->nl);
-    p->v.resize(p->nl);
-    p->itau.resize(p->nl);
-    p->Ctot = 0;
-    for (int l = 0; l < p->nl; ++l) {
-        if (!(mat->C[l] > 0) || !(mat->v[l] >= 0) || !(mat->tau[l] > 0)) {
-            p->err = "band properties must satisfy C > 0, v >= 0, tau > 0";
+    p->nmat = n_mat;
+    const size_t nml = (size_t)n_mat * p->nl;
+    p->C4.resize(nml);
+    p->v.resize(nml);
+    p->itau.resize(nml);
+    p->Ctot_m.assign(n_mat, 0.0);
+    for (int m = 0; m < n_mat; ++m)
+        for (int l = 0; l < p->nl; ++l) {
+            const bte_material &mm = mats[m];
+            if (!(mm.C[l] > 0) || !(mm.v[l] >= 0) || !(mm.tau[l] > 0)) {
+                p->err = "band properties must satisfy C > 0, v >= 0, tau > 0";
+                return bail(BTE_ERR_ARG);
+            }
+            const size_t i = (size_t)m * p->nl + l;
+            p->C4[i] = mm.C[l] / p->omega;
+            p->v[i] = mm.v[l];
+            p->itau[i] = 1.0 / mm.tau[l];
+            p->Ctot_m[m] += mm.C[l];
+            p->vmax = std::max(p->vmax, mm.v[l]);
+            p->itau_max = std::max(p->itau_max, p->itau[i]);
+        }
+    p->Ctot = p->Ctot_m[0];
+    // interfaces: which face of which geometry faces which
+    p->nifc = n_ifc;
+    p->ifc_end.assign(6 * (size_t)n_geo, bte_problem::IfcEnd{});
+    for (int i = 0; i < n_ifc; ++i) {
+        const bte_interface &q = ifc[i];
+        if (q.geo_a < 0 || q.geo_a >= n_geo || q.geo_b < 0 || q.geo_b >= n_geo || q.face_a < 0 ||
+            q.face_a >= 2 * geo[0].dim || q.face_b < 0 || q.face_b >= 2 * geo[0].dim || !q.beta_ab || !q.beta_ba) {
+            p->err = "interface " + std::to_string(i) + ": bad geometry, face or beta";
             return bail(BTE_ERR_ARG);
         }
-        p->C4[l] = mat->C[l] / p->omega;
-        p->v[l] = mat->v[l];
-        p->itau[l] = 1.0 / mat->tau[l];
-        p->Ctot += mat->C[l];
-        p->vmax = std::max(p->vmax, mat->v[l]);
-        p->itau_max = std::max(p->itau_max, p->itau[l]);
+        const int ax = q.face_a >> 1;
+        if ((q.face_b >> 1) != ax || q.face_b == q.face_a) {
+            p->err = "interface " + std::to_string(i) + ": the faces must be opposite faces of one axis";
+            return bail(BTE_ERR_ARG);
+        }
+        const bte_geometry &ga = geo[q.geo_a], &gb = geo[q.geo_b];
+        if (ga.bc[q.face_a] != BTE_BC_INTERFACE || gb.bc[q.face_b] != BTE_BC_INTERFACE) {
+            p->err = "interface " + std::to_string(i) + ": both faces must be BTE_BC_INTERFACE";
+            return bail(BTE_ERR_ARG);
+        }
+        for (int a = 0; a < ga.dim; ++a) {
+            const double ha = ga.len[a] / ga.n[a], hb = gb.len[a] / gb.n[a];
+            const bool same_n = a == ax || ga.n[a] == gb.n[a];
+            if (!same_n || std::fabs(ha - hb) > 1e-12 * std::max(ha, hb)) {
+                p->err = "interface " + std::to_string(i) + ": the faces do not match cell for cell";
+                return bail(BTE_ERR_ARG);
+            }
+        }
+        bte_problem::IfcEnd &ea = p->ifc_end[6 * q.geo_a + q.face_a], &eb = p->ifc_end[6 * q.geo_b + q.face_b];
+        if (ea.film >= 0 || eb.film >= 0) {
+            p->err = "interface " + std::to_string(i) + ": a face is used twice";
+            return bail(BTE_ERR_ARG);
+        }
+        ea = {q.geo_b, q.face_b, i, 1};
+        eb = {q.geo_a, q.face_a, i, 0};
+        std::vector<double> bt(2 * (size_t)p->nl);
+        for (int l = 0; l < p->nl; ++l) {
+            bt[l] = q.beta_ab[l];
+            bt[p->nl + l] = q.beta_ba[l];
+            if (!(bt[l] >= 0 && bt[l] <= 1) || !(bt[p->nl + l] >= 0 && bt[p->nl + l] <= 1)) {
+                p->err = "interface " + std::to_string(i) + ": beta outside [0, 1]";
+                return bail(BTE_ERR_ARG);
+            }
+        }
+        p->ifcs.push_back(q);
+        p->ifc_beta.push_back(bt);
     }
     if ((st = build_geometry(p, geo, n_geo)) != BTE_OK) return bail(st);
+    for (int f = 0; f < n_geo; ++f) {
+        Film &fm = p->films[f];
+        fm.mat = geo_mat ? geo_mat[f] : 0;
+        fm.moff = fm.mat * p->nl;
+        fm.Ctot = p->Ctot_m[fm.mat];
+    }
     if ((st = build_quadrature(p, mat->n_theta, mat->n_phi, planar)) != BTE_OK) return bail(st);
+    finish_materials(p);
+    if (n_ifc > 0)
+        for (int f = 0; f < n_geo; ++f)
+            if (p->films[f].floating) {
+                p->err = "with interfaces every geometry needs a thermalizing wall";
+                return bail(BTE_ERR_UNSUPPORTED);
+            }
     p->nk = p->na * p->nl;
     choose_default_tiles(p);
     build_schedule(p);
@@ -884,9 +1058,11 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     HIPCHK(p, up("s", p->s.data(), 8 * p->s.size()));
     HIPCHK(p, up("w", p->w.data(), 8 * p->w.size()));
     HIPCHK(p, up("mirror", p->mirror.data(), 4 * p->mirror.size()));
-    HIPCHK(p, up("C4", p->C4.data(), 8 * p->nl));
-    HIPCHK(p, up("v", p->v.data(), 8 * p->nl));
-    HIPCHK(p, up("itau", p->itau.data(), 8 * p->nl));
+    HIPCHK(p, up("C4", p->C4.data(), 8 * p->C4.size()));
+    HIPCHK(p, up("v", p->v.data(), 8 * p->v.size()));
+    HIPCHK(p, up("itau", p->itau.data(), 8 * p->itau.size()));
+    HIPCHK(p, up("wpart", p->wpart.data(), 4 * p->wpart.size()));
+    HIPCHK(p, up("wbeta", p->wbeta.data(), 8 * p->wbeta.size()));
     HIPCHK(p, up("film", p->films.data(), sizeof(Film) * p->nfilm));
     HIPCHK(p, up("code", p->code.data(), 4 * (size_t)p->nc));
     HIPCHK(p, up("nb", p->nb.data(), 4 * p->nb.size()));
@@ -921,6 +1097,9 @@ bte_status bte_bind(bte_problem *p, void *ws, size_t bytes)
     d.C4 = wsptr<double>(p, "C4");
     d.v = wsptr<double>(p, "v");
     d.itau = wsptr<double>(p, "itau");
+    d.nmat = p->nmat;
+    d.wpart = wsptr<int>(p, "wpart");
+    d.wbeta = wsptr<double>(p, "wbeta");
     d.film = wsptr<Film>(p, "film");
     d.code = wsptr<uint32_t>(p, "code");
     d.nb = wsptr<int>(p, "nb");
@@ -1020,10 +1199,6 @@ CgArgs cg_args(bte_problem *p, int corr)
     g.kax = corr ? p->kcor : p->kdif;
     g.coef = corr ? p->ccor : p->cdif;
     g.dg = corr ? p->dcor : p->ddif;
-    double cv = 0;
-    for (int l = 0; l < p->nl; ++l) cv += p->C4[l] * p->omega * p->v[l];
-    // wall emission conductance of the correction (first-moment closure)
-    for (int a = 0; a < 3; ++a) g.Hm[a] = 2.0 * cv * p->H[a] / p->omega;
     g.corr = corr;
     g.p = p->cg_p;
     g.rb[0] = p->cg_r;
@@ -1265,6 +1440,8 @@ bte_status steady_impl(bte_problem *p, T *e, int init, bte_solve_stats *stats, h
             eq = std::max(eq, b);
             if (a <= p->ctl.residual_temp && b <= p->ctl.residual_flux) newly.push_back(f);
         }
+        // geometries joined by interfaces converge together: no masks
+        if (p->nifc > 0 && (int)newly.size() < p->nfilm) newly.clear();
         std::swap(p->T0, p->T1);
         std::swap(p->q0, p->q1);
         cur = 1 - cur;
@@ -1749,6 +1926,7 @@ bte_status bte_transient_step(bte_problem *p, void *e_dev, int n_steps, double t
     if (!e_dev) FAIL(p, BTE_ERR_ARG, "e is null");
     if (n_steps < 0) FAIL(p, BTE_ERR_ARG, "n_steps < 0");
     if (pulse && !(pulse[1] > 0)) FAIL(p, BTE_ERR_ARG, "pulse FWHM must be > 0");
+    if (p->nmat > 1 || p->nifc > 0) FAIL(p, BTE_ERR_UNSUPPORTED, "transient steps: one material, no interface");
     {
         const bte_status cs = check_cfl(p);
         if (cs != BTE_OK) return cs;
@@ -1794,6 +1972,7 @@ bte_status bte_adjoint(bte_problem *p, const void *e_dev, int objective, double 
     if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
     if (!e_dev || !dJ_dgamma_dev) FAIL(p, BTE_ERR_ARG, "null e or gradient");
     if (objective != BTE_OBJ_KEFF_X) FAIL(p, BTE_ERR_ARG, "unknown objective %d", objective);
+    if (p->nmat > 1 || p->nifc > 0) FAIL(p, BTE_ERR_UNSUPPORTED, "the adjoint: one material, no interface");
     if (!p->ctl.adjoint) FAIL(p, BTE_ERR_STATE, "control.adjoint was 0 at setup: no adjoint workspace");
     if (p->ctl.limiter != BTE_LIM_NONE) FAIL(p, BTE_ERR_UNSUPPORTED, "the adjoint needs limiter NONE");
     for (const Film &fm : p->films)
@@ -1820,6 +1999,7 @@ bte_status bte_transient_adjoint(bte_problem *p, const void *e0_dev, int n_steps
     if (!p->ws) FAIL(p, BTE_ERR_STATE, "no workspace bound");
     if (!e0_dev || !weights_dev || !ckpt_dev || !dJ_dgamma_dev) FAIL(p, BTE_ERR_ARG, "null argument");
     if (n_steps < 1 || every < 1) FAIL(p, BTE_ERR_ARG, "n_steps and every must be >= 1");
+    if (p->nmat > 1 || p->nifc > 0) FAIL(p, BTE_ERR_UNSUPPORTED, "the adjoint: one material, no interface");
     if (!p->ctl.adjoint) FAIL(p, BTE_ERR_STATE, "control.adjoint was 0 at setup: no adjoint workspace");
     if (p->ctl.limiter != BTE_LIM_NONE) FAIL(p, BTE_ERR_UNSUPPORTED, "the adjoint needs limiter NONE");
     if (pulse && !(pulse[1] > 0)) FAIL(p, BTE_ERR_ARG, "pulse FWHM must be > 0");

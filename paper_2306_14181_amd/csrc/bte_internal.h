@@ -23,6 +23,10 @@ __host__ __device__ inline uint32_t axis_bits(uint32_t code, int a) { return (co
 __host__ __device__ inline bool side_is_cell(uint32_t ab, int side) { return ab & (side > 0 ? 2u : 1u); }
 __host__ __device__ inline bool side_wraps(uint32_t ab, int side) { return ab & (side > 0 ? 8u : 4u); }
 __host__ __device__ inline int side_wall(uint32_t ab, int side) { return (ab >> (side > 0 ? 6 : 4)) & 3; }
+// Wall kinds in a cell code: 0 thermalizing, 1 specular, 2 diffuse,
+// 3 interface (its inflow, like a diffuse wall's, comes from a wall record).
+constexpr int kWallInterface = 3;
+__host__ __device__ inline bool side_record(uint32_t ab, int side) { return side_wall(ab, side) >= 2; }
 __host__ __device__ inline bool side_outer(uint32_t code, int a, int side)
 {
     return code & (1u << ((side > 0 ? 28 : 25) + a));
@@ -40,6 +44,11 @@ struct Film {
     int nsolid;
     int floating;            // no thermalizing wall: gauge fixed by zero mean T - T_ref
     int periodic[3];         // axis is periodic
+    int moff;                // material: its band tables start at C4[moff], v[moff], itau[moff]
+    int mat;                 // material index
+    double Ctot;             // sum_lambda C of the material
+    double Hm[3];            // wall emission conductance 2 sum C v H_a / Omega (correction operator)
+    double gif[6];           // interface conductance per face (W m^-2 K^-1; 0: not an interface)
 };
 
 // Everything a kernel needs to evaluate the discrete operators.
@@ -47,15 +56,18 @@ struct Dev {
     int dim, nc, na, nl, nk, nfilm;
     int jumps;               // 1: some geometry has a periodic axis with a temperature drop
     int limiter;
-    double Ctot;             // sum_lambda C
+    double Ctot;             // sum_lambda C of material 0 (single-material paths; Film::Ctot otherwise)
     double omega;            // total angle of the direction set: 4 pi, or 2 pi for a two-dimensional material
     double poreT;            // thermalizing pore wall temperature minus T_ref
     const double *s;         // [na][3]
     const double *w;         // [na]
     const int *mirror;       // [3][na]
-    const double *C4;        // [nl] C/omega (C/(4 pi) for a bulk material)
-    const double *v;         // [nl]
-    const double *itau;      // [nl] 1/tau
+    const double *C4;        // [nmat][nl] C/omega (C/(4 pi) for a bulk material)
+    const double *v;         // [nmat][nl]
+    const double *itau;      // [nmat][nl] 1/tau
+    int nmat;                // materials (a geometry's are at Film::moff)
+    const double *wbeta;     // [nw][2][nl] interface record: transmittance into its cell, out of it
+    const int *wpart;        // [nw] the cell across an interface record's face, -1 for a diffuse wall
     const Film *film;        // [nfilm]
     const uint32_t *code;    // [nc]
     const int *nb;           // [6][nc] neighbour cell per face (or -1)
@@ -81,7 +93,8 @@ struct Sweep2Item {
     int oct, chunk, film, flags;   // flags: bit0/1 periodic x/y, bit2/3 octant sign of x/y positive
     int o0, o1, e0, e1;            // tile origin and extent (cells) in the geometry
     int n0, n1, cell0;             // geometry size and first cell
-    int upx, upy, pad;             // items of the x- / y-upwind tiles in the sweep order (-1: none)
+    int upx, upy, moff;            // items of the x- / y-upwind tiles in the sweep order (-1: none); material
+    double Ctot;                   // sum_lambda C of the geometry's material
     double pdT0, pdT1;             // periodic temperature drops along x, y
     double h0, h1, ih0, ih1;       // cell size and inverse along x, y
     double wallT[4];               // thermalizing wall temperatures minus T_ref, faces -x, +x, -y, +y
@@ -103,7 +116,6 @@ struct CgArgs {
     const double *kax;      // [3][nc] per-axis conductivity
     const double *coef;     // [6][nc] coupling to the neighbour across each face (0: none)
     const double *dg;       // [nc] diagonal (faces plus thermalizing walls)
-    double Hm[3];           // wall emission conductance sum C v H_a/(2pi) (correction operator only)
     int corr;               // 1: correction operator, 0: heat diffusion
     double *x, *p;
     double *rb[2], *wb[2], *sb[2];   // r, w = A r/diag and s = A p by iteration parity

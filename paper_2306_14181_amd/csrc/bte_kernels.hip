@@ -65,17 +65,19 @@ __global__ void k_cell_setup(Dev d, double *S, double *kdif, double *kcor, doubl
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.nc) return;
     const double g = d.gamma ? d.gamma[c] : 0.0;
+    const Film &fm = d.film[d.fid[c]];
+    const int mo = fm.moff;   // the geometry's material
     double sm = 0, k = 0, cv = 0;
     for (int l = 0; l < d.nl; ++l) {
-        const double C = d.C4[l] * d.omega;
-        const double it = d.itau[l] + g;
+        const double C = d.C4[mo + l] * d.omega;
+        const double it = d.itau[mo + l] + g;
+        const double v = d.v[mo + l];
         sm += C * it;
-        k += C * d.v[l] * d.v[l] / it;
-        cv += C * d.v[l];
+        k += C * v * v / it;
+        cv += C * v;
     }
     S[c] = sm;
     const double m[3] = {m0, m1, m2}, H[3] = {H0, H1, H2};
-    const Film &fm = d.film[d.fid[c]];
     for (int a = 0; a < 3; ++a) {
         kdif[a * d.nc + c] = k * m[a];
         kcor[a * d.nc + c] = k * m[a] + cv * fm.h[a] * H[a] / d.omega;
@@ -101,17 +103,18 @@ __global__ __launch_bounds__(256) void k_moments_wave(Dev d, const T *__restrict
     extern __shared__ double tab[];
     const int na = d.na, nl = d.nl, nk = d.nk;
     double *tw = tab, *ts0 = tab + na, *ts1 = tab + 2 * na, *ts2 = tab + 3 * na;
-    double *tv = tab + 4 * na, *tit = tv + nl, *tc4 = tv + 2 * nl;
+    const int nml = d.nmat * nl;   // band tables of every material
+    double *tv0 = tab + 4 * na, *tit0 = tv0 + nml, *tc40 = tv0 + 2 * nml;
     for (int i = threadIdx.x; i < na; i += blockDim.x) {
         tw[i] = d.w[i];
         ts0[i] = d.s[3 * i];
         ts1[i] = d.s[3 * i + 1];
         ts2[i] = d.s[3 * i + 2];
     }
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) {
-        tv[i] = d.v[i];
-        tit[i] = d.itau[i];
-        tc4[i] = d.C4[i];
+    for (int i = threadIdx.x; i < nml; i += blockDim.x) {
+        tv0[i] = d.v[i];
+        tit0[i] = d.itau[i];
+        tc40[i] = d.C4[i];
     }
     __syncthreads();
     const int c = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -119,6 +122,8 @@ __global__ __launch_bounds__(256) void k_moments_wave(Dev d, const T *__restrict
     const int lane = threadIdx.x & 63;
     double acc[kMomN] = {0, 0, 0, 0, 0};
     if (d.code[c] & kSolidBit) {
+        const int mo = d.nmat > 1 ? d.film[d.fid[c]].moff : 0;
+        const double *tv = tv0 + mo, *tit = tit0 + mo, *tc4 = tc40 + mo;
         const double g = d.gamma[c];
         const double dp = dpend ? dpend[c] : 0.0;
         // (direction, band) of the lane's first element and the advance per
@@ -220,11 +225,12 @@ __global__ __launch_bounds__(256) void k_moments_band(Dev d, const T *__restrict
         const int b0 = k0 % nl, dA = step / nl;
         int a = k0 / nl;
         double it[kV], vb[kV], c4[kV];
+        const int mo = d.nmat > 1 ? d.film[d.fid[c]].moff : 0;   // the cell's material
 #pragma unroll
         for (int u = 0; u < kV; ++u) {
-            it[u] = d.itau[b0 + u];
-            vb[u] = d.v[b0 + u];
-            c4[u] = d.C4[b0 + u] * dp;   // pending correction of value u
+            it[u] = d.itau[mo + b0 + u];
+            vb[u] = d.v[mo + b0 + u];
+            c4[u] = d.C4[mo + b0 + u] * dp;   // pending correction of value u
         }
         const T *row = e + (size_t)c * nk;
         auto load = [&](int kb, T (&v)[kV]) {
@@ -288,8 +294,9 @@ __global__ __launch_bounds__(kBlock) void k_moments_block(Dev d, const T *__rest
     if (d.code[c] & kSolidBit) {
         const double g = d.gamma[c];
         const double dp = dpend ? dpend[c] : 0.0;
+        const int mo = d.nmat > 1 ? d.film[d.fid[c]].moff : 0;
         for (int k = threadIdx.x; k < d.nk; k += kBlock) {
-            const LaneConst L = lane_const(d, k);
+            const LaneConst L = lane_const(d, k, mo);
             const double x = (double)e[(size_t)c * d.nk + k] + L.C4 * dp;
             const double wx = L.w * x;
             acc[0] += wx;
@@ -315,7 +322,7 @@ __global__ void k_finalize(Dev d, const double *__restrict__ part, int np, doubl
     for (int p = 0; p < np; ++p)
         for (int i = 0; i < kMomN; ++i) s[i] += part[((size_t)p * d.nc + c) * kMomN + i];
     const bool solid = d.code[c] & kSolidBit;
-    const double td = solid ? s[0] / d.Ctot : 0.0;
+    const double td = solid ? s[0] / d.film[d.fid[c]].Ctot : 0.0;
     const double tl = solid ? s[1] / d.S[c] : 0.0;
     if (T) T[c] = Tref + td;
     if (TL) TL[c] = Tref + tl;
@@ -338,46 +345,66 @@ __global__ void k_finalize_tl(Dev d, const double *__restrict__ part, int np, do
 
 // ---------------------------------------------------------------- diffuse walls
 
-// Incoming value of each diffuse wall record (Sec. 2.2, eq. diff_bound, with
-// the discrete normalisation): sum_{s.n>0} w s.n e_face / sum_{s.n<0} w |s.n|.
+// Incoming value of each wall record.  Diffuse wall (Sec. 2.2 (iii), eq.
+// diff_bound, with the discrete normalisation): sum_{s.n>0} w s.n e_face /
+// sum_{s.n<0} w |s.n|.  Interface (Sec. 2.2 (v)) between the record's cell
+// (material A) and the cell across the face (material B):
+// [beta_BA (v_B / v_A) F_B + (1 - beta_AB) F_A] / sum_{s.n<0} w |s.n|, with
+// F_X the outgoing sum_{s.n>0} w |s.n| e_face of side X; the fractions act
+// on energy fluxes, hence the speed ratio.  Face values: the cell value plus
+// the one-sided slope toward the face (unlimited scheme only).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_walls(Dev d, const T *__restrict__ e, const double *__restrict__ dpend,
                                                    const int *__restrict__ wrec, const double *__restrict__ wden,
                                                    double *__restrict__ din, int nw)
 {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[2][kBlock];
     const int r = blockIdx.x;
     if (r >= nw) return;
     const int c = wrec[2 * r], f = wrec[2 * r + 1];
     const int a = f >> 1, side = (f & 1) ? 1 : -1;
     const Film &fm = d.film[d.fid[c]];
-    const uint32_t ab = axis_bits(d.code[c], a);
-    const bool hu = side_is_cell(ab, -side);
-    const int j1 = hu ? d.nb[face_of(a, -side) * d.nc + c] : -1;
+    const int jp = d.wpart[r];   // the cell across an interface, -1 for a diffuse wall
+    const Film &fp = d.film[d.fid[jp >= 0 ? jp : c]];
     const int G = kBlock / d.nl;     // groups of n_bands threads (n_bands <= 256)
     const int grp = threadIdx.x / d.nl, l = threadIdx.x - grp * d.nl;
-    double sum = 0.0;
+    // the outgoing face value of cell x through its face on side sx, for lane k
+    auto face_out = [&](const Film &fx, int x, int sx, int k, T C4) -> T {
+        const uint32_t ab = axis_bits(d.code[x], a);
+        const bool hb = side_is_cell(ab, -sx);
+        const T ex = ld_e(e, dpend, d, x, k, C4);
+        if (d.limiter != LIM_NONE || !hb) return ex;
+        const int jb = d.nb[face_of(a, -sx) * d.nc + x];
+        const T J = C4 * (T)fx.pdT[a];
+        const T jump = side_wraps(ab, -sx) ? (T)sx * J : (T)0;
+        return ex + (T)(0.5 * fx.h[a]) * ((ex - (ld_e(e, dpend, d, jb, k, C4) + jump)) * (T)fx.ih[a]);
+    };
+    double sum = 0.0, sumb = 0.0;
     if (grp < G) {
-        const T C4 = (T)d.C4[l];
-        const T J = C4 * (T)fm.pdT[a];
-        const T jump1 = (hu && side_wraps(ab, -side)) ? (T)side * J : (T)0;
-        const T ih = (T)fm.ih[a], hh = (T)(0.5 * fm.h[a]);
+        const T C4 = (T)d.C4[fm.moff + l], C4p = (T)d.C4[fp.moff + l];
         for (int al = grp; al < d.na; al += G) {
             const double sa = d.s[3 * al + a];
-            if (sa * side <= 0.0) continue;
             const int k = al * d.nl + l;
-            const T ec = ld_e(e, dpend, d, c, k, C4);
-            T g = (T)0;
-            if (d.limiter == LIM_NONE && hu) g = (ec - (ld_e(e, dpend, d, j1, k, C4) + jump1)) * ih;
-            sum += d.w[al] * fabs(sa) * (double)(ec + hh * g);
+            if (sa * side > 0.0) sum += d.w[al] * fabs(sa) * (double)face_out(fm, c, side, k, C4);
+            else if (jp >= 0 && sa * side < 0.0) sumb += d.w[al] * fabs(sa) * (double)face_out(fp, jp, -side, k, C4p);
         }
     }
-    sh[threadIdx.x] = sum;
+    sh[0][threadIdx.x] = sum;
+    sh[1][threadIdx.x] = sumb;
     __syncthreads();
     if (threadIdx.x < d.nl) {
-        double t = 0.0;
-        for (int g2 = 0; g2 < G; ++g2) t += sh[g2 * d.nl + threadIdx.x];
-        din[(size_t)r * d.nl + threadIdx.x] = t / wden[f];
+        double t = 0.0, tb = 0.0;
+        for (int g2 = 0; g2 < G; ++g2) {
+            t += sh[0][g2 * d.nl + threadIdx.x];
+            tb += sh[1][g2 * d.nl + threadIdx.x];
+        }
+        double v = t;
+        if (jp >= 0) {
+            const double *bt = d.wbeta + 2 * (size_t)r * d.nl;
+            const double ratio = d.v[fp.moff + threadIdx.x] / d.v[fm.moff + threadIdx.x];
+            v = bt[threadIdx.x] * ratio * tb + (1.0 - bt[d.nl + threadIdx.x]) * t;
+        }
+        din[(size_t)r * d.nl + threadIdx.x] = v / wden[f];
     }
 }
 
@@ -392,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Dev d, const T *__restrict_
     if (chunk >= nchunk) return;
     const int k = chunk * kBlock + threadIdx.x;
     if (k >= d.nk) return;
-    const LaneConst L = lane_const(d, k);
+    const LaneConst L0 = lane_const(d, k, 0);
     for (int ci = 0; ci < cpb; ++ci) {
         const int c = grp * cpb + ci;
         if (c >= d.nc) break;
@@ -402,8 +429,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(Dev d, const T *__restrict_
             continue;
         }
         const Film &fm = d.film[d.fid[c]];
+        const LaneConst L = d.nmat > 1 ? lane_const(d, k, fm.moff) : L0;
         const double itc = L.itau + d.gamma[c];
-        const double qsrc = d.P ? d.P[c] / d.Ctot : 0.0;
+        const double qsrc = d.P ? d.P[c] / fm.Ctot : 0.0;
         const T ec = e[(size_t)c * d.nk + k];
         const StencilOut<T> so = stencil<T>(e, nullptr, din, d, fm, c, code, L, ec);
         const T e0 = (T)(L.C4 * TLdev[c]);
@@ -420,7 +448,7 @@ __global__ void k_set_equilibrium(Dev d, T *__restrict__ e, const double *__rest
     const size_t n = (size_t)d.nc * d.nk;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const int c = (int)(i / d.nk), k = (int)(i - (size_t)c * d.nk);
-        const int l = k % d.nl;
+        const int l = k % d.nl + (d.nmat > 1 ? d.film[d.fid[c]].moff : 0);
         e[i] = (d.code[c] & kSolidBit) ? (T)(d.C4[l] * Tdev[c]) : (T)0;
     }
 }
@@ -433,7 +461,7 @@ __global__ void k_apply_shift(Dev d, const T *__restrict__ in, T *__restrict__ o
     const size_t n = (size_t)d.nc * d.nk;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const int c = (int)(i / d.nk), k = (int)(i - (size_t)c * d.nk);
-        const int l = k % d.nl;
+        const int l = k % d.nl + (d.nmat > 1 ? d.film[d.fid[c]].moff : 0);
         double sft = (dpend ? dpend[c] : 0.0) - (fshift ? fshift[d.fid[c]] : 0.0);
         out[i] = (d.code[c] & kSolidBit) ? (T)((double)in[i] + d.C4[l] * sft) : in[i];
     }
@@ -453,7 +481,7 @@ __global__ void k_steady_post(Dev d, const double *__restrict__ part, int np, co
     const bool solid = d.code[c] & kSolidBit;
     const double tl = solid ? s[1] / d.S[c] : 0.0;
     TLkin[c] = tl;
-    Tnew[c] = solid ? s[0] / d.Ctot : 0.0;
+    Tnew[c] = solid ? s[0] / d.film[d.fid[c]].Ctot : 0.0;
     qnew[c] = solid ? sqrt(s[2] * s[2] + s[3] * s[3] + s[4] * s[4]) : 0.0;
     // a converged geometry gets no further correction
     if (synthetic) r[c] = (solid && !d.fdone[d.fid[c]]) ? d.S[c] * (tl - TLn[c]) : 0.0;
@@ -599,7 +627,7 @@ __device__ inline double wall_cond(const Dev &d, const CgArgs &g, int c, int a, 
 {
     const double kd = 2.0 * g.kax[a * d.nc + c] * fm.ih[a];
     if (!g.corr) return kd;
-    return 1.0 / (1.0 / kd + 1.0 / g.Hm[a]);
+    return 1.0 / (1.0 / kd + 1.0 / fm.Hm[a]);
 }
 
 // Face couplings and diagonal of the diffusion operator per unit volume:
@@ -626,6 +654,16 @@ __global__ void k_cg_coef(Dev d, CgArgs g, double *coef, double *dgo)
                     const double kf = 2.0 * ki * kj / (ki + kj) * ih2;
                     coef[face_of(a, side) * d.nc + c] = kf;
                     diag += kf;
+                } else if (side_wall(ab, side) == kWallInterface) {
+                    // the half cells in series with the interface conductance
+                    const double G = fm.gif[face_of(a, side)];
+                    if (G > 0.0) {
+                        const int j = d.nb[face_of(a, side) * d.nc + c];
+                        const double kj = g.kax[a * d.nc + j];
+                        const double kf = fm.ih[a] / (0.5 * fm.h[a] / ki + 1.0 / G + 0.5 * fm.h[a] / kj);
+                        coef[face_of(a, side) * d.nc + c] = kf;
+                        diag += kf;
+                    }
                 } else if (side_wall(ab, side) == 0) {
                     diag += wall_cond(d, g, c, a, fm) * fm.ih[a];
                 }
@@ -883,7 +921,7 @@ template <typename T>
 void launch_moments(const Dev &d, const T *e, const double *dpend, double *part, hipStream_t s)
 {
     constexpr int kV = 16 / (int)sizeof(T);
-    const size_t tab = 8 * (4 * (size_t)d.na + 3 * (size_t)d.nl);
+    const size_t tab = 8 * (4 * (size_t)d.na + 3 * (size_t)d.nl * d.nmat);
     const bool aligned = d.nk % kV == 0 && (reinterpret_cast<uintptr_t>(e) & 15) == 0;
     // lanes per step of the band-factored form: at most 64, kV nL a multiple of nl
     int nL = 0;

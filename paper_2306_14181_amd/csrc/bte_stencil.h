@@ -21,7 +21,9 @@ struct LaneConst {
     double w, s[3], v, C4, itau;
 };
 
-__device__ inline LaneConst lane_const(const Dev &d, int k)
+// Constants of lane k (direction, band) for the material whose band tables
+// start at moff.
+__device__ inline LaneConst lane_const(const Dev &d, int k, int moff)
 {
     LaneConst c;
     c.k = k;
@@ -31,9 +33,9 @@ __device__ inline LaneConst lane_const(const Dev &d, int k)
     c.s[0] = d.s[3 * c.al + 0];
     c.s[1] = d.s[3 * c.al + 1];
     c.s[2] = d.s[3 * c.al + 2];
-    c.v = d.v[c.l];
-    c.C4 = d.C4[c.l];
-    c.itau = d.itau[c.l];
+    c.v = d.v[moff + c.l];
+    c.C4 = d.C4[moff + c.l];
+    c.itau = d.itau[moff + c.l];
     return c;
 }
 
@@ -74,7 +76,7 @@ __device__ inline int diffuse_index(const Dev &d, int c, uint32_t code, int f)
     for (int g = 0; g < f; ++g) {
         int a = g >> 1, side = (g & 1) ? 1 : -1;
         uint32_t ab = axis_bits(code, a);
-        if (a < d.dim && !side_is_cell(ab, side) && side_wall(ab, side) == 2) ++idx;
+        if (a < d.dim && !side_is_cell(ab, side) && side_record(ab, side)) ++idx;
     }
     return idx;
 }

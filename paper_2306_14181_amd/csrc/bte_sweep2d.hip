@@ -188,7 +188,7 @@ __device__ inline int diffuse_rank2(uint32_t code, int f)
     for (int g = 0; g < 3; ++g) {
         const uint32_t ab = axis_bits(code, g >> 1);
         const int side = (g & 1) ? 1 : -1;
-        n += (g < f && !side_is_cell(ab, side) && side_wall(ab, side) == 2) ? 1 : 0;
+        n += (g < f && !side_is_cell(ab, side) && side_record(ab, side)) ? 1 : 0;
     }
     return n;
 }
@@ -266,9 +266,10 @@ __global__ __launch_bounds__(64 * (kTY / kRW), (sweep2d_waves<T, kRW, QUEUE>()))
     const int kk = active ? k : kbeg;
     const int al = kk / nl, l = kk - al * nl;
     // lane constants (direction al, band l)
-    const double wq = d.w[al], vq = d.v[l], itq = d.itau[l];
+    const int mb = it.moff + l;   // the band in the geometry's material
+    const double wq = d.w[al], vq = d.v[mb], itq = d.itau[mb];
     const double s0 = d.s[3 * al], s1 = d.s[3 * al + 1], s2 = d.s[3 * al + 2];
-    const T C4 = (T)d.C4[l], itau = (T)itq;
+    const T C4 = (T)d.C4[mb], itau = (T)itq;
     const T cp0 = (T)(vq * fabs(s0) * it.ih0), cp1 = (T)(vq * fabs(s1) * it.ih1);
     const T hh0 = (T)(0.5 * it.h0), hh1 = (T)(0.5 * it.h1), ih0 = (T)it.ih0, ih1 = (T)it.ih1;
     if (w == 0) {
@@ -396,14 +397,14 @@ __global__ __launch_bounds__(64 * (kTY / kRW), (sweep2d_waves<T, kRW, QUEUE>()))
             if (hu21 && side_is_cell(ab1, sg1)) wd |= W_FY;
             if (hu0 && !side_wraps(ab0, -sg0)) wd |= W_CX;
             if (hu1 && !side_wraps(ab1, -sg1)) wd |= W_CY;
-            if (!hu0 && side_wall(ab0, -sg0) == 2) wd |= W_DX;
-            if (!hu1 && side_wall(ab1, -sg1) == 2) wd |= W_DY;
+            if (!hu0 && side_record(ab0, -sg0)) wd |= W_DX;   // diffuse wall or interface
+            if (!hu1 && side_record(ab1, -sg1)) wd |= W_DY;
             t_w = wd;
         }
         const bool sol = t_w & W_SOLID;
         t_tl = sol ? (T)t_tld : (T)0;
         t_gam = sol ? (T)t_gamd : (T)0;
-        t_qs = sol ? (T)(t_qsd / d.Ctot) : (T)0;
+        t_qs = sol ? (T)(t_qsd / it.Ctot) : (T)0;
         t_x = sol ? (T)t_xd : (T)0;
         h_x = (T)(h_xd + h_j);
     }

@@ -124,7 +124,7 @@ __device__ inline void tile_tables(const TileCtx t, const Film &fm, const Dev &d
             S.code[s] = d.code[craw];
             S.gam[s] = d.gamma[craw];
             S.tl[s] = TLdev ? TLdev[craw] : 0.0;
-            S.qs[s] = d.P ? d.P[craw] / d.Ctot : 0.0;
+            S.qs[s] = d.P ? d.P[craw] / fm.Ctot : 0.0;
             short *st = S.stn + 9 * s;
             st[0] = (short)tile_slot(t, f0 - 1, f1, f2);
             st[1] = (short)tile_slot(t, f0 - 2, f1, f2);
@@ -273,8 +273,9 @@ template <typename T> __device__ inline LaneT<T> lane_make(const Dev &d, const F
     L.al = k / d.nl;
     L.l = k - L.al * d.nl;
     L.w = d.w[L.al];
-    const double v = d.v[L.l], it = d.itau[L.l];
-    L.C4 = (T)d.C4[L.l];
+    const int mb = fm.moff + L.l;   // the band in the geometry's material
+    const double v = d.v[mb], it = d.itau[mb];
+    L.C4 = (T)d.C4[mb];
     L.itau = (T)it;
     L.witau = L.w * it;
 #pragma unroll

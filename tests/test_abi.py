@@ -200,3 +200,63 @@ def test_one_launch_sweep_is_the_2d_register_sweeps(lib, dim):
     assert lib.bte_set_persistent(h, 0) == 0
     assert lib.bte_set_persistent(h, 1) == (0 if dim == 2 else 2)   # BTE_ERR_UNSUPPORTED
     lib.bte_destroy(h)
+
+
+def _setup_multi(lib, geos, mats, geo_mat, ifcs):
+    from paper_2306_14181_amd import bte
+    keep = []
+    arr = (bte.Geometry * len(geos))()
+    for i, g in enumerate(geos):
+        s, k = bte._geometry_struct(g)
+        arr[i] = s
+        keep.append(k)
+    marr = (bte.Material * len(mats))()
+    for i, m in enumerate(mats):
+        bands = [np.ascontiguousarray(m[k], dtype=np.float64) for k in ("C", "v", "tau")]
+        keep.append(bands)
+        mm = marr[i]
+        mm.n_bands = len(bands[0])
+        mm.C, mm.v, mm.tau = [b.ctypes.data_as(C.POINTER(C.c_double)) for b in bands]
+        mm.n_theta, mm.n_phi, mm.T_ref = m["n_theta"], m.get("n_phi", 1), m["Tref"]
+        mm.material_dim = int(m.get("material_dim", 3))
+    gm = (C.c_int * len(geo_mat))(*geo_mat)
+    iarr = (bte.Interface * max(len(ifcs), 1))()
+    for i, q in enumerate(ifcs):
+        ab = np.ascontiguousarray(q["beta_ab"], dtype=np.float64)
+        ba = np.ascontiguousarray(q["beta_ba"], dtype=np.float64)
+        keep += [ab, ba]
+        iarr[i].geo_a, iarr[i].face_a, iarr[i].geo_b, iarr[i].face_b = q["geo_a"], q["face_a"], q["geo_b"], q["face_b"]
+        iarr[i].beta_ab = ab.ctypes.data_as(C.POINTER(C.c_double))
+        iarr[i].beta_ba = ba.ctypes.data_as(C.POINTER(C.c_double))
+    c = bte.Control()
+    h = C.c_void_p()
+    st = lib.bte_setup_multi(arr, len(geos), marr, len(mats), gm, iarr, len(ifcs), C.byref(c), C.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("what", ["ok", "3d", "unmatched_face", "same_side", "no_interface", "beta", "twice",
+                                  "bands", "floating"])
+def test_setup_multi_validates_interfaces(lib, what):
+    """bte_setup_multi: two geometries of two materials joined at A's +x and
+    B's -x face; each broken variant is refused with BTE_ERR_ARG (or
+    BTE_ERR_UNSUPPORTED for 3D and for a geometry without a thermalizing
+    wall), nothing on the device."""
+    dim = 3 if what == "3d" else 2
+    b = I.bands(0, 3)
+    ma, mb = mat(b, 2, 2), mat(dict(b, C=b["C"] * 2.0, v=b["v"] * 0.5), 2, 2)
+    if what == "bands":
+        mb = mat(I.bands(0, 4), 2, 2)
+    n = (6, 5, 4)[:dim]
+    nB = (8, 5, 4)[:dim] if what != "unmatched_face" else (8, 4, 4)[:dim]
+    bcA = [I.BC_THERMAL, 4] + [I.BC_SPECULAR] * 4
+    bcB = [4 if what != "no_interface" else I.BC_DIFFUSE, I.BC_THERMAL if what != "floating" else I.BC_DIFFUSE] \
+        + [I.BC_SPECULAR] * 4
+    gA = geo(dim, n, tuple(1e-7 * k for k in n), bcA)
+    gB = geo(dim, nB, tuple(1e-7 * k for k in nB), bcB)
+    q = dict(geo_a=0, face_a=1, geo_b=1, face_b=0 if what != "same_side" else 1,
+             beta_ab=np.full(3, 0.4 if what != "beta" else 1.2), beta_ba=np.full(3, 0.5))
+    ifcs = [q, q] if what == "twice" else [q]
+    st, h = _setup_multi(lib, [gA, gB], [ma, mb], [0, 1], ifcs)
+    expect = {"ok": 0, "3d": 2, "floating": 2}.get(what, 1)
+    assert st == expect, (what, lib.bte_last_error(h))
+    lib.bte_destroy(h)

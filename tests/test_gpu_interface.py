@@ -1,0 +1,202 @@
+"""Two materials joined by the interfacial boundary condition (Sec. 2.2 (v);
+the Ge-Si verification case of Sec. 3.6 in shape: a film of material A
+between a thermalizing wall and the interface, a film of material B between
+the interface and a second thermalizing wall).
+
+On the device the two materials are two geometries joined by a
+bte_interface; in the oracle they are one geometry whose cells carry their
+material, the interface being every face between cells of different
+materials.  The tests map cells between the two numberings and compare the
+residual, the moments, source iterations (both schemes: the synthetic
+correction couples the geometries through the interface conductance) and
+converged solutions, at the stated bars (FP64 1e-11, FP32 1e-5).  Synthetic
+materials and transmittances (not Ge or Si data); pores next to the
+interface and ragged 8 x 8 tiles in 2D."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TREF = 300.0
+MAT_A = dict(C=np.array([1.0e5, 2.0e5, 3.0e5]), v=np.array([1000.0, 2000.0, 3000.0]),
+             tau=np.array([1e-10, 3e-10, 2e-11]), Tref=TREF)
+MAT_B = dict(C=np.array([2.0e5, 1.0e5, 4.0e5]), v=np.array([1500.0, 700.0, 2500.0]),
+             tau=np.array([5e-11, 2e-10, 1e-10]), Tref=TREF)
+BETA_AB = np.array([0.3, 0.55, 0.8])
+BETA_BA = np.array([0.6, 0.25, 0.45])
+H = 50e-9
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2306_14181_amd import bte
+    bte.load()
+    return bte
+
+
+def case_def(name):
+    """(device geometries, union oracle geometry, material dicts, cell map):
+    map[i] is the device cell of oracle cell i."""
+    if name == "iface1d":
+        nA, nB, ny, dim = 7, 9, 1, 1
+        nth = dict(n_theta=4, n_phi=1)
+        yb = [O.BC_SPECULAR, O.BC_SPECULAR]
+        solid = None
+    else:
+        nA, nB, ny, dim = 10, 13, 12, 2
+        nth = dict(n_theta=2, n_phi=2)
+        yb = [O.BC_PERIODIC, O.BC_PERIODIC]
+        solid = np.ones((ny, nA + nB), dtype=np.uint8)
+        solid[5, 4] = 0          # a pore in A
+        solid[2, nA + 7] = 0     # a pore in B
+        solid[8, nA] = 0         # a pore of B facing A across the interface
+    ma, mb = dict(MAT_A, **nth), dict(MAT_B, **nth)
+    T1, T2 = TREF + 1.0, TREF - 0.5
+    zb = [O.BC_SPECULAR, O.BC_SPECULAR]
+
+    def dev_geo(nx, lo, hi, Tlo, Thi, sol):
+        g = dict(dim=dim, n=[nx, ny, 1], len=[nx * H, ny * H, 1.0], bc=[lo, hi] + yb + zb,
+                 bcT=[Tlo, Thi] + [TREF] * 4, pdT=[0.0, 0.0, 0.0], pore_bc=O.BC_DIFFUSE)
+        if sol is not None:
+            g["solid"] = np.ascontiguousarray(sol).reshape(-1)
+        return g
+
+    gA = dev_geo(nA, O.BC_THERMAL, O.BC_INTERFACE, T1, TREF, None if solid is None else solid[:, :nA])
+    gB = dev_geo(nB, O.BC_INTERFACE, O.BC_THERMAL, TREF, T2, None if solid is None else solid[:, nA:])
+    n = nA + nB
+    mat = np.zeros((ny, n), dtype=np.int32)
+    mat[:, nA:] = 1
+    gu = dict(dim=dim, n=[n, ny, 1], len=[n * H, ny * H, 1.0], bc=[O.BC_THERMAL, O.BC_THERMAL] + yb + zb,
+              bcT=[T1, T2] + [TREF] * 4, pdT=[0.0, 0.0, 0.0], pore_bc=O.BC_DIFFUSE,
+              solid=None if solid is None else solid.reshape(-1), mat=mat.reshape(-1))
+    cmap = np.empty(n * ny, dtype=np.int64)
+    for iy in range(ny):
+        for ix in range(n):
+            cmap[ix + n * iy] = ix + nA * iy if ix < nA else nA * ny + (ix - nA) + nB * iy
+    return [gA, gB], gu, [ma, mb], cmap
+
+
+def build(B, name, prec, limiter=O.LIM_NONE, scheme=1, **ctl):
+    geos, gu, mats, cmap = case_def(name)
+    case = O.Case(gu, mats, limiter=limiter, beta=np.array([[np.zeros(3), BETA_AB], [BETA_BA, np.zeros(3)]]))
+    control = dict(precision=prec, scheme=scheme, limiter=limiter)
+    control.update(ctl)
+    prob = B.Problem(geos, mats, control, geo_mat=[0, 1],
+                     interfaces=[dict(geo_a=0, face_a=1, geo_b=1, face_b=0, beta_ab=BETA_AB, beta_ba=BETA_BA)])
+    return case, prob, cmap
+
+
+def to_dev(prob, case, cmap, e):
+    """Oracle-ordered e -> device tensor."""
+    ed = np.empty_like(e.reshape(case.nc, -1))
+    ed[cmap] = e.reshape(case.nc, -1)
+    return torch.as_tensor(ed.reshape(-1), device="cuda").to(prob.dtype).contiguous()
+
+
+def to_orc(case, cmap, t, width=None):
+    """Device tensor (cells first) -> oracle order."""
+    x = t.detach().double().cpu().numpy()
+    x = x.reshape(case.nc, -1)
+    return x[cmap].reshape(-1) if width is None else x[cmap]
+
+
+def seeded(case, seed):
+    rng = np.random.default_rng(seed)
+    T = rng.uniform(-1, 1, case.nc)
+    mat = case.mat
+    C = case.C.reshape(case.nmat, case.nl)[mat]                  # [nc, nl]
+    e = (C[:, None, :] * T[:, None, None] / (4 * np.pi)) * np.ones((1, case.na, 1))
+    e = e + 0.05 * np.abs(e).max() * rng.normal(size=e.shape)
+    if case.solid is not None:
+        e[case.solid == 0] = 0.0
+    return e.reshape(-1)
+
+
+CASES = ["iface1d", "iface2d"]
+
+
+@pytest.mark.parametrize("lim", [O.LIM_NONE, O.LIM_MC, O.LIM_MINMOD])
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("name", CASES)
+def test_interface_residual(B, name, prec, lim):
+    case, prob, cmap = build(B, name, prec, limiter=lim)
+    e = seeded(case, 2)
+    eg = to_dev(prob, case, cmap, e)
+    e = to_orc(case, cmap, eg)   # the stored (possibly FP32-rounded) values
+    R = to_orc(case, cmap, prob.residual(eg))
+    Ro = O.residual(case, e)
+    err = rel_err(R, Ro)
+    print(name, prec, lim, err)
+    assert err < (1e-11 if prec == 1 else 1e-5), err
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("name", CASES)
+def test_interface_moments(B, name, prec):
+    case, prob, cmap = build(B, name, prec)
+    e = seeded(case, 1)
+    eg = to_dev(prob, case, cmap, e)
+    e = to_orc(case, cmap, eg)
+    T, TL, q = prob.moments(eg)
+    To, TLo, qo = O.moments(case, e)
+    tol = 1e-12
+    assert rel_err(to_orc(case, cmap, T), To, TREF) < tol
+    assert rel_err(to_orc(case, cmap, TL), TLo, TREF) < tol
+    assert rel_err(to_orc(case, cmap, q, 3).reshape(-1), qo.reshape(-1)) < tol
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("name", CASES)
+def test_interface_sweep_iterates_fp64(B, name, scheme, persistent):
+    """Three source iterations from the same state (the synthetic scheme's
+    correction couples the two geometries through the interface)."""
+    if persistent and name == "iface1d":
+        pytest.skip("the one-launch sweep is the 2D register-tile form")
+    case, prob, cmap = build(B, name, 1, scheme=scheme, max_iter=3, residual_temp=0.0, residual_flux=0.0,
+                             cg_rtol=1e-13, cg_max_iter=20000)
+    if persistent:
+        prob.set_persistent(True)
+    e = seeded(case, 4)
+    eg = to_dev(prob, case, cmap, e)
+    st = prob.steady_solve(eg, init=False, allow_not_converged=True)
+    assert st["iters"] == 3
+    eo, _ = O.steady(case, scheme=scheme, tol_T=0.0, tol_q=0.0, max_iter=3, cg_rtol=1e-13, cg_maxit=20000,
+                     e=e.copy())
+    err = rel_err(to_orc(case, cmap, eg), eo)
+    print(name, scheme, persistent, err)
+    assert err < 1e-11, err
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("name", CASES)
+def test_interface_steady_converged(B, name, prec):
+    tolT = 2e-13 if prec == 1 else 1e-7
+    case, prob, cmap = build(B, name, prec, scheme=1, max_iter=4000, residual_temp=tolT, residual_flux=tolT * 10,
+                             cg_rtol=1e-12)
+    eg = prob.zeros()
+    st = prob.steady_solve(eg, init=True)
+    assert st["converged"]
+    eo, _ = O.steady(case, scheme=1, tol_T=1e-13, tol_q=1e-13, max_iter=20000, cg_rtol=1e-13)
+    T, TL, q = prob.moments(eg)
+    To, TLo, qo = O.moments(case, eo)
+    tol = 1e-11 if prec == 1 else 1e-5
+    errs = (rel_err(to_orc(case, cmap, T), To, TREF), rel_err(to_orc(case, cmap, TL), TLo, TREF),
+            rel_err(to_orc(case, cmap, q, 3).reshape(-1), qo.reshape(-1)))
+    print(name, prec, errs, st["iters"])
+    assert max(errs) < tol, errs
+
+
+def test_interface_refuses_transient_and_adjoint(B):
+    case, prob, cmap = build(B, "iface1d", 1, dt=1e-14)
+    eg = prob.zeros()
+    with pytest.raises(B.BteError) as ex:
+        prob.transient_step(eg, 1)
+    assert ex.value.status == B.BTE_ERR_UNSUPPORTED
