@@ -23,7 +23,10 @@ pulse; a step is one explicit step of every (cell, direction, band).
 reports k_eff per film; --workload porous3d_adjoint solves the 48^3 porous
 cube (96 directions, 40 bands, per-cell gamma) and its adjoint d k_eff /
 d gamma; --workload tadjoint3d runs the transient adjoint of 500 explicit
-steps on a 32^3 cube with checkpoints every 50 steps.
+steps on a 32^3 cube with checkpoints every 50 steps; --workload interface2d
+solves two materials joined by the interfacial boundary condition (two
+128 x 256 halves of a 1 um square, 20 bands, 128 directions, walls at
+301 K / 299 K) to convergence and reports the interface conductance.
 
 --copy-calibration runs a plain 2 GiB device copy (for scaling HBM counters).
 
@@ -393,6 +396,65 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_interface(args):
+    """Two materials joined by the interfacial boundary condition: steady
+    FP32 solve to convergence, the sweep roofline and the interface
+    conductance q_x / (T just left of the interface - T just right of it)."""
+    import numpy as np
+    import torch
+    import bte_inputs as I
+    from paper_2306_14181_amd import bte as B
+    torch.cuda.set_device(0)
+    cfg = I.interface2d_case()
+    geos, mats = cfg["geometries"], cfg["materials"]
+    prob = B.Problem(geos, mats, dict(precision=B.F32, scheme=B.SYNTHETIC, limiter=cfg["limiter"],
+                                      residual_temp=1e-6, residual_flux=1e-5, max_iter=args.max_iter,
+                                      cg_rtol=1e-6, cg_max_iter=40),
+                     geo_mat=cfg["geo_mat"], interfaces=cfg["interfaces"])
+    prob.set_persistent(not args.no_persistent)
+    e = prob.zeros()
+    tune = []
+    if not args.no_autotune:
+        tune = tune_sweep(B, prob, e, 2, not args.no_persistent)
+        e.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = prob.steady_solve(e, init=True, allow_not_converged=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    T, _, q = prob.moments(e)
+    T, q = T.cpu().numpy(), q.cpu().numpy()
+    nA, ny = geos[0]["n"][0], geos[0]["n"][1]
+    nB = geos[1]["n"][0]
+    TA = T[: nA * ny].reshape(ny, nA)
+    TB = T[nA * ny:].reshape(ny, nB)
+    qA = q[: nA * ny, 0].reshape(ny, nA)
+    qB = q[nA * ny:, 0].reshape(ny, nB)
+    dT = float(TA[:, -1].mean() - TB[:, 0].mean())
+    qi = float(0.5 * (qA[:, -1].mean() + qB[:, 0].mean()))
+    upd = st["updates"]
+    sweep_ms = st["ms_sweep"] / max(st["iters"], 1)
+    sweep_bytes = BYTES_PER_UPDATE[B.F32] * prob.n_cells * prob.n_dirs * prob.n_bands
+    achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9
+    kept = next((x for x in tune if x["chosen"]), None)
+    log("interface2d: %d iterations %.2f s, sweep %.3f ms, G = %.4g W/m^2/K" % (st["iters"], t, sweep_ms, qi / dT))
+    out = {"metric": "cell*dir*band updates/s of the steady solve of two materials joined by an interface",
+           "value": upd / t, "unit": "updates/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f32 (e), f64 (moments, CG)", "data": "synthetic (seeded bands, diffuse-mismatch-form beta)",
+           "config": {"workload": "interface2d: 2 x (128 x 256) cells of a 1 um square, 20 bands, 128 directions, "
+                                  "walls 301 K / 299 K, specular top and bottom", "unknowns": prob.n_unknowns},
+           "iterations": st["iters"], "converged": st["converged"], "eps_T": st["eps_T"], "solve_s": t,
+           "roofline": {"bound": "hbm", "kernel": kept["kernel"] if kept else "k_sweep2d", "achieved": achieved,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                        "avg_sweep_ms": sweep_ms, "bytes_per_sweep": sweep_bytes},
+           "interface": {"q_x": qi, "T_left": float(TA[:, -1].mean()), "T_right": float(TB[:, 0].mean()),
+                         "conductance_W_m2K": qi / dT,
+                         "q_x_spread": float((max(qA.max(), qB.max()) - min(qA.min(), qB.min())) / abs(qi))},
+           "autotune": [{"tile": list(x["tile"]), "kernel": x["kernel"], "ms_per_sweep": x["ms"],
+                         "chosen": x["chosen"]} for x in tune]}
+    print(json.dumps(out), flush=True)
+
+
 def bench_adjoint(args):
     """48^3 porous cube: FP32 forward steady solve and the adjoint gradient."""
     import numpy as np
@@ -503,7 +565,7 @@ def bench_tadjoint(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=("steady2d", "transient3d", "porous2d_batch", "porous3d_adjoint",
-                                           "tadjoint3d", "ttg1d"), default="steady2d")
+                                           "tadjoint3d", "ttg1d", "interface2d"), default="steady2d")
     ap.add_argument("--max-iter", type=int, default=1000, help="iteration cap of the converged solves")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--gpus", type=int, default=1)
@@ -542,6 +604,9 @@ def main():
         return
     if args.workload == "ttg1d":
         bench_ttg(args)
+        return
+    if args.workload == "interface2d":
+        bench_interface(args)
         return
 
     import numpy as np

@@ -14,7 +14,7 @@ body are filled; the solid must percolate along x.
 """
 import numpy as np
 
-BC_THERMAL, BC_SPECULAR, BC_DIFFUSE, BC_PERIODIC = 0, 1, 2, 3
+BC_THERMAL, BC_SPECULAR, BC_DIFFUSE, BC_PERIODIC, BC_INTERFACE = 0, 1, 2, 3, 4
 LIM_NONE, LIM_MC, LIM_MINMOD = 0, 1, 2
 SCHEME_SEQUENTIAL, SCHEME_SYNTHETIC = 0, 1
 
@@ -143,6 +143,34 @@ def square2d_source_case(seed=1, n=256, n_bands=20, n_theta=2, n_phi=8):
     sig = 50e-9
     P = 1e17 * np.exp(-((x - L / 2) ** 2 + (y - L / 2) ** 2) / (2 * sig * sig))
     return dict(name="square2d_source", geometry=geo, material=mat, P=P, gamma=None,
+                limiter=LIM_NONE, scheme=SCHEME_SYNTHETIC)
+
+
+def interface2d_case(seed=5, n=256, n_bands=20, n_theta=2, n_phi=8):
+    """Two materials side by side in a 1 um square (the shape of the paper's
+    interface verification case): material A on the left half between a
+    thermalizing wall at 301 K and the interface, material B on the right
+    half between the interface and a wall at 299 K, specular top and bottom;
+    n/2 x n cells per half.  Both band tables are seeded draws (B with twice
+    the heat capacity, 0.4-0.9x the speeds, its own relaxation times); the
+    transmittances follow the diffuse-mismatch form per band,
+    beta_AB = C_B v_B / (C_A v_A + C_B v_B), beta_BA = 1 - beta_AB (which keeps
+    a uniform temperature in equilibrium)."""
+    rng = np.random.default_rng(seed)
+    ma = bands(rng, n_bands, 1e-12, 1e-9)
+    mb = bands(rng, n_bands, 1e-12, 1e-9)
+    mb["C"] = ma["C"] * 2.0
+    mb["v"] = ma["v"] * rng.uniform(0.4, 0.9, n_bands)
+    for m in (ma, mb):
+        m.update(n_theta=n_theta, n_phi=n_phi, Tref=300.0)
+    ga, gb = ma["C"] * ma["v"], mb["C"] * mb["v"]
+    beta_ab = gb / (ga + gb)
+    L, h = 1e-6, n // 2
+    spec = [BC_SPECULAR] * 4
+    gA = _geometry(2, (h, n), (L / 2, L), [BC_THERMAL, BC_INTERFACE] + spec, [301.0, 300.0] + [300.0] * 4)
+    gB = _geometry(2, (h, n), (L / 2, L), [BC_INTERFACE, BC_THERMAL] + spec, [300.0, 299.0] + [300.0] * 4)
+    ifc = dict(geo_a=0, face_a=1, geo_b=1, face_b=0, beta_ab=beta_ab, beta_ba=1.0 - beta_ab)
+    return dict(name="interface2d", geometries=[gA, gB], materials=[ma, mb], geo_mat=[0, 1], interfaces=[ifc],
                 limiter=LIM_NONE, scheme=SCHEME_SYNTHETIC)
 
 
