@@ -181,15 +181,15 @@ typedef struct {
  * geometries of different (or equal) materials.  The materials share
  * n_bands, n_theta, n_phi, T_ref and material_dim (band l of one is
  * matched with band l of the other across an interface); their C, v and
- * tau differ.  Supported: steady solves (both schemes, every limiter),
- * bte_moments, bte_residual and bte_keff of 1D and 2D geometries; every
- * geometry joined by an interface needs a thermalizing wall (the synthetic
- * correction and the initial guess couple the geometries across the
- * interfaces through the half cells in series with the interface
- * conductance sum_l beta C v H / Omega, averaged over the two directions).
- * BTE_ERR_UNSUPPORTED for 3D geometries with more than one material or an
- * interface, and, on such a problem, for transient steps and both
- * adjoints.  BTE_ERR_ARG for an invalid interface (face not set to
+ * tau differ.  Every geometry joined by an interface needs a thermalizing
+ * wall (BTE_ERR_UNSUPPORTED otherwise).  The synthetic correction and the
+ * initial guess couple the geometries across the interfaces through the
+ * half cells in series with the interface conductance
+ * sum_l beta C v H / Omega, averaged over the two directions.
+ * Supported on such a problem: steady solves (both schemes, every
+ * limiter, both 2D launch forms), transient steps, bte_moments,
+ * bte_residual and bte_keff, in 1D, 2D and 3D; BTE_ERR_UNSUPPORTED for the
+ * two adjoints.  BTE_ERR_ARG for an invalid interface (face not set to
  * BTE_BC_INTERFACE or used twice, faces that do not match, beta outside
  * [0, 1]), a BTE_BC_INTERFACE face without an interface, or materials that
  * differ in what they must share; otherwise as bte_setup.  bte_setup(geo,

@@ -900,10 +900,6 @@ bte_status bte_setup_multi(const bte_geometry *geo, int n_geo, const bte_materia
             p->err = "geo_mat out of range";
             return bail(BTE_ERR_ARG);
         }
-    if (geo[0].dim == 3 && (n_mat > 1 || n_ifc > 0)) {
-        p->err = "several materials or interfaces: 1D and 2D geometries only";
-        return bail(BTE_ERR_UNSUPPORTED);
-    }
     p->ctl = *ctl;
     if (p->ctl.precision != BTE_F32 && p->ctl.precision != BTE_F64) {
         p->err = "precision must be BTE_F32 or BTE_F64";
@@ -1926,7 +1922,6 @@ bte_status bte_transient_step(bte_problem *p, void *e_dev, int n_steps, double t
     if (!e_dev) FAIL(p, BTE_ERR_ARG, "e is null");
     if (n_steps < 0) FAIL(p, BTE_ERR_ARG, "n_steps < 0");
     if (pulse && !(pulse[1] > 0)) FAIL(p, BTE_ERR_ARG, "pulse FWHM must be > 0");
-    if (p->nmat > 1 || p->nifc > 0) FAIL(p, BTE_ERR_UNSUPPORTED, "transient steps: one material, no interface");
     {
         const bte_status cs = check_cfl(p);
         if (cs != BTE_OK) return cs;

@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void k_sweep3d(Dev d, const T *__restrict__ ei
         }
         r_gam = d.gamma[c];
         r_tl = (T)TLdev[c];   // ADJ: the isotropic closure term X
-        if constexpr (!ADJ) r_qs = (T)(*(d.P ? d.P + c : zd) / d.Ctot);   // P is null without a heat source
+        if constexpr (!ADJ) r_qs = (T)(*(d.P ? d.P + c : zd) / fm.Ctot);   // P is null without a heat source
         if constexpr (ADD) {
             // additive terms (units of C/4pi): pending correction plus the
             // periodic jump of the value as seen from this column

@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
         r_gam = d.gamma[c];
         r_tlT = (T)TLdev[c];
         r_gamT = (T)r_gam;
-        r_qsT = (T)(*(d.P ? d.P + c : zd) / d.Ctot);   // P is null without a heat source
+        r_qsT = (T)(*(d.P ? d.P + c : zd) / fm.Ctot);   // P is null without a heat source
     };
     auto rlt = [&](T v, int q) -> T {
         if constexpr (sizeof(T) == 4) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));

@@ -44,11 +44,19 @@ def B():
 def case_def(name):
     """(device geometries, union oracle geometry, material dicts, cell map):
     map[i] is the device cell of oracle cell i."""
+    nz = 1
     if name == "iface1d":
         nA, nB, ny, dim = 7, 9, 1, 1
         nth = dict(n_theta=4, n_phi=1)
         yb = [O.BC_SPECULAR, O.BC_SPECULAR]
         solid = None
+    elif name == "iface3d":
+        nA, nB, ny, nz, dim = 5, 6, 4, 7, 3
+        nth = dict(n_theta=2, n_phi=2)
+        yb = [O.BC_PERIODIC, O.BC_PERIODIC]
+        solid = np.ones((nz, ny, nA + nB), dtype=np.uint8)
+        solid[3, 1, 2] = 0       # a pore in A
+        solid[5, 2, nA] = 0      # a pore of B facing A across the interface
     else:
         nA, nB, ny, dim = 10, 13, 12, 2
         nth = dict(n_theta=2, n_phi=2)
@@ -59,27 +67,31 @@ def case_def(name):
         solid[8, nA] = 0         # a pore of B facing A across the interface
     ma, mb = dict(MAT_A, **nth), dict(MAT_B, **nth)
     T1, T2 = TREF + 1.0, TREF - 0.5
-    zb = [O.BC_SPECULAR, O.BC_SPECULAR]
+    zb = [O.BC_DIFFUSE, O.BC_SPECULAR]
+    if solid is not None and solid.ndim == 2:
+        solid = solid[None]
 
     def dev_geo(nx, lo, hi, Tlo, Thi, sol):
-        g = dict(dim=dim, n=[nx, ny, 1], len=[nx * H, ny * H, 1.0], bc=[lo, hi] + yb + zb,
-                 bcT=[Tlo, Thi] + [TREF] * 4, pdT=[0.0, 0.0, 0.0], pore_bc=O.BC_DIFFUSE)
+        g = dict(dim=dim, n=[nx, ny, nz], len=[nx * H, ny * H, nz * H if dim == 3 else 1.0],
+                 bc=[lo, hi] + yb + zb, bcT=[Tlo, Thi] + [TREF] * 4, pdT=[0.0, 0.0, 0.0], pore_bc=O.BC_DIFFUSE)
         if sol is not None:
             g["solid"] = np.ascontiguousarray(sol).reshape(-1)
         return g
 
-    gA = dev_geo(nA, O.BC_THERMAL, O.BC_INTERFACE, T1, TREF, None if solid is None else solid[:, :nA])
-    gB = dev_geo(nB, O.BC_INTERFACE, O.BC_THERMAL, TREF, T2, None if solid is None else solid[:, nA:])
+    gA = dev_geo(nA, O.BC_THERMAL, O.BC_INTERFACE, T1, TREF, None if solid is None else solid[:, :, :nA])
+    gB = dev_geo(nB, O.BC_INTERFACE, O.BC_THERMAL, TREF, T2, None if solid is None else solid[:, :, nA:])
     n = nA + nB
-    mat = np.zeros((ny, n), dtype=np.int32)
-    mat[:, nA:] = 1
-    gu = dict(dim=dim, n=[n, ny, 1], len=[n * H, ny * H, 1.0], bc=[O.BC_THERMAL, O.BC_THERMAL] + yb + zb,
-              bcT=[T1, T2] + [TREF] * 4, pdT=[0.0, 0.0, 0.0], pore_bc=O.BC_DIFFUSE,
-              solid=None if solid is None else solid.reshape(-1), mat=mat.reshape(-1))
-    cmap = np.empty(n * ny, dtype=np.int64)
-    for iy in range(ny):
-        for ix in range(n):
-            cmap[ix + n * iy] = ix + nA * iy if ix < nA else nA * ny + (ix - nA) + nB * iy
+    mat = np.zeros((nz, ny, n), dtype=np.int32)
+    mat[:, :, nA:] = 1
+    gu = dict(dim=dim, n=[n, ny, nz], len=[n * H, ny * H, nz * H if dim == 3 else 1.0],
+              bc=[O.BC_THERMAL, O.BC_THERMAL] + yb + zb, bcT=[T1, T2] + [TREF] * 4, pdT=[0.0, 0.0, 0.0],
+              pore_bc=O.BC_DIFFUSE, solid=None if solid is None else solid.reshape(-1), mat=mat.reshape(-1))
+    cmap = np.empty(n * ny * nz, dtype=np.int64)
+    for iz in range(nz):
+        for iy in range(ny):
+            for ix in range(n):
+                cmap[ix + n * (iy + ny * iz)] = (ix + nA * (iy + ny * iz) if ix < nA
+                                                 else nA * ny * nz + (ix - nA) + nB * (iy + ny * iz))
     return [gA, gB], gu, [ma, mb], cmap
 
 
@@ -119,7 +131,7 @@ def seeded(case, seed):
     return e.reshape(-1)
 
 
-CASES = ["iface1d", "iface2d"]
+CASES = ["iface1d", "iface2d", "iface3d"]
 
 
 @pytest.mark.parametrize("lim", [O.LIM_NONE, O.LIM_MC, O.LIM_MINMOD])
@@ -158,7 +170,7 @@ def test_interface_moments(B, name, prec):
 def test_interface_sweep_iterates_fp64(B, name, scheme, persistent):
     """Three source iterations from the same state (the synthetic scheme's
     correction couples the two geometries through the interface)."""
-    if persistent and name == "iface1d":
+    if persistent and name != "iface2d":
         pytest.skip("the one-launch sweep is the 2D register-tile form")
     case, prob, cmap = build(B, name, 1, scheme=scheme, max_iter=3, residual_temp=0.0, residual_flux=0.0,
                              cg_rtol=1e-13, cg_max_iter=20000)
@@ -194,9 +206,27 @@ def test_interface_steady_converged(B, name, prec):
     assert max(errs) < tol, errs
 
 
-def test_interface_refuses_transient_and_adjoint(B):
-    case, prob, cmap = build(B, "iface1d", 1, dt=1e-14)
+@pytest.mark.parametrize("lim", [O.LIM_NONE, O.LIM_MC])
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("name", CASES)
+def test_interface_transient_steps(B, name, prec, lim):
+    """Explicit steps (Algorithm 2): the interface inflow from the previous
+    step's outgoing fluxes of both sides."""
+    dt = 2e-13
+    case, prob, cmap = build(B, name, prec, limiter=lim, dt=dt)
+    e = seeded(case, 3)
+    eg = to_dev(prob, case, cmap, e)
+    e = to_orc(case, cmap, eg)
+    prob.transient_step(eg, 7, 0.0, None)
+    eo, _ = O.transient(case, e.copy(), 7, dt, 0.0, None)
+    err = rel_err(to_orc(case, cmap, eg), eo)
+    print(name, prec, lim, err)
+    assert err < (1e-11 if prec == 1 else 1e-5), err
+
+
+def test_interface_refuses_the_adjoint(B):
+    case, prob, cmap = build(B, "iface1d", 1, limiter=O.LIM_NONE, adjoint=1)
     eg = prob.zeros()
     with pytest.raises(B.BteError) as ex:
-        prob.transient_step(eg, 1)
+        prob.adjoint(eg)
     assert ex.value.status == B.BTE_ERR_UNSUPPORTED
