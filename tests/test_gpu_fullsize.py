@@ -15,6 +15,10 @@ times (the same tiles, columns, chunks and launches):
   x, diffuse pores) swept in one problem, FP32 and FP64: the three smallest
   films and the largest element by element against the oracle's sweep of
   each film alone (the films are independent);
+* one source iteration of the two-material interface workload (two
+  128 x 256 halves of a 1 um square joined by the interfacial boundary
+  condition, 128 directions, 20 bands per material), FP32 and FP64, element
+  by element against the oracle's sweep of the same two-material geometry;
 * the adjoint gradient d k_eff / d gamma of the 48^3 porous cube: FP64
   against central differences of the FP64 k_eff on 20 random cells, and
   the FP32 forward solve and adjoint behind autograd against FP64.
@@ -265,3 +269,67 @@ def test_full_size_adjoint_against_central_differences(B):
     err = float(np.abs(grad32 - grad64).max() / gmax)
     print("k_eff FP32", k32.item(), "FP64", k64, "grad FP32 vs FP64", err)
     assert abs(k32.item() / k64 - 1) < 1e-5 and err < 5e-5, (k32.item(), k64, err)
+
+
+_IFACE = {}
+
+
+def interface_reference():
+    """The interface workload as the oracle's one two-material geometry, a
+    seeded anisotropic FP32 state and the oracle's sweep of it; cmap[i] is
+    the device cell of oracle cell i."""
+    if "ref" not in _IFACE:
+        cfg = I.interface2d_case()
+        gA, gB = cfg["geometries"]
+        nA, nB, ny = gA["n"][0], gB["n"][0], gA["n"][1]
+        n = nA + nB
+        mat = np.zeros((ny, n), dtype=np.int32)
+        mat[:, nA:] = 1
+        gu = dict(dim=2, n=[n, ny, 1], len=[gA["len"][0] + gB["len"][0], gA["len"][1], 1.0],
+                  bc=[gA["bc"][0], gB["bc"][1]] + gA["bc"][2:], bcT=[gA["bcT"][0], gB["bcT"][1]] + gA["bcT"][2:],
+                  pdT=[0.0, 0.0, 0.0], solid=None, pore_bc=gA["pore_bc"], mat=mat.reshape(-1))
+        q = cfg["interfaces"][0]
+        beta = np.zeros((2, 2, len(q["beta_ab"])))
+        beta[0, 1], beta[1, 0] = q["beta_ab"], q["beta_ba"]
+        case = O.Case(gu, cfg["materials"], beta=beta)
+        rng = np.random.default_rng(102)
+        T = rng.uniform(-1.0, 1.0, case.nc)
+        C4 = case.C.reshape(case.nmat, case.nl)[case.mat] / (4 * np.pi)          # [nc, nl]
+        scale = 0.05 * np.abs(C4).max()
+        e0 = np.empty((case.nc, case.na, case.nl), dtype=np.float32)
+        for c0 in range(0, case.nc, 4096):
+            c1 = min(case.nc, c0 + 4096)
+            blk = T[c0:c1, None, None] * C4[c0:c1, None, :] + scale * rng.standard_normal((c1 - c0, case.na, case.nl))
+            e0[c0:c1] = blk.astype(np.float32)
+        e0 = e0.reshape(-1)
+        e1, st = O.steady(case, scheme=0, tol_T=0.0, tol_q=0.0, max_iter=1, e=e0.astype(np.float64))
+        assert st["iters"] == 1
+        cmap = np.empty(n * ny, dtype=np.int64)
+        iy, ix = np.divmod(np.arange(n * ny), n)
+        cmap[:] = np.where(ix < nA, ix + nA * iy, nA * ny + (ix - nA) + nB * iy)
+        _IFACE["ref"] = (cfg, case, cmap, e0, e1)
+    return _IFACE["ref"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_full_size_interface_sweep_matches_oracle(B, prec):
+    cfg, case, cmap, e0, e1 = interface_reference()
+    p = B.F32 if prec == "f32" else B.F64
+    prob = B.Problem(cfg["geometries"], cfg["materials"],
+                     dict(precision=p, scheme=B.SEQUENTIAL, limiter=B.LIM_NONE, max_iter=1, residual_temp=0.0,
+                          residual_flux=0.0),
+                     geo_mat=cfg["geo_mat"], interfaces=cfg["interfaces"])
+    prob.set_persistent(True)   # the form the bench keeps
+    ed = np.empty_like(e0.reshape(case.nc, -1))
+    ed[cmap] = e0.reshape(case.nc, -1)
+    e = torch.as_tensor(ed.reshape(-1), device="cuda").to(prob.dtype)
+    del ed
+    st = prob.steady_solve(e, init=False, allow_not_converged=True)
+    assert st["iters"] == 1 and st["updates"] == prob.n_unknowns
+    g = e.double().cpu().numpy().reshape(case.nc, -1)[cmap].reshape(-1)
+    del e, prob
+    torch.cuda.empty_cache()
+    err = rel(g, e1)
+    print(prec, "full-size interface sweep rel err", err)
+    assert err < (1e-5 if p == B.F32 else 1e-11), err
+
