@@ -307,8 +307,8 @@ bte_status bte_transient_adjoint(bte_problem *p, const void *e0_dev, int n_steps
                                  double *dJ_dgamma_dev, bte_solve_stats *stats, void *stream);
 
 /* Bytes of the checkpoint buffer of bte_transient_adjoint:
- * (ceil(n_steps / every) + every) states of e plus one double per cell and
- * checkpoint (0 on invalid arguments). */
+ * (ceil(n_steps / every) + every) states of e, each with one double per cell
+ * (its lattice temperature T_L), 0 on invalid arguments. */
 size_t bte_transient_adjoint_bytes(const bte_problem *p, int n_steps, int every);
 
 /* Device timers of bte_transient_step (off by default).  With on != 0 every

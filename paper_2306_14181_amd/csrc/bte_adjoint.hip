@@ -216,15 +216,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(Dev d, const T *__restrict_
 
 // Transposed explicit step of the transient adjoint (reverse mode of
 // e^{k+1} = e^k + dt R(e^k)):  lam^k = lam^{k+1} + dt J^T lam^{k+1}, with the
-// forward state e^k read alongside for the gradient.  Per (octant, cell) the
-// block writes five partial sums, part[(oct * 5 + q) * nc + cell]:
+// forward state e^k read alongside for the gradient and TLk = T_L(e^k), the
+// lattice temperature the forward step of e^k used.  Per (octant, cell) the
+// block writes two partial sums, part[(oct * 2 + q) * nc + cell]:
 //   q = 0: sum C/(4 pi) (1/tau) lam^k        (closure term of the next step)
-//   q = 1: sum lam^{k+1} e^k,  q = 2: sum lam^{k+1} C/(4 pi)
-//   q = 3: sum w e^k,          q = 4: sum w (1/tau) e^k   (T and T_L of e^k)
+//   q = 1: sum lam^{k+1} (C/(4 pi) T_L - e^k) + w X e^k
+// (the gradient's sums over (direction, band) in one: with X = Phi(lam^{k+1})
+// and T = sum w e^k / C_tot, the per-cell term -sum lam e + T_L sum lam C/4pi
+// + C_tot (T - T_L) X is q = 1 minus C_tot T_L X).
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_adj_step(Dev d, const T *__restrict__ lam, T *__restrict__ lout,
                                                   const T *__restrict__ ek, const double *__restrict__ X,
-                                                  const double *__restrict__ dinA,
+                                                  const double *__restrict__ TLk, const double *__restrict__ dinA,
                                                   const TileItem *__restrict__ items, int nitems, int3 tdim,
                                                   int na_oct, int nchunk_oct, int cap, double dt,
                                                   double *__restrict__ part)
@@ -240,7 +243,7 @@ __global__ __launch_bounds__(256) void k_adj_step(Dev d, const T *__restrict__ l
     const TileCtx t = tile_make(fm, d.dim, octant_sign(d, it.oct, na_oct, 0), octant_sign(d, it.oct, na_oct, 1),
                                 octant_sign(d, it.oct, na_oct, 2), it.tile, tdim);
     tile_tables<T>(t, fm, d, S, X, nullptr, false);
-    for (int i = threadIdx.x; i < 5 * 64; i += blockDim.x) S.mom[i] = 0.0;
+    for (int i = threadIdx.x; i < 2 * 64; i += blockDim.x) S.mom[i] = 0.0;
     __syncthreads();
     tile_modes<T>(t, d, S, true);
     const int loct = it.oct ^ ((1 << d.dim) - 1);
@@ -259,7 +262,7 @@ __global__ __launch_bounds__(256) void k_adj_step(Dev d, const T *__restrict__ l
         for (int i = wave; i < t.nt; i += 4) {
             const int c = uni(S.cell[i]);
             const bool solid = uni(S.code[i]) & kSolidBit;
-            double acc[5] = {0, 0, 0, 0, 0};
+            double acc[2] = {0, 0};
             if (active) {
                 if (solid) {
                     int up_out[3];
@@ -269,48 +272,57 @@ __global__ __launch_bounds__(256) void k_adj_step(Dev d, const T *__restrict__ l
                     const T ln = lc + tdt * (tf - lc * itc + (T)L.w * itc * (T)S.tl[i]);
                     lout[(size_t)c * d.nk + k] = ln;
                     const double x = (double)ek[(size_t)c * d.nk + k];
-                    const double itd = it0 + S.gam[i];
-                    acc[0] = c4 * itd * (double)ln;
-                    acc[1] = (double)lc * x;
-                    acc[2] = (double)lc * c4;
-                    acc[3] = L.w * x;
-                    acc[4] = L.w * itd * x;
+                    acc[0] = c4 * (it0 + S.gam[i]) * (double)ln;
+                    acc[1] = (double)lc * (c4 * TLk[c] - x) + L.w * X[c] * x;
                 } else {
                     lout[(size_t)c * d.nk + k] = (T)0;
                 }
             }
-            wave_sum_t<5>(acc);
+            wave_sum_t<2>(acc);
             if (lane == 0)
 #pragma unroll
-                for (int q = 0; q < 5; ++q) S.mom[5 * i + q] += acc[q];
+                for (int q = 0; q < 2; ++q) S.mom[2 * i + q] += acc[q];
         }
         __syncthreads();
     }
     for (int i = threadIdx.x; i < t.nt; i += blockDim.x)
 #pragma unroll
-        for (int q = 0; q < 5; ++q) part[((size_t)it.oct * 5 + q) * d.nc + S.cell[i]] = S.mom[5 * i + q];
+        for (int q = 0; q < 2; ++q) part[((size_t)it.oct * 2 + q) * d.nc + S.cell[i]] = S.mom[2 * i + q];
 }
 
-// Per cell after a transposed step: the next closure term Xn = Phi(lam^k) and
+// Per cell after a transposed step (two partials per octant, or per (octant,
+// chunk) column group, as the step kernels write them): the next closure
+// term Xn = Phi(lam^k) and
 //   grad += dt (-sum lam e + T_L sum lam C/4pi + C_tot (T - T_L) X)
-// with T, T_L the deviations of e^k and X = Phi(lam^{k+1}) (dR/dgamma as in
-// the steady gradient).
-__global__ void k_adj_step_post(Dev d, const double *__restrict__ part, int noct, const double *__restrict__ X,
-                                double *__restrict__ Xn, double *__restrict__ grad, double dt)
+//         = dt (part_1 - C_tot T_L X)
+// with T, T_L the deviations of e^k, T_L = TLk, and X = Phi(lam^{k+1})
+// (dR/dgamma as in the steady gradient).
+// 64 cells per block, the partials split over the four wavefronts as in
+// k_finalize_tl.
+__global__ __launch_bounds__(kBlock) void k_adj_step_post(Dev d, const double *__restrict__ part, int noct,
+                                                          const double *__restrict__ X,
+                                                          const double *__restrict__ TLk, double *__restrict__ Xn,
+                                                          double *__restrict__ grad, double dt)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.nc) return;
-    double s[5] = {0, 0, 0, 0, 0};
-    for (int o = 0; o < noct; ++o)
-        for (int q = 0; q < 5; ++q) s[q] += part[((size_t)o * 5 + q) * d.nc + c];
+    __shared__ double sh[2][4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
+    double s[2] = {0, 0};
+    if (c < d.nc)
+        for (int o = w; o < noct; o += 4)
+            for (int q = 0; q < 2; ++q) s[q] += part[((size_t)o * 2 + q) * d.nc + c];
+    sh[0][w][lane] = s[0];
+    sh[1][w][lane] = s[1];
+    __syncthreads();
+    if (w != 0 || c >= d.nc) return;
     if (!(d.code[c] & kSolidBit)) {
         Xn[c] = 0.0;
         return;
     }
-    const double Sc = d.S[c];
-    const double Td = s[3] / d.Ctot, TLd = s[4] / Sc;
-    grad[c] += dt * (-s[1] + TLd * s[2] + d.Ctot * (Td - TLd) * X[c]);
-    Xn[c] = s[0] / Sc;
+    const double s0 = (sh[0][0][lane] + sh[0][1][lane]) + (sh[0][2][lane] + sh[0][3][lane]);
+    const double s1 = (sh[1][0][lane] + sh[1][1][lane]) + (sh[1][2][lane] + sh[1][3][lane]);
+    grad[c] += dt * (s1 - d.Ctot * TLk[c] * X[c]);
+    Xn[c] = s0 / d.S[c];
 }
 
 // lam^N = dJ/de^N for J = sum_c a_c T_c / sum_c a_c:  a_c w / (A C_tot)
@@ -419,32 +431,35 @@ void launch_adj_grad(const Dev &d, const T *e, const T *psi, const double *Tdev,
 
 
 template <typename T, int DIM>
-void adj_step_launch(const Dev &d, const T *lam, T *lout, const T *ek, const double *X, const double *dinA,
-                     const TileItem *items, int nitems, int3 tdim, int na_oct, int nchunk_oct, int cap, double dt,
-                     double *part, hipStream_t s)
+void adj_step_launch(const Dev &d, const T *lam, T *lout, const T *ek, const double *X, const double *TLk,
+                     const double *dinA, const TileItem *items, int nitems, int3 tdim, int na_oct, int nchunk_oct,
+                     int cap, double dt, double *part, hipStream_t s)
 {
     const size_t sm = tile_smem_bytes(cap, sizeof(T), false);
     const int grid = (nitems + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_adj_step<T, DIM>), dim3(grid), dim3(256), sm, s, d, lam, lout, ek, X, dinA, items, nitems,
-                       tdim, na_oct, nchunk_oct, cap, dt, part);
+    hipLaunchKernelGGL((k_adj_step<T, DIM>), dim3(grid), dim3(256), sm, s, d, lam, lout, ek, X, TLk, dinA, items,
+                       nitems, tdim, na_oct, nchunk_oct, cap, dt, part);
 }
 
 template <typename T>
-hipError_t launch_adj_step(const Dev &d, const T *lam, T *lout, const T *ek, const double *X, const double *dinA,
-                           const TileItem *items, int nitems, int3 tdim, int na_oct, int nchunk_oct, int cap,
-                           double dt, double *part, hipStream_t s)
+hipError_t launch_adj_step(const Dev &d, const T *lam, T *lout, const T *ek, const double *X, const double *TLk,
+                           const double *dinA, const TileItem *items, int nitems, int3 tdim, int na_oct,
+                           int nchunk_oct, int cap, double dt, double *part, hipStream_t s)
 {
-    if (d.dim == 1) adj_step_launch<T, 1>(d, lam, lout, ek, X, dinA, items, nitems, tdim, na_oct, nchunk_oct, cap, dt, part, s);
-    if (d.dim == 2) adj_step_launch<T, 2>(d, lam, lout, ek, X, dinA, items, nitems, tdim, na_oct, nchunk_oct, cap, dt, part, s);
-    if (d.dim == 3) adj_step_launch<T, 3>(d, lam, lout, ek, X, dinA, items, nitems, tdim, na_oct, nchunk_oct, cap, dt, part, s);
+    if (d.dim == 1)
+        adj_step_launch<T, 1>(d, lam, lout, ek, X, TLk, dinA, items, nitems, tdim, na_oct, nchunk_oct, cap, dt, part, s);
+    if (d.dim == 2)
+        adj_step_launch<T, 2>(d, lam, lout, ek, X, TLk, dinA, items, nitems, tdim, na_oct, nchunk_oct, cap, dt, part, s);
+    if (d.dim == 3)
+        adj_step_launch<T, 3>(d, lam, lout, ek, X, TLk, dinA, items, nitems, tdim, na_oct, nchunk_oct, cap, dt, part, s);
     return hipGetLastError();
 }
 
-void launch_adj_step_post(const Dev &d, const double *part, int noct, const double *X, double *Xn, double *grad,
-                          double dt, hipStream_t s)
+void launch_adj_step_post(const Dev &d, const double *part, int noct, const double *X, const double *TLk, double *Xn,
+                          double *grad, double dt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adj_step_post, dim3((d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, part, noct, X, Xn,
-                       grad, dt);
+    hipLaunchKernelGGL(k_adj_step_post, dim3((d.nc + 63) / 64), dim3(kBlock), 0, s, d, part, noct, X, TLk, Xn, grad,
+                       dt);
 }
 
 template <typename T>
@@ -503,11 +518,11 @@ template void launch_adj_grad<double>(const Dev &, const double *, const double 
                                       const double *, double *, hipStream_t);
 
 template hipError_t launch_adj_step<float>(const Dev &, const float *, float *, const float *, const double *,
-                                           const double *, const TileItem *, int, int3, int, int, int, double, double *,
-                                           hipStream_t);
+                                           const double *, const double *, const TileItem *, int, int3, int, int, int,
+                                           double, double *, hipStream_t);
 template hipError_t launch_adj_step<double>(const Dev &, const double *, double *, const double *, const double *,
-                                            const double *, const TileItem *, int, int3, int, int, int, double,
-                                            double *, hipStream_t);
+                                            const double *, const double *, const TileItem *, int, int3, int, int, int,
+                                            double, double *, hipStream_t);
 template void launch_adj_tave_init<float>(const Dev &, const double *, double, float *, hipStream_t);
 template void launch_adj_tave_init<double>(const Dev &, const double *, double, double *, hipStream_t);
 template void launch_adj_phi_cell<float>(const Dev &, const float *, double *, hipStream_t);

@@ -54,16 +54,16 @@ template <typename T>
 hipError_t launch_transient3d(const Dev &, const T *, T *, const double *, const double *, const ColItem *, int, int,
                               int, double, double, double *, hipStream_t);
 template <typename T>
-hipError_t launch_adj_step(const Dev &, const T *, T *, const T *, const double *, const double *, const TileItem *,
-                           int, int3, int, int, int, double, double *, hipStream_t);
+hipError_t launch_adj_step(const Dev &, const T *, T *, const T *, const double *, const double *, const double *,
+                           const TileItem *, int, int3, int, int, int, double, double *, hipStream_t);
 template <typename T>
-hipError_t launch_adj_step3d(const Dev &, const T *, T *, const T *, const double *, const double *, const ColItem *,
-                             int, int, int, double, double *, hipStream_t);
+hipError_t launch_adj_step3d(const Dev &, const T *, T *, const T *, const double *, const double *, const double *,
+                             const ColItem *, int, int, int, double, double *, hipStream_t);
 template <typename T>
 hipError_t launch_adj_res3d(const Dev &, const T *, const double *, const double *, const ColItem *, int, int, int,
                             double *, hipStream_t);
-void launch_adj_step_post(const Dev &, const double *, int, const double *, double *, double *, double,
-                          hipStream_t);
+void launch_adj_step_post(const Dev &, const double *, int, const double *, const double *, double *, double *,
+                          double, hipStream_t);
 template <typename T> void launch_adj_tave_init(const Dev &, const double *, double, T *, hipStream_t);
 template <typename T> void launch_adj_phi_cell(const Dev &, const T *, double *, hipStream_t);
 void launch_tave(const Dev &, const double *, const double *, double *, hipStream_t);
@@ -1732,6 +1732,9 @@ bte_status tadj_impl(bte_problem *p, const T *e0, int n_steps, double t0, const 
     auto CTL = [&](int i) {
         return reinterpret_cast<double *>(ck + (size_t)(nseg + every) * bytes) + (size_t)i * p->nc;
     };
+    // T_L of the recomputed states of the current segment (slot 0 unused:
+    // the segment's first state is its checkpoint)
+    auto STL = [&](int j) { return CTL(nseg + j); };
     const size_t tlb = 8 * (size_t)p->nc;
     T *buf[2] = {(T *)p->psi, (T *)p->psi2};
     // forward pass with checkpoints
@@ -1769,21 +1772,24 @@ bte_status tadj_impl(bte_problem *p, const T *e0, int n_steps, double t0, const 
         const int start = sg * every, len = std::min(every, n_steps - start);
         HIPCHK(p, hipMemcpyAsync(SG(0), CK(sg), bytes, hipMemcpyDeviceToDevice, s));
         HIPCHK(p, hipMemcpyAsync(p->TL, CTL(sg), tlb, hipMemcpyDeviceToDevice, s));
-        for (int j = 1; j < len; ++j)
+        for (int j = 1; j < len; ++j) {
             HIPCHK(p, one_step<T>(p, SG(j - 1), SG(j), pulse_factor(pulse, t0 + (start + j - 1) * dt), nullptr, s));
+            HIPCHK(p, hipMemcpyAsync(STL(j), p->TL, tlb, hipMemcpyDeviceToDevice, s));
+        }
         for (int j = len - 1; j >= 0; --j) {
+            const double *tlk = j == 0 ? CTL(sg) : STL(j);
             launch_walls_adj<T>(d, lam[lc], p->d_wrec, p->d_wden, p->din, p->nw, s);
             int np = p->noct;
             if (p->dim == 3) {
-                HIPCHK(p, launch_adj_step3d<T>(d, lam[lc], lam[1 - lc], SG(j), X[lc], p->din, p->d_citems,
+                HIPCHK(p, launch_adj_step3d<T>(d, lam[lc], lam[1 - lc], SG(j), X[lc], tlk, p->din, p->d_citems,
                                                (int)p->citems.size(), p->na_oct, p->nchunk_oct, dt, p->part, s));
                 np = p->noct * p->nchunk_oct;
             } else {
-                HIPCHK(p, launch_adj_step<T>(d, lam[lc], lam[1 - lc], SG(j), X[lc], p->din, p->d_titems,
+                HIPCHK(p, launch_adj_step<T>(d, lam[lc], lam[1 - lc], SG(j), X[lc], tlk, p->din, p->d_titems,
                                              (int)p->titems.size(), p->tdim_tr, p->na_oct, p->nchunk_oct,
                                              p->tile_cap_tr, dt, p->part, s));
             }
-            launch_adj_step_post(d, p->part, np, X[lc], X[1 - lc], grad, dt, s);
+            launch_adj_step_post(d, p->part, np, X[lc], tlk, X[1 - lc], grad, dt, s);
             lc = 1 - lc;
         }
     }
@@ -1983,7 +1989,7 @@ size_t bte_transient_adjoint_bytes(const bte_problem *p, int n_steps, int every)
     if (!p || n_steps < 1 || every < 1) return 0;
     every = std::min(every, n_steps);
     const size_t nseg = (size_t)(n_steps + every - 1) / every;
-    return (nseg + (size_t)every) * p->esize() * p->nelem() + nseg * 8 * (size_t)p->nc;
+    return (nseg + (size_t)every) * (p->esize() * p->nelem() + 8 * (size_t)p->nc);
 }
 
 bte_status bte_transient_adjoint(bte_problem *p, const void *e0_dev, int n_steps, double t0, const double *pulse,

@@ -333,14 +333,25 @@ __global__ void k_finalize(Dev d, const double *__restrict__ part, int np, doubl
     if (qmag) qmag[c] = solid ? sqrt(s[2] * s[2] + s[3] * s[3] + s[4] * s[4]) : 0.0;
 }
 
-// T_L deviation from per-octant partials of sum w e/tau (transient step)
-__global__ void k_finalize_tl(Dev d, const double *__restrict__ part, int np, double *__restrict__ TLdev)
+// T_L deviation from per-octant (or per (octant, chunk)) partials of
+// sum w e/tau (transient step).  64 cells per block: wavefront w sums the
+// partials p = w mod 4 (four independent load chains per cell instead of
+// one), then the four sums are added in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_finalize_tl(Dev d, const double *__restrict__ part, int np,
+                                                        double *__restrict__ TLdev)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.nc) return;
+    __shared__ double sh[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
     double s = 0;
-    for (int p = 0; p < np; ++p) s += part[(size_t)p * d.nc + c];
-    TLdev[c] = (d.code[c] & kSolidBit) ? s / d.S[c] : 0.0;
+    if (c < d.nc)
+        for (int p = w; p < np; p += 4) s += part[(size_t)p * d.nc + c];
+    sh[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && c < d.nc) {
+        const double t = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+        TLdev[c] = (d.code[c] & kSolidBit) ? t / d.S[c] : 0.0;
+    }
 }
 
 // ---------------------------------------------------------------- diffuse walls
@@ -1004,7 +1015,7 @@ void launch_finalize(const Dev &d, const double *part, int np, double Tref, doub
 
 void launch_finalize_tl(const Dev &d, const double *part, int np, double *TLdev, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize_tl, dim3((d.nc + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, part, np, TLdev);
+    hipLaunchKernelGGL(k_finalize_tl, dim3((d.nc + 63) / 64), dim3(kBlock), 0, s, d, part, np, TLdev);
 }
 
 void launch_steady_post(const Dev &d, const double *part, int np, const double *TLn, double *TLkin, double *Tnew,

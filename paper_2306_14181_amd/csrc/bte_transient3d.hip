@@ -315,10 +315,12 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
 // limiter, no jumps: the transposed operator is linear).  Walls: a specular
 // wall feeds the mirror lane's lam, a diffuse wall the record dinA (k_walls_adj)
 // with weight w |s_a|, at the wall cell (3/2 or 1) and at its neighbour (-1/2).
-// Per (octant, chunk, cell) five partial sums go to
-// part[((octant * nchunk + chunk) * 5 + q) * nc + cell]:
-//   q = 0: sum C/(4 pi) (1/tau) lam^k,  q = 1: sum lam^{k+1} e^k,
-//   q = 2: sum lam^{k+1} C/(4 pi),      q = 3: sum w e^k,  q = 4: sum w (1/tau) e^k.
+// TLk = T_L(e^k), the lattice temperature the forward step of e^k used.
+// Per (octant, chunk, cell) two partial sums go to
+// part[((octant * nchunk + chunk) * 2 + q) * nc + cell]:
+//   q = 0: sum C/(4 pi) (1/tau) lam^k,
+//   q = 1: sum lam^{k+1} (C/(4 pi) T_L - e^k) + w X e^k  (the gradient's sums
+//          over (direction, band), combined as in k_adj_step).
 
 // RES: the transposed residual of the steady adjoint iteration instead of a
 // transposed step (no output field, no forward state):
@@ -329,13 +331,14 @@ __global__ __launch_bounds__(256) void k_transient3d(Dev d, const T *__restrict_
 template <typename T, bool RES>
 __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__ lam, T *__restrict__ lout,
                                                     const T *__restrict__ ek, const double *__restrict__ X,
-                                                    const double *__restrict__ dinA,
+                                                    const double *__restrict__ TLk, const double *__restrict__ dinA,
                                                     const ColItem *__restrict__ items, int nitems, int na_oct,
                                                     int nchunk_oct, double dt, double *__restrict__ part)
 {
-    // five partials of four consecutive cells per wavefront, reduced
+    // two partials of four consecutive cells per wavefront, reduced
     // transposed (lane = 16 cell + part) every four cells
-    __shared__ double red[4][5][4][64];
+    constexpr int NP = 2;
+    __shared__ double red[4][NP][4][64];
     const int nb = gridDim.x, bb = blockIdx.x;
     const int lb = (bb & 7) * (nb >> 3) + (bb >> 3);
     const int wi = lb * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -430,7 +433,7 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
     // and of its frame-upwind / frame-downwind neighbours along x, y, z,
     // the closure term X and gamma
     uint32_t r_code = 0, r_cxu = 0, r_cyu = 0, r_cxd = 0, r_cyd = 0, r_czu = 0, r_czd = 0, r_mode = 0;
-    double r_X = 0, r_gam = 0;
+    double r_X = 0, r_gam = 0, r_tl = 0;
     auto records = [&](int f0) {
         const int fl = min(f0 + lane, n2 - 1);
         const int o = plane * (sg2 > 0 ? fl : n2 - 1 - fl);
@@ -448,6 +451,7 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
         r_czd = cd >= 0 ? czd : 0u;
         r_X = X[c];
         r_gam = d.gamma[c];
+        if constexpr (!RES) r_tl = TLk[c];
         // bit 0 solid, bit 1 the interior transposed stencil on every axis
         // (two cells on each side where the forward stencil reaches)
         auto inner = [&](int a, int sg, uint32_t cu_, uint32_t cd_) {
@@ -459,7 +463,6 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
         r_mode = ((r_code & kSolidBit) ? 1u : 0u) | (all ? 2u : 0u);
     };
     auto rlu = [&](uint32_t v, int q) -> uint32_t { return (uint32_t)__builtin_amdgcn_readlane((int)v, q); };
-    constexpr int NP = RES ? 2 : 5;
     double *__restrict__ pbase = part + (size_t)((it.oct * nchunk_oct + it.chunk) * NP) * nc;
     const double gfac = fm.pdT[0] != 0.0 ? fm.len[0] / (fm.pdT[0] * fm.ncell) : 0.0;
     const T gl = (T)(gfac * L.wv[0]);
@@ -472,7 +475,7 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
         const uint32_t mode = rlu(r_mode, q);
         const bool solid = mode & 1u;
         T ln = (T)0;
-        double acc[5] = {0, 0, 0, 0, 0};
+        double acc[NP] = {0, 0};
         if (solid) {
           const double Xc = rl_d(r_X, q), gam = rl_d(r_gam, q);
           T tf;
@@ -525,12 +528,9 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
             } else {
                 ln = zc + tdt * (tf - zc * itc + (T)L.w * itc * (T)Xc);
                 if (active) {
-                    const double xe = (double)in.e, itd = it0 + gam;
-                    acc[0] = c4 * itd * (double)ln;
-                    acc[1] = (double)zc * xe;
-                    acc[2] = (double)zc * c4;
-                    acc[3] = L.w * xe;
-                    acc[4] = L.w * itd * xe;
+                    const double xe = (double)in.e;
+                    acc[0] = c4 * (it0 + gam) * (double)ln;
+                    acc[1] = (double)zc * (c4 * rl_d(r_tl, q) - xe) + L.w * Xc * xe;
                 }
             }
         }
@@ -583,14 +583,14 @@ __global__ __launch_bounds__(256) void k_adj_step3d(Dev d, const T *__restrict__
 }
 
 template <typename T>
-hipError_t launch_adj_step3d(const Dev &d, const T *lam, T *lout, const T *ek, const double *X, const double *dinA,
-                             const ColItem *items, int nitems, int na_oct, int nchunk_oct, double dt, double *part,
-                             hipStream_t s)
+hipError_t launch_adj_step3d(const Dev &d, const T *lam, T *lout, const T *ek, const double *X, const double *TLk,
+                             const double *dinA, const ColItem *items, int nitems, int na_oct, int nchunk_oct,
+                             double dt, double *part, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
     const int blocks = ((nitems + 3) / 4 + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_adj_step3d<T, false>), dim3(blocks), dim3(256), 0, s, d, lam, lout, ek, X, dinA, items,
-                       nitems, na_oct, nchunk_oct, dt, part);
+    hipLaunchKernelGGL((k_adj_step3d<T, false>), dim3(blocks), dim3(256), 0, s, d, lam, lout, ek, X, TLk, dinA,
+                       items, nitems, na_oct, nchunk_oct, dt, part);
     return hipGetLastError();
 }
 
@@ -600,8 +600,8 @@ hipError_t launch_adj_res3d(const Dev &d, const T *psi, const double *X, const d
 {
     if (nitems <= 0) return hipSuccess;
     const int blocks = ((nitems + 3) / 4 + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_adj_step3d<T, true>), dim3(blocks), dim3(256), 0, s, d, psi, nullptr, nullptr, X, dinA,
-                       items, nitems, na_oct, nchunk_oct, 0.0, part);
+    hipLaunchKernelGGL((k_adj_step3d<T, true>), dim3(blocks), dim3(256), 0, s, d, psi, nullptr, nullptr, X, nullptr,
+                       dinA, items, nitems, na_oct, nchunk_oct, 0.0, part);
     return hipGetLastError();
 }
 
@@ -611,11 +611,11 @@ template hipError_t launch_adj_res3d<double>(const Dev &, const double *, const 
                                              const ColItem *, int, int, int, double *, hipStream_t);
 
 template hipError_t launch_adj_step3d<float>(const Dev &, const float *, float *, const float *, const double *,
-                                             const double *, const ColItem *, int, int, int, double, double *,
-                                             hipStream_t);
+                                             const double *, const double *, const ColItem *, int, int, int, double,
+                                             double *, hipStream_t);
 template hipError_t launch_adj_step3d<double>(const Dev &, const double *, double *, const double *, const double *,
-                                              const double *, const ColItem *, int, int, int, double, double *,
-                                              hipStream_t);
+                                              const double *, const double *, const ColItem *, int, int, int, double,
+                                              double *, hipStream_t);
 
 template <typename T, int LIM>
 void transient3d_launch(const Dev &d, const T *ein, T *eout, const double *TLdev, const double *din,
