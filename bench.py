@@ -551,14 +551,31 @@ def bench_tadjoint(args):
     J, grad, st = prob.transient_adjoint(prob.zeros(), n, w, 0.0, cfg["pulse"], every=50)
     torch.cuda.synchronize()
     ta = time.perf_counter() - t0
-    log("tadjoint3d: forward %d steps %.3f s, adjoint (forward + recompute + reverse) %.3f s" % (n, tf, ta))
+    back = st["ms_post"] / 1e3
+    log("tadjoint3d: forward %d steps %.3f s, adjoint (forward + recompute + reverse) %.3f s, backward pass %.3f s"
+        % (n, tf, ta, back))
+    # the same adjoint with the smallest checkpoint interval that fits in
+    # 90 % of the free device memory (fewer recomputed steps)
+    free, _ = torch.cuda.mem_get_info()
+    every_hbm = prob.transient_adjoint_interval(n, int(0.9 * free))
+    hbm = None
+    if every_hbm > 0:
+        t0 = time.perf_counter()
+        J2, grad2, st2 = prob.transient_adjoint(prob.zeros(), n, w, 0.0, cfg["pulse"], every=every_hbm)
+        torch.cuda.synchronize()
+        ta2 = time.perf_counter() - t0
+        hbm = {"every": every_hbm, "buffer_GB": prob.transient_adjoint_bytes(n, every_hbm) / 1e9,
+               "adjoint_s": ta2, "over_forward": ta2 / tf, "backward_over_forward": st2["ms_post"] / 1e3 / tf,
+               "same_gradient": bool(torch.equal(grad, grad2)) and J2 == J}
+        log("tadjoint3d: checkpoints every %d (%.1f GB): adjoint %.3f s, gradient identical: %s"
+            % (every_hbm, hbm["buffer_GB"], ta2, hbm["same_gradient"]))
     out = {"metric": "transient adjoint cost (checkpointed reverse mode) over the forward run",
            "value": ta / tf, "unit": "ratio", "n_gpus": 1, "higher_is_better": False,
            "dtype": "f32 (e, lambda), f64 (moments, gradient)", "data": "synthetic (seeded bands, laser pulse)",
            "config": {"workload": "tadjoint3d: 32^3 cells of (2 um)^3, 128 directions, 40 bands, 500 steps, "
                                   "checkpoints every 50, limiter NONE"},
-           "forward_s": tf, "adjoint_s": ta, "J": J,
-           "forward_updates_per_s": prob.n_unknowns * n / tf}
+           "forward_s": tf, "adjoint_s": ta, "backward_s": back, "backward_over_forward": back / tf, "J": J,
+           "forward_updates_per_s": prob.n_unknowns * n / tf, "hbm_sized_interval": hbm}
     print(json.dumps(out), flush=True)
 
 

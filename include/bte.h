@@ -292,24 +292,37 @@ bte_status bte_adjoint(bte_problem *p, const void *e_dev, int objective, double 
 /* Transient adjoint (reverse mode of n_steps explicit steps, Sec. 4.1,
  * Algorithm 2) for J = sum_c a_c T_c(e^N) / sum_c a_c, the weighted mean
  * local temperature after the last step.  e0_dev: start state (not
- * modified); weights_dev: device double[n_cells] a_c >= 0 with a positive
- * sum; pulse as in bte_transient_step.  The forward pass keeps e every
- * `every` steps in ckpt_dev (device memory of at least
- * bte_transient_adjoint_bytes(p, n_steps, every) bytes, 256-byte aligned,
- * owned by the caller and overwritten); the backward pass recomputes one
- * segment of `every` states at a time and runs the transposed steps with the
- * gradient accumulated on the fly.  Writes J (host, may be NULL) and
- * dJ/dgamma per cell (device double[n_cells]).  Requires control.adjoint != 0
- * at setup, limiter NONE and a stable dt (BTE_ERR_CFL).  Synchronous. */
+ * modified; read again by the backward pass); weights_dev: device
+ * double[n_cells] a_c >= 0 with a positive sum; pulse as in
+ * bte_transient_step.  The forward pass writes e every `every` steps into
+ * ckpt_dev (device memory of at least bte_transient_adjoint_bytes(p,
+ * n_steps, every) bytes, 256-byte aligned, owned by the caller and
+ * overwritten); the backward pass recomputes one segment of `every` states
+ * at a time and runs the transposed steps with the gradient accumulated on
+ * the fly.  Writes J (host, may be NULL) and dJ/dgamma per cell (device
+ * double[n_cells]).  stats: iters = n_steps, updates = forward, recomputed
+ * and transposed steps times the unknowns, ms_sweep = device time of the
+ * forward pass (with J), ms_post = device time of the backward pass.
+ * Requires control.adjoint != 0 at setup, limiter NONE and a stable dt
+ * (BTE_ERR_CFL).  Synchronous. */
 bte_status bte_transient_adjoint(bte_problem *p, const void *e0_dev, int n_steps, double t0,
                                  const double *pulse, const double *weights_dev, int every,
                                  void *ckpt_dev, size_t ckpt_bytes, double *J_host,
                                  double *dJ_dgamma_dev, bte_solve_stats *stats, void *stream);
 
-/* Bytes of the checkpoint buffer of bte_transient_adjoint:
- * (ceil(n_steps / every) + every) states of e, each with one double per cell
- * (its lattice temperature T_L), 0 on invalid arguments. */
+/* Bytes of the checkpoint buffer of bte_transient_adjoint, with
+ * m = ceil(n_steps / every) (every clamped to n_steps):
+ * (m + every - 2) states of e (checkpoints 1 .. m - 1, the recomputed
+ * states of one segment) plus (m + every - 1) doubles per cell (T_L of the
+ * checkpoints and of the recomputed states); 0 on invalid arguments. */
 size_t bte_transient_adjoint_bytes(const bte_problem *p, int n_steps, int every);
+
+/* The smallest checkpoint interval whose buffer fits in max_bytes (0 if
+ * none, or on invalid arguments).  The backward pass recomputes
+ * n_steps - ceil(n_steps / every) forward steps, so the smallest interval
+ * that fits is the fastest: with the state in HBM-sized buffers, every = 1
+ * (nothing recomputed) needs n_steps - 1 states, every = 2 about half. */
+int bte_transient_adjoint_interval(const bte_problem *p, int n_steps, size_t max_bytes);
 
 /* Device timers of bte_transient_step (off by default).  With on != 0 every
  * step records HIP events around its wall, transport and T_L kernels, and

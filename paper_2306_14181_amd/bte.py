@@ -29,6 +29,7 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_UNSUPPORTED", 3: "ERR_HIP", 4: "E
 EXPORTS = ["bte_setup", "bte_setup_multi", "bte_set_control", "bte_workspace_bytes", "bte_num_unknowns", "bte_num_cells", "bte_num_directions",
            "bte_bind", "bte_set_fields", "bte_moments", "bte_moments_static", "bte_residual", "bte_transient_step",
            "bte_steady_solve", "bte_keff", "bte_adjoint", "bte_transient_adjoint", "bte_transient_adjoint_bytes",
+           "bte_transient_adjoint_interval",
            "bte_set_timing", "bte_set_graphs", "bte_set_persistent", "bte_tile_candidates", "bte_set_tiles",
            "bte_autotune", "bte_last_stats",
            "bte_get_directions", "bte_band_discretize", "bte_band_discretize_dev",
@@ -112,6 +113,7 @@ def load():
         "bte_transient_adjoint": ([vp, vp, C.c_int, C.c_double, dp, vp, C.c_int, vp, C.c_size_t, dp, vp,
                                    C.POINTER(SolveStats), vp], st),
         "bte_transient_adjoint_bytes": ([vp, C.c_int, C.c_int], C.c_size_t),
+        "bte_transient_adjoint_interval": ([vp, C.c_int, C.c_size_t], C.c_int),
         "bte_set_timing": ([vp, C.c_int], st),
         "bte_set_graphs": ([vp, C.c_int], st),
         "bte_set_persistent": ([vp, C.c_int], st),
@@ -388,6 +390,16 @@ class Problem:
             pl = (C.c_double * 2)(float(pulse[0]), float(pulse[1]))
         self._check(load().bte_transient_step(self._h, self._e(e), int(n_steps), float(t0), pl, _stream()))
         return e
+
+    def transient_adjoint_bytes(self, n_steps, every):
+        """Bytes of the checkpoint buffer for n_steps with checkpoints every
+        `every` steps (0 on invalid arguments)."""
+        return int(load().bte_transient_adjoint_bytes(self._h, int(n_steps), int(every)))
+
+    def transient_adjoint_interval(self, n_steps, max_bytes):
+        """The smallest checkpoint interval whose buffer fits in max_bytes
+        (0 if none)."""
+        return int(load().bte_transient_adjoint_interval(self._h, int(n_steps), C.c_size_t(int(max_bytes))))
 
     def transient_adjoint(self, e0, n_steps, weights, t0=0.0, pulse=None, every=50):
         """J = sum a T(e^N) / sum a after n_steps explicit steps from e0, and

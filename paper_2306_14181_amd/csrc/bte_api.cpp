@@ -1725,43 +1725,50 @@ bte_status tadj_impl(bte_problem *p, const T *e0, int n_steps, double t0, const 
     const size_t bytes = p->esize() * p->nelem();
     const int nseg = (n_steps + every - 1) / every;
     const double dt = p->ctl.dt;
-    auto CK = [&](int i) { return reinterpret_cast<T *>(ck + (size_t)i * bytes); };
-    auto SG = [&](int j) { return reinterpret_cast<T *>(ck + (size_t)(nseg + j) * bytes); };
-    // T_L of each checkpoint, so that a recomputed segment repeats the
-    // forward pass bit for bit
+    // checkpoints 1 .. nseg - 1 (the state after i * every steps; checkpoint
+    // 0 is e0 itself, read in place), then the recomputed states
+    // 1 .. every - 1 of the current segment
+    auto CK = [&](int i) -> T * { return reinterpret_cast<T *>(ck + (size_t)(i - 1) * bytes); };
+    auto SG = [&](int j) -> T * { return reinterpret_cast<T *>(ck + (size_t)(nseg - 2 + j) * bytes); };
+    // T_L of each checkpoint 0 .. nseg - 1, so that a recomputed segment
+    // repeats the forward pass bit for bit, then T_L of the recomputed
+    // states 1 .. every - 1 (the lattice temperature each transposed step
+    // needs)
     auto CTL = [&](int i) {
-        return reinterpret_cast<double *>(ck + (size_t)(nseg + every) * bytes) + (size_t)i * p->nc;
+        return reinterpret_cast<double *>(ck + (size_t)(nseg + every - 2) * bytes) + (size_t)i * p->nc;
     };
-    // T_L of the recomputed states of the current segment (slot 0 unused:
-    // the segment's first state is its checkpoint)
-    auto STL = [&](int j) { return CTL(nseg + j); };
+    auto STL = [&](int j) { return CTL(nseg - 1 + j); };
     const size_t tlb = 8 * (size_t)p->nc;
     T *buf[2] = {(T *)p->psi, (T *)p->psi2};
-    // forward pass with checkpoints
-    HIPCHK(p, hipMemcpyAsync(CK(0), e0, bytes, hipMemcpyDeviceToDevice, s));
-    HIPCHK(p, hipMemcpyAsync(buf[0], e0, bytes, hipMemcpyDeviceToDevice, s));
+    while (p->tev.size() < 3) {
+        hipEvent_t x;
+        HIPCHK(p, hipEventCreate(&x));
+        p->tev.push_back(x);
+    }
+    HIPCHK(p, hipEventRecord(p->tev[0], s));
+    // forward pass: a step whose result is a checkpoint writes it in place
     launch_moments<T>(d, e0, nullptr, p->part, s);
     launch_finalize(d, p->part, 1, p->Tref, nullptr, nullptr, nullptr, p->TL, nullptr, nullptr, s);
     HIPCHK(p, hipMemcpyAsync(CTL(0), p->TL, tlb, hipMemcpyDeviceToDevice, s));
-    int c = 0;
+    const T *cur = e0;
     for (int n = 0; n < n_steps; ++n) {
-        HIPCHK(p, one_step<T>(p, buf[c], buf[1 - c], pulse_factor(pulse, t0 + n * dt), nullptr, s));
-        c = 1 - c;
-        if ((n + 1) % every == 0 && n + 1 < n_steps) {
-            HIPCHK(p, hipMemcpyAsync(CK((n + 1) / every), buf[c], bytes, hipMemcpyDeviceToDevice, s));
-            HIPCHK(p, hipMemcpyAsync(CTL((n + 1) / every), p->TL, tlb, hipMemcpyDeviceToDevice, s));
-        }
+        const bool keep = (n + 1) % every == 0 && n + 1 < n_steps;
+        T *dst = keep ? CK((n + 1) / every) : (cur == buf[0] ? buf[1] : buf[0]);
+        HIPCHK(p, one_step<T>(p, cur, dst, pulse_factor(pulse, t0 + n * dt), nullptr, s));
+        cur = dst;
+        if (keep) HIPCHK(p, hipMemcpyAsync(CTL((n + 1) / every), p->TL, tlb, hipMemcpyDeviceToDevice, s));
     }
     // J from the final state
-    launch_moments<T>(d, buf[c], nullptr, p->part, s);
+    launch_moments<T>(d, cur, nullptr, p->part, s);
     launch_finalize(d, p->part, 1, p->Tref, p->T1, nullptr, nullptr, nullptr, nullptr, nullptr, s);
     launch_tave(d, a, p->T1, p->fmean, s);
+    HIPCHK(p, hipEventRecord(p->tev[1], s));
     double jt[2];
     HIPCHK(p, hipMemcpyAsync(jt, p->fmean, 16, hipMemcpyDeviceToHost, s));
     HIPCHK(p, hipStreamSynchronize(s));
     if (!(jt[1] > 0)) FAIL(p, BTE_ERR_ARG, "weights must have a positive sum");
     if (J_host) *J_host = jt[0];
-    // backward pass
+    // backward pass (the two step buffers now hold lambda)
     T *lam[2] = {buf[0], buf[1]};
     double *X[2] = {p->adjX, p->adju};
     launch_adj_tave_init<T>(d, a, 1.0 / jt[1], lam[0], s);
@@ -1770,10 +1777,11 @@ bte_status tadj_impl(bte_problem *p, const T *e0, int n_steps, double t0, const 
     int lc = 0;
     for (int sg = nseg - 1; sg >= 0; --sg) {
         const int start = sg * every, len = std::min(every, n_steps - start);
-        HIPCHK(p, hipMemcpyAsync(SG(0), CK(sg), bytes, hipMemcpyDeviceToDevice, s));
+        const T *first = sg == 0 ? e0 : CK(sg);
+        auto state = [&](int j) -> const T * { return j == 0 ? first : SG(j); };
         HIPCHK(p, hipMemcpyAsync(p->TL, CTL(sg), tlb, hipMemcpyDeviceToDevice, s));
         for (int j = 1; j < len; ++j) {
-            HIPCHK(p, one_step<T>(p, SG(j - 1), SG(j), pulse_factor(pulse, t0 + (start + j - 1) * dt), nullptr, s));
+            HIPCHK(p, one_step<T>(p, state(j - 1), SG(j), pulse_factor(pulse, t0 + (start + j - 1) * dt), nullptr, s));
             HIPCHK(p, hipMemcpyAsync(STL(j), p->TL, tlb, hipMemcpyDeviceToDevice, s));
         }
         for (int j = len - 1; j >= 0; --j) {
@@ -1781,11 +1789,11 @@ bte_status tadj_impl(bte_problem *p, const T *e0, int n_steps, double t0, const 
             launch_walls_adj<T>(d, lam[lc], p->d_wrec, p->d_wden, p->din, p->nw, s);
             int np = p->noct;
             if (p->dim == 3) {
-                HIPCHK(p, launch_adj_step3d<T>(d, lam[lc], lam[1 - lc], SG(j), X[lc], tlk, p->din, p->d_citems,
+                HIPCHK(p, launch_adj_step3d<T>(d, lam[lc], lam[1 - lc], state(j), X[lc], tlk, p->din, p->d_citems,
                                                (int)p->citems.size(), p->na_oct, p->nchunk_oct, dt, p->part, s));
                 np = p->noct * p->nchunk_oct;
             } else {
-                HIPCHK(p, launch_adj_step<T>(d, lam[lc], lam[1 - lc], SG(j), X[lc], tlk, p->din, p->d_titems,
+                HIPCHK(p, launch_adj_step<T>(d, lam[lc], lam[1 - lc], state(j), X[lc], tlk, p->din, p->d_titems,
                                              (int)p->titems.size(), p->tdim_tr, p->na_oct, p->nchunk_oct,
                                              p->tile_cap_tr, dt, p->part, s));
             }
@@ -1793,12 +1801,18 @@ bte_status tadj_impl(bte_problem *p, const T *e0, int n_steps, double t0, const 
             lc = 1 - lc;
         }
     }
+    HIPCHK(p, hipEventRecord(p->tev[2], s));
     HIPCHK(p, hipGetLastError());
     HIPCHK(p, hipStreamSynchronize(s));
     bte_solve_stats st{};
     st.iters = n_steps;
-    st.updates = 3.0 * (double)n_steps * (double)p->nelem();   // forward, recompute, transposed steps
+    st.updates = (double)(2 * n_steps - nseg + n_steps) * (double)p->nelem();   // forward, recompute, transposed
     st.converged = 1;
+    float ms[2];
+    HIPCHK(p, hipEventElapsedTime(&ms[0], p->tev[0], p->tev[1]));
+    HIPCHK(p, hipEventElapsedTime(&ms[1], p->tev[1], p->tev[2]));
+    st.ms_sweep = ms[0];
+    st.ms_post = ms[1];
     st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
     p->last = st;
     if (stats) *stats = st;
@@ -1989,7 +2003,18 @@ size_t bte_transient_adjoint_bytes(const bte_problem *p, int n_steps, int every)
     if (!p || n_steps < 1 || every < 1) return 0;
     every = std::min(every, n_steps);
     const size_t nseg = (size_t)(n_steps + every - 1) / every;
-    return (nseg + (size_t)every) * (p->esize() * p->nelem() + 8 * (size_t)p->nc);
+    return (nseg + (size_t)every - 2) * p->esize() * p->nelem() + (nseg + (size_t)every - 1) * 8 * (size_t)p->nc;
+}
+
+int bte_transient_adjoint_interval(const bte_problem *p, int n_steps, size_t max_bytes)
+{
+    if (!p || n_steps < 1) return 0;
+    // the recompute costs n_steps - ceil(n_steps / every) steps: the
+    // smallest interval that fits is the fastest (the size is not monotonic
+    // in the interval, hence the scan)
+    for (int every = 1; every <= n_steps; ++every)
+        if (bte_transient_adjoint_bytes(p, n_steps, every) <= max_bytes) return every;
+    return 0;
 }
 
 bte_status bte_transient_adjoint(bte_problem *p, const void *e0_dev, int n_steps, double t0, const double *pulse,

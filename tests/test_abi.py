@@ -260,3 +260,33 @@ def test_setup_multi_validates_interfaces(lib, what):
     expect = {"ok": 0, "3d": 0, "floating": 2}.get(what, 1)
     assert st == expect, (what, lib.bte_last_error(h))
     lib.bte_destroy(h)
+
+
+def test_transient_adjoint_buffer_and_interval(lib):
+    """Checkpoint buffer of the transient adjoint: (m + every - 2) states and
+    (m + every - 1) T_L fields for m = ceil(n / every); the interval helper
+    returns the smallest interval that fits a byte budget."""
+    b = I.bands(0, 2)
+    g = geo(3, (4, 4, 4), (1e-7,) * 3, [I.BC_THERMAL] * 6)
+    st, h = _setup(lib, g, mat(b, 2, 2), dict(precision=1, dt=1e-13, adjoint=1))
+    assert st == 0, lib.bte_last_error(h)
+    nc = lib.bte_num_cells(h)
+    S = 8 * lib.bte_num_unknowns(h)
+    size = lambda n, e: lib.bte_transient_adjoint_bytes(h, n, e)
+    for n, e in ((500, 50), (500, 1), (500, 2), (7, 3), (1, 1), (5, 9)):
+        ee = min(e, n)
+        m = -(-n // ee)
+        assert size(n, e) == (m + ee - 2) * S + (m + ee - 1) * 8 * nc, (n, e)
+    assert size(500, 0) == 0 and size(0, 5) == 0
+    pick = lambda n, budget: lib.bte_transient_adjoint_interval(h, n, C.c_size_t(budget))
+    assert pick(500, size(500, 1)) == 1
+    assert pick(500, size(500, 1) - 1) == 2
+    sizes = [size(500, e) for e in range(1, 501)]
+    smallest = min(sizes)
+    assert sizes.index(smallest) + 1 == 20          # 43 states at every = 20, 21, 22
+    assert pick(500, smallest) == 20
+    assert pick(500, smallest - 1) == 0
+    for budget in (size(500, 3), size(500, 7) + 12345, size(500, 40)):
+        e = pick(500, budget)
+        assert size(500, e) <= budget and all(size(500, j) > budget for j in range(1, e))
+    lib.bte_destroy(h)
