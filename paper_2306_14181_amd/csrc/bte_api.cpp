@@ -499,13 +499,13 @@ int3 lds_tdim(const bte_problem *p) { return reg2d(p) ? make_int3(8, 8, 1) : p->
 // sweep, at most 48 cells in the first upwind halo layers of all axes (the
 // LDS buffer of upwind increments has 48 rows).
 // A 3D sweep segment addresses its rows by 32-bit byte offsets from the
-// lowest row of the segment's planes: (zseg + 1) planes of every geometry
-// must span less than 4 GiB, and one plane less than 2 GiB.
+// lowest row of the plane below the segment: (zseg + 2) planes of every
+// geometry must span less than 4 GiB, and one plane less than 2 GiB.
 bool seg_fits(const bte_problem *p, int zseg)
 {
     for (const Film &fm : p->films) {
         const double plane = (double)fm.n[0] * fm.n[1] * p->nk * (double)p->esize();
-        if (plane >= 2147483648.0 || (zseg + 1) * plane >= 4294967296.0) return false;
+        if (plane >= 2147483648.0 || (zseg + 2) * plane >= 4294967296.0) return false;
     }
     return true;
 }

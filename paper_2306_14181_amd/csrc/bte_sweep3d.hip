@@ -202,24 +202,31 @@ __global__ __launch_bounds__(256) void k_sweep3d(Dev d, const T *__restrict__ ei
     auto rlu = [&](uint32_t v, int q) -> uint32_t { return (uint32_t)__builtin_amdgcn_readlane((int)v, q); };
 
     // ---- stencil rows.  The x / y neighbour rows (and the new values of the
-    // x- and y-upwind cells) are addressed from one base per buffer (the
-    // lowest of the rows involved, at the segment's lowest plane) by 32-bit
-    // byte offsets that move one plane per cell; an absent neighbour points
-    // at the column's own row (its value is never used: the mode bits say it
-    // is absent), so every offset moves by the same step.
+    // x- and y-upwind cells) and the column's own rows are addressed from
+    // one base per buffer (the lowest of the rows involved, one plane below
+    // the segment's lowest plane where there is one) by 32-bit byte offsets
+    // that move one plane per cell; an absent neighbour points at the
+    // column's own row (its value is never used: the mode bits say it is
+    // absent), so every offset moves by the same step.
     const int own = cb;
     auto pick = [&](int b) { return b >= 0 ? b : own; };
     const int cx1 = pick(bx1), cx2 = pick(bx2), cxd = pick(bxd), cy1 = pick(by1), cy2 = pick(by2), cyd = pick(byd);
     const int cmin = min(min(min(cx1, cx2), min(cxd, cy1)), min(min(cy2, cyd), own));
     const size_t rowb = (size_t)nk * sizeof(T);
-    const size_t basecell = (size_t)cmin + (size_t)plane * gz0;
+    const int zbase = gz0 > 0 ? gz0 - 1 : 0;
+    const size_t basecell = (size_t)cmin + (size_t)plane * zbase;
     const char *eb = reinterpret_cast<const char *>(ein) + basecell * rowb;
-    const char *ob = reinterpret_cast<const char *>(eout) + basecell * rowb;
+    char *ob = reinterpret_cast<char *>(eout) + basecell * rowb;
     const int zgb = sg2 > 0 ? fb : n2 - 1 - fb;
-    const unsigned zb0 = (unsigned)((size_t)(zgb - gz0) * plane * rowb);
+    const unsigned zb0 = (unsigned)((size_t)(zgb - zbase) * plane * rowb);
     const int zstepb = (sg2 > 0 ? 1 : -1) * (int)((size_t)plane * rowb);
     auto off0 = [&](int c) -> unsigned { return (unsigned)((size_t)(c - cmin) * rowb) + zb0 + koff; };
     unsigned vx1 = off0(cx1), vx2 = off0(cx2), vxd = off0(cxd), vy1 = off0(cy1), vy2 = off0(cy2), vyd = off0(cyd);
+    // the column's own row at the cell being swept, and at the flow index
+    // the next z value is prefetched from (inside the column, up to flow
+    // index fe, one past the segment: at most one plane below the segment's
+    // lowest or above its highest plane)
+    unsigned vc = off0(own), vzn = off0(own) + (unsigned)zstepb;
     auto atb = [&](const char *b, unsigned o) -> T { return *reinterpret_cast<const T *>(b + o); };
     auto zraw = [&](int f) -> T {
         int jz;
@@ -236,8 +243,9 @@ __global__ __launch_bounds__(256) void k_sweep3d(Dev d, const T *__restrict__ ei
         T nz, x1, x2, xd, y1, y2, yd, ux, uy;
     };
     // loads of cell fn (x / y neighbours, new values of the x- / y-upwind
-    // cells) and the raw column value at fn + 1; the running pointers stop
-    // at the segment's last cell
+    // cells) and the raw column value at fn + 1 (by the running offset
+    // inside the column, past its end the periodic image or zero); the x / y
+    // offsets stop at the segment's last cell
     auto prefetch = [&](int fn, Pre &q) {
         q.x1 = atb(eb, vx1);
         q.x2 = atb(eb, vx2);
@@ -247,7 +255,12 @@ __global__ __launch_bounds__(256) void k_sweep3d(Dev d, const T *__restrict__ ei
         q.yd = atb(eb, vyd);
         q.ux = atb(ob, vx1);
         q.uy = atb(ob, vy1);
-        q.nz = zraw(fn + 1);
+        if (fn < fe) {
+            q.nz = fn + 1 < n2 ? atb(eb, vzn) : zraw(fn + 1);
+            vzn += (unsigned)zstepb;
+        } else {
+            q.nz = (T)0;   // past the segment: never used
+        }
         if (fn + 1 < fe) {
             vx1 += zstepb;
             vx2 += zstepb;
@@ -380,10 +393,11 @@ __global__ __launch_bounds__(256) void k_sweep3d(Dev d, const T *__restrict__ ei
             if constexpr (sizeof(T) == 4) de = num * __builtin_amdgcn_rcpf(den);
             else de = num / den;
             en = ec + de;
-            if (active) eout[(size_t)c * nk + k] = en;
+            if (active) *reinterpret_cast<T *>(ob + vc) = en;
         } else if (active) {
-            eout[(size_t)c * nk + k] = ein[(size_t)c * nk + k];
+            *reinterpret_cast<T *>(ob + vc) = atb(eb, vc);
         }
+        vc += (unsigned)zstepb;
         // moment partials: eight cells staged, then reduced transposed
         const int mloc = f - fb;
         xs[wv][mloc & 7][lane] = (active && (mode & S3_SOLID)) ? en : (T)0;
@@ -444,7 +458,7 @@ __global__ __launch_bounds__(256) void k_sweep3d(Dev d, const T *__restrict__ ei
 
 // --------------------------------------------------------------- launchers
 
-// Segment lengths the kernel takes (the host also keeps (zseg + 1) planes
+// Segment lengths the kernel takes (the host also keeps (zseg + 2) planes
 // of rows of every geometry below 4 GiB: the row offsets are 32-bit).
 static bool sweep3d_fits(const Dev &, int zseg, size_t) { return zseg >= 1 && zseg <= 48; }
 
