@@ -299,3 +299,58 @@ def random_field(seed, size, scale=1.0):
     """Seeded uniform random array in [-scale, scale) (test perturbations)."""
     rng = np.random.default_rng(seed)
     return scale * (2.0 * rng.random(size) - 1.0)
+
+
+def mesh2d(seed, nx, ny, lx, ly, jitter=0.25, quad_frac=0.3, bc=(BC_THERMAL, BC_THERMAL, BC_SPECULAR, BC_SPECULAR),
+           bcT=(301.0, 299.0, 300.0, 300.0)):
+    """Unstructured 2D mesh of the rectangle [0, lx] x [0, ly] (topology and
+    vertices only): an nx x ny grid whose interior vertices are moved by up to
+    `jitter` of a cell size, each quadrilateral kept with probability
+    quad_frac (a hybrid mesh) or split into two triangles along a random
+    diagonal.  Cells are counter-clockwise vertex lists in grid order (row by
+    row; a split square gives two consecutive cells).  edge_tag[i] is the
+    boundary side of the edge from vertex i of its cell to the next (0: x = 0,
+    1: x = lx, 2: y = 0, 3: y = ly), -1 inside; tag_bc / tag_T give each
+    side's boundary condition and wall temperature.  With jitter = 0 and
+    quad_frac = 1 it is the Cartesian grid, cell ix + nx iy."""
+    rng = np.random.default_rng(seed)
+    hx, hy = lx / nx, ly / ny
+    X, Y = np.meshgrid(np.arange(nx + 1) * hx, np.arange(ny + 1) * hy)   # [ny+1, nx+1]
+    X, Y = X.copy(), Y.copy()
+    if jitter > 0:
+        dx = rng.uniform(-jitter, jitter, X.shape) * hx
+        dy = rng.uniform(-jitter, jitter, Y.shape) * hy
+        X[1:-1, 1:-1] += dx[1:-1, 1:-1]
+        Y[1:-1, 1:-1] += dy[1:-1, 1:-1]
+    xy = np.stack([X.reshape(-1), Y.reshape(-1)], axis=1)
+    vid = lambda i, j: j * (nx + 1) + i   # noqa: E731
+
+    def side_of(a, b):
+        ia, ja = a % (nx + 1), a // (nx + 1)
+        ib, jb = b % (nx + 1), b // (nx + 1)
+        if ia == 0 and ib == 0:
+            return 0
+        if ia == nx and ib == nx:
+            return 1
+        if ja == 0 and jb == 0:
+            return 2
+        if ja == ny and jb == ny:
+            return 3
+        return -1
+
+    cells = []
+    for j in range(ny):
+        for i in range(nx):
+            v00, v10, v11, v01 = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
+            if quad_frac >= 1.0 or rng.uniform() < quad_frac:
+                cells.append([v00, v10, v11, v01])
+            elif rng.uniform() < 0.5:
+                cells += [[v00, v10, v11], [v00, v11, v01]]
+            else:
+                cells += [[v00, v10, v01], [v10, v11, v01]]
+    ptr = np.zeros(len(cells) + 1, dtype=np.int32)
+    ptr[1:] = np.cumsum([len(c) for c in cells])
+    vtx = np.array([v for c in cells for v in c], dtype=np.int32)
+    tag = np.array([side_of(c[k], c[(k + 1) % len(c)]) for c in cells for k in range(len(c))], dtype=np.int32)
+    return dict(xy=xy, cell_ptr=ptr, cell_vtx=vtx, edge_tag=tag, tag_bc=np.asarray(bc, dtype=np.int32),
+                tag_T=np.asarray(bcT, dtype=np.float64))
