@@ -302,7 +302,7 @@ def random_field(seed, size, scale=1.0):
 
 
 def mesh2d(seed, nx, ny, lx, ly, jitter=0.25, quad_frac=0.3, bc=(BC_THERMAL, BC_THERMAL, BC_SPECULAR, BC_SPECULAR),
-           bcT=(301.0, 299.0, 300.0, 300.0)):
+           bcT=(301.0, 299.0, 300.0, 300.0), gradient_stencil=0):
     """Unstructured 2D mesh of the rectangle [0, lx] x [0, ly] (topology and
     vertices only): an nx x ny grid whose interior vertices are moved by up to
     `jitter` of a cell size, each quadrilateral kept with probability
@@ -311,8 +311,10 @@ def mesh2d(seed, nx, ny, lx, ly, jitter=0.25, quad_frac=0.3, bc=(BC_THERMAL, BC_
     row; a split square gives two consecutive cells).  edge_tag[i] is the
     boundary side of the edge from vertex i of its cell to the next (0: x = 0,
     1: x = lx, 2: y = 0, 3: y = ly), -1 inside; tag_bc / tag_T give each
-    side's boundary condition and wall temperature.  With jitter = 0 and
-    quad_frac = 1 it is the Cartesian grid, cell ix + nx iy."""
+    side's boundary condition and wall temperature; gradient_stencil is
+    passed through (0: least-squares gradients over the cells sharing a
+    vertex, 1: over the face neighbours).  With jitter = 0 and quad_frac = 1
+    it is the Cartesian grid, cell ix + nx iy."""
     rng = np.random.default_rng(seed)
     hx, hy = lx / nx, ly / ny
     X, Y = np.meshgrid(np.arange(nx + 1) * hx, np.arange(ny + 1) * hy)   # [ny+1, nx+1]
@@ -353,4 +355,4 @@ def mesh2d(seed, nx, ny, lx, ly, jitter=0.25, quad_frac=0.3, bc=(BC_THERMAL, BC_
     vtx = np.array([v for c in cells for v in c], dtype=np.int32)
     tag = np.array([side_of(c[k], c[(k + 1) % len(c)]) for c in cells for k in range(len(c))], dtype=np.int32)
     return dict(xy=xy, cell_ptr=ptr, cell_vtx=vtx, edge_tag=tag, tag_bc=np.asarray(bc, dtype=np.int32),
-                tag_T=np.asarray(bcT, dtype=np.float64))
+                tag_T=np.asarray(bcT, dtype=np.float64), gradient_stencil=int(gradient_stencil))

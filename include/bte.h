@@ -456,6 +456,90 @@ bte_status bte_get_directions(const bte_problem *p, double *s_host, double *w_ho
 const char *bte_last_error(const bte_problem *p);
 void bte_destroy(bte_problem *p);
 
+/* ------------------------------------------------------------------------
+ * Unstructured two-dimensional meshes of triangles and quadrilaterals
+ * (Sec. 3.3, eq. disretized_BTE, with the least-squares gradient and the
+ * first-order upwind stiffness matrix of Sec. 3.5), steady, sequential
+ * scheme (Sec. 3.4), bulk materials (directions on the sphere, in-plane
+ * fluxes).  Cell i: area V_i, centre = area centroid x_i; face ij: length
+ * S_ij, exterior unit normal n_ij, centre x_f.  Gradient
+ * grad e_i = X_i^+ sum_j d_ij (e_j - e_i), d_ij = x_j - x_i, X_i =
+ * sum_j d_ij d_ij^T over the stencil of i (the pseudo-inverse drops
+ * eigenvalues below 1e-10 of the largest: a cell with one stencil neighbour
+ * gets the derivative along it only).  Stencil (the paper names none):
+ * every cell sharing a vertex with i (gradient_stencil 0), or the face
+ * neighbours (1: on a Cartesian grid the central / one-sided difference of
+ * bte_problem; on triangle meshes the sequential iteration then diverges).  Face value e_ij = e_m + grad e_m . (x_f -
+ * x_m), m upwind; at a boundary edge the incoming value is the wall's:
+ * thermalizing C (T_w - T_ref) / 4 pi, specular the mirror direction's
+ * outgoing face value (edges parallel to x or y), diffuse
+ * sum_{s.n>0} w s.n e_f / sum_{s.n<0} w |s.n|.  One iteration: T_L from the
+ * moments, R = -(1/V) sum_j v (s.n) S e_ij - (e - C T_L / 4 pi) / tau +
+ * C P / (4 pi C_tot), then A de = R with A_ii = 1/tau + (1/V) sum_{s.n>0}
+ * v s.n S and A_ij = -(1/V) v |s.n| S for the interior upwind neighbour j,
+ * solved in per-direction upwind (dependency-graph) order, one launch per
+ * level of all directions together; on a cyclic graph the smallest-index
+ * cell left is taken with its unresolved upwind couplings lagged (their
+ * increments count as zero).  e layout and moments as for bte_problem:
+ * e[cell][direction][band], direction-major within a cell. */
+typedef struct {
+    int n_vertices;
+    const double *xy;        /* host [n_vertices][2] vertex coordinates, m       */
+    int n_cells;
+    const int *cell_ptr;     /* host [n_cells + 1]: cell c has the vertices
+                                cell_vtx[cell_ptr[c] .. cell_ptr[c + 1])         */
+    const int *cell_vtx;     /* counter-clockwise, 3 or 4 vertices per cell      */
+    const int *edge_tag;     /* host [cell_ptr[n_cells]]: boundary tag of the edge
+                                from vertex k to vertex k + 1 of each cell, -1
+                                for an edge shared with another cell             */
+    int n_tags;
+    const int *tag_bc;       /* host [n_tags]: BTE_BC_THERMAL, BTE_BC_SPECULAR or
+                                BTE_BC_DIFFUSE                                   */
+    const double *tag_T;     /* host [n_tags]: wall temperature, K (thermalizing) */
+    int gradient_stencil;    /* 0: cells sharing a vertex, 1: face neighbours     */
+} bte_mesh;
+
+typedef struct bte_mesh_problem bte_mesh_problem;
+
+/* Builds the geometry, least-squares matrices, wall records, directions and
+ * the per-level sweep schedule on the host.  Errors: BTE_ERR_ARG (null
+ * pointers, a cell that is not 3 or 4 vertices, counter-clockwise and of
+ * positive area, an edge shared by more than two cells, a boundary edge
+ * without a tag or an interior edge with one, a tag out of range, a
+ * specular edge not parallel to x or y, bad bands), BTE_ERR_UNSUPPORTED
+ * (synthetic scheme, a limiter, two-dimensional materials).  The control's
+ * precision, max_iter and residual_temp are used.  *out is set whenever
+ * allocation succeeded (destroy it also on error). */
+bte_status bte_mesh_setup(const bte_mesh *mesh, const bte_material *mat, const bte_control *ctl,
+                          bte_mesh_problem **out);
+/* Device workspace the caller provides (256-byte aligned) and binds. */
+size_t bte_mesh_workspace_bytes(const bte_mesh_problem *p);
+bte_status bte_mesh_bind(bte_mesh_problem *p, void *ws_dev, size_t bytes);
+int bte_mesh_num_cells(const bte_mesh_problem *p);
+int bte_mesh_num_directions(const bte_mesh_problem *p);
+/* Level launches of one sweep (the depth of the deepest direction's
+ * dependency graph) and the number of lagged couplings over all directions. */
+int bte_mesh_num_levels(const bte_mesh_problem *p);
+int bte_mesh_num_lagged(const bte_mesh_problem *p);
+/* Heat source P per cell (device double[n_cells], W/m^3; NULL: none). */
+bte_status bte_mesh_set_source(bte_mesh_problem *p, const double *P_dev, void *stream);
+/* T, T_L (K) and q (W/m^2, [n_cells][3]) of e, device doubles; any may be
+ * NULL. */
+bte_status bte_mesh_moments(bte_mesh_problem *p, const void *e_dev, double *T_dev, double *TL_dev, double *q_dev,
+                            void *stream);
+/* R(e) with e0 from TLdev (device double[n_cells], T_L - T_ref; NULL: from
+ * the moments of e), into R_dev (same type and size as e). */
+bte_status bte_mesh_residual(bte_mesh_problem *p, const void *e_dev, const double *TLdev_dev, void *R_dev,
+                             void *stream);
+/* Source iterations on e in place (init != 0: start from e = 0, i.e.
+ * T = T_ref) until max |T^{n+1} - T^n| <= residual_temp max |T^{n+1} - T_ref|
+ * or max_iter iterations (BTE_ERR_NOT_CONVERGED).  stats: iters, eps_T,
+ * converged, ms_total, sweep_launches, updates.  Synchronous. */
+bte_status bte_mesh_steady_solve(bte_mesh_problem *p, void *e_dev, int init, bte_solve_stats *stats,
+                                 void *stream);
+const char *bte_mesh_last_error(const bte_mesh_problem *p);
+void bte_mesh_destroy(bte_mesh_problem *p);
+
 #ifdef __cplusplus
 }
 #endif

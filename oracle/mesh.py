@@ -7,11 +7,16 @@ with the stiffness matrix and right-hand side of Sec. 3.5):
 
 * cell i of volume (area) V_i, faces ij of length S_ij, exterior unit normal
   n_ij, centre x_f; cell centre x_i = the polygon's centroid;
-* least-squares gradient (Sec. 3.3, the matrix X of Sec. 3.5): over the face
-  neighbours j of i, d_ij = x_j - x_i, X_i = sum_j d_ij d_ij^T and
+* least-squares gradient (Sec. 3.3, the matrix X of Sec. 3.5): over the
+  stencil cells j of i, d_ij = x_j - x_i, X_i = sum_j d_ij d_ij^T and
   grad e_i = X_i^+ sum_j d_ij (e_j - e_i)  (boundary faces do not enter;
   X^+ is the inverse, or the pseudo-inverse with eigenvalues below 1e-10 of
-  the largest dropped when the offsets do not span the plane);
+  the largest dropped when the offsets do not span the plane).  The paper
+  does not name the stencil: mesh["gradient_stencil"] = 0 (default) takes
+  every cell sharing a vertex with i, 1 the face neighbours only (on a
+  Cartesian grid that is the central / one-sided difference of the
+  structured-grid oracle; on triangles it makes the sequential iteration
+  diverge, the vertex stencil does not);
 * second-order upwind face value: e_ij = e_m + grad e_m . l_{m,ij} with m the
   upwind cell (s . n_ij > 0 for m) and l the vector from x_m to x_f;
   across a boundary face the incoming value is the wall's (Sec. 2.2):
@@ -92,18 +97,33 @@ class MeshCase:
                     raise ValueError("boundary edge without a tag")
                 fl.append((nb, tag, S, n, xf))
             self.faces.append(fl)
-        # least-squares matrices; a cell whose neighbour offsets do not span
-        # the plane (one neighbour, e.g. a corner triangle) takes the
-        # pseudo-inverse: the gradient along the offsets it has, none across
-        # them (on a Cartesian grid: zero slope along an axis without
-        # neighbours, as the structured oracle)
+        # least-squares stencils: cells sharing a vertex (0) or a face (1)
+        self.stencil = int(mesh.get("gradient_stencil", 0))
+        if self.stencil == 0:
+            vcells = {}
+            for c in range(nc):
+                for v in vtx[ptr[c]:ptr[c + 1]]:
+                    vcells.setdefault(int(v), set()).add(c)
+            self.lsn = []
+            for c in range(nc):
+                near = set()
+                for v in vtx[ptr[c]:ptr[c + 1]]:
+                    near |= vcells[int(v)]
+                near.discard(c)
+                self.lsn.append(sorted(near))
+        else:
+            self.lsn = [[nb for nb, _, _, _, _ in self.faces[c] if nb >= 0] for c in range(nc)]
+        # least-squares matrices; a cell whose offsets do not span the plane
+        # (one neighbour) takes the pseudo-inverse: the gradient along the
+        # offsets it has, none across them (on a Cartesian grid with the face
+        # stencil: zero slope along an axis without neighbours, as the
+        # structured oracle)
         self.Xinv = np.zeros((nc, 2, 2))
         for c in range(nc):
             X = np.zeros((2, 2))
-            for nb, _, _, _, _ in self.faces[c]:
-                if nb >= 0:
-                    d = self.xc[nb] - self.xc[c]
-                    X += np.outer(d, d)
+            for nb in self.lsn[c]:
+                d = self.xc[nb] - self.xc[c]
+                X += np.outer(d, d)
             self.Xinv[c] = np.linalg.pinv(X, rcond=1e-10, hermitian=True)
         m = material
         self.s, self.w = quadrature(2, int(m["n_theta"]), int(m.get("n_phi", 1)), 3)
@@ -158,10 +178,9 @@ def grad(case, e):
     g = np.zeros((case.nc, 2, case.nk))
     for c in range(case.nc):
         y = np.zeros((2, case.nk))
-        for nb, _, _, _, _ in case.faces[c]:
-            if nb >= 0:
-                d = case.xc[nb] - case.xc[c]
-                y += np.outer(d, e[nb] - e[c])
+        for nb in case.lsn[c]:
+            d = case.xc[nb] - case.xc[c]
+            y += np.outer(d, e[nb] - e[c])
         g[c] = case.Xinv[c] @ y
     return g
 

@@ -33,7 +33,11 @@ EXPORTS = ["bte_setup", "bte_setup_multi", "bte_set_control", "bte_workspace_byt
            "bte_set_timing", "bte_set_graphs", "bte_set_persistent", "bte_tile_candidates", "bte_set_tiles",
            "bte_autotune", "bte_last_stats",
            "bte_get_directions", "bte_band_discretize", "bte_band_discretize_dev",
-           "bte_band_discretize_scratch_bytes", "bte_last_error", "bte_destroy"]
+           "bte_band_discretize_scratch_bytes", "bte_last_error", "bte_destroy",
+           "bte_mesh_setup", "bte_mesh_workspace_bytes", "bte_mesh_bind", "bte_mesh_num_cells",
+           "bte_mesh_num_directions", "bte_mesh_num_levels", "bte_mesh_num_lagged", "bte_mesh_set_source",
+           "bte_mesh_moments", "bte_mesh_residual", "bte_mesh_steady_solve", "bte_mesh_last_error",
+           "bte_mesh_destroy"]
 
 
 class BteError(RuntimeError):
@@ -57,6 +61,13 @@ class Material(C.Structure):
 class Interface(C.Structure):
     _fields_ = [("geo_a", C.c_int), ("face_a", C.c_int), ("geo_b", C.c_int), ("face_b", C.c_int),
                 ("beta_ab", C.POINTER(C.c_double)), ("beta_ba", C.POINTER(C.c_double))]
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_vertices", C.c_int), ("xy", C.POINTER(C.c_double)), ("n_cells", C.c_int),
+                ("cell_ptr", C.POINTER(C.c_int)), ("cell_vtx", C.POINTER(C.c_int)), ("edge_tag", C.POINTER(C.c_int)),
+                ("n_tags", C.c_int), ("tag_bc", C.POINTER(C.c_int)), ("tag_T", C.POINTER(C.c_double)),
+                ("gradient_stencil", C.c_int)]
 
 
 class Control(C.Structure):
@@ -129,6 +140,19 @@ def load():
         "bte_band_discretize_scratch_bytes": ([C.c_int], C.c_size_t),
         "bte_last_error": ([vp], C.c_char_p),
         "bte_destroy": ([vp], None),
+        "bte_mesh_setup": ([C.POINTER(Mesh), C.POINTER(Material), C.POINTER(Control), C.POINTER(vp)], st),
+        "bte_mesh_workspace_bytes": ([vp], C.c_size_t),
+        "bte_mesh_bind": ([vp, vp, C.c_size_t], st),
+        "bte_mesh_num_cells": ([vp], C.c_int),
+        "bte_mesh_num_directions": ([vp], C.c_int),
+        "bte_mesh_num_levels": ([vp], C.c_int),
+        "bte_mesh_num_lagged": ([vp], C.c_int),
+        "bte_mesh_set_source": ([vp, vp, vp], st),
+        "bte_mesh_moments": ([vp, vp, vp, vp, vp, vp], st),
+        "bte_mesh_residual": ([vp, vp, vp, vp, vp], st),
+        "bte_mesh_steady_solve": ([vp, vp, C.c_int, C.POINTER(SolveStats), vp], st),
+        "bte_mesh_last_error": ([vp], C.c_char_p),
+        "bte_mesh_destroy": ([vp], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -541,3 +565,112 @@ class TaveTransient(torch.autograd.Function):
     def backward(ctx, grad_J):
         (g,) = ctx.saved_tensors
         return g * grad_J.to(torch.float64), None, None, None, None, None, None, None
+
+
+def mesh_struct(mesh):
+    """ctypes bte_mesh of a mesh dict (xy, cell_ptr, cell_vtx, edge_tag,
+    tag_bc, tag_T, optional gradient_stencil; see bte_inputs.mesh2d) and the
+    arrays it points into."""
+    import numpy as np
+    xy = np.ascontiguousarray(mesh["xy"], dtype=np.float64).reshape(-1, 2)
+    ptr = np.ascontiguousarray(mesh["cell_ptr"], dtype=np.int32)
+    vtx = np.ascontiguousarray(mesh["cell_vtx"], dtype=np.int32)
+    tag = np.ascontiguousarray(mesh["edge_tag"], dtype=np.int32)
+    tbc = np.ascontiguousarray(mesh["tag_bc"], dtype=np.int32)
+    tT = np.ascontiguousarray(mesh["tag_T"], dtype=np.float64)
+    ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int))   # noqa: E731
+    m = Mesh()
+    m.n_vertices, m.xy = len(xy), xy.ctypes.data_as(C.POINTER(C.c_double))
+    m.n_cells, m.cell_ptr, m.cell_vtx, m.edge_tag = len(ptr) - 1, ip(ptr), ip(vtx), ip(tag)
+    m.n_tags, m.tag_bc, m.tag_T = len(tbc), ip(tbc), tT.ctypes.data_as(C.POINTER(C.c_double))
+    m.gradient_stencil = int(mesh.get("gradient_stencil", 0))
+    return m, (xy, ptr, vtx, tag, tbc, tT)
+
+
+class MeshProblem:
+    """Steady BTE on an unstructured 2D mesh (bte_mesh_*), bound to a device
+    workspace.  control: precision, max_iter, residual_temp (scheme
+    SEQUENTIAL and limiter NONE)."""
+
+    def __init__(self, mesh, material, control, device="cuda"):
+        import numpy as np
+        lib = load()
+        self.device = torch.device(device)
+        ms, self._keep = mesh_struct(mesh)
+        self._bands = [np.ascontiguousarray(material[k], dtype=np.float64) for k in ("C", "v", "tau")]
+        mt = Material()
+        mt.n_bands = len(self._bands[0])
+        mt.C, mt.v, mt.tau = [b.ctypes.data_as(C.POINTER(C.c_double)) for b in self._bands]
+        mt.n_theta, mt.n_phi = int(material["n_theta"]), int(material.get("n_phi", 1))
+        mt.T_ref, mt.material_dim = float(material["Tref"]), int(material.get("material_dim", 3))
+        ctl = dict(scheme=SEQUENTIAL, limiter=LIM_NONE)
+        ctl.update(control)
+        c = _control_struct(ctl)
+        self.dtype = torch.float64 if c.precision == F64 else torch.float32
+        h = C.c_void_p()
+        st = lib.bte_mesh_setup(C.byref(ms), C.byref(mt), C.byref(c), C.byref(h))
+        self._h = h
+        if st != BTE_OK:
+            msg = lib.bte_mesh_last_error(h).decode() if h else "setup failed"
+            if h:
+                lib.bte_mesh_destroy(h)
+                self._h = None
+            raise BteError(st, msg)
+        self.n_cells = lib.bte_mesh_num_cells(h)
+        self.n_dirs = lib.bte_mesh_num_directions(h)
+        self.n_bands = mt.n_bands
+        self.n_unknowns = self.n_cells * self.n_dirs * self.n_bands
+        self.n_levels = lib.bte_mesh_num_levels(h)
+        self.n_lagged = lib.bte_mesh_num_lagged(h)
+        nbytes = lib.bte_mesh_workspace_bytes(h)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self._check(lib.bte_mesh_bind(h, C.c_void_p(aligned), C.c_size_t(nbytes)))
+
+    def _check(self, st, ok=(BTE_OK,)):
+        if st not in ok:
+            raise BteError(st, load().bte_mesh_last_error(self._h).decode())
+        return st
+
+    def _e(self, e):
+        if not (isinstance(e, torch.Tensor) and e.device.type == "cuda" and e.dtype == self.dtype
+                and e.is_contiguous() and e.numel() == self.n_unknowns):
+            raise ValueError("e must be a contiguous %s cuda tensor with %d elements"
+                             % (self.dtype, self.n_unknowns))
+        return _ptr(e)
+
+    def zeros(self):
+        return torch.zeros(self.n_unknowns, dtype=self.dtype, device=self.device)
+
+    def set_source(self, P):
+        Pt = None if P is None else torch.as_tensor(P, dtype=torch.float64, device=self.device).contiguous()
+        self._check(load().bte_mesh_set_source(self._h, _ptr(Pt), _stream()))
+        torch.cuda.current_stream().synchronize()
+
+    def moments(self, e):
+        T = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)
+        TL = torch.empty_like(T)
+        q = torch.empty(self.n_cells, 3, dtype=torch.float64, device=self.device)
+        self._check(load().bte_mesh_moments(self._h, self._e(e), _ptr(T), _ptr(TL), _ptr(q), _stream()))
+        return T, TL, q
+
+    def residual(self, e, TLdev=None):
+        R = torch.empty_like(e)
+        tl = None if TLdev is None else torch.as_tensor(TLdev, dtype=torch.float64, device=self.device).contiguous()
+        self._check(load().bte_mesh_residual(self._h, self._e(e), _ptr(tl), _ptr(R), _stream()))
+        return R
+
+    def steady_solve(self, e, init=True, allow_not_converged=False):
+        st = SolveStats()
+        ok = (BTE_OK, BTE_ERR_NOT_CONVERGED) if allow_not_converged else (BTE_OK,)
+        self._check(load().bte_mesh_steady_solve(self._h, self._e(e), int(init), C.byref(st), _stream()), ok)
+        return st.as_dict()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                load().bte_mesh_destroy(h)
+            except Exception:
+                pass
+            self._h = None

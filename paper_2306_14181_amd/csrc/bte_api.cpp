@@ -88,16 +88,6 @@ void launch_cg_coef(const Dev &, const CgArgs &, double *, double *, hipStream_t
 void launch_diff_rhs(const Dev &, const CgArgs &, double *, hipStream_t);
 void launch_cg_begin(const Dev &, const CgArgs &, const double *, hipStream_t);
 void launch_cg_iters(const Dev &, const CgArgs &, int, int, hipStream_t);
-}  // namespace bte
-
-using namespace bte;
-
-namespace {
-
-// Width (in columns) of the strips in which the three-dimensional column
-// walks are ordered.
-constexpr int kColStrip = 16;
-
 // Gauss-Legendre nodes/weights on [-1, 1], ascending (Newton on P_n).
 void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
 {
@@ -133,6 +123,44 @@ void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
         w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
     }
 }
+
+
+// Directions on the sphere for two- and three-dimensional geometries
+// (Sec. 3.2, eq. directiondis): Gauss-Legendre nodes of theta and phi on the
+// first octant, weight w_theta w_phi sin(theta), mirrored to the eight
+// octants (bits 1 = s_x < 0, 2 = s_y < 0, 4 = s_z < 0), then theta, then
+// phi; weights scaled to sum to omega exactly.
+void sphere_directions(int n_theta, int n_phi, double omega, std::vector<double> &s, std::vector<double> &w)
+{
+    std::vector<double> xt, wt, xp, wp;
+    gauss_legendre(n_theta, xt, wt);
+    gauss_legendre(n_phi, xp, wp);
+    s.clear();
+    w.clear();
+    for (int o = 0; o < 8; ++o)
+        for (int i = 0; i < n_theta; ++i)
+            for (int j = 0; j < n_phi; ++j) {
+                const double th = (xt[i] + 1.0) * M_PI / 4.0, wth = wt[i] * M_PI / 4.0;
+                const double ph = (xp[j] + 1.0) * M_PI / 4.0, wph = wp[j] * M_PI / 4.0, st = std::sin(th);
+                s.push_back((o & 1 ? -1.0 : 1.0) * st * std::cos(ph));
+                s.push_back((o & 2 ? -1.0 : 1.0) * st * std::sin(ph));
+                s.push_back((o & 4 ? -1.0 : 1.0) * std::cos(th));
+                w.push_back(wth * wph * st);
+            }
+    double sw = 0;
+    for (double x : w) sw += x;
+    for (double &x : w) x *= omega / sw;
+}
+
+}  // namespace bte
+
+using namespace bte;
+
+namespace {
+
+// Width (in columns) of the strips in which the three-dimensional column
+// walks are ordered.
+constexpr int kColStrip = 16;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -417,16 +445,7 @@ bte_status build_quadrature(bte_problem *p, int n_theta, int n_phi, bool planar)
             }
         p->noct = 2;
     } else {
-        gauss_legendre(n_phi, xp, wp);
-        for (int o = 0; o < 8; ++o)
-            for (int i = 0; i < n_theta; ++i)
-                for (int j = 0; j < n_phi; ++j) {
-                    double ph = (xp[j] + 1.0) * M_PI / 4.0, wph = wp[j] * M_PI / 4.0, st = std::sin(th[i]);
-                    p->s.push_back((o & 1 ? -1.0 : 1.0) * st * std::cos(ph));
-                    p->s.push_back((o & 2 ? -1.0 : 1.0) * st * std::sin(ph));
-                    p->s.push_back((o & 4 ? -1.0 : 1.0) * std::cos(th[i]));
-                    p->w.push_back(wth[i] * wph * st);
-                }
+        sphere_directions(n_theta, n_phi, p->omega, p->s, p->w);
         p->noct = 8;
     }
     p->na = (int)p->w.size();

@@ -2,6 +2,7 @@
 // the host runtime of the phonon-BTE library.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <vector>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -123,5 +124,11 @@ struct CgArgs {
     double *scal;           // [1] |b|^2, [5] done, [6] iterations, [9] total iterations, [10..13] gamma, alpha by parity
     double rtol2;
 };
+
+// Gauss-Legendre nodes / weights on [-1, 1], ascending.
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
+// Directions and weights on the sphere (two- and three-dimensional
+// geometries), weights summing to omega.
+void sphere_directions(int n_theta, int n_phi, double omega, std::vector<double> &s, std::vector<double> &w);
 
 }  // namespace bte

@@ -1,0 +1,851 @@
+// bte_mesh.hip -- steady BTE on unstructured two-dimensional meshes of
+// triangles and quadrilaterals (Sec. 3.3, eq. disretized_BTE: second-order
+// upwind face values from least-squares gradients on the right-hand side,
+// the first-order upwind stiffness matrix of Sec. 3.5 on the left; the
+// sequential scheme of Sec. 3.4).
+//
+// Host: per-cell areas and centroids, face lengths / normals / offsets, the
+// least-squares stencils (cells sharing a vertex, or the face neighbours)
+// and matrices (pseudo-inverse where the offsets do not span the plane),
+// diffuse-wall records, directions, and the sweep schedule:
+// for every direction the cells' upwind dependency graph is levelled (Kahn
+// order; a cycle is broken at its smallest-index cell, whose unresolved
+// upwind couplings are lagged), and the (direction, cell) items of all
+// directions are launched level by level.
+//
+// Device: e[cell][direction][band] as for the structured grids.  One
+// iteration = moments (T_L) -> gradients -> diffuse-wall inflow ->
+// residual R -> level launches, each thread one (direction, cell, band)
+// item: de = (R + sum_upwind v |s.n| S/V de_j) / (1/tau + sum_out v s.n S/V),
+// the increments replacing R in place, e += de.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/bte.h"
+#include "bte_internal.h"
+
+namespace bte {
+namespace {
+
+constexpr int kFG = 8;   // doubles per face slot: S/V, n_x, n_y, l_x, l_y, d_x, d_y, unused
+
+struct MeshDev {
+    int nc, na, nl, nk;
+    const int *fptr;       // [nc + 1] face slots of each cell
+    const int *fnb;        // [nf] neighbour across the face, -1 at a boundary
+    const int *ftag;       // [nf] boundary tag, -1 inside
+    const int *frec;       // [nf] diffuse-wall record, -1 otherwise
+    const double *fgeo;    // [nf][kFG]
+    const double *xinv;    // [nc][3] symmetric X^+ = [[a, b], [b, c]]
+    const int *lsptr;      // [nc + 1] least-squares stencil of each cell
+    const int *lsnb;       // [nls] stencil cells
+    const double *lsd;     // [nls][2] offsets x_j - x_i
+    const int *tag_bc;     // [ntag]
+    const double *tag_dT;  // [ntag] wall temperature - T_ref
+    const double *s;       // [na][3]
+    const double *w;       // [na]
+    const int *mirror;     // [2][na]: flip s_x, flip s_y
+    const double *C4, *v, *itau;   // [nl]
+    double Ctot, Ssum;
+    const double *P;       // [nc] heat source or null
+    const int *rec_cell, *rec_face;   // [nrec]
+    const double *rec_den;            // [nrec] sum_{s.n<0} w |s.n|
+    const int *item;       // [na * nc] items by level: direction * nc + cell
+    const uint8_t *lag;    // [na * nc] bit j: the coupling through face slot j is lagged
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mesh_grad(MeshDev d, const T *__restrict__ e, T *__restrict__ g, int nkb)
+{
+    // block = (cell, block of 256 lanes)
+    const int c = blockIdx.x / nkb;
+    const int k = (blockIdx.x - c * nkb) * kBlock + threadIdx.x;
+    if (k >= d.nk) return;
+    const double ec = (double)e[(size_t)c * d.nk + k];
+    double y0 = 0.0, y1 = 0.0;
+    for (int j = d.lsptr[c]; j < d.lsptr[c + 1]; ++j) {
+        const double diff = (double)e[(size_t)d.lsnb[j] * d.nk + k] - ec;
+        y0 += d.lsd[2 * j] * diff;
+        y1 += d.lsd[2 * j + 1] * diff;
+    }
+    const double a = d.xinv[3 * c], b = d.xinv[3 * c + 1], cc = d.xinv[3 * c + 2];
+    g[((size_t)c * 2) * d.nk + k] = (T)(a * y0 + b * y1);
+    g[((size_t)c * 2 + 1) * d.nk + k] = (T)(b * y0 + cc * y1);
+}
+
+// outgoing second-order face value of lane k of cell c at the offset
+// (lx, ly) of the face centre from the cell centre
+template <typename T>
+__device__ inline double face_out(const MeshDev &d, const T *__restrict__ e, const T *__restrict__ g, int c, int k,
+                                  double lx, double ly)
+{
+    return (double)e[(size_t)c * d.nk + k] + (double)g[((size_t)c * 2) * d.nk + k] * lx +
+           (double)g[((size_t)c * 2 + 1) * d.nk + k] * ly;
+}
+
+// Diffuse-wall inflow per record and band: outgoing energy flux of the face
+// over the incoming quadrature weight (one block per record).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mesh_walls(MeshDev d, const T *__restrict__ e, const T *__restrict__ g,
+                                                       double *__restrict__ din)
+{
+    __shared__ double sh[kBlock];
+    const int r = blockIdx.x;
+    const int c = d.rec_cell[r], f = d.rec_face[r];
+    const double *fg = d.fgeo + (size_t)f * kFG;
+    const int G = kBlock / d.nl;
+    const int grp = threadIdx.x / d.nl, l = threadIdx.x - grp * d.nl;
+    double sum = 0.0;
+    if (grp < G)
+        for (int al = grp; al < d.na; al += G) {
+            const double sn = d.s[3 * al] * fg[1] + d.s[3 * al + 1] * fg[2];
+            if (sn > 0.0) sum += d.w[al] * sn * face_out(d, e, g, c, al * d.nl + l, fg[3], fg[4]);
+        }
+    sh[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x < d.nl) {
+        double t = 0.0;
+        for (int g2 = 0; g2 < G; ++g2) t += sh[g2 * d.nl + threadIdx.x];
+        din[(size_t)r * d.nl + threadIdx.x] = t / d.rec_den[r];
+    }
+}
+
+// R = -(1/V) sum_f v (s.n) S e_f - (e - C4 T_L) / tau + C4 P / C_tot
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mesh_residual(MeshDev d, const T *__restrict__ e, const T *__restrict__ g,
+                                                          const double *__restrict__ din,
+                                                          const double *__restrict__ TLdev, T *__restrict__ R,
+                                                          int nkb)
+{
+    const int c = blockIdx.x / nkb;
+    const int k = (blockIdx.x - c * nkb) * kBlock + threadIdx.x;
+    if (k >= d.nk) return;
+    const int al = k / d.nl, l = k - al * d.nl;
+    const double sx = d.s[3 * al], sy = d.s[3 * al + 1];
+    double acc = 0.0;
+    for (int f = d.fptr[c]; f < d.fptr[c + 1]; ++f) {
+        const double *fg = d.fgeo + (size_t)f * kFG;
+        const double sn = sx * fg[1] + sy * fg[2];
+        double ef;
+        if (sn > 0.0) {
+            ef = face_out(d, e, g, c, k, fg[3], fg[4]);
+        } else if (sn < 0.0) {
+            const int nb = d.fnb[f];
+            if (nb >= 0) {
+                ef = face_out(d, e, g, nb, k, fg[3] - fg[5], fg[4] - fg[6]);
+            } else {
+                const int tag = d.ftag[f];
+                const int kind = d.tag_bc[tag];
+                if (kind == BTE_BC_THERMAL) {
+                    ef = d.C4[l] * d.tag_dT[tag];
+                } else if (kind == BTE_BC_SPECULAR) {
+                    const int axis = fabs(fg[1]) > 0.5 ? 0 : 1;
+                    const int km = d.mirror[axis * d.na + al] * d.nl + l;
+                    ef = face_out(d, e, g, c, km, fg[3], fg[4]);
+                } else {
+                    ef = din[(size_t)d.frec[f] * d.nl + l];
+                }
+            }
+        } else {
+            continue;
+        }
+        acc += sn * fg[0] * ef;
+    }
+    const double ec = (double)e[(size_t)c * d.nk + k];
+    double r = -d.v[l] * acc - (ec - d.C4[l] * TLdev[c]) * d.itau[l];
+    if (d.P) r += d.C4[l] * d.P[c] / d.Ctot;
+    R[(size_t)c * d.nk + k] = (T)r;
+}
+
+// One level of the sweep: thread = (item, band).  b holds R on entry and the
+// increment de once the item is done (read by the downwind items of later
+// levels); e += de.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mesh_sweep_level(MeshDev d, T *__restrict__ e, T *__restrict__ b,
+                                                             int item0, int nitems)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nitems * d.nl) return;
+    const int i = item0 + t / d.nl, l = t - (t / d.nl) * d.nl;
+    const int it = d.item[i];
+    const int al = it / d.nc, c = it - al * d.nc;
+    const uint32_t lag = d.lag[i];
+    const double sx = d.s[3 * al], sy = d.s[3 * al + 1];
+    const double vl = d.v[l];
+    const int k = al * d.nl + l;
+    double A = d.itau[l];
+    double num = (double)b[(size_t)c * d.nk + k];
+    const int f0 = d.fptr[c];
+    for (int f = f0; f < d.fptr[c + 1]; ++f) {
+        const double *fg = d.fgeo + (size_t)f * kFG;
+        const double sn = sx * fg[1] + sy * fg[2];
+        if (sn > 0.0) {
+            A += vl * sn * fg[0];
+        } else if (sn < 0.0) {
+            const int nb = d.fnb[f];
+            if (nb >= 0 && !((lag >> (f - f0)) & 1u)) num += vl * (-sn) * fg[0] * (double)b[(size_t)nb * d.nk + k];
+        }
+    }
+    const double de = num / A;
+    b[(size_t)c * d.nk + k] = (T)de;
+    e[(size_t)c * d.nk + k] = (T)((double)e[(size_t)c * d.nk + k] + de);
+}
+
+// Moments per cell (one block per cell): T - T_ref, T_L - T_ref and q.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mesh_moments(MeshDev d, const T *__restrict__ e, double *__restrict__ Tdev,
+                                                         double *__restrict__ TLdev, double *__restrict__ q)
+{
+    __shared__ double sh[5][kBlock];
+    const int c = blockIdx.x;
+    double a[5] = {0, 0, 0, 0, 0};
+    for (int k = threadIdx.x; k < d.nk; k += kBlock) {
+        const int al = k / d.nl, l = k - al * d.nl;
+        const double x = d.w[al] * (double)e[(size_t)c * d.nk + k];
+        a[0] += x;
+        a[1] += x * d.itau[l];
+        a[2] += x * d.v[l] * d.s[3 * al];
+        a[3] += x * d.v[l] * d.s[3 * al + 1];
+        a[4] += x * d.v[l] * d.s[3 * al + 2];
+    }
+    for (int m = 0; m < 5; ++m) sh[m][threadIdx.x] = a[m];
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int m = 0; m < 5; ++m) sh[m][threadIdx.x] += sh[m][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (Tdev) Tdev[c] = sh[0][0] / d.Ctot;
+        if (TLdev) TLdev[c] = sh[1][0] / d.Ssum;
+        if (q)
+            for (int m = 0; m < 3; ++m) q[3 * c + m] = sh[2 + m][0];
+    }
+}
+
+// out[0] = max |T1 - T0|, out[1] = max |T1| (deviations), one block
+__global__ __launch_bounds__(kBlock) void k_mesh_eps(int nc, const double *__restrict__ T0,
+                                                     const double *__restrict__ T1, double *__restrict__ out)
+{
+    __shared__ double sh[2][kBlock];
+    double a = 0.0, b = 0.0;
+    for (int c = threadIdx.x; c < nc; c += kBlock) {
+        a = fmax(a, fabs(T1[c] - T0[c]));
+        b = fmax(b, fabs(T1[c]));
+    }
+    sh[0][threadIdx.x] = a;
+    sh[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            sh[0][threadIdx.x] = fmax(sh[0][threadIdx.x], sh[0][threadIdx.x + off]);
+            sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sh[0][0];
+        out[1] = sh[1][0];
+    }
+}
+
+// T_abs = T_ref + dev
+__global__ void k_mesh_abs(int n, double Tref, const double *__restrict__ dev, double *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = Tref + dev[i];
+}
+
+}  // namespace
+}  // namespace bte
+
+using namespace bte;
+
+struct bte_mesh_problem {
+    bte_control ctl{};
+    std::string err;
+    int nc = 0, na = 0, nl = 0, nk = 0, nf = 0, nrec = 0, ntag = 0, nlev = 0, nlag = 0;
+    double Tref = 0;
+    // host tables
+    std::vector<int> fptr, fnb, ftag, frec, tag_bc, mirror, rec_cell, rec_face, item, lev_off, lsptr, lsnb;
+    std::vector<uint8_t> lag;
+    std::vector<double> fgeo, xinv, lsd, tag_dT, s, w, C4, v, itau, rec_den;
+    double Ctot = 0, Ssum = 0;
+    // device
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    MeshDev dev{};
+    void *g = nullptr, *b = nullptr;
+    double *din = nullptr, *Tdev = nullptr, *Tprev = nullptr, *TLdev = nullptr, *P = nullptr, *eps = nullptr;
+    bool hasP = false;
+    size_t esize() const { return ctl.precision == BTE_F64 ? 8 : 4; }
+    size_t nelem() const { return (size_t)nc * nk; }
+};
+
+namespace {
+
+#define MFAIL(p, st, ...)                                                                                              \
+    do {                                                                                                               \
+        char _b[512];                                                                                                  \
+        snprintf(_b, sizeof _b, __VA_ARGS__);                                                                          \
+        (p)->err = _b;                                                                                                 \
+        return st;                                                                                                     \
+    } while (0)
+
+#define MHIP(p, x)                                                                                                     \
+    do {                                                                                                               \
+        hipError_t _e = (x);                                                                                           \
+        if (_e != hipSuccess) MFAIL(p, BTE_ERR_HIP, "%s: %s", #x, hipGetErrorString(_e));                              \
+    } while (0)
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// symmetric 2 x 2 pseudo-inverse [[xx, xy], [xy, yy]]^+ (eigenvalues below
+// 1e-10 of the largest dropped)
+void pinv2(double xx, double xy, double yy, double out[3])
+{
+    const double h = 0.5 * (xx + yy), r = std::sqrt(0.25 * (xx - yy) * (xx - yy) + xy * xy);
+    const double l1 = h + r, l2 = h - r;
+    if (!(l1 > 0)) {
+        out[0] = out[1] = out[2] = 0.0;
+        return;
+    }
+    if (l2 > 1e-10 * l1) {
+        const double det = xx * yy - xy * xy;
+        out[0] = yy / det;
+        out[1] = -xy / det;
+        out[2] = xx / det;
+        return;
+    }
+    // rank one: X^+ = u u^T / l1 with u the unit eigenvector of l1
+    double ux = xy, uy = l1 - xx, vx = l1 - yy, vy = xy;
+    if (vx * vx + vy * vy > ux * ux + uy * uy) ux = vx, uy = vy;
+    const double n = std::sqrt(ux * ux + uy * uy);
+    ux /= n;
+    uy /= n;
+    out[0] = ux * ux / l1;
+    out[1] = ux * uy / l1;
+    out[2] = uy * uy / l1;
+}
+
+bte_status mesh_build(bte_mesh_problem *p, const bte_mesh *m, const bte_material *mat)
+{
+    const int nc = m->n_cells;
+    if (nc < 1 || m->n_vertices < 3 || !m->xy || !m->cell_ptr || !m->cell_vtx || !m->edge_tag)
+        MFAIL(p, BTE_ERR_ARG, "mesh: empty or null arrays");
+    if (m->n_tags < 0 || (m->n_tags > 0 && (!m->tag_bc || !m->tag_T))) MFAIL(p, BTE_ERR_ARG, "mesh: bad tags");
+    if (m->cell_ptr[0] != 0) MFAIL(p, BTE_ERR_ARG, "mesh: cell_ptr[0] must be 0");
+    p->nc = nc;
+    p->ntag = m->n_tags;
+    p->Tref = mat->T_ref;
+    for (int t = 0; t < m->n_tags; ++t) {
+        const int k = m->tag_bc[t];
+        if (k != BTE_BC_THERMAL && k != BTE_BC_SPECULAR && k != BTE_BC_DIFFUSE)
+            MFAIL(p, BTE_ERR_ARG, "mesh: tag %d: boundary condition must be thermal, specular or diffuse", t);
+        p->tag_bc.push_back(k);
+        p->tag_dT.push_back(m->tag_T[t] - mat->T_ref);
+    }
+    std::vector<double> V(nc), xc(2 * (size_t)nc);
+    for (int c = 0; c < nc; ++c) {
+        const int a = m->cell_ptr[c], b = m->cell_ptr[c + 1], nv = b - a;
+        if (nv != 3 && nv != 4) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d has %d vertices (3 or 4)", c, nv);
+        double A = 0, cx = 0, cy = 0;
+        for (int k = 0; k < nv; ++k) {
+            const int i = m->cell_vtx[a + k], j = m->cell_vtx[a + (k + 1) % nv];
+            if (i < 0 || i >= m->n_vertices || j < 0 || j >= m->n_vertices)
+                MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: vertex index out of range", c);
+            const double x0 = m->xy[2 * i], y0 = m->xy[2 * i + 1], x1 = m->xy[2 * j], y1 = m->xy[2 * j + 1];
+            const double cr = x0 * y1 - x1 * y0;
+            A += cr;
+            cx += (x0 + x1) * cr;
+            cy += (y0 + y1) * cr;
+        }
+        A *= 0.5;
+        if (!(A > 0)) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d is not counter-clockwise with positive area", c);
+        V[c] = A;
+        xc[2 * c] = cx / (6.0 * A);
+        xc[2 * c + 1] = cy / (6.0 * A);
+    }
+    const int nf = m->cell_ptr[nc];
+    p->nf = nf;
+    std::map<std::pair<int, int>, std::vector<int>> owner;   // edge -> face slots
+    for (int c = 0; c < nc; ++c) {
+        const int a = m->cell_ptr[c], nv = m->cell_ptr[c + 1] - a;
+        for (int k = 0; k < nv; ++k) {
+            const int i = m->cell_vtx[a + k], j = m->cell_vtx[a + (k + 1) % nv];
+            owner[{std::min(i, j), std::max(i, j)}].push_back(a + k);
+        }
+    }
+    std::vector<int> slot_cell(nf);
+    for (int c = 0; c < nc; ++c)
+        for (int f = m->cell_ptr[c]; f < m->cell_ptr[c + 1]; ++f) slot_cell[f] = c;
+    p->fptr.assign(m->cell_ptr, m->cell_ptr + nc + 1);
+    p->fnb.assign(nf, -1);
+    p->ftag.assign(nf, -1);
+    p->frec.assign(nf, -1);
+    p->fgeo.assign((size_t)nf * kFG, 0.0);
+    for (auto &kv : owner) {
+        if (kv.second.size() > 2) MFAIL(p, BTE_ERR_ARG, "mesh: an edge is shared by more than two cells");
+        if (kv.second.size() == 2) {
+            p->fnb[kv.second[0]] = slot_cell[kv.second[1]];
+            p->fnb[kv.second[1]] = slot_cell[kv.second[0]];
+        }
+    }
+    for (int c = 0; c < nc; ++c) {
+        const int a = m->cell_ptr[c], nv = m->cell_ptr[c + 1] - a;
+        for (int k = 0; k < nv; ++k) {
+            const int f = a + k;
+            const int i = m->cell_vtx[f], j = m->cell_vtx[a + (k + 1) % nv];
+            const double dx = m->xy[2 * j] - m->xy[2 * i], dy = m->xy[2 * j + 1] - m->xy[2 * i + 1];
+            const double S = std::hypot(dx, dy);
+            if (!(S > 0)) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d has an edge of zero length", c);
+            const double nx = dy / S, ny = -dx / S;
+            const double xf = 0.5 * (m->xy[2 * i] + m->xy[2 * j]), yf = 0.5 * (m->xy[2 * i + 1] + m->xy[2 * j + 1]);
+            double *fg = &p->fgeo[(size_t)f * kFG];
+            fg[0] = S / V[c];
+            fg[1] = nx;
+            fg[2] = ny;
+            fg[3] = xf - xc[2 * c];
+            fg[4] = yf - xc[2 * c + 1];
+            const int nb = p->fnb[f], tag = m->edge_tag[f];
+            if (nb >= 0) {
+                if (tag >= 0) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: a shared edge carries a boundary tag", c);
+                fg[5] = xc[2 * nb] - xc[2 * c];
+                fg[6] = xc[2 * nb + 1] - xc[2 * c + 1];
+            } else {
+                if (tag < 0 || tag >= m->n_tags) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: boundary edge without a valid tag", c);
+                p->ftag[f] = tag;
+                if (p->tag_bc[tag] == BTE_BC_SPECULAR && std::min(std::fabs(nx), std::fabs(ny)) > 1e-12)
+                    MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: specular edge not parallel to x or y", c);
+            }
+        }
+    }
+    // least-squares stencils, ascending cell index
+    if (m->gradient_stencil != 0 && m->gradient_stencil != 1) MFAIL(p, BTE_ERR_ARG, "mesh: gradient_stencil 0 or 1");
+    std::vector<std::vector<int>> vcells;
+    if (m->gradient_stencil == 0) {
+        vcells.assign(m->n_vertices, {});
+        for (int c = 0; c < nc; ++c)
+            for (int f = m->cell_ptr[c]; f < m->cell_ptr[c + 1]; ++f) vcells[m->cell_vtx[f]].push_back(c);
+    }
+    p->lsptr.assign(1, 0);
+    for (int c = 0; c < nc; ++c) {
+        std::vector<int> near;
+        for (int f = m->cell_ptr[c]; f < m->cell_ptr[c + 1]; ++f) {
+            if (m->gradient_stencil == 0) {
+                for (int j : vcells[m->cell_vtx[f]])
+                    if (j != c) near.push_back(j);
+            } else if (p->fnb[f] >= 0) {
+                near.push_back(p->fnb[f]);
+            }
+        }
+        std::sort(near.begin(), near.end());
+        near.erase(std::unique(near.begin(), near.end()), near.end());
+        for (int j : near) {
+            p->lsnb.push_back(j);
+            p->lsd.push_back(xc[2 * j] - xc[2 * c]);
+            p->lsd.push_back(xc[2 * j + 1] - xc[2 * c + 1]);
+        }
+        p->lsptr.push_back((int)p->lsnb.size());
+    }
+    p->xinv.assign(3 * (size_t)nc, 0.0);
+    for (int c = 0; c < nc; ++c) {
+        double xx = 0, xy = 0, yy = 0;
+        for (int j = p->lsptr[c]; j < p->lsptr[c + 1]; ++j) {
+            const double dx = p->lsd[2 * (size_t)j], dy = p->lsd[2 * (size_t)j + 1];
+            xx += dx * dx;
+            xy += dx * dy;
+            yy += dy * dy;
+        }
+        pinv2(xx, xy, yy, &p->xinv[3 * (size_t)c]);
+    }
+    // directions (bulk material: on the sphere, 4 pi)
+    if (mat->n_theta < 1 || mat->n_phi < 1) MFAIL(p, BTE_ERR_ARG, "n_theta and n_phi must be >= 1");
+    sphere_directions(mat->n_theta, mat->n_phi, 4.0 * M_PI, p->s, p->w);
+    p->na = (int)p->w.size();
+    p->nl = mat->n_bands;
+    p->nk = p->na * p->nl;
+    if ((double)p->na * nc >= 2147483647.0) MFAIL(p, BTE_ERR_ARG, "mesh: directions x cells must stay below 2^31");
+    p->mirror.assign(2 * (size_t)p->na, 0);
+    for (int a = 0; a < 2; ++a)
+        for (int al = 0; al < p->na; ++al) {
+            double t[3] = {p->s[3 * al], p->s[3 * al + 1], p->s[3 * al + 2]};
+            t[a] = -t[a];
+            int best = -1;
+            double bd = 1e300;
+            for (int b2 = 0; b2 < p->na; ++b2) {
+                const double dd = std::fabs(p->s[3 * b2] - t[0]) + std::fabs(p->s[3 * b2 + 1] - t[1]) +
+                                  std::fabs(p->s[3 * b2 + 2] - t[2]);
+                if (dd < bd) bd = dd, best = b2;
+            }
+            if (bd > 1e-9) MFAIL(p, BTE_ERR_ARG, "quadrature without mirror directions");
+            p->mirror[(size_t)a * p->na + al] = best;
+        }
+    for (int l = 0; l < p->nl; ++l) {
+        const double C = mat->C[l], v = mat->v[l], tau = mat->tau[l];
+        if (!(C > 0) || !(v >= 0) || !(tau > 0)) MFAIL(p, BTE_ERR_ARG, "band %d: C > 0, v >= 0, tau > 0 required", l);
+        p->C4.push_back(C / (4.0 * M_PI));
+        p->v.push_back(v);
+        p->itau.push_back(1.0 / tau);
+        p->Ctot += C;
+        p->Ssum += C / tau;
+    }
+    // diffuse-wall records
+    for (int f = 0; f < nf; ++f) {
+        if (p->fnb[f] >= 0 || p->tag_bc[p->ftag[f]] != BTE_BC_DIFFUSE) continue;
+        const double nx = p->fgeo[(size_t)f * kFG + 1], ny = p->fgeo[(size_t)f * kFG + 2];
+        double den = 0;
+        for (int al = 0; al < p->na; ++al) {
+            const double sn = p->s[3 * al] * nx + p->s[3 * al + 1] * ny;
+            if (sn < 0) den += p->w[al] * (-sn);
+        }
+        p->frec[f] = p->nrec++;
+        p->rec_cell.push_back(slot_cell[f]);
+        p->rec_face.push_back(f);
+        p->rec_den.push_back(den);
+    }
+    // sweep schedule: per direction, Kahn order with the lagging rule, the
+    // level of a cell one more than its deepest non-lagged upwind cell
+    std::vector<int> level((size_t)p->na * nc);
+    std::vector<uint8_t> lagm((size_t)p->na * nc, 0);
+    p->nlag = 0;
+    int maxlev = 0;
+    for (int al = 0; al < p->na; ++al) {
+        const double sx = p->s[3 * al], sy = p->s[3 * al + 1];
+        std::vector<std::vector<int>> down(nc);
+        std::vector<int> indeg(nc, 0);
+        std::vector<std::vector<int>> deps(nc);
+        for (int c = 0; c < nc; ++c)
+            for (int f = p->fptr[c]; f < p->fptr[c + 1]; ++f) {
+                const int nb = p->fnb[f];
+                if (nb < 0) continue;
+                const double sn = sx * p->fgeo[(size_t)f * kFG + 1] + sy * p->fgeo[(size_t)f * kFG + 2];
+                if (sn < 0 && std::find(deps[c].begin(), deps[c].end(), nb) == deps[c].end()) {
+                    deps[c].push_back(nb);
+                    down[nb].push_back(c);
+                }
+            }
+        for (int c = 0; c < nc; ++c) indeg[c] = (int)deps[c].size();
+        std::vector<char> done(nc, 0);
+        std::vector<int> ready;
+        std::vector<std::pair<int, int>> lagged;
+        auto is_lagged = [&](int c, int j) {
+            return std::find(lagged.begin(), lagged.end(), std::make_pair(c, j)) != lagged.end();
+        };
+        for (int c = 0; c < nc; ++c)
+            if (indeg[c] == 0) ready.push_back(c);
+        size_t head = 0;
+        int ndone = 0, lowest = 0;
+        while (ndone < nc) {
+            if (head == ready.size()) {
+                while (done[lowest]) ++lowest;
+                const int c = lowest;
+                for (int j : deps[c])
+                    if (!done[j]) lagged.push_back({c, j});
+                indeg[c] = 0;
+                ready.push_back(c);
+            }
+            const int c = ready[head++];
+            done[c] = 1;
+            ++ndone;
+            int lv = 0;
+            for (int j : deps[c])
+                if (!is_lagged(c, j)) lv = std::max(lv, level[(size_t)al * nc + j] + 1);
+            level[(size_t)al * nc + c] = lv;
+            maxlev = std::max(maxlev, lv);
+            for (int dd : down[c]) {
+                if (is_lagged(dd, c)) continue;
+                if (--indeg[dd] == 0 && !done[dd]) ready.push_back(dd);
+            }
+        }
+        for (auto &pr : lagged) {
+            const int c = pr.first;
+            for (int f = p->fptr[c]; f < p->fptr[c + 1]; ++f)
+                if (p->fnb[f] == pr.second) lagm[(size_t)al * nc + c] |= (uint8_t)(1u << (f - p->fptr[c]));
+        }
+        p->nlag += (int)lagged.size();
+    }
+    p->nlev = maxlev + 1;
+    std::vector<int> cnt(p->nlev + 1, 0);
+    for (size_t i = 0; i < level.size(); ++i) ++cnt[level[i] + 1];
+    for (int L = 0; L < p->nlev; ++L) cnt[L + 1] += cnt[L];
+    p->lev_off = cnt;
+    p->item.assign(level.size(), 0);
+    p->lag.assign(level.size(), 0);
+    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+    for (int al = 0; al < p->na; ++al)
+        for (int c = 0; c < nc; ++c) {
+            const size_t i = (size_t)al * nc + c;
+            const int at = pos[level[i]]++;
+            p->item[at] = al * nc + c;
+            p->lag[at] = lagm[i];
+        }
+    return BTE_OK;
+}
+
+template <typename T>
+void mesh_iteration_rhs(bte_mesh_problem *p, const T *e, const double *TLdev, T *R, hipStream_t s)
+{
+    const MeshDev &d = p->dev;
+    const int nkb = (p->nk + kBlock - 1) / kBlock;
+    const dim3 grid((unsigned)((size_t)nkb * p->nc));
+    hipLaunchKernelGGL(k_mesh_grad<T>, grid, dim3(kBlock), 0, s, d, e, (T *)p->g, nkb);
+    if (p->nrec > 0)
+        hipLaunchKernelGGL(k_mesh_walls<T>, dim3(p->nrec), dim3(kBlock), 0, s, d, e, (const T *)p->g, p->din);
+    hipLaunchKernelGGL(k_mesh_residual<T>, grid, dim3(kBlock), 0, s, d, e, (const T *)p->g, p->din, TLdev, R, nkb);
+}
+
+template <typename T>
+bte_status mesh_solve(bte_mesh_problem *p, T *e, int init, bte_solve_stats *stats, hipStream_t s)
+{
+    const auto h0 = std::chrono::steady_clock::now();
+    const MeshDev &d = p->dev;
+    if (init) MHIP(p, hipMemsetAsync(e, 0, p->esize() * p->nelem(), s));
+    hipLaunchKernelGGL(k_mesh_moments<T>, dim3(p->nc), dim3(kBlock), 0, s, d, e, p->Tprev, p->TLdev, nullptr);
+    const int max_iter = p->ctl.max_iter > 0 ? p->ctl.max_iter : 10000;
+    bte_solve_stats st{};
+    bool conv = false;
+    double eps = 0;
+    int it = 0;
+    for (it = 1; it <= max_iter; ++it) {
+        mesh_iteration_rhs<T>(p, e, p->TLdev, (T *)p->b, s);
+        for (int L = 0; L < p->nlev; ++L) {
+            const int i0 = p->lev_off[L], n = p->lev_off[L + 1] - i0;
+            const int blocks = (int)(((size_t)n * p->nl + kBlock - 1) / kBlock);
+            hipLaunchKernelGGL(k_mesh_sweep_level<T>, dim3(blocks), dim3(kBlock), 0, s, d, e, (T *)p->b, i0, n);
+        }
+        hipLaunchKernelGGL(k_mesh_moments<T>, dim3(p->nc), dim3(kBlock), 0, s, d, e, p->Tdev, p->TLdev, nullptr);
+        hipLaunchKernelGGL(k_mesh_eps, dim3(1), dim3(kBlock), 0, s, p->nc, p->Tprev, p->Tdev, p->eps);
+        double h[2];
+        MHIP(p, hipMemcpyAsync(h, p->eps, 16, hipMemcpyDeviceToHost, s));
+        MHIP(p, hipStreamSynchronize(s));
+        std::swap(p->Tprev, p->Tdev);
+        eps = h[1] > 0 ? h[0] / h[1] : h[0];
+        if (!std::isfinite(eps)) MFAIL(p, BTE_ERR_NONFINITE, "non-finite temperature at iteration %d", it);
+        if (eps <= p->ctl.residual_temp) {
+            conv = true;
+            break;
+        }
+    }
+    if (it > max_iter) it = max_iter;
+    MHIP(p, hipGetLastError());
+    st.iters = it;
+    st.eps_T = eps;
+    st.converged = conv;
+    st.sweep_launches = it * p->nlev;
+    st.updates = (double)it * (double)p->nelem();
+    st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
+    if (stats) *stats = st;
+    if (!conv) MFAIL(p, BTE_ERR_NOT_CONVERGED, "not converged after %d iterations (eps_T %.3g)", it, eps);
+    return BTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bte_status bte_mesh_setup(const bte_mesh *mesh, const bte_material *mat, const bte_control *ctl,
+                          bte_mesh_problem **out)
+{
+    if (!out) return BTE_ERR_ARG;
+    *out = nullptr;
+    bte_mesh_problem *p = new (std::nothrow) bte_mesh_problem();
+    if (!p) return BTE_ERR_ARG;
+    *out = p;
+    if (!mesh || !mat || !ctl) MFAIL(p, BTE_ERR_ARG, "null argument");
+    p->ctl = *ctl;
+    if (ctl->precision != BTE_F32 && ctl->precision != BTE_F64) MFAIL(p, BTE_ERR_ARG, "bad precision");
+    if (ctl->scheme != BTE_SEQUENTIAL) MFAIL(p, BTE_ERR_UNSUPPORTED, "meshes run the sequential scheme");
+    if (ctl->limiter != BTE_LIM_NONE) MFAIL(p, BTE_ERR_UNSUPPORTED, "meshes take the unlimited gradient");
+    if (mat->material_dim == 2) MFAIL(p, BTE_ERR_UNSUPPORTED, "meshes take bulk materials");
+    if (mat->n_bands < 1 || mat->n_bands > kBlock || !mat->C || !mat->v || !mat->tau)
+        MFAIL(p, BTE_ERR_ARG, "n_bands must be 1 .. %d with C, v, tau given", kBlock);
+    return mesh_build(p, mesh, mat);
+}
+
+size_t bte_mesh_workspace_bytes(const bte_mesh_problem *p)
+{
+    if (!p || p->nc == 0) return 0;
+    size_t b = 0;
+    auto add = [&](size_t n) { b += al256(n); };
+    add(4 * p->fptr.size());
+    add(4 * (size_t)p->nf * 3);
+    add(8 * p->fgeo.size());
+    add(8 * p->xinv.size());
+    add(4 * p->lsptr.size());
+    add(4 * p->lsnb.size() + 4);
+    add(8 * p->lsd.size() + 8);
+    add(4 * p->tag_bc.size() + 8);
+    add(8 * p->tag_dT.size() + 8);
+    add(8 * p->s.size());
+    add(8 * p->w.size());
+    add(4 * p->mirror.size());
+    add(8 * 3 * (size_t)p->nl);
+    add(4 * p->rec_cell.size() + 4);
+    add(4 * p->rec_face.size() + 4);
+    add(8 * p->rec_den.size() + 8);
+    add(4 * p->item.size());
+    add(p->lag.size());
+    add(2 * p->esize() * p->nelem());   // gradients
+    add(p->esize() * p->nelem());       // residual / increments
+    add(8 * ((size_t)p->nrec * p->nl + 1));
+    add(8 * 5 * (size_t)p->nc + 16);    // Tdev, Tprev, TLdev, P, eps
+    return b;
+}
+
+bte_status bte_mesh_bind(bte_mesh_problem *p, void *ws_dev, size_t bytes)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (p->nc == 0) MFAIL(p, BTE_ERR_STATE, "setup failed");
+    if (!ws_dev || ((uintptr_t)ws_dev & 255)) MFAIL(p, BTE_ERR_ARG, "workspace must be non-null and 256-byte aligned");
+    if (bytes < bte_mesh_workspace_bytes(p)) MFAIL(p, BTE_ERR_ARG, "workspace too small");
+    char *q = static_cast<char *>(ws_dev);
+    auto take = [&](size_t n) {
+        char *r = q;
+        q += al256(n);
+        return r;
+    };
+    auto up = [&](const void *src, size_t n, char *dst) -> hipError_t {
+        return n ? hipMemcpy(dst, src, n, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    MeshDev &d = p->dev;
+    d.nc = p->nc;
+    d.na = p->na;
+    d.nl = p->nl;
+    d.nk = p->nk;
+    char *x;
+    x = take(4 * p->fptr.size()); MHIP(p, up(p->fptr.data(), 4 * p->fptr.size(), x)); d.fptr = (const int *)x;
+    x = take(4 * (size_t)p->nf * 3);
+    MHIP(p, up(p->fnb.data(), 4 * (size_t)p->nf, x));
+    MHIP(p, up(p->ftag.data(), 4 * (size_t)p->nf, x + 4 * (size_t)p->nf));
+    MHIP(p, up(p->frec.data(), 4 * (size_t)p->nf, x + 8 * (size_t)p->nf));
+    d.fnb = (const int *)x;
+    d.ftag = (const int *)(x + 4 * (size_t)p->nf);
+    d.frec = (const int *)(x + 8 * (size_t)p->nf);
+    x = take(8 * p->fgeo.size()); MHIP(p, up(p->fgeo.data(), 8 * p->fgeo.size(), x)); d.fgeo = (const double *)x;
+    x = take(8 * p->xinv.size()); MHIP(p, up(p->xinv.data(), 8 * p->xinv.size(), x)); d.xinv = (const double *)x;
+    x = take(4 * p->lsptr.size()); MHIP(p, up(p->lsptr.data(), 4 * p->lsptr.size(), x)); d.lsptr = (const int *)x;
+    x = take(4 * p->lsnb.size() + 4); MHIP(p, up(p->lsnb.data(), 4 * p->lsnb.size(), x)); d.lsnb = (const int *)x;
+    x = take(8 * p->lsd.size() + 8); MHIP(p, up(p->lsd.data(), 8 * p->lsd.size(), x)); d.lsd = (const double *)x;
+    x = take(4 * p->tag_bc.size() + 8); MHIP(p, up(p->tag_bc.data(), 4 * p->tag_bc.size(), x)); d.tag_bc = (const int *)x;
+    x = take(8 * p->tag_dT.size() + 8); MHIP(p, up(p->tag_dT.data(), 8 * p->tag_dT.size(), x)); d.tag_dT = (const double *)x;
+    x = take(8 * p->s.size()); MHIP(p, up(p->s.data(), 8 * p->s.size(), x)); d.s = (const double *)x;
+    x = take(8 * p->w.size()); MHIP(p, up(p->w.data(), 8 * p->w.size(), x)); d.w = (const double *)x;
+    x = take(4 * p->mirror.size()); MHIP(p, up(p->mirror.data(), 4 * p->mirror.size(), x)); d.mirror = (const int *)x;
+    x = take(8 * 3 * (size_t)p->nl);
+    MHIP(p, up(p->C4.data(), 8 * (size_t)p->nl, x));
+    MHIP(p, up(p->v.data(), 8 * (size_t)p->nl, x + 8 * (size_t)p->nl));
+    MHIP(p, up(p->itau.data(), 8 * (size_t)p->nl, x + 16 * (size_t)p->nl));
+    d.C4 = (const double *)x;
+    d.v = (const double *)(x + 8 * (size_t)p->nl);
+    d.itau = (const double *)(x + 16 * (size_t)p->nl);
+    const size_t nr = p->rec_cell.size();
+    x = take(4 * nr + 4); MHIP(p, up(p->rec_cell.data(), 4 * nr, x)); d.rec_cell = (const int *)x;
+    x = take(4 * nr + 4); MHIP(p, up(p->rec_face.data(), 4 * nr, x)); d.rec_face = (const int *)x;
+    x = take(8 * nr + 8); MHIP(p, up(p->rec_den.data(), 8 * nr, x)); d.rec_den = (const double *)x;
+    x = take(4 * p->item.size()); MHIP(p, up(p->item.data(), 4 * p->item.size(), x)); d.item = (const int *)x;
+    x = take(p->lag.size()); MHIP(p, up(p->lag.data(), p->lag.size(), x)); d.lag = (const uint8_t *)x;
+    d.Ctot = p->Ctot;
+    d.Ssum = p->Ssum;
+    p->g = take(2 * p->esize() * p->nelem());
+    p->b = take(p->esize() * p->nelem());
+    p->din = (double *)take(8 * ((size_t)p->nrec * p->nl + 1));
+    x = take(8 * 5 * (size_t)p->nc + 16);
+    p->Tdev = (double *)x;
+    p->Tprev = p->Tdev + p->nc;
+    p->TLdev = p->Tprev + p->nc;
+    p->P = p->TLdev + p->nc;
+    p->eps = p->P + p->nc;
+    d.P = p->hasP ? p->P : nullptr;
+    p->ws = static_cast<char *>(ws_dev);
+    p->ws_bytes = bytes;
+    return BTE_OK;
+}
+
+int bte_mesh_num_cells(const bte_mesh_problem *p) { return p ? p->nc : 0; }
+int bte_mesh_num_directions(const bte_mesh_problem *p) { return p ? p->na : 0; }
+int bte_mesh_num_levels(const bte_mesh_problem *p) { return p ? p->nlev : 0; }
+int bte_mesh_num_lagged(const bte_mesh_problem *p) { return p ? p->nlag : 0; }
+
+bte_status bte_mesh_set_source(bte_mesh_problem *p, const double *P_dev, void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!p->ws) MFAIL(p, BTE_ERR_STATE, "no workspace bound");
+    hipStream_t s = (hipStream_t)stream;
+    if (P_dev) {
+        MHIP(p, hipMemcpyAsync(p->P, P_dev, 8 * (size_t)p->nc, hipMemcpyDeviceToDevice, s));
+        p->hasP = true;
+        p->dev.P = p->P;
+    } else {
+        p->hasP = false;
+        p->dev.P = nullptr;
+    }
+    return BTE_OK;
+}
+
+bte_status bte_mesh_moments(bte_mesh_problem *p, const void *e_dev, double *T_dev, double *TL_dev, double *q_dev,
+                            void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!p->ws) MFAIL(p, BTE_ERR_STATE, "no workspace bound");
+    if (!e_dev) MFAIL(p, BTE_ERR_ARG, "null e");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->ctl.precision == BTE_F64)
+        hipLaunchKernelGGL(k_mesh_moments<double>, dim3(p->nc), dim3(kBlock), 0, s, p->dev, (const double *)e_dev,
+                           p->Tdev, p->TLdev, q_dev);
+    else
+        hipLaunchKernelGGL(k_mesh_moments<float>, dim3(p->nc), dim3(kBlock), 0, s, p->dev, (const float *)e_dev,
+                           p->Tdev, p->TLdev, q_dev);
+    const dim3 gr((p->nc + kBlock - 1) / kBlock);
+    if (T_dev) hipLaunchKernelGGL(k_mesh_abs, gr, dim3(kBlock), 0, s, p->nc, p->Tref, p->Tdev, T_dev);
+    if (TL_dev) hipLaunchKernelGGL(k_mesh_abs, gr, dim3(kBlock), 0, s, p->nc, p->Tref, p->TLdev, TL_dev);
+    MHIP(p, hipGetLastError());
+    return BTE_OK;
+}
+
+bte_status bte_mesh_residual(bte_mesh_problem *p, const void *e_dev, const double *TLdev_dev, void *R_dev,
+                             void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!p->ws) MFAIL(p, BTE_ERR_STATE, "no workspace bound");
+    if (!e_dev || !R_dev) MFAIL(p, BTE_ERR_ARG, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    const double *tl = TLdev_dev;
+    if (!tl) {
+        if (p->ctl.precision == BTE_F64)
+            hipLaunchKernelGGL(k_mesh_moments<double>, dim3(p->nc), dim3(kBlock), 0, s, p->dev, (const double *)e_dev,
+                               nullptr, p->TLdev, nullptr);
+        else
+            hipLaunchKernelGGL(k_mesh_moments<float>, dim3(p->nc), dim3(kBlock), 0, s, p->dev, (const float *)e_dev,
+                               nullptr, p->TLdev, nullptr);
+        tl = p->TLdev;
+    }
+    if (p->ctl.precision == BTE_F64)
+        mesh_iteration_rhs<double>(p, (const double *)e_dev, tl, (double *)R_dev, s);
+    else
+        mesh_iteration_rhs<float>(p, (const float *)e_dev, tl, (float *)R_dev, s);
+    MHIP(p, hipGetLastError());
+    return BTE_OK;
+}
+
+bte_status bte_mesh_steady_solve(bte_mesh_problem *p, void *e_dev, int init, bte_solve_stats *stats, void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!p->ws) MFAIL(p, BTE_ERR_STATE, "no workspace bound");
+    if (!e_dev) MFAIL(p, BTE_ERR_ARG, "null e");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->ctl.precision == BTE_F64) return mesh_solve<double>(p, (double *)e_dev, init, stats, s);
+    return mesh_solve<float>(p, (float *)e_dev, init, stats, s);
+}
+
+const char *bte_mesh_last_error(const bte_mesh_problem *p) { return p ? p->err.c_str() : "null handle"; }
+
+void bte_mesh_destroy(bte_mesh_problem *p) { delete p; }
+
+}  // extern "C"

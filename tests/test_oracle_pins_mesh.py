@@ -44,8 +44,8 @@ def structured(nx, ny, lx, ly, bc4, bcT4):
 def test_cartesian_mesh_equals_the_structured_oracle(bc4):
     nx, ny, lx, ly = 6, 5, 6e-7, 5e-7
     bcT4 = (301.0, 299.5, 300.5, 299.0)
-    mc = M.MeshCase(I.mesh2d(0, nx, ny, lx, ly, jitter=0.0, quad_frac=1.0, bc=bc4, bcT=bcT4), MAT,
-                    P=np.linspace(0, 1e15, nx * ny))
+    mc = M.MeshCase(I.mesh2d(0, nx, ny, lx, ly, jitter=0.0, quad_frac=1.0, bc=bc4, bcT=bcT4, gradient_stencil=1),
+                    MAT, P=np.linspace(0, 1e15, nx * ny))
     sc = structured(nx, ny, lx, ly, bc4, bcT4).with_(P=np.linspace(0, 1e15, nx * ny))
     rng = np.random.default_rng(1)
     e = rng.normal(size=sc.size) * 1e3
@@ -91,8 +91,9 @@ def test_geometry_closed_cells_outward_normals_total_area():
         assert abs(mc.V[c] - den) <= 1e-12 * den
 
 
-def test_least_squares_gradient_and_face_values_exact_for_linear_fields():
-    mc = M.MeshCase(hybrid(), MAT)
+@pytest.mark.parametrize("stencil", [0, 1])
+def test_least_squares_gradient_and_face_values_exact_for_linear_fields(stencil):
+    mc = M.MeshCase(dict(hybrid(), gradient_stencil=stencil), MAT)
     rng = np.random.default_rng(2)
     a0, ax, ay = (rng.normal(size=mc.nk) for _ in range(3))
     ax, ay = ax * 1e9, ay * 1e9
@@ -173,3 +174,37 @@ def test_no_lagging_on_conforming_meshes_and_the_cycle_rule():
     r.faces = [[out(2)], [out(0)], [out(1)], [out(2)]]
     order, lagged = M.upwind_order(r, 0)
     assert order == [0, 1, 2, 3] and lagged == {(0, 2)}
+
+
+def test_vertex_stencil_on_a_cartesian_grid_is_the_three_by_three_fit():
+    """Interior cell of a uniform grid: the eight cells around it, X =
+    diag(6 hx^2, 6 hy^2), so d e/dx = (east column - west column) / (6 hx)."""
+    nx, ny, hx, hy = 5, 4, 60e-9, 50e-9
+    mc = M.MeshCase(I.mesh2d(0, nx, ny, nx * hx, ny * hy, jitter=0.0, quad_frac=1.0), MAT)
+    rng = np.random.default_rng(6)
+    e = rng.normal(size=(mc.nc, mc.nk))
+    g = M.grad(mc, e)
+    at = lambda i, j: e[i + nx * j]   # noqa: E731
+    for (i, j) in [(1, 1), (2, 2), (3, 1)]:
+        gx = (at(i + 1, j - 1) + at(i + 1, j) + at(i + 1, j + 1) - at(i - 1, j - 1) - at(i - 1, j) - at(i - 1, j + 1))
+        gy = (at(i - 1, j + 1) + at(i, j + 1) + at(i + 1, j + 1) - at(i - 1, j - 1) - at(i, j - 1) - at(i + 1, j - 1))
+        c = i + nx * j
+        assert np.abs(g[c, 0] - gx / (6 * hx)).max() <= 1e-6 * np.abs(gx / hx).max()
+        assert np.abs(g[c, 1] - gy / (6 * hy)).max() <= 1e-6 * np.abs(gy / hy).max()
+
+
+def test_sequential_iteration_contracts_on_triangles_with_the_vertex_stencil():
+    """The iteration e <- e + A^-1 R(e) converges on a distorted triangle
+    mesh (ratio of successive updates below 1): the property the paper
+    relies on for its sequential scheme."""
+    mesh = I.mesh2d(13, 10, 8, 10 * 60e-9, 8 * 50e-9, jitter=0.3, quad_frac=0.0, bc=(I.BC_THERMAL,) * 4)
+    mc = M.MeshCase(mesh, dict(MAT, tau=np.array([2e-9, 1e-9, 5e-10])))
+    e = mc.zeros()
+    prev, ratios = None, []
+    for _ in range(15):
+        e1 = M.sweep(mc, e, M.moments(mc, e)[1] - mc.Tref)
+        d = np.abs(e1 - e).max()
+        if prev:
+            ratios.append(d / prev)
+        prev, e = d, e1
+    assert max(ratios[-5:]) < 0.7, ratios
