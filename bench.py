@@ -525,6 +525,64 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_mesh(args):
+    """Steady FP32 source iterations on an unstructured hybrid mesh of
+    triangles and quadrilaterals (least-squares gradients over the cells
+    sharing a vertex, sweeps by upwind levels): updates/s over a fixed
+    number of iterations, the level-sweep roofline, and the oracle on a
+    bounded sample."""
+    import numpy as np
+    import torch
+    import bte_inputs as I
+    from paper_2306_14181_amd import bte as B
+    torch.cuda.set_device(0)
+    mesh = I.mesh2d(21, 128, 128, 1e-6, 1e-6, jitter=0.25, quad_frac=0.3)
+    mat = dict(I.bands(np.random.default_rng(21), 20), n_theta=2, n_phi=8, Tref=300.0)
+    iters = max(args.steps, 1)
+    prob = B.MeshProblem(mesh, mat, dict(precision=B.F32, max_iter=iters, residual_temp=0.0))
+    e = prob.zeros()
+    prob.steady_solve(e, init=True, allow_not_converged=True)   # warm-up (the same iterations)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = prob.steady_solve(e, init=True, allow_not_converged=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    upd = st["updates"]
+    sweep_ms = st["ms_sweep"] / st["iters"]
+    # level sweep: read R and e, write de and e per update
+    sweep_bytes = 4.0 * 4 * prob.n_unknowns
+    achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9
+    log("mesh2d: %d cells, %d levels, %d iterations %.3f s: sweep %.3f ms, gradient+walls+residual %.3f ms, "
+        "moments %.3f ms per iteration" % (prob.n_cells, prob.n_levels, st["iters"], t, sweep_ms,
+                                           st["ms_walls"] / st["iters"], st["ms_post"] / st["iters"]))
+    out = {"metric": "cell*dir*band updates/s of steady source iterations on an unstructured 2D mesh",
+           "value": upd / t, "unit": "updates/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f32 (e), f64 (gradient arithmetic, moments)", "data": "synthetic (seeded hybrid mesh, bands)",
+           "config": {"workload": "mesh2d: 128 x 128 jittered grid of a 1 um square, squares kept (30 %) or split "
+                                  "into triangles, 128 directions, 20 bands, thermalizing x walls, specular y walls",
+                      "cells": prob.n_cells, "levels": prob.n_levels, "iterations": st["iters"]},
+           "ms_per_iteration": t / st["iters"] * 1e3,
+           "phase_ms_per_iteration": {"sweep": sweep_ms, "gradient_walls_residual": st["ms_walls"] / st["iters"],
+                                      "moments": st["ms_post"] / st["iters"]},
+           "roofline": {"bound": "hbm", "kernel": "k_mesh_sweep_level<float> (the level launches of one sweep)",
+                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": None, "avg_sweep_ms": sweep_ms, "launches_per_sweep": prob.n_levels,
+                        "bytes_per_sweep": sweep_bytes}}
+    if not args.no_cpu_baseline:
+        from oracle import mesh as M
+        small = I.mesh2d(21, 16, 16, 1e-6 / 8, 1e-6 / 8, jitter=0.25, quad_frac=0.3)
+        case = M.MeshCase(small, mat)
+        ec = case.zeros()
+        t1 = time.perf_counter()
+        ec = M.sweep(case, ec, M.moments(case, ec)[1] - case.Tref)
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": case.size / dt, "unit": "cell*dir*band updates/s", "cores": 1,
+                               "kind": "oracle", "host": host_cpu(),
+                               "sample": "1 source iteration (numpy, FP64, one thread) of a 16 x 16 version of the "
+                                         "mesh with the same directions and bands, %.1f s" % dt}
+    print(json.dumps(out), flush=True)
+
+
 def bench_tadjoint(args):
     """Transient adjoint: 500 explicit steps of the laser physics on 32^3,
     checkpoints every 50 steps, objective = weighted top-layer temperature."""
@@ -582,7 +640,7 @@ def bench_tadjoint(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=("steady2d", "transient3d", "porous2d_batch", "porous3d_adjoint",
-                                           "tadjoint3d", "ttg1d", "interface2d"), default="steady2d")
+                                           "tadjoint3d", "ttg1d", "interface2d", "mesh2d"), default="steady2d")
     ap.add_argument("--max-iter", type=int, default=1000, help="iteration cap of the converged solves")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--gpus", type=int, default=1)
@@ -615,6 +673,9 @@ def main():
         return
     if args.workload == "porous3d_adjoint":
         bench_adjoint(args)
+        return
+    if args.workload == "mesh2d":
+        bench_mesh(args)
         return
     if args.workload == "tadjoint3d":
         bench_tadjoint(args)

@@ -534,7 +534,10 @@ bte_status bte_mesh_residual(bte_mesh_problem *p, const void *e_dev, const doubl
 /* Source iterations on e in place (init != 0: start from e = 0, i.e.
  * T = T_ref) until max |T^{n+1} - T^n| <= residual_temp max |T^{n+1} - T_ref|
  * or max_iter iterations (BTE_ERR_NOT_CONVERGED).  stats: iters, eps_T,
- * converged, ms_total, sweep_launches, updates.  Synchronous. */
+ * converged, ms_total, sweep_launches, updates and the device times (HIP
+ * events on the stream, summed over the iterations) of the level sweeps
+ * (ms_sweep), of gradients + wall inflow + residual (ms_walls) and of the
+ * moments and convergence test (ms_post).  Synchronous. */
 bte_status bte_mesh_steady_solve(bte_mesh_problem *p, void *e_dev, int init, bte_solve_stats *stats,
                                  void *stream);
 const char *bte_mesh_last_error(const bte_mesh_problem *p);

@@ -284,6 +284,12 @@ struct bte_mesh_problem {
     void *g = nullptr, *b = nullptr;
     double *din = nullptr, *Tdev = nullptr, *Tprev = nullptr, *TLdev = nullptr, *P = nullptr, *eps = nullptr;
     bool hasP = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // phase timers of the steady solve
+    ~bte_mesh_problem()
+    {
+        for (hipEvent_t x : ev)
+            if (x) (void)hipEventDestroy(x);
+    }
     size_t esize() const { return ctl.precision == BTE_F64 ? 8 : 4; }
     size_t nelem() const { return (size_t)nc * nk; }
 };
@@ -609,22 +615,33 @@ bte_status mesh_solve(bte_mesh_problem *p, T *e, int init, bte_solve_stats *stat
     if (init) MHIP(p, hipMemsetAsync(e, 0, p->esize() * p->nelem(), s));
     hipLaunchKernelGGL(k_mesh_moments<T>, dim3(p->nc), dim3(kBlock), 0, s, d, e, p->Tprev, p->TLdev, nullptr);
     const int max_iter = p->ctl.max_iter > 0 ? p->ctl.max_iter : 10000;
+    for (hipEvent_t &x : p->ev)
+        if (!x) MHIP(p, hipEventCreate(&x));
     bte_solve_stats st{};
     bool conv = false;
     double eps = 0;
     int it = 0;
     for (it = 1; it <= max_iter; ++it) {
+        MHIP(p, hipEventRecord(p->ev[0], s));
         mesh_iteration_rhs<T>(p, e, p->TLdev, (T *)p->b, s);
+        MHIP(p, hipEventRecord(p->ev[1], s));
         for (int L = 0; L < p->nlev; ++L) {
             const int i0 = p->lev_off[L], n = p->lev_off[L + 1] - i0;
             const int blocks = (int)(((size_t)n * p->nl + kBlock - 1) / kBlock);
             hipLaunchKernelGGL(k_mesh_sweep_level<T>, dim3(blocks), dim3(kBlock), 0, s, d, e, (T *)p->b, i0, n);
         }
+        MHIP(p, hipEventRecord(p->ev[2], s));
         hipLaunchKernelGGL(k_mesh_moments<T>, dim3(p->nc), dim3(kBlock), 0, s, d, e, p->Tdev, p->TLdev, nullptr);
         hipLaunchKernelGGL(k_mesh_eps, dim3(1), dim3(kBlock), 0, s, p->nc, p->Tprev, p->Tdev, p->eps);
+        MHIP(p, hipEventRecord(p->ev[3], s));
         double h[2];
         MHIP(p, hipMemcpyAsync(h, p->eps, 16, hipMemcpyDeviceToHost, s));
         MHIP(p, hipStreamSynchronize(s));
+        float ms[3];
+        for (int i = 0; i < 3; ++i) MHIP(p, hipEventElapsedTime(&ms[i], p->ev[i], p->ev[i + 1]));
+        st.ms_walls += ms[0];
+        st.ms_sweep += ms[1];
+        st.ms_post += ms[2];
         std::swap(p->Tprev, p->Tdev);
         eps = h[1] > 0 ? h[0] / h[1] : h[0];
         if (!std::isfinite(eps)) MFAIL(p, BTE_ERR_NONFINITE, "non-finite temperature at iteration %d", it);
