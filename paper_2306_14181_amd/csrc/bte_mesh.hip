@@ -16,8 +16,10 @@
 // Device: e[cell][direction][band] as for the structured grids.  One
 // iteration = moments (T_L) -> gradients -> diffuse-wall inflow ->
 // residual R -> level launches, each thread one (direction, cell, band)
-// item: de = (R + sum_upwind v |s.n| S/V de_j) / (1/tau + sum_out v s.n S/V),
-// the increments replacing R in place, e += de.
+// item: de = (R + sum_upwind v |s.n| S/V de_j) / (1/tau + sum_out v s.n S/V)
+// with the geometric sums and the upwind cells of the (direction, cell)
+// item precomputed on the host, the increments replacing R in place,
+// e += de.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -56,8 +58,13 @@ struct MeshDev {
     const double *P;       // [nc] heat source or null
     const int *rec_cell, *rec_face;   // [nrec]
     const double *rec_den;            // [nrec] sum_{s.n<0} w |s.n|
-    const int *item;       // [na * nc] items by level: direction * nc + cell
-    const uint8_t *lag;    // [na * nc] bit j: the coupling through face slot j is lagged
+    // sweep items by level: cell, direction, the outflow sum
+    // sum_{s.n>0} s.n S/V, and up to four upwind couplings (interior inflow
+    // faces not lagged): upwind cell (-1: none) and |s.n| S/V
+    const int *item_c, *item_al;
+    const double *item_out;
+    const int4 *item_up;
+    const double4 *item_coef;
 };
 
 template <typename T>
@@ -172,27 +179,19 @@ __global__ __launch_bounds__(kBlock) void k_mesh_sweep_level(MeshDev d, T *__res
 {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= nitems * d.nl) return;
-    const int i = item0 + t / d.nl, l = t - (t / d.nl) * d.nl;
-    const int it = d.item[i];
-    const int al = it / d.nc, c = it - al * d.nc;
-    const uint32_t lag = d.lag[i];
-    const double sx = d.s[3 * al], sy = d.s[3 * al + 1];
+    const int q = t / d.nl;
+    const int i = item0 + q, l = t - q * d.nl;
+    const int c = d.item_c[i];
+    const int k = d.item_al[i] * d.nl + l;
+    const int4 up = d.item_up[i];
+    const double4 cf = d.item_coef[i];
     const double vl = d.v[l];
-    const int k = al * d.nl + l;
-    double A = d.itau[l];
     double num = (double)b[(size_t)c * d.nk + k];
-    const int f0 = d.fptr[c];
-    for (int f = f0; f < d.fptr[c + 1]; ++f) {
-        const double *fg = d.fgeo + (size_t)f * kFG;
-        const double sn = sx * fg[1] + sy * fg[2];
-        if (sn > 0.0) {
-            A += vl * sn * fg[0];
-        } else if (sn < 0.0) {
-            const int nb = d.fnb[f];
-            if (nb >= 0 && !((lag >> (f - f0)) & 1u)) num += vl * (-sn) * fg[0] * (double)b[(size_t)nb * d.nk + k];
-        }
-    }
-    const double de = num / A;
+    if (up.x >= 0) num += vl * cf.x * (double)b[(size_t)up.x * d.nk + k];
+    if (up.y >= 0) num += vl * cf.y * (double)b[(size_t)up.y * d.nk + k];
+    if (up.z >= 0) num += vl * cf.z * (double)b[(size_t)up.z * d.nk + k];
+    if (up.w >= 0) num += vl * cf.w * (double)b[(size_t)up.w * d.nk + k];
+    const double de = num / (d.itau[l] + vl * d.item_out[i]);
     b[(size_t)c * d.nk + k] = (T)de;
     e[(size_t)c * d.nk + k] = (T)((double)e[(size_t)c * d.nk + k] + de);
 }
@@ -273,9 +272,11 @@ struct bte_mesh_problem {
     int nc = 0, na = 0, nl = 0, nk = 0, nf = 0, nrec = 0, ntag = 0, nlev = 0, nlag = 0;
     double Tref = 0;
     // host tables
-    std::vector<int> fptr, fnb, ftag, frec, tag_bc, mirror, rec_cell, rec_face, item, lev_off, lsptr, lsnb;
-    std::vector<uint8_t> lag;
-    std::vector<double> fgeo, xinv, lsd, tag_dT, s, w, C4, v, itau, rec_den;
+    std::vector<int> fptr, fnb, ftag, frec, tag_bc, mirror, rec_cell, rec_face, lev_off, lsptr, lsnb;
+    std::vector<int> item_c, item_al;
+    std::vector<int4> item_up;
+    std::vector<double4> item_coef;
+    std::vector<double> fgeo, xinv, lsd, tag_dT, s, w, C4, v, itau, rec_den, item_out;
     double Ctot = 0, Ssum = 0;
     // device
     char *ws = nullptr;
@@ -582,16 +583,40 @@ bte_status mesh_build(bte_mesh_problem *p, const bte_mesh *m, const bte_material
     for (size_t i = 0; i < level.size(); ++i) ++cnt[level[i] + 1];
     for (int L = 0; L < p->nlev; ++L) cnt[L + 1] += cnt[L];
     p->lev_off = cnt;
-    p->item.assign(level.size(), 0);
-    p->lag.assign(level.size(), 0);
+    const size_t ni = level.size();
+    p->item_c.assign(ni, 0);
+    p->item_al.assign(ni, 0);
+    p->item_out.assign(ni, 0.0);
+    p->item_up.assign(ni, make_int4(-1, -1, -1, -1));
+    p->item_coef.assign(ni, make_double4(0, 0, 0, 0));
     std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-    for (int al = 0; al < p->na; ++al)
+    for (int al = 0; al < p->na; ++al) {
+        const double sx = p->s[3 * al], sy = p->s[3 * al + 1];
         for (int c = 0; c < nc; ++c) {
             const size_t i = (size_t)al * nc + c;
             const int at = pos[level[i]]++;
-            p->item[at] = al * nc + c;
-            p->lag[at] = lagm[i];
+            p->item_c[at] = c;
+            p->item_al[at] = al;
+            int upc[4] = {-1, -1, -1, -1};
+            double cof[4] = {0, 0, 0, 0};
+            int nu = 0;
+            double aout = 0;
+            for (int f = p->fptr[c]; f < p->fptr[c + 1]; ++f) {
+                const double *fg = &p->fgeo[(size_t)f * kFG];
+                const double sn = sx * fg[1] + sy * fg[2];
+                if (sn > 0) {
+                    aout += sn * fg[0];
+                } else if (sn < 0 && p->fnb[f] >= 0 && !((lagm[i] >> (f - p->fptr[c])) & 1u)) {
+                    upc[nu] = p->fnb[f];
+                    cof[nu] = -sn * fg[0];
+                    ++nu;
+                }
+            }
+            p->item_out[at] = aout;
+            p->item_up[at] = make_int4(upc[0], upc[1], upc[2], upc[3]);
+            p->item_coef[at] = make_double4(cof[0], cof[1], cof[2], cof[3]);
         }
+    }
     return BTE_OK;
 }
 
@@ -707,8 +732,11 @@ size_t bte_mesh_workspace_bytes(const bte_mesh_problem *p)
     add(4 * p->rec_cell.size() + 4);
     add(4 * p->rec_face.size() + 4);
     add(8 * p->rec_den.size() + 8);
-    add(4 * p->item.size());
-    add(p->lag.size());
+    add(4 * p->item_c.size());
+    add(4 * p->item_al.size());
+    add(8 * p->item_out.size());
+    add(sizeof(int4) * p->item_up.size());
+    add(sizeof(double4) * p->item_coef.size());
     add(2 * p->esize() * p->nelem());   // gradients
     add(p->esize() * p->nelem());       // residual / increments
     add(8 * ((size_t)p->nrec * p->nl + 1));
@@ -766,8 +794,16 @@ bte_status bte_mesh_bind(bte_mesh_problem *p, void *ws_dev, size_t bytes)
     x = take(4 * nr + 4); MHIP(p, up(p->rec_cell.data(), 4 * nr, x)); d.rec_cell = (const int *)x;
     x = take(4 * nr + 4); MHIP(p, up(p->rec_face.data(), 4 * nr, x)); d.rec_face = (const int *)x;
     x = take(8 * nr + 8); MHIP(p, up(p->rec_den.data(), 8 * nr, x)); d.rec_den = (const double *)x;
-    x = take(4 * p->item.size()); MHIP(p, up(p->item.data(), 4 * p->item.size(), x)); d.item = (const int *)x;
-    x = take(p->lag.size()); MHIP(p, up(p->lag.data(), p->lag.size(), x)); d.lag = (const uint8_t *)x;
+    {
+        const size_t ni = p->item_c.size();
+        x = take(4 * ni); MHIP(p, up(p->item_c.data(), 4 * ni, x)); d.item_c = (const int *)x;
+        x = take(4 * ni); MHIP(p, up(p->item_al.data(), 4 * ni, x)); d.item_al = (const int *)x;
+        x = take(8 * ni); MHIP(p, up(p->item_out.data(), 8 * ni, x)); d.item_out = (const double *)x;
+        x = take(sizeof(int4) * ni); MHIP(p, up(p->item_up.data(), sizeof(int4) * ni, x)); d.item_up = (const int4 *)x;
+        x = take(sizeof(double4) * ni);
+        MHIP(p, up(p->item_coef.data(), sizeof(double4) * ni, x));
+        d.item_coef = (const double4 *)x;
+    }
     d.Ctot = p->Ctot;
     d.Ssum = p->Ssum;
     p->g = take(2 * p->esize() * p->nelem());
