@@ -459,9 +459,9 @@ void bte_destroy(bte_problem *p);
 /* ------------------------------------------------------------------------
  * Unstructured two-dimensional meshes of triangles and quadrilaterals
  * (Sec. 3.3, eq. disretized_BTE, with the least-squares gradient and the
- * first-order upwind stiffness matrix of Sec. 3.5), steady, sequential
- * scheme (Sec. 3.4), bulk materials (directions on the sphere, in-plane
- * fluxes).  Cell i: area V_i, centre = area centroid x_i; face ij: length
+ * first-order upwind stiffness matrix of Sec. 3.5), steady (sequential
+ * scheme, Sec. 3.4) and explicit transient steps (Sec. 4.1), bulk
+ * materials (directions on the sphere, in-plane fluxes).  Cell i: area V_i, centre = area centroid x_i; face ij: length
  * S_ij, exterior unit normal n_ij, centre x_f.  Gradient
  * grad e_i = X_i^+ sum_j d_ij (e_j - e_i), d_ij = x_j - x_i, X_i =
  * sum_j d_ij d_ij^T over the stencil of i (the pseudo-inverse drops
@@ -508,7 +508,7 @@ typedef struct bte_mesh_problem bte_mesh_problem;
  * without a tag or an interior edge with one, a tag out of range, a
  * specular edge not parallel to x or y, bad bands), BTE_ERR_UNSUPPORTED
  * (synthetic scheme, a limiter, two-dimensional materials).  The control's
- * precision, max_iter and residual_temp are used.  *out is set whenever
+ * precision, max_iter, residual_temp and dt are used.  *out is set whenever
  * allocation succeeded (destroy it also on error). */
 bte_status bte_mesh_setup(const bte_mesh *mesh, const bte_material *mat, const bte_control *ctl,
                           bte_mesh_problem **out);
@@ -540,6 +540,12 @@ bte_status bte_mesh_residual(bte_mesh_problem *p, const void *e_dev, const doubl
  * moments and convergence test (ms_post).  Synchronous. */
 bte_status bte_mesh_steady_solve(bte_mesh_problem *p, void *e_dev, int init, bte_solve_stats *stats,
                                  void *stream);
+/* n_steps explicit steps on e in place (Sec. 4.1, Algorithm 2):
+ * e^{n+1} = e^n + dt R(e^n), T_L from the moments of e^n, dt =
+ * control.dt.  BTE_ERR_CFL unless dt / tau_min < 1 and
+ * dt v_max max_i (sum_f S_f / V_i) / 2 < 1 (on a square cell the structured
+ * grids' dt v_max sum_a 1/h_a < 1).  Asynchronous on the stream. */
+bte_status bte_mesh_transient_step(bte_mesh_problem *p, void *e_dev, int n_steps, void *stream);
 const char *bte_mesh_last_error(const bte_mesh_problem *p);
 void bte_mesh_destroy(bte_mesh_problem *p);
 

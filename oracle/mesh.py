@@ -33,7 +33,9 @@ with the stiffness matrix and right-hand side of Sec. 3.5):
   A_ii = 1/tau + (1/V_i) sum_{s.n>0} v s.n S, A_ij = -(1/V_i) v |s.n| S for
   the upwind neighbour j across an interior face (wall inflow enters R
   only), solved by marching the cells of each direction in upwind order,
-  e^{n+1} = e^n + de.
+  e^{n+1} = e^n + de;
+* an explicit transient step (Sec. 4.1, Algorithm 2): e^{n+1} = e^n +
+  dt R(e^n), T_L from the moments of e^n.
 
 Upwind order: for each direction the cells form a dependency graph (i
 depends on j when j is upwind across an interior face).  Cells are taken in
@@ -328,3 +330,13 @@ def steady(case, e=None, tol_T=1e-12, max_iter=10000):
             return e, dict(iters=it, converged=True)
         T0 = T1
     return e, dict(iters=max_iter, converged=False)
+
+
+def transient(case, e, n_steps, dt):
+    """Explicit steps (Sec. 4.1, Algorithm 2): e^{n+1} = e^n + dt R(e^n) with
+    T_L from the moments of e^n."""
+    e = np.asarray(e, dtype=np.float64).copy()
+    for _ in range(n_steps):
+        TL = moments(case, e)[1] - case.Tref
+        e = e + dt * residual(case, e, TL)
+    return e

@@ -36,8 +36,8 @@ EXPORTS = ["bte_setup", "bte_setup_multi", "bte_set_control", "bte_workspace_byt
            "bte_band_discretize_scratch_bytes", "bte_last_error", "bte_destroy",
            "bte_mesh_setup", "bte_mesh_workspace_bytes", "bte_mesh_bind", "bte_mesh_num_cells",
            "bte_mesh_num_directions", "bte_mesh_num_levels", "bte_mesh_num_lagged", "bte_mesh_set_source",
-           "bte_mesh_moments", "bte_mesh_residual", "bte_mesh_steady_solve", "bte_mesh_last_error",
-           "bte_mesh_destroy"]
+           "bte_mesh_moments", "bte_mesh_residual", "bte_mesh_steady_solve", "bte_mesh_transient_step",
+           "bte_mesh_last_error", "bte_mesh_destroy"]
 
 
 class BteError(RuntimeError):
@@ -151,6 +151,7 @@ def load():
         "bte_mesh_moments": ([vp, vp, vp, vp, vp, vp], st),
         "bte_mesh_residual": ([vp, vp, vp, vp, vp], st),
         "bte_mesh_steady_solve": ([vp, vp, C.c_int, C.POINTER(SolveStats), vp], st),
+        "bte_mesh_transient_step": ([vp, vp, C.c_int, vp], st),
         "bte_mesh_last_error": ([vp], C.c_char_p),
         "bte_mesh_destroy": ([vp], None),
     }
@@ -588,9 +589,9 @@ def mesh_struct(mesh):
 
 
 class MeshProblem:
-    """Steady BTE on an unstructured 2D mesh (bte_mesh_*), bound to a device
-    workspace.  control: precision, max_iter, residual_temp (scheme
-    SEQUENTIAL and limiter NONE)."""
+    """Steady solves and explicit transient steps on an unstructured 2D mesh
+    (bte_mesh_*), bound to a device workspace.  control: precision,
+    max_iter, residual_temp, dt (scheme SEQUENTIAL and limiter NONE)."""
 
     def __init__(self, mesh, material, control, device="cuda"):
         import numpy as np
@@ -665,6 +666,11 @@ class MeshProblem:
         ok = (BTE_OK, BTE_ERR_NOT_CONVERGED) if allow_not_converged else (BTE_OK,)
         self._check(load().bte_mesh_steady_solve(self._h, self._e(e), int(init), C.byref(st), _stream()), ok)
         return st.as_dict()
+
+    def transient_step(self, e, n_steps):
+        """n_steps explicit steps (control dt) on e in place."""
+        self._check(load().bte_mesh_transient_step(self._h, self._e(e), int(n_steps), _stream()))
+        return e
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -228,6 +228,14 @@ __global__ __launch_bounds__(kBlock) void k_mesh_moments(MeshDev d, const T *__r
     }
 }
 
+// explicit step e += dt R
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mesh_axpy(size_t n, T *__restrict__ e, const T *__restrict__ R, double dt)
+{
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        e[i] = (T)((double)e[i] + dt * (double)R[i]);
+}
+
 // out[0] = max |T1 - T0|, out[1] = max |T1| (deviations), one block
 __global__ __launch_bounds__(kBlock) void k_mesh_eps(int nc, const double *__restrict__ T0,
                                                      const double *__restrict__ T1, double *__restrict__ out)
@@ -278,6 +286,7 @@ struct bte_mesh_problem {
     std::vector<double4> item_coef;
     std::vector<double> fgeo, xinv, lsd, tag_dT, s, w, C4, v, itau, rec_den, item_out;
     double Ctot = 0, Ssum = 0;
+    double vmax = 0, itau_max = 0, sv_max = 0;   // stability bound of the explicit step
     // device
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -502,6 +511,13 @@ bte_status mesh_build(bte_mesh_problem *p, const bte_mesh *m, const bte_material
         p->itau.push_back(1.0 / tau);
         p->Ctot += C;
         p->Ssum += C / tau;
+        p->vmax = std::max(p->vmax, v);
+        p->itau_max = std::max(p->itau_max, 1.0 / tau);
+    }
+    for (int c = 0; c < nc; ++c) {
+        double sv = 0;
+        for (int f = p->fptr[c]; f < p->fptr[c + 1]; ++f) sv += p->fgeo[(size_t)f * kFG];
+        p->sv_max = std::max(p->sv_max, sv);
     }
     // diffuse-wall records
     for (int f = 0; f < nf; ++f) {
@@ -895,6 +911,37 @@ bte_status bte_mesh_steady_solve(bte_mesh_problem *p, void *e_dev, int init, bte
     hipStream_t s = (hipStream_t)stream;
     if (p->ctl.precision == BTE_F64) return mesh_solve<double>(p, (double *)e_dev, init, stats, s);
     return mesh_solve<float>(p, (float *)e_dev, init, stats, s);
+}
+
+bte_status bte_mesh_transient_step(bte_mesh_problem *p, void *e_dev, int n_steps, void *stream)
+{
+    if (!p) return BTE_ERR_ARG;
+    if (!p->ws) MFAIL(p, BTE_ERR_STATE, "no workspace bound");
+    if (!e_dev || n_steps < 0) MFAIL(p, BTE_ERR_ARG, "null e or negative n_steps");
+    const double dt = p->ctl.dt;
+    if (!(dt > 0)) MFAIL(p, BTE_ERR_ARG, "control.dt must be > 0");
+    if (dt * p->itau_max >= 1.0 || 0.5 * dt * p->vmax * p->sv_max >= 1.0)
+        MFAIL(p, BTE_ERR_CFL, "dt violates dt/tau_min < 1 or dt v_max max_i sum_f S/V / 2 < 1");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = p->nelem();
+    const int blocks = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
+    for (int it = 0; it < n_steps; ++it) {
+        if (p->ctl.precision == BTE_F64) {
+            hipLaunchKernelGGL(k_mesh_moments<double>, dim3(p->nc), dim3(kBlock), 0, s, p->dev, (const double *)e_dev,
+                               nullptr, p->TLdev, nullptr);
+            mesh_iteration_rhs<double>(p, (const double *)e_dev, p->TLdev, (double *)p->b, s);
+            hipLaunchKernelGGL(k_mesh_axpy<double>, dim3(blocks), dim3(kBlock), 0, s, n, (double *)e_dev,
+                               (const double *)p->b, dt);
+        } else {
+            hipLaunchKernelGGL(k_mesh_moments<float>, dim3(p->nc), dim3(kBlock), 0, s, p->dev, (const float *)e_dev,
+                               nullptr, p->TLdev, nullptr);
+            mesh_iteration_rhs<float>(p, (const float *)e_dev, p->TLdev, (float *)p->b, s);
+            hipLaunchKernelGGL(k_mesh_axpy<float>, dim3(blocks), dim3(kBlock), 0, s, n, (float *)e_dev,
+                               (const float *)p->b, dt);
+        }
+    }
+    MHIP(p, hipGetLastError());
+    return BTE_OK;
 }
 
 const char *bte_mesh_last_error(const bte_mesh_problem *p) { return p ? p->err.c_str() : "null handle"; }

@@ -139,3 +139,25 @@ def test_mesh_converged(B, prec):
     errs = (rel_err(host(T), To, case.Tref), rel_err(host(TL), TLo, case.Tref), rel_err(host(q), qo.reshape(-1)))
     print(prec, errs, st["iters"], sto["iters"])
     assert max(errs) < bar, errs
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("name", ["ts", "tri"])
+def test_mesh_transient_steps(B, name, prec):
+    """Seven explicit steps (Algorithm 2 on the mesh)."""
+    dt = 2e-13
+    case, prob = build(B, name, prec, dt=dt)
+    eg = to_dev(prob, seeded(case, 5))
+    e = host(eg)
+    prob.transient_step(eg, 7)
+    eo = M.transient(case, e, 7, dt)
+    err = rel_err(host(eg), eo)
+    print(name, prec, err)
+    assert err < (1e-11 if prec == 1 else 1e-5), err
+
+
+def test_mesh_transient_refuses_unstable_steps(B):
+    case, prob = build(B, "ts", 1, dt=5e-11)
+    with pytest.raises(B.BteError) as ex:
+        prob.transient_step(prob.zeros(), 1)
+    assert ex.value.status == B.BTE_ERR_CFL

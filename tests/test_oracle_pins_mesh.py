@@ -208,3 +208,18 @@ def test_sequential_iteration_contracts_on_triangles_with_the_vertex_stencil():
             ratios.append(d / prev)
         prev, e = d, e1
     assert max(ratios[-5:]) < 0.7, ratios
+
+
+def test_explicit_steps_conserve_energy_with_adiabatic_walls():
+    """Algorithm 2 on the mesh: with specular and diffuse walls and no
+    source, sum_i V_i sum_k w e is invariant (the flux divergence sums to
+    zero and the scattering term sum w (e - C T_L / 4 pi) / tau vanishes by
+    the definition of T_L); taking T_L from the wrong moment breaks it."""
+    mc = M.MeshCase(hybrid(bc=(I.BC_SPECULAR, I.BC_DIFFUSE, I.BC_DIFFUSE, I.BC_SPECULAR)), MAT)
+    rng = np.random.default_rng(8)
+    e0 = rng.normal(size=mc.size) * 1e3
+    energy = lambda x: np.einsum("c,a,cal->", mc.V, mc.w, x.reshape(mc.nc, mc.na, mc.nl))   # noqa: E731
+    e1 = M.transient(mc, e0, 5, 1e-13)
+    scale = np.einsum("c,a,cal->", mc.V, mc.w, np.abs(e0.reshape(mc.nc, mc.na, mc.nl)))
+    assert abs(energy(e1) - energy(e0)) <= 1e-12 * scale
+    assert np.abs(e1 - e0).max() > 1e-3 * np.abs(e0).max()     # the state did move
