@@ -302,7 +302,7 @@ def random_field(seed, size, scale=1.0):
 
 
 def mesh2d(seed, nx, ny, lx, ly, jitter=0.25, quad_frac=0.3, bc=(BC_THERMAL, BC_THERMAL, BC_SPECULAR, BC_SPECULAR),
-           bcT=(301.0, 299.0, 300.0, 300.0), gradient_stencil=0):
+           bcT=(301.0, 299.0, 300.0, 300.0), gradient_stencil=0, pores=(), pore_bc=BC_DIFFUSE):
     """Unstructured 2D mesh of the rectangle [0, lx] x [0, ly] (topology and
     vertices only): an nx x ny grid whose interior vertices are moved by up to
     `jitter` of a cell size, each quadrilateral kept with probability
@@ -313,8 +313,11 @@ def mesh2d(seed, nx, ny, lx, ly, jitter=0.25, quad_frac=0.3, bc=(BC_THERMAL, BC_
     1: x = lx, 2: y = 0, 3: y = ly), -1 inside; tag_bc / tag_T give each
     side's boundary condition and wall temperature; gradient_stencil is
     passed through (0: least-squares gradients over the cells sharing a
-    vertex, 1: over the face neighbours).  With jitter = 0 and quad_frac = 1
-    it is the Cartesian grid, cell ix + nx iy."""
+    vertex, 1: over the face neighbours).  pores: circles (cx, cy, r); the
+    cells whose vertex mean lies inside one are left out, and the edges
+    they shared with kept cells get tag 4 (pore surface, condition pore_bc).
+    With jitter = 0 and quad_frac = 1 it is the Cartesian grid, cell
+    ix + nx iy."""
     rng = np.random.default_rng(seed)
     hx, hy = lx / nx, ly / ny
     X, Y = np.meshgrid(np.arange(nx + 1) * hx, np.arange(ny + 1) * hy)   # [ny+1, nx+1]
@@ -350,9 +353,27 @@ def mesh2d(seed, nx, ny, lx, ly, jitter=0.25, quad_frac=0.3, bc=(BC_THERMAL, BC_
                 cells += [[v00, v10, v11], [v00, v11, v01]]
             else:
                 cells += [[v00, v10, v01], [v10, v11, v01]]
+    if pores:
+        def inside(c):
+            m = xy[c].mean(axis=0)
+            return any((m[0] - px) ** 2 + (m[1] - py) ** 2 < r * r for px, py, r in pores)
+        cells = [c for c in cells if not inside(c)]
+    count = {}
+    for c in cells:
+        for k in range(len(c)):
+            key = (min(c[k], c[(k + 1) % len(c)]), max(c[k], c[(k + 1) % len(c)]))
+            count[key] = count.get(key, 0) + 1
+
+    def tag_of(a, b):
+        t = side_of(a, b)
+        if t < 0 and count[(min(a, b), max(a, b))] == 1:
+            return 4                     # an edge left open by a pore
+        return t
+
     ptr = np.zeros(len(cells) + 1, dtype=np.int32)
     ptr[1:] = np.cumsum([len(c) for c in cells])
     vtx = np.array([v for c in cells for v in c], dtype=np.int32)
-    tag = np.array([side_of(c[k], c[(k + 1) % len(c)]) for c in cells for k in range(len(c))], dtype=np.int32)
-    return dict(xy=xy, cell_ptr=ptr, cell_vtx=vtx, edge_tag=tag, tag_bc=np.asarray(bc, dtype=np.int32),
-                tag_T=np.asarray(bcT, dtype=np.float64), gradient_stencil=int(gradient_stencil))
+    tag = np.array([tag_of(c[k], c[(k + 1) % len(c)]) for c in cells for k in range(len(c))], dtype=np.int32)
+    return dict(xy=xy, cell_ptr=ptr, cell_vtx=vtx, edge_tag=tag,
+                tag_bc=np.asarray(list(bc) + [pore_bc], dtype=np.int32),
+                tag_T=np.asarray(list(bcT) + [300.0], dtype=np.float64), gradient_stencil=int(gradient_stencil))

@@ -1,10 +1,11 @@
 """GPU parity of the unstructured 2D mesh path (bte_mesh_*; Sec. 3.3 eq.
 disretized_BTE with least-squares gradients, Sec. 3.4 sequential scheme,
 Sec. 3.5 first-order upwind sweep) against the oracle (oracle/mesh.py) on
-seeded hybrid meshes of triangles and quadrilaterals: residual (every wall
-kind, heat source, both least-squares stencils), moments, three source
-iterations (the level-by-level sweep over all directions) and converged
-solutions.  Bars: FP64 1e-11, FP32
+seeded hybrid meshes of triangles and quadrilaterals, with and without
+pores (holes with diffuse surfaces): residual (every wall kind, heat source,
+both least-squares stencils), moments, three source iterations (the
+level-by-level sweep over all directions), converged solutions and
+explicit steps.  Bars: FP64 1e-11, FP32
 1e-5 (relative to the field's largest magnitude)."""
 import numpy as np
 import pytest
@@ -34,6 +35,9 @@ CASES = {
                  stencil=1),
     # thermalizing walls all round (the converged solve)
     "tt": dict(seed=14, nx=9, ny=8, bc=(I.BC_THERMAL,) * 4, src=True),
+    # two pores with diffuse surfaces
+    "pores": dict(seed=16, nx=14, ny=10, bc=(I.BC_THERMAL,) * 4, src=False,
+                  pores=[(4 * 60e-9, 5 * 50e-9, 100e-9), (10 * 60e-9, 4 * 50e-9, 80e-9)]),
 }
 
 
@@ -50,7 +54,7 @@ def build(B, name, prec, mat=MAT, **ctl):
     cf = CASES[name]
     mesh = I.mesh2d(cf["seed"], cf["nx"], cf["ny"], cf["nx"] * 60e-9, cf["ny"] * 50e-9, jitter=0.3,
                     quad_frac=cf.get("quad_frac", 0.4), bc=cf["bc"], bcT=(301.0, 299.0, 300.5, 299.5),
-                    gradient_stencil=cf.get("stencil", 0))
+                    gradient_stencil=cf.get("stencil", 0), pores=cf.get("pores", ()))
     nc = len(mesh["cell_ptr"]) - 1
     P = np.random.default_rng(cf["seed"]).uniform(0, 2e16, nc) if cf["src"] else None
     case = M.MeshCase(mesh, mat, P=P)
@@ -107,7 +111,7 @@ def test_mesh_moments(B, prec):
 
 
 @pytest.mark.parametrize("prec", [1, 0])
-@pytest.mark.parametrize("name", ["ts", "diffuse", "tri", "face"])
+@pytest.mark.parametrize("name", ["ts", "diffuse", "tri", "face", "pores"])
 def test_mesh_source_iterations(B, name, prec):
     """Three source iterations from the same state: moments, gradients,
     walls, residual and the level sweep over every direction."""
@@ -125,9 +129,10 @@ def test_mesh_source_iterations(B, name, prec):
 
 
 @pytest.mark.parametrize("prec", [1, 0])
-def test_mesh_converged(B, prec):
+@pytest.mark.parametrize("name", ["tt", "pores"])
+def test_mesh_converged(B, name, prec):
     tol = 1e-12 if prec == 1 else 1e-6
-    case, prob = build(B, "tt", prec, mat=MAT_BALLISTIC, max_iter=500, residual_temp=tol)
+    case, prob = build(B, name, prec, mat=MAT_BALLISTIC, max_iter=500, residual_temp=tol)
     eg = prob.zeros()
     st = prob.steady_solve(eg, init=True)
     assert st["converged"]
@@ -137,12 +142,12 @@ def test_mesh_converged(B, prec):
     To, TLo, qo = M.moments(case, eo)
     bar = 1e-10 if prec == 1 else 1e-5
     errs = (rel_err(host(T), To, case.Tref), rel_err(host(TL), TLo, case.Tref), rel_err(host(q), qo.reshape(-1)))
-    print(prec, errs, st["iters"], sto["iters"])
+    print(name, prec, errs, st["iters"], sto["iters"])
     assert max(errs) < bar, errs
 
 
 @pytest.mark.parametrize("prec", [1, 0])
-@pytest.mark.parametrize("name", ["ts", "tri"])
+@pytest.mark.parametrize("name", ["ts", "tri", "pores"])
 def test_mesh_transient_steps(B, name, prec):
     """Seven explicit steps (Algorithm 2 on the mesh)."""
     dt = 2e-13

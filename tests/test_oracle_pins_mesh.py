@@ -113,9 +113,17 @@ def test_least_squares_gradient_and_face_values_exact_for_linear_fields(stencil)
         assert np.abs(D[c] - exact).max() <= 1e-8 * np.abs(exact).max()
 
 
-@pytest.mark.parametrize("bc", [(O.BC_SPECULAR,) * 4, (O.BC_DIFFUSE, O.BC_SPECULAR, O.BC_DIFFUSE, O.BC_DIFFUSE)])
-def test_adiabatic_walls_conserve_energy_for_any_state(bc):
-    mc = M.MeshCase(hybrid(bc=bc), MAT)
+PORES = [(2.2e-7, 3.0e-7, 1.1e-7), (5.3e-7, 2.0e-7, 0.8e-7)]
+
+
+@pytest.mark.parametrize("bc,pores", [((O.BC_SPECULAR,) * 4, ()),
+                                      ((O.BC_DIFFUSE, O.BC_SPECULAR, O.BC_DIFFUSE, O.BC_DIFFUSE), ()),
+                                      ((O.BC_SPECULAR,) * 4, PORES)])
+def test_adiabatic_walls_conserve_energy_for_any_state(bc, pores):
+    mesh = I.mesh2d(3, 7, 6, 7e-7, 6e-7, jitter=0.3, quad_frac=0.4, bc=bc, pores=pores)
+    if pores:
+        assert (mesh["edge_tag"] == 4).sum() > 8     # pore surfaces (diffuse)
+    mc = M.MeshCase(mesh, MAT)
     rng = np.random.default_rng(4)
     for _ in range(2):
         e = rng.normal(size=mc.size) * 1e3
