@@ -377,3 +377,73 @@ def mesh2d(seed, nx, ny, lx, ly, jitter=0.25, quad_frac=0.3, bc=(BC_THERMAL, BC_
     return dict(xy=xy, cell_ptr=ptr, cell_vtx=vtx, edge_tag=tag,
                 tag_bc=np.asarray(list(bc) + [pore_bc], dtype=np.int32),
                 tag_T=np.asarray(list(bcT) + [300.0], dtype=np.float64), gradient_stencil=int(gradient_stencil))
+
+
+def mesh3d(seed, nx, ny, nz, lx, ly, lz, jitter=0.15,
+           bc=(BC_THERMAL, BC_THERMAL, BC_SPECULAR, BC_SPECULAR, BC_SPECULAR, BC_SPECULAR),
+           bcT=(301.0, 299.0, 300.0, 300.0, 300.0, 300.0), gradient_stencil=0, pores=(), pore_bc=BC_DIFFUSE):
+    """Tetrahedral mesh of the box [0, lx] x [0, ly] x [0, lz] (topology and
+    vertices only): an nx x ny x nz grid whose interior vertices are moved by
+    up to `jitter` of a cell size, each cube split into the six tetrahedra
+    around its diagonal from its lowest to its highest corner (the same
+    split in every cube, so faces match).  cell_vtx[c] holds the four
+    vertices of tetrahedron c (any order); face_tag[c][k] is the boundary
+    side of the face opposite vertex k (0: x = 0, 1: x = lx, 2: y = 0,
+    3: y = ly, 4: z = 0, 5: z = lz), -1 inside; pores are spheres
+    (cx, cy, cz, r) whose tetrahedra (by vertex mean) are left out, the
+    faces they open getting tag 6 (condition pore_bc)."""
+    rng = np.random.default_rng(seed)
+    h = np.array([lx / nx, ly / ny, lz / nz])
+    g = np.stack(np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij"), axis=-1)
+    xyz = (g * h).astype(np.float64)                        # [nx+1, ny+1, nz+1, 3]
+    if jitter > 0:
+        d = rng.uniform(-jitter, jitter, xyz.shape) * h
+        xyz[1:-1, 1:-1, 1:-1] += d[1:-1, 1:-1, 1:-1]
+    xyz = xyz.reshape(-1, 3)
+    vid = lambda i, j, k: (i * (ny + 1) + j) * (nz + 1) + k   # noqa: E731
+    unit = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    cells = []
+    for i in range(nx):
+        for j in range(ny):
+            for k in range(nz):
+                for p in perms:
+                    a = [i, j, k]
+                    t = [vid(*a)]
+                    for ax in p:
+                        a = [a[q] + unit[ax][q] for q in range(3)]
+                        t.append(vid(*a))
+                    cells.append(t)
+    if pores:
+        def inside(c):
+            m = xyz[c].mean(axis=0)
+            return any(((m - np.array(pc[:3])) ** 2).sum() < pc[3] ** 2 for pc in pores)
+        cells = [c for c in cells if not inside(c)]
+    cells = np.array(cells, dtype=np.int32)
+    for c in cells:
+        a, b, cc, dd = xyz[c]
+        if np.linalg.det(np.stack([b - a, cc - a, dd - a])) == 0:
+            raise ValueError("degenerate tetrahedron: lower the jitter")
+    ijk = np.stack(np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij"),
+                   axis=-1).reshape(-1, 3)
+    top = np.array([nx, ny, nz])
+    count = {}
+    for c in cells:
+        for q in range(4):
+            key = tuple(sorted(np.delete(c, q)))
+            count[key] = count.get(key, 0) + 1
+    tag = np.full((len(cells), 4), -1, dtype=np.int32)
+    for ci, c in enumerate(cells):
+        for q in range(4):
+            f = np.delete(c, q)
+            t = -1
+            for ax in range(3):
+                if (ijk[f, ax] == 0).all():
+                    t = 2 * ax
+                elif (ijk[f, ax] == top[ax]).all():
+                    t = 2 * ax + 1
+            if t < 0 and count[tuple(sorted(f))] == 1:
+                t = 6
+            tag[ci, q] = t
+    return dict(xyz=xyz, cell_vtx=cells, face_tag=tag, tag_bc=np.asarray(list(bc) + [pore_bc], dtype=np.int32),
+                tag_T=np.asarray(list(bcT) + [300.0], dtype=np.float64), gradient_stencil=int(gradient_stencil))

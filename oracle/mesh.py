@@ -65,6 +65,7 @@ class MeshCase:
         self.tag_T = np.asarray(mesh["tag_T"], dtype=np.float64)
         nc = len(ptr) - 1
         self.nc = nc
+        self.dim = 2
         # polygon area and centroid (shoelace)
         self.V = np.zeros(nc)
         self.xc = np.zeros((nc, 2))
@@ -161,8 +162,9 @@ class MeshCase:
         return np.zeros(self.size)
 
     def sn(self, n):
-        """s . n for every direction (the normal lies in the plane)."""
-        return self.s[:, 0] * n[0] + self.s[:, 1] * n[1]
+        """s . n for every direction (n has the mesh's dimension)."""
+        out = self.s[:, 0] * n[0] + self.s[:, 1] * n[1]
+        return out + self.s[:, 2] * n[2] if len(n) == 3 else out
 
     def lanes_v(self):
         return np.tile(self.v, self.na)           # v of lane k = al * nl + l
@@ -174,12 +176,19 @@ class MeshCase:
         return np.tile(self.C4, self.na)
 
 
+def _dot(s, n):
+    """s . n with n in the mesh's dimension."""
+    out = s[0] * n[0] + s[1] * n[1]
+    return out + s[2] * n[2] if len(n) == 3 else out
+
+
 def grad(case, e):
-    """Least-squares gradient [nc, 2, nk] (Sec. 3.3)."""
+    """Least-squares gradient [nc, dim, nk] (Sec. 3.3)."""
     e = np.asarray(e, dtype=np.float64).reshape(case.nc, case.nk)
-    g = np.zeros((case.nc, 2, case.nk))
+    D = case.dim
+    g = np.zeros((case.nc, D, case.nk))
     for c in range(case.nc):
-        y = np.zeros((2, case.nk))
+        y = np.zeros((D, case.nk))
         for nb in case.lsn[c]:
             d = case.xc[nb] - case.xc[c]
             y += np.outer(d, e[nb] - e[c])
@@ -190,7 +199,8 @@ def grad(case, e):
 def _face_out(case, e, g, c, xf):
     """Outgoing second-order face value of cell c at face centre xf, all lanes."""
     l = xf - case.xc[c]
-    return e[c] + g[c, 0] * l[0] + g[c, 1] * l[1]
+    out = e[c] + g[c, 0] * l[0] + g[c, 1] * l[1]
+    return out + g[c, 2] * l[2] if case.dim == 3 else out
 
 
 def _wall_in(case, e, g, c, tag, n, xf):
@@ -202,7 +212,7 @@ def _wall_in(case, e, g, c, tag, n, xf):
         return np.tile(case.C4 * (case.tag_T[tag] - case.Tref), case.na)
     out = _face_out(case, e, g, c, xf).reshape(case.na, nl)
     if kind == BC_SPECULAR:
-        a = 0 if abs(n[0]) > 0.5 else 1     # the wall's normal axis: flip that component
+        a = int(np.argmax(np.abs(n)))      # the wall's normal axis: flip that component
         return out[case.mirror[a]].reshape(-1)
     if kind == BC_DIFFUSE:
         sn = case.sn(n)
@@ -263,7 +273,7 @@ def upwind_order(case, al):
     down = [[] for _ in range(case.nc)]
     for c in range(case.nc):
         for nb, _, _, n, _ in case.faces[c]:
-            if nb >= 0 and s[0] * n[0] + s[1] * n[1] < 0:
+            if nb >= 0 and _dot(s, n) < 0:
                 deps[c].add(nb)
                 down[nb].append(c)
     indeg = [len(x) for x in deps]
@@ -306,7 +316,7 @@ def sweep(case, e, TLdev):
             A = 1.0 / case.tau
             num = b[c, al].copy()
             for nb, _, S, n, _ in case.faces[c]:
-                sn = s[0] * n[0] + s[1] * n[1]
+                sn = _dot(s, n)
                 if sn > 0:
                     A = A + case.v * sn * S / case.V[c]
                 elif sn < 0 and nb >= 0 and (c, nb) not in lagged:
@@ -340,3 +350,94 @@ def transient(case, e, n_steps, dt):
         TL = moments(case, e)[1] - case.Tref
         e = e + dt * residual(case, e, TL)
     return e
+
+
+class TetMeshCase(MeshCase):
+    """Tetrahedral mesh (dict of xyz, cell_vtx [nc][4], face_tag [nc][4]
+    with face k opposite vertex k, tag_bc, tag_T, optional
+    gradient_stencil; see bte_inputs.mesh3d) + bands + optional P.  Cell
+    volume |det| / 6, centre = vertex mean (the centroid of a
+    tetrahedron); face area |cross| / 2, centre = vertex mean, normal away
+    from the opposite vertex; specular walls on faces normal to x, y or z.
+    The functions of this module (grad, flux_div, residual, moments, sweep,
+    steady, transient) take it like a two-dimensional case."""
+
+    def __init__(self, mesh, material, P=None):
+        xyz = np.asarray(mesh["xyz"], dtype=np.float64)
+        cells = np.asarray(mesh["cell_vtx"], dtype=np.int64).reshape(-1, 4)
+        ftag = np.asarray(mesh["face_tag"], dtype=np.int64).reshape(-1, 4)
+        self.tag_bc = np.asarray(mesh["tag_bc"], dtype=np.int64)
+        self.tag_T = np.asarray(mesh["tag_T"], dtype=np.float64)
+        nc = len(cells)
+        self.nc, self.dim = nc, 3
+        P4 = xyz[cells]                                        # [nc, 4, 3]
+        self.xc = P4.mean(axis=1)
+        self.V = np.abs(np.linalg.det(P4[:, 1:] - P4[:, :1])) / 6.0
+        owner = {}
+        for c in range(nc):
+            for k in range(4):
+                owner.setdefault(tuple(sorted(np.delete(cells[c], k))), []).append(c)
+        self.faces = []
+        for c in range(nc):
+            fl = []
+            for k in range(4):
+                f = np.delete(cells[c], k)
+                a, b, d = xyz[f]
+                cr = np.cross(b - a, d - a)
+                S = 0.5 * float(np.linalg.norm(cr))
+                n = cr / np.linalg.norm(cr)
+                xf = (a + b + d) / 3.0
+                if n @ (xf - xyz[cells[c][k]]) < 0:
+                    n = -n
+                others = [o for o in owner[tuple(sorted(f))] if o != c]
+                nb = others[0] if others else -1
+                tag = int(ftag[c][k])
+                if nb < 0 and tag < 0:
+                    raise ValueError("boundary face without a tag")
+                fl.append((nb, tag, S, n, xf))
+            self.faces.append(fl)
+        self.stencil = int(mesh.get("gradient_stencil", 0))
+        if self.stencil == 0:
+            vcells = {}
+            for c in range(nc):
+                for v in cells[c]:
+                    vcells.setdefault(int(v), set()).add(c)
+            self.lsn = []
+            for c in range(nc):
+                near = set()
+                for v in cells[c]:
+                    near |= vcells[int(v)]
+                near.discard(c)
+                self.lsn.append(sorted(near))
+        else:
+            self.lsn = [[nb for nb, _, _, _, _ in self.faces[c] if nb >= 0] for c in range(nc)]
+        self.Xinv = np.zeros((nc, 3, 3))
+        for c in range(nc):
+            X = np.zeros((3, 3))
+            for nb in self.lsn[c]:
+                d = self.xc[nb] - self.xc[c]
+                X += np.outer(d, d)
+            self.Xinv[c] = np.linalg.pinv(X, rcond=1e-10, hermitian=True)
+        m = material
+        self.s, self.w = quadrature(3, int(m["n_theta"]), int(m.get("n_phi", 1)), 3)
+        self.C = np.asarray(m["C"], dtype=np.float64)
+        self.v = np.asarray(m["v"], dtype=np.float64)
+        self.tau = np.asarray(m["tau"], dtype=np.float64)
+        self.Tref = float(m["Tref"])
+        self.na, self.nl = len(self.w), len(self.C)
+        self.nk = self.na * self.nl
+        self.C4 = self.C / FOURPI
+        self.Ctot = self.C.sum()
+        self.Ssum = (self.C / self.tau).sum()
+        self.P = None if P is None else np.asarray(P, dtype=np.float64)
+        self.mirror = np.zeros((3, self.na), dtype=np.int64)
+        for a in range(3):
+            for al in range(self.na):
+                t = self.s[al].copy()
+                t[a] = -t[a]
+                self.mirror[a, al] = int(np.argmin(np.abs(self.s - t).sum(axis=1)))
+        for c in range(nc):
+            for nb, tag, _, n, _ in self.faces[c]:
+                if nb < 0 and self.tag_bc[tag] == BC_SPECULAR and np.sort(np.abs(n))[1] > 1e-12:
+                    raise ValueError("specular walls must be normal to x, y or z")
+        self._order = None

@@ -231,3 +231,86 @@ def test_explicit_steps_conserve_energy_with_adiabatic_walls():
     scale = np.einsum("c,a,cal->", mc.V, mc.w, np.abs(e0.reshape(mc.nc, mc.na, mc.nl)))
     assert abs(energy(e1) - energy(e0)) <= 1e-12 * scale
     assert np.abs(e1 - e0).max() > 1e-3 * np.abs(e0).max()     # the state did move
+
+
+# ---------------------------------------------------------------- tetrahedra
+
+def tets(seed=1, n=(4, 3, 3), bc=(O.BC_THERMAL, O.BC_THERMAL) + (O.BC_SPECULAR,) * 4, **kw):
+    L = [x * 1e-7 for x in n]
+    return I.mesh3d(seed, *n, *L, jitter=0.15, bc=bc, **kw)
+
+
+def test_tet_geometry_closed_cells_outward_normals_total_volume():
+    mc = M.TetMeshCase(tets(), MAT)
+    assert abs(mc.V.sum() - 4e-7 * 3e-7 * 3e-7) <= 1e-12 * 3.6e-20
+    for c in range(mc.nc):
+        tot = sum(S * n for _, _, S, n, _ in mc.faces[c])
+        assert np.abs(tot).max() <= 1e-12 * 1e-14
+        for _, _, _, n, xf in mc.faces[c]:
+            assert n @ (xf - mc.xc[c]) > 0
+        # volume from the divergence theorem: V = (1/3) sum_f (x_f . n) S
+        assert abs(sum(xf @ n * S for _, _, S, n, xf in mc.faces[c]) / 3.0 - mc.V[c]) <= 1e-10 * mc.V[c]
+
+
+@pytest.mark.parametrize("stencil", [0, 1])
+def test_tet_gradient_and_flux_divergence_exact_for_linear_fields(stencil):
+    mc = M.TetMeshCase(dict(tets(n=(5, 4, 4)), gradient_stencil=stencil), MAT)
+    rng = np.random.default_rng(2)
+    a0, ax, ay, az = (rng.normal(size=mc.nk) for _ in range(4))
+    ax, ay, az = ax * 1e9, ay * 1e9, az * 1e9
+    e = a0[None, :] + mc.xc[:, :1] * ax + mc.xc[:, 1:2] * ay + mc.xc[:, 2:] * az
+    g = M.grad(mc, e)
+    # exact wherever the stencil spans space (with the face stencil a
+    # boundary tetrahedron may have one or two neighbours: pseudo-inverse)
+    full = np.array([np.linalg.matrix_rank(mc.Xinv[c]) == 3 for c in range(mc.nc)])
+    assert full.mean() > (0.999 if stencil == 0 else 0.6)
+    for q, a in enumerate((ax, ay, az)):
+        assert np.abs(g[full, q] - a).max() <= 1e-8 * np.abs(a).max()
+    D = M.flux_div(mc, e.reshape(-1)).reshape(mc.nc, mc.nk)
+    sx, sy, sz = (np.repeat(mc.s[:, q], mc.nl) for q in range(3))
+    exact = mc.lanes_v() * (sx * ax + sy * ay + sz * az)
+    interior = [c for c in range(mc.nc) if all(nb >= 0 and full[nb] for nb, *_ in mc.faces[c]) and full[c]]
+    assert len(interior) > 20
+    for c in interior:
+        assert np.abs(D[c] - exact).max() <= 1e-8 * np.abs(exact).max()
+
+
+@pytest.mark.parametrize("bc,pores", [((O.BC_SPECULAR,) * 6, ()),
+                                      ((O.BC_DIFFUSE, O.BC_SPECULAR) * 3, ()),
+                                      ((O.BC_SPECULAR,) * 6, [(2e-7, 1.5e-7, 1.5e-7, 0.9e-7)])])
+def test_tet_adiabatic_walls_conserve_energy(bc, pores):
+    mesh = tets(bc=bc, pores=pores)
+    if pores:
+        assert (mesh["face_tag"] == 6).sum() > 8
+    mc = M.TetMeshCase(mesh, MAT)
+    e = np.random.default_rng(4).normal(size=mc.size) * 1e3
+    D = M.flux_div(mc, e).reshape(mc.nc, mc.na, mc.nl)
+    tot = np.einsum("c,a,cal->", mc.V, mc.w, D)
+    assert abs(tot) <= 1e-13 * np.einsum("c,a,cal->", mc.V, mc.w, np.abs(D))
+    e1 = M.transient(mc, e, 3, 1e-13)
+    energy = lambda x: np.einsum("c,a,cal->", mc.V, mc.w, x.reshape(mc.nc, mc.na, mc.nl))   # noqa: E731
+    assert abs(energy(e1) - energy(e)) <= 1e-12 * np.einsum("c,a,cal->", mc.V, mc.w, np.abs(e.reshape(mc.nc, mc.na, mc.nl)))
+
+
+def test_tet_equilibrium_and_sweep_system():
+    mc = M.TetMeshCase(tets(bc=(O.BC_THERMAL,) * 6, bcT=(301.5,) * 6), MAT)
+    e = np.tile(mc.lanes_C4() * 1.5, mc.nc)
+    assert np.abs(M.residual(mc, e)).max() <= 1e-12 * np.abs(e).max() / mc.tau.min()
+    rng = np.random.default_rng(5)
+    e = rng.normal(size=mc.size) * 1e3
+    TL = rng.normal(size=mc.nc)
+    b = M.residual(mc, e, TL).reshape(mc.nc, mc.na, mc.nl)
+    de = (M.sweep(mc, e, TL) - e).reshape(mc.nc, mc.na, mc.nl)
+    for al in range(0, mc.na, 5):
+        _, lagged = M.upwind_order(mc, al)
+        for l in range(mc.nl):
+            A = np.diag(np.full(mc.nc, 1.0 / mc.tau[l]))
+            for c in range(mc.nc):
+                for nb, _, S, n, _ in mc.faces[c]:
+                    sn = mc.s[al] @ n
+                    if sn > 0:
+                        A[c, c] += mc.v[l] * sn * S / mc.V[c]
+                    elif sn < 0 and nb >= 0 and (c, nb) not in lagged:
+                        A[c, nb] -= mc.v[l] * (-sn) * S / mc.V[c]
+            r = A @ de[:, al, l] - b[:, al, l]
+            assert np.abs(r).max() <= 1e-12 * np.abs(b[:, al, l]).max()
