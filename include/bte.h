@@ -499,6 +499,25 @@ typedef struct {
     int gradient_stencil;    /* 0: cells sharing a vertex, 1: face neighbours     */
 } bte_mesh;
 
+/* Tetrahedral meshes (three dimensions): cell volume |det| / 6, centre =
+ * vertex mean, face k of a cell = the triangle opposite its vertex k (area
+ * |cross| / 2, centre = vertex mean, normal away from vertex k); the
+ * least-squares fit is 3 x 3; specular faces must be normal to x, y or z.
+ * Everything else as for bte_mesh. */
+typedef struct {
+    int n_vertices;
+    const double *xyz;       /* host [n_vertices][3] vertex coordinates, m       */
+    int n_cells;
+    const int *cell_vtx;     /* host [n_cells][4] vertices of each tetrahedron   */
+    const int *face_tag;     /* host [n_cells][4]: boundary tag of the face
+                                opposite vertex k, -1 for a shared face          */
+    int n_tags;
+    const int *tag_bc;       /* host [n_tags]: BTE_BC_THERMAL, BTE_BC_SPECULAR or
+                                BTE_BC_DIFFUSE                                   */
+    const double *tag_T;     /* host [n_tags]: wall temperature, K (thermalizing) */
+    int gradient_stencil;    /* 0: cells sharing a vertex, 1: face neighbours     */
+} bte_tet_mesh;
+
 typedef struct bte_mesh_problem bte_mesh_problem;
 
 /* Builds the geometry, least-squares matrices, wall records, directions and
@@ -512,6 +531,11 @@ typedef struct bte_mesh_problem bte_mesh_problem;
  * allocation succeeded (destroy it also on error). */
 bte_status bte_mesh_setup(const bte_mesh *mesh, const bte_material *mat, const bte_control *ctl,
                           bte_mesh_problem **out);
+/* The same for a tetrahedral mesh (errors as above: zero volume or area,
+ * a face shared by more than two cells, tags, a specular face not normal
+ * to an axis); the problem takes every bte_mesh_* call below. */
+bte_status bte_mesh_setup_tet(const bte_tet_mesh *mesh, const bte_material *mat, const bte_control *ctl,
+                              bte_mesh_problem **out);
 /* Device workspace the caller provides (256-byte aligned) and binds. */
 size_t bte_mesh_workspace_bytes(const bte_mesh_problem *p);
 bte_status bte_mesh_bind(bte_mesh_problem *p, void *ws_dev, size_t bytes);

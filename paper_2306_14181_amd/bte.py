@@ -34,7 +34,7 @@ EXPORTS = ["bte_setup", "bte_setup_multi", "bte_set_control", "bte_workspace_byt
            "bte_autotune", "bte_last_stats",
            "bte_get_directions", "bte_band_discretize", "bte_band_discretize_dev",
            "bte_band_discretize_scratch_bytes", "bte_last_error", "bte_destroy",
-           "bte_mesh_setup", "bte_mesh_workspace_bytes", "bte_mesh_bind", "bte_mesh_num_cells",
+           "bte_mesh_setup", "bte_mesh_setup_tet", "bte_mesh_workspace_bytes", "bte_mesh_bind", "bte_mesh_num_cells",
            "bte_mesh_num_directions", "bte_mesh_num_levels", "bte_mesh_num_lagged", "bte_mesh_set_source",
            "bte_mesh_moments", "bte_mesh_residual", "bte_mesh_steady_solve", "bte_mesh_transient_step",
            "bte_mesh_last_error", "bte_mesh_destroy"]
@@ -68,6 +68,12 @@ class Mesh(C.Structure):
                 ("cell_ptr", C.POINTER(C.c_int)), ("cell_vtx", C.POINTER(C.c_int)), ("edge_tag", C.POINTER(C.c_int)),
                 ("n_tags", C.c_int), ("tag_bc", C.POINTER(C.c_int)), ("tag_T", C.POINTER(C.c_double)),
                 ("gradient_stencil", C.c_int)]
+
+
+class TetMesh(C.Structure):
+    _fields_ = [("n_vertices", C.c_int), ("xyz", C.POINTER(C.c_double)), ("n_cells", C.c_int),
+                ("cell_vtx", C.POINTER(C.c_int)), ("face_tag", C.POINTER(C.c_int)), ("n_tags", C.c_int),
+                ("tag_bc", C.POINTER(C.c_int)), ("tag_T", C.POINTER(C.c_double)), ("gradient_stencil", C.c_int)]
 
 
 class Control(C.Structure):
@@ -141,6 +147,7 @@ def load():
         "bte_last_error": ([vp], C.c_char_p),
         "bte_destroy": ([vp], None),
         "bte_mesh_setup": ([C.POINTER(Mesh), C.POINTER(Material), C.POINTER(Control), C.POINTER(vp)], st),
+        "bte_mesh_setup_tet": ([C.POINTER(TetMesh), C.POINTER(Material), C.POINTER(Control), C.POINTER(vp)], st),
         "bte_mesh_workspace_bytes": ([vp], C.c_size_t),
         "bte_mesh_bind": ([vp, vp, C.c_size_t], st),
         "bte_mesh_num_cells": ([vp], C.c_int),
@@ -569,10 +576,25 @@ class TaveTransient(torch.autograd.Function):
 
 
 def mesh_struct(mesh):
-    """ctypes bte_mesh of a mesh dict (xy, cell_ptr, cell_vtx, edge_tag,
-    tag_bc, tag_T, optional gradient_stencil; see bte_inputs.mesh2d) and the
-    arrays it points into."""
+    """ctypes bte_mesh of a 2D mesh dict (xy, cell_ptr, cell_vtx, edge_tag,
+    tag_bc, tag_T, optional gradient_stencil; see bte_inputs.mesh2d), or
+    bte_tet_mesh of a tetrahedral one (xyz, cell_vtx [n][4], face_tag
+    [n][4], tag_bc, tag_T; bte_inputs.mesh3d), and the arrays it points
+    into."""
     import numpy as np
+    if "xyz" in mesh:
+        xyz = np.ascontiguousarray(mesh["xyz"], dtype=np.float64).reshape(-1, 3)
+        vtx = np.ascontiguousarray(mesh["cell_vtx"], dtype=np.int32).reshape(-1, 4)
+        tag = np.ascontiguousarray(mesh["face_tag"], dtype=np.int32).reshape(-1, 4)
+        tbc = np.ascontiguousarray(mesh["tag_bc"], dtype=np.int32)
+        tT = np.ascontiguousarray(mesh["tag_T"], dtype=np.float64)
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int))   # noqa: E731
+        m = TetMesh()
+        m.n_vertices, m.xyz = len(xyz), xyz.ctypes.data_as(C.POINTER(C.c_double))
+        m.n_cells, m.cell_vtx, m.face_tag = len(vtx), ip(vtx), ip(tag)
+        m.n_tags, m.tag_bc, m.tag_T = len(tbc), ip(tbc), tT.ctypes.data_as(C.POINTER(C.c_double))
+        m.gradient_stencil = int(mesh.get("gradient_stencil", 0))
+        return m, (xyz, vtx, tag, tbc, tT)
     xy = np.ascontiguousarray(mesh["xy"], dtype=np.float64).reshape(-1, 2)
     ptr = np.ascontiguousarray(mesh["cell_ptr"], dtype=np.int32)
     vtx = np.ascontiguousarray(mesh["cell_vtx"], dtype=np.int32)
@@ -589,8 +611,9 @@ def mesh_struct(mesh):
 
 
 class MeshProblem:
-    """Steady solves and explicit transient steps on an unstructured 2D mesh
-    (bte_mesh_*), bound to a device workspace.  control: precision,
+    """Steady solves and explicit transient steps on an unstructured mesh
+    (2D triangles / quadrilaterals or tetrahedra; bte_mesh_*), bound to a
+    device workspace.  control: precision,
     max_iter, residual_temp, dt (scheme SEQUENTIAL and limiter NONE)."""
 
     def __init__(self, mesh, material, control, device="cuda"):
@@ -609,7 +632,8 @@ class MeshProblem:
         c = _control_struct(ctl)
         self.dtype = torch.float64 if c.precision == F64 else torch.float32
         h = C.c_void_p()
-        st = lib.bte_mesh_setup(C.byref(ms), C.byref(mt), C.byref(c), C.byref(h))
+        setup = lib.bte_mesh_setup_tet if isinstance(ms, TetMesh) else lib.bte_mesh_setup
+        st = setup(C.byref(ms), C.byref(mt), C.byref(c), C.byref(h))
         self._h = h
         if st != BTE_OK:
             msg = lib.bte_mesh_last_error(h).decode() if h else "setup failed"

@@ -1,5 +1,6 @@
-// bte_mesh.hip -- steady BTE on unstructured two-dimensional meshes of
-// triangles and quadrilaterals (Sec. 3.3, eq. disretized_BTE: second-order
+// bte_mesh.hip -- the BTE on unstructured meshes: two-dimensional meshes of
+// triangles and quadrilaterals, three-dimensional meshes of tetrahedra
+// (Sec. 3.3, eq. disretized_BTE: second-order
 // upwind face values from least-squares gradients on the right-hand side,
 // the first-order upwind stiffness matrix of Sec. 3.5 on the left; the
 // sequential scheme of Sec. 3.4).
@@ -25,6 +26,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <map>
 #include <string>
 #include <vector>
@@ -35,7 +37,9 @@
 namespace bte {
 namespace {
 
-constexpr int kFG = 8;   // doubles per face slot: S/V, n_x, n_y, l_x, l_y, d_x, d_y, unused
+// doubles per face slot: S/V, n (3), l = x_f - x_i (3), d = x_j - x_i (3)
+// (two-dimensional meshes: z components zero)
+constexpr int kFG = 10;
 
 struct MeshDev {
     int nc, na, nl, nk;
@@ -44,15 +48,15 @@ struct MeshDev {
     const int *ftag;       // [nf] boundary tag, -1 inside
     const int *frec;       // [nf] diffuse-wall record, -1 otherwise
     const double *fgeo;    // [nf][kFG]
-    const double *xinv;    // [nc][3] symmetric X^+ = [[a, b], [b, c]]
+    const double *xinv;    // [nc][6] symmetric X^+: 00, 01, 02, 11, 12, 22
     const int *lsptr;      // [nc + 1] least-squares stencil of each cell
     const int *lsnb;       // [nls] stencil cells
-    const double *lsd;     // [nls][2] offsets x_j - x_i
+    const double *lsd;     // [nls][3] offsets x_j - x_i
     const int *tag_bc;     // [ntag]
     const double *tag_dT;  // [ntag] wall temperature - T_ref
     const double *s;       // [na][3]
     const double *w;       // [na]
-    const int *mirror;     // [2][na]: flip s_x, flip s_y
+    const int *mirror;     // [3][na]: flip s_x, s_y, s_z
     const double *C4, *v, *itau;   // [nl]
     double Ctot, Ssum;
     const double *P;       // [nc] heat source or null
@@ -67,7 +71,8 @@ struct MeshDev {
     const double4 *item_coef;
 };
 
-template <typename T>
+// gradient of lane k of cell c: D components at g[(c * D + q) * nk + k]
+template <typename T, int D>
 __global__ __launch_bounds__(kBlock) void k_mesh_grad(MeshDev d, const T *__restrict__ e, T *__restrict__ g, int nkb)
 {
     // block = (cell, block of 256 lanes)
@@ -75,30 +80,35 @@ __global__ __launch_bounds__(kBlock) void k_mesh_grad(MeshDev d, const T *__rest
     const int k = (blockIdx.x - c * nkb) * kBlock + threadIdx.x;
     if (k >= d.nk) return;
     const double ec = (double)e[(size_t)c * d.nk + k];
-    double y0 = 0.0, y1 = 0.0;
+    double y[3] = {0.0, 0.0, 0.0};
     for (int j = d.lsptr[c]; j < d.lsptr[c + 1]; ++j) {
         const double diff = (double)e[(size_t)d.lsnb[j] * d.nk + k] - ec;
-        y0 += d.lsd[2 * j] * diff;
-        y1 += d.lsd[2 * j + 1] * diff;
+#pragma unroll
+        for (int q = 0; q < D; ++q) y[q] += d.lsd[3 * j + q] * diff;
     }
-    const double a = d.xinv[3 * c], b = d.xinv[3 * c + 1], cc = d.xinv[3 * c + 2];
-    g[((size_t)c * 2) * d.nk + k] = (T)(a * y0 + b * y1);
-    g[((size_t)c * 2 + 1) * d.nk + k] = (T)(b * y0 + cc * y1);
+    const double *xi = d.xinv + 6 * (size_t)c;
+    const double gx = xi[0] * y[0] + xi[1] * y[1] + xi[2] * y[2];
+    const double gy = xi[1] * y[0] + xi[3] * y[1] + xi[4] * y[2];
+    g[((size_t)c * D) * d.nk + k] = (T)gx;
+    g[((size_t)c * D + 1) * d.nk + k] = (T)gy;
+    if constexpr (D == 3) g[((size_t)c * D + 2) * d.nk + k] = (T)(xi[2] * y[0] + xi[4] * y[1] + xi[5] * y[2]);
 }
 
-// outgoing second-order face value of lane k of cell c at the offset
-// (lx, ly) of the face centre from the cell centre
-template <typename T>
+// outgoing second-order face value of lane k of cell c at the offset l of
+// the face centre from the cell centre
+template <typename T, int D>
 __device__ inline double face_out(const MeshDev &d, const T *__restrict__ e, const T *__restrict__ g, int c, int k,
-                                  double lx, double ly)
+                                  double lx, double ly, double lz)
 {
-    return (double)e[(size_t)c * d.nk + k] + (double)g[((size_t)c * 2) * d.nk + k] * lx +
-           (double)g[((size_t)c * 2 + 1) * d.nk + k] * ly;
+    double v = (double)e[(size_t)c * d.nk + k] + (double)g[((size_t)c * D) * d.nk + k] * lx +
+               (double)g[((size_t)c * D + 1) * d.nk + k] * ly;
+    if constexpr (D == 3) v += (double)g[((size_t)c * D + 2) * d.nk + k] * lz;
+    return v;
 }
 
 // Diffuse-wall inflow per record and band: outgoing energy flux of the face
 // over the incoming quadrature weight (one block per record).
-template <typename T>
+template <typename T, int D>
 __global__ __launch_bounds__(kBlock) void k_mesh_walls(MeshDev d, const T *__restrict__ e, const T *__restrict__ g,
                                                        double *__restrict__ din)
 {
@@ -111,8 +121,8 @@ __global__ __launch_bounds__(kBlock) void k_mesh_walls(MeshDev d, const T *__res
     double sum = 0.0;
     if (grp < G)
         for (int al = grp; al < d.na; al += G) {
-            const double sn = d.s[3 * al] * fg[1] + d.s[3 * al + 1] * fg[2];
-            if (sn > 0.0) sum += d.w[al] * sn * face_out(d, e, g, c, al * d.nl + l, fg[3], fg[4]);
+            const double sn = d.s[3 * al] * fg[1] + d.s[3 * al + 1] * fg[2] + d.s[3 * al + 2] * fg[3];
+            if (sn > 0.0) sum += d.w[al] * sn * face_out<T, D>(d, e, g, c, al * d.nl + l, fg[4], fg[5], fg[6]);
         }
     sh[threadIdx.x] = sum;
     __syncthreads();
@@ -124,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_mesh_walls(MeshDev d, const T *__res
 }
 
 // R = -(1/V) sum_f v (s.n) S e_f - (e - C4 T_L) / tau + C4 P / C_tot
-template <typename T>
+template <typename T, int D>
 __global__ __launch_bounds__(kBlock) void k_mesh_residual(MeshDev d, const T *__restrict__ e, const T *__restrict__ g,
                                                           const double *__restrict__ din,
                                                           const double *__restrict__ TLdev, T *__restrict__ R,
@@ -134,27 +144,28 @@ __global__ __launch_bounds__(kBlock) void k_mesh_residual(MeshDev d, const T *__
     const int k = (blockIdx.x - c * nkb) * kBlock + threadIdx.x;
     if (k >= d.nk) return;
     const int al = k / d.nl, l = k - al * d.nl;
-    const double sx = d.s[3 * al], sy = d.s[3 * al + 1];
+    const double sx = d.s[3 * al], sy = d.s[3 * al + 1], sz = d.s[3 * al + 2];
     double acc = 0.0;
     for (int f = d.fptr[c]; f < d.fptr[c + 1]; ++f) {
         const double *fg = d.fgeo + (size_t)f * kFG;
-        const double sn = sx * fg[1] + sy * fg[2];
+        const double sn = sx * fg[1] + sy * fg[2] + sz * fg[3];
         double ef;
         if (sn > 0.0) {
-            ef = face_out(d, e, g, c, k, fg[3], fg[4]);
+            ef = face_out<T, D>(d, e, g, c, k, fg[4], fg[5], fg[6]);
         } else if (sn < 0.0) {
             const int nb = d.fnb[f];
             if (nb >= 0) {
-                ef = face_out(d, e, g, nb, k, fg[3] - fg[5], fg[4] - fg[6]);
+                ef = face_out<T, D>(d, e, g, nb, k, fg[4] - fg[7], fg[5] - fg[8], fg[6] - fg[9]);
             } else {
                 const int tag = d.ftag[f];
                 const int kind = d.tag_bc[tag];
                 if (kind == BTE_BC_THERMAL) {
                     ef = d.C4[l] * d.tag_dT[tag];
                 } else if (kind == BTE_BC_SPECULAR) {
-                    const int axis = fabs(fg[1]) > 0.5 ? 0 : 1;
+                    // the wall's normal axis (the face is normal to x, y or z)
+                    const int axis = fabs(fg[1]) > 0.5 ? 0 : (fabs(fg[2]) > 0.5 ? 1 : 2);
                     const int km = d.mirror[axis * d.na + al] * d.nl + l;
-                    ef = face_out(d, e, g, c, km, fg[3], fg[4]);
+                    ef = face_out<T, D>(d, e, g, c, km, fg[4], fg[5], fg[6]);
                 } else {
                     ef = din[(size_t)d.frec[f] * d.nl + l];
                 }
@@ -277,7 +288,7 @@ using namespace bte;
 struct bte_mesh_problem {
     bte_control ctl{};
     std::string err;
-    int nc = 0, na = 0, nl = 0, nk = 0, nf = 0, nrec = 0, ntag = 0, nlev = 0, nlag = 0;
+    int nc = 0, na = 0, nl = 0, nk = 0, nf = 0, nrec = 0, ntag = 0, nlev = 0, nlag = 0, dim = 2;
     double Tref = 0;
     // host tables
     std::vector<int> fptr, fnb, ftag, frec, tag_bc, mirror, rec_cell, rec_face, lev_off, lsptr, lsnb;
@@ -322,21 +333,19 @@ namespace {
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// symmetric 2 x 2 pseudo-inverse [[xx, xy], [xy, yy]]^+ (eigenvalues below
-// 1e-10 of the largest dropped)
-void pinv2(double xx, double xy, double yy, double out[3])
+// Symmetric pseudo-inverse, eigenvalues below 1e-10 of the largest dropped.
+// 2 x 2 [[xx, xy], [xy, yy]] in closed form; out = 00, 01, 02, 11, 12, 22.
+void pinv2(double xx, double xy, double yy, double out[6])
 {
+    for (int i = 0; i < 6; ++i) out[i] = 0.0;
     const double h = 0.5 * (xx + yy), r = std::sqrt(0.25 * (xx - yy) * (xx - yy) + xy * xy);
     const double l1 = h + r, l2 = h - r;
-    if (!(l1 > 0)) {
-        out[0] = out[1] = out[2] = 0.0;
-        return;
-    }
+    if (!(l1 > 0)) return;
     if (l2 > 1e-10 * l1) {
         const double det = xx * yy - xy * xy;
         out[0] = yy / det;
         out[1] = -xy / det;
-        out[2] = xx / det;
+        out[3] = xx / det;
         return;
     }
     // rank one: X^+ = u u^T / l1 with u the unit eigenvector of l1
@@ -347,139 +356,112 @@ void pinv2(double xx, double xy, double yy, double out[3])
     uy /= n;
     out[0] = ux * ux / l1;
     out[1] = ux * uy / l1;
-    out[2] = uy * uy / l1;
+    out[3] = uy * uy / l1;
 }
 
-bte_status mesh_build(bte_mesh_problem *p, const bte_mesh *m, const bte_material *mat)
+// 3 x 3 by cyclic Jacobi rotations (to machine precision), then
+// X^+ = sum over kept eigenpairs of u u^T / lambda.
+void pinv3(const double X[3][3], double out[6])
 {
-    const int nc = m->n_cells;
-    if (nc < 1 || m->n_vertices < 3 || !m->xy || !m->cell_ptr || !m->cell_vtx || !m->edge_tag)
-        MFAIL(p, BTE_ERR_ARG, "mesh: empty or null arrays");
-    if (m->n_tags < 0 || (m->n_tags > 0 && (!m->tag_bc || !m->tag_T))) MFAIL(p, BTE_ERR_ARG, "mesh: bad tags");
-    if (m->cell_ptr[0] != 0) MFAIL(p, BTE_ERR_ARG, "mesh: cell_ptr[0] must be 0");
-    p->nc = nc;
-    p->ntag = m->n_tags;
-    p->Tref = mat->T_ref;
-    for (int t = 0; t < m->n_tags; ++t) {
-        const int k = m->tag_bc[t];
-        if (k != BTE_BC_THERMAL && k != BTE_BC_SPECULAR && k != BTE_BC_DIFFUSE)
-            MFAIL(p, BTE_ERR_ARG, "mesh: tag %d: boundary condition must be thermal, specular or diffuse", t);
-        p->tag_bc.push_back(k);
-        p->tag_dT.push_back(m->tag_T[t] - mat->T_ref);
-    }
-    std::vector<double> V(nc), xc(2 * (size_t)nc);
-    for (int c = 0; c < nc; ++c) {
-        const int a = m->cell_ptr[c], b = m->cell_ptr[c + 1], nv = b - a;
-        if (nv != 3 && nv != 4) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d has %d vertices (3 or 4)", c, nv);
-        double A = 0, cx = 0, cy = 0;
-        for (int k = 0; k < nv; ++k) {
-            const int i = m->cell_vtx[a + k], j = m->cell_vtx[a + (k + 1) % nv];
-            if (i < 0 || i >= m->n_vertices || j < 0 || j >= m->n_vertices)
-                MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: vertex index out of range", c);
-            const double x0 = m->xy[2 * i], y0 = m->xy[2 * i + 1], x1 = m->xy[2 * j], y1 = m->xy[2 * j + 1];
-            const double cr = x0 * y1 - x1 * y0;
-            A += cr;
-            cx += (x0 + x1) * cr;
-            cy += (y0 + y1) * cr;
-        }
-        A *= 0.5;
-        if (!(A > 0)) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d is not counter-clockwise with positive area", c);
-        V[c] = A;
-        xc[2 * c] = cx / (6.0 * A);
-        xc[2 * c + 1] = cy / (6.0 * A);
-    }
-    const int nf = m->cell_ptr[nc];
-    p->nf = nf;
-    std::map<std::pair<int, int>, std::vector<int>> owner;   // edge -> face slots
-    for (int c = 0; c < nc; ++c) {
-        const int a = m->cell_ptr[c], nv = m->cell_ptr[c + 1] - a;
-        for (int k = 0; k < nv; ++k) {
-            const int i = m->cell_vtx[a + k], j = m->cell_vtx[a + (k + 1) % nv];
-            owner[{std::min(i, j), std::max(i, j)}].push_back(a + k);
-        }
-    }
-    std::vector<int> slot_cell(nf);
-    for (int c = 0; c < nc; ++c)
-        for (int f = m->cell_ptr[c]; f < m->cell_ptr[c + 1]; ++f) slot_cell[f] = c;
-    p->fptr.assign(m->cell_ptr, m->cell_ptr + nc + 1);
-    p->fnb.assign(nf, -1);
-    p->ftag.assign(nf, -1);
-    p->frec.assign(nf, -1);
-    p->fgeo.assign((size_t)nf * kFG, 0.0);
-    for (auto &kv : owner) {
-        if (kv.second.size() > 2) MFAIL(p, BTE_ERR_ARG, "mesh: an edge is shared by more than two cells");
-        if (kv.second.size() == 2) {
-            p->fnb[kv.second[0]] = slot_cell[kv.second[1]];
-            p->fnb[kv.second[1]] = slot_cell[kv.second[0]];
-        }
-    }
-    for (int c = 0; c < nc; ++c) {
-        const int a = m->cell_ptr[c], nv = m->cell_ptr[c + 1] - a;
-        for (int k = 0; k < nv; ++k) {
-            const int f = a + k;
-            const int i = m->cell_vtx[f], j = m->cell_vtx[a + (k + 1) % nv];
-            const double dx = m->xy[2 * j] - m->xy[2 * i], dy = m->xy[2 * j + 1] - m->xy[2 * i + 1];
-            const double S = std::hypot(dx, dy);
-            if (!(S > 0)) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d has an edge of zero length", c);
-            const double nx = dy / S, ny = -dx / S;
-            const double xf = 0.5 * (m->xy[2 * i] + m->xy[2 * j]), yf = 0.5 * (m->xy[2 * i + 1] + m->xy[2 * j + 1]);
-            double *fg = &p->fgeo[(size_t)f * kFG];
-            fg[0] = S / V[c];
-            fg[1] = nx;
-            fg[2] = ny;
-            fg[3] = xf - xc[2 * c];
-            fg[4] = yf - xc[2 * c + 1];
-            const int nb = p->fnb[f], tag = m->edge_tag[f];
-            if (nb >= 0) {
-                if (tag >= 0) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: a shared edge carries a boundary tag", c);
-                fg[5] = xc[2 * nb] - xc[2 * c];
-                fg[6] = xc[2 * nb + 1] - xc[2 * c + 1];
-            } else {
-                if (tag < 0 || tag >= m->n_tags) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: boundary edge without a valid tag", c);
-                p->ftag[f] = tag;
-                if (p->tag_bc[tag] == BTE_BC_SPECULAR && std::min(std::fabs(nx), std::fabs(ny)) > 1e-12)
-                    MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: specular edge not parallel to x or y", c);
+    double A[3][3], U[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) A[i][j] = X[i][j];
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+        if (off <= 1e-32 * dia) break;
+        for (int pq = 0; pq < 3; ++pq) {
+            const int pi = pq == 2 ? 1 : 0, qi = pq == 0 ? 1 : 2;
+            if (A[pi][qi] == 0.0) continue;
+            const double th = 0.5 * (A[qi][qi] - A[pi][pi]) / A[pi][qi];
+            const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+            const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+            for (int k = 0; k < 3; ++k) {   // A <- A R (columns pi, qi)
+                const double akp = A[k][pi], akq = A[k][qi];
+                A[k][pi] = cs * akp - sn * akq;
+                A[k][qi] = sn * akp + cs * akq;
+            }
+            for (int k = 0; k < 3; ++k) {   // A <- R^T A (rows pi, qi)
+                const double apk = A[pi][k], aqk = A[qi][k];
+                A[pi][k] = cs * apk - sn * aqk;
+                A[qi][k] = sn * apk + cs * aqk;
+            }
+            for (int k = 0; k < 3; ++k) {   // U <- U R
+                const double ukp = U[k][pi], ukq = U[k][qi];
+                U[k][pi] = cs * ukp - sn * ukq;
+                U[k][qi] = sn * ukp + cs * ukq;
             }
         }
     }
-    // least-squares stencils, ascending cell index
-    if (m->gradient_stencil != 0 && m->gradient_stencil != 1) MFAIL(p, BTE_ERR_ARG, "mesh: gradient_stencil 0 or 1");
+    const double lmax = std::max(A[0][0], std::max(A[1][1], A[2][2]));
+    for (int i = 0; i < 6; ++i) out[i] = 0.0;
+    if (!(lmax > 0)) return;
+    const int idx[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    for (int m = 0; m < 3; ++m) {
+        const double lm = A[m][m];
+        if (!(lm > 1e-10 * lmax)) continue;
+        for (int i = 0; i < 6; ++i) out[i] += U[idx[i][0]][m] * U[idx[i][1]][m] / lm;
+    }
+}
+
+bte_status mesh_tags(bte_mesh_problem *p, int n_tags, const int *tag_bc, const double *tag_T,
+                     const bte_material *mat)
+{
+    if (n_tags < 0 || (n_tags > 0 && (!tag_bc || !tag_T))) MFAIL(p, BTE_ERR_ARG, "mesh: bad tags");
+    p->ntag = n_tags;
+    p->Tref = mat->T_ref;
+    for (int t = 0; t < n_tags; ++t) {
+        const int k = tag_bc[t];
+        if (k != BTE_BC_THERMAL && k != BTE_BC_SPECULAR && k != BTE_BC_DIFFUSE)
+            MFAIL(p, BTE_ERR_ARG, "mesh: tag %d: boundary condition must be thermal, specular or diffuse", t);
+        p->tag_bc.push_back(k);
+        p->tag_dT.push_back(tag_T[t] - mat->T_ref);
+    }
+    return BTE_OK;
+}
+
+// Everything after the cells' geometry: least-squares stencils and
+// matrices, directions, bands, diffuse-wall records and the sweep schedule.
+// V, xc (3 per cell), the face slots in p, and the vertices of each cell
+// (cptr / cvtx, for the vertex stencil) are given.
+bte_status mesh_finish(bte_mesh_problem *p, const bte_material *mat, int stencil, const std::vector<double> &xc,
+                       const std::vector<int> &cptr, const std::vector<int> &cvtx, int nvert)
+{
+    const int nc = p->nc, D = p->dim;
+    if (stencil != 0 && stencil != 1) MFAIL(p, BTE_ERR_ARG, "mesh: gradient_stencil 0 or 1");
     std::vector<std::vector<int>> vcells;
-    if (m->gradient_stencil == 0) {
-        vcells.assign(m->n_vertices, {});
+    if (stencil == 0) {
+        vcells.assign(nvert, {});
         for (int c = 0; c < nc; ++c)
-            for (int f = m->cell_ptr[c]; f < m->cell_ptr[c + 1]; ++f) vcells[m->cell_vtx[f]].push_back(c);
+            for (int f = cptr[c]; f < cptr[c + 1]; ++f) vcells[cvtx[f]].push_back(c);
     }
     p->lsptr.assign(1, 0);
     for (int c = 0; c < nc; ++c) {
         std::vector<int> near;
-        for (int f = m->cell_ptr[c]; f < m->cell_ptr[c + 1]; ++f) {
-            if (m->gradient_stencil == 0) {
-                for (int j : vcells[m->cell_vtx[f]])
+        if (stencil == 0) {
+            for (int f = cptr[c]; f < cptr[c + 1]; ++f)
+                for (int j : vcells[cvtx[f]])
                     if (j != c) near.push_back(j);
-            } else if (p->fnb[f] >= 0) {
-                near.push_back(p->fnb[f]);
-            }
+        } else {
+            for (int f = p->fptr[c]; f < p->fptr[c + 1]; ++f)
+                if (p->fnb[f] >= 0) near.push_back(p->fnb[f]);
         }
         std::sort(near.begin(), near.end());
         near.erase(std::unique(near.begin(), near.end()), near.end());
         for (int j : near) {
             p->lsnb.push_back(j);
-            p->lsd.push_back(xc[2 * j] - xc[2 * c]);
-            p->lsd.push_back(xc[2 * j + 1] - xc[2 * c + 1]);
+            for (int q = 0; q < 3; ++q) p->lsd.push_back(xc[3 * j + q] - xc[3 * c + q]);
         }
         p->lsptr.push_back((int)p->lsnb.size());
     }
-    p->xinv.assign(3 * (size_t)nc, 0.0);
+    p->xinv.assign(6 * (size_t)nc, 0.0);
     for (int c = 0; c < nc; ++c) {
-        double xx = 0, xy = 0, yy = 0;
-        for (int j = p->lsptr[c]; j < p->lsptr[c + 1]; ++j) {
-            const double dx = p->lsd[2 * (size_t)j], dy = p->lsd[2 * (size_t)j + 1];
-            xx += dx * dx;
-            xy += dx * dy;
-            yy += dy * dy;
-        }
-        pinv2(xx, xy, yy, &p->xinv[3 * (size_t)c]);
+        double X[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int j = p->lsptr[c]; j < p->lsptr[c + 1]; ++j)
+            for (int a = 0; a < 3; ++a)
+                for (int b2 = 0; b2 < 3; ++b2) X[a][b2] += p->lsd[3 * (size_t)j + a] * p->lsd[3 * (size_t)j + b2];
+        if (D == 2) pinv2(X[0][0], X[0][1], X[1][1], &p->xinv[6 * (size_t)c]);
+        else pinv3(X, &p->xinv[6 * (size_t)c]);
     }
     // directions (bulk material: on the sphere, 4 pi)
     if (mat->n_theta < 1 || mat->n_phi < 1) MFAIL(p, BTE_ERR_ARG, "n_theta and n_phi must be >= 1");
@@ -488,8 +470,8 @@ bte_status mesh_build(bte_mesh_problem *p, const bte_mesh *m, const bte_material
     p->nl = mat->n_bands;
     p->nk = p->na * p->nl;
     if ((double)p->na * nc >= 2147483647.0) MFAIL(p, BTE_ERR_ARG, "mesh: directions x cells must stay below 2^31");
-    p->mirror.assign(2 * (size_t)p->na, 0);
-    for (int a = 0; a < 2; ++a)
+    p->mirror.assign(3 * (size_t)p->na, 0);
+    for (int a = 0; a < 3; ++a)
         for (int al = 0; al < p->na; ++al) {
             double t[3] = {p->s[3 * al], p->s[3 * al + 1], p->s[3 * al + 2]};
             t[a] = -t[a];
@@ -519,13 +501,19 @@ bte_status mesh_build(bte_mesh_problem *p, const bte_mesh *m, const bte_material
         for (int f = p->fptr[c]; f < p->fptr[c + 1]; ++f) sv += p->fgeo[(size_t)f * kFG];
         p->sv_max = std::max(p->sv_max, sv);
     }
+    auto sdotn = [&](int al, int f) {
+        const double *fg = &p->fgeo[(size_t)f * kFG];
+        return p->s[3 * al] * fg[1] + p->s[3 * al + 1] * fg[2] + p->s[3 * al + 2] * fg[3];
+    };
     // diffuse-wall records
-    for (int f = 0; f < nf; ++f) {
+    std::vector<int> slot_cell(p->nf);
+    for (int c = 0; c < nc; ++c)
+        for (int f = p->fptr[c]; f < p->fptr[c + 1]; ++f) slot_cell[f] = c;
+    for (int f = 0; f < p->nf; ++f) {
         if (p->fnb[f] >= 0 || p->tag_bc[p->ftag[f]] != BTE_BC_DIFFUSE) continue;
-        const double nx = p->fgeo[(size_t)f * kFG + 1], ny = p->fgeo[(size_t)f * kFG + 2];
         double den = 0;
         for (int al = 0; al < p->na; ++al) {
-            const double sn = p->s[3 * al] * nx + p->s[3 * al + 1] * ny;
+            const double sn = sdotn(al, f);
             if (sn < 0) den += p->w[al] * (-sn);
         }
         p->frec[f] = p->nrec++;
@@ -540,16 +528,13 @@ bte_status mesh_build(bte_mesh_problem *p, const bte_mesh *m, const bte_material
     p->nlag = 0;
     int maxlev = 0;
     for (int al = 0; al < p->na; ++al) {
-        const double sx = p->s[3 * al], sy = p->s[3 * al + 1];
-        std::vector<std::vector<int>> down(nc);
+        std::vector<std::vector<int>> down(nc), deps(nc);
         std::vector<int> indeg(nc, 0);
-        std::vector<std::vector<int>> deps(nc);
         for (int c = 0; c < nc; ++c)
             for (int f = p->fptr[c]; f < p->fptr[c + 1]; ++f) {
                 const int nb = p->fnb[f];
                 if (nb < 0) continue;
-                const double sn = sx * p->fgeo[(size_t)f * kFG + 1] + sy * p->fgeo[(size_t)f * kFG + 2];
-                if (sn < 0 && std::find(deps[c].begin(), deps[c].end(), nb) == deps[c].end()) {
+                if (sdotn(al, f) < 0 && std::find(deps[c].begin(), deps[c].end(), nb) == deps[c].end()) {
                     deps[c].push_back(nb);
                     down[nb].push_back(c);
                 }
@@ -606,8 +591,7 @@ bte_status mesh_build(bte_mesh_problem *p, const bte_mesh *m, const bte_material
     p->item_up.assign(ni, make_int4(-1, -1, -1, -1));
     p->item_coef.assign(ni, make_double4(0, 0, 0, 0));
     std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-    for (int al = 0; al < p->na; ++al) {
-        const double sx = p->s[3 * al], sy = p->s[3 * al + 1];
+    for (int al = 0; al < p->na; ++al)
         for (int c = 0; c < nc; ++c) {
             const size_t i = (size_t)al * nc + c;
             const int at = pos[level[i]]++;
@@ -618,13 +602,12 @@ bte_status mesh_build(bte_mesh_problem *p, const bte_mesh *m, const bte_material
             int nu = 0;
             double aout = 0;
             for (int f = p->fptr[c]; f < p->fptr[c + 1]; ++f) {
-                const double *fg = &p->fgeo[(size_t)f * kFG];
-                const double sn = sx * fg[1] + sy * fg[2];
+                const double sn = sdotn(al, f), sv = p->fgeo[(size_t)f * kFG];
                 if (sn > 0) {
-                    aout += sn * fg[0];
+                    aout += sn * sv;
                 } else if (sn < 0 && p->fnb[f] >= 0 && !((lagm[i] >> (f - p->fptr[c])) & 1u)) {
                     upc[nu] = p->fnb[f];
-                    cof[nu] = -sn * fg[0];
+                    cof[nu] = -sn * sv;
                     ++nu;
                 }
             }
@@ -632,8 +615,193 @@ bte_status mesh_build(bte_mesh_problem *p, const bte_mesh *m, const bte_material
             p->item_up[at] = make_int4(upc[0], upc[1], upc[2], upc[3]);
             p->item_coef[at] = make_double4(cof[0], cof[1], cof[2], cof[3]);
         }
-    }
     return BTE_OK;
+}
+
+bte_status mesh_build(bte_mesh_problem *p, const bte_mesh *m, const bte_material *mat)
+{
+    const int nc = m->n_cells;
+    if (nc < 1 || m->n_vertices < 3 || !m->xy || !m->cell_ptr || !m->cell_vtx || !m->edge_tag)
+        MFAIL(p, BTE_ERR_ARG, "mesh: empty or null arrays");
+    if (m->cell_ptr[0] != 0) MFAIL(p, BTE_ERR_ARG, "mesh: cell_ptr[0] must be 0");
+    p->nc = nc;
+    p->dim = 2;
+    bte_status st = mesh_tags(p, m->n_tags, m->tag_bc, m->tag_T, mat);
+    if (st != BTE_OK) return st;
+    std::vector<double> V(nc), xc(3 * (size_t)nc, 0.0);
+    for (int c = 0; c < nc; ++c) {
+        const int a = m->cell_ptr[c], b = m->cell_ptr[c + 1], nv = b - a;
+        if (nv != 3 && nv != 4) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d has %d vertices (3 or 4)", c, nv);
+        double A = 0, cx = 0, cy = 0;
+        for (int k = 0; k < nv; ++k) {
+            const int i = m->cell_vtx[a + k], j = m->cell_vtx[a + (k + 1) % nv];
+            if (i < 0 || i >= m->n_vertices || j < 0 || j >= m->n_vertices)
+                MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: vertex index out of range", c);
+            const double x0 = m->xy[2 * i], y0 = m->xy[2 * i + 1], x1 = m->xy[2 * j], y1 = m->xy[2 * j + 1];
+            const double cr = x0 * y1 - x1 * y0;
+            A += cr;
+            cx += (x0 + x1) * cr;
+            cy += (y0 + y1) * cr;
+        }
+        A *= 0.5;
+        if (!(A > 0)) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d is not counter-clockwise with positive area", c);
+        V[c] = A;
+        xc[3 * c] = cx / (6.0 * A);
+        xc[3 * c + 1] = cy / (6.0 * A);
+    }
+    const int nf = m->cell_ptr[nc];
+    p->nf = nf;
+    std::map<std::pair<int, int>, std::vector<int>> owner;   // edge -> face slots
+    for (int c = 0; c < nc; ++c) {
+        const int a = m->cell_ptr[c], nv = m->cell_ptr[c + 1] - a;
+        for (int k = 0; k < nv; ++k) {
+            const int i = m->cell_vtx[a + k], j = m->cell_vtx[a + (k + 1) % nv];
+            owner[{std::min(i, j), std::max(i, j)}].push_back(a + k);
+        }
+    }
+    std::vector<int> slot_cell(nf);
+    for (int c = 0; c < nc; ++c)
+        for (int f = m->cell_ptr[c]; f < m->cell_ptr[c + 1]; ++f) slot_cell[f] = c;
+    p->fptr.assign(m->cell_ptr, m->cell_ptr + nc + 1);
+    p->fnb.assign(nf, -1);
+    p->ftag.assign(nf, -1);
+    p->frec.assign(nf, -1);
+    p->fgeo.assign((size_t)nf * kFG, 0.0);
+    for (auto &kv : owner) {
+        if (kv.second.size() > 2) MFAIL(p, BTE_ERR_ARG, "mesh: an edge is shared by more than two cells");
+        if (kv.second.size() == 2) {
+            p->fnb[kv.second[0]] = slot_cell[kv.second[1]];
+            p->fnb[kv.second[1]] = slot_cell[kv.second[0]];
+        }
+    }
+    for (int c = 0; c < nc; ++c) {
+        const int a = m->cell_ptr[c], nv = m->cell_ptr[c + 1] - a;
+        for (int k = 0; k < nv; ++k) {
+            const int f = a + k;
+            const int i = m->cell_vtx[f], j = m->cell_vtx[a + (k + 1) % nv];
+            const double dx = m->xy[2 * j] - m->xy[2 * i], dy = m->xy[2 * j + 1] - m->xy[2 * i + 1];
+            const double S = std::hypot(dx, dy);
+            if (!(S > 0)) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d has an edge of zero length", c);
+            const double nx = dy / S, ny = -dx / S;
+            const double xf = 0.5 * (m->xy[2 * i] + m->xy[2 * j]), yf = 0.5 * (m->xy[2 * i + 1] + m->xy[2 * j + 1]);
+            double *fg = &p->fgeo[(size_t)f * kFG];
+            fg[0] = S / V[c];
+            fg[1] = nx;
+            fg[2] = ny;
+            fg[4] = xf - xc[3 * c];
+            fg[5] = yf - xc[3 * c + 1];
+            const int nb = p->fnb[f], tag = m->edge_tag[f];
+            if (nb >= 0) {
+                if (tag >= 0) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: a shared edge carries a boundary tag", c);
+                fg[7] = xc[3 * nb] - xc[3 * c];
+                fg[8] = xc[3 * nb + 1] - xc[3 * c + 1];
+            } else {
+                if (tag < 0 || tag >= m->n_tags) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: boundary edge without a valid tag", c);
+                p->ftag[f] = tag;
+                if (p->tag_bc[tag] == BTE_BC_SPECULAR && std::min(std::fabs(nx), std::fabs(ny)) > 1e-12)
+                    MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: specular edge not parallel to x or y", c);
+            }
+        }
+    }
+    std::vector<int> cptr(m->cell_ptr, m->cell_ptr + nc + 1), cvtx(m->cell_vtx, m->cell_vtx + nf);
+    return mesh_finish(p, mat, m->gradient_stencil, xc, cptr, cvtx, m->n_vertices);
+}
+
+// Tetrahedra: face k of a cell is the triangle opposite its vertex k.
+bte_status mesh_build_tet(bte_mesh_problem *p, const bte_tet_mesh *m, const bte_material *mat)
+{
+    const int nc = m->n_cells;
+    if (nc < 1 || m->n_vertices < 4 || !m->xyz || !m->cell_vtx || !m->face_tag)
+        MFAIL(p, BTE_ERR_ARG, "mesh: empty or null arrays");
+    p->nc = nc;
+    p->dim = 3;
+    bte_status st = mesh_tags(p, m->n_tags, m->tag_bc, m->tag_T, mat);
+    if (st != BTE_OK) return st;
+    const double *X = m->xyz;
+    std::vector<double> V(nc), xc(3 * (size_t)nc);
+    for (int c = 0; c < nc; ++c) {
+        const int *t = m->cell_vtx + 4 * (size_t)c;
+        for (int k = 0; k < 4; ++k)
+            if (t[k] < 0 || t[k] >= m->n_vertices) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: vertex index out of range", c);
+        double e1[3], e2[3], e3[3];
+        for (int q = 0; q < 3; ++q) {
+            e1[q] = X[3 * t[1] + q] - X[3 * t[0] + q];
+            e2[q] = X[3 * t[2] + q] - X[3 * t[0] + q];
+            e3[q] = X[3 * t[3] + q] - X[3 * t[0] + q];
+            xc[3 * c + q] = 0.25 * (X[3 * t[0] + q] + X[3 * t[1] + q] + X[3 * t[2] + q] + X[3 * t[3] + q]);
+        }
+        const double det = e1[0] * (e2[1] * e3[2] - e2[2] * e3[1]) - e1[1] * (e2[0] * e3[2] - e2[2] * e3[0]) +
+                           e1[2] * (e2[0] * e3[1] - e2[1] * e3[0]);
+        V[c] = std::fabs(det) / 6.0;
+        if (!(V[c] > 0)) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d has zero volume", c);
+    }
+    const int nf = 4 * nc;
+    p->nf = nf;
+    std::map<std::array<int, 3>, std::vector<int>> owner;   // face -> face slots
+    auto face_key = [&](int c, int k) {
+        std::array<int, 3> f;
+        int q = 0;
+        for (int r = 0; r < 4; ++r)
+            if (r != k) f[q++] = m->cell_vtx[4 * (size_t)c + r];
+        std::sort(f.begin(), f.end());
+        return f;
+    };
+    for (int c = 0; c < nc; ++c)
+        for (int k = 0; k < 4; ++k) owner[face_key(c, k)].push_back(4 * c + k);
+    p->fptr.resize(nc + 1);
+    for (int c = 0; c <= nc; ++c) p->fptr[c] = 4 * c;
+    p->fnb.assign(nf, -1);
+    p->ftag.assign(nf, -1);
+    p->frec.assign(nf, -1);
+    p->fgeo.assign((size_t)nf * kFG, 0.0);
+    for (auto &kv : owner) {
+        if (kv.second.size() > 2) MFAIL(p, BTE_ERR_ARG, "mesh: a face is shared by more than two cells");
+        if (kv.second.size() == 2) {
+            p->fnb[kv.second[0]] = kv.second[1] / 4;
+            p->fnb[kv.second[1]] = kv.second[0] / 4;
+        }
+    }
+    for (int c = 0; c < nc; ++c)
+        for (int k = 0; k < 4; ++k) {
+            const int f = 4 * c + k;
+            int v3[3], q = 0;
+            for (int r = 0; r < 4; ++r)
+                if (r != k) v3[q++] = m->cell_vtx[4 * (size_t)c + r];
+            double a[3], b[3], xf[3];
+            for (int i = 0; i < 3; ++i) {
+                a[i] = X[3 * v3[1] + i] - X[3 * v3[0] + i];
+                b[i] = X[3 * v3[2] + i] - X[3 * v3[0] + i];
+                xf[i] = (X[3 * v3[0] + i] + X[3 * v3[1] + i] + X[3 * v3[2] + i]) / 3.0;
+            }
+            double n[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+            const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+            if (!(nn > 0)) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d has a face of zero area", c);
+            const int opp = m->cell_vtx[4 * (size_t)c + k];
+            double side = 0;
+            for (int i = 0; i < 3; ++i) side += n[i] * (xf[i] - X[3 * opp + i]);
+            const double sg = side < 0 ? -1.0 : 1.0;   // away from the opposite vertex
+            double *fg = &p->fgeo[(size_t)f * kFG];
+            fg[0] = 0.5 * nn / V[c];
+            for (int i = 0; i < 3; ++i) {
+                fg[1 + i] = sg * n[i] / nn;
+                fg[4 + i] = xf[i] - xc[3 * c + i];
+            }
+            const int nb = p->fnb[f], tag = m->face_tag[f];
+            if (nb >= 0) {
+                if (tag >= 0) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: a shared face carries a boundary tag", c);
+                for (int i = 0; i < 3; ++i) fg[7 + i] = xc[3 * nb + i] - xc[3 * c + i];
+            } else {
+                if (tag < 0 || tag >= m->n_tags) MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: boundary face without a valid tag", c);
+                p->ftag[f] = tag;
+                double an[3] = {std::fabs(fg[1]), std::fabs(fg[2]), std::fabs(fg[3])};
+                std::sort(an, an + 3);
+                if (p->tag_bc[tag] == BTE_BC_SPECULAR && an[1] > 1e-12)
+                    MFAIL(p, BTE_ERR_ARG, "mesh: cell %d: specular face not normal to x, y or z", c);
+            }
+        }
+    std::vector<int> cptr(nc + 1), cvtx(m->cell_vtx, m->cell_vtx + 4 * (size_t)nc);
+    for (int c = 0; c <= nc; ++c) cptr[c] = 4 * c;
+    return mesh_finish(p, mat, m->gradient_stencil, xc, cptr, cvtx, m->n_vertices);
 }
 
 template <typename T>
@@ -642,10 +810,19 @@ void mesh_iteration_rhs(bte_mesh_problem *p, const T *e, const double *TLdev, T 
     const MeshDev &d = p->dev;
     const int nkb = (p->nk + kBlock - 1) / kBlock;
     const dim3 grid((unsigned)((size_t)nkb * p->nc));
-    hipLaunchKernelGGL(k_mesh_grad<T>, grid, dim3(kBlock), 0, s, d, e, (T *)p->g, nkb);
-    if (p->nrec > 0)
-        hipLaunchKernelGGL(k_mesh_walls<T>, dim3(p->nrec), dim3(kBlock), 0, s, d, e, (const T *)p->g, p->din);
-    hipLaunchKernelGGL(k_mesh_residual<T>, grid, dim3(kBlock), 0, s, d, e, (const T *)p->g, p->din, TLdev, R, nkb);
+    if (p->dim == 3) {
+        hipLaunchKernelGGL((k_mesh_grad<T, 3>), grid, dim3(kBlock), 0, s, d, e, (T *)p->g, nkb);
+        if (p->nrec > 0)
+            hipLaunchKernelGGL((k_mesh_walls<T, 3>), dim3(p->nrec), dim3(kBlock), 0, s, d, e, (const T *)p->g, p->din);
+        hipLaunchKernelGGL((k_mesh_residual<T, 3>), grid, dim3(kBlock), 0, s, d, e, (const T *)p->g, p->din, TLdev,
+                           R, nkb);
+    } else {
+        hipLaunchKernelGGL((k_mesh_grad<T, 2>), grid, dim3(kBlock), 0, s, d, e, (T *)p->g, nkb);
+        if (p->nrec > 0)
+            hipLaunchKernelGGL((k_mesh_walls<T, 2>), dim3(p->nrec), dim3(kBlock), 0, s, d, e, (const T *)p->g, p->din);
+        hipLaunchKernelGGL((k_mesh_residual<T, 2>), grid, dim3(kBlock), 0, s, d, e, (const T *)p->g, p->din, TLdev,
+                           R, nkb);
+    }
 }
 
 template <typename T>
@@ -727,6 +904,25 @@ bte_status bte_mesh_setup(const bte_mesh *mesh, const bte_material *mat, const b
     return mesh_build(p, mesh, mat);
 }
 
+bte_status bte_mesh_setup_tet(const bte_tet_mesh *mesh, const bte_material *mat, const bte_control *ctl,
+                              bte_mesh_problem **out)
+{
+    if (!out) return BTE_ERR_ARG;
+    *out = nullptr;
+    bte_mesh_problem *p = new (std::nothrow) bte_mesh_problem();
+    if (!p) return BTE_ERR_ARG;
+    *out = p;
+    if (!mesh || !mat || !ctl) MFAIL(p, BTE_ERR_ARG, "null argument");
+    p->ctl = *ctl;
+    if (ctl->precision != BTE_F32 && ctl->precision != BTE_F64) MFAIL(p, BTE_ERR_ARG, "bad precision");
+    if (ctl->scheme != BTE_SEQUENTIAL) MFAIL(p, BTE_ERR_UNSUPPORTED, "meshes run the sequential scheme");
+    if (ctl->limiter != BTE_LIM_NONE) MFAIL(p, BTE_ERR_UNSUPPORTED, "meshes take the unlimited gradient");
+    if (mat->material_dim == 2) MFAIL(p, BTE_ERR_UNSUPPORTED, "meshes take bulk materials");
+    if (mat->n_bands < 1 || mat->n_bands > kBlock || !mat->C || !mat->v || !mat->tau)
+        MFAIL(p, BTE_ERR_ARG, "n_bands must be 1 .. %d with C, v, tau given", kBlock);
+    return mesh_build_tet(p, mesh, mat);
+}
+
 size_t bte_mesh_workspace_bytes(const bte_mesh_problem *p)
 {
     if (!p || p->nc == 0) return 0;
@@ -753,7 +949,7 @@ size_t bte_mesh_workspace_bytes(const bte_mesh_problem *p)
     add(8 * p->item_out.size());
     add(sizeof(int4) * p->item_up.size());
     add(sizeof(double4) * p->item_coef.size());
-    add(2 * p->esize() * p->nelem());   // gradients
+    add((size_t)p->dim * p->esize() * p->nelem());   // gradients
     add(p->esize() * p->nelem());       // residual / increments
     add(8 * ((size_t)p->nrec * p->nl + 1));
     add(8 * 5 * (size_t)p->nc + 16);    // Tdev, Tprev, TLdev, P, eps
@@ -822,7 +1018,7 @@ bte_status bte_mesh_bind(bte_mesh_problem *p, void *ws_dev, size_t bytes)
     }
     d.Ctot = p->Ctot;
     d.Ssum = p->Ssum;
-    p->g = take(2 * p->esize() * p->nelem());
+    p->g = take((size_t)p->dim * p->esize() * p->nelem());
     p->b = take(p->esize() * p->nelem());
     p->din = (double *)take(8 * ((size_t)p->nrec * p->nl + 1));
     x = take(8 * 5 * (size_t)p->nc + 16);

@@ -376,3 +376,36 @@ def test_mesh_setup_validates(lib, what):
     assert st == want, (what, st, lib.bte_mesh_last_error(h))
     assert len(lib.bte_mesh_last_error(h)) > 0
     lib.bte_mesh_destroy(h)
+
+
+def test_tet_mesh_levels_and_lagging_match_the_oracle(lib):
+    """Tetrahedral schedule: levels and lagged couplings (3D upwind graphs
+    may have cycles) as the oracle's rule gives them."""
+    from paper_2306_14181_amd import bte
+    from oracle import mesh as M
+    mesh = I.mesh3d(2, 4, 4, 3, 4e-7, 4e-7, 3e-7, jitter=0.15)
+    ms, keep = bte.mesh_struct(mesh)
+    bands = [np.ascontiguousarray(MESH_MAT[k], dtype=np.float64) for k in ("C", "v", "tau")]
+    mm = bte.Material()
+    mm.n_bands = 3
+    mm.C, mm.v, mm.tau = [b.ctypes.data_as(C.POINTER(C.c_double)) for b in bands]
+    mm.n_theta, mm.n_phi, mm.T_ref, mm.material_dim = 2, 2, 300.0, 3
+    c = bte._control_struct(dict(scheme=0, limiter=0))
+    h = C.c_void_p()
+    st = lib.bte_mesh_setup_tet(C.byref(ms), C.byref(mm), C.byref(c), C.byref(h))
+    assert st == 0, lib.bte_mesh_last_error(h)
+    mc = M.TetMeshCase(mesh, MESH_MAT)
+    depth, nlag = 0, 0
+    for al in range(mc.na):
+        order, lagged = M.upwind_order(mc, al)
+        nlag += len(lagged)
+        lev = {}
+        for cc in order:
+            ups = [nb for nb, _, _, n, _ in mc.faces[cc]
+                   if nb >= 0 and mc.s[al] @ n < 0 and (cc, nb) not in lagged]
+            lev[cc] = 1 + max((lev[j] for j in ups), default=-1)
+        depth = max(depth, max(lev.values()))
+    assert lib.bte_mesh_num_levels(h) == depth + 1
+    assert lib.bte_mesh_num_lagged(h) == nlag
+    assert lib.bte_mesh_num_cells(h) == mc.nc and lib.bte_mesh_num_directions(h) == mc.na
+    lib.bte_mesh_destroy(h)

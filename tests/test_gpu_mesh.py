@@ -166,3 +166,85 @@ def test_mesh_transient_refuses_unstable_steps(B):
     with pytest.raises(B.BteError) as ex:
         prob.transient_step(prob.zeros(), 1)
     assert ex.value.status == B.BTE_ERR_CFL
+
+
+# ---------------------------------------------------------------- tetrahedra
+
+TET_CASES = {
+    # thermalizing x walls, specular y, diffuse z, heat source
+    "tet": dict(seed=21, n=(5, 4, 3), bc=(I.BC_THERMAL, I.BC_THERMAL, I.BC_SPECULAR, I.BC_SPECULAR,
+                                          I.BC_DIFFUSE, I.BC_DIFFUSE), src=True),
+    "tet_face": dict(seed=22, n=(4, 4, 3), bc=(I.BC_THERMAL, I.BC_DIFFUSE) + (I.BC_SPECULAR,) * 4, src=False,
+                     stencil=1),
+    "tet_pore": dict(seed=23, n=(5, 4, 4), bc=(I.BC_THERMAL,) * 6, src=False,
+                     pores=[(2.5e-7, 2e-7, 2e-7, 0.9e-7)]),
+    "tet_tt": dict(seed=24, n=(3, 3, 3), bc=(I.BC_THERMAL,) * 6, src=True),
+}
+
+
+def build_tet(B, name, prec, mat=MAT, **ctl):
+    cf = TET_CASES[name]
+    L = [x * 1e-7 for x in cf["n"]]
+    mesh = I.mesh3d(cf["seed"], *cf["n"], *L, jitter=0.15, bc=cf["bc"],
+                    bcT=(301.0, 299.0, 300.5, 299.5, 300.2, 299.8), gradient_stencil=cf.get("stencil", 0),
+                    pores=cf.get("pores", ()))
+    nc = len(mesh["cell_vtx"])
+    P = np.random.default_rng(cf["seed"]).uniform(0, 2e16, nc) if cf["src"] else None
+    case = M.TetMeshCase(mesh, mat, P=P)
+    control = dict(precision=prec)
+    control.update(ctl)
+    prob = B.MeshProblem(mesh, mat, control)
+    if P is not None:
+        prob.set_source(P)
+    return case, prob
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("name", ["tet", "tet_face", "tet_pore"])
+def test_tet_residual_and_moments(B, name, prec):
+    case, prob = build_tet(B, name, prec)
+    eg = to_dev(prob, seeded(case, 1))
+    e = host(eg)
+    TL = np.random.default_rng(2).uniform(-1, 1, case.nc)
+    err = rel_err(host(prob.residual(eg, TL)), M.residual(case, e, TL))
+    print(name, prec, err, prob.n_levels, prob.n_lagged)
+    assert err < (1e-11 if prec == 1 else 1e-5), err
+    T, TLd, q = prob.moments(eg)
+    To, TLo, qo = M.moments(case, e)
+    assert rel_err(host(T), To, case.Tref) < 1e-12 and rel_err(host(q), qo.reshape(-1)) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("name", ["tet", "tet_pore"])
+def test_tet_source_iterations(B, name, prec):
+    case, prob = build_tet(B, name, prec, max_iter=3, residual_temp=0.0)
+    eg = to_dev(prob, seeded(case, 4))
+    e = host(eg)
+    st = prob.steady_solve(eg, init=False, allow_not_converged=True)
+    assert st["iters"] == 3
+    for _ in range(3):
+        e = M.sweep(case, e, M.moments(case, e)[1] - case.Tref)
+    err = rel_err(host(eg), e)
+    print(name, prec, err)
+    assert err < (1e-11 if prec == 1 else 1e-5), err
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_tet_converged_and_transient(B, prec):
+    tol = 1e-12 if prec == 1 else 1e-6
+    case, prob = build_tet(B, "tet_tt", prec, mat=MAT_BALLISTIC, max_iter=500, residual_temp=tol, dt=2e-13)
+    eg = prob.zeros()
+    st = prob.steady_solve(eg, init=True)
+    assert st["converged"]
+    eo, sto = M.steady(case, tol_T=1e-13, max_iter=500)
+    T, _, q = prob.moments(eg)
+    To, _, qo = M.moments(case, eo)
+    bar = 1e-10 if prec == 1 else 1e-5
+    errs = (rel_err(host(T), To, case.Tref), rel_err(host(q), qo.reshape(-1)))
+    print(prec, errs, st["iters"], sto["iters"])
+    assert max(errs) < bar, errs
+    eg2 = to_dev(prob, seeded(case, 6))
+    e2 = host(eg2)
+    prob.transient_step(eg2, 5)
+    err = rel_err(host(eg2), M.transient(case, e2, 5, 2e-13))
+    assert err < (1e-11 if prec == 1 else 1e-5), err
