@@ -420,30 +420,23 @@ def mesh3d(seed, nx, ny, nz, lx, ly, lz, jitter=0.15,
             return any(((m - np.array(pc[:3])) ** 2).sum() < pc[3] ** 2 for pc in pores)
         cells = [c for c in cells if not inside(c)]
     cells = np.array(cells, dtype=np.int32)
-    for c in cells:
-        a, b, cc, dd = xyz[c]
-        if np.linalg.det(np.stack([b - a, cc - a, dd - a])) == 0:
-            raise ValueError("degenerate tetrahedron: lower the jitter")
+    P = xyz[cells]
+    if (np.linalg.det(P[:, 1:] - P[:, :1]) == 0).any():
+        raise ValueError("degenerate tetrahedron: lower the jitter")
     ijk = np.stack(np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij"),
                    axis=-1).reshape(-1, 3)
     top = np.array([nx, ny, nz])
-    count = {}
-    for c in cells:
-        for q in range(4):
-            key = tuple(sorted(np.delete(c, q)))
-            count[key] = count.get(key, 0) + 1
+    # faces: vertices other than vertex q, for every cell and q
+    others = np.array([[r for r in range(4) if r != q] for q in range(4)])
+    F = cells[:, others]                                     # [nc, 4, 3]
+    keys = np.sort(F, axis=2).reshape(-1, 3)
+    _, inv, cnt = np.unique(keys, axis=0, return_inverse=True, return_counts=True)
+    once = (cnt[inv.reshape(-1)] == 1).reshape(len(cells), 4)
     tag = np.full((len(cells), 4), -1, dtype=np.int32)
-    for ci, c in enumerate(cells):
-        for q in range(4):
-            f = np.delete(c, q)
-            t = -1
-            for ax in range(3):
-                if (ijk[f, ax] == 0).all():
-                    t = 2 * ax
-                elif (ijk[f, ax] == top[ax]).all():
-                    t = 2 * ax + 1
-            if t < 0 and count[tuple(sorted(f))] == 1:
-                t = 6
-            tag[ci, q] = t
+    G = ijk[F]                                               # [nc, 4, 3 vertices, 3 axes]
+    for ax in range(3):
+        tag[(G[..., ax] == 0).all(axis=2)] = 2 * ax
+        tag[(G[..., ax] == top[ax]).all(axis=2)] = 2 * ax + 1
+    tag[(tag < 0) & once] = 6
     return dict(xyz=xyz, cell_vtx=cells, face_tag=tag, tag_bc=np.asarray(list(bc) + [pore_bc], dtype=np.int32),
                 tag_T=np.asarray(list(bcT) + [300.0], dtype=np.float64), gradient_stencil=int(gradient_stencil))
