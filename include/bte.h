@@ -457,7 +457,8 @@ const char *bte_last_error(const bte_problem *p);
 void bte_destroy(bte_problem *p);
 
 /* ------------------------------------------------------------------------
- * Unstructured two-dimensional meshes of triangles and quadrilaterals
+ * Unstructured meshes: two-dimensional meshes of triangles and
+ * quadrilaterals (bte_mesh_setup), tetrahedral meshes (bte_mesh_setup_tet)
  * (Sec. 3.3, eq. disretized_BTE, with the least-squares gradient and the
  * first-order upwind stiffness matrix of Sec. 3.5), steady (sequential
  * scheme, Sec. 3.4) and explicit transient steps (Sec. 4.1), bulk
