@@ -705,7 +705,7 @@ def main():
                     help="2D sweeps with one launch per tile diagonal instead of one launch per sweep")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU sharding is not implemented",
+        print("bench.py: runs on one GPU only (--gpus 1); multi-GPU sharding is not implemented",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
