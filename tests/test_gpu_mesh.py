@@ -248,3 +248,36 @@ def test_tet_converged_and_transient(B, prec):
     prob.transient_step(eg2, 5)
     err = rel_err(host(eg2), M.transient(case, e2, 5, 2e-13))
     assert err < (1e-11 if prec == 1 else 1e-5), err
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("kind", ["triangle", "tetrahedron"])
+def test_single_cell_meshes(B, kind, prec):
+    """Degenerate meshes of one cell (no neighbours: the least-squares fit
+    is empty and the gradient zero; every face a wall): residual, three
+    source iterations and explicit steps against the oracle."""
+    if kind == "triangle":
+        mesh = dict(xy=np.array([[0.0, 0.0], [1e-7, 0.0], [0.3e-7, 0.8e-7]]), cell_ptr=np.array([0, 3]),
+                    cell_vtx=np.array([0, 1, 2]), edge_tag=np.array([0, 1, 2]),
+                    tag_bc=np.array([I.BC_THERMAL, I.BC_DIFFUSE, I.BC_THERMAL]), tag_T=np.array([301.0, 300.0, 299.0]))
+        case = M.MeshCase(mesh, MAT)
+    else:
+        mesh = dict(xyz=np.array([[0.0, 0.0, 0.0], [1e-7, 0.0, 0.0], [0.0, 1e-7, 0.0], [0.0, 0.0, 1e-7]]),
+                    cell_vtx=np.array([[0, 1, 2, 3]]), face_tag=np.array([[0, 1, 2, 3]]),
+                    tag_bc=np.array([I.BC_DIFFUSE, I.BC_THERMAL, I.BC_SPECULAR, I.BC_THERMAL]),
+                    tag_T=np.array([300.0, 301.0, 300.0, 299.0]))
+        case = M.TetMeshCase(mesh, MAT)
+    prob = B.MeshProblem(mesh, MAT, dict(precision=prec, max_iter=3, residual_temp=0.0, dt=1e-13))
+    assert prob.n_cells == 1 and prob.n_levels == 1
+    eg = to_dev(prob, seeded(case, 7))
+    e = host(eg)
+    bar = 1e-11 if prec == 1 else 1e-5
+    assert rel_err(host(prob.residual(eg)), M.residual(case, e)) < bar
+    prob.steady_solve(eg, init=False, allow_not_converged=True)
+    eo = e
+    for _ in range(3):
+        eo = M.sweep(case, eo, M.moments(case, eo)[1] - case.Tref)
+    assert rel_err(host(eg), eo) < bar
+    e2 = host(eg)
+    prob.transient_step(eg, 4)
+    assert rel_err(host(eg), M.transient(case, e2, 4, 1e-13)) < bar
