@@ -51,6 +51,7 @@ struct MeshDev {
     const double *xinv;    // [nc][6] symmetric X^+: 00, 01, 02, 11, 12, 22
     const int *lsptr;      // [nc + 1] least-squares stencil of each cell
     const int *lsnb;       // [nls] stencil cells
+    const int *vorder;     // [nc] cell visited by the i-th block group
     const double *lsd;     // [nls][3] offsets x_j - x_i
     const int *tag_bc;     // [ntag]
     const double *tag_dT;  // [ntag] wall temperature - T_ref
@@ -75,16 +76,52 @@ struct MeshDev {
 template <typename T, int D>
 __global__ __launch_bounds__(kBlock) void k_mesh_grad(MeshDev d, const T *__restrict__ e, T *__restrict__ g, int nkb)
 {
-    // block = (cell, block of 256 lanes)
-    const int c = blockIdx.x / nkb;
-    const int k = (blockIdx.x - c * nkb) * kBlock + threadIdx.x;
+    // block = (cell, block of 256 lanes); cells in the Morton visit order
+    const int i = blockIdx.x / nkb;
+    const int c = d.vorder[i];
+    const int k = (blockIdx.x - i * nkb) * kBlock + threadIdx.x;
     if (k >= d.nk) return;
     const double ec = (double)e[(size_t)c * d.nk + k];
     double y[3] = {0.0, 0.0, 0.0};
-    for (int j = d.lsptr[c]; j < d.lsptr[c + 1]; ++j) {
-        const double diff = (double)e[(size_t)d.lsnb[j] * d.nk + k] - ec;
+    // stencil rows eight, then four at a time in flight (the loads do not
+    // wait on each other's sums), summed in stencil order; the row indices
+    // and offsets are read through pointers that step by whole groups, so
+    // that each group costs one scalar address computation
+    const int j0 = d.lsptr[c];
+    int n = d.lsptr[c + 1] - j0;
+    const int *nbp = d.lsnb + j0;
+    const double *ldp = d.lsd + 3 * (size_t)j0;
+    const T *ek = e + k;
+    const size_t nk = (size_t)d.nk;
+    for (; n >= 8; n -= 8, nbp += 8, ldp += 24) {
+        T v[8];
 #pragma unroll
-        for (int q = 0; q < D; ++q) y[q] += d.lsd[3 * j + q] * diff;
+        for (int u = 0; u < 8; ++u) v[u] = ek[(size_t)nbp[u] * nk];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double diff = (double)v[u] - ec;
+#pragma unroll
+            for (int q = 0; q < D; ++q) y[q] += ldp[3 * u + q] * diff;
+        }
+    }
+    if (n >= 4) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = ek[(size_t)nbp[u] * nk];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double diff = (double)v[u] - ec;
+#pragma unroll
+            for (int q = 0; q < D; ++q) y[q] += ldp[3 * u + q] * diff;
+        }
+        n -= 4;
+        nbp += 4;
+        ldp += 12;
+    }
+    for (; n > 0; --n, ++nbp, ldp += 3) {
+        const double diff = (double)ek[(size_t)*nbp * nk] - ec;
+#pragma unroll
+        for (int q = 0; q < D; ++q) y[q] += ldp[q] * diff;
     }
     const double *xi = d.xinv + 6 * (size_t)c;
     const double gx = xi[0] * y[0] + xi[1] * y[1] + xi[2] * y[2];
@@ -140,8 +177,9 @@ __global__ __launch_bounds__(kBlock) void k_mesh_residual(MeshDev d, const T *__
                                                           const double *__restrict__ TLdev, T *__restrict__ R,
                                                           int nkb)
 {
-    const int c = blockIdx.x / nkb;
-    const int k = (blockIdx.x - c * nkb) * kBlock + threadIdx.x;
+    const int i = blockIdx.x / nkb;
+    const int c = d.vorder[i];
+    const int k = (blockIdx.x - i * nkb) * kBlock + threadIdx.x;
     if (k >= d.nk) return;
     const int al = k / d.nl, l = k - al * d.nl;
     const double sx = d.s[3 * al], sy = d.s[3 * al + 1], sz = d.s[3 * al + 2];
@@ -149,26 +187,29 @@ __global__ __launch_bounds__(kBlock) void k_mesh_residual(MeshDev d, const T *__
     for (int f = d.fptr[c]; f < d.fptr[c + 1]; ++f) {
         const double *fg = d.fgeo + (size_t)f * kFG;
         const double sn = sx * fg[1] + sy * fg[2] + sz * fg[3];
+        const int nb = d.fnb[f];
         double ef;
-        if (sn > 0.0) {
+        if (nb >= 0) {
+            // interior face: the upwind cell per lane, so that the lanes of
+            // a wave issue one set of loads whichever side is upwind (a lane
+            // with s.n = 0 adds zero)
+            const bool own = sn > 0.0;
+            ef = face_out<T, D>(d, e, g, own ? c : nb, k, own ? fg[4] : fg[4] - fg[7], own ? fg[5] : fg[5] - fg[8],
+                                own ? fg[6] : fg[6] - fg[9]);
+        } else if (sn > 0.0) {
             ef = face_out<T, D>(d, e, g, c, k, fg[4], fg[5], fg[6]);
         } else if (sn < 0.0) {
-            const int nb = d.fnb[f];
-            if (nb >= 0) {
-                ef = face_out<T, D>(d, e, g, nb, k, fg[4] - fg[7], fg[5] - fg[8], fg[6] - fg[9]);
+            const int tag = d.ftag[f];
+            const int kind = d.tag_bc[tag];
+            if (kind == BTE_BC_THERMAL) {
+                ef = d.C4[l] * d.tag_dT[tag];
+            } else if (kind == BTE_BC_SPECULAR) {
+                // the wall's normal axis (the face is normal to x, y or z)
+                const int axis = fabs(fg[1]) > 0.5 ? 0 : (fabs(fg[2]) > 0.5 ? 1 : 2);
+                const int km = d.mirror[axis * d.na + al] * d.nl + l;
+                ef = face_out<T, D>(d, e, g, c, km, fg[4], fg[5], fg[6]);
             } else {
-                const int tag = d.ftag[f];
-                const int kind = d.tag_bc[tag];
-                if (kind == BTE_BC_THERMAL) {
-                    ef = d.C4[l] * d.tag_dT[tag];
-                } else if (kind == BTE_BC_SPECULAR) {
-                    // the wall's normal axis (the face is normal to x, y or z)
-                    const int axis = fabs(fg[1]) > 0.5 ? 0 : (fabs(fg[2]) > 0.5 ? 1 : 2);
-                    const int km = d.mirror[axis * d.na + al] * d.nl + l;
-                    ef = face_out<T, D>(d, e, g, c, km, fg[4], fg[5], fg[6]);
-                } else {
-                    ef = din[(size_t)d.frec[f] * d.nl + l];
-                }
+                ef = din[(size_t)d.frec[f] * d.nl + l];
             }
         } else {
             continue;
@@ -291,7 +332,7 @@ struct bte_mesh_problem {
     int nc = 0, na = 0, nl = 0, nk = 0, nf = 0, nrec = 0, ntag = 0, nlev = 0, nlag = 0, dim = 2;
     double Tref = 0;
     // host tables
-    std::vector<int> fptr, fnb, ftag, frec, tag_bc, mirror, rec_cell, rec_face, lev_off, lsptr, lsnb;
+    std::vector<int> fptr, fnb, ftag, frec, tag_bc, mirror, rec_cell, rec_face, lev_off, lsptr, lsnb, vorder;
     std::vector<int> item_c, item_al;
     std::vector<int4> item_up;
     std::vector<double4> item_coef;
@@ -420,6 +461,40 @@ bte_status mesh_tags(bte_mesh_problem *p, int n_tags, const int *tag_bc, const d
     return BTE_OK;
 }
 
+// Cells sorted by the Morton (Z-order) code of their centroids, quantised to
+// 2^10 steps per axis of the bounding box: consecutive blocks of the
+// gradient and residual launches then read the rows of nearby cells, which
+// the previous blocks have just brought into the L2 cache (the stored cell
+// numbering may follow one axis, putting a neighbour across the slowest axis
+// a whole layer of cells away).  Ties keep the stored order.
+static void morton_order(const std::vector<double> &xc, int nc, int D, std::vector<int> &order)
+{
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int q = 0; q < D; ++q) {
+        lo[q] = hi[q] = nc > 0 ? xc[q] : 0.0;
+        for (int c = 1; c < nc; ++c) {
+            lo[q] = std::min(lo[q], xc[3 * (size_t)c + q]);
+            hi[q] = std::max(hi[q], xc[3 * (size_t)c + q]);
+        }
+    }
+    std::vector<unsigned long long> key(nc);
+    for (int c = 0; c < nc; ++c) {
+        unsigned long long code = 0;
+        unsigned u[3] = {0, 0, 0};
+        for (int q = 0; q < D; ++q) {
+            const double span = hi[q] - lo[q];
+            const double t = span > 0.0 ? (xc[3 * (size_t)c + q] - lo[q]) / span : 0.0;
+            u[q] = (unsigned)std::min(1023.0, std::max(0.0, std::floor(t * 1024.0)));
+        }
+        for (int b = 9; b >= 0; --b)
+            for (int q = 0; q < D; ++q) code = (code << 1) | ((u[q] >> b) & 1u);
+        key[c] = code;
+    }
+    order.resize(nc);
+    for (int c = 0; c < nc; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+}
+
 // Everything after the cells' geometry: least-squares stencils and
 // matrices, directions, bands, diffuse-wall records and the sweep schedule.
 // V, xc (3 per cell), the face slots in p, and the vertices of each cell
@@ -463,6 +538,7 @@ bte_status mesh_finish(bte_mesh_problem *p, const bte_material *mat, int stencil
         if (D == 2) pinv2(X[0][0], X[0][1], X[1][1], &p->xinv[6 * (size_t)c]);
         else pinv3(X, &p->xinv[6 * (size_t)c]);
     }
+    morton_order(xc, nc, D, p->vorder);
     // directions (bulk material: on the sphere, 4 pi)
     if (mat->n_theta < 1 || mat->n_phi < 1) MFAIL(p, BTE_ERR_ARG, "n_theta and n_phi must be >= 1");
     sphere_directions(mat->n_theta, mat->n_phi, 4.0 * M_PI, p->s, p->w);
@@ -934,6 +1010,7 @@ size_t bte_mesh_workspace_bytes(const bte_mesh_problem *p)
     add(8 * p->xinv.size());
     add(4 * p->lsptr.size());
     add(4 * p->lsnb.size() + 4);
+    add(4 * p->vorder.size());
     add(8 * p->lsd.size() + 8);
     add(4 * p->tag_bc.size() + 8);
     add(8 * p->tag_dT.size() + 8);
@@ -989,6 +1066,7 @@ bte_status bte_mesh_bind(bte_mesh_problem *p, void *ws_dev, size_t bytes)
     x = take(8 * p->xinv.size()); MHIP(p, up(p->xinv.data(), 8 * p->xinv.size(), x)); d.xinv = (const double *)x;
     x = take(4 * p->lsptr.size()); MHIP(p, up(p->lsptr.data(), 4 * p->lsptr.size(), x)); d.lsptr = (const int *)x;
     x = take(4 * p->lsnb.size() + 4); MHIP(p, up(p->lsnb.data(), 4 * p->lsnb.size(), x)); d.lsnb = (const int *)x;
+    x = take(4 * p->vorder.size()); MHIP(p, up(p->vorder.data(), 4 * p->vorder.size(), x)); d.vorder = (const int *)x;
     x = take(8 * p->lsd.size() + 8); MHIP(p, up(p->lsd.data(), 8 * p->lsd.size(), x)); d.lsd = (const double *)x;
     x = take(4 * p->tag_bc.size() + 8); MHIP(p, up(p->tag_bc.data(), 4 * p->tag_bc.size(), x)); d.tag_bc = (const int *)x;
     x = take(8 * p->tag_dT.size() + 8); MHIP(p, up(p->tag_dT.data(), 8 * p->tag_dT.size(), x)); d.tag_dT = (const double *)x;
