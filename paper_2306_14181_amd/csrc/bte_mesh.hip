@@ -184,7 +184,40 @@ __global__ __launch_bounds__(kBlock) void k_mesh_residual(MeshDev d, const T *__
     const int al = k / d.nl, l = k - al * d.nl;
     const double sx = d.s[3 * al], sy = d.s[3 * al + 1], sz = d.s[3 * al + 2];
     double acc = 0.0;
-    for (int f = d.fptr[c]; f < d.fptr[c + 1]; ++f) {
+    const int f0 = d.fptr[c], f1 = d.fptr[c + 1];
+    int nbv[4] = {-1, -1, -1, -1};
+    bool inner = f1 - f0 == 4;
+    if (inner) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) nbv[u] = d.fnb[f0 + u];
+        inner = nbv[0] >= 0 && nbv[1] >= 0 && nbv[2] >= 0 && nbv[3] >= 0;
+    }
+    if (inner) {
+        // four interior faces (the common cell): every face's loads are
+        // issued before the sums, which run in face order
+        double sn[4], ev[4], gv[4][3], lo[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double *fg = d.fgeo + (size_t)(f0 + u) * kFG;
+            sn[u] = sx * fg[1] + sy * fg[2] + sz * fg[3];
+            const bool own = sn[u] > 0.0;
+            const int src = own ? c : nbv[u];
+            // offset of the face centre from the upwind cell's centre
+            const double m = own ? 0.0 : 1.0;
+#pragma unroll
+            for (int q = 0; q < D; ++q) lo[u][q] = fg[4 + q] - m * fg[7 + q];
+            ev[u] = (double)e[(size_t)src * d.nk + k];
+#pragma unroll
+            for (int q = 0; q < D; ++q) gv[u][q] = (double)g[((size_t)src * D + q) * d.nk + k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double ef = ev[u] + gv[u][0] * lo[u][0] + gv[u][1] * lo[u][1];
+            if constexpr (D == 3) ef += gv[u][2] * lo[u][2];
+            acc += sn[u] * d.fgeo[(size_t)(f0 + u) * kFG] * ef;
+        }
+    }
+    for (int f = inner ? f1 : f0; f < f1; ++f) {
         const double *fg = d.fgeo + (size_t)f * kFG;
         const double sn = sx * fg[1] + sy * fg[2] + sz * fg[3];
         const int nb = d.fnb[f];
