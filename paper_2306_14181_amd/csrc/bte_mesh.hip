@@ -270,15 +270,23 @@ __global__ __launch_bounds__(kBlock) void k_mesh_sweep_level(MeshDev d, T *__res
     const int k = d.item_al[i] * d.nl + l;
     const int4 up = d.item_up[i];
     const double4 cf = d.item_coef[i];
-    const double vl = d.v[l];
-    double num = (double)b[(size_t)c * d.nk + k];
-    if (up.x >= 0) num += vl * cf.x * (double)b[(size_t)up.x * d.nk + k];
-    if (up.y >= 0) num += vl * cf.y * (double)b[(size_t)up.y * d.nk + k];
-    if (up.z >= 0) num += vl * cf.z * (double)b[(size_t)up.z * d.nk + k];
-    if (up.w >= 0) num += vl * cf.w * (double)b[(size_t)up.w * d.nk + k];
-    const double de = num / (d.itau[l] + vl * d.item_out[i]);
-    b[(size_t)c * d.nk + k] = (T)de;
-    e[(size_t)c * d.nk + k] = (T)((double)e[(size_t)c * d.nk + k] + de);
+    const double vl = d.v[l], den = d.itau[l] + vl * d.item_out[i];
+    const size_t nk = (size_t)d.nk, ck = (size_t)c * nk + k;
+    // an absent coupling (-1) reads the item's own slot with weight zero, so
+    // that every load of the item issues at once, without branches
+    const T b0 = b[ck], e0 = e[ck];
+    const T bx = b[(size_t)(up.x >= 0 ? up.x : c) * nk + k];
+    const T by = b[(size_t)(up.y >= 0 ? up.y : c) * nk + k];
+    const T bz = b[(size_t)(up.z >= 0 ? up.z : c) * nk + k];
+    const T bw = b[(size_t)(up.w >= 0 ? up.w : c) * nk + k];
+    double num = (double)b0;
+    num += (up.x >= 0 ? vl * cf.x : 0.0) * (double)bx;
+    num += (up.y >= 0 ? vl * cf.y : 0.0) * (double)by;
+    num += (up.z >= 0 ? vl * cf.z : 0.0) * (double)bz;
+    num += (up.w >= 0 ? vl * cf.w : 0.0) * (double)bw;
+    const double de = num / den;
+    b[ck] = (T)de;
+    e[ck] = (T)((double)e0 + de);
 }
 
 // Moments per cell (one block per cell): T - T_ref, T_L - T_ref and q.
