@@ -289,37 +289,54 @@ __global__ __launch_bounds__(kBlock) void k_mesh_sweep_level(MeshDev d, T *__res
     e[ck] = (T)((double)e0 + de);
 }
 
-// Moments per cell (one block per cell): T - T_ref, T_L - T_ref and q.
+// Moments per cell: T - T_ref, T_L - T_ref and q.  A block takes
+// kMomCells cells, so that each lane's direction and band weights serve all
+// of them; wave sums by shuffles, then one pass over the block's waves.
+constexpr int kMomCells = 4;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mesh_moments(MeshDev d, const T *__restrict__ e, double *__restrict__ Tdev,
                                                          double *__restrict__ TLdev, double *__restrict__ q)
 {
-    __shared__ double sh[5][kBlock];
-    const int c = blockIdx.x;
-    double a[5] = {0, 0, 0, 0, 0};
+    __shared__ double sh[kBlock / 64][kMomCells][5];
+    const int c0 = blockIdx.x * kMomCells;
+    double a[kMomCells][5] = {};
     for (int k = threadIdx.x; k < d.nk; k += kBlock) {
         const int al = k / d.nl, l = k - al * d.nl;
-        const double x = d.w[al] * (double)e[(size_t)c * d.nk + k];
-        a[0] += x;
-        a[1] += x * d.itau[l];
-        a[2] += x * d.v[l] * d.s[3 * al];
-        a[3] += x * d.v[l] * d.s[3 * al + 1];
-        a[4] += x * d.v[l] * d.s[3 * al + 2];
+        const double w = d.w[al], wv = w * d.v[l];
+        const double cw[5] = {w, w * d.itau[l], wv * d.s[3 * al], wv * d.s[3 * al + 1], wv * d.s[3 * al + 2]};
+        T ev[kMomCells];
+        // past the last cell the loads repeat it and the sums are dropped
+#pragma unroll
+        for (int m = 0; m < kMomCells; ++m) ev[m] = e[(size_t)min(c0 + m, d.nc - 1) * d.nk + k];
+#pragma unroll
+        for (int m = 0; m < kMomCells; ++m)
+#pragma unroll
+            for (int j = 0; j < 5; ++j) a[m][j] += cw[j] * (double)ev[m];
     }
-    for (int m = 0; m < 5; ++m) sh[m][threadIdx.x] = a[m];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int m = 0; m < kMomCells; ++m)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            double x = a[m][j];
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+            if (lane == 0) sh[wv][m][j] = x;
+        }
     __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off)
-            for (int m = 0; m < 5; ++m) sh[m][threadIdx.x] += sh[m][threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        if (Tdev) Tdev[c] = sh[0][0] / d.Ctot;
-        if (TLdev) TLdev[c] = sh[1][0] / d.Ssum;
-        if (q)
-            for (int m = 0; m < 3; ++m) q[3 * c + m] = sh[2 + m][0];
+    if ((int)threadIdx.x < kMomCells * 5) {
+        const int m = threadIdx.x / 5, j = threadIdx.x - 5 * m, c = c0 + m;
+        double t = 0.0;
+        for (int u = 0; u < kBlock / 64; ++u) t += sh[u][m][j];
+        if (c < d.nc) {
+            if (j == 0 && Tdev) Tdev[c] = t / d.Ctot;
+            if (j == 1 && TLdev) TLdev[c] = t / d.Ssum;
+            if (j >= 2 && q) q[3 * c + j - 2] = t;
+        }
     }
 }
+
+// grid of k_mesh_moments over nc cells
+static inline dim3 mom_grid(int nc) { return dim3((unsigned)((nc + kMomCells - 1) / kMomCells)); }
 
 // explicit step e += dt R
 template <typename T>
@@ -329,30 +346,48 @@ __global__ __launch_bounds__(kBlock) void k_mesh_axpy(size_t n, T *__restrict__ 
         e[i] = (T)((double)e[i] + dt * (double)R[i]);
 }
 
-// out[0] = max |T1 - T0|, out[1] = max |T1| (deviations), one block
-__global__ __launch_bounds__(kBlock) void k_mesh_eps(int nc, const double *__restrict__ T0,
-                                                     const double *__restrict__ T1, double *__restrict__ out)
+// max |T1 - T0| and max |T1| (deviations) in two passes: kEpsBlocks blocks
+// write their maxima to part[2 * block + {0, 1}], then one block of kBlock
+// (= kEpsBlocks) threads reduces those into out[0], out[1]
+constexpr int kEpsBlocks = kBlock;
+__device__ inline void block_max2(double &a, double &b, double *out)
 {
-    __shared__ double sh[2][kBlock];
+    __shared__ double sh[2][kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        a = fmax(a, __shfl_xor(a, off, 64));
+        b = fmax(b, __shfl_xor(b, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = a;
+        sh[1][threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = sh[0][0], y = sh[1][0];
+        for (int w = 1; w < kBlock / 64; ++w) {
+            x = fmax(x, sh[0][w]);
+            y = fmax(y, sh[1][w]);
+        }
+        out[0] = x;
+        out[1] = y;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mesh_eps(int nc, const double *__restrict__ T0,
+                                                     const double *__restrict__ T1, double *__restrict__ part)
+{
     double a = 0.0, b = 0.0;
-    for (int c = threadIdx.x; c < nc; c += kBlock) {
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += kEpsBlocks * kBlock) {
         a = fmax(a, fabs(T1[c] - T0[c]));
         b = fmax(b, fabs(T1[c]));
     }
-    sh[0][threadIdx.x] = a;
-    sh[1][threadIdx.x] = b;
-    __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            sh[0][threadIdx.x] = fmax(sh[0][threadIdx.x], sh[0][threadIdx.x + off]);
-            sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + off]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        out[0] = sh[0][0];
-        out[1] = sh[1][0];
-    }
+    block_max2(a, b, part + 2 * blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mesh_eps_final(const double *__restrict__ part, double *__restrict__ out)
+{
+    double a = part[2 * threadIdx.x], b = part[2 * threadIdx.x + 1];
+    block_max2(a, b, out);
 }
 
 // T_abs = T_ref + dev
@@ -385,7 +420,7 @@ struct bte_mesh_problem {
     size_t ws_bytes = 0;
     MeshDev dev{};
     void *g = nullptr, *b = nullptr;
-    double *din = nullptr, *Tdev = nullptr, *Tprev = nullptr, *TLdev = nullptr, *P = nullptr, *eps = nullptr;
+    double *din = nullptr, *Tdev = nullptr, *Tprev = nullptr, *TLdev = nullptr, *P = nullptr, *eps = nullptr, *eps_part = nullptr;
     bool hasP = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // phase timers of the steady solve
     ~bte_mesh_problem()
@@ -948,7 +983,7 @@ bte_status mesh_solve(bte_mesh_problem *p, T *e, int init, bte_solve_stats *stat
     const auto h0 = std::chrono::steady_clock::now();
     const MeshDev &d = p->dev;
     if (init) MHIP(p, hipMemsetAsync(e, 0, p->esize() * p->nelem(), s));
-    hipLaunchKernelGGL(k_mesh_moments<T>, dim3(p->nc), dim3(kBlock), 0, s, d, e, p->Tprev, p->TLdev, nullptr);
+    hipLaunchKernelGGL(k_mesh_moments<T>, mom_grid(p->nc), dim3(kBlock), 0, s, d, e, p->Tprev, p->TLdev, nullptr);
     const int max_iter = p->ctl.max_iter > 0 ? p->ctl.max_iter : 10000;
     for (hipEvent_t &x : p->ev)
         if (!x) MHIP(p, hipEventCreate(&x));
@@ -966,8 +1001,9 @@ bte_status mesh_solve(bte_mesh_problem *p, T *e, int init, bte_solve_stats *stat
             hipLaunchKernelGGL(k_mesh_sweep_level<T>, dim3(blocks), dim3(kBlock), 0, s, d, e, (T *)p->b, i0, n);
         }
         MHIP(p, hipEventRecord(p->ev[2], s));
-        hipLaunchKernelGGL(k_mesh_moments<T>, dim3(p->nc), dim3(kBlock), 0, s, d, e, p->Tdev, p->TLdev, nullptr);
-        hipLaunchKernelGGL(k_mesh_eps, dim3(1), dim3(kBlock), 0, s, p->nc, p->Tprev, p->Tdev, p->eps);
+        hipLaunchKernelGGL(k_mesh_moments<T>, mom_grid(p->nc), dim3(kBlock), 0, s, d, e, p->Tdev, p->TLdev, nullptr);
+        hipLaunchKernelGGL(k_mesh_eps, dim3(kEpsBlocks), dim3(kBlock), 0, s, p->nc, p->Tprev, p->Tdev, p->eps_part);
+        hipLaunchKernelGGL(k_mesh_eps_final, dim3(1), dim3(kBlock), 0, s, p->eps_part, p->eps);
         MHIP(p, hipEventRecord(p->ev[3], s));
         double h[2];
         MHIP(p, hipMemcpyAsync(h, p->eps, 16, hipMemcpyDeviceToHost, s));
@@ -1071,6 +1107,7 @@ size_t bte_mesh_workspace_bytes(const bte_mesh_problem *p)
     add(p->esize() * p->nelem());       // residual / increments
     add(8 * ((size_t)p->nrec * p->nl + 1));
     add(8 * 5 * (size_t)p->nc + 16);    // Tdev, Tprev, TLdev, P, eps
+    add(8 * 2 * (size_t)kEpsBlocks);    // per-block maxima of the eps test
     return b;
 }
 
@@ -1146,6 +1183,7 @@ bte_status bte_mesh_bind(bte_mesh_problem *p, void *ws_dev, size_t bytes)
     p->TLdev = p->Tprev + p->nc;
     p->P = p->TLdev + p->nc;
     p->eps = p->P + p->nc;
+    p->eps_part = (double *)take(8 * 2 * (size_t)kEpsBlocks);
     d.P = p->hasP ? p->P : nullptr;
     p->ws = static_cast<char *>(ws_dev);
     p->ws_bytes = bytes;
@@ -1181,10 +1219,10 @@ bte_status bte_mesh_moments(bte_mesh_problem *p, const void *e_dev, double *T_de
     if (!e_dev) MFAIL(p, BTE_ERR_ARG, "null e");
     hipStream_t s = (hipStream_t)stream;
     if (p->ctl.precision == BTE_F64)
-        hipLaunchKernelGGL(k_mesh_moments<double>, dim3(p->nc), dim3(kBlock), 0, s, p->dev, (const double *)e_dev,
+        hipLaunchKernelGGL(k_mesh_moments<double>, mom_grid(p->nc), dim3(kBlock), 0, s, p->dev, (const double *)e_dev,
                            p->Tdev, p->TLdev, q_dev);
     else
-        hipLaunchKernelGGL(k_mesh_moments<float>, dim3(p->nc), dim3(kBlock), 0, s, p->dev, (const float *)e_dev,
+        hipLaunchKernelGGL(k_mesh_moments<float>, mom_grid(p->nc), dim3(kBlock), 0, s, p->dev, (const float *)e_dev,
                            p->Tdev, p->TLdev, q_dev);
     const dim3 gr((p->nc + kBlock - 1) / kBlock);
     if (T_dev) hipLaunchKernelGGL(k_mesh_abs, gr, dim3(kBlock), 0, s, p->nc, p->Tref, p->Tdev, T_dev);
@@ -1203,10 +1241,10 @@ bte_status bte_mesh_residual(bte_mesh_problem *p, const void *e_dev, const doubl
     const double *tl = TLdev_dev;
     if (!tl) {
         if (p->ctl.precision == BTE_F64)
-            hipLaunchKernelGGL(k_mesh_moments<double>, dim3(p->nc), dim3(kBlock), 0, s, p->dev, (const double *)e_dev,
+            hipLaunchKernelGGL(k_mesh_moments<double>, mom_grid(p->nc), dim3(kBlock), 0, s, p->dev, (const double *)e_dev,
                                nullptr, p->TLdev, nullptr);
         else
-            hipLaunchKernelGGL(k_mesh_moments<float>, dim3(p->nc), dim3(kBlock), 0, s, p->dev, (const float *)e_dev,
+            hipLaunchKernelGGL(k_mesh_moments<float>, mom_grid(p->nc), dim3(kBlock), 0, s, p->dev, (const float *)e_dev,
                                nullptr, p->TLdev, nullptr);
         tl = p->TLdev;
     }
@@ -1242,13 +1280,13 @@ bte_status bte_mesh_transient_step(bte_mesh_problem *p, void *e_dev, int n_steps
     const int blocks = (int)std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
     for (int it = 0; it < n_steps; ++it) {
         if (p->ctl.precision == BTE_F64) {
-            hipLaunchKernelGGL(k_mesh_moments<double>, dim3(p->nc), dim3(kBlock), 0, s, p->dev, (const double *)e_dev,
+            hipLaunchKernelGGL(k_mesh_moments<double>, mom_grid(p->nc), dim3(kBlock), 0, s, p->dev, (const double *)e_dev,
                                nullptr, p->TLdev, nullptr);
             mesh_iteration_rhs<double>(p, (const double *)e_dev, p->TLdev, (double *)p->b, s);
             hipLaunchKernelGGL(k_mesh_axpy<double>, dim3(blocks), dim3(kBlock), 0, s, n, (double *)e_dev,
                                (const double *)p->b, dt);
         } else {
-            hipLaunchKernelGGL(k_mesh_moments<float>, dim3(p->nc), dim3(kBlock), 0, s, p->dev, (const float *)e_dev,
+            hipLaunchKernelGGL(k_mesh_moments<float>, mom_grid(p->nc), dim3(kBlock), 0, s, p->dev, (const float *)e_dev,
                                nullptr, p->TLdev, nullptr);
             mesh_iteration_rhs<float>(p, (const float *)e_dev, p->TLdev, (float *)p->b, s);
             hipLaunchKernelGGL(k_mesh_axpy<float>, dim3(blocks), dim3(kBlock), 0, s, n, (float *)e_dev,
