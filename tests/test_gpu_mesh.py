@@ -281,3 +281,68 @@ def test_single_cell_meshes(B, kind, prec):
     e2 = host(eg)
     prob.transient_step(eg, 4)
     assert rel_err(host(eg), M.transient(case, e2, 4, 1e-13)) < bar
+
+
+# ------------------------------------------- bench-sized meshes: linear field
+
+def _centroids(mesh):
+    """Cell centroids as the setup defines them: the vertex mean of a
+    tetrahedron, the area centroid of a polygon."""
+    if "xyz" in mesh:
+        return np.asarray(mesh["xyz"])[np.asarray(mesh["cell_vtx"])].mean(axis=1)
+    xy, ptr, vtx = np.asarray(mesh["xy"]), np.asarray(mesh["cell_ptr"]), np.asarray(mesh["cell_vtx"])
+    out = np.zeros((len(ptr) - 1, 3))
+    for c in range(len(ptr) - 1):
+        p = xy[vtx[ptr[c]:ptr[c + 1]]]
+        q = np.roll(p, -1, axis=0)
+        cr = p[:, 0] * q[:, 1] - q[:, 0] * p[:, 1]
+        A = cr.sum() / 2
+        out[c, :2] = ((p + q) * cr[:, None]).sum(axis=0) / (6 * A)
+    return out
+
+
+@pytest.mark.parametrize("kind", ["mesh2d_128", "mesh3d_32"])
+def test_full_size_linear_field(B, kind):
+    """The bench meshes at full size (27 904 cells x 128 directions x 20
+    bands; 196 608 tetrahedra x 96 directions x 20 bands), FP64, every cell
+    through the kernels the bench times.  For e = C4_l T(x) with T linear in
+    x, the least-squares gradients are exact (full-rank stencils) and so is
+    each second-order face value; by the divergence theorem the face sum of
+    a cell with interior faces is then V s.grad(e), and with T_L = T the
+    relaxation term vanishes: R = -v_l C4_l (s . grad T) on sampled interior
+    cells.  The moments return T and T_L = T(x_c) at every cell (isotropic
+    state, weights summing to 4 pi)."""
+    from oracle.oracle import quadrature
+    if kind == "mesh2d_128":
+        mesh = I.mesh2d(21, 128, 128, 1e-6, 1e-6, jitter=0.25, quad_frac=0.3)
+        mat = dict(I.bands(np.random.default_rng(21), 20), n_theta=2, n_phi=8, Tref=300.0)
+        s, _ = quadrature(2, 2, 8, 3)
+        gT = np.array([3e6, -2e6, 0.0])
+    else:
+        mesh = I.mesh3d(31, 32, 32, 32, 1e-6, 1e-6, 1e-6, jitter=0.15)
+        mat = dict(I.bands(np.random.default_rng(31), 20), n_theta=3, n_phi=4, Tref=300.0)
+        s, _ = quadrature(3, 3, 4, 3)
+        gT = np.array([3e6, -2e6, 2.5e6])
+    prob = B.MeshProblem(mesh, mat, dict(precision=B.F64))
+    xc = _centroids(mesh)
+    nc, na, nl = prob.n_cells, prob.n_dirs, prob.n_bands
+    assert (nc, na) == (len(xc), len(s))
+    print(kind, nc, na, nl, flush=True)
+    C4 = np.asarray(mat["C"]) / (4 * np.pi)
+    T = 0.5 + xc @ gT
+    e = (T[:, None, None] * C4[None, None, :]) * np.ones((1, na, 1))
+    eg = torch.as_tensor(e.reshape(-1), device="cuda").contiguous()
+    R = prob.residual(eg, T).view(nc, na, nl)
+    # interior cells: centroid at least two cells' widths from the walls
+    h = 1e-6 / (128 if kind == "mesh2d_128" else 32)
+    dim = 2 if kind == "mesh2d_128" else 3
+    inner = np.all((xc[:, :dim] > 2 * h) & (xc[:, :dim] < 1e-6 - 2 * h), axis=1)
+    cells = np.random.default_rng(5).choice(np.flatnonzero(inner), 2000, replace=False)
+    got = R[torch.as_tensor(cells, device="cuda")].double().cpu().numpy()
+    want = -(np.asarray(mat["v"]) * C4)[None, None, :] * (s @ gT)[None, :, None] * np.ones((len(cells), 1, 1))
+    err = rel_err(got.reshape(-1), want.reshape(-1))
+    Tg, TLg, _ = prob.moments(eg)
+    errT = (rel_err(host(Tg), 300.0 + T, 300.0), rel_err(host(TLg), 300.0 + T, 300.0))
+    print(kind, err, errT)
+    assert err < 1e-10, err
+    assert max(errT) < 1e-12, errT
