@@ -170,6 +170,39 @@ __global__ __launch_bounds__(kBlock) void k_mesh_walls(MeshDev d, const T *__res
     }
 }
 
+// Face sum of a cell whose NF faces are all interior (the common cell):
+// every face's loads are issued before the sums, which run in face order,
+// and the upwind side is picked per lane without branches (a lane with
+// s.n = 0 adds zero).
+template <typename T, int D, int NF>
+__device__ inline double interior_flux(const MeshDev &d, const T *__restrict__ e, const T *__restrict__ g, int c,
+                                       int k, int f0, const int *nbv, double sx, double sy, double sz)
+{
+    double sn[NF], ev[NF], gv[NF][3], lo[NF][3];
+#pragma unroll
+    for (int u = 0; u < NF; ++u) {
+        const double *fg = d.fgeo + (size_t)(f0 + u) * kFG;
+        sn[u] = sx * fg[1] + sy * fg[2] + sz * fg[3];
+        const bool own = sn[u] > 0.0;
+        const int src = own ? c : nbv[u];
+        // offset of the face centre from the upwind cell's centre
+        const double m = own ? 0.0 : 1.0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) lo[u][q] = fg[4 + q] - m * fg[7 + q];
+        ev[u] = (double)e[(size_t)src * d.nk + k];
+#pragma unroll
+        for (int q = 0; q < D; ++q) gv[u][q] = (double)g[((size_t)src * D + q) * d.nk + k];
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < NF; ++u) {
+        double ef = ev[u] + gv[u][0] * lo[u][0] + gv[u][1] * lo[u][1];
+        if constexpr (D == 3) ef += gv[u][2] * lo[u][2];
+        acc += sn[u] * d.fgeo[(size_t)(f0 + u) * kFG] * ef;
+    }
+    return acc;
+}
+
 // R = -(1/V) sum_f v (s.n) S e_f - (e - C4 T_L) / tau + C4 P / C_tot
 template <typename T, int D>
 __global__ __launch_bounds__(kBlock) void k_mesh_residual(MeshDev d, const T *__restrict__ e, const T *__restrict__ g,
@@ -185,37 +218,22 @@ __global__ __launch_bounds__(kBlock) void k_mesh_residual(MeshDev d, const T *__
     const double sx = d.s[3 * al], sy = d.s[3 * al + 1], sz = d.s[3 * al + 2];
     double acc = 0.0;
     const int f0 = d.fptr[c], f1 = d.fptr[c + 1];
+    const int nf = f1 - f0;
     int nbv[4] = {-1, -1, -1, -1};
-    bool inner = f1 - f0 == 4;
+    // tetrahedra: four faces; polygons: triangles and quadrilaterals
+    bool inner = nf == 4 || (D == 2 && nf == 3);
     if (inner) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) nbv[u] = d.fnb[f0 + u];
-        inner = nbv[0] >= 0 && nbv[1] >= 0 && nbv[2] >= 0 && nbv[3] >= 0;
+        for (int u = 0; u < 3; ++u) nbv[u] = d.fnb[f0 + u];
+        if (nf == 4) nbv[3] = d.fnb[f0 + 3];
+        inner = nbv[0] >= 0 && nbv[1] >= 0 && nbv[2] >= 0 && (nf == 3 || nbv[3] >= 0);
     }
     if (inner) {
-        // four interior faces (the common cell): every face's loads are
-        // issued before the sums, which run in face order
-        double sn[4], ev[4], gv[4][3], lo[4][3];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double *fg = d.fgeo + (size_t)(f0 + u) * kFG;
-            sn[u] = sx * fg[1] + sy * fg[2] + sz * fg[3];
-            const bool own = sn[u] > 0.0;
-            const int src = own ? c : nbv[u];
-            // offset of the face centre from the upwind cell's centre
-            const double m = own ? 0.0 : 1.0;
-#pragma unroll
-            for (int q = 0; q < D; ++q) lo[u][q] = fg[4 + q] - m * fg[7 + q];
-            ev[u] = (double)e[(size_t)src * d.nk + k];
-#pragma unroll
-            for (int q = 0; q < D; ++q) gv[u][q] = (double)g[((size_t)src * D + q) * d.nk + k];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            double ef = ev[u] + gv[u][0] * lo[u][0] + gv[u][1] * lo[u][1];
-            if constexpr (D == 3) ef += gv[u][2] * lo[u][2];
-            acc += sn[u] * d.fgeo[(size_t)(f0 + u) * kFG] * ef;
-        }
+        if constexpr (D == 3)
+            acc = interior_flux<T, D, 4>(d, e, g, c, k, f0, nbv, sx, sy, sz);
+        else
+            acc = nf == 4 ? interior_flux<T, D, 4>(d, e, g, c, k, f0, nbv, sx, sy, sz)
+                          : interior_flux<T, D, 3>(d, e, g, c, k, f0, nbv, sx, sy, sz);
     }
     for (int f = inner ? f1 : f0; f < f1; ++f) {
         const double *fg = d.fgeo + (size_t)f * kFG;
