@@ -72,8 +72,30 @@ struct MeshDev {
     const double4 *item_coef;
 };
 
+// Lane k of a cell's row.  BUF (FP32 states below 2 GiB): one buffer
+// descriptor over the whole state, the row's byte offset as the scalar
+// offset and the lane's as the vector offset, so that a row costs no vector
+// address arithmetic; otherwise a plain load.
+template <typename T, bool BUF>
+struct RowReader {
+    const T *e;
+    int nk, k;
+    __amdgpu_buffer_rsrc_t r;
+    __device__ RowReader(const T *e_, int nk_, int k_, int nc) : e(e_), nk(nk_), k(k_)
+    {
+        if constexpr (BUF) r = __builtin_amdgcn_make_buffer_rsrc((void *)e_, (short)0, nk_ * nc * 4, 0x00020000);
+    }
+    __device__ T operator()(int c) const
+    {
+        if constexpr (BUF && sizeof(T) == 4)
+            return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, k * 4, c * nk * 4, 0));
+        else
+            return e[(size_t)c * nk + k];
+    }
+};
+
 // gradient of lane k of cell c: D components at g[(c * D + q) * nk + k]
-template <typename T, int D>
+template <typename T, int D, bool BUF>
 __global__ __launch_bounds__(kBlock) void k_mesh_grad(MeshDev d, const T *__restrict__ e, T *__restrict__ g, int nkb)
 {
     // block = (cell, block of 256 lanes); cells in the Morton visit order
@@ -81,22 +103,23 @@ __global__ __launch_bounds__(kBlock) void k_mesh_grad(MeshDev d, const T *__rest
     const int c = d.vorder[i];
     const int k = (blockIdx.x - i * nkb) * kBlock + threadIdx.x;
     if (k >= d.nk) return;
-    const double ec = (double)e[(size_t)c * d.nk + k];
+    const RowReader<T, BUF> row(e, d.nk, k, d.nc);
+    const double ec = (double)row(c);
     double y[3] = {0.0, 0.0, 0.0};
     // stencil rows eight, then four at a time in flight (the loads do not
     // wait on each other's sums), summed in stencil order; the row indices
     // and offsets are read through pointers that step by whole groups, so
-    // that each group costs one scalar address computation
+    // that each group costs one scalar address computation; a row's load is
+    // read by RowReader
     const int j0 = d.lsptr[c];
     int n = d.lsptr[c + 1] - j0;
     const int *nbp = d.lsnb + j0;
     const double *ldp = d.lsd + 3 * (size_t)j0;
-    const T *ek = e + k;
     const size_t nk = (size_t)d.nk;
     for (; n >= 8; n -= 8, nbp += 8, ldp += 24) {
         T v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = ek[(size_t)nbp[u] * nk];
+        for (int u = 0; u < 8; ++u) v[u] = row(nbp[u]);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const double diff = (double)v[u] - ec;
@@ -107,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_mesh_grad(MeshDev d, const T *__rest
     if (n >= 4) {
         T v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = ek[(size_t)nbp[u] * nk];
+        for (int u = 0; u < 4; ++u) v[u] = row(nbp[u]);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const double diff = (double)v[u] - ec;
@@ -119,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_mesh_grad(MeshDev d, const T *__rest
         ldp += 12;
     }
     for (; n > 0; --n, ++nbp, ldp += 3) {
-        const double diff = (double)ek[(size_t)*nbp * nk] - ec;
+        const double diff = (double)row(*nbp) - ec;
 #pragma unroll
         for (int q = 0; q < D; ++q) y[q] += ldp[q] * diff;
     }
@@ -980,14 +1003,21 @@ void mesh_iteration_rhs(bte_mesh_problem *p, const T *e, const double *TLdev, T 
     const MeshDev &d = p->dev;
     const int nkb = (p->nk + kBlock - 1) / kBlock;
     const dim3 grid((unsigned)((size_t)nkb * p->nc));
+    const bool buf = sizeof(T) == 4 && p->nelem() * 4 < (size_t(1) << 31);
     if (p->dim == 3) {
-        hipLaunchKernelGGL((k_mesh_grad<T, 3>), grid, dim3(kBlock), 0, s, d, e, (T *)p->g, nkb);
+        if (buf)
+            hipLaunchKernelGGL((k_mesh_grad<T, 3, true>), grid, dim3(kBlock), 0, s, d, e, (T *)p->g, nkb);
+        else
+            hipLaunchKernelGGL((k_mesh_grad<T, 3, false>), grid, dim3(kBlock), 0, s, d, e, (T *)p->g, nkb);
         if (p->nrec > 0)
             hipLaunchKernelGGL((k_mesh_walls<T, 3>), dim3(p->nrec), dim3(kBlock), 0, s, d, e, (const T *)p->g, p->din);
         hipLaunchKernelGGL((k_mesh_residual<T, 3>), grid, dim3(kBlock), 0, s, d, e, (const T *)p->g, p->din, TLdev,
                            R, nkb);
     } else {
-        hipLaunchKernelGGL((k_mesh_grad<T, 2>), grid, dim3(kBlock), 0, s, d, e, (T *)p->g, nkb);
+        if (buf)
+            hipLaunchKernelGGL((k_mesh_grad<T, 2, true>), grid, dim3(kBlock), 0, s, d, e, (T *)p->g, nkb);
+        else
+            hipLaunchKernelGGL((k_mesh_grad<T, 2, false>), grid, dim3(kBlock), 0, s, d, e, (T *)p->g, nkb);
         if (p->nrec > 0)
             hipLaunchKernelGGL((k_mesh_walls<T, 2>), dim3(p->nrec), dim3(kBlock), 0, s, d, e, (const T *)p->g, p->din);
         hipLaunchKernelGGL((k_mesh_residual<T, 2>), grid, dim3(kBlock), 0, s, d, e, (const T *)p->g, p->din, TLdev,
