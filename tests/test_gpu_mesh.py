@@ -301,8 +301,9 @@ def _centroids(mesh):
     return out
 
 
+@pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("kind", ["mesh2d_128", "mesh3d_32"])
-def test_full_size_linear_field(B, kind):
+def test_full_size_linear_field(B, kind, prec):
     """The bench meshes at full size (27 904 cells x 128 directions x 20
     bands; 196 608 tetrahedra x 96 directions x 20 bands), FP64, every cell
     through the kernels the bench times.  For e = C4_l T(x) with T linear in
@@ -311,7 +312,17 @@ def test_full_size_linear_field(B, kind):
     a cell with interior faces is then V s.grad(e), and with T_L = T the
     relaxation term vanishes: R = -v_l C4_l (s . grad T) on sampled interior
     cells.  The moments return T and T_L = T(x_c) at every cell (isotropic
-    state, weights summing to 4 pi)."""
+    state, weights summing to 4 pi).
+
+    FP32 (the bench's precision; rows read through the buffer-descriptor
+    path): the kernels compute in FP64 on stored values rounded by at most
+    u = 2^-24 relative, so the error is the operator applied to that
+    rounding: the face values move by at most u max|e| (1 + G), G the
+    gradient's amplification times the centre-to-face distance (a few), and
+    the face sum by v sum_f S_f / V times that (about 1e3 m/s x 4e8 1/m on
+    the tetrahedra), against a residual of 2 v max|e| / L (T spans about
+    +-3 K over L = 1 um): u x 4e8 x 6 x L / 2 ~ 7e-5, bar 1e-4.  The moments
+    are weighted sums of the stored values: relative error below 1e-6."""
     from oracle.oracle import quadrature
     if kind == "mesh2d_128":
         mesh = I.mesh2d(21, 128, 128, 1e-6, 1e-6, jitter=0.25, quad_frac=0.3)
@@ -323,7 +334,7 @@ def test_full_size_linear_field(B, kind):
         mat = dict(I.bands(np.random.default_rng(31), 20), n_theta=3, n_phi=4, Tref=300.0)
         s, _ = quadrature(3, 3, 4, 3)
         gT = np.array([3e6, -2e6, 2.5e6])
-    prob = B.MeshProblem(mesh, mat, dict(precision=B.F64))
+    prob = B.MeshProblem(mesh, mat, dict(precision=B.F64 if prec == 1 else B.F32))
     xc = _centroids(mesh)
     nc, na, nl = prob.n_cells, prob.n_dirs, prob.n_bands
     assert (nc, na) == (len(xc), len(s))
@@ -331,7 +342,7 @@ def test_full_size_linear_field(B, kind):
     C4 = np.asarray(mat["C"]) / (4 * np.pi)
     T = 0.5 + xc @ gT
     e = (T[:, None, None] * C4[None, None, :]) * np.ones((1, na, 1))
-    eg = torch.as_tensor(e.reshape(-1), device="cuda").contiguous()
+    eg = torch.as_tensor(e.reshape(-1), device="cuda").to(prob.dtype).contiguous()
     R = prob.residual(eg, T).view(nc, na, nl)
     # interior cells: centroid at least two cells' widths from the walls
     h = 1e-6 / (128 if kind == "mesh2d_128" else 32)
@@ -343,6 +354,6 @@ def test_full_size_linear_field(B, kind):
     err = rel_err(got.reshape(-1), want.reshape(-1))
     Tg, TLg, _ = prob.moments(eg)
     errT = (rel_err(host(Tg), 300.0 + T, 300.0), rel_err(host(TLg), 300.0 + T, 300.0))
-    print(kind, err, errT)
-    assert err < 1e-10, err
-    assert max(errT) < 1e-12, errT
+    print(kind, prec, err, errT)
+    assert err < (1e-10 if prec == 1 else 1e-4), err
+    assert max(errT) < (1e-12 if prec == 1 else 1e-6), errT
